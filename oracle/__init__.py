@@ -1,0 +1,227 @@
+"""CPU FP64 oracle for the space-time DG-SEM slab system (ctypes wrapper).
+
+TEST INFRASTRUCTURE ONLY: the tests, the smoke check and the CPU-baseline leg
+of the benchmark may import this module; the product package never does.
+The arithmetic lives in ``oracle.cpp`` (see its header for the formulations
+and the readings of the paper it takes).  Build it with ``build()`` (plain
+g++ with OpenMP); nothing here depends on the GPU library.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liboracle.so")
+
+ADVECTION, ADVDIFF_BR1, BURGERS, EULER, NS_BR1 = 1, 2, 3, 4, 5
+FORM_DG, FORM_RK, FORM_GALERKIN = 0, 1, 2
+
+
+class Problem(ctypes.Structure):
+    _fields_ = [
+        ("dim", ctypes.c_int),
+        ("K", ctypes.c_int * 3),
+        ("lo", ctypes.c_double * 3),
+        ("hi", ctypes.c_double * 3),
+        ("N", ctypes.c_int),
+        ("Nt", ctypes.c_int),
+        ("eq", ctypes.c_int),
+        ("a", ctypes.c_double * 3),
+        ("nu", ctypes.c_double),
+        ("gamma", ctypes.c_double),
+        ("mu", ctypes.c_double),
+        ("prandtl", ctypes.c_double),
+        ("react", ctypes.c_double),
+    ]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [
+        ("newton_its", ctypes.c_int),
+        ("linear_its", ctypes.c_int),
+        ("res0", ctypes.c_double),
+        ("res_final", ctypes.c_double),
+        ("converged", ctypes.c_int),
+    ]
+
+
+def build(force: bool = False) -> str:
+    """Compile liboracle.so with g++ (-O2, OpenMP)."""
+    src = os.path.join(HERE, "oracle.cpp")
+    if force or not os.path.exists(LIB_PATH) or os.path.getmtime(LIB_PATH) < os.path.getmtime(src):
+        cmd = ["g++", "-O2", "-std=c++17", "-fopenmp", "-fPIC", "-shared", src, "-o", LIB_PATH]
+        subprocess.check_call(cmd)
+    return LIB_PATH
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            build()
+        L = ctypes.CDLL(LIB_PATH)
+        P = ctypes.POINTER(Problem)
+        dp = ctypes.POINTER(ctypes.c_double)
+        L.orc_nvars.argtypes = [ctypes.c_int, ctypes.c_int]
+        L.orc_slab_size.argtypes = [P]
+        L.orc_slab_size.restype = ctypes.c_long
+        L.orc_space_size.argtypes = [P]
+        L.orc_space_size.restype = ctypes.c_long
+        L.orc_set_threads.argtypes = [ctypes.c_int]
+        L.orc_get_threads.restype = ctypes.c_int
+        L.orc_lgl.argtypes = [ctypes.c_int, dp, dp, dp]
+        L.orc_butcher_from_sbp.argtypes = [ctypes.c_int, dp, dp, dp]
+        L.orc_butcher_appendix_b.argtypes = [ctypes.c_int, dp, dp, dp]
+        L.orc_node_coords.argtypes = [P, dp]
+        L.orc_spatial_op.argtypes = [P, dp, dp]
+        L.orc_spatial_jvp.argtypes = [P, dp, dp, dp]
+        L.orc_num_flux.argtypes = [P, ctypes.c_int, dp, dp, dp, dp, dp]
+        L.orc_flux.argtypes = [P, ctypes.c_int, dp, dp, dp]
+        L.orc_residual.argtypes = [P, ctypes.c_int, dp, dp, ctypes.c_double, dp]
+        L.orc_jvp.argtypes = [P, ctypes.c_int, dp, ctypes.c_double, dp, dp]
+        L.orc_solve.argtypes = [P, ctypes.c_int, dp, ctypes.c_double, ctypes.c_double,
+                                ctypes.c_int, ctypes.c_int, dp, ctypes.POINTER(Stats)]
+        _lib = L
+    return _lib
+
+
+def _p(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _c(a) -> np.ndarray:
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def nvars(eq: int, dim: int) -> int:
+    return lib().orc_nvars(eq, dim)
+
+
+def problem(dim, K, lo, hi, N, Nt, eq, a=(0.0, 0.0, 0.0), nu=0.0, gamma=1.4, mu=0.0,
+            prandtl=0.72, react=0.0) -> Problem:
+    p = Problem()
+    p.dim = dim
+    for i in range(3):
+        p.K[i] = int(K[i]) if i < dim else 1
+        p.lo[i] = float(lo[i]) if i < dim else 0.0
+        p.hi[i] = float(hi[i]) if i < dim else 1.0
+        p.a[i] = float(a[i]) if i < len(a) else 0.0
+    p.N, p.Nt, p.eq = N, Nt, eq
+    p.nu, p.gamma, p.mu, p.prandtl, p.react = nu, gamma, mu, prandtl, react
+    return p
+
+
+def slab_size(p) -> int:
+    return lib().orc_slab_size(ctypes.byref(p))
+
+
+def space_size(p) -> int:
+    return lib().orc_space_size(ctypes.byref(p))
+
+
+def set_threads(n: int) -> None:
+    lib().orc_set_threads(n)
+
+
+def get_threads() -> int:
+    return lib().orc_get_threads()
+
+
+def lgl(n: int):
+    x, w, D = np.zeros(n), np.zeros(n), np.zeros((n, n))
+    lib().orc_lgl(n, _p(x), _p(w), _p(D))
+    return x, w, D
+
+
+def butcher_from_sbp(Nt: int):
+    A, b, c = np.zeros((Nt, Nt)), np.zeros(Nt), np.zeros(Nt)
+    lib().orc_butcher_from_sbp(Nt, _p(A), _p(b), _p(c))
+    return A, b, c
+
+
+def butcher_appendix_b(Nt: int):
+    A, b, c = np.zeros((Nt, Nt)), np.zeros(Nt), np.zeros(Nt)
+    if lib().orc_butcher_appendix_b(Nt, _p(A), _p(b), _p(c)) != 0:
+        raise ValueError("Appendix B lists Nt = 2, 3, 4 only")
+    return A, b, c
+
+
+def node_coords(p) -> np.ndarray:
+    """Physical node coordinates, shape (E, dim, ns)."""
+    ns = (p.N + 1) ** p.dim
+    E = int(np.prod([p.K[i] for i in range(p.dim)]))
+    X = np.zeros((E, p.dim, ns))
+    lib().orc_node_coords(ctypes.byref(p), _p(X))
+    return X
+
+
+def spatial_op(p, u) -> np.ndarray:
+    u = _c(u)
+    F = np.zeros_like(u)
+    lib().orc_spatial_op(ctypes.byref(p), _p(u), _p(F))
+    return F
+
+
+def spatial_jvp(p, u, v) -> np.ndarray:
+    u, v = _c(u), _c(v)
+    J = np.zeros_like(u)
+    lib().orc_spatial_jvp(ctypes.byref(p), _p(u), _p(v), _p(J))
+    return J
+
+
+def num_flux(p, axis, uL, uR, qL=None, qR=None) -> np.ndarray:
+    uL, uR = _c(uL), _c(uR)
+    H = np.zeros_like(uL)
+    qLa = _c(qL) if qL is not None else None
+    qRa = _c(qR) if qR is not None else None
+    lib().orc_num_flux(ctypes.byref(p), axis, _p(uL), _p(uR),
+                       _p(qLa) if qLa is not None else None,
+                       _p(qRa) if qRa is not None else None, _p(H))
+    return H
+
+
+def flux(p, axis, u, q=None) -> np.ndarray:
+    u = _c(u)
+    f = np.zeros_like(u)
+    qa = _c(q) if q is not None else None
+    lib().orc_flux(ctypes.byref(p), axis, _p(u), _p(qa) if qa is not None else None, _p(f))
+    return f
+
+
+def residual(p, U, uprev, dt, form=FORM_DG) -> np.ndarray:
+    U, uprev = _c(U), _c(uprev)
+    R = np.zeros_like(U)
+    lib().orc_residual(ctypes.byref(p), form, _p(U), _p(uprev), float(dt), _p(R))
+    return R
+
+
+def jvp(p, U, dt, V, form=FORM_DG) -> np.ndarray:
+    U, V = _c(U), _c(V)
+    JV = np.zeros_like(U)
+    lib().orc_jvp(ctypes.byref(p), form, _p(U), float(dt), _p(V), _p(JV))
+    return JV
+
+
+def solve(p, uprev, dt, tol=1e-13, form=FORM_DG, max_newton=30, dense_limit=1500):
+    """Newton solve of one slab; returns (U, stats dict)."""
+    uprev = _c(uprev)
+    U = np.zeros(slab_size(p))
+    st = Stats()
+    rc = lib().orc_solve(ctypes.byref(p), form, _p(uprev), float(dt), float(tol), max_newton,
+                         dense_limit, _p(U), ctypes.byref(st))
+    return U, dict(rc=rc, newton_its=st.newton_its, linear_its=st.linear_its, res0=st.res0,
+                   res_final=st.res_final, converged=bool(st.converged))
+
+
+def last_time_node(p, U) -> np.ndarray:
+    """u^{Nt} = (e_Nt^T (x) I) U, eq. (un), in the spatial layout [E][nv][ns]."""
+    nv = nvars(p.eq, p.dim)
+    ns = (p.N + 1) ** p.dim
+    return np.ascontiguousarray(np.asarray(U).reshape(-1, nv, p.Nt, ns)[:, :, -1, :]).reshape(-1)

@@ -1,0 +1,579 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix.
+
+Every test here runs on the CPU only.  None of them retypes the oracle's
+formula: each compares against printed values of the paper (fixtures under
+tests/golden/, with citations), closed forms, invariants, or brute force.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+from paper_2201_05800_amd import inputs
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+R5 = math.sqrt(5.0)
+
+
+def _val(x):
+    """Evaluate a printed table entry such as '(10-7*r5)/60'."""
+    if isinstance(x, (int, float)):
+        return float(x)
+    return float(eval(x, {"__builtins__": {}}, {"r5": R5}))
+
+
+def _mat(rows):
+    return np.array([[_val(v) for v in r] for r in rows])
+
+
+def _load(name):
+    with open(os.path.join(GOLD, name)) as f:
+        return json.load(f)
+
+
+# ---------------------------------------------------------------------------
+# P1-P5: node sets, SBP matrices, Butcher tableaux
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("n", [2, 3, 4, 5, 6])
+def test_sbp_property(orc, n):
+    """eq. (SBP): M = M^T > 0 and M D + (M D)^T = B = diag(-1, 0, ..., 0, 1)."""
+    x, w, D = orc.lgl(n)
+    M = np.diag(w)
+    B = np.zeros((n, n))
+    B[0, 0], B[-1, -1] = -1.0, 1.0
+    assert np.all(w > 0)
+    assert np.abs(M @ D + (M @ D).T - B).max() < 1e-13
+
+
+@pytest.mark.parametrize("n", [2, 3, 4, 5, 6])
+def test_operator_order(orc, n):
+    """Operator order q = n - 1 (Sec. "Comparison of terminology"): D tau^q = q tau^(q-1),
+    D 1 = 0, and the quadrature order of the LGL weights."""
+    x, w, D = orc.lgl(n)
+    assert np.abs(D @ np.ones(n)).max() < 1e-13
+    for q in range(1, n):
+        assert np.abs(D @ x ** q - q * x ** (q - 1)).max() < 1e-12
+    assert np.abs(D @ x ** n - n * x ** (n - 1)).max() > 1e-3
+    # "order 2(n-1)" of the quadrature in the sense of B(2n-2): monomials of
+    # degree m <= 2n-3 are integrated exactly, degree 2n-2 is not
+    for m in range(2 * n - 2):
+        assert abs((m + 1) * w @ x ** m - (1 - (-1) ** (m + 1))) < 1e-13
+    m = 2 * n - 2
+    assert abs((m + 1) * w @ x ** m - (1 - (-1) ** (m + 1))) > 1e-6
+
+
+def test_lgl_small_closed_forms(orc):
+    """n = 3: nodes 0, +-1, weights 1/3, 4/3; n = 4: nodes +-1/sqrt(5)."""
+    x, w, _ = orc.lgl(3)
+    assert np.allclose(x, [-1, 0, 1], atol=1e-15) and np.allclose(w, [1 / 3, 4 / 3, 1 / 3], atol=1e-15)
+    x, w, _ = orc.lgl(4)
+    assert np.allclose(x, [-1, -1 / R5, 1 / R5, 1], atol=1e-15)
+    assert np.allclose(w, [1 / 6, 5 / 6, 5 / 6, 1 / 6], atol=1e-15)
+
+
+@pytest.mark.parametrize("Nt", [2, 3, 4])
+def test_appendix_d_matrices(orc, Nt):
+    """Appendix D: computed B_tau, M_tau, D_tau equal the printed matrices
+    (with the Nt = 4 sign reading recorded in the fixture)."""
+    g = _load("appendix_d_sbp.json")[str(Nt)]
+    x, w, D = orc.lgl(Nt)
+    assert np.abs(np.diag(w) - _mat(g["M"])).max() < 1e-14
+    assert np.abs(D - _mat(g["D"])).max() < 1e-13
+    B = np.diag(w) @ D + (np.diag(w) @ D).T
+    assert np.abs(B - _mat(g["B"])).max() < 1e-13
+    if "D_printed" in g:
+        # the printed entry violates D 1 = 0; the corrected one satisfies it
+        assert abs(_mat(g["D_printed"]).sum(axis=1)).max() > 1.0
+        assert abs(_mat(g["D"]).sum(axis=1)).max() < 1e-14
+
+
+@pytest.mark.parametrize("Nt", [2, 3, 4])
+def test_butcher_from_sbp_matches_appendix_b(orc, Nt):
+    """eq. (SBP_to_RK) applied to the LGL SBP matrices gives the Lobatto IIIC
+    tableau printed in Appendix B."""
+    g = _load("appendix_b_butcher.json")[str(Nt)]
+    A, b, c = orc.butcher_from_sbp(Nt)
+    assert np.abs(A - _mat(g["A"])).max() < 1e-14
+    assert np.abs(b - np.array([_val(v) for v in g["b"]])).max() < 1e-14
+    assert np.abs(c - np.array([_val(v) for v in g["c"]])).max() < 1e-14
+    A2, b2, c2 = orc.butcher_appendix_b(Nt)
+    assert np.abs(A2 - _mat(g["A"])).max() < 1e-15
+
+
+@pytest.mark.parametrize("Nt", [2, 3, 4])
+def test_simplified_order_conditions(orc, Nt):
+    """Thm. (Lobatto_IIIC_order): B(2Nt-2), C(Nt-1), D(Nt-1) hold; B(2Nt-1)
+    and C(Nt) fail (so the check is sharp)."""
+    A, b, c = orc.butcher_from_sbp(Nt)
+
+    def B(j):
+        return abs(b @ c ** (j - 1) - 1.0 / j)
+
+    def C(j):
+        return np.abs(A @ c ** (j - 1) - c ** j / j).max()
+
+    def Dc(j):
+        return np.abs(A.T @ (b * c ** (j - 1)) - b * (1 - c ** j) / j).max()
+
+    for j in range(1, 2 * Nt - 1):
+        assert B(j) < 1e-14
+    for j in range(1, Nt):
+        assert C(j) < 1e-14 and Dc(j) < 1e-14
+    assert B(2 * Nt - 1) > 1e-6
+    assert C(Nt) > 1e-6
+
+
+# ---------------------------------------------------------------------------
+# P6: linear test equation, Tables TablePointwise and TableL2
+# ---------------------------------------------------------------------------
+def _linear_test_run(orc, Nt, nsteps, form):
+    p = orc.problem(1, [1], [0], [1], 1, Nt, orc.ADVECTION, a=(0.0,), react=-1.0)
+    up = np.full(orc.space_size(p), 4.0)
+    dt = 1.0 / nsteps
+    tau, _, _ = orc.lgl(Nt)
+    gx, gw = np.polynomial.legendre.leggauss(12)
+    l2 = 0.0
+    for n in range(nsteps):
+        U, st = orc.solve(p, up, dt, tol=1e-14, form=form, max_newton=3)
+        assert st["res_final"] < 1e-12
+        Ut = U.reshape(1, 1, Nt, 2)[0, 0, :, 0]
+        coef = np.polyfit(tau, Ut, Nt - 1)           # interpolant in time
+        t = n * dt + 0.5 * dt * (1 + gx)
+        err = np.polyval(coef, gx) - 4.0 * np.exp(-t)
+        l2 += 0.5 * dt * np.sum(gw * err ** 2)
+        up = orc.last_time_node(p, U)
+    return abs(up[0] - 4.0 * math.exp(-1.0)), math.sqrt(l2)
+
+
+@pytest.mark.parametrize("Nt", [2, 3, 4])
+def test_linear_test_equation_eoc(orc, Nt):
+    """Reproduce the paper's EOC tables (rows whose errors stay above the
+    round-off floor; rows printed as machine-precision artefacts are not pins)."""
+    g = _load("linear_test_eoc.json")
+    Ns = {2: [8, 16, 32, 64, 128, 256, 512], 3: [8, 16, 32, 64, 128], 4: [8, 16, 32, 64, 128, 256]}[Nt]
+    for form, col in ((orc.FORM_RK, "lobatto"), (orc.FORM_DG, "dgsem")):
+        res = {n: _linear_test_run(orc, Nt, n, form) for n in Ns}
+        pw = g["pointwise"][str(Nt)]
+        for N, ref in zip(pw["N"], pw[col]):
+            if N not in res or N // 2 not in res:
+                continue
+            e1, e2 = res[N // 2][0], res[N][0]
+            if min(e1, e2) < 1e-10:      # round-off dominated row
+                continue
+            tol = 0.01 if min(e1, e2) > 1e-9 else 0.03
+            assert abs(math.log2(e1 / e2) - ref) <= tol, (Nt, col, N, math.log2(e1 / e2), ref)
+        l2 = g["l2"][str(Nt)]
+        for N, ref in zip(l2["N"], l2[col]):
+            if N not in res or N // 2 not in res:
+                continue
+            e1, e2 = res[N // 2][1], res[N][1]
+            if min(e1, e2) < 1e-12:
+                continue
+            assert abs(math.log2(e1 / e2) - ref) <= 0.011, (Nt, col, N, math.log2(e1 / e2), ref)
+
+
+# ---------------------------------------------------------------------------
+# helpers for PDE problems
+# ---------------------------------------------------------------------------
+CASES = {
+    "adv1": dict(dim=1, K=[5], N=3, Nt=3, eq=1, kw=dict(a=(1.0,))),
+    "adv2": dict(dim=2, K=[3, 4], N=2, Nt=2, eq=1, kw=dict(a=(1.0, -0.5))),
+    "advdiff2": dict(dim=2, K=[3, 3], N=3, Nt=4, eq=2, kw=dict(a=(1.0, 0.5), nu=0.02)),
+    "burgers1": dict(dim=1, K=[6], N=4, Nt=3, eq=3, kw={}),
+    "euler2": dict(dim=2, K=[3, 3], N=2, Nt=3, eq=4, kw=dict(gamma=1.4)),
+    "euler1": dict(dim=1, K=[4], N=3, Nt=2, eq=4, kw=dict(gamma=1.4)),
+    "euler3": dict(dim=3, K=[2, 2, 2], N=1, Nt=2, eq=4, kw=dict(gamma=1.4)),
+    "ns3": dict(dim=3, K=[2, 2, 2], N=2, Nt=2, eq=5, kw=dict(gamma=1.4, mu=0.02, prandtl=0.71)),
+    "ns2": dict(dim=2, K=[3, 2], N=2, Nt=3, eq=5, kw=dict(gamma=1.4, mu=0.05, prandtl=0.71)),
+}
+
+
+def make(orc, name, lo=None, hi=None):
+    c = CASES[name]
+    d = c["dim"]
+    lo = lo or [0.0] * d
+    hi = hi or [1.0] * d
+    p = orc.problem(d, c["K"], lo, hi, c["N"], c["Nt"], c["eq"], **c["kw"])
+    nv = orc.nvars(c["eq"], d)
+    ns = (c["N"] + 1) ** d
+    E = int(np.prod(c["K"]))
+    return p, E, nv, ns, c["Nt"]
+
+
+def phys_weights(orc, p):
+    x, w, _ = orc.lgl(p.N + 1)
+    n1 = p.N + 1
+    ns = n1 ** p.dim
+    W = np.ones(ns)
+    for s in range(ns):
+        for a in range(p.dim):
+            i = (s // n1 ** a) % n1
+            W[s] *= 0.5 * (p.hi[a] - p.lo[a]) / p.K[a] * w[i]
+    return W
+
+
+# ---------------------------------------------------------------------------
+# P7: equivalence of the three formulations
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("name", list(CASES))
+def test_residual_identities(orc, name):
+    """R = -((M D + e1 e1^T) (x) I) R_RK (Sec. "DG-SEM and Lobatto IIIC") and
+    R_Gal = (I (x) M_xi^phys) R (weak vs strong form, SBP) for random states."""
+    p, E, nv, ns, Nt = make(orc, name)
+    U, up, _ = inputs.random_slab(p.eq, p.dim, E, nv, Nt, ns, seed=11)
+    dt = 0.07
+    R = orc.residual(p, U, up, dt, orc.FORM_DG).reshape(E, nv, Nt, ns)
+    Rrk = orc.residual(p, U, up, dt, orc.FORM_RK).reshape(E, nv, Nt, ns)
+    Rg = orc.residual(p, U, up, dt, orc.FORM_GALERKIN).reshape(E, nv, Nt, ns)
+    _, w, D = orc.lgl(Nt)
+    T = -(np.diag(w) @ D + np.outer(np.eye(Nt)[0], np.eye(Nt)[0]))
+    scale = np.abs(R).max()
+    assert np.abs(np.einsum("jk,evks->evjs", T, Rrk) - R).max() < 1e-13 * scale
+    W = phys_weights(orc, p)
+    assert np.abs(Rg - R * W).max() < 1e-13 * np.abs(Rg).max()
+
+
+@pytest.mark.parametrize("name", ["adv1", "adv2", "advdiff2", "burgers1", "euler2"])
+def test_stdg_and_lodg_same_solution(orc, name):
+    """Both nonlinear systems (eqs. (DG_vs_RK:DG), (DG_vs_RK:RK)) have the same
+    solution when solved exactly (direct linear solves)."""
+    p, E, nv, ns, Nt = make(orc, name)
+    if p.eq == orc.EULER:
+        X = orc.node_coords(p)
+        rho = 1.0 + 0.2 * np.sin(2 * np.pi * X[:, 0, :]) * np.cos(2 * np.pi * X[:, 1, :])
+        up = inputs.euler_conservative(rho, [0.5 + 0 * rho, -0.3 + 0 * rho], 1.0 + 0 * rho, 1.4).ravel()
+    else:
+        _, up, _ = inputs.random_slab(p.eq, p.dim, E, nv, Nt, ns, seed=5)
+        if p.eq == orc.BURGERS:
+            up = 0.5 + 0.1 * (up - 0.5)
+    dt = 0.05
+    U1, s1 = orc.solve(p, up, dt, tol=1e-14, form=orc.FORM_DG, dense_limit=5000)
+    U2, s2 = orc.solve(p, up, dt, tol=1e-14, form=orc.FORM_RK, dense_limit=5000)
+    assert s1["converged"] and s2["converged"]
+    assert np.linalg.norm(U1 - U2) <= 1e-12 * np.linalg.norm(U1)
+
+
+def test_gmres_path_matches_direct(orc):
+    """The oracle's own MGS-GMRES Newton path reaches the direct-solve solution."""
+    p, E, nv, ns, Nt = make(orc, "euler2")
+    X = orc.node_coords(p)
+    rho = 1.0 + 0.2 * np.sin(2 * np.pi * X[:, 0, :])
+    up = inputs.euler_conservative(rho, [0.4 + 0 * rho, 0.2 + 0 * rho], 1.0 + 0 * rho, 1.4).ravel()
+    U1, s1 = orc.solve(p, up, 0.05, tol=1e-13, dense_limit=5000)
+    U2, s2 = orc.solve(p, up, 0.05, tol=1e-13, dense_limit=0)
+    assert s2["linear_its"] > 0
+    assert np.linalg.norm(U1 - U2) <= 1e-11 * np.linalg.norm(U1)
+
+
+# ---------------------------------------------------------------------------
+# P8, P9: conservation and free-stream preservation
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("name", list(CASES))
+def test_discrete_conservation(orc, name):
+    """Periodic mesh, any U: sum_e W^T sum_j R_j = mass(u^n) - mass(u^Nt)
+    (SBP in time, telescoping single-valued interface fluxes in space)."""
+    p, E, nv, ns, Nt = make(orc, name)
+    U, up, _ = inputs.random_slab(p.eq, p.dim, E, nv, Nt, ns, seed=3)
+    R = orc.residual(p, U, up, 0.11).reshape(E, nv, Nt, ns)
+    W = phys_weights(orc, p)
+    lhs = np.einsum("evjs,s->v", R, W)
+    rhs = np.einsum("evs,s->v", up.reshape(E, nv, ns), W) - np.einsum(
+        "evs,s->v", U.reshape(E, nv, Nt, ns)[:, :, -1, :], W)
+    assert np.abs(lhs - rhs).max() < 1e-13 * max(1.0, np.abs(U).max() * E)
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_free_stream(orc, name):
+    """A constant state with u^n equal to it is an exact slab solution: R = 0."""
+    p, E, nv, ns, Nt = make(orc, name)
+    if p.eq in (orc.EULER, orc.NS_BR1):
+        c = np.array([1.2] + [0.3, -0.4, 0.2][:p.dim] + [3.1])
+    else:
+        c = np.array([0.7])
+    U = np.broadcast_to(c[None, :, None, None], (E, nv, Nt, ns)).ravel()
+    up = np.broadcast_to(c[None, :, None], (E, nv, ns)).ravel()
+    R = orc.residual(p, U, up, 0.13)
+    assert np.abs(R).max() < 1e-13 * np.abs(c).max()
+
+
+# ---------------------------------------------------------------------------
+# P10: polynomial exactness
+# ---------------------------------------------------------------------------
+def test_polynomial_exactness_advection(orc):
+    """u = p(x - a t) with deg p <= min(N, Nt-1) solves the slab system exactly
+    on every element not touching the periodic seam (2D, a = (1, -0.5))."""
+    N, Nt, K = 3, 3, 6
+    a = (1.0, -0.5)
+    p = orc.problem(2, [K, K], [0, 0], [1, 1], N, Nt, orc.ADVECTION, a=a)
+    X = orc.node_coords(p)
+    tau, _, _ = orc.lgl(Nt)
+    dt, t0 = 0.1, 0.0
+    poly = lambda x, y: 0.3 + 1.7 * x - 0.4 * y + 0.9 * x * y - 0.6 * x * x
+    ns = (N + 1) ** 2
+    U = np.zeros((K * K, 1, Nt, ns))
+    for j in range(Nt):
+        t = t0 + 0.5 * dt * (1 + tau[j])
+        U[:, 0, j, :] = poly(X[:, 0, :] - a[0] * t, X[:, 1, :] - a[1] * t)
+    up = poly(X[:, 0, :] - a[0] * t0, X[:, 1, :] - a[1] * t0)
+    R = orc.residual(p, U.ravel(), up.ravel(), dt).reshape(K, K, Nt, ns)   # [ey][ex]
+    inner = R[1:-1, 1:-1]
+    assert np.abs(inner).max() < 1e-12
+    assert np.abs(R).max() > 1e-3    # the seam does see the jump
+
+
+def test_polynomial_exactness_advdiff(orc):
+    """Advection-diffusion with BR1: u = xi^2 + 2 nu t, xi = x - a t, is an exact
+    solution of degree 2 in x and in t; R = 0 two elements off the seam."""
+    N, Nt, K, nu, a = 3, 3, 8, 0.05, 0.7
+    p = orc.problem(1, [K], [0], [1], N, Nt, orc.ADVDIFF_BR1, a=(a,), nu=nu)
+    X = orc.node_coords(p)
+    tau, _, _ = orc.lgl(Nt)
+    dt = 0.1
+    ex = lambda x, t: (x - a * t) ** 2 + 2 * nu * t
+    U = np.zeros((K, 1, Nt, N + 1))
+    for j in range(Nt):
+        U[:, 0, j, :] = ex(X[:, 0, :], 0.5 * dt * (1 + tau[j]))
+    R = orc.residual(p, U.ravel(), ex(X[:, 0, :], 0.0).ravel(), dt).reshape(K, Nt, N + 1)
+    assert np.abs(R[2:-2]).max() < 1e-12
+    assert np.abs(R).max() > 1e-3
+
+
+# ---------------------------------------------------------------------------
+# P11: design order of accuracy
+# ---------------------------------------------------------------------------
+def test_advection_design_order(orc):
+    """1D advection of sin 2 pi (x - t) over T = 0.25 with a temporal error far
+    below the spatial one: L2 error converges at about N + 1."""
+    N, Nt = 3, 4
+    errs = []
+    for K in (4, 8, 16):
+        p = orc.problem(1, [K], [0], [1], N, Nt, orc.ADVECTION, a=(1.0,))
+        X = orc.node_coords(p)
+        W = phys_weights(orc, p)
+        u = np.sin(2 * np.pi * X[:, 0, :]).ravel()
+        nsteps = 8
+        dt = 0.25 / nsteps
+        for _ in range(nsteps):
+            U, st = orc.solve(p, u, dt, tol=1e-14)
+            u = orc.last_time_node(p, U)
+        ex = np.sin(2 * np.pi * (X[:, 0, :] - 0.25))
+        errs.append(math.sqrt(np.sum(W * (u.reshape(K, -1) - ex) ** 2)))
+    eoc = [math.log2(errs[i] / errs[i + 1]) for i in range(2)]
+    assert eoc[-1] > N + 0.6, eoc
+
+
+def test_temporal_superconvergence_pde(orc):
+    """Slab-end temporal order 2(Nt-1) on a fine spatial mesh (advection of a
+    sine, dt halved)."""
+    N, Nt, K = 7, 2, 8
+    p = orc.problem(1, [K], [0], [1], N, Nt, orc.ADVECTION, a=(1.0,))
+    X = orc.node_coords(p)
+    errs = []
+    for nsteps in (4, 8, 16):
+        u = np.sin(2 * np.pi * X[:, 0, :]).ravel()
+        dt = 0.5 / nsteps
+        for _ in range(nsteps):
+            U, _ = orc.solve(p, u, dt, tol=1e-14)
+            u = orc.last_time_node(p, U)
+        errs.append(np.abs(u.reshape(K, -1) - np.sin(2 * np.pi * (X[:, 0, :] - 0.5))).max())
+    eoc = math.log2(errs[1] / errs[2])
+    assert abs(eoc - 2 * (Nt - 1)) < 0.15, (errs, eoc)
+
+
+def test_euler_vortex_truncation_order(orc):
+    """Isentropic vortex (exact translating solution of the Euler equations):
+    the truncation error F(I u) - I(u_t) of the spatial operator decays at
+    order N in h (rms over nodes), u_t from the exact solution."""
+    N = 3
+    errs = []
+    for K in (8, 16, 32):
+        p = orc.problem(2, [K, K], [-5, -5], [5, 5], N, 3, orc.EULER, gamma=1.4)
+        X = orc.node_coords(p)
+        u0 = inputs.isentropic_vortex(X, noise=0.0)
+        F = orc.spatial_op(p, u0.ravel()).reshape(u0.shape)
+        e = 1e-5
+        ut = (inputs.isentropic_vortex(X, noise=0.0, t=e) - inputs.isentropic_vortex(X, noise=0.0, t=-e)) / (2 * e)
+        errs.append(math.sqrt(np.mean((F - ut) ** 2)))
+    assert math.log2(errs[1] / errs[2]) > N - 0.25, errs
+
+
+# ---------------------------------------------------------------------------
+# pointwise physics pins
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("d", [1, 2, 3])
+def test_euler_flux_jacobian_eigenvalues(orc, d):
+    """The Euler flux Jacobian along x_a has eigenvalues v_a - c, v_a (d-fold),
+    v_a + c (finite differences of the oracle's flux, no dual numbers)."""
+    p = orc.problem(d, [1] * d, [0] * d, [1] * d, 1, 2, orc.EULER, gamma=1.4)
+    rho, vel, pr = 1.3, np.array([0.4, -0.7, 0.25])[:d], 2.1
+    u = inputs.euler_conservative(np.array([rho]), [np.array([v]) for v in vel], np.array([pr]), 1.4)[0]
+    c = math.sqrt(1.4 * pr / rho)
+    for a in range(d):
+        J = np.zeros((d + 2, d + 2))
+        for k in range(d + 2):
+            e = np.zeros(d + 2)
+            e[k] = 1e-6
+            J[:, k] = (orc.flux(p, a, u + e) - orc.flux(p, a, u - e)) / 2e-6
+        ev = np.sort(np.linalg.eigvals(J).real)
+        ref = np.sort([vel[a] - c] + [vel[a]] * d + [vel[a] + c])
+        assert np.abs(ev - ref).max() < 1e-6
+
+
+def test_rusanov_consistency_and_upwinding(orc):
+    """H(u, u) = f(u) for every equation; for advection with a > 0 the Rusanov
+    flux is the upwind flux a u_L, and for a < 0 it is a u_R."""
+    for name in CASES:
+        p, E, nv, ns, Nt = make(orc, name)
+        u = np.array([1.1] + [0.2, -0.3, 0.1][:p.dim] + [2.9]) if nv > 1 else np.array([0.8])
+        q = np.linspace(-1, 1, p.dim * nv)
+        for a in range(p.dim):
+            assert np.allclose(orc.num_flux(p, a, u, u, q, q), orc.flux(p, a, u, q), atol=1e-14)
+    for av in (1.3, -0.8):
+        p = orc.problem(1, [1], [0], [1], 1, 2, orc.ADVECTION, a=(av,))
+        uL, uR = np.array([0.9]), np.array([-0.4])
+        H = orc.num_flux(p, 0, uL, uR)
+        assert abs(H[0] - av * (uL[0] if av > 0 else uR[0])) < 1e-15
+
+
+def test_burgers_rusanov_wave_speed(orc):
+    """Burgers: lambda = max(|uL|, |uR|) in H = {u^2/2} + lambda/2 (uL - uR)."""
+    p = orc.problem(1, [1], [0], [1], 1, 2, orc.BURGERS)
+    for uL, uR in ((0.3, -0.9), (1.2, 0.5), (-0.2, 0.1)):
+        lam = max(abs(uL), abs(uR))
+        H = orc.num_flux(p, 0, np.array([uL]), np.array([uR]))[0]
+        assert abs(H - (0.25 * (uL ** 2 + uR ** 2) + 0.5 * lam * (uL - uR))) < 1e-15
+
+
+def test_br1_diffusion_of_sine(orc):
+    """Advection-diffusion with a = 0: F(sin 2 pi x) -> -nu (2 pi)^2 sin 2 pi x
+    at high order (BR1 sign and scale)."""
+    errs = []
+    nu = 0.3
+    for K in (8, 16):
+        p = orc.problem(1, [K], [0], [1], 4, 2, orc.ADVDIFF_BR1, a=(0.0,), nu=nu)
+        X = orc.node_coords(p)
+        F = orc.spatial_op(p, np.sin(2 * np.pi * X[:, 0, :]).ravel())
+        ex = -nu * (2 * np.pi) ** 2 * np.sin(2 * np.pi * X[:, 0, :]).ravel()
+        errs.append(np.abs(F - ex).max() / np.abs(ex).max())
+    assert errs[1] < 1e-3 and errs[0] / errs[1] > 6   # BR1 max-norm rate is about N - 1
+
+
+def _ns_problem(orc, d, K, N, mu=0.01, pr=0.71):
+    L = 2 * np.pi
+    return orc.problem(d, [K] * d, [0] * d, [L] * d, N, 2, orc.NS_BR1, gamma=1.4, mu=mu, prandtl=pr)
+
+
+def _euler_twin(orc, p):
+    return orc.problem(p.dim, list(p.K)[:p.dim], list(p.lo)[:p.dim], list(p.hi)[:p.dim], p.N, p.Nt,
+                       orc.EULER, gamma=p.gamma)
+
+
+def test_ns_rigid_rotation_is_stress_free(orc):
+    """Rigid rotation v = w x r with uniform rho and T: the viscous stress and
+    heat flux vanish, so NS and Euler spatial operators coincide (2D, away
+    from the non-periodic velocity seam)."""
+    K, N = 6, 3
+    p = orc.problem(2, [K, K], [-1, -1], [1, 1], N, 2, orc.NS_BR1, gamma=1.4, mu=0.3, prandtl=0.71)
+    X = orc.node_coords(p)
+    x, y = X[:, 0, :], X[:, 1, :]
+    rho = np.ones_like(x)
+    u = inputs.euler_conservative(rho, [-0.5 * y, 0.5 * x], 2.0 + 0 * x, 1.4)
+    Fns = orc.spatial_op(p, u.ravel()).reshape(K, K, 4, -1)
+    Feu = orc.spatial_op(_euler_twin(orc, p), u.ravel()).reshape(K, K, 4, -1)
+    assert np.abs(Fns - Feu)[2:-2, 2:-2].max() < 1e-11
+
+
+def test_ns_viscous_dissipation(orc):
+    """v = (sin x, 0, 0), rho = 1, uniform pressure on [0, 2pi]^3: the viscous
+    work sum W v . F_visc tends to -mu (4/3) int cos^2 x = -(4/3) mu (2pi)^3 / 2
+    (compressible stress with the Stokes hypothesis)."""
+    mu = 0.01
+    vals = []
+    for K in (3, 6):
+        p = _ns_problem(orc, 3, K, 3, mu=mu)
+        X = orc.node_coords(p)
+        x = X[:, 0, :]
+        one = np.ones_like(x)
+        u = inputs.euler_conservative(one, [np.sin(x), 0 * x, 0 * x], 5.0 * one, 1.4)
+        Fv = (orc.spatial_op(p, u.ravel()) - orc.spatial_op(_euler_twin(orc, p), u.ravel())).reshape(u.shape)
+        W = phys_weights(orc, p)
+        vals.append(np.sum(W * np.sin(x) * Fv[:, 1, :]))
+    ref = -(4.0 / 3.0) * mu * (2 * np.pi) ** 3 / 2
+    assert abs(vals[-1] - ref) < 1e-3 * abs(ref), (vals, ref)
+
+
+def test_ns_heat_conduction(orc):
+    """rho = 1, v = 0, T = T0 + eps sin x: the energy equation reduces to
+    dE/dt = kappa T_xx with kappa = mu gamma / ((gamma - 1) Pr)."""
+    mu, pr, g, eps = 0.02, 0.71, 1.4, 0.1
+    p = orc.problem(1, [12], [0], [2 * np.pi], 4, 2, orc.NS_BR1, gamma=g, mu=mu, prandtl=pr)
+    X = orc.node_coords(p)
+    x = X[:, 0, :]
+    T = 3.0 + eps * np.sin(x)
+    u = inputs.euler_conservative(np.ones_like(x), [0 * x], T, g)     # p = rho T
+    F = orc.spatial_op(p, u.ravel()).reshape(u.shape)
+    kappa = mu * g / ((g - 1) * pr)
+    ref = -kappa * eps * np.sin(x)
+    assert np.abs(F[:, 2, :] - ref).max() < 5e-3 * np.abs(ref).max()
+
+
+# ---------------------------------------------------------------------------
+# P12, P13: Jacobian-vector products
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("name", list(CASES))
+def test_jvp_central_difference(orc, name):
+    """J v matches (R(U + e v) - R(U - e v)) / 2e to O(e^2)."""
+    p, E, nv, ns, Nt = make(orc, name)
+    U, up, V = inputs.random_slab(p.eq, p.dim, E, nv, Nt, ns, seed=21)
+    dt = 0.05
+    for form in (orc.FORM_DG, orc.FORM_RK):
+        J = orc.jvp(p, U, dt, V, form)
+        e = 1e-5
+        fd = (orc.residual(p, U + e * V, up, dt, form) - orc.residual(p, U - e * V, up, dt, form)) / (2 * e)
+        assert np.abs(fd - J).max() < 1e-7 * np.abs(J).max()
+
+
+@pytest.mark.parametrize("name", ["adv1", "advdiff2"])
+def test_linear_jvp_is_residual(orc, name):
+    """Linear equations: J v = R(v) with u^n = 0."""
+    p, E, nv, ns, Nt = make(orc, name)
+    U, up, V = inputs.random_slab(p.eq, p.dim, E, nv, Nt, ns, seed=8)
+    J = orc.jvp(p, U, 0.1, V)
+    R = orc.residual(p, V, np.zeros_like(up), 0.1)
+    assert np.abs(J - R).max() < 1e-13 * np.abs(R).max()
+
+
+@pytest.mark.parametrize("name", ["adv1", "burgers1", "euler1"])
+def test_jacobian_block_structure(orc, name):
+    """Brute force on a tiny slab: the Jacobian assembled column by column
+    equals eq. (Jacobian_ST), (D^T M - e_Nt e_Nt^T) (x) I + dt/2 (M (x) J_F),
+    with J_F assembled from the spatial operator by finite differences."""
+    p, E, nv, ns, Nt = make(orc, name)
+    U, up, _ = inputs.random_slab(p.eq, p.dim, E, nv, Nt, ns, seed=4)
+    dt = 0.09
+    n = U.size
+    m = E * nv * ns
+    Jfull = np.stack([orc.jvp(p, U, dt, np.eye(n)[k]) for k in range(n)], axis=1)
+    _, w, D = orc.lgl(Nt)
+    T = D.T @ np.diag(w)
+    T[-1, -1] -= 1.0
+    U4 = U.reshape(E, nv, Nt, ns)
+    # index maps between slab ordering and (time, spatial index)
+    idx = np.arange(n).reshape(E, nv, Nt, ns)
+    pred = np.zeros((n, n))
+    for j in range(Nt):
+        uj = np.ascontiguousarray(U4[:, :, j, :]).ravel()
+        JF = np.zeros((m, m))
+        for k in range(m):
+            e = np.zeros(m)
+            e[k] = 1e-6
+            JF[:, k] = (orc.spatial_op(p, uj + e) - orc.spatial_op(p, uj - e)) / 2e-6
+        rows = idx[:, :, j, :].ravel()
+        pred[np.ix_(rows, rows)] += 0.5 * dt * w[j] * JF
+        for k in range(Nt):
+            pred[idx[:, :, j, :].ravel(), idx[:, :, k, :].ravel()] += T[j, k]
+    assert np.abs(Jfull - pred).max() < 1e-7 * np.abs(Jfull).max()
+    # same sparsity (entries below 1e-8 are finite-difference noise in pred)
+    assert np.array_equal(np.abs(Jfull) > 1e-8, np.abs(pred) > 1e-8)
