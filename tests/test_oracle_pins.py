@@ -471,15 +471,16 @@ def _euler_twin(orc, p):
 
 
 def test_ns_rigid_rotation_is_stress_free(orc):
-    """Rigid rotation v = w x r with uniform rho and T: the viscous stress and
-    heat flux vanish, so NS and Euler spatial operators coincide (2D, away
-    from the non-periodic velocity seam)."""
+    """Rigid rotation v = w x r with uniform temperature and a linear density
+    (every conservative variable a polynomial of degree <= N): the viscous
+    stress and heat flux vanish, so NS and Euler spatial operators coincide
+    (2D, away from the non-periodic seam)."""
     K, N = 6, 3
     p = orc.problem(2, [K, K], [-1, -1], [1, 1], N, 2, orc.NS_BR1, gamma=1.4, mu=0.3, prandtl=0.71)
     X = orc.node_coords(p)
     x, y = X[:, 0, :], X[:, 1, :]
-    rho = np.ones_like(x)
-    u = inputs.euler_conservative(rho, [-0.5 * y, 0.5 * x], 2.0 + 0 * x, 1.4)
+    rho = 1.0 + 0.2 * x - 0.1 * y
+    u = inputs.euler_conservative(rho, [-0.5 * y, 0.5 * x], 2.0 * rho, 1.4)   # T = p / rho = 2
     Fns = orc.spatial_op(p, u.ravel()).reshape(K, K, 4, -1)
     Feu = orc.spatial_op(_euler_twin(orc, p), u.ravel()).reshape(K, K, 4, -1)
     assert np.abs(Fns - Feu)[2:-2, 2:-2].max() < 1e-11
@@ -505,18 +506,44 @@ def test_ns_viscous_dissipation(orc):
 
 
 def test_ns_heat_conduction(orc):
-    """rho = 1, v = 0, T = T0 + eps sin x: the energy equation reduces to
-    dE/dt = kappa T_xx with kappa = mu gamma / ((gamma - 1) Pr)."""
+    """rho = 1, v = 0, T = T0 + eps (sin x + sin 2y) in 2D: the energy equation
+    reduces to dE/dt = kappa lap T with kappa = mu gamma / ((gamma - 1) Pr)."""
     mu, pr, g, eps = 0.02, 0.71, 1.4, 0.1
-    p = orc.problem(1, [12], [0], [2 * np.pi], 4, 2, orc.NS_BR1, gamma=g, mu=mu, prandtl=pr)
+    p = orc.problem(2, [10, 10], [0, 0], [2 * np.pi, 2 * np.pi], 4, 2, orc.NS_BR1, gamma=g, mu=mu, prandtl=pr)
     X = orc.node_coords(p)
-    x = X[:, 0, :]
-    T = 3.0 + eps * np.sin(x)
-    u = inputs.euler_conservative(np.ones_like(x), [0 * x], T, g)     # p = rho T
+    x, y = X[:, 0, :], X[:, 1, :]
+    T = 3.0 + eps * (np.sin(x) + np.sin(2 * y))
+    u = inputs.euler_conservative(np.ones_like(x), [0 * x, 0 * x], T, g)     # p = rho T
     F = orc.spatial_op(p, u.ravel()).reshape(u.shape)
     kappa = mu * g / ((g - 1) * pr)
-    ref = -kappa * eps * np.sin(x)
-    assert np.abs(F[:, 2, :] - ref).max() < 5e-3 * np.abs(ref).max()
+    ref = -kappa * eps * (np.sin(x) + 4 * np.sin(2 * y))
+    assert np.abs(F[:, 3, :] - ref).max() < 2e-2 * np.abs(ref).max()
+
+
+def test_euler_rusanov_wave_speed(orc):
+    """Euler: the dissipation coefficient in H = {f} + lambda/2 (uL - uR) is the
+    largest |eigenvalue| of the flux Jacobians of the two states (eigenvalues
+    from finite differences of the physical flux)."""
+    d = 2
+    p = orc.problem(d, [1, 1], [0, 0], [1, 1], 1, 2, orc.EULER, gamma=1.4)
+
+    def state(rho, vel, pr):
+        return inputs.euler_conservative(np.array([rho]), [np.array([v]) for v in vel], np.array([pr]), 1.4)[0]
+
+    def spectral_radius(u, a):
+        J = np.zeros((d + 2, d + 2))
+        for k in range(d + 2):
+            e = np.zeros(d + 2)
+            e[k] = 1e-6
+            J[:, k] = (orc.flux(p, a, u + e) - orc.flux(p, a, u - e)) / 2e-6
+        return np.abs(np.linalg.eigvals(J)).max()
+
+    uL, uR = state(1.0, [0.3, -0.6], 1.0), state(0.7, [-0.9, 0.2], 1.8)
+    for a in range(d):
+        H = orc.num_flux(p, a, uL, uR)
+        lam = 2 * (H - 0.5 * (orc.flux(p, a, uL) + orc.flux(p, a, uR))) / (uL - uR)
+        ref = max(spectral_radius(uL, a), spectral_radius(uR, a))
+        assert np.abs(lam - ref).max() < 1e-6
 
 
 # ---------------------------------------------------------------------------
