@@ -1,0 +1,211 @@
+/*
+ * st.h -- C ABI of the MI355X space-time DG-SEM slab library (libstdg.so).
+ *
+ * Method: Versbach, Linders, Kloefkorn, Birken, "Theoretical and Practical
+ * Aspects of Space-Time DG-SEM Implementations" (arXiv 2201.05800).
+ *
+ * One SLAB is one time element [t0, t0 + dt] of a periodic Cartesian spatial
+ * mesh (Sec. "Space-Time DG-SEM": the upwind flux in time decouples the time
+ * elements, so each is a stand-alone system).  The unknowns are the nodal
+ * values at the tensor LGL nodes of every space-time element, N + 1 nodes per
+ * space axis and Nt nodes in time (degree Nt - 1, the Remark after eq.
+ * (stsurfaceint)).  The library evaluates the slab residual, its exact
+ * Jacobian-vector product, and solves the slab system by Newton-GMRES; every
+ * step runs in hand-written HIP kernels for gfx950.
+ *
+ * CONVENTIONS
+ *   Pointers named U, R, v, Jv, u_prev, U_out, u_next are DEVICE pointers to
+ *   FP64 arrays owned by the caller (e.g. torch CUDA tensors); the library
+ *   keeps none of them after the call returns.  `stream` is a hipStream_t
+ *   (NULL = default stream); every call is asynchronous on that stream
+ *   unless stated otherwise.
+ *
+ *   Slab vector layout (length n = E * nv * Nt * ns):
+ *       index = ((e * nv + var) * Nt + j) * ns + s
+ *   e = ex + Kx * (ey + Ky * ez) (element, x fastest), j = time node,
+ *   s = ix + n1 * (iy + n1 * iz) (spatial node, x fastest), n1 = N + 1,
+ *   ns = n1^dim.  This is a permutation of the coefficient vector
+ *   (u^1, ..., u^Nt) of eq. (StCoeff); node order does not change the
+ *   solution (Sec. "Algorithmic Aspects").
+ *   Spatial vectors (u_prev, u_next): index = (e * nv + var) * ns + s.
+ *
+ *   Return codes: ST_OK (0) or a negative ST_ERR_*; st_last_error() gives a
+ *   thread-local message.  No C++ exception crosses this boundary.
+ */
+#ifndef ST_H
+#define ST_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define ST_OK 0
+#define ST_PENDING 1
+#define ST_ERR_BAD_ARG (-1)        /* invalid handle, size, pointer or option  */
+#define ST_ERR_HIP (-2)            /* a HIP runtime call failed               */
+#define ST_ERR_NONFINITE (-3)      /* NaN/Inf in an input or in a residual    */
+#define ST_ERR_NO_CONVERGENCE (-4) /* Newton/GMRES limit reached              */
+#define ST_ERR_OOM_ADMISSION (-5)  /* request larger than the server's budget */
+#define ST_ERR_UNSUPPORTED (-6)    /* (eq, dim, N, Nt) not compiled in        */
+#define ST_ERR_NOT_FOUND (-7)      /* unknown ticket                          */
+#define ST_ERR_CANCELLED (-8)      /* ticket cancelled before completion      */
+
+/* Periodic Cartesian mesh, cf. cartesianDomain(lower, upper, counts) in
+ * Sec. "DG-SEM in Space".  Every axis is periodic. */
+typedef struct {
+    int dim;          /* 1, 2 or 3 */
+    int K[3];         /* elements per axis (unused axes: 1) */
+    double lo[3];     /* lower corner */
+    double hi[3];     /* upper corner */
+} st_mesh_t;
+
+/* u_t + div(Fc(u) - Fv(u, grad u)) = 0, eq. (general) without source. */
+typedef enum {
+    ST_ADVECTION = 1,   /* Fc = a u; Rusanov = upwind                       */
+    ST_ADVDIFF_BR1 = 2, /* Fc = a u, Fv = nu grad u; BR1 viscous flux        */
+    ST_BURGERS = 3,     /* Fc = u^2 / 2, dim = 1                             */
+    ST_EULER = 4,       /* compressible Euler, Sec. "Euler Equations"        */
+    ST_NS_BR1 = 5       /* compressible Navier-Stokes (constant mu, Stokes   */
+                        /* hypothesis, T = p / rho, Fourier heat flux), BR1  */
+} st_eq_kind_t;
+
+typedef struct {
+    int kind;         /* st_eq_kind_t */
+    double a[3];      /* advection velocity (ADVECTION, ADVDIFF_BR1) */
+    double nu;        /* diffusivity (ADVDIFF_BR1) */
+    double gamma;     /* ratio of specific heats (EULER, NS_BR1) */
+    double mu;        /* dynamic viscosity (NS_BR1) */
+    double prandtl;   /* Prandtl number (NS_BR1) */
+} st_equation_t;
+
+/* Newton-GMRES options (the paper names Newton-GMRES, Sec. "Euler
+ * Equations"; everything below is this library's choice). */
+typedef struct {
+    int restart;       /* GMRES restart length m, 1..32 (default 30)            */
+    int max_newton;    /* outer iterations; each is one residual evaluation and */
+                       /* one GMRES cycle of at most m steps (default 60)       */
+    int cgs_passes;    /* classical Gram-Schmidt passes, 1 or 2 (default 2)     */
+    int inner_fp32;    /* 1: JVPs in FP32 (state, math, accumulation); the      */
+                       /* residual, Arnoldi and update stay FP64                */
+    double gmres_rtol; /* minimum inner forcing term eta (default 1e-3; raised  */
+                       /* to 1e-5 at least when inner_fp32)                     */
+} st_solver_opts_t;
+
+typedef struct {
+    int newton_its;    /* outer iterations done */
+    int gmres_its;     /* Arnoldi steps summed over all cycles */
+    double res0;       /* ||R(U0)||_2, U0 = 1 (x) u_prev */
+    double res_final;  /* ||R(U)||_2 at return */
+    double usec;       /* wall time of the call (host clock, includes syncs) */
+    int status;        /* ST_OK or ST_ERR_NO_CONVERGENCE / ST_ERR_NONFINITE */
+} st_stats_t;
+
+typedef struct st_ctx* st_handle_t;
+typedef struct st_srv* st_server_t;
+
+/* Library version string. */
+const char* st_version(void);
+/* Thread-local text of the last error. */
+const char* st_last_error(void);
+
+/* Default solver options. */
+void st_default_opts(st_solver_opts_t* opts);
+
+/* Host-side LGL nodes x[n], weights w[n] and differentiation matrix
+ * D[j * n + k] = l_k'(x_j) (Sec. "DG-SEM in Space"; eq. (DG_in_time) for the
+ * temporal D_tau).  n in 2..8.  No GPU needed. */
+int st_lgl(int n, double* x, double* w, double* D);
+
+/* Create a handle for one (mesh, N, Nt, equation).  N in 1..5 (1..4 for
+ * dim 3; 1..4 for EULER / NS_BR1), Nt in 2..4.  Allocates device workspace
+ * on the current device.  Returns ST_ERR_UNSUPPORTED for combinations that
+ * are not compiled in. */
+int st_create(const st_mesh_t* mesh, int N, int Nt, const st_equation_t* eq, st_handle_t* out);
+int st_destroy(st_handle_t h);
+
+/* Sizes: n_slab = E * nv * Nt * ns unknowns, n_space = E * nv * ns, nv. */
+int st_sizes(st_handle_t h, int64_t* n_slab, int64_t* n_space, int* nv);
+
+/* Host: physical coordinates of the spatial nodes, X[(e * dim + a) * ns + s]. */
+int st_node_coords(st_handle_t h, double* X);
+
+/* Slab residual (eq. (DG_vs_RK:DG) as right side minus left side):
+ *   R = (D_tau^T M_tau (x) I) U - (B_tau (x) I) U* + dt/2 (M_tau (x) I) F(U),
+ * upwind U* = (u_prev, 0, ..., 0, u^Nt) (eq. (upwind_flux)), F = M^-1 L_h the
+ * DG-SEM spatial operator (Rusanov convective flux, BR1 viscous flux).  Its
+ * Jacobian is exactly eq. (Jacobian_ST).  t0 is accepted for the ABI's
+ * completeness; the supported equations are autonomous. */
+int st_residual(st_handle_t h, const double* U, const double* u_prev, double t0, double dt,
+                double* R, void* stream);
+
+/* Jv = dR/dU (U) v, eq. (Jacobian_ST), exact linearisation (active branch of
+ * the Rusanov max, d|x|/dx = sign(x), sign(0) = +1).  inner_fp32 = 1
+ * evaluates it with FP32 state, arithmetic and accumulation (v read as FP64
+ * and rounded, Jv written as FP64). */
+int st_jvp(st_handle_t h, const double* U, double t0, double dt, const double* v, double* Jv,
+           int inner_fp32, void* stream);
+
+/* Solve R(U) = 0 for one slab by Newton-GMRES from U0 = 1 (x) u_prev; stops
+ * when ||R(U)||_2 <= tol * max(1, ||R(U0)||_2).  Writes the whole slab
+ * U_out (may be NULL) and the end-of-slab state u_next = (e_Nt^T (x) I) U
+ * (eq. (un); may be NULL).  Synchronises `stream` once per outer iteration.
+ * On ST_ERR_NO_CONVERGENCE the last iterate is written and stats filled. */
+int st_solve_slab(st_handle_t h, const double* u_prev, double t0, double dt, double tol,
+                  const st_solver_opts_t* opts, double* U_out, double* u_next, st_stats_t* stats,
+                  void* stream);
+
+/* ---------------------------------------------------------------------------
+ * Serving: continuous batching of independent slab solves.
+ * A server owns one HIP stream and a scheduler thread.  Requests are admitted
+ * while their device footprint fits the HBM budget and a slot is free; every
+ * scheduler tick advances each admitted request by one outer iteration, with
+ * the operator kernels grouped per (equation, dim, N, Nt, precision) and the
+ * Krylov kernels batched over all requests.  Each request's arithmetic does
+ * not depend on what else is in the batch (per-request reductions in a fixed
+ * order), so a result is bitwise the same alone and in a mix.
+ * ------------------------------------------------------------------------- */
+typedef struct {
+    int64_t hbm_budget_bytes;  /* device memory the server may hold for requests */
+    int max_active;            /* admitted requests at most (slots)              */
+    int device;                /* HIP device ordinal                              */
+} st_server_opts_t;
+
+typedef struct {
+    st_mesh_t mesh;
+    int N, Nt;
+    st_equation_t eq;
+    const double* u_prev;      /* HOST pointer, n_space doubles, copied at submit */
+    double t0, dt, tol;
+    st_solver_opts_t opts;
+} st_request_t;
+
+typedef struct {
+    int status;                /* ST_OK, ST_ERR_NO_CONVERGENCE, ST_ERR_NONFINITE ... */
+    double* u_next;            /* HOST buffer of n_space doubles supplied by caller */
+    st_stats_t stats;
+    double submit_us, admit_us, done_us;   /* server clock (microseconds)  */
+} st_result_t;
+
+int st_server_create(const st_server_opts_t* opts, st_server_t* out);
+/* Stops the scheduler thread (pending requests are cancelled) and frees all. */
+int st_server_destroy(st_server_t s);
+/* Copies *req (and u_prev) and enqueues it; never blocks on the GPU.
+ * ST_ERR_OOM_ADMISSION if the request alone exceeds the budget. */
+int st_submit(st_server_t s, const st_request_t* req, uint64_t* ticket);
+/* Non-blocking: ST_PENDING while queued or running; otherwise the final
+ * status, with u_next copied into out->u_next and the ticket released. */
+int st_poll(st_server_t s, uint64_t ticket, st_result_t* out);
+/* Cancel a queued or running request (its slot is freed at the next tick). */
+int st_cancel(st_server_t s, uint64_t ticket);
+/* Counters: queued, active, completed, ticks, bytes in use. */
+int st_server_stats(st_server_t s, int64_t* queued, int64_t* active, int64_t* completed,
+                    int64_t* ticks, int64_t* bytes_in_use);
+/* Device bytes a request would hold while admitted. */
+int64_t st_request_footprint(const st_request_t* req);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,286 @@
+// st_device.hpp -- device-side types and pointwise physics for the
+// space-time DG-SEM slab kernels (gfx950).
+//
+// Pointwise physics of eq. (general) without source: convective flux Fc,
+// its largest wave speed (for the Rusanov flux, eq. (flux:llf)), and the
+// viscous flux Fv(u, grad u) evaluated from the BR1 lifted gradient of the
+// conservative variables.  Everything is templated on the scalar so that the
+// same code gives residuals (double / float) and exact Jacobian-vector
+// products (forward-mode dual numbers Dual<double> / Dual<float>).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace stdg {
+
+constexpr int MMAX = 32;           // largest GMRES restart length
+constexpr int BLOCK = 256;         // threads per block of every kernel
+
+enum EqKind { EQ_ADV = 1, EQ_ADVDIFF = 2, EQ_BURGERS = 3, EQ_EULER = 4, EQ_NS = 5 };
+
+__host__ __device__ constexpr int nvars_of(int eq, int dim) {
+    return (eq == EQ_EULER || eq == EQ_NS) ? dim + 2 : 1;
+}
+__host__ __device__ constexpr bool viscous_eq(int eq) { return eq == EQ_ADVDIFF || eq == EQ_NS; }
+__host__ __device__ constexpr bool linear_eq(int eq) { return eq == EQ_ADV || eq == EQ_ADVDIFF; }
+__host__ __device__ constexpr int ipow(int b, int e) { return e == 0 ? 1 : b * ipow(b, e - 1); }
+
+// ---------------------------------------------------------------------------
+// forward-mode dual numbers  x + x' eps,  eps^2 = 0
+// ---------------------------------------------------------------------------
+template <class S>
+struct Dual {
+    S v, d;
+};
+template <class T> struct BaseOf { using type = T; };
+template <class S> struct BaseOf<Dual<S>> { using type = S; };
+
+#define SDI static __device__ __forceinline__
+#define DI __device__ __forceinline__
+
+template <class S> DI Dual<S> operator+(Dual<S> a, Dual<S> b) { return {a.v + b.v, a.d + b.d}; }
+template <class S> DI Dual<S> operator-(Dual<S> a, Dual<S> b) { return {a.v - b.v, a.d - b.d}; }
+template <class S> DI Dual<S> operator-(Dual<S> a) { return {-a.v, -a.d}; }
+template <class S> DI Dual<S> operator*(Dual<S> a, Dual<S> b) { return {a.v * b.v, a.d * b.v + a.v * b.d}; }
+template <class S> DI Dual<S> operator/(Dual<S> a, Dual<S> b) {
+    S r = S(1) / b.v;
+    S q = a.v * r;
+    return {q, (a.d - q * b.d) * r};
+}
+template <class S> DI Dual<S> operator+(Dual<S> a, S b) { return {a.v + b, a.d}; }
+template <class S> DI Dual<S> operator+(S a, Dual<S> b) { return {a + b.v, b.d}; }
+template <class S> DI Dual<S> operator-(Dual<S> a, S b) { return {a.v - b, a.d}; }
+template <class S> DI Dual<S> operator-(S a, Dual<S> b) { return {a - b.v, -b.d}; }
+template <class S> DI Dual<S> operator*(Dual<S> a, S b) { return {a.v * b, a.d * b}; }
+template <class S> DI Dual<S> operator*(S a, Dual<S> b) { return {a * b.v, a * b.d}; }
+template <class S> DI Dual<S> operator/(Dual<S> a, S b) { S r = S(1) / b; return {a.v * r, a.d * r}; }
+template <class S> DI Dual<S> operator/(S a, Dual<S> b) {
+    S r = S(1) / b.v;
+    S q = a * r;
+    return {q, -(q * b.d) * r};
+}
+
+DI double sqrt_(double x) { return sqrt(x); }
+DI float sqrt_(float x) { return sqrtf(x); }
+template <class S> DI Dual<S> sqrt_(Dual<S> a) {
+    S s = sqrt_(a.v);
+    return {s, a.d / (S(2) * s)};
+}
+DI double value(double x) { return x; }
+DI float value(float x) { return x; }
+template <class S> DI S value(Dual<S> x) { return x.v; }
+// |x| with derivative sign(x), sign(0) = +1
+template <class T> DI T absval(T x) { return value(x) >= 0 ? x : -x; }
+// max(a, b); a tie selects a
+template <class T> DI T larger(T a, T b) { return value(a) >= value(b) ? a : b; }
+
+// the part of a result that the caller stores: the value for residuals,
+// the tangent for Jacobian-vector products
+DI double part(double x) { return x; }
+DI float part(float x) { return x; }
+template <class S> DI S part(Dual<S> x) { return x.d; }
+
+template <class T> DI T make_state(typename BaseOf<T>::type u, typename BaseOf<T>::type v);
+template <> DI double make_state<double>(double u, double) { return u; }
+template <> DI float make_state<float>(float u, float) { return u; }
+template <> DI Dual<double> make_state<Dual<double>>(double u, double v) { return {u, v}; }
+template <> DI Dual<float> make_state<Dual<float>>(float u, float v) { return {u, v}; }
+
+// ---------------------------------------------------------------------------
+// equation parameters (by value in kernel arguments)
+// ---------------------------------------------------------------------------
+struct EqParams {
+    double a[3];
+    double nu;
+    double gamma;
+    double mu;
+    double kappa;   // mu gamma / ((gamma - 1) Pr), gas constant 1
+};
+
+// ---------------------------------------------------------------------------
+// pointwise physics
+// ---------------------------------------------------------------------------
+template <int EQ, int D, class T>
+struct Phys {
+    using S = typename BaseOf<T>::type;
+    static constexpr int R = nvars_of(EQ, D);
+
+    // convective flux along axis a
+    SDI void conv(int a, const T* u, T* f, const EqParams& P) {
+        if constexpr (EQ == EQ_ADV || EQ == EQ_ADVDIFF) {
+            f[0] = u[0] * S(P.a[a]);
+        } else if constexpr (EQ == EQ_BURGERS) {
+            f[0] = S(0.5) * (u[0] * u[0]);
+        } else {
+            const S gm1 = S(P.gamma) - S(1);
+            T rinv = S(1) / u[0];
+            T ke = u[1] * u[1];
+#pragma unroll
+            for (int b = 1; b < D; ++b) ke = ke + u[1 + b] * u[1 + b];
+            T p = gm1 * (u[D + 1] - S(0.5) * (ke * rinv));
+            T va = u[1 + a] * rinv;
+#pragma unroll
+            for (int b = 0; b < D; ++b) f[1 + b] = va * u[1 + b];
+            f[1 + a] = f[1 + a] + p;
+            f[0] = u[1 + a];
+            f[D + 1] = (u[D + 1] + p) * va;
+        }
+    }
+
+    // largest characteristic speed along axis a
+    SDI T speed(int a, const T* u, const EqParams& P) {
+        if constexpr (EQ == EQ_ADV || EQ == EQ_ADVDIFF) {
+            T r;
+            r = make_state<T>(S(fabs(P.a[a])), S(0));
+            return r;
+        } else if constexpr (EQ == EQ_BURGERS) {
+            return absval(u[0]);
+        } else {
+            const S g = S(P.gamma);
+            T rinv = S(1) / u[0];
+            T ke = u[1] * u[1];
+#pragma unroll
+            for (int b = 1; b < D; ++b) ke = ke + u[1 + b] * u[1 + b];
+            T p = (g - S(1)) * (u[D + 1] - S(0.5) * (ke * rinv));
+            T c = sqrt_(g * p * rinv);
+            return absval(u[1 + a] * rinv) + c;
+        }
+    }
+
+    // viscous flux along axis a; q[b * R + v] = d u_v / d x_b
+    SDI void visc(int a, const T* u, const T* q, T* f, const EqParams& P) {
+        if constexpr (EQ == EQ_ADVDIFF) {
+            f[0] = q[a] * S(P.nu);
+        } else if constexpr (EQ == EQ_NS) {
+            const S g = S(P.gamma);
+            const S mu = S(P.mu);
+            T rinv = S(1) / u[0];
+            T vel[D];
+#pragma unroll
+            for (int b = 0; b < D; ++b) vel[b] = u[1 + b] * rinv;
+            T ke = vel[0] * u[1];
+#pragma unroll
+            for (int b = 1; b < D; ++b) ke = ke + vel[b] * u[1 + b];
+            T p = (g - S(1)) * (u[D + 1] - S(0.5) * ke);
+            T Tm = p * rinv;
+            T v2 = vel[0] * vel[0];
+#pragma unroll
+            for (int b = 1; b < D; ++b) v2 = v2 + vel[b] * vel[b];
+            // velocity gradient gv[b][c] = d v_c / d x_b and temperature gradient
+            T gv[D][D];
+            T gT[D];
+#pragma unroll
+            for (int b = 0; b < D; ++b) {
+                const T gr = q[b * R];
+                T vgm = vel[0] * q[b * R + 1];
+#pragma unroll
+                for (int c = 0; c < D; ++c) {
+                    gv[b][c] = (q[b * R + 1 + c] - vel[c] * gr) * rinv;
+                    if (c > 0) vgm = vgm + vel[c] * q[b * R + 1 + c];
+                }
+                T gp = (g - S(1)) * (q[b * R + D + 1] - vgm + S(0.5) * (v2 * gr));
+                gT[b] = (gp - Tm * gr) * rinv;
+            }
+            T div = gv[0][0];
+#pragma unroll
+            for (int c = 1; c < D; ++c) div = div + gv[c][c];
+            f[0] = make_state<T>(S(0), S(0));
+            T work = make_state<T>(S(0), S(0));
+#pragma unroll
+            for (int c = 0; c < D; ++c) {
+                T tau = mu * (gv[a][c] + gv[c][a]);
+                if (c == a) tau = tau - (S(2) / S(3)) * mu * div;
+                f[1 + c] = tau;
+                work = work + tau * vel[c];
+            }
+            f[D + 1] = work + S(P.kappa) * gT[a];
+        }
+    }
+};
+
+// ---------------------------------------------------------------------------
+// launch descriptors
+// ---------------------------------------------------------------------------
+// GMRES state of one slab solve (device resident).
+struct GState {
+    int k;          // index of the newest basis vector; this step builds k+1
+    int done;       // cycle finished (converged, breakdown, m steps, non-finite)
+    int kfinal;     // basis vectors used in the update when done
+    int iters;      // Arnoldi steps in the current cycle
+    int iters_total;// Arnoldi steps over the whole solve
+    int outer;      // outer (Newton) iterations started
+    int nonfinite;  // a NaN/Inf was met
+    unsigned ticket;// last-block-done counter of the running reduction
+    double target;  // outer stopping threshold tol * max(1, ||R(U0)||)
+    double beta;    // ||r0|| of the cycle
+    double eta_abs; // absolute inner tolerance of the cycle
+    double rnorm;   // ||R(U)|| at the cycle start
+    double wn0;     // ||w||^2 before orthogonalisation
+    double inv;     // 1 / h_{k+1,k} for the normalisation
+    double hacc[MMAX + 1];
+    double hp[MMAX + 1];
+    double H[(MMAX + 1) * MMAX];
+    double cs[MMAX], sn[MMAX], g[MMAX + 1], y[MMAX];
+};
+
+// A device pointer that may follow the Arnoldi index: base + (*kp + koff) * ld.
+struct DynPtr {
+    const void* base;
+    int64_t ld;
+    const int* kp;
+    int koff;
+};
+
+// One slab instance inside an operator launch.
+struct OpSeg {
+    DynPtr U;            // state (double or float)
+    DynPtr V;            // direction (JVP only), double
+    const double* uprev; // previous-slab state (residual), may be null = 0
+    DynPtr Q;            // gradient of U (viscous)
+    DynPtr dQ;           // gradient of V (viscous JVP)
+    DynPtr out;          // double output
+    const int* skip;     // skip the segment when *skip != 0 (may be null)
+    int K[3];
+    int E;
+    double rh[3];        // 2 / h_a
+    double dt;
+    int blk0;            // first logical block
+    int nblk;
+    EqParams P;          // equation parameters
+    // LGL tables: Dx[j * n1 + k] = l_k'(x_j) in space, Dt likewise in time
+    double Dx[64];
+    double wx[8];
+    double Dt[16];
+    double wt[4];
+};
+
+// One slab instance inside a vector (Krylov) launch.
+struct VecSeg {
+    double* V;       // basis, (m+1) vectors of n
+    double* w;       // Arnoldi work vector
+    double* R;       // residual
+    double* U;       // state
+    int64_t n;
+    GState* st;
+    double* part;    // per-block partials, nblk * (MMAX + 2)
+    double eta_rel;  // inner forcing: eta_abs = max(eta_rel ||R||, eta_tgt * target)
+    double eta_tgt;
+    double tol;      // outer tolerance (relative to max(1, ||R(U0)||))
+    int m;           // restart length
+    const double* uprev;  // previous-slab state (initial guess)
+    double* unext;   // end-of-slab state output
+    float* U32;      // FP32 copy of U (FP32-inner JVPs)
+    int nt;          // temporal nodes
+    int ns;          // spatial nodes per element
+    int blk0;
+    int nblk;
+};
+
+__host__ __device__ inline int vec_blocks(int64_t n) {
+    int64_t b = (n + 1023) / 1024;
+    if (b < 1) b = 1;
+    if (b > 2048) b = 2048;
+    return (int)b;
+}
+
+}  // namespace stdg

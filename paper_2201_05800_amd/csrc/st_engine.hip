@@ -1,0 +1,583 @@
+// st_engine.hip -- host side of libstdg: handles, LGL tables, the residual
+// and JVP entry points, and the Newton-GMRES slab driver.
+#include "st_engine.hpp"
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+namespace stdg {
+
+thread_local std::string g_last_error;
+
+int set_error(int code, const std::string& msg) {
+    g_last_error = msg;
+    return code;
+}
+
+// ---------------------------------------------------------------------------
+// LGL nodes, weights and differentiation matrix.
+// Nodes: Newton iteration on (x P_p - P_{p-1}) / ((p+1) P_p), whose roots are
+// -1, +1 and the zeros of P_p' (starting from the Chebyshev-Gauss-Lobatto
+// points).  Weights 2 / (p (p+1) P_p(x)^2).  D from barycentric weights:
+// D_jk = (b_k / b_j) / (x_j - x_k), D_jj = -sum_{k != j} D_jk.
+// ---------------------------------------------------------------------------
+void lgl_tables(int n, double* x, double* w, double* D) {
+    const int p = n - 1;
+    std::vector<double> xs(n), xo(n), P(n * (p + 1));
+    for (int i = 0; i < n; ++i) xs[i] = std::cos(M_PI * i / p);
+    for (int it = 0; it < 200; ++it) {
+        double dmax = 0.0;
+        for (int i = 0; i < n; ++i) {
+            double pm = 1.0, pc = xs[i];
+            for (int k = 2; k <= p; ++k) {
+                double pn = ((2 * k - 1) * xs[i] * pc - (k - 1) * pm) / k;
+                pm = pc;
+                pc = pn;
+            }
+            if (p == 1) { pm = 1.0; pc = xs[i]; }
+            double xn = xs[i] - (xs[i] * pc - pm) / ((p + 1) * pc);
+            dmax = std::max(dmax, std::fabs(xn - xs[i]));
+            xs[i] = xn;
+        }
+        if (dmax < 1e-16) break;
+    }
+    for (int i = 0; i < n; ++i) x[i] = -xs[i];   // ascending
+    for (int i = 0; i < n; ++i) {
+        double pm = 1.0, pc = x[i];
+        for (int k = 2; k <= p; ++k) {
+            double pn = ((2 * k - 1) * x[i] * pc - (k - 1) * pm) / k;
+            pm = pc;
+            pc = pn;
+        }
+        w[i] = 2.0 / (p * (p + 1.0) * pc * pc);
+    }
+    std::vector<double> b(n, 1.0);
+    for (int j = 0; j < n; ++j)
+        for (int k = 0; k < n; ++k)
+            if (k != j) b[j] /= (x[j] - x[k]);
+    for (int j = 0; j < n; ++j) {
+        double diag = 0.0;
+        for (int k = 0; k < n; ++k) {
+            if (k == j) continue;
+            double v = (b[k] / b[j]) / (x[j] - x[k]);
+            D[j * n + k] = v;
+            diag -= v;
+        }
+        D[j * n + j] = diag;
+    }
+}
+
+const OpTable* find_table(int eq, int dim, int n1, int nt) {
+    static std::vector<OpTable> tables;
+    static std::once_flag once;
+    std::call_once(once, [] {
+        register_ops_adv(tables);
+        register_ops_advdiff(tables);
+        register_ops_burgers(tables);
+        register_ops_euler(tables);
+        register_ops_ns(tables);
+    });
+    for (const auto& t : tables)
+        if (t.eq == eq && t.dim == dim && t.n1 == n1 && t.nt == nt) return &t;
+    return nullptr;
+}
+
+// ---------------------------------------------------------------------------
+// problem description
+// ---------------------------------------------------------------------------
+int make_problem(const st_mesh_t* mesh, int N, int Nt, const st_equation_t* eq, Problem& pb) {
+    if (!mesh || !eq) return set_error(ST_ERR_BAD_ARG, "null mesh or equation");
+    const int d = mesh->dim;
+    if (d < 1 || d > 3) return set_error(ST_ERR_BAD_ARG, "dim must be 1, 2 or 3");
+    if (eq->kind < ST_ADVECTION || eq->kind > ST_NS_BR1) return set_error(ST_ERR_BAD_ARG, "unknown equation kind");
+    if (eq->kind == ST_BURGERS && d != 1) return set_error(ST_ERR_UNSUPPORTED, "Burgers is one-dimensional");
+    if (N < 1 || Nt < 2) return set_error(ST_ERR_BAD_ARG, "need N >= 1 and Nt >= 2");
+    pb.mesh = *mesh;
+    pb.eq = *eq;
+    pb.N = N;
+    pb.Nt = Nt;
+    pb.n1 = N + 1;
+    pb.nv = nvars_of(eq->kind, d);
+    pb.ns = 1;
+    for (int a = 0; a < d; ++a) pb.ns *= pb.n1;
+    pb.E = 1;
+    for (int a = 0; a < 3; ++a) {
+        int K = a < d ? mesh->K[a] : 1;
+        if (K < 1) return set_error(ST_ERR_BAD_ARG, "element counts must be >= 1");
+        double L = a < d ? mesh->hi[a] - mesh->lo[a] : 1.0;
+        if (!(L > 0.0)) return set_error(ST_ERR_BAD_ARG, "hi must exceed lo on every axis");
+        pb.K[a] = K;
+        pb.h[a] = L / K;
+        pb.E *= K;
+    }
+    if (pb.E > (int64_t)1 << 30) return set_error(ST_ERR_BAD_ARG, "too many elements");
+    pb.n = pb.E * pb.nv * Nt * pb.ns;
+    pb.nsp = pb.E * pb.nv * pb.ns;
+    pb.ops = find_table(eq->kind, d, pb.n1, Nt);
+    if (!pb.ops)
+        return set_error(ST_ERR_UNSUPPORTED, "(equation, dim, N, Nt) = (" + std::to_string(eq->kind) + ", " +
+                                                 std::to_string(d) + ", " + std::to_string(N) + ", " +
+                                                 std::to_string(Nt) + ") is not compiled in");
+    if ((eq->kind == ST_EULER || eq->kind == ST_NS_BR1) && !(eq->gamma > 1.0))
+        return set_error(ST_ERR_BAD_ARG, "gamma must exceed 1");
+    if (eq->kind == ST_NS_BR1 && !(eq->prandtl > 0.0)) return set_error(ST_ERR_BAD_ARG, "Prandtl must be > 0");
+    for (int a = 0; a < 3; ++a) pb.P.a[a] = eq->a[a];
+    pb.P.nu = eq->nu;
+    pb.P.gamma = eq->gamma;
+    pb.P.mu = eq->mu;
+    pb.P.kappa = eq->kind == ST_NS_BR1 ? eq->mu * eq->gamma / ((eq->gamma - 1.0) * eq->prandtl) : 0.0;
+    std::vector<double> x(8), w(8), Dm(64);
+    lgl_tables(pb.n1, x.data(), w.data(), Dm.data());
+    std::memcpy(pb.Dx, Dm.data(), sizeof(double) * pb.n1 * pb.n1);
+    std::memcpy(pb.wx, w.data(), sizeof(double) * pb.n1);
+    std::memcpy(pb.xi, x.data(), sizeof(double) * pb.n1);
+    lgl_tables(Nt, x.data(), w.data(), Dm.data());
+    std::memcpy(pb.Dt, Dm.data(), sizeof(double) * Nt * Nt);
+    std::memcpy(pb.wt, w.data(), sizeof(double) * Nt);
+    return ST_OK;
+}
+
+OpSeg base_opseg(const Problem& pb, double dt) {
+    OpSeg s;
+    std::memset(&s, 0, sizeof(s));
+    for (int a = 0; a < 3; ++a) {
+        s.K[a] = pb.K[a];
+        s.rh[a] = 2.0 / pb.h[a];
+    }
+    s.E = (int)pb.E;
+    s.P = pb.P;
+    s.dt = dt;
+    s.blk0 = 0;
+    s.nblk = op_blocks(pb);
+    std::memcpy(s.Dx, pb.Dx, sizeof(s.Dx));
+    std::memcpy(s.wx, pb.wx, sizeof(s.wx));
+    std::memcpy(s.Dt, pb.Dt, sizeof(s.Dt));
+    std::memcpy(s.wt, pb.wt, sizeof(s.wt));
+    return s;
+}
+
+DynPtr dptr(const void* p) { return DynPtr{p, 0, nullptr, 0}; }
+DynPtr dptr_k(const void* base, int64_t ld, const int* kp) { return DynPtr{base, ld, kp, 0}; }
+
+}  // namespace stdg
+
+using namespace stdg;
+
+// ---------------------------------------------------------------------------
+// handle
+// ---------------------------------------------------------------------------
+struct st_ctx {
+    Problem pb;
+    int device = 0;
+    OpSeg* d_op = nullptr;      // 8 operator descriptor slots
+    VecSeg* d_vs = nullptr;     // 1 vector descriptor slot
+    GState* d_st = nullptr;
+    double* d_part = nullptr;
+    double* Q = nullptr;        // gradient of U (viscous)
+    double* dQ = nullptr;       // gradient of the direction (viscous JVP)
+    float* U32 = nullptr;
+    float* Q32 = nullptr;
+    float* dQ32 = nullptr;
+    double* V = nullptr;        // Krylov basis (m vectors)
+    double* w = nullptr;
+    double* R = nullptr;
+    double* U = nullptr;
+    int m_alloc = 0;
+    GState* h_st = nullptr;     // pinned host mirror of the state header
+    std::vector<void*> allocs;
+
+    template <class T>
+    int alloc(T** p, size_t count) {
+        if (count == 0) count = 1;
+        hipError_t e = hipMalloc((void**)p, count * sizeof(T));
+        if (e != hipSuccess) return set_error(ST_ERR_HIP, std::string("hipMalloc: ") + hipGetErrorString(e));
+        allocs.push_back(*p);
+        return ST_OK;
+    }
+    ~st_ctx() {
+        for (void* p : allocs) (void)hipFree(p);
+        if (h_st) (void)hipHostFree(h_st);
+    }
+};
+
+#define CHK(x)                                  \
+    do {                                        \
+        int rc_ = (x);                          \
+        if (rc_ != ST_OK) return rc_;           \
+    } while (0)
+#define HIPCHK(x)                                                                                  \
+    do {                                                                                           \
+        hipError_t e_ = (x);                                                                       \
+        if (e_ != hipSuccess) return set_error(ST_ERR_HIP, std::string(#x) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+static int ensure_fp32(st_ctx* h) {
+    const Problem& pb = h->pb;
+    if (h->U32) return ST_OK;
+    CHK(h->alloc(&h->U32, pb.n));
+    if (viscous_eq(pb.eq.kind)) {
+        CHK(h->alloc(&h->Q32, (size_t)pb.n * pb.mesh.dim));
+        CHK(h->alloc(&h->dQ32, (size_t)pb.n * pb.mesh.dim));
+    }
+    return ST_OK;
+}
+
+static int ensure_solve(st_ctx* h, int m) {
+    const Problem& pb = h->pb;
+    if (h->m_alloc >= m) return ST_OK;
+    if (h->V) {
+        // grow: drop the old basis
+        auto it = std::find(h->allocs.begin(), h->allocs.end(), (void*)h->V);
+        if (it != h->allocs.end()) h->allocs.erase(it);
+        (void)hipFree(h->V);
+        h->V = nullptr;
+    }
+    CHK(h->alloc(&h->V, (size_t)pb.n * m));
+    if (!h->w) {
+        CHK(h->alloc(&h->w, pb.n));
+        CHK(h->alloc(&h->R, pb.n));
+        CHK(h->alloc(&h->U, pb.n));
+    }
+    h->m_alloc = m;
+    return ST_OK;
+}
+
+extern "C" {
+
+const char* st_version(void) { return "stdg 0.1 (gfx950)"; }
+const char* st_last_error(void) { return g_last_error.c_str(); }
+
+void st_default_opts(st_solver_opts_t* o) {
+    if (!o) return;
+    o->restart = 30;
+    o->max_newton = 60;
+    o->cgs_passes = 2;
+    o->inner_fp32 = 0;
+    o->gmres_rtol = 1e-3;
+}
+
+int st_lgl(int n, double* x, double* w, double* D) {
+    if (n < 2 || n > 8 || !x || !w || !D) return set_error(ST_ERR_BAD_ARG, "st_lgl: n in 2..8, non-null outputs");
+    lgl_tables(n, x, w, D);
+    return ST_OK;
+}
+
+int st_create(const st_mesh_t* mesh, int N, int Nt, const st_equation_t* eq, st_handle_t* out) {
+    if (!out) return set_error(ST_ERR_BAD_ARG, "null output handle");
+    *out = nullptr;
+    st_ctx* h = new st_ctx();
+    int rc = make_problem(mesh, N, Nt, eq, h->pb);
+    if (rc != ST_OK) { delete h; return rc; }
+    hipError_t e = hipGetDevice(&h->device);
+    if (e != hipSuccess) { delete h; return set_error(ST_ERR_HIP, std::string("hipGetDevice: ") + hipGetErrorString(e)); }
+    const Problem& pb = h->pb;
+    if ((rc = h->alloc(&h->d_op, 8)) != ST_OK ||
+        (rc = h->alloc(&h->d_vs, 1)) != ST_OK ||
+        (rc = h->alloc(&h->d_st, 1)) != ST_OK ||
+        (rc = h->alloc(&h->d_part, (size_t)vec_blocks(pb.n) * NPART_SLOTS)) != ST_OK) {
+        delete h;
+        return rc;
+    }
+    if (viscous_eq(pb.eq.kind)) {
+        if ((rc = h->alloc(&h->Q, (size_t)pb.n * pb.mesh.dim)) != ST_OK ||
+            (rc = h->alloc(&h->dQ, (size_t)pb.n * pb.mesh.dim)) != ST_OK) {
+            delete h;
+            return rc;
+        }
+    }
+    e = hipHostMalloc((void**)&h->h_st, sizeof(GState), hipHostMallocDefault);
+    if (e != hipSuccess) { delete h; return set_error(ST_ERR_HIP, std::string("hipHostMalloc: ") + hipGetErrorString(e)); }
+    *out = h;
+    return ST_OK;
+}
+
+int st_destroy(st_handle_t h) {
+    if (!h) return set_error(ST_ERR_BAD_ARG, "null handle");
+    (void)hipDeviceSynchronize();
+    delete h;
+    return ST_OK;
+}
+
+int st_sizes(st_handle_t h, int64_t* n_slab, int64_t* n_space, int* nv) {
+    if (!h) return set_error(ST_ERR_BAD_ARG, "null handle");
+    if (n_slab) *n_slab = h->pb.n;
+    if (n_space) *n_space = h->pb.nsp;
+    if (nv) *nv = h->pb.nv;
+    return ST_OK;
+}
+
+int st_node_coords(st_handle_t h, double* X) {
+    if (!h || !X) return set_error(ST_ERR_BAD_ARG, "null argument");
+    const Problem& pb = h->pb;
+    const int d = pb.mesh.dim, n1 = pb.n1;
+    for (int64_t e = 0; e < pb.E; ++e) {
+        const int64_t ec[3] = {e % pb.K[0], (e / pb.K[0]) % pb.K[1], e / ((int64_t)pb.K[0] * pb.K[1])};
+        for (int a = 0; a < d; ++a)
+            for (int s = 0; s < pb.ns; ++s) {
+                const int ia = a == 0 ? s % n1 : (a == 1 ? (s / n1) % n1 : s / (n1 * n1));
+                X[(e * d + a) * pb.ns + s] = pb.mesh.lo[a] + pb.h[a] * (ec[a] + 0.5 * (1.0 + pb.xi[ia]));
+            }
+    }
+    return ST_OK;
+}
+
+int st_residual(st_handle_t h, const double* U, const double* u_prev, double t0, double dt, double* R,
+                void* stream) {
+    (void)t0;
+    if (!h || !U || !u_prev || !R) return set_error(ST_ERR_BAD_ARG, "st_residual: null argument");
+    if (!(dt > 0.0) || !std::isfinite(dt)) return set_error(ST_ERR_BAD_ARG, "st_residual: dt must be positive");
+    const Problem& pb = h->pb;
+    hipStream_t st = (hipStream_t)stream;
+    const int G = op_blocks(pb);
+    OpSeg s = base_opseg(pb, dt);
+    if (viscous_eq(pb.eq.kind)) {
+        OpSeg g = s;
+        g.U = dptr(U);
+        g.out = dptr(h->Q);
+        put_opseg(h->d_op + 0, g, st);
+        pb.ops->grad64(h->d_op + 0, 1, G, st);
+        s.Q = dptr(h->Q);
+    }
+    s.U = dptr(U);
+    s.uprev = u_prev;
+    s.out = dptr(R);
+    put_opseg(h->d_op + 1, s, st);
+    pb.ops->res64(h->d_op + 1, 1, G, st);
+    HIPCHK(hipGetLastError());
+    return ST_OK;
+}
+
+}  // extern "C"
+
+namespace stdg {
+
+// Jv for the handle's problem, in two halves: upload the descriptors (slots
+// `slot`, `slot + 1`) and launch the kernels.  U: double state (U32 / Q32 must
+// hold the FP32 copies when inner_fp32 and the equation is nonlinear, Q must
+// hold grad U for NS); the direction may follow the Arnoldi index.
+void setup_jvp(st_ctx* h, const double* U, DynPtr V, double* out, const int* skip, bool fp32, double dt,
+               int slot, hipStream_t st) {
+    const Problem& pb = h->pb;
+    const int kind = pb.eq.kind;
+    OpSeg s = base_opseg(pb, dt);
+    s.skip = skip;
+    s.out = dptr(out);
+    if (viscous_eq(kind)) {
+        OpSeg g = s;
+        g.U = V;
+        g.out = dptr(fp32 ? (void*)h->dQ32 : (void*)h->dQ);
+        put_opseg(h->d_op + slot, g, st);
+    }
+    if (linear_eq(kind)) {
+        // J v = R(v) with u_prev = 0
+        s.U = V;
+        s.uprev = nullptr;
+        if (viscous_eq(kind)) s.Q = dptr(fp32 ? (void*)h->dQ32 : (void*)h->dQ);
+    } else {
+        s.U = dptr(fp32 ? (const void*)h->U32 : (const void*)U);
+        s.V = V;
+        if (viscous_eq(kind)) {
+            s.Q = dptr(fp32 ? (void*)h->Q32 : (void*)h->Q);
+            s.dQ = dptr(fp32 ? (void*)h->dQ32 : (void*)h->dQ);
+        }
+    }
+    put_opseg(h->d_op + slot + 1, s, st);
+}
+
+void launch_jvp(st_ctx* h, bool fp32, int slot, hipStream_t st) {
+    const Problem& pb = h->pb;
+    const int G = op_blocks(pb);
+    const int kind = pb.eq.kind;
+    if (viscous_eq(kind)) (fp32 ? pb.ops->grad64to32 : pb.ops->grad64)(h->d_op + slot, 1, G, st);
+    if (linear_eq(kind)) (fp32 ? pb.ops->lin32 : pb.ops->res64)(h->d_op + slot + 1, 1, G, st);
+    else (fp32 ? pb.ops->jvp32 : pb.ops->jvp64)(h->d_op + slot + 1, 1, G, st);
+}
+
+// FP32 copies of U (and grad U for NS) for FP32-inner JVPs; grad U (FP64) for
+// the FP64 NS JVP.  Uses the vector slot for the cast.
+void enqueue_jvp_prepare(st_ctx* h, const double* U, bool fp32, double dt, int slot, hipStream_t st) {
+    const Problem& pb = h->pb;
+    const int kind = pb.eq.kind;
+    if (linear_eq(kind)) return;
+    const int G = op_blocks(pb);
+    if (fp32) {
+        VecSeg v;
+        std::memset(&v, 0, sizeof(v));
+        v.U = const_cast<double*>(U);
+        v.U32 = h->U32;
+        v.n = pb.n;
+        v.nblk = vec_blocks(pb.n);
+        v.st = h->d_st;
+        put_vecseg(h->d_vs, v, st);
+        vk_cast32(h->d_vs, 1, v.nblk, st);
+    }
+    if (viscous_eq(kind)) {
+        OpSeg g = base_opseg(pb, dt);
+        g.U = dptr(fp32 ? (const void*)h->U32 : (const void*)U);
+        g.out = dptr(fp32 ? (void*)h->Q32 : (void*)h->Q);
+        put_opseg(h->d_op + slot, g, st);
+        (fp32 ? pb.ops->grad32 : pb.ops->grad64)(h->d_op + slot, 1, G, st);
+    }
+}
+
+}  // namespace stdg
+
+extern "C" {
+
+int st_jvp(st_handle_t h, const double* U, double t0, double dt, const double* v, double* Jv, int inner_fp32,
+           void* stream) {
+    (void)t0;
+    if (!h || !v || !Jv) return set_error(ST_ERR_BAD_ARG, "st_jvp: null argument");
+    if (!linear_eq(h->pb.eq.kind) && !U) return set_error(ST_ERR_BAD_ARG, "st_jvp: null state");
+    if (!(dt > 0.0) || !std::isfinite(dt)) return set_error(ST_ERR_BAD_ARG, "st_jvp: dt must be positive");
+    hipStream_t st = (hipStream_t)stream;
+    const bool fp32 = inner_fp32 != 0;
+    if (fp32) CHK(ensure_fp32(h));
+    enqueue_jvp_prepare(h, U, fp32, dt, 2, st);
+    setup_jvp(h, U, dptr(v), Jv, nullptr, fp32, dt, 3, st);
+    launch_jvp(h, fp32, 3, st);
+    HIPCHK(hipGetLastError());
+    return ST_OK;
+}
+
+int st_solve_slab(st_handle_t h, const double* u_prev, double t0, double dt, double tol,
+                  const st_solver_opts_t* opts_in, double* U_out, double* u_next, st_stats_t* stats,
+                  void* stream) {
+    (void)t0;
+    auto t_start = std::chrono::steady_clock::now();
+    if (!h || !u_prev) return set_error(ST_ERR_BAD_ARG, "st_solve_slab: null argument");
+    if (!(dt > 0.0) || !std::isfinite(dt)) return set_error(ST_ERR_BAD_ARG, "st_solve_slab: dt must be positive");
+    if (!(tol > 0.0)) return set_error(ST_ERR_BAD_ARG, "st_solve_slab: tol must be positive");
+    st_solver_opts_t o;
+    st_default_opts(&o);
+    if (opts_in) o = *opts_in;
+    if (o.restart < 1 || o.restart > MMAX) return set_error(ST_ERR_BAD_ARG, "restart must be in 1..32");
+    if (o.cgs_passes < 1 || o.cgs_passes > 2) return set_error(ST_ERR_BAD_ARG, "cgs_passes must be 1 or 2");
+    if (o.max_newton < 1) return set_error(ST_ERR_BAD_ARG, "max_newton must be >= 1");
+    const Problem& pb = h->pb;
+    const bool fp32 = o.inner_fp32 != 0;
+    const int m = o.restart;
+    CHK(ensure_solve(h, m));
+    if (fp32) CHK(ensure_fp32(h));
+    hipStream_t st = (hipStream_t)stream;
+    const int kind = pb.eq.kind;
+    const int Gop = op_blocks(pb);
+
+    // forcing: linear equations solve each cycle as far as the outer tolerance
+    double eta_rel = linear_eq(kind) ? 0.0 : std::max(o.gmres_rtol, 0.0);
+    if (fp32) eta_rel = std::max(eta_rel, 1e-5);
+
+    VecSeg vs;
+    std::memset(&vs, 0, sizeof(vs));
+    vs.V = h->V;
+    vs.w = h->w;
+    vs.R = h->R;
+    vs.U = h->U;
+    vs.n = pb.n;
+    vs.st = h->d_st;
+    vs.part = h->d_part;
+    vs.eta_rel = eta_rel;
+    vs.eta_tgt = 0.5;
+    vs.tol = tol;
+    vs.m = m;
+    vs.uprev = u_prev;
+    vs.unext = u_next;
+    vs.U32 = h->U32;
+    vs.nt = pb.Nt;
+    vs.ns = pb.ns;
+    vs.blk0 = 0;
+    vs.nblk = vec_blocks(pb.n);
+    const int Gv = vs.nblk;
+    HIPCHK(hipMemsetAsync(h->d_st, 0, sizeof(GState), st));
+    put_vecseg(h->d_vs, vs, st);
+    vk_init_guess(h->d_vs, 1, Gv, st);
+
+    // residual descriptors (slots 0, 1), fixed for the whole solve
+    OpSeg rs = base_opseg(pb, dt);
+    if (viscous_eq(kind)) {
+        OpSeg g = rs;
+        g.U = dptr(h->U);
+        g.out = dptr(h->Q);
+        put_opseg(h->d_op + 0, g, st);
+        rs.Q = dptr(h->Q);
+    }
+    rs.U = dptr(h->U);
+    rs.uprev = u_prev;
+    rs.out = dptr(h->R);
+    put_opseg(h->d_op + 1, rs, st);
+
+    // JVP descriptors (slots 4, 5): the direction V_k follows the device
+    // Arnoldi index; the whole segment is skipped once the cycle is done
+    const int* kp = &h->d_st->k;
+    const int* skip = &h->d_st->done;
+    setup_jvp(h, h->U, dptr_k(h->V, pb.n, kp), h->w, skip, fp32, dt, 4, st);
+    if (fp32 && viscous_eq(kind) && !linear_eq(kind)) {
+        OpSeg g = base_opseg(pb, dt);
+        g.U = dptr(h->U32);
+        g.out = dptr(h->Q32);
+        put_opseg(h->d_op + 2, g, st);
+    }
+
+    int status = ST_ERR_NO_CONVERGENCE;
+    int outer = 0;
+    double r0 = 0.0, rn = 0.0, best = INFINITY;
+    int stall = 0;
+    for (;;) {
+        if (viscous_eq(kind)) pb.ops->grad64(h->d_op + 0, 1, Gop, st);
+        pb.ops->res64(h->d_op + 1, 1, Gop, st);
+        vk_norm_begin(h->d_vs, 1, Gv, st);
+        HIPCHK(hipMemcpyAsync(h->h_st, h->d_st, offsetof(GState, hacc), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        const GState& hs = *h->h_st;
+        rn = hs.rnorm;
+        if (outer == 0) r0 = rn;
+        if (hs.nonfinite) { status = ST_ERR_NONFINITE; break; }
+        if (rn <= hs.target) { status = ST_OK; break; }
+        if (outer >= o.max_newton) break;
+        if (rn < 0.9 * best) { best = rn; stall = 0; }
+        else if (++stall >= 8) break;     // no progress over 8 outer iterations
+        ++outer;
+        // Jacobian base point: the FP32 copy of U (and grad U32 for NS); the
+        // FP64 NS JVP reuses grad U from the residual evaluation above
+        if (fp32 && !linear_eq(kind)) {
+            vk_cast32(h->d_vs, 1, Gv, st);
+            if (viscous_eq(kind)) pb.ops->grad32(h->d_op + 2, 1, Gop, st);
+        }
+        vk_scale_v0(h->d_vs, 1, Gv, st);
+        for (int k = 0; k < m; ++k) {
+            launch_jvp(h, fp32, 4, st);
+            for (int p = 0; p < o.cgs_passes; ++p) {
+                vk_multidot(h->d_vs, 1, Gv, p, st);
+                vk_update(h->d_vs, 1, Gv, p == o.cgs_passes - 1, st);
+            }
+            vk_normalize(h->d_vs, 1, Gv, st);
+        }
+        vk_finish(h->d_vs, 1, st);
+        vk_update_u(h->d_vs, 1, Gv, st);
+        HIPCHK(hipGetLastError());
+    }
+    if (u_next) vk_extract_last(h->d_vs, 1, Gv, st);
+    if (U_out) HIPCHK(hipMemcpyAsync(U_out, h->U, sizeof(double) * pb.n, hipMemcpyDeviceToDevice, st));
+    HIPCHK(hipMemcpyAsync(h->h_st, h->d_st, offsetof(GState, hacc), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    if (stats) {
+        stats->newton_its = outer;
+        stats->gmres_its = h->h_st->iters_total;
+        stats->res0 = r0;
+        stats->res_final = rn;
+        stats->status = status;
+        stats->usec = std::chrono::duration<double, std::micro>(std::chrono::steady_clock::now() - t_start).count();
+    }
+    if (status == ST_ERR_NONFINITE) return set_error(status, "non-finite residual or Krylov quantity");
+    if (status != ST_OK)
+        return set_error(status, "no convergence: ||R|| = " + std::to_string(rn) + " after " +
+                                     std::to_string(outer) + " outer iterations");
+    return ST_OK;
+}
+
+}  // extern "C"

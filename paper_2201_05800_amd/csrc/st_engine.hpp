@@ -1,0 +1,35 @@
+// st_engine.hpp -- host-side problem description shared by the engine and
+// the serving scheduler.
+#pragma once
+#include "../../include/st.h"
+#include "st_krylov.hpp"
+
+#include <string>
+
+namespace stdg {
+
+struct Problem {
+    st_mesh_t mesh;
+    st_equation_t eq;
+    int N, Nt, n1, nv, ns;
+    int K[3];
+    double h[3];
+    int64_t E, n, nsp;
+    const OpTable* ops;
+    EqParams P;
+    double Dx[64], wx[8], xi[8], Dt[16], wt[4];
+};
+
+inline int op_blocks(const Problem& pb) {
+    return (int)((pb.E + pb.ops->epb - 1) / pb.ops->epb);
+}
+
+int set_error(int code, const std::string& msg);
+void lgl_tables(int n, double* x, double* w, double* D);
+const OpTable* find_table(int eq, int dim, int n1, int nt);
+int make_problem(const st_mesh_t* mesh, int N, int Nt, const st_equation_t* eq, Problem& pb);
+OpSeg base_opseg(const Problem& pb, double dt);
+DynPtr dptr(const void* p);
+DynPtr dptr_k(const void* base, int64_t ld, const int* kp);
+
+}  // namespace stdg

@@ -1,0 +1,44 @@
+// st_krylov.hpp -- host launchers of the Newton-GMRES vector kernels and of
+// the slab operator tables.
+#pragma once
+#include "st_device.hpp"
+#include <vector>
+
+namespace stdg {
+
+constexpr int NPART_SLOTS = MMAX + 2;   // per-block partial slots of the reductions
+
+void vk_norm_begin(const VecSeg* s, int nseg, int G, hipStream_t st);
+void vk_scale_v0(const VecSeg* s, int nseg, int G, hipStream_t st);
+void vk_multidot(const VecSeg* s, int nseg, int G, int pass, hipStream_t st);
+void vk_update(const VecSeg* s, int nseg, int G, int last, hipStream_t st);
+void vk_normalize(const VecSeg* s, int nseg, int G, hipStream_t st);
+void vk_finish(const VecSeg* s, int nseg, hipStream_t st);
+void vk_update_u(const VecSeg* s, int nseg, int G, hipStream_t st);
+void vk_init_guess(const VecSeg* s, int nseg, int G, hipStream_t st);
+void vk_extract_last(const VecSeg* s, int nseg, int G, hipStream_t st);
+void vk_cast32(const VecSeg* s, int nseg, int G, hipStream_t st);
+void put_opseg(OpSeg* dst, const OpSeg& v, hipStream_t st);
+void put_vecseg(VecSeg* dst, const VecSeg& v, hipStream_t st);
+
+using OpLaunch = void (*)(const OpSeg*, int, int, hipStream_t);
+
+// Kernels of one (equation, dim, N+1, Nt).
+struct OpTable {
+    int eq, dim, n1, nt, epb;
+    OpLaunch res64;      // residual, FP64
+    OpLaunch lin32;      // linear equations: R(v) with u_prev = 0 in FP32 (FP32-inner JVP)
+    OpLaunch jvp64;      // nonlinear JVP, FP64
+    OpLaunch jvp32;      // nonlinear JVP, FP32 state and arithmetic
+    OpLaunch grad64;     // BR1 gradient double -> double
+    OpLaunch grad32;     // BR1 gradient float -> float
+    OpLaunch grad64to32; // BR1 gradient double -> float
+};
+
+void register_ops_adv(std::vector<OpTable>& t);
+void register_ops_advdiff(std::vector<OpTable>& t);
+void register_ops_burgers(std::vector<OpTable>& t);
+void register_ops_euler(std::vector<OpTable>& t);
+void register_ops_ns(std::vector<OpTable>& t);
+
+}  // namespace stdg

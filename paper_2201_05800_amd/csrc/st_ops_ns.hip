@@ -1,0 +1,14 @@
+// Operator kernels of the compressible Navier-Stokes equations (BR1).
+#include "st_ops_impl.hpp"
+
+namespace stdg {
+#define ST_NT3(EQ, D, N1)                       \
+    t.push_back(make_table<EQ, D, N1, 2>());    \
+    t.push_back(make_table<EQ, D, N1, 3>());    \
+    t.push_back(make_table<EQ, D, N1, 4>());
+
+void register_ops_ns(std::vector<OpTable>& t) {
+    ST_NT3(EQ_NS, 2, 2) ST_NT3(EQ_NS, 2, 3) ST_NT3(EQ_NS, 2, 4) ST_NT3(EQ_NS, 2, 5)
+    ST_NT3(EQ_NS, 3, 2) ST_NT3(EQ_NS, 3, 3) ST_NT3(EQ_NS, 3, 4) ST_NT3(EQ_NS, 3, 5)
+}
+}  // namespace stdg
