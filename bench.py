@@ -1,0 +1,223 @@
+"""Benchmark of the space-time DG-SEM slab path on one MI355X.
+
+Workload (default): 2D advection-diffusion with the BR1 viscous flux,
+velocity (1, 0.5), viscosity 1e-3, periodic [0,1]^2, 64 x 64 quads, N = 4,
+Nt = 4 (Lobatto IIIC 4 stages), dt = 1/128, initial data a sum of 8 seeded
+Fourier modes.  One STEP is one slab solve (Newton-GMRES around the residual
+and its JVP, all in HIP kernels): the K timed steps are K consecutive slabs of
+that run, each starting from the previous slab's end state.
+
+value = space-time DOF operator evaluations per second: every residual and
+every JVP evaluation counts n = 409,600 unknowns.  The JSON line also carries
+slab solves/s, per-slab latency p50/p99, the roofline of the dominant kernel
+(timed live with HIP events on the solve's stream) and the CPU oracle timed
+on a bounded sample of the same workload on this host.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0      # MI355X HBM3E, GB/s
+
+CONFIGS = {
+    # 2D advection-diffusion, BR1
+    "advdiff2d": dict(workload="2D advection-diffusion BR1, periodic [0,1]^2, 64x64 quads, N=4, Nt=4, dt=1/128",
+                      kind=2, dim=2, K=[64, 64], lo=[0.0, 0.0], hi=[1.0, 1.0], N=4, Nt=4, a=(1.0, 0.5),
+                      nu=1e-3, dt=1.0 / 128, init="fourier", tol=1e-10),
+    # 2D Euler isentropic vortex
+    "euler2d": dict(workload="2D Euler isentropic vortex + 1e-3 density noise, periodic [-5,5]^2, 128x128 quads, "
+                             "N=3, Nt=3, CFL 5",
+                    kind=4, dim=2, K=[128, 128], lo=[-5.0, -5.0], hi=[5.0, 5.0], N=3, Nt=3, gamma=1.4,
+                    dt=None, init="vortex", tol=1e-8),
+    # 3D Navier-Stokes Taylor-Green vortex
+    "ns3d": dict(workload="3D Navier-Stokes Taylor-Green vortex Re=1600 Mach 0.1, periodic [0,2pi]^3, 16^3 hexes, "
+                          "N=3, Nt=3, dt=0.05",
+                 kind=5, dim=3, K=[16, 16, 16], lo=[0.0] * 3, hi=[2 * math.pi] * 3, N=3, Nt=3, gamma=1.4,
+                 mu=1.0 / 1600, prandtl=0.71, dt=0.05, init="tgv", tol=1e-8),
+}
+
+# algorithmic bytes per unknown of one launch of each kernel class
+#   residual: read U, read u_prev (1/Nt of a vector), write R
+#   jvp: linear equations read v, write Jv; nonlinear read U and v, write Jv
+#   grad: read the input once, write d values per unknown
+#   multidot at Arnoldi index k: read k+1 basis vectors and w
+#   update: read k+1 basis vectors, read and write w
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=32)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--config", default="advdiff2d", choices=sorted(CONFIGS))
+    ap.add_argument("--fp32-inner", type=int, default=0)
+    ap.add_argument("--cpu-baseline-seconds", type=float, default=12.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--restart", type=int, default=30)
+    ap.add_argument("--cgs-passes", type=int, default=1)
+    return ap.parse_args()
+
+
+def initial_state(cfg, X):
+    from paper_2201_05800_amd import inputs
+    if cfg["init"] == "fourier":
+        return inputs.fourier_modes(X, inputs.fourier_params(2))
+    if cfg["init"] == "vortex":
+        return inputs.isentropic_vortex(X, seed=3)
+    if cfg["init"] == "tgv":
+        return inputs.taylor_green(X)
+    raise ValueError(cfg["init"])
+
+
+def cpu_baseline(cfg, u0, U, dt, seconds):
+    """The oracle's residual evaluation of the same slab on this host's cores,
+    repeated for about `seconds` (a bounded sample of the workload)."""
+    import numpy as np
+    import oracle
+    oracle.build()
+    p = oracle.problem(cfg["dim"], cfg["K"], cfg["lo"], cfg["hi"], cfg["N"], cfg["Nt"], cfg["kind"],
+                       a=cfg.get("a", (0, 0, 0)), nu=cfg.get("nu", 0.0), gamma=cfg.get("gamma", 1.4),
+                       mu=cfg.get("mu", 0.0), prandtl=cfg.get("prandtl", 0.72))
+    n = U.size
+    oracle.residual(p, U, u0, dt)         # warm (page-in, thread start)
+    t0 = time.perf_counter()
+    evals = 0
+    while True:
+        oracle.residual(p, U, u0, dt)
+        evals += 1
+        el = time.perf_counter() - t0
+        if el >= seconds:
+            break
+    return dict(value=evals * n / el, unit="space-time DOF residual evals/s", cores=oracle.get_threads(),
+                kind="oracle",
+                sample=f"{evals} oracle residual evaluations of one {n}-unknown slab of the same workload "
+                       f"({el:.1f} s)")
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py: this build runs on one GPU (one slab per GPU; the multi-GPU "
+              "decomposition is described in DESIGN.md, not built); use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    from paper_2201_05800_amd import inputs, st
+
+    torch.cuda.set_device(0)
+    cfg = CONFIGS[args.config]
+    d = cfg["dim"]
+    m = st.mesh(d, cfg["K"], cfg["lo"], cfg["hi"])
+    eq = st.equation(cfg["kind"], a=cfg.get("a", (0, 0, 0)), nu=cfg.get("nu", 0.0), gamma=cfg.get("gamma", 1.4),
+                     mu=cfg.get("mu", 0.0), prandtl=cfg.get("prandtl", 0.72))
+    h = st.st_create(m, cfg["N"], cfg["Nt"], eq)
+    n, nsp, nv = st.st_sizes(h)
+    ns = (cfg["N"] + 1) ** d
+    X = st.st_node_coords(h, d, ns)
+    u0 = initial_state(cfg, X)
+    dt = cfg["dt"]
+    if dt is None:
+        hmin = min((cfg["hi"][a] - cfg["lo"][a]) / cfg["K"][a] for a in range(d))
+        dt = inputs.cfl_dt(5.0, hmin, cfg["N"], inputs.euler_max_speed(u0, cfg.get("gamma", 1.4)))
+    u0 = u0.ravel()
+
+    # HIP-event timing of the operator and Gram-Schmidt kernel classes
+    timed = (1 << st.ST_K_MULTIDOT) | (1 << st.ST_K_UPDATE) | (1 << st.ST_K_JVP) | (1 << st.ST_K_RESIDUAL) \
+        | (1 << st.ST_K_GRAD)
+    opts = st.st_default_opts(restart=args.restart, cgs_passes=args.cgs_passes, inner_fp32=args.fp32_inner,
+                              timing=timed)
+    stream = torch.cuda.current_stream()
+    u = torch.as_tensor(u0).cuda()
+    un = torch.empty(nsp, dtype=torch.float64, device="cuda")
+    U = torch.empty(n, dtype=torch.float64, device="cuda")
+
+    def step(uin, uout):
+        return st.st_solve_slab(h, uin, 0.0, dt, cfg["tol"], opts, U, uout, stream)
+
+    for _ in range(args.warmup):
+        step(u, un)
+        u, un = un, u
+    u.copy_(torch.as_tensor(u0))
+    torch.cuda.synchronize()
+
+    lat, stats = [], []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        ts = time.perf_counter()
+        s = step(u, un)      # synchronises the stream at its end
+        lat.append(time.perf_counter() - ts)
+        stats.append(s)
+        u, un = un, u
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+
+    op_evals = sum(s["newton_its"] + 1 + s["gmres_its"] for s in stats)
+    value = op_evals * n / elapsed
+    lat_ms = np.array(lat) * 1e3
+
+    # roofline of the dominant kernel: algorithmic bytes (accumulated by the
+    # library per kernel class) over the HIP-event time of its launches
+    def roof_of(cls, name, bound="hbm"):
+        us = sum(s["kernel_us"][cls] for s in stats)
+        calls = sum(s["kernel_calls"][cls] for s in stats)
+        by = sum(s["kernel_bytes"][cls] for s in stats)
+        ach = by / (us * 1e-6) / 1e9 if us > 0 else 0.0
+        return dict(bound=bound, kernel=name, achieved=round(ach, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                    frac=round(ach / HBM_PEAK_GBS, 4), traffic=None, avg_launch_us=round(us / max(calls, 1), 3),
+                    launches=calls, algorithmic_bytes_per_launch=round(by / max(calls, 1)))
+
+    shares = {name: sum(s["kernel_us"][i] for s in stats) / (elapsed * 1e6)
+              for i, name in enumerate(st.KERNEL_CLASSES)}
+    names = {st.ST_K_RESIDUAL: "k_op (residual)", st.ST_K_JVP: "k_op (JVP)", st.ST_K_GRAD: "k_grad",
+             st.ST_K_MULTIDOT: "k_multidot", st.ST_K_UPDATE: "k_update"}
+    roofs = {st.KERNEL_CLASSES[c]: roof_of(c, nm) for c, nm in names.items()}
+    dom_name = max((c for c in names), key=lambda c: shares[st.KERNEL_CLASSES[c]])
+    roof = roofs[st.KERNEL_CLASSES[dom_name]]
+    jvp_roof = roofs["jvp"]
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        Uh = U.cpu().numpy()
+        cpu = cpu_baseline(cfg, u0, Uh, dt, args.cpu_baseline_seconds)
+
+    out = {
+        "metric": "space-time DOF residual evals/s + slab solves/s, p50/p99 latency, % HBM peak",
+        "value": value,
+        "unit": "space-time DOF residual evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed * 1e3 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if not args.fp32_inner else "f64 (f32 inner JVP)",
+        "data": "synthetic",
+        "config": {"workload": cfg["workload"], "unknowns_per_slab": n, "restart": args.restart,
+                   "cgs_passes": args.cgs_passes, "inner_fp32": args.fp32_inner, "tol": cfg["tol"]},
+        "slab_solves_per_s": args.steps / elapsed,
+        "latency_ms_p50": float(np.percentile(lat_ms, 50)),
+        "latency_ms_p99": float(np.percentile(lat_ms, 99)),
+        "newton_its_per_slab": sum(s["newton_its"] for s in stats) / len(stats),
+        "gmres_its_per_slab": sum(s["gmres_its"] for s in stats) / len(stats),
+        "operator_evals": op_evals,
+        "kernel_time_share": {k: round(v, 4) for k, v in shares.items()},
+        "roofline": roof,
+        "roofline_by_kernel": roofs,
+        "cpu_baseline": cpu,
+    }
+    st.st_destroy(h)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

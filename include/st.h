@@ -86,12 +86,27 @@ typedef struct {
     int restart;       /* GMRES restart length m, 1..32 (default 30)            */
     int max_newton;    /* outer iterations; each is one residual evaluation and */
                        /* one GMRES cycle of at most m steps (default 60)       */
-    int cgs_passes;    /* classical Gram-Schmidt passes, 1 or 2 (default 2)     */
+    int cgs_passes;    /* classical Gram-Schmidt passes, 1 or 2 (default 1)     */
     int inner_fp32;    /* 1: JVPs in FP32 (state, math, accumulation); the      */
                        /* residual, Arnoldi and update stay FP64                */
     double gmres_rtol; /* minimum inner forcing term eta (default 1e-3; raised  */
                        /* to 1e-5 at least when inner_fp32)                     */
+    int timing;        /* bit mask of ST_K_* kernel classes to time with HIP    */
+                       /* events on the solve's stream (0 = none)               */
 } st_solver_opts_t;
+
+/* Kernel classes of the slab solve (bits of st_solver_opts_t.timing and
+ * indices of st_stats_t.kernel_us / kernel_calls). */
+enum {
+    ST_K_RESIDUAL = 0,  /* residual operator kernel                          */
+    ST_K_JVP = 1,       /* Jacobian-vector product operator kernel           */
+    ST_K_GRAD = 2,      /* BR1 lifted-gradient kernels                       */
+    ST_K_MULTIDOT = 3,  /* Gram-Schmidt projections (fused multi-dot)        */
+    ST_K_UPDATE = 4,    /* Gram-Schmidt correction + norm + Givens           */
+    ST_K_NORMALIZE = 5, /* Krylov vector normalisation                       */
+    ST_K_NEWTON = 6,    /* Newton update U += V y, residual norm, setup      */
+    ST_K_COUNT = 8
+};
 
 typedef struct {
     int newton_its;    /* outer iterations done */
@@ -100,6 +115,10 @@ typedef struct {
     double res_final;  /* ||R(U)||_2 at return */
     double usec;       /* wall time of the call (host clock, includes syncs) */
     int status;        /* ST_OK or ST_ERR_NO_CONVERGENCE / ST_ERR_NONFINITE */
+    double kernel_us[8];  /* summed event time per timed kernel class */
+    int kernel_calls[8];  /* timed launches per kernel class          */
+    double kernel_bytes[8];  /* algorithmic bytes moved per kernel class (launches  */
+                             /* that did work; BR1 gradient: input + output)        */
 } st_stats_t;
 
 typedef struct st_ctx* st_handle_t;

@@ -217,10 +217,14 @@ struct GState {
     double rnorm;   // ||R(U)|| at the cycle start
     double wn0;     // ||w||^2 before orthogonalisation
     double inv;     // 1 / h_{k+1,k} for the normalisation
+    double kbytes[8];  // algorithmic bytes of the Krylov kernels that did work
     double hacc[MMAX + 1];
     double hp[MMAX + 1];
     double H[(MMAX + 1) * MMAX];
-    double cs[MMAX], sn[MMAX], g[MMAX + 1], y[MMAX];
+    double cs[MMAX], sn[MMAX];
+    double g[MMAX + 1];  // g[k]: unrotated right-hand side entry carried to step k
+    double gr[MMAX];     // rotated right-hand side of the least-squares problem
+    double y[MMAX];
 };
 
 // A device pointer that may follow the Arnoldi index: base + (*kp + koff) * ld.
@@ -262,7 +266,8 @@ struct VecSeg {
     double* U;       // state
     int64_t n;
     GState* st;
-    double* part;    // per-block partials, nblk * (MMAX + 2)
+    double* part;    // per-block partials of the multi-dot, nblk * (MMAX + 2)
+    double* part2;   // per-block partial norms, nblk
     double eta_rel;  // inner forcing: eta_abs = max(eta_rel ||R||, eta_tgt * target)
     double eta_tgt;
     double tol;      // outer tolerance (relative to max(1, ||R(U0)||))
@@ -276,10 +281,14 @@ struct VecSeg {
     int nblk;
 };
 
+// blocks of one slab in a vector launch: about 4 elements per thread, at
+// most 256 blocks (one per CU); larger slabs loop (grid stride).  Consumers
+// reduce the per-block partial tables redundantly in every block, so the
+// block count is kept at what the bandwidth needs.
 __host__ __device__ inline int vec_blocks(int64_t n) {
     int64_t b = (n + 1023) / 1024;
     if (b < 1) b = 1;
-    if (b > 2048) b = 2048;
+    if (b > 256) b = 256;
     return (int)b;
 }
 

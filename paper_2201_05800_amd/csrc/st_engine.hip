@@ -191,6 +191,39 @@ struct st_ctx {
     GState* h_st = nullptr;     // pinned host mirror of the state header
     std::vector<void*> allocs;
 
+    // optional HIP-event timing of kernel classes (st_solver_opts_t.timing)
+    struct Timer {
+        int mask = 0;
+        std::vector<hipEvent_t> pool;
+        std::vector<std::pair<int, size_t>> marks;   // (class, first event)
+        size_t used = 0;
+        void reset(int m) { mask = m; marks.clear(); used = 0; }
+        template <class F>
+        void run(int cls, hipStream_t st, F&& launch) {
+            if (!((mask >> cls) & 1)) { launch(); return; }
+            while (pool.size() < used + 2) {
+                hipEvent_t e;
+                if (hipEventCreate(&e) != hipSuccess) { launch(); return; }
+                pool.push_back(e);
+            }
+            (void)hipEventRecord(pool[used], st);
+            launch();
+            (void)hipEventRecord(pool[used + 1], st);
+            marks.push_back({cls, used});
+            used += 2;
+        }
+        void collect(st_stats_t* s) {
+            for (int c = 0; c < ST_K_COUNT; ++c) { s->kernel_us[c] = 0.0; s->kernel_calls[c] = 0; }
+            for (auto& mk : marks) {
+                float ms = 0.f;
+                if (hipEventElapsedTime(&ms, pool[mk.second], pool[mk.second + 1]) == hipSuccess) {
+                    s->kernel_us[mk.first] += 1000.0 * ms;
+                    s->kernel_calls[mk.first] += 1;
+                }
+            }
+        }
+    } timer;
+
     template <class T>
     int alloc(T** p, size_t count) {
         if (count == 0) count = 1;
@@ -200,6 +233,7 @@ struct st_ctx {
         return ST_OK;
     }
     ~st_ctx() {
+        for (hipEvent_t e : timer.pool) (void)hipEventDestroy(e);
         for (void* p : allocs) (void)hipFree(p);
         if (h_st) (void)hipHostFree(h_st);
     }
@@ -256,9 +290,10 @@ void st_default_opts(st_solver_opts_t* o) {
     if (!o) return;
     o->restart = 30;
     o->max_newton = 60;
-    o->cgs_passes = 2;
+    o->cgs_passes = 1;
     o->inner_fp32 = 0;
     o->gmres_rtol = 1e-3;
+    o->timing = 0;
 }
 
 int st_lgl(int n, double* x, double* w, double* D) {
@@ -279,7 +314,7 @@ int st_create(const st_mesh_t* mesh, int N, int Nt, const st_equation_t* eq, st_
     if ((rc = h->alloc(&h->d_op, 8)) != ST_OK ||
         (rc = h->alloc(&h->d_vs, 1)) != ST_OK ||
         (rc = h->alloc(&h->d_st, 1)) != ST_OK ||
-        (rc = h->alloc(&h->d_part, (size_t)vec_blocks(pb.n) * NPART_SLOTS)) != ST_OK) {
+        (rc = h->alloc(&h->d_part, (size_t)vec_blocks(pb.n) * (NPART_SLOTS + 1))) != ST_OK) {
         delete h;
         return rc;
     }
@@ -393,9 +428,12 @@ void launch_jvp(st_ctx* h, bool fp32, int slot, hipStream_t st) {
     const Problem& pb = h->pb;
     const int G = op_blocks(pb);
     const int kind = pb.eq.kind;
-    if (viscous_eq(kind)) (fp32 ? pb.ops->grad64to32 : pb.ops->grad64)(h->d_op + slot, 1, G, st);
-    if (linear_eq(kind)) (fp32 ? pb.ops->lin32 : pb.ops->res64)(h->d_op + slot + 1, 1, G, st);
-    else (fp32 ? pb.ops->jvp32 : pb.ops->jvp64)(h->d_op + slot + 1, 1, G, st);
+    if (viscous_eq(kind))
+        h->timer.run(ST_K_GRAD, st, [&] { (fp32 ? pb.ops->grad64to32 : pb.ops->grad64)(h->d_op + slot, 1, G, st); });
+    h->timer.run(ST_K_JVP, st, [&] {
+        if (linear_eq(kind)) (fp32 ? pb.ops->lin32 : pb.ops->res64)(h->d_op + slot + 1, 1, G, st);
+        else (fp32 ? pb.ops->jvp32 : pb.ops->jvp64)(h->d_op + slot + 1, 1, G, st);
+    });
 }
 
 // FP32 copies of U (and grad U for NS) for FP32-inner JVPs; grad U (FP64) for
@@ -438,6 +476,7 @@ int st_jvp(st_handle_t h, const double* U, double t0, double dt, const double* v
     hipStream_t st = (hipStream_t)stream;
     const bool fp32 = inner_fp32 != 0;
     if (fp32) CHK(ensure_fp32(h));
+    h->timer.reset(0);
     enqueue_jvp_prepare(h, U, fp32, dt, 2, st);
     setup_jvp(h, U, dptr(v), Jv, nullptr, fp32, dt, 3, st);
     launch_jvp(h, fp32, 3, st);
@@ -481,6 +520,7 @@ int st_solve_slab(st_handle_t h, const double* u_prev, double t0, double dt, dou
     vs.n = pb.n;
     vs.st = h->d_st;
     vs.part = h->d_part;
+    vs.part2 = h->d_part + (size_t)vec_blocks(pb.n) * NPART_SLOTS;
     vs.eta_rel = eta_rel;
     vs.eta_tgt = 0.5;
     vs.tol = tol;
@@ -493,6 +533,7 @@ int st_solve_slab(st_handle_t h, const double* u_prev, double t0, double dt, dou
     vs.blk0 = 0;
     vs.nblk = vec_blocks(pb.n);
     const int Gv = vs.nblk;
+    h->timer.reset(o.timing);
     HIPCHK(hipMemsetAsync(h->d_st, 0, sizeof(GState), st));
     put_vecseg(h->d_vs, vs, st);
     vk_init_guess(h->d_vs, 1, Gv, st);
@@ -527,10 +568,14 @@ int st_solve_slab(st_handle_t h, const double* u_prev, double t0, double dt, dou
     int outer = 0;
     double r0 = 0.0, rn = 0.0, best = INFINITY;
     int stall = 0;
+    auto& T = h->timer;
     for (;;) {
-        if (viscous_eq(kind)) pb.ops->grad64(h->d_op + 0, 1, Gop, st);
-        pb.ops->res64(h->d_op + 1, 1, Gop, st);
-        vk_norm_begin(h->d_vs, 1, Gv, st);
+        if (viscous_eq(kind)) T.run(ST_K_GRAD, st, [&] { pb.ops->grad64(h->d_op + 0, 1, Gop, st); });
+        T.run(ST_K_RESIDUAL, st, [&] { pb.ops->res64(h->d_op + 1, 1, Gop, st); });
+        T.run(ST_K_NEWTON, st, [&] {
+            vk_rnorm(h->d_vs, 1, Gv, st);
+            vk_begin(h->d_vs, 1, st);
+        });
         HIPCHK(hipMemcpyAsync(h->h_st, h->d_st, offsetof(GState, hacc), hipMemcpyDeviceToHost, st));
         HIPCHK(hipStreamSynchronize(st));
         const GState& hs = *h->h_st;
@@ -545,20 +590,22 @@ int st_solve_slab(st_handle_t h, const double* u_prev, double t0, double dt, dou
         // Jacobian base point: the FP32 copy of U (and grad U32 for NS); the
         // FP64 NS JVP reuses grad U from the residual evaluation above
         if (fp32 && !linear_eq(kind)) {
-            vk_cast32(h->d_vs, 1, Gv, st);
-            if (viscous_eq(kind)) pb.ops->grad32(h->d_op + 2, 1, Gop, st);
+            T.run(ST_K_NEWTON, st, [&] { vk_cast32(h->d_vs, 1, Gv, st); });
+            if (viscous_eq(kind)) T.run(ST_K_GRAD, st, [&] { pb.ops->grad32(h->d_op + 2, 1, Gop, st); });
         }
-        vk_scale_v0(h->d_vs, 1, Gv, st);
+        T.run(ST_K_NORMALIZE, st, [&] { vk_scale_v0(h->d_vs, 1, Gv, st); });
         for (int k = 0; k < m; ++k) {
             launch_jvp(h, fp32, 4, st);
             for (int p = 0; p < o.cgs_passes; ++p) {
-                vk_multidot(h->d_vs, 1, Gv, p, st);
-                vk_update(h->d_vs, 1, Gv, p == o.cgs_passes - 1, st);
+                T.run(ST_K_MULTIDOT, st, [&] { vk_multidot(h->d_vs, 1, Gv, k, st); });
+                T.run(ST_K_UPDATE, st, [&] { vk_update(h->d_vs, 1, Gv, p, k, st); });
             }
-            vk_normalize(h->d_vs, 1, Gv, st);
+            T.run(ST_K_NORMALIZE, st, [&] { vk_normalize(h->d_vs, 1, Gv, k, st); });
         }
-        vk_finish(h->d_vs, 1, st);
-        vk_update_u(h->d_vs, 1, Gv, st);
+        T.run(ST_K_NEWTON, st, [&] {
+            vk_finish(h->d_vs, 1, st);
+            vk_update_u(h->d_vs, 1, Gv, st);
+        });
         HIPCHK(hipGetLastError());
     }
     if (u_next) vk_extract_last(h->d_vs, 1, Gv, st);
@@ -566,6 +613,23 @@ int st_solve_slab(st_handle_t h, const double* u_prev, double t0, double dt, dou
     HIPCHK(hipMemcpyAsync(h->h_st, h->d_st, offsetof(GState, hacc), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
     if (stats) {
+        h->timer.collect(stats);
+        // algorithmic bytes: operator kernels from launch counts, Krylov
+        // kernels accumulated on the device
+        const double n8 = 8.0 * (double)pb.n;
+        const int its = h->h_st->iters_total;
+        const bool visc = viscous_eq(kind), lin = linear_eq(kind);
+        for (int c = 0; c < ST_K_COUNT; ++c) stats->kernel_bytes[c] = 0.0;
+        stats->kernel_bytes[ST_K_RESIDUAL] = (outer + 1) * n8 * (2.0 + 1.0 / pb.Nt);
+        const double jvp_b = lin ? 2.0 * n8 : (fp32 ? 2.5 : 3.0) * n8;   // [U,] v in, Jv out
+        stats->kernel_bytes[ST_K_JVP] = its * jvp_b;
+        if (visc) {
+            const double d = pb.mesh.dim;
+            stats->kernel_bytes[ST_K_GRAD] = (outer + 1) * n8 * (1.0 + d) + its * n8 * (1.0 + (fp32 ? 0.5 : 1.0) * d);
+        }
+        stats->kernel_bytes[ST_K_MULTIDOT] = h->h_st->kbytes[3] * o.cgs_passes;
+        stats->kernel_bytes[ST_K_UPDATE] = h->h_st->kbytes[4] * o.cgs_passes;
+        stats->kernel_bytes[ST_K_NORMALIZE] = h->h_st->kbytes[5];
         stats->newton_its = outer;
         stats->gmres_its = h->h_st->iters_total;
         stats->res0 = r0;

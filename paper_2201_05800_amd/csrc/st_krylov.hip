@@ -1,22 +1,42 @@
 // st_krylov.hip -- Newton-GMRES vector kernels (FP64), batched over slabs.
 //
-// GMRES(m) with classical Gram-Schmidt: the k+1 projections of the new
-// Krylov vector are one fused multi-dot (one pass over the basis), the
-// correction is one multi-axpy pass; an optional second pass (CGS2) repeats
-// both.  Reductions are two-stage and deterministic: fixed per-block chunks,
-// block partials, and a final reduction in fixed order by the last block to
-// finish (device-scope ticket).  The Givens update of the Hessenberg least
-// squares problem and the stopping test run in that last block, so the
-// iteration never needs the host.  Every kernel takes a table of VecSeg
-// descriptors (one per slab); a slab's block count depends only on its own
-// length, so its arithmetic is identical alone and in a batch.
+// GMRES(m) with classical Gram-Schmidt: the k+1 projections of a new Krylov
+// vector are one fused multi-dot (one pass over the basis), the correction is
+// one fused multi-axpy pass that also takes the new norm; an optional second
+// pass (CGS2) repeats both.  Reductions are deterministic and need no atomics:
+// a producer kernel writes one row of partial sums per block, and the
+// consumer kernel reduces that table in a fixed order -- redundantly in every
+// block, so every block holds the same bits.  The Givens update of the
+// Hessenberg least-squares problem and the stopping test run redundantly in
+// every block of the normalisation kernel; block 0 commits them to the
+// device state, which no other block of that kernel reads, so the iteration
+// never needs the host.
+//
+// Every kernel takes a table of VecSeg descriptors (one per slab); a slab's
+// block count depends only on its own length, so its arithmetic is identical
+// alone and in a batch.  The Gram-Schmidt kernels are instantiated per number
+// of basis vectors NV = k + 1, with k the host's Arnoldi step index.
 #include "st_krylov.hpp"
+
+#include <array>
+#include <utility>
 
 namespace stdg {
 
 namespace {
 
-constexpr int NPART = MMAX + 2;   // partial slots per block
+constexpr int NPART = MMAX + 2;   // partial slots per block row (multi-dot table)
+
+// descriptor pointers are generic; loads through the global address space
+// give global_load instructions (no flat-address waits)
+template <class T>
+DI __attribute__((address_space(1))) T* gl(T* p) {
+    return (__attribute__((address_space(1))) T*)p;
+}
+template <class T>
+DI const __attribute__((address_space(1))) T* gl(const T* p) {
+    return (const __attribute__((address_space(1))) T*)p;
+}
 
 DI double wave_sum(double x) {
 #pragma unroll
@@ -33,84 +53,85 @@ DI int find_vseg(const VecSeg* segs, int nseg, int b) {
     return lo;
 }
 
-// Reduce nval per-thread values over the block; thread i < nval of the
-// block returns the block sum of value i in `out` (others unspecified).
-template <int NMAX>
-DI void block_sums(const double (&acc)[NMAX], int nval, double* smem /* [4][NMAX] */, double& out) {
+// Block reduction of NV per-thread values; returns with sums in out[0..NV).
+// smem: 4 * NV doubles.
+template <int NV>
+DI void block_sums(const double (&acc)[NV], double* smem, double* out) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
-    for (int i = 0; i < NMAX; ++i) {
-        if (i < nval) {
-            double s = wave_sum(acc[i]);
-            if (lane == 0) smem[wave * NMAX + i] = s;
-        }
+    for (int i = 0; i < NV; ++i) {
+        const double s = wave_sum(acc[i]);
+        if (lane == 0) smem[wave * NV + i] = s;
     }
     __syncthreads();
-    out = 0.0;
-    if (threadIdx.x < nval) {
+    if (threadIdx.x < NV) {
         const int i = threadIdx.x;
-        out = smem[i] + smem[NMAX + i] + smem[2 * NMAX + i] + smem[3 * NMAX + i];
-    }
-}
-
-// Publish the block partials; returns true in the last block of the segment
-// to arrive (which then sees every partial).
-DI bool arrive_last(const VecSeg& sg, int lb, int nval, double bsum, bool* s_last) {
-    if (threadIdx.x < nval) sg.part[(int64_t)lb * NPART + threadIdx.x] = bsum;
-    __threadfence();
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        unsigned t = atomicAdd(&sg.st->ticket, 1u);
-        *s_last = (t == (unsigned)sg.nblk - 1);
+        out[i] = smem[i] + smem[NV + i] + smem[2 * NV + i] + smem[3 * NV + i];
     }
     __syncthreads();
-    if (*s_last) __threadfence();
-    return *s_last;
 }
 
-// Fixed-order sum of partial slot i over the segment's blocks.
-DI double final_sum(const VecSeg& sg, int i) {
-    double s = 0.0;
-    for (int b = 0; b < sg.nblk; ++b) s += sg.part[(int64_t)b * NPART + i];
-    return s;
+// Column sums of a partial table P[b * ld + c] (b < nb, c < NVAL), in the same
+// fixed order in every block; result in s_out[0..NVAL).  s_tmp: BLOCK doubles.
+template <int NVAL>
+DI void reduce_table(const __attribute__((address_space(1))) double* P, int ld, int nb, double* s_tmp,
+                     double* s_out) {
+    constexpr int G = (BLOCK / NVAL) < 64 ? (BLOCK / NVAL) : 64;
+    const int c = threadIdx.x % NVAL, r = threadIdx.x / NVAL;
+    double a = 0.0;
+    if (r < G)
+        for (int b = r; b < nb; b += G) a += P[(int64_t)b * ld + c];
+    s_tmp[threadIdx.x] = a;
+    __syncthreads();
+    if (threadIdx.x < NVAL) {
+        double s = 0.0;
+        for (int g = 0; g < G; ++g) s += s_tmp[g * NVAL + threadIdx.x];
+        s_out[threadIdx.x] = s;
+    }
+    __syncthreads();
 }
 
 }  // namespace
 
-// ||R||_2 and the start of a GMRES cycle: beta = ||R||, g = beta e1, k = 0,
-// eta_abs = max(eta_rel beta, eta_floor).
-__global__ __launch_bounds__(BLOCK) void k_norm_begin(const VecSeg* __restrict__ segs, int nseg) {
-    __shared__ double smem[4 * 1];
-    __shared__ bool s_last;
+// Partial sums of ||R||^2 (one per block) -> part2.
+__global__ __launch_bounds__(BLOCK) void k_rnorm(const VecSeg* __restrict__ segs, int nseg) {
+    __shared__ double smem[4];
+    __shared__ double s_out[1];
     const VecSeg& sg = segs[find_vseg(segs, nseg, blockIdx.x)];
     const int lb = blockIdx.x - sg.blk0;
+    const auto* __restrict__ R = gl((const double*)sg.R);
     double acc[1] = {0.0};
     const int64_t stride = (int64_t)sg.nblk * BLOCK;
-    for (int64_t i = (int64_t)lb * BLOCK + threadIdx.x; i < sg.n; i += stride) {
-        const double r = sg.R[i];
-        acc[0] += r * r;
-    }
-    double bs;
-    block_sums<1>(acc, 1, smem, bs);
-    if (!arrive_last(sg, lb, 1, bs, &s_last)) return;
-    if (threadIdx.x == 0) {
-        GState* st = sg.st;
-        const double nr2 = final_sum(sg, 0);
-        const double nr = sqrt(nr2);
-        st->ticket = 0;
-        if (st->outer == 0) st->target = sg.tol * (nr > 1.0 ? nr : 1.0);
-        st->outer += 1;
-        st->rnorm = nr;
-        st->beta = nr;
-        st->k = 0;
-        st->kfinal = 0;
-        st->iters = 0;
-        st->g[0] = nr;
-        const double ea = sg.eta_rel * nr, ef = sg.eta_tgt * st->target;
-        st->eta_abs = ea > ef ? ea : ef;
-        st->nonfinite = !isfinite(nr2);
-        st->done = (nr <= st->target) || st->nonfinite;
-    }
+    for (int64_t i = (int64_t)lb * BLOCK + threadIdx.x; i < sg.n; i += stride) acc[0] += R[i] * R[i];
+    block_sums<1>(acc, smem, s_out);
+    if (threadIdx.x == 0) gl(sg.part2)[lb] = s_out[0];
+}
+
+// Start of an outer iteration (one block per slab): ||R|| from the partials,
+// the stopping threshold on the first iteration, and the GMRES cycle state
+// beta = ||R||, g = beta e1, k = 0, eta_abs = max(eta_rel beta, eta_tgt target).
+__global__ __launch_bounds__(BLOCK) void k_begin(const VecSeg* __restrict__ segs, int nseg) {
+    __shared__ double s_tmp[BLOCK];
+    __shared__ double s_out[1];
+    if (blockIdx.x >= nseg) return;
+    const VecSeg& sg = segs[blockIdx.x];
+    reduce_table<1>(gl((const double*)sg.part2), 1, sg.nblk, s_tmp, s_out);
+    if (threadIdx.x != 0) return;
+    GState* st = sg.st;
+    const double nr2 = s_out[0];
+    const double nr = sqrt(nr2);
+    if (st->outer == 0) st->target = sg.tol * (nr > 1.0 ? nr : 1.0);
+    st->outer += 1;
+    st->rnorm = nr;
+    st->beta = nr;
+    st->k = 0;
+    st->kfinal = 0;
+    st->iters = 0;
+    st->g[0] = nr;
+    const double ea = sg.eta_rel * nr, ef = sg.eta_tgt * st->target;
+    st->eta_abs = ea > ef ? ea : ef;
+    st->nonfinite = !isfinite(nr2);
+    st->done = (nr <= st->target) || st->nonfinite;
 }
 
 // V_0 = -R / beta
@@ -119,135 +140,181 @@ __global__ __launch_bounds__(BLOCK) void k_scale_v0(const VecSeg* __restrict__ s
     if (sg.st->done) return;
     const int lb = blockIdx.x - sg.blk0;
     const double s = -1.0 / sg.st->beta;
+    const auto* __restrict__ R = gl((const double*)sg.R);
+    auto* __restrict__ V = gl(sg.V);
     const int64_t stride = (int64_t)sg.nblk * BLOCK;
-    for (int64_t i = (int64_t)lb * BLOCK + threadIdx.x; i < sg.n; i += stride) sg.V[i] = s * sg.R[i];
+    for (int64_t i = (int64_t)lb * BLOCK + threadIdx.x; i < sg.n; i += stride) V[i] = s * R[i];
 }
 
-// Projections hp_i = V_i . w (i <= k) of one Gram-Schmidt pass; pass 0 also
-// takes ||w||^2 before orthogonalisation (for the breakdown test).
-__global__ __launch_bounds__(BLOCK) void k_multidot(const VecSeg* __restrict__ segs, int nseg, int pass) {
-    __shared__ double smem[4 * NPART];
-    __shared__ bool s_last;
-    const VecSeg& sg = segs[find_vseg(segs, nseg, blockIdx.x)];
-    GState* st = sg.st;
-    if (st->done) return;
-    const int k = st->k;
-    const int nval = k + 2;
-    const int lb = blockIdx.x - sg.blk0;
-    double acc[NPART];
-#pragma unroll
-    for (int i = 0; i < NPART; ++i) acc[i] = 0.0;
-    const int64_t n = sg.n;
-    const int64_t stride = (int64_t)sg.nblk * BLOCK;
-    for (int64_t t = (int64_t)lb * BLOCK + threadIdx.x; t < n; t += stride) {
-        const double wv = sg.w[t];
-#pragma unroll
-        for (int i = 0; i < MMAX; ++i)
-            if (i <= k) acc[i] += sg.V[(int64_t)i * n + t] * wv;
-        acc[MMAX] += wv * wv;
-    }
-    // move the w.w slot next to the projections
-#pragma unroll
-    for (int i = 0; i < MMAX; ++i)
-        if (i == k + 1) acc[i] = acc[MMAX];
-    double bs;
-    block_sums<NPART>(acc, nval, smem, bs);
-    if (!arrive_last(sg, lb, nval, bs, &s_last)) return;
-    if (threadIdx.x < nval) {
-        const int i = threadIdx.x;
-        const double s = final_sum(sg, i);
-        if (i <= k) {
-            st->hp[i] = s;
-            st->hacc[i] = (pass == 0 ? 0.0 : st->hacc[i]) + s;
-        } else if (pass == 0) {
-            st->wn0 = s;
-        }
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) st->ticket = 0;
-}
-
-// w -= sum_i hp_i V_i; on the last pass the last block also finishes the
-// Arnoldi column: h_{k+1,k} = ||w||, Givens rotations, residual estimate,
-// stopping test, and 1/h_{k+1,k} for the normalisation.
-__global__ __launch_bounds__(BLOCK) void k_update(const VecSeg* __restrict__ segs, int nseg, int last) {
-    __shared__ double smem[4 * 1];
-    __shared__ bool s_last;
-    __shared__ double s_h[MMAX];
-    const VecSeg& sg = segs[find_vseg(segs, nseg, blockIdx.x)];
-    GState* st = sg.st;
-    if (st->done) return;
-    const int k = st->k;
-    if (threadIdx.x < MMAX) s_h[threadIdx.x] = threadIdx.x <= k ? st->hp[threadIdx.x] : 0.0;
-    __syncthreads();
-    const int lb = blockIdx.x - sg.blk0;
-    const int64_t n = sg.n;
-    const int64_t stride = (int64_t)sg.nblk * BLOCK;
-    double acc[1] = {0.0};
-    for (int64_t t = (int64_t)lb * BLOCK + threadIdx.x; t < n; t += stride) {
-        double wv = sg.w[t];
-#pragma unroll
-        for (int i = 0; i < MMAX; ++i)
-            if (i <= k) wv -= s_h[i] * sg.V[(int64_t)i * n + t];
-        sg.w[t] = wv;
-        acc[0] += wv * wv;
-    }
-    double bs;
-    block_sums<1>(acc, 1, smem, bs);
-    if (!arrive_last(sg, lb, 1, bs, &s_last)) return;
-    if (threadIdx.x != 0) return;
-    st->ticket = 0;
-    if (!last) return;
-    const int m = sg.m;
-    const double w2 = final_sum(sg, 0);
-    const double hn = sqrt(w2);
-    double* H = st->H;
-    for (int i = 0; i <= k; ++i) H[i * MMAX + k] = st->hacc[i];
-    H[(k + 1) * MMAX + k] = hn;
-    for (int i = 0; i < k; ++i) {
-        const double a = H[i * MMAX + k], b = H[(i + 1) * MMAX + k];
-        H[i * MMAX + k] = st->cs[i] * a + st->sn[i] * b;
-        H[(i + 1) * MMAX + k] = -st->sn[i] * a + st->cs[i] * b;
-    }
-    const double a = H[k * MMAX + k], b = hn;
-    const double den = sqrt(a * a + b * b);
-    const double c = den > 0.0 ? a / den : 1.0;
-    const double s = den > 0.0 ? b / den : 0.0;
-    st->cs[k] = c;
-    st->sn[k] = s;
-    H[k * MMAX + k] = den;
-    H[(k + 1) * MMAX + k] = 0.0;
-    const double gk = st->g[k];
-    st->g[k + 1] = -s * gk;
-    st->g[k] = c * gk;
-    st->iters += 1;
-    st->iters_total += 1;
-    const double res = fabs(st->g[k + 1]);
-    const bool nonfin = !isfinite(hn) || !isfinite(res) || !isfinite(den);
-    const bool breakdown = hn <= 1e-14 * sqrt(st->wn0);
-    if (nonfin) {
-        st->nonfinite = 1;
-        st->done = 1;
-        st->kfinal = k;          // drop the broken column
-    } else if (res <= st->eta_abs || breakdown || k + 1 >= m) {
-        st->done = 1;
-        st->kfinal = k + 1;
-    } else {
-        st->k = k + 1;
-        st->inv = 1.0 / hn;
-    }
-}
-
-// V_{k} = w / h_{k,k-1} (k already advanced by k_update)
-__global__ __launch_bounds__(BLOCK) void k_normalize(const VecSeg* __restrict__ segs, int nseg) {
+// Projections V_i . w (i < NV) and w . w of one Gram-Schmidt pass, as one
+// row of partial sums per block -> part.
+template <int NV>
+__global__ __launch_bounds__(BLOCK) void k_multidot(const VecSeg* __restrict__ segs, int nseg) {
+    __shared__ double smem[4 * (NV + 1)];
+    __shared__ double s_out[NV + 1];
     const VecSeg& sg = segs[find_vseg(segs, nseg, blockIdx.x)];
     const GState* st = sg.st;
-    if (st->done) return;
+    if (st->done || st->k != NV - 1) return;
     const int lb = blockIdx.x - sg.blk0;
-    const double s = st->inv;
-    double* __restrict__ vk = sg.V + (int64_t)st->k * sg.n;
+    double acc[NV + 1];
+#pragma unroll
+    for (int i = 0; i <= NV; ++i) acc[i] = 0.0;
+    const int64_t n = sg.n;
     const int64_t stride = (int64_t)sg.nblk * BLOCK;
-    for (int64_t i = (int64_t)lb * BLOCK + threadIdx.x; i < sg.n; i += stride) vk[i] = s * sg.w[i];
+    const auto* __restrict__ V = gl((const double*)sg.V);
+    const auto* __restrict__ w = gl((const double*)sg.w);
+    int64_t t = (int64_t)lb * BLOCK + threadIdx.x;
+    for (; t + stride < n; t += 2 * stride) {
+        const double w0 = w[t], w1 = w[t + stride];
+        double a0[NV], a1[NV];
+#pragma unroll
+        for (int i = 0; i < NV; ++i) {
+            a0[i] = V[(int64_t)i * n + t];
+            a1[i] = V[(int64_t)i * n + t + stride];
+        }
+#pragma unroll
+        for (int i = 0; i < NV; ++i) acc[i] += a0[i] * w0 + a1[i] * w1;
+        acc[NV] += w0 * w0 + w1 * w1;
+    }
+    if (t < n) {
+        const double w0 = w[t];
+#pragma unroll
+        for (int i = 0; i < NV; ++i) acc[i] += V[(int64_t)i * n + t] * w0;
+        acc[NV] += w0 * w0;
+    }
+    block_sums<NV + 1>(acc, smem, s_out);
+    if (threadIdx.x <= NV) gl(sg.part)[(int64_t)lb * NPART + threadIdx.x] = s_out[threadIdx.x];
+}
+
+// w -= sum_i h_i V_i with h the column sums of the multi-dot table (every
+// block reduces it the same way); one row of partial ||w||^2 -> part2.
+// Block 0 accumulates h into the Arnoldi column (hacc) and keeps ||w||^2
+// before orthogonalisation (pass 0) for the breakdown test.
+template <int NV>
+__global__ __launch_bounds__(BLOCK) void k_update(const VecSeg* __restrict__ segs, int nseg, int pass) {
+    __shared__ double smem[4];
+    __shared__ double s_tmp[BLOCK];
+    __shared__ double s_h[NV + 1];
+    __shared__ double s_out[1];
+    const VecSeg& sg = segs[find_vseg(segs, nseg, blockIdx.x)];
+    GState* st = sg.st;
+    if (st->done || st->k != NV - 1) return;
+    const int lb = blockIdx.x - sg.blk0;
+    reduce_table<NV + 1>(gl((const double*)sg.part), NPART, sg.nblk, s_tmp, s_h);
+    if (lb == 0 && threadIdx.x <= NV) {
+        const int i = threadIdx.x;
+        if (i < NV) st->hacc[i] = (pass == 0 ? 0.0 : st->hacc[i]) + s_h[i];
+        else if (pass == 0) st->wn0 = s_h[NV];
+    }
+    double h[NV];
+#pragma unroll
+    for (int i = 0; i < NV; ++i) h[i] = s_h[i];
+    const int64_t n = sg.n;
+    const int64_t stride = (int64_t)sg.nblk * BLOCK;
+    const auto* __restrict__ V = gl((const double*)sg.V);
+    auto* __restrict__ w = gl(sg.w);
+    double acc[1] = {0.0};
+    int64_t t = (int64_t)lb * BLOCK + threadIdx.x;
+    for (; t + stride < n; t += 2 * stride) {
+        double a0[NV], a1[NV];
+#pragma unroll
+        for (int i = 0; i < NV; ++i) {
+            a0[i] = V[(int64_t)i * n + t];
+            a1[i] = V[(int64_t)i * n + t + stride];
+        }
+        double w0 = w[t], w1 = w[t + stride];
+#pragma unroll
+        for (int i = 0; i < NV; ++i) {
+            w0 -= h[i] * a0[i];
+            w1 -= h[i] * a1[i];
+        }
+        w[t] = w0;
+        w[t + stride] = w1;
+        acc[0] += w0 * w0 + w1 * w1;
+    }
+    if (t < n) {
+        double w0 = w[t];
+#pragma unroll
+        for (int i = 0; i < NV; ++i) w0 -= h[i] * V[(int64_t)i * n + t];
+        w[t] = w0;
+        acc[0] += w0 * w0;
+    }
+    block_sums<1>(acc, smem, s_out);
+    if (threadIdx.x == 0) gl(sg.part2)[lb] = s_out[0];
+}
+
+// End of an Arnoldi step k = NV - 1: h_{k+1,k} = ||w|| from the update's
+// partials, the Givens rotations of column k, the residual estimate and the
+// stopping test -- computed identically in every block.  Unless the cycle
+// ends here, every block writes its chunk of V_{k+1} = w / h_{k+1,k}.
+// Block 0 commits the column, rotation and the next step to the state.
+template <int NV>
+__global__ __launch_bounds__(BLOCK) void k_normalize(const VecSeg* __restrict__ segs, int nseg) {
+    __shared__ double s_tmp[BLOCK];
+    __shared__ double s_out[1];
+    __shared__ double s_col[NV + 1];
+    const VecSeg& sg = segs[find_vseg(segs, nseg, blockIdx.x)];
+    GState* st = sg.st;
+    // only block 0 of this kernel writes done / k, and a cycle that ends here
+    // needs no V_{k+1}, so reading done here is safe in every block
+    if (st->done) return;
+    constexpr int k = NV - 1;
+    const int lb = blockIdx.x - sg.blk0;
+    reduce_table<1>(gl((const double*)sg.part2), 1, sg.nblk, s_tmp, s_out);
+    const double hn = sqrt(s_out[0]);
+    // Givens: rotate column k by the previous rotations, then make a new one
+    if (threadIdx.x == 0) {
+        double col[NV + 1];
+        for (int i = 0; i < NV; ++i) col[i] = st->hacc[i];
+        col[NV] = hn;
+        for (int i = 0; i < k; ++i) {
+            const double a = col[i], b = col[i + 1];
+            col[i] = st->cs[i] * a + st->sn[i] * b;
+            col[i + 1] = -st->sn[i] * a + st->cs[i] * b;
+        }
+        for (int i = 0; i <= NV; ++i) s_col[i] = col[i];
+    }
+    __syncthreads();
+    const double a = s_col[k], b = hn;
+    const double den = sqrt(a * a + b * b);
+    const double c = den > 0.0 ? a / den : 1.0;
+    const double sn = den > 0.0 ? b / den : 0.0;
+    const double gk = st->g[k];
+    const double gk1 = -sn * gk;
+    const double res = fabs(gk1);
+    const bool nonfin = !isfinite(hn) || !isfinite(res) || !isfinite(den);
+    const bool breakdown = hn <= 1e-14 * sqrt(st->wn0);
+    const bool stop = nonfin || res <= st->eta_abs || breakdown || k + 1 >= sg.m;
+    if (lb == 0 && threadIdx.x == 0) {
+        double* H = st->H;
+        for (int i = 0; i < k; ++i) H[i * MMAX + k] = s_col[i];
+        H[k * MMAX + k] = den;
+        st->cs[k] = c;
+        st->sn[k] = sn;
+        st->g[k + 1] = gk1;       // read by the next step's kernel only
+        st->gr[k] = c * gk;
+        st->iters += 1;
+        st->iters_total += 1;
+        st->kbytes[3] += 8.0 * (double)(NV + 1) * (double)sg.n;   // multi-dot: V_0..V_k and w
+        st->kbytes[4] += 8.0 * (double)(NV + 2) * (double)sg.n;   // update: V_0..V_k, w in and out
+        if (nonfin) {
+            st->nonfinite = 1;
+            st->done = 1;
+            st->kfinal = k;          // drop the broken column
+        } else if (stop) {
+            st->done = 1;
+            st->kfinal = k + 1;
+        } else {
+            st->k = k + 1;
+            st->kbytes[5] += 16.0 * (double)sg.n;                // normalise: w in, V_{k+1} out
+        }
+    }
+    if (stop) return;
+    const double s = 1.0 / hn;
+    auto* __restrict__ vk = gl(sg.V + (int64_t)(k + 1) * sg.n);
+    const auto* __restrict__ w = gl((const double*)sg.w);
+    const int64_t stride = (int64_t)sg.nblk * BLOCK;
+    for (int64_t i = (int64_t)lb * BLOCK + threadIdx.x; i < sg.n; i += stride) vk[i] = s * w[i];
 }
 
 // y = H(0:kf, 0:kf)^-1 g(0:kf) by back substitution; one block per segment.
@@ -256,7 +323,7 @@ __global__ void k_finish(const VecSeg* __restrict__ segs, int nseg) {
     GState* st = segs[blockIdx.x].st;
     const int kf = st->kfinal;
     for (int i = kf - 1; i >= 0; --i) {
-        double s = st->g[i];
+        double s = st->gr[i];
         for (int j = i + 1; j < kf; ++j) s -= st->H[i * MMAX + j] * st->y[j];
         st->y[i] = s / st->H[i * MMAX + i];
     }
@@ -274,12 +341,22 @@ __global__ __launch_bounds__(BLOCK) void k_update_u(const VecSeg* __restrict__ s
     const int lb = blockIdx.x - sg.blk0;
     const int64_t n = sg.n;
     const int64_t stride = (int64_t)sg.nblk * BLOCK;
+    const auto* __restrict__ V = gl((const double*)sg.V);
+    auto* __restrict__ U = gl(sg.U);
     for (int64_t t = (int64_t)lb * BLOCK + threadIdx.x; t < n; t += stride) {
-        double u = sg.U[t];
+        double u = U[t];
+        // groups of 4 independent loads; indices past kf re-read V_{kf-1} with weight 0
+        for (int i0 = 0; i0 < kf; i0 += 4) {
+            double a[4];
 #pragma unroll
-        for (int i = 0; i < MMAX; ++i)
-            if (i < kf) u += s_y[i] * sg.V[(int64_t)i * n + t];
-        sg.U[t] = u;
+            for (int j = 0; j < 4; ++j) {
+                const int i = i0 + j < kf ? i0 + j : kf - 1;
+                a[j] = V[(int64_t)i * n + t];
+            }
+#pragma unroll
+            for (int j = 0; j < 4; ++j) u += s_y[i0 + j < MMAX ? i0 + j : MMAX - 1] * (i0 + j < kf ? a[j] : 0.0);
+        }
+        U[t] = u;
     }
 }
 
@@ -325,11 +402,37 @@ __global__ void k_put_vecseg(VecSeg* dst, VecSeg v) { if (threadIdx.x == 0 && bl
 // ---------------------------------------------------------------------------
 #define LAUNCH_V(K, G, ...) hipLaunchKernelGGL(K, dim3(G), dim3(BLOCK), 0, st, __VA_ARGS__)
 
-void vk_norm_begin(const VecSeg* s, int nseg, int G, hipStream_t st) { LAUNCH_V(k_norm_begin, G, s, nseg); }
+namespace {
+template <int NV>
+void md_launch(const VecSeg* s, int nseg, int G, int, hipStream_t st) { LAUNCH_V(k_multidot<NV>, G, s, nseg); }
+template <int NV>
+void up_launch(const VecSeg* s, int nseg, int G, int pass, hipStream_t st) { LAUNCH_V(k_update<NV>, G, s, nseg, pass); }
+template <int NV>
+void nm_launch(const VecSeg* s, int nseg, int G, int, hipStream_t st) { LAUNCH_V(k_normalize<NV>, G, s, nseg); }
+using VLaunch = void (*)(const VecSeg*, int, int, int, hipStream_t);
+template <int... I>
+constexpr std::array<VLaunch, sizeof...(I)> md_table(std::integer_sequence<int, I...>) { return {&md_launch<I + 1>...}; }
+template <int... I>
+constexpr std::array<VLaunch, sizeof...(I)> up_table(std::integer_sequence<int, I...>) { return {&up_launch<I + 1>...}; }
+template <int... I>
+constexpr std::array<VLaunch, sizeof...(I)> nm_table(std::integer_sequence<int, I...>) { return {&nm_launch<I + 1>...}; }
+}  // namespace
+
+void vk_rnorm(const VecSeg* s, int nseg, int G, hipStream_t st) { LAUNCH_V(k_rnorm, G, s, nseg); }
+void vk_begin(const VecSeg* s, int nseg, hipStream_t st) { LAUNCH_V(k_begin, nseg, s, nseg); }
 void vk_scale_v0(const VecSeg* s, int nseg, int G, hipStream_t st) { LAUNCH_V(k_scale_v0, G, s, nseg); }
-void vk_multidot(const VecSeg* s, int nseg, int G, int pass, hipStream_t st) { LAUNCH_V(k_multidot, G, s, nseg, pass); }
-void vk_update(const VecSeg* s, int nseg, int G, int last, hipStream_t st) { LAUNCH_V(k_update, G, s, nseg, last); }
-void vk_normalize(const VecSeg* s, int nseg, int G, hipStream_t st) { LAUNCH_V(k_normalize, G, s, nseg); }
+void vk_multidot(const VecSeg* s, int nseg, int G, int k, hipStream_t st) {
+    static const auto tbl = md_table(std::make_integer_sequence<int, MMAX>{});
+    tbl[k](s, nseg, G, 0, st);
+}
+void vk_update(const VecSeg* s, int nseg, int G, int pass, int k, hipStream_t st) {
+    static const auto tbl = up_table(std::make_integer_sequence<int, MMAX>{});
+    tbl[k](s, nseg, G, pass, st);
+}
+void vk_normalize(const VecSeg* s, int nseg, int G, int k, hipStream_t st) {
+    static const auto tbl = nm_table(std::make_integer_sequence<int, MMAX>{});
+    tbl[k](s, nseg, G, 0, st);
+}
 void vk_finish(const VecSeg* s, int nseg, hipStream_t st) {
     hipLaunchKernelGGL(k_finish, dim3(nseg), dim3(64), 0, st, s, nseg);
 }

@@ -6,13 +6,15 @@
 
 namespace stdg {
 
-constexpr int NPART_SLOTS = MMAX + 2;   // per-block partial slots of the reductions
+constexpr int NPART_SLOTS = MMAX + 2;   // per-block partial slots of the multi-dot table
 
-void vk_norm_begin(const VecSeg* s, int nseg, int G, hipStream_t st);
+void vk_rnorm(const VecSeg* s, int nseg, int G, hipStream_t st);      // partial ||R||^2
+void vk_begin(const VecSeg* s, int nseg, hipStream_t st);             // ||R||, cycle state
 void vk_scale_v0(const VecSeg* s, int nseg, int G, hipStream_t st);
-void vk_multidot(const VecSeg* s, int nseg, int G, int pass, hipStream_t st);
-void vk_update(const VecSeg* s, int nseg, int G, int last, hipStream_t st);
-void vk_normalize(const VecSeg* s, int nseg, int G, hipStream_t st);
+// k: the Arnoldi step index (0 .. m-1), the same for every slab of the launch
+void vk_multidot(const VecSeg* s, int nseg, int G, int k, hipStream_t st);
+void vk_update(const VecSeg* s, int nseg, int G, int pass, int k, hipStream_t st);
+void vk_normalize(const VecSeg* s, int nseg, int G, int k, hipStream_t st);
 void vk_finish(const VecSeg* s, int nseg, hipStream_t st);
 void vk_update_u(const VecSeg* s, int nseg, int G, hipStream_t st);
 void vk_init_guess(const VecSeg* s, int nseg, int G, hipStream_t st);

@@ -44,11 +44,16 @@ DI int find_seg(const Seg* segs, int nseg, int L) {
     return lo;
 }
 
+// Device pointer of a descriptor entry, in the global address space (so that
+// accesses compile to global_load/global_store rather than flat ones).
 template <class P>
-DI P* resolve(const DynPtr& d) {
+using gptr = __attribute__((address_space(1))) P*;
+
+template <class P>
+DI gptr<P> resolve(const DynPtr& d) {
     const P* b = static_cast<const P*>(d.base);
     if (d.kp) b += (int64_t)(*d.kp + d.koff) * d.ld;
-    return const_cast<P*>(b);
+    return (gptr<P>)const_cast<P*>(b);
 }
 
 template <int D> DI int node_coord(int s, int n1, int a) {
@@ -116,11 +121,12 @@ __global__ __launch_bounds__(BLOCK) void k_op(const OpSeg* __restrict__ segs, in
     const int64_t e = (int64_t)(L - sg.blk0) * EPB + el;
     const bool active = (el < EPB) && (e < sg.E);
 
-    const UT* __restrict__ Up = resolve<UT>(sg.U);
-    const double* __restrict__ Vp = JVP ? resolve<double>(sg.V) : nullptr;
-    const CT* __restrict__ Qp = VISC ? resolve<CT>(sg.Q) : nullptr;
-    const CT* __restrict__ dQp = (VISC && JVP) ? resolve<CT>(sg.dQ) : nullptr;
-    double* __restrict__ out = resolve<double>(sg.out);
+    const gptr<UT> __restrict__ Up = resolve<UT>(sg.U);
+    const gptr<double> __restrict__ Vp = JVP ? resolve<double>(sg.V) : nullptr;
+    const gptr<CT> __restrict__ Qp = VISC ? resolve<CT>(sg.Q) : nullptr;
+    const gptr<CT> __restrict__ dQp = (VISC && JVP) ? resolve<CT>(sg.dQ) : nullptr;
+    const gptr<double> __restrict__ out = resolve<double>(sg.out);
+    const gptr<const double> __restrict__ upv = (gptr<const double>)sg.uprev;
 
     const int ec[3] = {(int)(e % sg.K[0]), (int)((e / sg.K[0]) % sg.K[1]), (int)(e / ((int64_t)sg.K[0] * sg.K[1]))};
     const int64_t es[3] = {1, sg.K[0], (int64_t)sg.K[0] * sg.K[1]};
@@ -140,7 +146,7 @@ __global__ __launch_bounds__(BLOCK) void k_op(const OpSeg* __restrict__ segs, in
             }
         }
 
-    auto load_q = [&](const CT* base, const CT* dbase, int64_t ee, int ss, int j, T* q) {
+    auto load_q = [&](gptr<CT> base, gptr<CT> dbase, int64_t ee, int ss, int j, T* q) {
 #pragma unroll
         for (int b = 0; b < D; ++b)
 #pragma unroll
@@ -226,7 +232,7 @@ __global__ __launch_bounds__(BLOCK) void k_op(const OpSeg* __restrict__ segs, in
 #pragma unroll
         for (int v = 0; v < R; ++v) {
             CT up = CT(0);
-            if (!JVP && sg.uprev) up = CT(sg.uprev[(e * R + v) * NS + s]);
+            if (!JVP && upv) up = CT(upv[(e * R + v) * NS + s]);
 #pragma unroll
             for (int j = 0; j < NT; ++j) {
                 CT dtu = CT(sg.Dt[j * NT]) * part(u[0][v]);
@@ -259,8 +265,8 @@ __global__ __launch_bounds__(BLOCK) void k_grad(const OpSeg* __restrict__ segs, 
     const int s = tid - el * NS;
     const int64_t e = (int64_t)(L - sg.blk0) * EPB + el;
     const bool active = (el < EPB) && (e < sg.E);
-    const UT* __restrict__ Up = resolve<UT>(sg.U);
-    CT* __restrict__ Qp = resolve<CT>(sg.out);
+    const gptr<UT> __restrict__ Up = resolve<UT>(sg.U);
+    const gptr<CT> __restrict__ Qp = resolve<CT>(sg.out);
     const int ec[3] = {(int)(e % sg.K[0]), (int)((e / sg.K[0]) % sg.K[1]), (int)(e / ((int64_t)sg.K[0] * sg.K[1]))};
     const int64_t es[3] = {1, sg.K[0], (int64_t)sg.K[0] * sg.K[1]};
 

@@ -100,7 +100,7 @@ Layout layout_of(const Problem& pb, const st_solver_opts_t& o) {
     L.U32 = (fp32 && nonlin) ? take(4 * n) : -1;
     L.Q32 = (fp32 && visc && nonlin) ? take(4 * d * n) : -1;
     L.dQ32 = (fp32 && visc) ? take(4 * d * n) : -1;
-    L.part = take(8 * (int64_t)vec_blocks(n) * NPART_SLOTS);
+    L.part = take(8 * (int64_t)vec_blocks(n) * (NPART_SLOTS + 1));
     L.total = off;
     return L;
 }
@@ -217,6 +217,7 @@ VecSeg vecseg_of(st_srv* s, Req* r) {
     v.n = r->pb.n;
     v.st = s->d_states + r->slot;
     v.part = r->dp(r->lay.part);
+    v.part2 = v.part + (int64_t)vec_blocks(r->pb.n) * NPART_SLOTS;
     v.eta_rel = r->eta_rel;
     v.eta_tgt = 0.5;
     v.tol = r->tol;
@@ -410,7 +411,8 @@ bool tick(st_srv* s) {
         if (!g.grad.empty()) g.ops->grad64((OpSeg*)(D0 + g.off_grad), (int)g.grad.size(), g.G, st);
         g.ops->res64((OpSeg*)(D0 + g.off_op), (int)g.op.size(), g.G, st);
     }
-    vk_norm_begin((VecSeg*)(D0 + off_vall), (int)vall.size(), Gall, st);
+    vk_rnorm((VecSeg*)(D0 + off_vall), (int)vall.size(), Gall, st);
+    vk_begin((VecSeg*)(D0 + off_vall), (int)vall.size(), st);
     // headers of every slot's state
     const size_t hdr = offsetof(GState, hacc);
     (void)hipMemcpy2DAsync(s->h_states, sizeof(GState), s->d_states, sizeof(GState), hdr, s->opts.max_active,
@@ -511,10 +513,10 @@ bool tick(st_srv* s) {
             f((OpSeg*)(D1 + g.off_op), (int)g.op.size(), g.G, st);
         }
         for (int p = 0; p < passes; ++p) {
-            vk_multidot(dvc, nc, Gc, p, st);
-            vk_update(dvc, nc, Gc, p == passes - 1, st);
+            vk_multidot(dvc, nc, Gc, k, st);
+            vk_update(dvc, nc, Gc, p, k, st);
         }
-        vk_normalize(dvc, nc, Gc, st);
+        vk_normalize(dvc, nc, Gc, k, st);
     }
     vk_finish(dvc, nc, st);
     vk_update_u(dvc, nc, Gc, st);

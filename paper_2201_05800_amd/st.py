@@ -26,6 +26,8 @@ ST_ERR_NOT_FOUND = -7
 ST_ERR_CANCELLED = -8
 
 ST_ADVECTION, ST_ADVDIFF_BR1, ST_BURGERS, ST_EULER, ST_NS_BR1 = 1, 2, 3, 4, 5
+ST_K_RESIDUAL, ST_K_JVP, ST_K_GRAD, ST_K_MULTIDOT, ST_K_UPDATE, ST_K_NORMALIZE, ST_K_NEWTON = range(7)
+KERNEL_CLASSES = ("residual", "jvp", "grad", "multidot", "update", "normalize", "newton")
 
 _c_double_p = ctypes.POINTER(ctypes.c_double)
 
@@ -42,12 +44,14 @@ class Equation(ctypes.Structure):
 
 class SolverOpts(ctypes.Structure):
     _fields_ = [("restart", ctypes.c_int), ("max_newton", ctypes.c_int), ("cgs_passes", ctypes.c_int),
-                ("inner_fp32", ctypes.c_int), ("gmres_rtol", ctypes.c_double)]
+                ("inner_fp32", ctypes.c_int), ("gmres_rtol", ctypes.c_double), ("timing", ctypes.c_int)]
 
 
 class Stats(ctypes.Structure):
     _fields_ = [("newton_its", ctypes.c_int), ("gmres_its", ctypes.c_int), ("res0", ctypes.c_double),
-                ("res_final", ctypes.c_double), ("usec", ctypes.c_double), ("status", ctypes.c_int)]
+                ("res_final", ctypes.c_double), ("usec", ctypes.c_double), ("status", ctypes.c_int),
+                ("kernel_us", ctypes.c_double * 8), ("kernel_calls", ctypes.c_int * 8),
+                ("kernel_bytes", ctypes.c_double * 8)]
 
 
 class ServerOpts(ctypes.Structure):
@@ -235,7 +239,8 @@ def st_solve_slab(h, u_prev, t0, dt, tol, opts=None, U_out=None, u_next=None, st
                              ctypes.byref(opts) if opts is not None else None, _dev(U_out, "U_out"),
                              _dev(u_next, "u_next"), ctypes.byref(st), _stream(stream))
     out = dict(rc=rc, newton_its=st.newton_its, gmres_its=st.gmres_its, res0=st.res0, res_final=st.res_final,
-               usec=st.usec, status=st.status)
+               usec=st.usec, status=st.status, kernel_us=list(st.kernel_us), kernel_calls=list(st.kernel_calls),
+               kernel_bytes=list(st.kernel_bytes))
     if check:
         _check(rc)
     return out
