@@ -63,6 +63,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--restart", type=int, default=30)
     ap.add_argument("--cgs-passes", type=int, default=1)
+    ap.add_argument("--no-timing", action="store_true", help="run without HIP-event kernel timing")
     return ap.parse_args()
 
 
@@ -132,9 +133,9 @@ def main():
 
     # HIP-event timing of the operator and Gram-Schmidt kernel classes
     timed = (1 << st.ST_K_MULTIDOT) | (1 << st.ST_K_UPDATE) | (1 << st.ST_K_JVP) | (1 << st.ST_K_RESIDUAL) \
-        | (1 << st.ST_K_GRAD)
+        | (1 << st.ST_K_GRAD) | (1 << st.ST_K_NORMALIZE)
     opts = st.st_default_opts(restart=args.restart, cgs_passes=args.cgs_passes, inner_fp32=args.fp32_inner,
-                              timing=timed)
+                              timing=0 if args.no_timing else timed)
     stream = torch.cuda.current_stream()
     u = torch.as_tensor(u0).cuda()
     un = torch.empty(nsp, dtype=torch.float64, device="cuda")

@@ -1,0 +1,95 @@
+"""CPU-side checks of the C ABI library: it loads, exports every entry point
+that include/st.h declares, and its host logic (LGL tables, footprints,
+argument validation) behaves; no GPU compute is called here."""
+import ctypes
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_functions():
+    txt = open(os.path.join(ROOT, "include", "st.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    names = re.findall(r"\b(st_[a-z_0-9]+)\s*\(", txt)
+    return sorted(set(names))
+
+
+def test_exports_every_declared_symbol():
+    from paper_2201_05800_amd import st
+    lib = ctypes.CDLL(st.LIB_PATH)
+    names = header_functions()
+    assert len(names) >= 17
+    for n in names:
+        assert hasattr(lib, n), n
+    # the binding wraps the same set
+    assert set(names) == set(st.symbols())
+
+
+def test_lgl_tables_closed_forms():
+    from paper_2201_05800_amd import st
+    x, w, D = st.st_lgl(3)
+    assert np.allclose(x, [-1, 0, 1], atol=1e-15) and np.allclose(w, [1 / 3, 4 / 3, 1 / 3], atol=1e-15)
+    x, w, D = st.st_lgl(4)
+    assert np.allclose(x, [-1, -1 / math.sqrt(5), 1 / math.sqrt(5), 1], atol=1e-15)
+    for n in range(2, 9):
+        x, w, D = st.st_lgl(n)
+        B = np.zeros((n, n))
+        B[0, 0], B[-1, -1] = -1, 1
+        M = np.diag(w)
+        assert np.abs(M @ D + (M @ D).T - B).max() < 1e-12      # SBP
+        assert np.abs(D @ np.ones(n)).max() < 1e-12
+        for q in range(1, n):
+            assert np.abs(D @ x ** q - q * x ** (q - 1)).max() < 1e-10
+
+
+def test_lgl_matches_oracle_independent_code(orc):
+    from paper_2201_05800_amd import st
+    for n in range(2, 8):
+        a, b = st.st_lgl(n), orc.lgl(n)
+        for u, v in zip(a, b):
+            assert np.abs(u - v).max() < 1e-13
+
+
+def test_lgl_rejects_bad_sizes():
+    from paper_2201_05800_amd import st
+    for n in (0, 1, 9):
+        with pytest.raises(st.StError):
+            st.st_lgl(n)
+
+
+def test_footprint_and_validation():
+    from paper_2201_05800_amd import st
+    m = st.mesh(2, [64, 64], [0, 0], [1, 1])
+    eq = st.equation(st.ST_ADVDIFF_BR1, a=(1.0, 0.5), nu=1e-3)
+    r = st.request(m, 4, 4, eq, np.zeros(64 * 64 * 25), 0.0, 1 / 128, 1e-10, st.st_default_opts(restart=30))
+    fp = st.st_request_footprint(r)
+    n = 64 * 64 * 25 * 4
+    # U, R, w, 30 basis vectors, two BR1 gradient buffers (2 n each), u_prev, u_next, partials
+    assert 8 * n * (3 + 30 + 4) <= fp <= 8 * n * (3 + 30 + 4) + 8 * 64 * 64 * 25 * 2 + 2 ** 20
+    # unsupported combination (Burgers in 2D) and bad arguments give -1 footprints
+    r.eq = st.equation(st.ST_BURGERS)
+    assert st.st_request_footprint(r) == -1
+    r.eq = eq
+    r.N = 9
+    assert st.st_request_footprint(r) == -1
+
+
+def test_default_opts():
+    from paper_2201_05800_amd import st
+    o = st.st_default_opts()
+    assert o.restart == 30 and o.cgs_passes == 1 and o.inner_fp32 == 0 and o.max_newton >= 1
+
+
+def test_create_fails_loudly_without_gpu():
+    """On a host without a GPU the product path raises (no CPU fallback)."""
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    from paper_2201_05800_amd import st
+    with pytest.raises(st.StError):
+        st.st_create(st.mesh(1, [4], [0], [1]), 3, 3, st.equation(st.ST_ADVECTION, a=(1.0,)))
