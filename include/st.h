@@ -102,8 +102,8 @@ enum {
     ST_K_JVP = 1,       /* Jacobian-vector product operator kernel           */
     ST_K_GRAD = 2,      /* BR1 lifted-gradient kernels                       */
     ST_K_MULTIDOT = 3,  /* Gram-Schmidt projections (fused multi-dot)        */
-    ST_K_UPDATE = 4,    /* Gram-Schmidt correction + norm + Givens           */
-    ST_K_NORMALIZE = 5, /* Krylov vector normalisation                       */
+    ST_K_UPDATE = 4,    /* Gram-Schmidt correction + Givens + normalisation  */
+    ST_K_NORMALIZE = 5, /* first Krylov vector V_0 = -R / ||R||              */
     ST_K_NEWTON = 6,    /* Newton update U += V y, residual norm, setup      */
     ST_K_COUNT = 8
 };

@@ -598,9 +598,8 @@ int st_solve_slab(st_handle_t h, const double* u_prev, double t0, double dt, dou
             launch_jvp(h, fp32, 4, st);
             for (int p = 0; p < o.cgs_passes; ++p) {
                 T.run(ST_K_MULTIDOT, st, [&] { vk_multidot(h->d_vs, 1, Gv, k, st); });
-                T.run(ST_K_UPDATE, st, [&] { vk_update(h->d_vs, 1, Gv, p, k, st); });
+                T.run(ST_K_UPDATE, st, [&] { vk_update(h->d_vs, 1, Gv, p, p == o.cgs_passes - 1, k, st); });
             }
-            T.run(ST_K_NORMALIZE, st, [&] { vk_normalize(h->d_vs, 1, Gv, k, st); });
         }
         T.run(ST_K_NEWTON, st, [&] {
             vk_finish(h->d_vs, 1, st);
@@ -629,7 +628,6 @@ int st_solve_slab(st_handle_t h, const double* u_prev, double t0, double dt, dou
         }
         stats->kernel_bytes[ST_K_MULTIDOT] = h->h_st->kbytes[3] * o.cgs_passes;
         stats->kernel_bytes[ST_K_UPDATE] = h->h_st->kbytes[4] * o.cgs_passes;
-        stats->kernel_bytes[ST_K_NORMALIZE] = h->h_st->kbytes[5];
         stats->newton_its = outer;
         stats->gmres_its = h->h_st->iters_total;
         stats->res0 = r0;

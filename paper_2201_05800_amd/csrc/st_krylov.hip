@@ -1,14 +1,15 @@
 // st_krylov.hip -- Newton-GMRES vector kernels (FP64), batched over slabs.
 //
 // GMRES(m) with classical Gram-Schmidt: the k+1 projections of a new Krylov
-// vector are one fused multi-dot (one pass over the basis), the correction is
-// one fused multi-axpy pass that also takes the new norm; an optional second
-// pass (CGS2) repeats both.  Reductions are deterministic and need no atomics:
+// vector and its squared norm are one fused multi-dot (one pass over the
+// basis); the correction is one fused multi-axpy pass that writes the next
+// basis vector already normalised (its norm follows from the projections by
+// Pythagoras); an optional second pass (CGS2) repeats both.  Reductions are deterministic and need no atomics:
 // a producer kernel writes one row of partial sums per block, and the
 // consumer kernel reduces that table in a fixed order -- redundantly in every
 // block, so every block holds the same bits.  The Givens update of the
 // Hessenberg least-squares problem and the stopping test run redundantly in
-// every block of the normalisation kernel; block 0 commits them to the
+// every block of the last correction kernel; block 0 commits them to the
 // device state, which no other block of that kernel reads, so the iteration
 // never needs the host.
 //
@@ -71,20 +72,32 @@ DI void block_sums(const double (&acc)[NV], double* smem, double* out) {
     __syncthreads();
 }
 
-// Column sums of a partial table P[b * ld + c] (b < nb, c < NVAL), in the same
-// fixed order in every block; result in s_out[0..NVAL).  s_tmp: BLOCK doubles.
+// Column sums of a partial table P[b * ld + c] (b < nb <= 256, c < NVAL), in
+// the same fixed order in every block; result in s_out[0..NVAL).  Every
+// thread issues all of its loads before adding (they come from other XCDs).
+// s_tmp: BLOCK doubles.
 template <int NVAL>
 DI void reduce_table(const __attribute__((address_space(1))) double* P, int ld, int nb, double* s_tmp,
                      double* s_out) {
     constexpr int G = (BLOCK / NVAL) < 64 ? (BLOCK / NVAL) : 64;
+    constexpr int MAXR = (256 + G - 1) / G;
     const int c = threadIdx.x % NVAL, r = threadIdx.x / NVAL;
     double a = 0.0;
-    if (r < G)
-        for (int b = r; b < nb; b += G) a += P[(int64_t)b * ld + c];
+    if (r < G) {
+        double v[MAXR];
+#pragma unroll
+        for (int q = 0; q < MAXR; ++q) {
+            const int b = r + q * G;
+            v[q] = b < nb ? P[(int64_t)b * ld + c] : 0.0;
+        }
+#pragma unroll
+        for (int q = 0; q < MAXR; ++q) a += v[q];
+    }
     s_tmp[threadIdx.x] = a;
     __syncthreads();
     if (threadIdx.x < NVAL) {
         double s = 0.0;
+#pragma unroll
         for (int g = 0; g < G; ++g) s += s_tmp[g * NVAL + threadIdx.x];
         s_out[threadIdx.x] = s;
     }
@@ -186,34 +199,105 @@ __global__ __launch_bounds__(BLOCK) void k_multidot(const VecSeg* __restrict__ s
     if (threadIdx.x <= NV) gl(sg.part)[(int64_t)lb * NPART + threadIdx.x] = s_out[threadIdx.x];
 }
 
-// w -= sum_i h_i V_i with h the column sums of the multi-dot table (every
-// block reduces it the same way); one row of partial ||w||^2 -> part2.
-// Block 0 accumulates h into the Arnoldi column (hacc) and keeps ||w||^2
-// before orthogonalisation (pass 0) for the breakdown test.
+// One Gram-Schmidt correction with h = the column sums of the multi-dot
+// table (every block reduces it the same way).
+//  * not the last pass: w -= sum_i h_i V_i; block 0 accumulates h into the
+//    Arnoldi column (hacc) and, on pass 0, keeps ||w||^2 (breakdown test).
+//  * last pass: the new norm follows from the multi-dot's w.w slot,
+//    h_{k+1,k}^2 = w.w - sum_i h_i^2 (the basis is orthonormal), so the
+//    Givens rotation of column k, the residual estimate and the stopping test
+//    are known before the sweep; unless the cycle ends here the sweep writes
+//    V_{k+1} = (w - sum_i h_i V_i) / h_{k+1,k} directly.  Every block
+//    computes the same column; block 0 commits it.
+// State written by block 0 here (done, k, H, rotations, g[k+1]) is never read
+// by another block of this kernel; a block that sees done = 1 set here skips
+// a sweep whose result is not needed.
 template <int NV>
-__global__ __launch_bounds__(BLOCK) void k_update(const VecSeg* __restrict__ segs, int nseg, int pass) {
-    __shared__ double smem[4];
+__global__ __launch_bounds__(BLOCK) void k_update(const VecSeg* __restrict__ segs, int nseg, int pass,
+                                                  int last) {
     __shared__ double s_tmp[BLOCK];
     __shared__ double s_h[NV + 1];
-    __shared__ double s_out[1];
+    __shared__ double s_col[NV + 1];
     const VecSeg& sg = segs[find_vseg(segs, nseg, blockIdx.x)];
     GState* st = sg.st;
-    if (st->done || st->k != NV - 1) return;
+    if (st->done) return;
+    constexpr int k = NV - 1;
     const int lb = blockIdx.x - sg.blk0;
     reduce_table<NV + 1>(gl((const double*)sg.part), NPART, sg.nblk, s_tmp, s_h);
-    if (lb == 0 && threadIdx.x <= NV) {
-        const int i = threadIdx.x;
-        if (i < NV) st->hacc[i] = (pass == 0 ? 0.0 : st->hacc[i]) + s_h[i];
-        else if (pass == 0) st->wn0 = s_h[NV];
-    }
     double h[NV];
 #pragma unroll
     for (int i = 0; i < NV; ++i) h[i] = s_h[i];
+    const double ww = s_h[NV];
     const int64_t n = sg.n;
     const int64_t stride = (int64_t)sg.nblk * BLOCK;
     const auto* __restrict__ V = gl((const double*)sg.V);
     auto* __restrict__ w = gl(sg.w);
-    double acc[1] = {0.0};
+
+    double scale = 1.0;                 // 1 / h_{k+1,k} on the last pass
+    auto* __restrict__ dst = w;         // where the corrected vector goes
+    if (!last) {
+        if (lb == 0 && threadIdx.x <= NV) {
+            const int i = threadIdx.x;
+            if (i < NV) st->hacc[i] = (pass == 0 ? 0.0 : st->hacc[i]) + s_h[i];
+            else if (pass == 0) st->wn0 = ww;
+        }
+    } else {
+        // Arnoldi column k (earlier passes were committed by earlier kernels)
+        double hn2 = ww;
+#pragma unroll
+        for (int i = 0; i < NV; ++i) hn2 -= h[i] * h[i];
+        const double wn0 = pass == 0 ? ww : st->wn0;
+        const bool cancel = !(hn2 > 1e-12 * ww);       // Pythagoras lost to round-off
+        const double hn = cancel ? 0.0 : sqrt(hn2);
+        if (threadIdx.x == 0) {
+            double col[NV + 1];
+            for (int i = 0; i < NV; ++i) col[i] = (pass == 0 ? 0.0 : st->hacc[i]) + h[i];
+            col[NV] = hn;
+            for (int i = 0; i < k; ++i) {
+                const double a = col[i], b = col[i + 1];
+                col[i] = st->cs[i] * a + st->sn[i] * b;
+                col[i + 1] = -st->sn[i] * a + st->cs[i] * b;
+            }
+            for (int i = 0; i <= NV; ++i) s_col[i] = col[i];
+        }
+        __syncthreads();
+        const double a = s_col[k];
+        const double den = sqrt(a * a + hn * hn);
+        const double c = den > 0.0 ? a / den : 1.0;
+        const double sn = den > 0.0 ? hn / den : 0.0;
+        const double gk = st->g[k];
+        const double gk1 = -sn * gk;
+        const double res = fabs(gk1);
+        const bool nonfin = !isfinite(ww) || !isfinite(res) || !isfinite(den);
+        const bool breakdown = cancel || hn <= 1e-14 * sqrt(wn0);
+        const bool stop = nonfin || res <= st->eta_abs || breakdown || k + 1 >= sg.m;
+        if (lb == 0 && threadIdx.x == 0) {
+            double* H = st->H;
+            for (int i = 0; i < k; ++i) H[i * MMAX + k] = s_col[i];
+            H[k * MMAX + k] = den;
+            st->cs[k] = c;
+            st->sn[k] = sn;
+            st->g[k + 1] = gk1;       // read by the next step's kernel only
+            st->gr[k] = c * gk;
+            st->iters += 1;
+            st->iters_total += 1;
+            st->kbytes[3] += 8.0 * (double)(NV + 1) * (double)n;   // multi-dot: V_0..V_k and w
+            st->kbytes[4] += 8.0 * (double)(NV + 2) * (double)n;   // update: V_0..V_k, w, V_{k+1}
+            if (nonfin) {
+                st->nonfinite = 1;
+                st->done = 1;
+                st->kfinal = k;          // drop the broken column
+            } else if (stop) {
+                st->done = 1;
+                st->kfinal = k + 1;
+            } else {
+                st->k = k + 1;
+            }
+        }
+        if (stop) return;
+        scale = 1.0 / hn;
+        dst = gl(sg.V + (int64_t)(k + 1) * n);
+    }
     int64_t t = (int64_t)lb * BLOCK + threadIdx.x;
     for (; t + stride < n; t += 2 * stride) {
         double a0[NV], a1[NV];
@@ -228,93 +312,15 @@ __global__ __launch_bounds__(BLOCK) void k_update(const VecSeg* __restrict__ seg
             w0 -= h[i] * a0[i];
             w1 -= h[i] * a1[i];
         }
-        w[t] = w0;
-        w[t + stride] = w1;
-        acc[0] += w0 * w0 + w1 * w1;
+        dst[t] = scale * w0;
+        dst[t + stride] = scale * w1;
     }
     if (t < n) {
         double w0 = w[t];
 #pragma unroll
         for (int i = 0; i < NV; ++i) w0 -= h[i] * V[(int64_t)i * n + t];
-        w[t] = w0;
-        acc[0] += w0 * w0;
+        dst[t] = scale * w0;
     }
-    block_sums<1>(acc, smem, s_out);
-    if (threadIdx.x == 0) gl(sg.part2)[lb] = s_out[0];
-}
-
-// End of an Arnoldi step k = NV - 1: h_{k+1,k} = ||w|| from the update's
-// partials, the Givens rotations of column k, the residual estimate and the
-// stopping test -- computed identically in every block.  Unless the cycle
-// ends here, every block writes its chunk of V_{k+1} = w / h_{k+1,k}.
-// Block 0 commits the column, rotation and the next step to the state.
-template <int NV>
-__global__ __launch_bounds__(BLOCK) void k_normalize(const VecSeg* __restrict__ segs, int nseg) {
-    __shared__ double s_tmp[BLOCK];
-    __shared__ double s_out[1];
-    __shared__ double s_col[NV + 1];
-    const VecSeg& sg = segs[find_vseg(segs, nseg, blockIdx.x)];
-    GState* st = sg.st;
-    // only block 0 of this kernel writes done / k, and a cycle that ends here
-    // needs no V_{k+1}, so reading done here is safe in every block
-    if (st->done) return;
-    constexpr int k = NV - 1;
-    const int lb = blockIdx.x - sg.blk0;
-    reduce_table<1>(gl((const double*)sg.part2), 1, sg.nblk, s_tmp, s_out);
-    const double hn = sqrt(s_out[0]);
-    // Givens: rotate column k by the previous rotations, then make a new one
-    if (threadIdx.x == 0) {
-        double col[NV + 1];
-        for (int i = 0; i < NV; ++i) col[i] = st->hacc[i];
-        col[NV] = hn;
-        for (int i = 0; i < k; ++i) {
-            const double a = col[i], b = col[i + 1];
-            col[i] = st->cs[i] * a + st->sn[i] * b;
-            col[i + 1] = -st->sn[i] * a + st->cs[i] * b;
-        }
-        for (int i = 0; i <= NV; ++i) s_col[i] = col[i];
-    }
-    __syncthreads();
-    const double a = s_col[k], b = hn;
-    const double den = sqrt(a * a + b * b);
-    const double c = den > 0.0 ? a / den : 1.0;
-    const double sn = den > 0.0 ? b / den : 0.0;
-    const double gk = st->g[k];
-    const double gk1 = -sn * gk;
-    const double res = fabs(gk1);
-    const bool nonfin = !isfinite(hn) || !isfinite(res) || !isfinite(den);
-    const bool breakdown = hn <= 1e-14 * sqrt(st->wn0);
-    const bool stop = nonfin || res <= st->eta_abs || breakdown || k + 1 >= sg.m;
-    if (lb == 0 && threadIdx.x == 0) {
-        double* H = st->H;
-        for (int i = 0; i < k; ++i) H[i * MMAX + k] = s_col[i];
-        H[k * MMAX + k] = den;
-        st->cs[k] = c;
-        st->sn[k] = sn;
-        st->g[k + 1] = gk1;       // read by the next step's kernel only
-        st->gr[k] = c * gk;
-        st->iters += 1;
-        st->iters_total += 1;
-        st->kbytes[3] += 8.0 * (double)(NV + 1) * (double)sg.n;   // multi-dot: V_0..V_k and w
-        st->kbytes[4] += 8.0 * (double)(NV + 2) * (double)sg.n;   // update: V_0..V_k, w in and out
-        if (nonfin) {
-            st->nonfinite = 1;
-            st->done = 1;
-            st->kfinal = k;          // drop the broken column
-        } else if (stop) {
-            st->done = 1;
-            st->kfinal = k + 1;
-        } else {
-            st->k = k + 1;
-            st->kbytes[5] += 16.0 * (double)sg.n;                // normalise: w in, V_{k+1} out
-        }
-    }
-    if (stop) return;
-    const double s = 1.0 / hn;
-    auto* __restrict__ vk = gl(sg.V + (int64_t)(k + 1) * sg.n);
-    const auto* __restrict__ w = gl((const double*)sg.w);
-    const int64_t stride = (int64_t)sg.nblk * BLOCK;
-    for (int64_t i = (int64_t)lb * BLOCK + threadIdx.x; i < sg.n; i += stride) vk[i] = s * w[i];
 }
 
 // y = H(0:kf, 0:kf)^-1 g(0:kf) by back substitution; one block per segment.
@@ -406,16 +412,14 @@ namespace {
 template <int NV>
 void md_launch(const VecSeg* s, int nseg, int G, int, hipStream_t st) { LAUNCH_V(k_multidot<NV>, G, s, nseg); }
 template <int NV>
-void up_launch(const VecSeg* s, int nseg, int G, int pass, hipStream_t st) { LAUNCH_V(k_update<NV>, G, s, nseg, pass); }
-template <int NV>
-void nm_launch(const VecSeg* s, int nseg, int G, int, hipStream_t st) { LAUNCH_V(k_normalize<NV>, G, s, nseg); }
+void up_launch(const VecSeg* s, int nseg, int G, int pl, hipStream_t st) {
+    LAUNCH_V(k_update<NV>, G, s, nseg, pl >> 1, pl & 1);
+}
 using VLaunch = void (*)(const VecSeg*, int, int, int, hipStream_t);
 template <int... I>
 constexpr std::array<VLaunch, sizeof...(I)> md_table(std::integer_sequence<int, I...>) { return {&md_launch<I + 1>...}; }
 template <int... I>
 constexpr std::array<VLaunch, sizeof...(I)> up_table(std::integer_sequence<int, I...>) { return {&up_launch<I + 1>...}; }
-template <int... I>
-constexpr std::array<VLaunch, sizeof...(I)> nm_table(std::integer_sequence<int, I...>) { return {&nm_launch<I + 1>...}; }
 }  // namespace
 
 void vk_rnorm(const VecSeg* s, int nseg, int G, hipStream_t st) { LAUNCH_V(k_rnorm, G, s, nseg); }
@@ -425,13 +429,9 @@ void vk_multidot(const VecSeg* s, int nseg, int G, int k, hipStream_t st) {
     static const auto tbl = md_table(std::make_integer_sequence<int, MMAX>{});
     tbl[k](s, nseg, G, 0, st);
 }
-void vk_update(const VecSeg* s, int nseg, int G, int pass, int k, hipStream_t st) {
+void vk_update(const VecSeg* s, int nseg, int G, int pass, int last, int k, hipStream_t st) {
     static const auto tbl = up_table(std::make_integer_sequence<int, MMAX>{});
-    tbl[k](s, nseg, G, pass, st);
-}
-void vk_normalize(const VecSeg* s, int nseg, int G, int k, hipStream_t st) {
-    static const auto tbl = nm_table(std::make_integer_sequence<int, MMAX>{});
-    tbl[k](s, nseg, G, 0, st);
+    tbl[k](s, nseg, G, (pass << 1) | (last ? 1 : 0), st);
 }
 void vk_finish(const VecSeg* s, int nseg, hipStream_t st) {
     hipLaunchKernelGGL(k_finish, dim3(nseg), dim3(64), 0, st, s, nseg);

@@ -13,8 +13,8 @@ void vk_begin(const VecSeg* s, int nseg, hipStream_t st);             // ||R||, 
 void vk_scale_v0(const VecSeg* s, int nseg, int G, hipStream_t st);
 // k: the Arnoldi step index (0 .. m-1), the same for every slab of the launch
 void vk_multidot(const VecSeg* s, int nseg, int G, int k, hipStream_t st);
-void vk_update(const VecSeg* s, int nseg, int G, int pass, int k, hipStream_t st);
-void vk_normalize(const VecSeg* s, int nseg, int G, int k, hipStream_t st);
+// pass: Gram-Schmidt pass index; last: the final pass (writes V_{k+1} normalised)
+void vk_update(const VecSeg* s, int nseg, int G, int pass, int last, int k, hipStream_t st);
 void vk_finish(const VecSeg* s, int nseg, hipStream_t st);
 void vk_update_u(const VecSeg* s, int nseg, int G, hipStream_t st);
 void vk_init_guess(const VecSeg* s, int nseg, int G, hipStream_t st);

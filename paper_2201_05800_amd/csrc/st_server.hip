@@ -514,9 +514,8 @@ bool tick(st_srv* s) {
         }
         for (int p = 0; p < passes; ++p) {
             vk_multidot(dvc, nc, Gc, k, st);
-            vk_update(dvc, nc, Gc, p, k, st);
+            vk_update(dvc, nc, Gc, p, p == passes - 1, k, st);
         }
-        vk_normalize(dvc, nc, Gc, k, st);
     }
     vk_finish(dvc, nc, st);
     vk_update_u(dvc, nc, Gc, st);
