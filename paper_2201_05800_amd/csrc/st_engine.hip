@@ -254,7 +254,7 @@ static int ensure_fp32(st_ctx* h) {
     const Problem& pb = h->pb;
     if (h->U32) return ST_OK;
     CHK(h->alloc(&h->U32, pb.n));
-    if (viscous_eq(pb.eq.kind)) {
+    if (grad_pass(pb)) {
         CHK(h->alloc(&h->Q32, (size_t)pb.n * pb.mesh.dim));
         CHK(h->alloc(&h->dQ32, (size_t)pb.n * pb.mesh.dim));
     }
@@ -318,7 +318,7 @@ int st_create(const st_mesh_t* mesh, int N, int Nt, const st_equation_t* eq, st_
         delete h;
         return rc;
     }
-    if (viscous_eq(pb.eq.kind)) {
+    if (grad_pass(pb)) {
         if ((rc = h->alloc(&h->Q, (size_t)pb.n * pb.mesh.dim)) != ST_OK ||
             (rc = h->alloc(&h->dQ, (size_t)pb.n * pb.mesh.dim)) != ST_OK) {
             delete h;
@@ -370,7 +370,7 @@ int st_residual(st_handle_t h, const double* U, const double* u_prev, double t0,
     hipStream_t st = (hipStream_t)stream;
     const int G = op_blocks(pb);
     OpSeg s = base_opseg(pb, dt);
-    if (viscous_eq(pb.eq.kind)) {
+    if (grad_pass(pb)) {
         OpSeg g = s;
         g.U = dptr(U);
         g.out = dptr(h->Q);
@@ -402,7 +402,7 @@ void setup_jvp(st_ctx* h, const double* U, DynPtr V, double* out, const int* ski
     OpSeg s = base_opseg(pb, dt);
     s.skip = skip;
     s.out = dptr(out);
-    if (viscous_eq(kind)) {
+    if (grad_pass(pb)) {
         OpSeg g = s;
         g.U = V;
         g.out = dptr(fp32 ? (void*)h->dQ32 : (void*)h->dQ);
@@ -412,11 +412,11 @@ void setup_jvp(st_ctx* h, const double* U, DynPtr V, double* out, const int* ski
         // J v = R(v) with u_prev = 0
         s.U = V;
         s.uprev = nullptr;
-        if (viscous_eq(kind)) s.Q = dptr(fp32 ? (void*)h->dQ32 : (void*)h->dQ);
+        if (grad_pass(pb)) s.Q = dptr(fp32 ? (void*)h->dQ32 : (void*)h->dQ);
     } else {
         s.U = dptr(fp32 ? (const void*)h->U32 : (const void*)U);
         s.V = V;
-        if (viscous_eq(kind)) {
+        if (grad_pass(pb)) {
             s.Q = dptr(fp32 ? (void*)h->Q32 : (void*)h->Q);
             s.dQ = dptr(fp32 ? (void*)h->dQ32 : (void*)h->dQ);
         }
@@ -428,7 +428,7 @@ void launch_jvp(st_ctx* h, bool fp32, int slot, hipStream_t st) {
     const Problem& pb = h->pb;
     const int G = op_blocks(pb);
     const int kind = pb.eq.kind;
-    if (viscous_eq(kind))
+    if (grad_pass(pb))
         h->timer.run(ST_K_GRAD, st, [&] { (fp32 ? pb.ops->grad64to32 : pb.ops->grad64)(h->d_op + slot, 1, G, st); });
     h->timer.run(ST_K_JVP, st, [&] {
         if (linear_eq(kind)) (fp32 ? pb.ops->lin32 : pb.ops->res64)(h->d_op + slot + 1, 1, G, st);
@@ -454,7 +454,7 @@ void enqueue_jvp_prepare(st_ctx* h, const double* U, bool fp32, double dt, int s
         put_vecseg(h->d_vs, v, st);
         vk_cast32(h->d_vs, 1, v.nblk, st);
     }
-    if (viscous_eq(kind)) {
+    if (grad_pass(pb)) {
         OpSeg g = base_opseg(pb, dt);
         g.U = dptr(fp32 ? (const void*)h->U32 : (const void*)U);
         g.out = dptr(fp32 ? (void*)h->Q32 : (void*)h->Q);
@@ -540,7 +540,7 @@ int st_solve_slab(st_handle_t h, const double* u_prev, double t0, double dt, dou
 
     // residual descriptors (slots 0, 1), fixed for the whole solve
     OpSeg rs = base_opseg(pb, dt);
-    if (viscous_eq(kind)) {
+    if (grad_pass(pb)) {
         OpSeg g = rs;
         g.U = dptr(h->U);
         g.out = dptr(h->Q);
@@ -557,7 +557,7 @@ int st_solve_slab(st_handle_t h, const double* u_prev, double t0, double dt, dou
     const int* kp = &h->d_st->k;
     const int* skip = &h->d_st->done;
     setup_jvp(h, h->U, dptr_k(h->V, pb.n, kp), h->w, skip, fp32, dt, 4, st);
-    if (fp32 && viscous_eq(kind) && !linear_eq(kind)) {
+    if (fp32 && grad_pass(pb) && !linear_eq(kind)) {
         OpSeg g = base_opseg(pb, dt);
         g.U = dptr(h->U32);
         g.out = dptr(h->Q32);
@@ -570,7 +570,7 @@ int st_solve_slab(st_handle_t h, const double* u_prev, double t0, double dt, dou
     int stall = 0;
     auto& T = h->timer;
     for (;;) {
-        if (viscous_eq(kind)) T.run(ST_K_GRAD, st, [&] { pb.ops->grad64(h->d_op + 0, 1, Gop, st); });
+        if (grad_pass(pb)) T.run(ST_K_GRAD, st, [&] { pb.ops->grad64(h->d_op + 0, 1, Gop, st); });
         T.run(ST_K_RESIDUAL, st, [&] { pb.ops->res64(h->d_op + 1, 1, Gop, st); });
         T.run(ST_K_NEWTON, st, [&] {
             vk_rnorm(h->d_vs, 1, Gv, st);
@@ -591,7 +591,7 @@ int st_solve_slab(st_handle_t h, const double* u_prev, double t0, double dt, dou
         // FP64 NS JVP reuses grad U from the residual evaluation above
         if (fp32 && !linear_eq(kind)) {
             T.run(ST_K_NEWTON, st, [&] { vk_cast32(h->d_vs, 1, Gv, st); });
-            if (viscous_eq(kind)) T.run(ST_K_GRAD, st, [&] { pb.ops->grad32(h->d_op + 2, 1, Gop, st); });
+            if (grad_pass(pb)) T.run(ST_K_GRAD, st, [&] { pb.ops->grad32(h->d_op + 2, 1, Gop, st); });
         }
         T.run(ST_K_NORMALIZE, st, [&] { vk_scale_v0(h->d_vs, 1, Gv, st); });
         for (int k = 0; k < m; ++k) {
@@ -617,7 +617,7 @@ int st_solve_slab(st_handle_t h, const double* u_prev, double t0, double dt, dou
         // kernels accumulated on the device
         const double n8 = 8.0 * (double)pb.n;
         const int its = h->h_st->iters_total;
-        const bool visc = viscous_eq(kind), lin = linear_eq(kind);
+        const bool visc = grad_pass(pb), lin = linear_eq(kind);
         for (int c = 0; c < ST_K_COUNT; ++c) stats->kernel_bytes[c] = 0.0;
         stats->kernel_bytes[ST_K_RESIDUAL] = (outer + 1) * n8 * (2.0 + 1.0 / pb.Nt);
         const double jvp_b = lin ? 2.0 * n8 : (fp32 ? 2.5 : 3.0) * n8;   // [U,] v in, Jv out

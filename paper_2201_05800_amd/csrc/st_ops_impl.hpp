@@ -319,6 +319,173 @@ __global__ __launch_bounds__(BLOCK) void k_grad(const OpSeg* __restrict__ segs, 
 }
 
 // ---------------------------------------------------------------------------
+// Advection-diffusion with the BR1 viscous flux in a single kernel.
+// Fv = nu grad u, so the central viscous flux through a face needs only the
+// neighbour's NORMAL lifted derivative at the face node, which depends on the
+// neighbour's line of nodes normal to the face and on this element's face
+// value.  Each face thread reads that line (L2) together with its own state,
+// so the lifted gradient never goes through HBM.  Same arithmetic as k_grad
+// followed by k_op; JVP of this linear operator = the operator applied to v
+// with u_prev = 0.
+// ---------------------------------------------------------------------------
+template <int D, int N1, int NT, class CT, class UT>
+__global__ __launch_bounds__(BLOCK) void k_advdiff(const OpSeg* __restrict__ segs, int nseg, int G) {
+    constexpr int NS = ipow(N1, D);
+    constexpr int EPB = BLOCK / NS > 0 ? BLOCK / NS : 1;
+    __shared__ CT tile[EPB * NT * NS];
+    __shared__ CT fl[EPB * NT * NS];
+
+    const int L = xcd_remap(blockIdx.x, G);
+    const OpSeg& sg = segs[find_seg(segs, nseg, L)];
+    if (sg.skip && *sg.skip) return;
+    const EqParams& P = sg.P;
+    const int tid = threadIdx.x;
+    const int el = tid / NS;
+    const int s = tid - el * NS;
+    const int64_t e = (int64_t)(L - sg.blk0) * EPB + el;
+    const bool active = (el < EPB) && (e < sg.E);
+    const gptr<UT> __restrict__ Up = resolve<UT>(sg.U);
+    const gptr<double> __restrict__ out = resolve<double>(sg.out);
+    const gptr<const double> __restrict__ upv = (gptr<const double>)sg.uprev;
+    const int ec[3] = {(int)(e % sg.K[0]), (int)((e / sg.K[0]) % sg.K[1]), (int)(e / ((int64_t)sg.K[0] * sg.K[1]))};
+    const int64_t es[3] = {1, sg.K[0], (int64_t)sg.K[0] * sg.K[1]};
+    const CT nu = CT(P.nu);
+    const CT w0 = CT(sg.wx[0]);
+
+    // own values and, on every face axis, the neighbour's line normal to it
+    CT u[NT];
+    CT line[D][N1][NT];
+    int side[D];
+#pragma unroll
+    for (int a = 0; a < D; ++a) side[a] = 0;
+    if (active) {
+#pragma unroll
+        for (int j = 0; j < NT; ++j) u[j] = CT(Up[(e * NT + j) * NS + s]);
+        static_for<0, D>([&](auto A) {
+            constexpr int a = decltype(A)::value;
+            constexpr int stride = ipow(N1, a);
+            const int ia = node_coord<D>(s, N1, a);
+            if (ia == 0 || ia == N1 - 1) {
+                side[a] = (ia == N1 - 1) ? 1 : -1;
+                const int ca = ec[a] + side[a];
+                const int cw = ca < 0 ? ca + sg.K[a] : (ca >= sg.K[a] ? ca - sg.K[a] : ca);
+                const int64_t en = e + (int64_t)(cw - ec[a]) * es[a];
+                const int s0 = s - ia * stride;
+#pragma unroll
+                for (int k = 0; k < N1; ++k)
+#pragma unroll
+                    for (int j = 0; j < NT; ++j) line[a][k][j] = CT(Up[(en * NT + j) * NS + s0 + k * stride]);
+            }
+        });
+#pragma unroll
+        for (int j = 0; j < NT; ++j) tile[(el * NT + j) * NS + s] = u[j];
+    } else {
+#pragma unroll
+        for (int j = 0; j < NT; ++j) u[j] = CT(0);
+    }
+    __syncthreads();
+
+    // own lifted gradient q[b][j] (central u-hat on faces)
+    CT q[D][NT];
+    if (active) {
+        static_for<0, D>([&](auto B) {
+            constexpr int b = decltype(B)::value;
+            constexpr int stride = ipow(N1, b);
+            const int ib = node_coord<D>(s, N1, b);
+            const int s0 = s - ib * stride;
+            CT Drow[N1];
+#pragma unroll
+            for (int k = 0; k < N1; ++k) Drow[k] = CT(sg.Dx[ib * N1 + k]);
+#pragma unroll
+            for (int j = 0; j < NT; ++j) {
+                const CT* ln = tile + (el * NT + j) * NS + s0;
+                CT g = Drow[0] * ln[0];
+#pragma unroll
+                for (int k = 1; k < N1; ++k) g += Drow[k] * ln[k * stride];
+                if (side[b] != 0) {
+                    const CT un = side[b] > 0 ? line[b][0][j] : line[b][N1 - 1][j];
+                    const CT uh = CT(0.5) * (u[j] + un);
+                    g += (side[b] > 0 ? CT(1) : CT(-1)) / w0 * (uh - u[j]);
+                }
+                q[b][j] = CT(sg.rh[b]) * g;
+            }
+        });
+    }
+
+    CT acc[NT];
+#pragma unroll
+    for (int j = 0; j < NT; ++j) acc[j] = CT(0);
+    static_for<0, D>([&](auto A) {
+        constexpr int a = decltype(A)::value;
+        constexpr int stride = ipow(N1, a);
+        const int ia = node_coord<D>(s, N1, a);
+        const CT av = CT(P.a[a]);
+        if (active) {
+#pragma unroll
+            for (int j = 0; j < NT; ++j) fl[(el * NT + j) * NS + s] = u[j] * av - q[a][j] * nu;
+        }
+        __syncthreads();
+        if (active) {
+            const CT J = CT(sg.rh[a]);
+            CT Drow[N1];
+#pragma unroll
+            for (int k = 0; k < N1; ++k) Drow[k] = CT(sg.Dx[ia * N1 + k]);
+            const int s0 = s - ia * stride;
+#pragma unroll
+            for (int j = 0; j < NT; ++j) {
+                const CT* ln = fl + (el * NT + j) * NS + s0;
+                CT sum = Drow[0] * ln[0];
+#pragma unroll
+                for (int k = 1; k < N1; ++k) sum += Drow[k] * ln[k * stride];
+                acc[j] -= J * sum;
+            }
+            if (side[a] != 0) {
+                // neighbour's normal derivative at its face node: its D row at
+                // that node plus its own lift with the same u-hat
+                const int inb = side[a] > 0 ? 0 : N1 - 1;
+                CT Dn[N1];
+#pragma unroll
+                for (int k = 0; k < N1; ++k) Dn[k] = CT(sg.Dx[inb * N1 + k]);
+                const CT lam = CT(fabs(P.a[a]));
+                const CT wl = J / w0;
+#pragma unroll
+                for (int j = 0; j < NT; ++j) {
+                    const CT un = side[a] > 0 ? line[a][0][j] : line[a][N1 - 1][j];
+                    CT gn = Dn[0] * line[a][0][j];
+#pragma unroll
+                    for (int k = 1; k < N1; ++k) gn += Dn[k] * line[a][k][j];
+                    const CT uh = CT(0.5) * (un + u[j]);
+                    gn += (side[a] > 0 ? CT(-1) : CT(1)) / w0 * (uh - un);
+                    const CT qn = J * gn;
+                    const CT uL = side[a] > 0 ? u[j] : un, uR = side[a] > 0 ? un : u[j];
+                    const CT qL = side[a] > 0 ? q[a][j] : qn, qR = side[a] > 0 ? qn : q[a][j];
+                    const CT fL = uL * av, fR = uR * av;
+                    CT H = CT(0.5) * (fL + fR) + (CT(0.5) * lam) * (uL - uR);
+                    H = H - CT(0.5) * (qL * nu + qR * nu);
+                    const CT fo = fl[(el * NT + j) * NS + s];
+                    acc[j] -= (side[a] > 0 ? wl : -wl) * (H - fo);
+                }
+            }
+        }
+        __syncthreads();
+    });
+
+    if (active) {
+        const CT hdt = CT(0.5 * sg.dt);
+        const CT up = upv ? CT(upv[e * NS + s]) : CT(0);
+#pragma unroll
+        for (int j = 0; j < NT; ++j) {
+            CT dtu = CT(sg.Dt[j * NT]) * u[0];
+#pragma unroll
+            for (int k = 1; k < NT; ++k) dtu += CT(sg.Dt[j * NT + k]) * u[k];
+            CT r = CT(sg.wt[j]) * (hdt * acc[j] - dtu);
+            if (j == 0) r -= u[0] - up;
+            out[(e * NT + j) * NS + s] = double(r);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // host launchers
 // ---------------------------------------------------------------------------
 template <int D, int N1>
@@ -330,6 +497,10 @@ template <int EQ, int D, int N1, int NT, class CT, class UT, bool JVP>
 void launch_op(const OpSeg* segs, int nseg, int G, hipStream_t st) {
     hipLaunchKernelGGL((k_op<EQ, D, N1, NT, CT, UT, JVP>), dim3(G), dim3(BLOCK), 0, st, segs, nseg, G);
 }
+template <int D, int N1, int NT, class CT, class UT>
+void launch_advdiff(const OpSeg* segs, int nseg, int G, hipStream_t st) {
+    hipLaunchKernelGGL((k_advdiff<D, N1, NT, CT, UT>), dim3(G), dim3(BLOCK), 0, st, segs, nseg, G);
+}
 template <int D, int N1, int NT, int R, class CT, class UT>
 void launch_grad(const OpSeg* segs, int nseg, int G, hipStream_t st) {
     hipLaunchKernelGGL((k_grad<D, N1, NT, R, CT, UT>), dim3(G), dim3(BLOCK), 0, st, segs, nseg, G);
@@ -340,6 +511,12 @@ OpTable make_table() {
     constexpr int R = nvars_of(EQ, D);
     OpTable t{};
     t.eq = EQ; t.dim = D; t.n1 = N1; t.nt = NT; t.epb = op_epb<D, N1>();
+    if constexpr (EQ == EQ_ADVDIFF) {
+        // single-kernel BR1: no gradient pass, no gradient buffers
+        t.res64 = launch_advdiff<D, N1, NT, double, double>;
+        t.lin32 = launch_advdiff<D, N1, NT, float, double>;
+        return t;
+    }
     t.res64 = launch_op<EQ, D, N1, NT, double, double, false>;
     if constexpr (linear_eq(EQ)) {
         t.lin32 = launch_op<EQ, D, N1, NT, float, double, false>;

@@ -88,7 +88,7 @@ Layout layout_of(const Problem& pb, const st_solver_opts_t& o) {
     int64_t off = 0;
     auto take = [&](int64_t bytes) { int64_t at = off; off += align_up(std::max<int64_t>(bytes, 8)); return at; };
     const int64_t n = pb.n, d = pb.mesh.dim;
-    const bool visc = viscous_eq(pb.eq.kind), nonlin = !linear_eq(pb.eq.kind), fp32 = o.inner_fp32 != 0;
+    const bool visc = grad_pass(pb), nonlin = !linear_eq(pb.eq.kind), fp32 = o.inner_fp32 != 0;
     L.U = take(8 * n);
     L.R = take(8 * n);
     L.w = take(8 * n);
@@ -263,7 +263,7 @@ std::vector<OpGroup> build_res_groups(st_srv* s, const std::vector<Req*>& rs) {
             g = &gs.back();
         }
         OpSeg base = base_opseg(pb, r->dt);
-        if (viscous_eq(pb.eq.kind)) {
+        if (grad_pass(pb)) {
             OpSeg gr = base;
             gr.U = dptr(r->dp(r->lay.U));
             gr.out = dptr(r->dp(r->lay.Q));
@@ -303,7 +303,7 @@ std::vector<OpGroup> build_jvp_groups(st_srv* s, const std::vector<Req*>& rs) {
         b.out = dptr(r->dp(r->lay.w));
         const int kind = pb.eq.kind;
         void* dQ = f32 ? (void*)r->fp(r->lay.dQ32) : (void*)r->dp(r->lay.dQ);
-        if (viscous_eq(kind)) {
+        if (grad_pass(pb)) {
             OpSeg gr = b;
             gr.U = Vk;
             gr.out = dptr(dQ);
@@ -312,11 +312,11 @@ std::vector<OpGroup> build_jvp_groups(st_srv* s, const std::vector<Req*>& rs) {
         if (linear_eq(kind)) {
             b.U = Vk;
             b.uprev = nullptr;
-            if (viscous_eq(kind)) b.Q = dptr(dQ);
+            if (grad_pass(pb)) b.Q = dptr(dQ);
         } else {
             b.U = dptr(f32 ? (const void*)r->fp(r->lay.U32) : (const void*)r->dp(r->lay.U));
             b.V = Vk;
-            if (viscous_eq(kind)) {
+            if (grad_pass(pb)) {
                 b.Q = dptr(f32 ? (void*)r->fp(r->lay.Q32) : (void*)r->dp(r->lay.Q));
                 b.dQ = dptr(dQ);
             }
@@ -479,7 +479,7 @@ bool tick(st_srv* s) {
     // FP32 gradient of U32 for FP32 NS requests
     std::vector<OpGroup> g32;
     for (Req* r : c32) {
-        if (!viscous_eq(r->pb.eq.kind)) continue;
+        if (!grad_pass(r->pb)) continue;
         OpGroup* g = nullptr;
         for (auto& x : g32)
             if (x.ops == r->pb.ops) g = &x;
