@@ -8,10 +8,32 @@
 // same code gives residuals (double / float) and exact Jacobian-vector
 // products (forward-mode dual numbers Dual<double> / Dual<float>).
 #pragma once
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
 namespace stdg {
+
+// Optional per-launch timing: when a start/stop event pair is armed, the next
+// kernel launched through launch_k records them at its own start and end
+// (hipExtLaunchKernelGGL), the same interval a kernel trace reports.
+struct LaunchTiming {
+    hipEvent_t start = nullptr;
+    hipEvent_t stop = nullptr;
+};
+LaunchTiming& launch_timing();   // thread-local
+
+template <class K, class... A>
+void launch_k(K kernel, dim3 grid, dim3 block, hipStream_t st, A... args) {
+    LaunchTiming& lt = launch_timing();
+    if (lt.start) {
+        hipEvent_t e0 = lt.start, e1 = lt.stop;
+        lt.start = lt.stop = nullptr;
+        hipExtLaunchKernelGGL(kernel, grid, block, 0, st, e0, e1, 0, args...);
+    } else {
+        hipLaunchKernelGGL(kernel, grid, block, 0, st, args...);
+    }
+}
 
 constexpr int MMAX = 32;           // largest GMRES restart length
 constexpr int BLOCK = 256;         // threads per block of every kernel

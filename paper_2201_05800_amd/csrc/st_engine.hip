@@ -198,17 +198,25 @@ struct st_ctx {
         std::vector<std::pair<int, size_t>> marks;   // (class, first event)
         size_t used = 0;
         void reset(int m) { mask = m; marks.clear(); used = 0; }
+        // time `launch` if its class is selected: a single kernel is timed by
+        // its own start/end (ext launch), several kernels by stream events
         template <class F>
-        void run(int cls, hipStream_t st, F&& launch) {
+        void run(int cls, hipStream_t st, F&& launch, bool single = true) {
             if (!((mask >> cls) & 1)) { launch(); return; }
             while (pool.size() < used + 2) {
                 hipEvent_t e;
                 if (hipEventCreate(&e) != hipSuccess) { launch(); return; }
                 pool.push_back(e);
             }
-            (void)hipEventRecord(pool[used], st);
-            launch();
-            (void)hipEventRecord(pool[used + 1], st);
+            if (single) {
+                launch_timing() = LaunchTiming{pool[used], pool[used + 1]};
+                launch();
+                launch_timing() = LaunchTiming{};
+            } else {
+                (void)hipEventRecord(pool[used], st);
+                launch();
+                (void)hipEventRecord(pool[used + 1], st);
+            }
             marks.push_back({cls, used});
             used += 2;
         }
@@ -575,7 +583,7 @@ int st_solve_slab(st_handle_t h, const double* u_prev, double t0, double dt, dou
         T.run(ST_K_NEWTON, st, [&] {
             vk_rnorm(h->d_vs, 1, Gv, st);
             vk_begin(h->d_vs, 1, st);
-        });
+        }, false);
         HIPCHK(hipMemcpyAsync(h->h_st, h->d_st, offsetof(GState, hacc), hipMemcpyDeviceToHost, st));
         HIPCHK(hipStreamSynchronize(st));
         const GState& hs = *h->h_st;
@@ -604,7 +612,7 @@ int st_solve_slab(st_handle_t h, const double* u_prev, double t0, double dt, dou
         T.run(ST_K_NEWTON, st, [&] {
             vk_finish(h->d_vs, 1, st);
             vk_update_u(h->d_vs, 1, Gv, st);
-        });
+        }, false);
         HIPCHK(hipGetLastError());
     }
     if (u_next) vk_extract_last(h->d_vs, 1, Gv, st);

@@ -323,16 +323,33 @@ __global__ __launch_bounds__(BLOCK) void k_update(const VecSeg* __restrict__ seg
     }
 }
 
-// y = H(0:kf, 0:kf)^-1 g(0:kf) by back substitution; one block per segment.
-__global__ void k_finish(const VecSeg* __restrict__ segs, int nseg) {
-    if (blockIdx.x >= nseg || threadIdx.x != 0) return;
+// y = H(0:kf, 0:kf)^-1 gr(0:kf) by back substitution; one block per segment
+// (the triangle is staged in LDS by the whole block first).
+__global__ __launch_bounds__(BLOCK) void k_finish(const VecSeg* __restrict__ segs, int nseg) {
+    __shared__ double sH[MMAX * MMAX];
+    __shared__ double sg[MMAX];
+    if (blockIdx.x >= nseg) return;
     GState* st = segs[blockIdx.x].st;
     const int kf = st->kfinal;
-    for (int i = kf - 1; i >= 0; --i) {
-        double s = st->gr[i];
-        for (int j = i + 1; j < kf; ++j) s -= st->H[i * MMAX + j] * st->y[j];
-        st->y[i] = s / st->H[i * MMAX + i];
+    // all loads in flight at once (the state was written from another XCD)
+    double v[MMAX * MMAX / BLOCK];
+#pragma unroll
+    for (int q = 0; q < MMAX * MMAX / BLOCK; ++q) {
+        const int i = threadIdx.x + q * BLOCK;
+        v[q] = i < kf * MMAX ? st->H[i] : 0.0;
     }
+#pragma unroll
+    for (int q = 0; q < MMAX * MMAX / BLOCK; ++q) sH[threadIdx.x + q * BLOCK] = v[q];
+    if (threadIdx.x < kf) sg[threadIdx.x] = st->gr[threadIdx.x];
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    double y[MMAX];
+    for (int i = kf - 1; i >= 0; --i) {
+        double s = sg[i];
+        for (int j = i + 1; j < kf; ++j) s -= sH[i * MMAX + j] * y[j];
+        y[i] = s / sH[i * MMAX + i];
+    }
+    for (int i = 0; i < kf; ++i) st->y[i] = y[i];
 }
 
 // U += sum_{i < kfinal} y_i V_i
@@ -406,7 +423,12 @@ __global__ void k_put_vecseg(VecSeg* dst, VecSeg v) { if (threadIdx.x == 0 && bl
 // ---------------------------------------------------------------------------
 // host launchers
 // ---------------------------------------------------------------------------
-#define LAUNCH_V(K, G, ...) hipLaunchKernelGGL(K, dim3(G), dim3(BLOCK), 0, st, __VA_ARGS__)
+#define LAUNCH_V(K, G, ...) launch_k(K, dim3(G), dim3(BLOCK), st, __VA_ARGS__)
+
+LaunchTiming& launch_timing() {
+    static thread_local LaunchTiming lt;
+    return lt;
+}
 
 namespace {
 template <int NV>
@@ -434,17 +456,17 @@ void vk_update(const VecSeg* s, int nseg, int G, int pass, int last, int k, hipS
     tbl[k](s, nseg, G, (pass << 1) | (last ? 1 : 0), st);
 }
 void vk_finish(const VecSeg* s, int nseg, hipStream_t st) {
-    hipLaunchKernelGGL(k_finish, dim3(nseg), dim3(64), 0, st, s, nseg);
+    launch_k(k_finish, dim3(nseg), dim3(BLOCK), st, s, nseg);
 }
 void vk_update_u(const VecSeg* s, int nseg, int G, hipStream_t st) { LAUNCH_V(k_update_u, G, s, nseg); }
 void vk_init_guess(const VecSeg* s, int nseg, int G, hipStream_t st) { LAUNCH_V(k_init_guess, G, s, nseg); }
 void vk_extract_last(const VecSeg* s, int nseg, int G, hipStream_t st) { LAUNCH_V(k_extract_last, G, s, nseg); }
 void vk_cast32(const VecSeg* s, int nseg, int G, hipStream_t st) { LAUNCH_V(k_cast32, G, s, nseg); }
 void put_opseg(OpSeg* dst, const OpSeg& v, hipStream_t st) {
-    hipLaunchKernelGGL(k_put_opseg, dim3(1), dim3(64), 0, st, dst, v);
+    launch_k(k_put_opseg, dim3(1), dim3(64), st, dst, v);
 }
 void put_vecseg(VecSeg* dst, const VecSeg& v, hipStream_t st) {
-    hipLaunchKernelGGL(k_put_vecseg, dim3(1), dim3(64), 0, st, dst, v);
+    launch_k(k_put_vecseg, dim3(1), dim3(64), st, dst, v);
 }
 
 }  // namespace stdg

@@ -495,15 +495,15 @@ constexpr int op_epb() {
 
 template <int EQ, int D, int N1, int NT, class CT, class UT, bool JVP>
 void launch_op(const OpSeg* segs, int nseg, int G, hipStream_t st) {
-    hipLaunchKernelGGL((k_op<EQ, D, N1, NT, CT, UT, JVP>), dim3(G), dim3(BLOCK), 0, st, segs, nseg, G);
+    launch_k(k_op<EQ, D, N1, NT, CT, UT, JVP>, dim3(G), dim3(BLOCK), st, segs, nseg, G);
 }
 template <int D, int N1, int NT, class CT, class UT>
 void launch_advdiff(const OpSeg* segs, int nseg, int G, hipStream_t st) {
-    hipLaunchKernelGGL((k_advdiff<D, N1, NT, CT, UT>), dim3(G), dim3(BLOCK), 0, st, segs, nseg, G);
+    launch_k(k_advdiff<D, N1, NT, CT, UT>, dim3(G), dim3(BLOCK), st, segs, nseg, G);
 }
 template <int D, int N1, int NT, int R, class CT, class UT>
 void launch_grad(const OpSeg* segs, int nseg, int G, hipStream_t st) {
-    hipLaunchKernelGGL((k_grad<D, N1, NT, R, CT, UT>), dim3(G), dim3(BLOCK), 0, st, segs, nseg, G);
+    launch_k(k_grad<D, N1, NT, R, CT, UT>, dim3(G), dim3(BLOCK), st, segs, nseg, G);
 }
 
 template <int EQ, int D, int N1, int NT>
