@@ -64,6 +64,8 @@ def parse():
     ap.add_argument("--restart", type=int, default=30)
     ap.add_argument("--cgs-passes", type=int, default=1)
     ap.add_argument("--no-timing", action="store_true", help="run without HIP-event kernel timing")
+    ap.add_argument("--serve-requests", type=int, default=96,
+                    help="requests in the served-stream sample (0: skip the serving leg)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (3 times) for counter calibration")
     return ap.parse_args()
@@ -123,6 +125,98 @@ def cpu_baseline(cfg, u0, U, dt, seconds):
                 kind="oracle",
                 sample=f"{evals} oracle residual evaluations of one {n}-unknown slab of the same workload "
                        f"({el:.1f} s)")
+
+
+def lgl_coords(st, dim, K, lo, hi, N):
+    """Physical node coordinates (E, dim, ns) of a periodic box mesh from the
+    library's LGL nodes (element-major, x fastest)."""
+    import numpy as np
+    x, _, _ = st.st_lgl(N + 1)
+    n1 = N + 1
+    ns = n1 ** dim
+    E = int(np.prod(K))
+    X = np.zeros((E, dim, ns))
+    e = np.arange(E)
+    s = np.arange(ns)
+    for a in range(dim):
+        ea = (e // int(np.prod(K[:a]))) % K[a]
+        ia = (s // n1 ** a) % n1
+        h = (hi[a] - lo[a]) / K[a]
+        X[:, a, :] = lo[a] + h * (ea[:, None] + 0.5 * (1.0 + x[ia][None, :]))
+    return X
+
+
+def serving_bench(n_requests, seed=4, budget_gib=64, max_active=64, load=0.7):
+    """Served mix of 1D Burgers and 2D advection-diffusion slab solves (K in
+    8..256 per axis, N in 2..5, Nt in 2..4, FP64 / FP32-inner 50/50, CFL 5):
+    saturated throughput with every request submitted at once, then latency
+    under Poisson arrivals at `load` times that throughput."""
+    import numpy as np
+    from paper_2201_05800_amd import inputs, st
+
+    def build(stream):
+        reqs = []
+        for q in stream:
+            if q["kind"] == "burgers":
+                d, K, lo, hi = 1, [q["K"]], [0.0], [1.0]
+                X = lgl_coords(st, d, K, lo, hi, q["N"])
+                up = inputs.burgers_smooth(X, inputs.burgers_params(q["seed"])).ravel()
+                eq = st.equation(st.ST_BURGERS)
+                lam = float(np.abs(up).max())
+            else:
+                d, K, lo, hi = 2, [q["K"], q["K"]], [0.0, 0.0], [1.0, 1.0]
+                X = lgl_coords(st, d, K, lo, hi, q["N"])
+                up = inputs.fourier_modes(X, inputs.fourier_params(q["seed"])).ravel()
+                eq = st.equation(st.ST_ADVDIFF_BR1, a=(1.0, 0.5), nu=1e-3)
+                lam = math.sqrt(1.25)
+            dt = inputs.cfl_dt(5.0, 1.0 / q["K"], q["N"], lam)
+            r = st.request(st.mesh(d, K, lo, hi), q["N"], q["Nt"], eq, up, 0.0, dt, 1e-10,
+                           st.st_default_opts(inner_fp32=int(q["inner_fp32"])))
+            reqs.append((q, r, up.size))
+        return reqs
+
+    def run(reqs, arrivals):
+        srv = st.st_server_create(hbm_budget_bytes=budget_gib << 30, max_active=max_active)
+        try:
+            tks, done = [], {}
+            t0 = time.perf_counter()
+            i = 0
+            while len(done) < len(reqs):
+                now = time.perf_counter() - t0
+                while i < len(reqs) and arrivals[i] <= now:
+                    tks.append((st.st_submit(srv, reqs[i][1]), reqs[i][2], i))
+                    i += 1
+                for t, nsp, j in tks:
+                    if j in done:
+                        continue
+                    buf = np.empty(nsp)
+                    rc, info = st.st_poll(srv, t, buf)
+                    if rc != st.ST_PENDING:
+                        done[j] = (rc, info)
+                time.sleep(0.0002)
+            wall = time.perf_counter() - t0
+            stats = st.st_server_stats(srv)
+        finally:
+            st.st_server_destroy(srv)
+        lat = np.array([(done[j][1]["done_us"] - done[j][1]["submit_us"]) * 1e-3 for j in range(len(reqs))])
+        ok = sum(1 for j in done if done[j][0] == st.ST_OK)
+        return wall, lat, ok, stats
+
+    stream = inputs.serving_stream(seed, n_requests, rate=0.0)
+    reqs = build(stream)
+    unknowns = sum(st.st_request_footprint(r) for _, r, _ in reqs)
+    wall_sat, lat_sat, ok_sat, _ = run(reqs, [0.0] * len(reqs))
+    thr = len(reqs) / wall_sat
+    rate = load * thr
+    g = np.random.default_rng(seed + 1)
+    arr = np.cumsum(g.exponential(1.0 / rate, size=len(reqs)))
+    wall_p, lat_p, ok_p, stats_p = run(reqs, arr)
+    return dict(requests=len(reqs), saturated_solves_per_s=thr, saturated_wall_s=wall_sat,
+                poisson_rate_per_s=rate, load=load, latency_ms_p50=float(np.percentile(lat_p, 50)),
+                latency_ms_p99=float(np.percentile(lat_p, 99)), latency_ms_p50_saturated=float(np.percentile(lat_sat, 50)),
+                latency_ms_p99_saturated=float(np.percentile(lat_sat, 99)), ok=min(ok_sat, ok_p),
+                ticks=stats_p["ticks"], footprint_bytes_total=unknowns,
+                mix="1D Burgers + 2D advection-diffusion, K 8..256, N 2..5, Nt 2..4, FP64/FP32-inner 50/50, CFL 5")
 
 
 def main():
@@ -221,6 +315,8 @@ def main():
     warm_total = sum(shares_w) or 1.0
     shares = {st.KERNEL_CLASSES[c]: round(shares_w[c] / warm_total, 4) for c in range(len(shares_w))}
 
+    serving = serving_bench(args.serve_requests) if args.serve_requests > 0 else None
+
     cpu = None
     if not args.no_cpu_baseline:
         Uh = U.cpu().numpy()
@@ -249,6 +345,7 @@ def main():
         "operator_evals": op_evals,
         "kernel_time_share_of_timed": shares,
         "roofline": roof,
+        "serving": serving,
         "cpu_baseline": cpu,
     }
     st.st_destroy(h)
