@@ -66,6 +66,9 @@ def parse():
     ap.add_argument("--no-timing", action="store_true", help="run without HIP-event kernel timing")
     ap.add_argument("--serve-requests", type=int, default=96,
                     help="requests in the served-stream sample (0: skip the serving leg)")
+    ap.add_argument("--operators", type=int, default=1,
+                    help="1: time st_residual / st_jvp on >= 1 GB working sets (0: skip)")
+    ap.add_argument("--operator-reps", type=int, default=10)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (3 times) for counter calibration")
     return ap.parse_args()
@@ -219,6 +222,77 @@ def serving_bench(n_requests, seed=4, budget_gib=64, max_active=64, load=0.7):
                 mix="1D Burgers + 2D advection-diffusion, K 8..256, N 2..5, Nt 2..4, FP64/FP32-inner 50/50, CFL 5")
 
 
+# Enlarged meshes of the three PDE workloads (same N, Nt, equation and data
+# recipe) whose vectors are 400-500 MB, so that one operator call moves about
+# 1 GB: beyond the 256 MB Infinity Cache, so the rate is an HBM rate.
+OPERATOR_WORKLOADS = {
+    "advdiff2d": dict(K=[768, 768], label="2D advection-diffusion BR1, 768x768 quads, N=4, Nt=4"),
+    "euler2d": dict(K=[512, 512], label="2D Euler vortex, 512x512 quads on [-5,5]^2, N=3, Nt=3"),
+    "ns3d": dict(K=[40, 40, 40], label="3D Navier-Stokes TGV, 40^3 hexes, N=3, Nt=3"),
+}
+
+
+def operator_bench(reps, fp32_too=True):
+    """st_residual and st_jvp on >= 1 GB working sets, timed with HIP events
+    on the calling stream (the whole API call: for Navier-Stokes it includes
+    the BR1 gradient passes).  Rates use the algorithmic bytes: residual
+    (2 + 1/Nt) n 8, JVP 24 n (linear equations 16 n, FP32-inner 20 n)."""
+    import numpy as np
+    import torch
+    from paper_2201_05800_amd import inputs, st
+    stream = torch.cuda.current_stream()
+    out = []
+    for name, ow in OPERATOR_WORKLOADS.items():
+        cfg = dict(CONFIGS[name])
+        cfg["K"] = ow["K"]
+        d = cfg["dim"]
+        eq = st.equation(cfg["kind"], a=cfg.get("a", (0, 0, 0)), nu=cfg.get("nu", 0.0), gamma=cfg.get("gamma", 1.4),
+                         mu=cfg.get("mu", 0.0), prandtl=cfg.get("prandtl", 0.72))
+        h = st.st_create(st.mesh(d, cfg["K"], cfg["lo"], cfg["hi"]), cfg["N"], cfg["Nt"], eq)
+        try:
+            n, nsp, nv = st.st_sizes(h)
+            ns = (cfg["N"] + 1) ** d
+            u0 = initial_state(cfg, st.st_node_coords(h, d, ns)).reshape(-1, nv, ns)
+            hmin = min((cfg["hi"][a] - cfg["lo"][a]) / cfg["K"][a] for a in range(d))
+            dt = cfg["dt"]
+            if dt is None:
+                dt = inputs.cfl_dt(5.0, hmin, cfg["N"], inputs.euler_max_speed(u0, cfg.get("gamma", 1.4)))
+            up = torch.as_tensor(u0.ravel()).cuda()
+            # a state near the solution: 1 (x) u^n with 1e-3 relative noise
+            U = up.view(-1, nv, 1, ns).expand(-1, nv, cfg["Nt"], ns).contiguous().view(-1)
+            g = torch.Generator(device="cuda").manual_seed(7)
+            U.mul_(1.0 + 1e-3 * torch.randn(n, generator=g, device="cuda", dtype=torch.float64))
+            v = torch.randn(n, generator=g, device="cuda", dtype=torch.float64)
+            R = torch.empty(n, dtype=torch.float64, device="cuda")
+            lin = cfg["kind"] in (st.ST_ADVECTION, st.ST_ADVDIFF_BR1)
+            calls = [("st_residual", lambda: st.st_residual(h, U, up, 0.0, dt, R, stream), (2.0 + 1.0 / cfg["Nt"]) * 8)]
+            calls.append(("st_jvp", lambda: st.st_jvp(h, U, 0.0, dt, v, R, 0, stream), 16.0 if lin else 24.0))
+            if fp32_too:
+                calls.append(("st_jvp fp32-inner", lambda: st.st_jvp(h, U, 0.0, dt, v, R, 1, stream),
+                              16.0 if lin else 20.0))
+            for op, fn, bpu in calls:
+                fn()
+                fn()
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                torch.cuda.synchronize()
+                e0.record(stream)
+                for _ in range(reps):
+                    fn()
+                e1.record(stream)
+                torch.cuda.synchronize()
+                ms = e0.elapsed_time(e1) / reps
+                gbs = bpu * n / (ms * 1e-3) / 1e9
+                out.append(dict(workload=ow["label"], op=op, unknowns=n, ms=round(ms, 4),
+                                dof_evals_per_s=n / (ms * 1e-3), algorithmic_GBs=round(gbs, 1),
+                                frac=round(gbs / HBM_PEAK_GBS, 4)))
+                print(f"# {ow['label']}: {op} {ms:.3f} ms, {gbs:.0f} GB/s", file=sys.stderr, flush=True)
+            del U, v, R, up
+        finally:
+            st.st_destroy(h)
+        torch.cuda.empty_cache()
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -316,6 +390,7 @@ def main():
     shares = {st.KERNEL_CLASSES[c]: round(shares_w[c] / warm_total, 4) for c in range(len(shares_w))}
 
     serving = serving_bench(args.serve_requests) if args.serve_requests > 0 else None
+    operators = operator_bench(args.operator_reps) if args.operators else None
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -346,6 +421,7 @@ def main():
         "kernel_time_share_of_timed": shares,
         "roofline": roof,
         "serving": serving,
+        "operators": operators,
         "cpu_baseline": cpu,
     }
     st.st_destroy(h)

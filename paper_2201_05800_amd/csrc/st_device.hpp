@@ -36,7 +36,8 @@ void launch_k(K kernel, dim3 grid, dim3 block, hipStream_t st, A... args) {
 }
 
 constexpr int MMAX = 32;           // largest GMRES restart length
-constexpr int BLOCK = 256;         // threads per block of every kernel
+constexpr int BLOCK = 256;         // threads per block of the operator kernels
+constexpr int VBLOCK = 512;        // threads per block of the Krylov vector kernels
 
 enum EqKind { EQ_ADV = 1, EQ_ADVDIFF = 2, EQ_BURGERS = 3, EQ_EULER = 4, EQ_NS = 5 };
 
@@ -303,7 +304,7 @@ struct VecSeg {
     int nblk;
 };
 
-// blocks of one slab in a vector launch: about 4 elements per thread, at
+// blocks of one slab in a vector launch: about 2 elements per thread, at
 // most 256 blocks (one per CU); larger slabs loop (grid stride).  Consumers
 // reduce the per-block partial tables redundantly in every block, so the
 // block count is kept at what the bandwidth needs.

@@ -54,8 +54,10 @@ DI int find_vseg(const VecSeg* segs, int nseg, int b) {
     return lo;
 }
 
-// Block reduction of NV per-thread values; returns with sums in out[0..NV).
-// smem: 4 * NV doubles.
+constexpr int VWAVES = VBLOCK / 64;
+
+// Block reduction of NV per-thread values; returns with sums in out[0..NV)
+// (waves added in a fixed order).  smem: VWAVES * NV doubles.
 template <int NV>
 DI void block_sums(const double (&acc)[NV], double* smem, double* out) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -67,7 +69,10 @@ DI void block_sums(const double (&acc)[NV], double* smem, double* out) {
     __syncthreads();
     if (threadIdx.x < NV) {
         const int i = threadIdx.x;
-        out[i] = smem[i] + smem[NV + i] + smem[2 * NV + i] + smem[3 * NV + i];
+        double s = smem[i];
+#pragma unroll
+        for (int q = 1; q < VWAVES; ++q) s += smem[q * NV + i];
+        out[i] = s;
     }
     __syncthreads();
 }
@@ -75,11 +80,11 @@ DI void block_sums(const double (&acc)[NV], double* smem, double* out) {
 // Column sums of a partial table P[b * ld + c] (b < nb <= 256, c < NVAL), in
 // the same fixed order in every block; result in s_out[0..NVAL).  Every
 // thread issues all of its loads before adding (they come from other XCDs).
-// s_tmp: BLOCK doubles.
+// s_tmp: VBLOCK doubles.
 template <int NVAL>
 DI void reduce_table(const __attribute__((address_space(1))) double* P, int ld, int nb, double* s_tmp,
                      double* s_out) {
-    constexpr int G = (BLOCK / NVAL) < 64 ? (BLOCK / NVAL) : 64;
+    constexpr int G = (VBLOCK / NVAL) < 64 ? (VBLOCK / NVAL) : 64;
     constexpr int MAXR = (256 + G - 1) / G;
     const int c = threadIdx.x % NVAL, r = threadIdx.x / NVAL;
     double a = 0.0;
@@ -104,18 +109,44 @@ DI void reduce_table(const __attribute__((address_space(1))) double* P, int ld, 
     __syncthreads();
 }
 
+// Elements per thread and loop step of the Gram-Schmidt sweeps: two while
+// the basis entries of both fit in registers, else one.
+template <int NV>
+constexpr int sweep_unroll() { return NV <= 24 ? 2 : 1; }
+
+// Basis entries V_i[t + q stride] (i < NV, q < UN) and w[t + q stride]; zero
+// past the end.  All loads are issued before any is used.
+template <int NV, int UN>
+DI void load_group(const __attribute__((address_space(1))) double* V, const __attribute__((address_space(1))) double* w,
+                   int64_t n, int64_t t, int64_t stride, double (&a)[UN][NV], double (&wv)[UN]) {
+#pragma unroll
+    for (int q = 0; q < UN; ++q) {
+        const int64_t tq = t + q * stride;
+        const bool p = tq < n;
+#pragma unroll
+        for (int i = 0; i < NV; ++i) a[q][i] = p ? V[(int64_t)i * n + tq] : 0.0;
+        wv[q] = p ? w[tq] : 0.0;
+    }
+}
+
 }  // namespace
 
 // Partial sums of ||R||^2 (one per block) -> part2.
-__global__ __launch_bounds__(BLOCK) void k_rnorm(const VecSeg* __restrict__ segs, int nseg) {
-    __shared__ double smem[4];
+__global__ __launch_bounds__(VBLOCK) void k_rnorm(const VecSeg* __restrict__ segs, int nseg) {
+    __shared__ double smem[VWAVES];
     __shared__ double s_out[1];
     const VecSeg& sg = segs[find_vseg(segs, nseg, blockIdx.x)];
     const int lb = blockIdx.x - sg.blk0;
     const auto* __restrict__ R = gl((const double*)sg.R);
     double acc[1] = {0.0};
-    const int64_t stride = (int64_t)sg.nblk * BLOCK;
-    for (int64_t i = (int64_t)lb * BLOCK + threadIdx.x; i < sg.n; i += stride) acc[0] += R[i] * R[i];
+    const int64_t stride = (int64_t)sg.nblk * VBLOCK;
+    for (int64_t i = (int64_t)lb * VBLOCK + threadIdx.x; i < sg.n; i += 4 * stride) {
+        double r[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) r[q] = i + q * stride < sg.n ? R[i + q * stride] : 0.0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) acc[0] += r[q] * r[q];
+    }
     block_sums<1>(acc, smem, s_out);
     if (threadIdx.x == 0) gl(sg.part2)[lb] = s_out[0];
 }
@@ -123,8 +154,8 @@ __global__ __launch_bounds__(BLOCK) void k_rnorm(const VecSeg* __restrict__ segs
 // Start of an outer iteration (one block per slab): ||R|| from the partials,
 // the stopping threshold on the first iteration, and the GMRES cycle state
 // beta = ||R||, g = beta e1, k = 0, eta_abs = max(eta_rel beta, eta_tgt target).
-__global__ __launch_bounds__(BLOCK) void k_begin(const VecSeg* __restrict__ segs, int nseg) {
-    __shared__ double s_tmp[BLOCK];
+__global__ __launch_bounds__(VBLOCK) void k_begin(const VecSeg* __restrict__ segs, int nseg) {
+    __shared__ double s_tmp[VBLOCK];
     __shared__ double s_out[1];
     if (blockIdx.x >= nseg) return;
     const VecSeg& sg = segs[blockIdx.x];
@@ -148,52 +179,54 @@ __global__ __launch_bounds__(BLOCK) void k_begin(const VecSeg* __restrict__ segs
 }
 
 // V_0 = -R / beta
-__global__ __launch_bounds__(BLOCK) void k_scale_v0(const VecSeg* __restrict__ segs, int nseg) {
+__global__ __launch_bounds__(VBLOCK) void k_scale_v0(const VecSeg* __restrict__ segs, int nseg) {
     const VecSeg& sg = segs[find_vseg(segs, nseg, blockIdx.x)];
     if (sg.st->done) return;
     const int lb = blockIdx.x - sg.blk0;
     const double s = -1.0 / sg.st->beta;
     const auto* __restrict__ R = gl((const double*)sg.R);
     auto* __restrict__ V = gl(sg.V);
-    const int64_t stride = (int64_t)sg.nblk * BLOCK;
-    for (int64_t i = (int64_t)lb * BLOCK + threadIdx.x; i < sg.n; i += stride) V[i] = s * R[i];
+    const int64_t stride = (int64_t)sg.nblk * VBLOCK;
+    for (int64_t i = (int64_t)lb * VBLOCK + threadIdx.x; i < sg.n; i += stride) V[i] = s * R[i];
 }
 
 // Projections V_i . w (i < NV) and w . w of one Gram-Schmidt pass, as one
-// row of partial sums per block -> part.
+// row of partial sums per block -> part.  The loads of every thread's first
+// elements are in flight before the cycle state is read.
 template <int NV>
-__global__ __launch_bounds__(BLOCK) void k_multidot(const VecSeg* __restrict__ segs, int nseg) {
-    __shared__ double smem[4 * (NV + 1)];
+__global__ __launch_bounds__(VBLOCK) void k_multidot(const VecSeg* __restrict__ segs, int nseg) {
+    __shared__ double smem[VWAVES * (NV + 1)];
     __shared__ double s_out[NV + 1];
     const VecSeg& sg = segs[find_vseg(segs, nseg, blockIdx.x)];
-    const GState* st = sg.st;
-    if (st->done || st->k != NV - 1) return;
     const int lb = blockIdx.x - sg.blk0;
-    double acc[NV + 1];
-#pragma unroll
-    for (int i = 0; i <= NV; ++i) acc[i] = 0.0;
     const int64_t n = sg.n;
-    const int64_t stride = (int64_t)sg.nblk * BLOCK;
+    const int64_t stride = (int64_t)sg.nblk * VBLOCK;
     const auto* __restrict__ V = gl((const double*)sg.V);
     const auto* __restrict__ w = gl((const double*)sg.w);
-    int64_t t = (int64_t)lb * BLOCK + threadIdx.x;
-    for (; t + stride < n; t += 2 * stride) {
-        const double w0 = w[t], w1 = w[t + stride];
-        double a0[NV], a1[NV];
+    constexpr int UN = sweep_unroll<NV>();
+    int64_t t = (int64_t)lb * VBLOCK + threadIdx.x;
+    double a[UN][NV], wv[UN];
+    load_group<NV, UN>(V, w, n, t, stride, a, wv);
+    const GState* st = sg.st;
+    if (st->done || st->k != NV - 1) return;
+    double acc[NV + 1];
+    auto accumulate = [&](bool first) {
 #pragma unroll
         for (int i = 0; i < NV; ++i) {
-            a0[i] = V[(int64_t)i * n + t];
-            a1[i] = V[(int64_t)i * n + t + stride];
+            double s = a[0][i] * wv[0];
+#pragma unroll
+            for (int q = 1; q < UN; ++q) s += a[q][i] * wv[q];
+            acc[i] = first ? s : acc[i] + s;
         }
+        double s = wv[0] * wv[0];
 #pragma unroll
-        for (int i = 0; i < NV; ++i) acc[i] += a0[i] * w0 + a1[i] * w1;
-        acc[NV] += w0 * w0 + w1 * w1;
-    }
-    if (t < n) {
-        const double w0 = w[t];
-#pragma unroll
-        for (int i = 0; i < NV; ++i) acc[i] += V[(int64_t)i * n + t] * w0;
-        acc[NV] += w0 * w0;
+        for (int q = 1; q < UN; ++q) s += wv[q] * wv[q];
+        acc[NV] = first ? s : acc[NV] + s;
+    };
+    accumulate(true);
+    for (t += UN * stride; t < n; t += UN * stride) {
+        load_group<NV, UN>(V, w, n, t, stride, a, wv);
+        accumulate(false);
     }
     block_sums<NV + 1>(acc, smem, s_out);
     if (threadIdx.x <= NV) gl(sg.part)[(int64_t)lb * NPART + threadIdx.x] = s_out[threadIdx.x];
@@ -211,27 +244,32 @@ __global__ __launch_bounds__(BLOCK) void k_multidot(const VecSeg* __restrict__ s
 //    computes the same column; block 0 commits it.
 // State written by block 0 here (done, k, H, rotations, g[k+1]) is never read
 // by another block of this kernel; a block that sees done = 1 set here skips
-// a sweep whose result is not needed.
+// a sweep whose result is not needed.  Every thread's first elements are
+// loaded while the table is reduced.
 template <int NV>
-__global__ __launch_bounds__(BLOCK) void k_update(const VecSeg* __restrict__ segs, int nseg, int pass,
-                                                  int last) {
-    __shared__ double s_tmp[BLOCK];
+__global__ __launch_bounds__(VBLOCK) void k_update(const VecSeg* __restrict__ segs, int nseg, int pass,
+                                                   int last) {
+    __shared__ double s_tmp[VBLOCK];
     __shared__ double s_h[NV + 1];
     __shared__ double s_col[NV + 1];
     const VecSeg& sg = segs[find_vseg(segs, nseg, blockIdx.x)];
     GState* st = sg.st;
-    if (st->done) return;
     constexpr int k = NV - 1;
     const int lb = blockIdx.x - sg.blk0;
+    const int64_t n = sg.n;
+    const int64_t stride = (int64_t)sg.nblk * VBLOCK;
+    const auto* __restrict__ V = gl((const double*)sg.V);
+    auto* __restrict__ w = gl(sg.w);
+    constexpr int UN = sweep_unroll<NV>();
+    int64_t t = (int64_t)lb * VBLOCK + threadIdx.x;
+    double a[UN][NV], wv[UN];
+    load_group<NV, UN>(V, w, n, t, stride, a, wv);
+    if (st->done) return;
     reduce_table<NV + 1>(gl((const double*)sg.part), NPART, sg.nblk, s_tmp, s_h);
     double h[NV];
 #pragma unroll
     for (int i = 0; i < NV; ++i) h[i] = s_h[i];
     const double ww = s_h[NV];
-    const int64_t n = sg.n;
-    const int64_t stride = (int64_t)sg.nblk * BLOCK;
-    const auto* __restrict__ V = gl((const double*)sg.V);
-    auto* __restrict__ w = gl(sg.w);
 
     double scale = 1.0;                 // 1 / h_{k+1,k} on the last pass
     auto* __restrict__ dst = w;         // where the corrected vector goes
@@ -298,28 +336,18 @@ __global__ __launch_bounds__(BLOCK) void k_update(const VecSeg* __restrict__ seg
         scale = 1.0 / hn;
         dst = gl(sg.V + (int64_t)(k + 1) * n);
     }
-    int64_t t = (int64_t)lb * BLOCK + threadIdx.x;
-    for (; t + stride < n; t += 2 * stride) {
-        double a0[NV], a1[NV];
+    auto correct = [&]() {
 #pragma unroll
-        for (int i = 0; i < NV; ++i) {
-            a0[i] = V[(int64_t)i * n + t];
-            a1[i] = V[(int64_t)i * n + t + stride];
+        for (int q = 0; q < UN; ++q) {
+#pragma unroll
+            for (int i = 0; i < NV; ++i) wv[q] -= h[i] * a[q][i];
+            if (t + q * stride < n) dst[t + q * stride] = scale * wv[q];
         }
-        double w0 = w[t], w1 = w[t + stride];
-#pragma unroll
-        for (int i = 0; i < NV; ++i) {
-            w0 -= h[i] * a0[i];
-            w1 -= h[i] * a1[i];
-        }
-        dst[t] = scale * w0;
-        dst[t + stride] = scale * w1;
-    }
-    if (t < n) {
-        double w0 = w[t];
-#pragma unroll
-        for (int i = 0; i < NV; ++i) w0 -= h[i] * V[(int64_t)i * n + t];
-        dst[t] = scale * w0;
+    };
+    correct();
+    for (t += UN * stride; t < n; t += UN * stride) {
+        load_group<NV, UN>(V, w, n, t, stride, a, wv);
+        correct();
     }
 }
 
@@ -353,7 +381,7 @@ __global__ __launch_bounds__(BLOCK) void k_finish(const VecSeg* __restrict__ seg
 }
 
 // U += sum_{i < kfinal} y_i V_i
-__global__ __launch_bounds__(BLOCK) void k_update_u(const VecSeg* __restrict__ segs, int nseg) {
+__global__ __launch_bounds__(VBLOCK) void k_update_u(const VecSeg* __restrict__ segs, int nseg) {
     __shared__ double s_y[MMAX];
     const VecSeg& sg = segs[find_vseg(segs, nseg, blockIdx.x)];
     const GState* st = sg.st;
@@ -363,33 +391,33 @@ __global__ __launch_bounds__(BLOCK) void k_update_u(const VecSeg* __restrict__ s
     __syncthreads();
     const int lb = blockIdx.x - sg.blk0;
     const int64_t n = sg.n;
-    const int64_t stride = (int64_t)sg.nblk * BLOCK;
+    const int64_t stride = (int64_t)sg.nblk * VBLOCK;
     const auto* __restrict__ V = gl((const double*)sg.V);
     auto* __restrict__ U = gl(sg.U);
-    for (int64_t t = (int64_t)lb * BLOCK + threadIdx.x; t < n; t += stride) {
+    for (int64_t t = (int64_t)lb * VBLOCK + threadIdx.x; t < n; t += stride) {
         double u = U[t];
-        // groups of 4 independent loads; indices past kf re-read V_{kf-1} with weight 0
-        for (int i0 = 0; i0 < kf; i0 += 4) {
-            double a[4];
+        // groups of 8 independent loads; indices past kf re-read V_{kf-1} with weight 0
+        for (int i0 = 0; i0 < kf; i0 += 8) {
+            double a[8];
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
+            for (int j = 0; j < 8; ++j) {
                 const int i = i0 + j < kf ? i0 + j : kf - 1;
                 a[j] = V[(int64_t)i * n + t];
             }
 #pragma unroll
-            for (int j = 0; j < 4; ++j) u += s_y[i0 + j < MMAX ? i0 + j : MMAX - 1] * (i0 + j < kf ? a[j] : 0.0);
+            for (int j = 0; j < 8; ++j) u += s_y[i0 + j < MMAX ? i0 + j : MMAX - 1] * (i0 + j < kf ? a[j] : 0.0);
         }
         U[t] = u;
     }
 }
 
 // U = 1 (x) u_prev (initial guess of the Newton iteration)
-__global__ __launch_bounds__(BLOCK) void k_init_guess(const VecSeg* __restrict__ segs, int nseg) {
+__global__ __launch_bounds__(VBLOCK) void k_init_guess(const VecSeg* __restrict__ segs, int nseg) {
     const VecSeg& sg = segs[find_vseg(segs, nseg, blockIdx.x)];
     const int lb = blockIdx.x - sg.blk0;
     const int64_t blkn = (int64_t)sg.nt * sg.ns;
-    const int64_t stride = (int64_t)sg.nblk * BLOCK;
-    for (int64_t i = (int64_t)lb * BLOCK + threadIdx.x; i < sg.n; i += stride) {
+    const int64_t stride = (int64_t)sg.nblk * VBLOCK;
+    for (int64_t i = (int64_t)lb * VBLOCK + threadIdx.x; i < sg.n; i += stride) {
         const int64_t ev = i / blkn;
         const int64_t s = i % sg.ns;
         sg.U[i] = sg.uprev[ev * sg.ns + s];
@@ -397,12 +425,12 @@ __global__ __launch_bounds__(BLOCK) void k_init_guess(const VecSeg* __restrict__
 }
 
 // u_next = (e_Nt^T (x) I) U (eq. (un))
-__global__ __launch_bounds__(BLOCK) void k_extract_last(const VecSeg* __restrict__ segs, int nseg) {
+__global__ __launch_bounds__(VBLOCK) void k_extract_last(const VecSeg* __restrict__ segs, int nseg) {
     const VecSeg& sg = segs[find_vseg(segs, nseg, blockIdx.x)];
     const int lb = blockIdx.x - sg.blk0;
     const int64_t nsp = sg.n / sg.nt;
-    const int64_t stride = (int64_t)sg.nblk * BLOCK;
-    for (int64_t i = (int64_t)lb * BLOCK + threadIdx.x; i < nsp; i += stride) {
+    const int64_t stride = (int64_t)sg.nblk * VBLOCK;
+    for (int64_t i = (int64_t)lb * VBLOCK + threadIdx.x; i < nsp; i += stride) {
         const int64_t ev = i / sg.ns;
         const int64_t s = i % sg.ns;
         sg.unext[i] = sg.U[(ev * sg.nt + (sg.nt - 1)) * sg.ns + s];
@@ -410,11 +438,18 @@ __global__ __launch_bounds__(BLOCK) void k_extract_last(const VecSeg* __restrict
 }
 
 // U32 = fl(U)
-__global__ __launch_bounds__(BLOCK) void k_cast32(const VecSeg* __restrict__ segs, int nseg) {
+__global__ __launch_bounds__(VBLOCK) void k_cast32(const VecSeg* __restrict__ segs, int nseg) {
     const VecSeg& sg = segs[find_vseg(segs, nseg, blockIdx.x)];
     const int lb = blockIdx.x - sg.blk0;
-    const int64_t stride = (int64_t)sg.nblk * BLOCK;
-    for (int64_t i = (int64_t)lb * BLOCK + threadIdx.x; i < sg.n; i += stride) sg.U32[i] = (float)sg.U[i];
+    const int64_t stride = (int64_t)sg.nblk * VBLOCK;
+    for (int64_t i = (int64_t)lb * VBLOCK + threadIdx.x; i < sg.n; i += 4 * stride) {
+        double u[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) u[q] = i + q * stride < sg.n ? sg.U[i + q * stride] : 0.0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            if (i + q * stride < sg.n) sg.U32[i + q * stride] = (float)u[q];
+    }
 }
 
 __global__ void k_put_opseg(OpSeg* dst, OpSeg v) { if (threadIdx.x == 0 && blockIdx.x == 0) *dst = v; }
@@ -423,7 +458,7 @@ __global__ void k_put_vecseg(VecSeg* dst, VecSeg v) { if (threadIdx.x == 0 && bl
 // ---------------------------------------------------------------------------
 // host launchers
 // ---------------------------------------------------------------------------
-#define LAUNCH_V(K, G, ...) launch_k(K, dim3(G), dim3(BLOCK), st, __VA_ARGS__)
+#define LAUNCH_V(K, G, ...) launch_k(K, dim3(G), dim3(VBLOCK), st, __VA_ARGS__)
 
 LaunchTiming& launch_timing() {
     static thread_local LaunchTiming lt;

@@ -1,15 +1,25 @@
 // st_ops_impl.hpp -- slab operator kernels: residual, Jacobian-vector
 // product and BR1 lifted gradient, for one (equation, dim, N+1, Nt).
 //
-// Thread mapping: one thread per (element, spatial node); the thread keeps
-// all Nt time nodes and all variables of its node in registers, so the time
-// derivative and the upwind coupling of the time element (eq. (DG_in_time))
-// are thread-local.  A block holds EPB = 256 / ns consecutive elements; the
-// per-axis flux values of the block are staged in LDS for the
-// sum-factorised D contractions along each space axis.  Interface traces of
-// neighbouring elements are read from global memory (L2 resident: the
-// logical block order is remapped so that each XCD sweeps one contiguous
-// range of elements).
+// Thread mapping: one thread per space-time node (element, time node,
+// spatial node), so a thread holds one state of R variables.  A block holds
+// EPB consecutive elements, chosen so that the block is a whole number of
+// wavefronts with few idle lanes.  The kernel runs in phases separated by
+// block barriers:
+//   0. the block's states (and, for a JVP, the direction) go to an LDS tile;
+//   1. every thread evaluates the total flux along all d axes at its node
+//      (primitive variables computed once) and stages it in LDS;
+//   2. volume term: the sum-factorised D contraction along each axis
+//      (eq. (elementint) in strong form);
+//   3. surface term on compacted threads: one thread per face point
+//      (element, axis, side, time node, face node) computes the Rusanov
+//      flux with the neighbour's trace (eq. (flux:llf)) and leaves H - f in
+//      the LDS slot of the face node, so no lane idles while face nodes work;
+//   4. each node adds the lifted surface terms of its faces and the DG
+//      time discretisation (eq. (DG_in_time)): the time derivative reads the
+//      other time nodes of the same spatial node from the tile.
+// Neighbour traces are read from global memory (L2 resident: the logical
+// block order is remapped so that each XCD sweeps one contiguous range).
 #pragma once
 #include "st_krylov.hpp"
 #include <type_traits>
@@ -56,44 +66,172 @@ DI gptr<P> resolve(const DynPtr& d) {
     return (gptr<P>)const_cast<P*>(b);
 }
 
-template <int D> DI int node_coord(int s, int n1, int a) {
-    return a == 0 ? s % n1 : (a == 1 ? (s / n1) % n1 : s / (n1 * n1));
+// ---------------------------------------------------------------------------
+// block shape: EPB elements of NPE = N1^D * NT space-time nodes per block
+// ---------------------------------------------------------------------------
+constexpr int best_epb(int npe) {
+    int best = 1, bnum = 0, bden = 1;
+    for (int e = 1; e * npe <= 512; ++e) {
+        const int b = e * npe, bs = (b + 63) / 64 * 64;
+        if (b * bden > bnum * bs) { best = e; bnum = b; bden = bs; }   // strictly better lane use
+    }
+    return best;
 }
 
-// numerical flux along +e_a between left state L and right state R:
-// Rusanov convective part (eq. (flux:llf)) minus the central BR1 viscous part
+// Time nodes per thread: the scalar equations keep all Nt time nodes of a
+// spatial node in one thread (few registers, index work shared by Nt
+// nodes); the systems take one space-time node per thread (registers).
+__host__ __device__ constexpr int tpt_of(int eq, int nt) { return nvars_of(eq, 1) == 1 ? nt : 1; }
+
+template <int D, int N1, int NT, int TPT>
+struct Shape {
+    static constexpr int NS = ipow(N1, D);            // spatial nodes per element
+    static constexpr int NPE = NS * NT;               // space-time nodes per element
+    static constexpr int NF = ipow(N1, D - 1);        // nodes per face
+    static constexpr int NJ = NT / TPT;               // time groups per spatial node
+    static constexpr int NTH = NS * NJ;               // threads per element
+    static constexpr int EPB = best_epb(NTH);         // elements per block
+    static constexpr int B = EPB * NTH;               // threads with nodes
+    static constexpr int BS = (B + 63) / 64 * 64;     // block size
+    static constexpr int NN = EPB * NPE;              // nodes per block
+    static constexpr int NFP = EPB * D * 2 * NJ * NF; // face points per block (TPT time nodes each)
+};
+
+template <int N1, int A>
+DI int coord(int s) { return (int)(((unsigned)s / (unsigned)ipow(N1, A)) % (unsigned)N1); }
+
+// Spatial node on face (axis a, side) from its face index f: the other axes
+// in increasing order, the first one fastest.
+template <int D, int N1, int A>
+DI int face_node(int f, bool right) {
+    int s = (right ? N1 - 1 : 0) * ipow(N1, A);
+    int m = 1;
+#pragma unroll
+    for (int b = 0; b < D; ++b) {
+        if (b == A) continue;
+        s += (int)(((unsigned)f / (unsigned)m) % (unsigned)N1) * ipow(N1, b);
+        m *= N1;
+    }
+    return s;
+}
+
+// Element across the face of element e along axis a (periodic); element
+// indices fit 31 bits (checked when the problem is made).
+DI int neighbour(const OpSeg& sg, int e, int a, bool right) {
+    const unsigned es = a == 0 ? 1u : (a == 1 ? (unsigned)sg.K[0] : (unsigned)sg.K[0] * (unsigned)sg.K[1]);
+    const int ca = (int)(((unsigned)e / es) % (unsigned)sg.K[a]);
+    const int cn = right ? (ca + 1 == sg.K[a] ? 0 : ca + 1) : (ca == 0 ? sg.K[a] - 1 : ca - 1);
+    return e + (cn - ca) * (int)es;
+}
+
+// ---------------------------------------------------------------------------
+// pointwise physics with the primitive variables shared by all axes
+// ---------------------------------------------------------------------------
 template <int EQ, int D, class T>
-DI void num_flux(int a, const T* uL, const T* uR, const T* qL, const T* qR, T* H, const EqParams& P) {
-    using Ph = Phys<EQ, D, T>;
+struct Flux {
     using S = typename BaseOf<T>::type;
-    constexpr int R = Ph::R;
-    T fL[R], fR[R];
-    Ph::conv(a, uL, fL, P);
-    Ph::conv(a, uR, fR, P);
-    T lam = larger(Ph::speed(a, uL, P), Ph::speed(a, uR, P));
-#pragma unroll
-    for (int v = 0; v < R; ++v) H[v] = S(0.5) * (fL[v] + fR[v]) + (S(0.5) * lam) * (uL[v] - uR[v]);
-    if constexpr (viscous_eq(EQ)) {
-        T gL[R], gR[R];
-        Ph::visc(a, uL, qL, gL, P);
-        Ph::visc(a, uR, qR, gR, P);
-#pragma unroll
-        for (int v = 0; v < R; ++v) H[v] = H[v] - S(0.5) * (gL[v] + gR[v]);
-    }
-}
+    static constexpr int R = nvars_of(EQ, D);
+    static constexpr bool GAS = (EQ == EQ_EULER || EQ == EQ_NS);
 
-template <int EQ, int D, class T>
-DI void total_flux(int a, const T* u, const T* q, T* f, const EqParams& P) {
-    using Ph = Phys<EQ, D, T>;
-    Ph::conv(a, u, f, P);
-    if constexpr (viscous_eq(EQ)) {
-        constexpr int R = Ph::R;
-        T g[R];
-        Ph::visc(a, u, q, g, P);
+    struct Prim {
+        T inv;        // 1 / rho
+        T vel[D];
+        T p;
+    };
+    SDI Prim prim(const T* u, const EqParams& P) {
+        Prim w;
+        if constexpr (GAS) {
+            w.inv = S(1) / u[0];
+            T mv = make_state<T>(S(0), S(0));
 #pragma unroll
-        for (int v = 0; v < R; ++v) f[v] = f[v] - g[v];
+            for (int b = 0; b < D; ++b) {
+                w.vel[b] = u[1 + b] * w.inv;
+                mv = b == 0 ? u[1] * w.vel[0] : mv + u[1 + b] * w.vel[b];
+            }
+            w.p = (S(P.gamma) - S(1)) * (u[D + 1] - S(0.5) * mv);
+        }
+        return w;
     }
-}
+
+    // convective flux along axis a
+    SDI void conv(int a, const T* u, const Prim& w, T* f, const EqParams& P) {
+        if constexpr (EQ == EQ_ADV || EQ == EQ_ADVDIFF) {
+            f[0] = u[0] * S(P.a[a]);
+        } else if constexpr (EQ == EQ_BURGERS) {
+            f[0] = S(0.5) * (u[0] * u[0]);
+        } else {
+            const T va = w.vel[a];
+            f[0] = u[1 + a];
+#pragma unroll
+            for (int b = 0; b < D; ++b) f[1 + b] = u[1 + b] * va;
+            f[1 + a] = f[1 + a] + w.p;
+            f[D + 1] = (u[D + 1] + w.p) * va;
+        }
+    }
+
+    // largest characteristic speed along axis a
+    SDI T speed(int a, const T* u, const EqParams& P) {
+        if constexpr (EQ == EQ_ADV || EQ == EQ_ADVDIFF) {
+            return make_state<T>(S(fabs(P.a[a])), S(0));
+        } else if constexpr (EQ == EQ_BURGERS) {
+            return absval(u[0]);
+        } else {
+            const Prim w = prim(u, P);
+            const T c = sqrt_(S(P.gamma) * w.p * w.inv);
+            return absval(w.vel[a]) + c;
+        }
+    }
+
+    // Navier-Stokes viscous quantities from the conservative gradient
+    // q[b * R + v] = d u_v / d x_b: velocity gradient gv[b][c] = d v_c / d x_b,
+    // temperature gradient (T = p / rho), divergence.
+    struct Visc {
+        T gv[D][D];
+        T gT[D];
+        T div;
+    };
+    SDI Visc visc_state(const Prim& w, const T* q, const EqParams& P) {
+        Visc z;
+        if constexpr (EQ == EQ_NS) {
+            const S gm1 = S(P.gamma) - S(1);
+            const T Tm = w.p * w.inv;
+            T v2 = w.vel[0] * w.vel[0];
+#pragma unroll
+            for (int b = 1; b < D; ++b) v2 = v2 + w.vel[b] * w.vel[b];
+#pragma unroll
+            for (int b = 0; b < D; ++b) {
+                const T gr = q[b * R];
+                T vgm = w.vel[0] * q[b * R + 1];
+#pragma unroll
+                for (int c = 0; c < D; ++c) {
+                    z.gv[b][c] = (q[b * R + 1 + c] - w.vel[c] * gr) * w.inv;
+                    if (c > 0) vgm = vgm + w.vel[c] * q[b * R + 1 + c];
+                }
+                const T gp = gm1 * (q[b * R + D + 1] - vgm + S(0.5) * (v2 * gr));
+                z.gT[b] = (gp - Tm * gr) * w.inv;
+            }
+            z.div = z.gv[0][0];
+#pragma unroll
+            for (int c = 1; c < D; ++c) z.div = z.div + z.gv[c][c];
+        }
+        return z;
+    }
+    // subtract the viscous flux along axis a from f (total flux = Fc - Fv)
+    SDI void sub_visc(int a, const Prim& w, const Visc& z, T* f, const EqParams& P) {
+        if constexpr (EQ == EQ_NS) {
+            const S mu = S(P.mu);
+            T work = make_state<T>(S(0), S(0));
+#pragma unroll
+            for (int c = 0; c < D; ++c) {
+                T tau = mu * (z.gv[a][c] + z.gv[c][a]);
+                if (c == a) tau = tau - (S(2) / S(3)) * mu * z.div;
+                f[1 + c] = f[1 + c] - tau;
+                work = c == 0 ? tau * w.vel[0] : work + tau * w.vel[c];
+            }
+            f[D + 1] = f[D + 1] - (work + S(P.kappa) * z.gT[a]);
+        }
+    }
+};
 
 // ---------------------------------------------------------------------------
 // Residual / JVP kernel.
@@ -101,146 +239,316 @@ DI void total_flux(int a, const T* u, const T* q, T* f, const EqParams& P) {
 //                type of U.  With U := v and u_prev = 0 this is also the JVP of
 //                the linear equations.
 //   JVP = true : out = J(U) v by dual numbers (U of type UT, v double).
+// Advection-diffusion computes its BR1 lifted gradient in the kernel: the
+// central viscous flux through a face needs only the neighbour's normal
+// derivative at the face node, which the face-point thread forms from the
+// neighbour's line of nodes normal to the face.  Navier-Stokes reads the
+// lifted gradient of U (and of v) from the gradient pass (k_grad).
 // ---------------------------------------------------------------------------
 template <int EQ, int D, int N1, int NT, class CT, class UT, bool JVP>
-__global__ __launch_bounds__(BLOCK) void k_op(const OpSeg* __restrict__ segs, int nseg, int G) {
+__global__ __launch_bounds__((Shape<D, N1, NT, tpt_of(EQ, NT)>::BS)) void k_op(const OpSeg* __restrict__ segs,
+                                                                               int nseg, int G) {
+    constexpr int TPT = tpt_of(EQ, NT);
+    using SH = Shape<D, N1, NT, TPT>;
     using T = typename std::conditional<JVP, Dual<CT>, CT>::type;
+    using F = Flux<EQ, D, T>;
     constexpr int R = nvars_of(EQ, D);
-    constexpr int NS = ipow(N1, D);
-    constexpr int EPB = BLOCK / NS > 0 ? BLOCK / NS : 1;
-    constexpr bool VISC = viscous_eq(EQ);
-    __shared__ CT buf[EPB * NT * R * NS];
+    constexpr int NS = SH::NS, NPE = SH::NPE, NF = SH::NF, NJ = SH::NJ, NTH = SH::NTH;
+    constexpr int EPB = SH::EPB, B = SH::B, BS = SH::BS, NN = SH::NN;
+    constexpr bool AD = EQ == EQ_ADVDIFF;
+    constexpr bool NSV = EQ == EQ_NS;
+    constexpr int TS = JVP ? 2 : 1;
+    constexpr int PL = JVP ? R : 0;             // tile plane of the stored part
+    constexpr int EV = R * NPE;                  // values of one element
+    __shared__ CT tile[TS * R * NN];             // [plane][v][node]: value, then tangent
+    __shared__ CT buf[D * R * NN];               // [a][v][node]: flux along a, then H - f
+    __shared__ int nbr[EPB * 2 * D];             // neighbour elements [el][a][side]
+    __shared__ CT sD[N1 * N1], sDt[NT * NT], swt[NT];
 
     const int L = xcd_remap(blockIdx.x, G);
     const OpSeg& sg = segs[find_seg(segs, nseg, L)];
-    if (sg.skip && *sg.skip) return;
+    if (sg.skip && *(const gptr<const int>)sg.skip) return;
     const EqParams& P = sg.P;
     const int tid = threadIdx.x;
-    const int el = tid / NS;
-    const int s = tid - el * NS;
-    const int64_t e = (int64_t)(L - sg.blk0) * EPB + el;
-    const bool active = (el < EPB) && (e < sg.E);
+    const int el = (int)((unsigned)tid / NTH);
+    const int jt = (int)((unsigned)(tid - el * NTH) / NS);   // time group
+    const int s = tid - el * NTH - jt * NS;                  // spatial node
+    const int e0 = (L - sg.blk0) * EPB;
+    const int e = e0 + el;
+    const bool active = (tid < B) && (e < sg.E);
+    const int nd0 = el * NPE + jt * TPT * NS + s;            // block node of time node jt*TPT
+    const int r0 = jt * TPT * NS + s;                        // element node of time node jt*TPT
+    int ic[D];                                               // coordinates of the spatial node
+    static_for<0, D>([&](auto A) { ic[decltype(A)::value] = coord<N1, decltype(A)::value>(s); });
+    const CT iw0 = CT(1) / CT(sg.wx[0]);                     // M^-1 B weight of the end nodes
 
     const gptr<UT> __restrict__ Up = resolve<UT>(sg.U);
     const gptr<double> __restrict__ Vp = JVP ? resolve<double>(sg.V) : nullptr;
-    const gptr<CT> __restrict__ Qp = VISC ? resolve<CT>(sg.Q) : nullptr;
-    const gptr<CT> __restrict__ dQp = (VISC && JVP) ? resolve<CT>(sg.dQ) : nullptr;
+    const gptr<CT> __restrict__ Qp = NSV ? resolve<CT>(sg.Q) : nullptr;
+    const gptr<CT> __restrict__ dQp = (NSV && JVP) ? resolve<CT>(sg.dQ) : nullptr;
     const gptr<double> __restrict__ out = resolve<double>(sg.out);
     const gptr<const double> __restrict__ upv = (gptr<const double>)sg.uprev;
 
-    const int ec[3] = {(int)(e % sg.K[0]), (int)((e / sg.K[0]) % sg.K[1]), (int)(e / ((int64_t)sg.K[0] * sg.K[1]))};
-    const int64_t es[3] = {1, sg.K[0], (int64_t)sg.K[0] * sg.K[1]};
-
-    T u[NT][R];
-    CT acc[NT][R];
-#pragma unroll
-    for (int j = 0; j < NT; ++j)
+    // state of element node rr (= j * NS + s) of element ee
+    auto load_state = [&](int ee, int rr, T* u) {
+        const gptr<UT> Ue = Up + (int64_t)ee * EV;
 #pragma unroll
         for (int v = 0; v < R; ++v) {
-            acc[j][v] = CT(0);
-            if (active) {
-                const int64_t idx = ((e * R + v) * NT + j) * NS + s;
-                u[j][v] = make_state<T>(CT(Up[idx]), JVP ? CT(Vp[idx]) : CT(0));
-            } else {
-                u[j][v] = make_state<T>(CT(1), CT(0));
-            }
+            if constexpr (JVP) u[v] = make_state<T>(CT(Ue[v * NPE + rr]), CT((Vp + (int64_t)ee * EV)[v * NPE + rr]));
+            else u[v] = CT(Ue[v * NPE + rr]);
         }
-
-    auto load_q = [&](gptr<CT> base, gptr<CT> dbase, int64_t ee, int ss, int j, T* q) {
+    };
+    auto load_grad = [&](int ee, int rr, T* q) {
+        const int64_t base = (int64_t)ee * (D * EV);
 #pragma unroll
         for (int b = 0; b < D; ++b)
 #pragma unroll
             for (int v = 0; v < R; ++v) {
-                const int64_t idx = (((ee * D + b) * R + v) * NT + j) * NS + ss;
-                q[b * R + v] = make_state<T>(base[idx], JVP ? dbase[idx] : CT(0));
+                const int off = (b * R + v) * NPE + rr;
+                if constexpr (JVP) q[b * R + v] = make_state<T>((Qp + base)[off], (dQp + base)[off]);
+                else q[b * R + v] = (Qp + base)[off];
             }
     };
 
-    static_for<0, D>([&](auto A) {
-        constexpr int a = decltype(A)::value;
-        constexpr int stride = ipow(N1, a);
-        const int ia = node_coord<D>(s, N1, a);
-        // (1) total flux along a at the own node, every time node -> LDS
-        if (active) {
+    // (0) tables and neighbour elements to LDS; own states -> tile; own
+    //     gradient (NS)
+    if (tid < N1 * N1) sD[tid] = CT(sg.Dx[tid]);
+    if (tid < NT * NT) sDt[tid] = CT(sg.Dt[tid]);
+    if (tid < NT) swt[tid] = CT(sg.wt[tid]);
+    if (tid < EPB * 2 * D) {
+        const int ee = e0 + tid / (2 * D), a = (tid >> 1) % D;
+        nbr[tid] = ee < sg.E ? neighbour(sg, ee, a, tid & 1) : 0;
+    }
+    T u[TPT][R];
+    T q[NSV ? TPT : 1][NSV ? D * R : 1];
+    if (active) {
 #pragma unroll
-            for (int j = 0; j < NT; ++j) {
-                T q[VISC ? D * R : 1];
-                if constexpr (VISC) load_q(Qp, dQp, e, s, j, q);
-                T f[R];
-                total_flux<EQ, D, T>(a, u[j], q, f, P);
+        for (int jj = 0; jj < TPT; ++jj) {
+            load_state(e, r0 + jj * NS, u[jj]);
+            if constexpr (NSV) load_grad(e, r0 + jj * NS, q[jj]);
+        }
 #pragma unroll
-                for (int v = 0; v < R; ++v) buf[((el * NT + j) * R + v) * NS + s] = part(f[v]);
+        for (int jj = 0; jj < TPT; ++jj)
+#pragma unroll
+            for (int v = 0; v < R; ++v) {
+                tile[v * NN + nd0 + jj * NS] = value(u[jj][v]);
+                if constexpr (JVP) tile[(R + v) * NN + nd0 + jj * NS] = part(u[jj][v]);
+            }
+    } else {
+#pragma unroll
+        for (int jj = 0; jj < TPT; ++jj)
+#pragma unroll
+            for (int v = 0; v < R; ++v) u[jj][v] = make_state<T>(CT(1), CT(0));
+    }
+    if constexpr (AD) __syncthreads();
+
+    // (1) total flux along every axis at the own nodes -> buf
+    if (active) {
+        if constexpr (AD) {
+            // own lifted gradient: D contraction, then the lift with the
+            // neighbour's face value (u_hat = {u})
+            const CT nu = CT(P.nu);
+            CT unb[D][TPT];
+            static_for<0, D>([&](auto A) {
+                constexpr int a = decltype(A)::value;
+                const int ia = ic[a];
+                if (ia == 0 || ia == N1 - 1) {
+                    const bool right = ia == N1 - 1;
+                    const gptr<UT> Un = Up + (int64_t)nbr[(el * D + a) * 2 + right] * EV +
+                                        (r0 + ((right ? 0 : N1 - 1) - ia) * ipow(N1, a));
+#pragma unroll
+                    for (int jj = 0; jj < TPT; ++jj) unb[a][jj] = CT(Un[jj * NS]);
+                }
+            });
+            static_for<0, D>([&](auto A) {
+                constexpr int a = decltype(A)::value;
+                constexpr int stride = ipow(N1, a);
+                const int ia = ic[a];
+                CT Dr[N1];
+#pragma unroll
+                for (int k = 0; k < N1; ++k) Dr[k] = sD[ia * N1 + k];
+                const CT J = CT(sg.rh[a]), av = CT(P.a[a]);
+                const bool face = ia == 0 || ia == N1 - 1;
+                const CT lw = ia == N1 - 1 ? iw0 : -iw0;
+#pragma unroll
+                for (int jj = 0; jj < TPT; ++jj) {
+                    const CT* ln = tile + nd0 + jj * NS - ia * stride;
+                    CT g = Dr[0] * ln[0];
+#pragma unroll
+                    for (int k = 1; k < N1; ++k) g += Dr[k] * ln[k * stride];
+                    if (face) g += lw * (CT(0.5) * (u[jj][0] + unb[a][jj]) - u[jj][0]);
+                    buf[a * NN + nd0 + jj * NS] = u[jj][0] * av - (J * g) * nu;
+                }
+            });
+        } else {
+#pragma unroll
+            for (int jj = 0; jj < TPT; ++jj) {
+                const typename F::Prim w = F::prim(u[jj], P);
+                typename F::Visc z;
+                if constexpr (NSV) z = F::visc_state(w, q[jj], P);
+                static_for<0, D>([&](auto A) {
+                    constexpr int a = decltype(A)::value;
+                    T f[R];
+                    F::conv(a, u[jj], w, f, P);
+                    if constexpr (NSV) F::sub_visc(a, w, z, f, P);
+#pragma unroll
+                    for (int v = 0; v < R; ++v) buf[(a * R + v) * NN + nd0 + jj * NS] = part(f[v]);
+                });
             }
         }
-        __syncthreads();
-        if (active) {
-            const CT J = CT(sg.rh[a]);
-            // (2) volume term -(2/h_a) sum_k D_{ia,k} f_k along the line
+    }
+    __syncthreads();
+
+    // (2) volume term -(2/h_a) sum_k D_{ia,k} f_k along each axis
+    CT acc[TPT][R];
+#pragma unroll
+    for (int jj = 0; jj < TPT; ++jj)
+#pragma unroll
+        for (int v = 0; v < R; ++v) acc[jj][v] = CT(0);
+    if (active) {
+        static_for<0, D>([&](auto A) {
+            constexpr int a = decltype(A)::value;
+            constexpr int stride = ipow(N1, a);
+            const int ia = ic[a];
             CT Drow[N1];
 #pragma unroll
-            for (int k = 0; k < N1; ++k) Drow[k] = CT(sg.Dx[ia * N1 + k]);
-            const int s0 = s - ia * stride;
+            for (int k = 0; k < N1; ++k) Drow[k] = sD[ia * N1 + k];
+            const CT J = CT(sg.rh[a]);
 #pragma unroll
-            for (int j = 0; j < NT; ++j)
+            for (int jj = 0; jj < TPT; ++jj)
 #pragma unroll
                 for (int v = 0; v < R; ++v) {
-                    const CT* line = buf + ((el * NT + j) * R + v) * NS + s0;
-                    CT sum = Drow[0] * line[0];
+                    const CT* ln = buf + (a * R + v) * NN + nd0 + jj * NS - ia * stride;
+                    CT sum = Drow[0] * ln[0];
 #pragma unroll
-                    for (int k = 1; k < N1; ++k) sum += Drow[k] * line[k * stride];
-                    acc[j][v] -= J * sum;
+                    for (int k = 1; k < N1; ++k) sum += Drow[k] * ln[k * stride];
+                    acc[jj][v] -= J * sum;
                 }
-            // (3) interface term -(2/h_a) M^-1 B (H - f) on the face nodes
-            if (ia == 0 || ia == N1 - 1) {
-                const int side = (ia == N1 - 1) ? 1 : -1;
-                const int ca = ec[a] + side;
-                const int cw = ca < 0 ? ca + sg.K[a] : (ca >= sg.K[a] ? ca - sg.K[a] : ca);
-                const int64_t en = e + (int64_t)(cw - ec[a]) * es[a];
-                const int sn = s + ((side > 0 ? 0 : N1 - 1) - ia) * stride;
-                const CT wl = J / CT(sg.wx[0]);
+        });
+    }
+    __syncthreads();
+
+    // (3) face points: H - f into the flux slot of the face node.  The slot
+    // of (axis, face node) belongs to exactly one face point.  Face points
+    // are numbered axis-major, so a wavefront mostly works on one axis.
+    for (int p = tid; p < SH::NFP; p += BS) {
+        constexpr int PER_AX = EPB * 2 * NJ * NF;
+        const int a = (int)((unsigned)p / PER_AX);
+        int rem = p - a * PER_AX;
+        const int pel = (int)((unsigned)rem / (2 * NJ * NF));
+        rem -= pel * (2 * NJ * NF);
+        const bool right = rem >= NJ * NF;
+        rem -= right ? NJ * NF : 0;
+        const int jg = (int)((unsigned)rem / NF);
+        const int f = rem - jg * NF;
+        if (e0 + pel >= sg.E) continue;
+        static_for<0, D>([&](auto A) {
+            constexpr int ax = decltype(A)::value;
+            if (ax != a) return;
+            constexpr int stride = ipow(N1, ax);
+            const int so = face_node<D, N1, ax>(f, right);
+            const int rn0 = jg * TPT * NS + so + (right ? -(N1 - 1) : (N1 - 1)) * stride;   // neighbour node
+            const int to0 = pel * NPE + jg * TPT * NS + so;                                  // own block node
+            const int en = nbr[(pel * D + ax) * 2 + right];
+            if constexpr (AD) {
+                // neighbour's lifted normal derivative at its face node, from
+                // its line of nodes normal to the face (all TPT time nodes),
+                // taken from the face node inwards: line[.][0] is the trace
+                const int inb = right ? 0 : N1 - 1;
+                const int step = right ? stride : -stride;
+                const gptr<UT> lb = Up + (int64_t)en * EV + rn0;
+                CT line[TPT][N1];
 #pragma unroll
-                for (int j = 0; j < NT; ++j) {
-                    T un[R];
+                for (int jj = 0; jj < TPT; ++jj)
+#pragma unroll
+                    for (int k = 0; k < N1; ++k) line[jj][k] = CT(lb[jj * NS + k * step]);
+                CT Dn[N1];
+#pragma unroll
+                for (int k = 0; k < N1; ++k) Dn[k] = sD[inb * N1 + (right ? k : N1 - 1 - k)];
+                const CT lw = right ? -iw0 : iw0;
+                const CT lam = CT(fabs(P.a[ax])), av = CT(P.a[ax]), J = CT(sg.rh[ax]), nu = CT(P.nu);
+#pragma unroll
+                for (int jj = 0; jj < TPT; ++jj) {
+                    const CT uo = tile[to0 + jj * NS];
+                    const CT unv = line[jj][0];
+                    CT gn = Dn[0] * line[jj][0];
+#pragma unroll
+                    for (int k = 1; k < N1; ++k) gn += Dn[k] * line[jj][k];
+                    gn += lw * (CT(0.5) * (unv + uo) - unv);
+                    const CT fn = unv * av - (J * gn) * nu;
+                    const CT jump = right ? uo - unv : unv - uo;
+                    CT& slot = buf[ax * NN + to0 + jj * NS];
+                    slot = CT(0.5) * (fn - slot) + (CT(0.5) * lam) * jump;
+                }
+            } else {
+#pragma unroll
+                for (int jj = 0; jj < TPT; ++jj) {
+                    const int to = to0 + jj * NS;
+                    T uo[R], un[R], fn[R];
 #pragma unroll
                     for (int v = 0; v < R; ++v) {
-                        const int64_t idx = ((en * R + v) * NT + j) * NS + sn;
-                        un[v] = make_state<T>(CT(Up[idx]), JVP ? CT(Vp[idx]) : CT(0));
+                        if constexpr (JVP) uo[v] = make_state<T>(tile[v * NN + to], tile[(R + v) * NN + to]);
+                        else uo[v] = tile[v * NN + to];
                     }
-                    T qo[VISC ? D * R : 1], qn[VISC ? D * R : 1];
-                    if constexpr (VISC) {
-                        load_q(Qp, dQp, e, s, j, qo);
-                        load_q(Qp, dQp, en, sn, j, qn);
+                    load_state(en, rn0 + jj * NS, un);
+                    const typename F::Prim w = F::prim(un, P);
+                    F::conv(ax, un, w, fn, P);
+                    if constexpr (NSV) {
+                        T qn[D * R];
+                        load_grad(en, rn0 + jj * NS, qn);
+                        const typename F::Visc z = F::visc_state(w, qn, P);
+                        F::sub_visc(ax, w, z, fn, P);
                     }
-                    T H[R];
-                    if (side > 0) num_flux<EQ, D, T>(a, u[j], un, qo, qn, H, P);
-                    else          num_flux<EQ, D, T>(a, un, u[j], qn, qo, H, P);
+                    const T lo = F::speed(ax, uo, P), ln = F::speed(ax, un, P);
+                    const T lam = right ? larger(lo, ln) : larger(ln, lo);
 #pragma unroll
                     for (int v = 0; v < R; ++v) {
-                        const CT fo = buf[((el * NT + j) * R + v) * NS + s];
-                        const CT d = part(H[v]) - fo;
-                        acc[j][v] -= (side > 0 ? wl : -wl) * d;
+                        const T jump = right ? uo[v] - un[v] : un[v] - uo[v];      // u_L - u_R
+                        const CT pen = part((CT(0.5) * lam) * jump);
+                        CT& slot = buf[(ax * R + v) * NN + to];
+                        slot = CT(0.5) * (part(fn[v]) - slot) + pen;
                     }
                 }
             }
-        }
-        __syncthreads();
-    });
+        });
+    }
+    __syncthreads();
 
-    // (4) DG in time: R_j = w_j (dt/2 F_j - (D_tau U)_j) - delta_{j1} (u^1 - u^n)
+    // (4) lifted surface terms and DG in time:
+    //   R_j = w_j (dt/2 F_j - (D_tau U)_j) - delta_{j1} (u^1 - u^n)
     if (active) {
+        static_for<0, D>([&](auto A) {
+            constexpr int a = decltype(A)::value;
+            const int ia = ic[a];
+            if (ia == 0 || ia == N1 - 1) {
+                const CT wl = ia == N1 - 1 ? CT(sg.rh[a]) * iw0 : -(CT(sg.rh[a]) * iw0);
+#pragma unroll
+                for (int jj = 0; jj < TPT; ++jj)
+#pragma unroll
+                    for (int v = 0; v < R; ++v) acc[jj][v] -= wl * buf[(a * R + v) * NN + nd0 + jj * NS];
+            }
+        });
         const CT hdt = CT(0.5 * sg.dt);
+        const gptr<double> oe = out + (int64_t)e * EV + r0;
 #pragma unroll
-        for (int v = 0; v < R; ++v) {
-            CT up = CT(0);
-            if (!JVP && upv) up = CT(upv[(e * R + v) * NS + s]);
+        for (int jj = 0; jj < TPT; ++jj) {
+            const int j = jt * TPT + jj;
 #pragma unroll
-            for (int j = 0; j < NT; ++j) {
-                CT dtu = CT(sg.Dt[j * NT]) * part(u[0][v]);
+            for (int v = 0; v < R; ++v) {
+                // the stored part at time node k of this spatial node
+                auto tv = [&](int k) -> CT {
+                    if constexpr (TPT == NT) return part(u[k][v]);
+                    else return tile[(PL + v) * NN + el * NPE + k * NS + s];
+                };
+                CT dtu = sDt[j * NT] * tv(0);
 #pragma unroll
-                for (int k = 1; k < NT; ++k) dtu += CT(sg.Dt[j * NT + k]) * part(u[k][v]);
-                CT r = CT(sg.wt[j]) * (hdt * acc[j][v] - dtu);
-                if (j == 0) r -= part(u[0][v]) - up;
-                out[((e * R + v) * NT + j) * NS + s] = double(r);
+                for (int k = 1; k < NT; ++k) dtu += sDt[j * NT + k] * tv(k);
+                CT res = swt[j] * (hdt * acc[jj][v] - dtu);
+                if (j == 0) {
+                    const CT up = (!JVP && upv) ? CT(upv[(int64_t)e * (R * NS) + v * NS + s]) : CT(0);
+                    res -= tv(0) - up;
+                }
+                oe[v * NPE + jj * NS] = double(res);
             }
         }
     }
@@ -249,274 +557,97 @@ __global__ __launch_bounds__(BLOCK) void k_op(const OpSeg* __restrict__ segs, in
 // ---------------------------------------------------------------------------
 // BR1 lifted gradient of the conservative variables (strong form):
 //   q_b = (2/h_b) [ sum_k D_{i_b,k} u_k + M^-1 B (u_hat - u) ],  u_hat = {u},
-// for every time node (no viscous flux in time).  Output layout
-//   Q[((e * D + b) * R + v) * Nt + j) * ns + s], type CT.
+// for every time node (no viscous flux in time).  Same block shape as k_op.
+// Output layout Q[((e * D + b) * R + v) * Nt + j) * ns + s], type CT.
 // ---------------------------------------------------------------------------
 template <int D, int N1, int NT, int R, class CT, class UT>
-__global__ __launch_bounds__(BLOCK) void k_grad(const OpSeg* __restrict__ segs, int nseg, int G) {
-    constexpr int NS = ipow(N1, D);
-    constexpr int EPB = BLOCK / NS > 0 ? BLOCK / NS : 1;
-    __shared__ CT buf[EPB * NT * R * NS];
+__global__ __launch_bounds__((Shape<D, N1, NT, 1>::BS)) void k_grad(const OpSeg* __restrict__ segs, int nseg, int G) {
+    using SH = Shape<D, N1, NT, 1>;
+    constexpr int NS = SH::NS, NPE = SH::NPE, EPB = SH::EPB, B = SH::B;
+    constexpr int EV = R * NPE;
+    __shared__ CT tile[R * B];
+    __shared__ int nbr[EPB * 2 * D];
+    __shared__ CT sD[N1 * N1];
     const int L = xcd_remap(blockIdx.x, G);
     const OpSeg& sg = segs[find_seg(segs, nseg, L)];
-    if (sg.skip && *sg.skip) return;
+    if (sg.skip && *(const gptr<const int>)sg.skip) return;
     const int tid = threadIdx.x;
-    const int el = tid / NS;
-    const int s = tid - el * NS;
-    const int64_t e = (int64_t)(L - sg.blk0) * EPB + el;
-    const bool active = (el < EPB) && (e < sg.E);
+    const int el = (int)((unsigned)tid / NPE);
+    const int r = tid - el * NPE;
+    const int s = (int)((unsigned)r % NS);
+    const int e0 = (L - sg.blk0) * EPB;
+    const int e = e0 + el;
+    const bool active = (tid < B) && (e < sg.E);
     const gptr<UT> __restrict__ Up = resolve<UT>(sg.U);
     const gptr<CT> __restrict__ Qp = resolve<CT>(sg.out);
-    const int ec[3] = {(int)(e % sg.K[0]), (int)((e / sg.K[0]) % sg.K[1]), (int)(e / ((int64_t)sg.K[0] * sg.K[1]))};
-    const int64_t es[3] = {1, sg.K[0], (int64_t)sg.K[0] * sg.K[1]};
 
+    if (tid < N1 * N1) sD[tid] = CT(sg.Dx[tid]);
+    if (tid < EPB * 2 * D) {
+        const int ee = e0 + tid / (2 * D), a = (tid >> 1) % D;
+        nbr[tid] = ee < sg.E ? neighbour(sg, ee, a, tid & 1) : 0;
+    }
+    CT u[R];
     if (active) {
+        const gptr<UT> Ue = Up + (int64_t)e * EV;
 #pragma unroll
-        for (int v = 0; v < R; ++v)
-#pragma unroll
-            for (int j = 0; j < NT; ++j)
-                buf[((el * NT + j) * R + v) * NS + s] = CT(Up[((e * R + v) * NT + j) * NS + s]);
+        for (int v = 0; v < R; ++v) {
+            u[v] = CT(Ue[v * NPE + r]);
+            tile[v * B + tid] = u[v];
+        }
     }
     __syncthreads();
     if (!active) return;
-    static_for<0, D>([&](auto B) {
-        constexpr int b = decltype(B)::value;
+    const CT wl = CT(1) / CT(sg.wx[0]);
+    const gptr<CT> Qe = Qp + (int64_t)e * (D * EV);
+    static_for<0, D>([&](auto B_) {
+        constexpr int b = decltype(B_)::value;
         constexpr int stride = ipow(N1, b);
-        const int ib = node_coord<D>(s, N1, b);
-        const int s0 = s - ib * stride;
-        const CT J = CT(sg.rh[b]);
+        const int ib = coord<N1, b>(s);
+        const bool face = (ib == 0 || ib == N1 - 1);
+        CT un[R];
+        if (face) {
+            const bool right = ib == N1 - 1;
+            const gptr<UT> Un = Up + (int64_t)nbr[(el * D + b) * 2 + right] * EV;
+            const int rn = r + ((right ? 0 : N1 - 1) - ib) * stride;
+#pragma unroll
+            for (int v = 0; v < R; ++v) un[v] = CT(Un[v * NPE + rn]);
+        }
         CT Drow[N1];
 #pragma unroll
-        for (int k = 0; k < N1; ++k) Drow[k] = CT(sg.Dx[ib * N1 + k]);
-        const bool face = (ib == 0 || ib == N1 - 1);
-        const int side = (ib == N1 - 1) ? 1 : -1;
-        int64_t en = e;
-        int sn = s;
-        if (face) {
-            const int ca = ec[b] + side;
-            const int cw = ca < 0 ? ca + sg.K[b] : (ca >= sg.K[b] ? ca - sg.K[b] : ca);
-            en = e + (int64_t)(cw - ec[b]) * es[b];
-            sn = s + ((side > 0 ? 0 : N1 - 1) - ib) * stride;
-        }
-        const CT wl = CT(1) / CT(sg.wx[0]);
+        for (int k = 0; k < N1; ++k) Drow[k] = sD[ib * N1 + k];
+        const CT J = CT(sg.rh[b]);
 #pragma unroll
-        for (int v = 0; v < R; ++v)
+        for (int v = 0; v < R; ++v) {
+            const CT* ln = tile + v * B + tid - ib * stride;
+            CT g = Drow[0] * ln[0];
 #pragma unroll
-            for (int j = 0; j < NT; ++j) {
-                const CT* line = buf + ((el * NT + j) * R + v) * NS + s0;
-                CT g = Drow[0] * line[0];
-#pragma unroll
-                for (int k = 1; k < N1; ++k) g += Drow[k] * line[k * stride];
-                if (face) {
-                    const CT uo = line[ib * stride];
-                    const CT un = CT(Up[((en * R + v) * NT + j) * NS + sn]);
-                    const CT uh = CT(0.5) * (uo + un);
-                    g += (side > 0 ? wl : -wl) * (uh - uo);
-                }
-                Qp[(((e * D + b) * R + v) * NT + j) * NS + s] = J * g;
+            for (int k = 1; k < N1; ++k) g += Drow[k] * ln[k * stride];
+            if (face) {
+                const CT uh = CT(0.5) * (u[v] + un[v]);
+                g += (ib == N1 - 1 ? wl : -wl) * (uh - u[v]);
             }
+            Qe[(b * R + v) * NPE + r] = J * g;
+        }
     });
-}
-
-// ---------------------------------------------------------------------------
-// Advection-diffusion with the BR1 viscous flux in a single kernel.
-// Fv = nu grad u, so the central viscous flux through a face needs only the
-// neighbour's NORMAL lifted derivative at the face node, which depends on the
-// neighbour's line of nodes normal to the face and on this element's face
-// value.  Each face thread reads that line (L2) together with its own state,
-// so the lifted gradient never goes through HBM.  Same arithmetic as k_grad
-// followed by k_op; JVP of this linear operator = the operator applied to v
-// with u_prev = 0.
-// ---------------------------------------------------------------------------
-template <int D, int N1, int NT, class CT, class UT>
-__global__ __launch_bounds__(BLOCK) void k_advdiff(const OpSeg* __restrict__ segs, int nseg, int G) {
-    constexpr int NS = ipow(N1, D);
-    constexpr int EPB = BLOCK / NS > 0 ? BLOCK / NS : 1;
-    __shared__ CT tile[EPB * NT * NS];
-    __shared__ CT fl[EPB * NT * NS];
-
-    const int L = xcd_remap(blockIdx.x, G);
-    const OpSeg& sg = segs[find_seg(segs, nseg, L)];
-    if (sg.skip && *sg.skip) return;
-    const EqParams& P = sg.P;
-    const int tid = threadIdx.x;
-    const int el = tid / NS;
-    const int s = tid - el * NS;
-    const int64_t e = (int64_t)(L - sg.blk0) * EPB + el;
-    const bool active = (el < EPB) && (e < sg.E);
-    const gptr<UT> __restrict__ Up = resolve<UT>(sg.U);
-    const gptr<double> __restrict__ out = resolve<double>(sg.out);
-    const gptr<const double> __restrict__ upv = (gptr<const double>)sg.uprev;
-    const int ec[3] = {(int)(e % sg.K[0]), (int)((e / sg.K[0]) % sg.K[1]), (int)(e / ((int64_t)sg.K[0] * sg.K[1]))};
-    const int64_t es[3] = {1, sg.K[0], (int64_t)sg.K[0] * sg.K[1]};
-    const CT nu = CT(P.nu);
-    const CT w0 = CT(sg.wx[0]);
-
-    // own values and, on every face axis, the neighbour's line normal to it
-    CT u[NT];
-    CT line[D][N1][NT];
-    int side[D];
-#pragma unroll
-    for (int a = 0; a < D; ++a) side[a] = 0;
-    if (active) {
-#pragma unroll
-        for (int j = 0; j < NT; ++j) u[j] = CT(Up[(e * NT + j) * NS + s]);
-        static_for<0, D>([&](auto A) {
-            constexpr int a = decltype(A)::value;
-            constexpr int stride = ipow(N1, a);
-            const int ia = node_coord<D>(s, N1, a);
-            if (ia == 0 || ia == N1 - 1) {
-                side[a] = (ia == N1 - 1) ? 1 : -1;
-                const int ca = ec[a] + side[a];
-                const int cw = ca < 0 ? ca + sg.K[a] : (ca >= sg.K[a] ? ca - sg.K[a] : ca);
-                const int64_t en = e + (int64_t)(cw - ec[a]) * es[a];
-                const int s0 = s - ia * stride;
-#pragma unroll
-                for (int k = 0; k < N1; ++k)
-#pragma unroll
-                    for (int j = 0; j < NT; ++j) line[a][k][j] = CT(Up[(en * NT + j) * NS + s0 + k * stride]);
-            }
-        });
-#pragma unroll
-        for (int j = 0; j < NT; ++j) tile[(el * NT + j) * NS + s] = u[j];
-    } else {
-#pragma unroll
-        for (int j = 0; j < NT; ++j) u[j] = CT(0);
-    }
-    __syncthreads();
-
-    // own lifted gradient q[b][j] (central u-hat on faces)
-    CT q[D][NT];
-    if (active) {
-        static_for<0, D>([&](auto B) {
-            constexpr int b = decltype(B)::value;
-            constexpr int stride = ipow(N1, b);
-            const int ib = node_coord<D>(s, N1, b);
-            const int s0 = s - ib * stride;
-            CT Drow[N1];
-#pragma unroll
-            for (int k = 0; k < N1; ++k) Drow[k] = CT(sg.Dx[ib * N1 + k]);
-#pragma unroll
-            for (int j = 0; j < NT; ++j) {
-                const CT* ln = tile + (el * NT + j) * NS + s0;
-                CT g = Drow[0] * ln[0];
-#pragma unroll
-                for (int k = 1; k < N1; ++k) g += Drow[k] * ln[k * stride];
-                if (side[b] != 0) {
-                    const CT un = side[b] > 0 ? line[b][0][j] : line[b][N1 - 1][j];
-                    const CT uh = CT(0.5) * (u[j] + un);
-                    g += (side[b] > 0 ? CT(1) : CT(-1)) / w0 * (uh - u[j]);
-                }
-                q[b][j] = CT(sg.rh[b]) * g;
-            }
-        });
-    }
-
-    CT acc[NT];
-#pragma unroll
-    for (int j = 0; j < NT; ++j) acc[j] = CT(0);
-    static_for<0, D>([&](auto A) {
-        constexpr int a = decltype(A)::value;
-        constexpr int stride = ipow(N1, a);
-        const int ia = node_coord<D>(s, N1, a);
-        const CT av = CT(P.a[a]);
-        if (active) {
-#pragma unroll
-            for (int j = 0; j < NT; ++j) fl[(el * NT + j) * NS + s] = u[j] * av - q[a][j] * nu;
-        }
-        __syncthreads();
-        if (active) {
-            const CT J = CT(sg.rh[a]);
-            CT Drow[N1];
-#pragma unroll
-            for (int k = 0; k < N1; ++k) Drow[k] = CT(sg.Dx[ia * N1 + k]);
-            const int s0 = s - ia * stride;
-#pragma unroll
-            for (int j = 0; j < NT; ++j) {
-                const CT* ln = fl + (el * NT + j) * NS + s0;
-                CT sum = Drow[0] * ln[0];
-#pragma unroll
-                for (int k = 1; k < N1; ++k) sum += Drow[k] * ln[k * stride];
-                acc[j] -= J * sum;
-            }
-            if (side[a] != 0) {
-                // neighbour's normal derivative at its face node: its D row at
-                // that node plus its own lift with the same u-hat
-                const int inb = side[a] > 0 ? 0 : N1 - 1;
-                CT Dn[N1];
-#pragma unroll
-                for (int k = 0; k < N1; ++k) Dn[k] = CT(sg.Dx[inb * N1 + k]);
-                const CT lam = CT(fabs(P.a[a]));
-                const CT wl = J / w0;
-#pragma unroll
-                for (int j = 0; j < NT; ++j) {
-                    const CT un = side[a] > 0 ? line[a][0][j] : line[a][N1 - 1][j];
-                    CT gn = Dn[0] * line[a][0][j];
-#pragma unroll
-                    for (int k = 1; k < N1; ++k) gn += Dn[k] * line[a][k][j];
-                    const CT uh = CT(0.5) * (un + u[j]);
-                    gn += (side[a] > 0 ? CT(-1) : CT(1)) / w0 * (uh - un);
-                    const CT qn = J * gn;
-                    const CT uL = side[a] > 0 ? u[j] : un, uR = side[a] > 0 ? un : u[j];
-                    const CT qL = side[a] > 0 ? q[a][j] : qn, qR = side[a] > 0 ? qn : q[a][j];
-                    const CT fL = uL * av, fR = uR * av;
-                    CT H = CT(0.5) * (fL + fR) + (CT(0.5) * lam) * (uL - uR);
-                    H = H - CT(0.5) * (qL * nu + qR * nu);
-                    const CT fo = fl[(el * NT + j) * NS + s];
-                    acc[j] -= (side[a] > 0 ? wl : -wl) * (H - fo);
-                }
-            }
-        }
-        __syncthreads();
-    });
-
-    if (active) {
-        const CT hdt = CT(0.5 * sg.dt);
-        const CT up = upv ? CT(upv[e * NS + s]) : CT(0);
-#pragma unroll
-        for (int j = 0; j < NT; ++j) {
-            CT dtu = CT(sg.Dt[j * NT]) * u[0];
-#pragma unroll
-            for (int k = 1; k < NT; ++k) dtu += CT(sg.Dt[j * NT + k]) * u[k];
-            CT r = CT(sg.wt[j]) * (hdt * acc[j] - dtu);
-            if (j == 0) r -= u[0] - up;
-            out[(e * NT + j) * NS + s] = double(r);
-        }
-    }
 }
 
 // ---------------------------------------------------------------------------
 // host launchers
 // ---------------------------------------------------------------------------
-template <int D, int N1>
-constexpr int op_epb() {
-    return BLOCK / ipow(N1, D) > 0 ? BLOCK / ipow(N1, D) : 1;
-}
-
 template <int EQ, int D, int N1, int NT, class CT, class UT, bool JVP>
 void launch_op(const OpSeg* segs, int nseg, int G, hipStream_t st) {
-    launch_k(k_op<EQ, D, N1, NT, CT, UT, JVP>, dim3(G), dim3(BLOCK), st, segs, nseg, G);
-}
-template <int D, int N1, int NT, class CT, class UT>
-void launch_advdiff(const OpSeg* segs, int nseg, int G, hipStream_t st) {
-    launch_k(k_advdiff<D, N1, NT, CT, UT>, dim3(G), dim3(BLOCK), st, segs, nseg, G);
+    launch_k(k_op<EQ, D, N1, NT, CT, UT, JVP>, dim3(G), dim3(Shape<D, N1, NT, tpt_of(EQ, NT)>::BS), st, segs, nseg, G);
 }
 template <int D, int N1, int NT, int R, class CT, class UT>
 void launch_grad(const OpSeg* segs, int nseg, int G, hipStream_t st) {
-    launch_k(k_grad<D, N1, NT, R, CT, UT>, dim3(G), dim3(BLOCK), st, segs, nseg, G);
+    launch_k(k_grad<D, N1, NT, R, CT, UT>, dim3(G), dim3(Shape<D, N1, NT, 1>::BS), st, segs, nseg, G);
 }
 
 template <int EQ, int D, int N1, int NT>
 OpTable make_table() {
     constexpr int R = nvars_of(EQ, D);
     OpTable t{};
-    t.eq = EQ; t.dim = D; t.n1 = N1; t.nt = NT; t.epb = op_epb<D, N1>();
-    if constexpr (EQ == EQ_ADVDIFF) {
-        // single-kernel BR1: no gradient pass, no gradient buffers
-        t.res64 = launch_advdiff<D, N1, NT, double, double>;
-        t.lin32 = launch_advdiff<D, N1, NT, float, double>;
-        return t;
-    }
+    t.eq = EQ; t.dim = D; t.n1 = N1; t.nt = NT; t.epb = Shape<D, N1, NT, tpt_of(EQ, NT)>::EPB;
     t.res64 = launch_op<EQ, D, N1, NT, double, double, false>;
     if constexpr (linear_eq(EQ)) {
         t.lin32 = launch_op<EQ, D, N1, NT, float, double, false>;
@@ -524,7 +655,7 @@ OpTable make_table() {
         t.jvp64 = launch_op<EQ, D, N1, NT, double, double, true>;
         t.jvp32 = launch_op<EQ, D, N1, NT, float, float, true>;
     }
-    if constexpr (viscous_eq(EQ)) {
+    if constexpr (EQ == EQ_NS) {
         t.grad64 = launch_grad<D, N1, NT, R, double, double>;
         t.grad32 = launch_grad<D, N1, NT, R, float, float>;
         t.grad64to32 = launch_grad<D, N1, NT, R, float, double>;
