@@ -37,7 +37,8 @@ void launch_k(K kernel, dim3 grid, dim3 block, hipStream_t st, A... args) {
 
 constexpr int MMAX = 32;           // largest GMRES restart length
 constexpr int BLOCK = 256;         // threads per block of the operator kernels
-constexpr int VBLOCK = 512;        // threads per block of the Krylov vector kernels
+constexpr int VBLOCK = 256;        // threads per block of the Krylov vector kernels
+constexpr int VMAXBLK = 512;       // most blocks of one slab in a Krylov vector launch
 
 enum EqKind { EQ_ADV = 1, EQ_ADVDIFF = 2, EQ_BURGERS = 3, EQ_EULER = 4, EQ_NS = 5 };
 
@@ -83,11 +84,31 @@ template <class S> DI Dual<S> operator/(S a, Dual<S> b) {
     return {q, -(q * b.d) * r};
 }
 
+// 1/x: the hardware reciprocal estimate refined by two Newton-Raphson steps
+// r <- r + r (1 - x r) (each step squares the relative error; the result is
+// within a few ulp of 1/x for normal x, and non-finite for x = 0 or NaN).
+DI double recip_(double x) {
+    double r = __builtin_amdgcn_rcp(x);
+    double e = __builtin_fma(-x, r, 1.0);
+    r = __builtin_fma(r, e, r);
+    e = __builtin_fma(-x, r, 1.0);
+    return __builtin_fma(r, e, r);
+}
+DI float recip_(float x) {
+    float r = __builtin_amdgcn_rcpf(x);
+    const float e = __builtin_fmaf(-x, r, 1.0f);
+    return __builtin_fmaf(r, e, r);
+}
+template <class S> DI Dual<S> recip_(Dual<S> a) {
+    const S r = recip_(a.v);
+    return {r, -(a.d * r) * r};
+}
+
 DI double sqrt_(double x) { return sqrt(x); }
 DI float sqrt_(float x) { return sqrtf(x); }
 template <class S> DI Dual<S> sqrt_(Dual<S> a) {
     S s = sqrt_(a.v);
-    return {s, a.d / (S(2) * s)};
+    return {s, a.d * (S(0.5) * recip_(s))};
 }
 DI double value(double x) { return x; }
 DI float value(float x) { return x; }
@@ -269,6 +290,8 @@ struct OpSeg {
     const int* skip;     // skip the segment when *skip != 0 (may be null)
     int K[3];
     int E;
+    unsigned dm[2];      // e / K[a] = (e * dm[a]) >> ds[a] for e < 2^31 (a = 0, 1)
+    int ds[2];
     double rh[3];        // 2 / h_a
     double dt;
     int blk0;            // first logical block
@@ -305,13 +328,13 @@ struct VecSeg {
 };
 
 // blocks of one slab in a vector launch: about 2 elements per thread, at
-// most 256 blocks (one per CU); larger slabs loop (grid stride).  Consumers
+// most VMAXBLK blocks; larger slabs loop (grid stride).  Consumers
 // reduce the per-block partial tables redundantly in every block, so the
 // block count is kept at what the bandwidth needs.
 __host__ __device__ inline int vec_blocks(int64_t n) {
-    int64_t b = (n + 1023) / 1024;
+    int64_t b = (n + 2 * VBLOCK - 1) / (2 * VBLOCK);
     if (b < 1) b = 1;
-    if (b > 256) b = 256;
+    if (b > VMAXBLK) b = VMAXBLK;
     return (int)b;
 }
 

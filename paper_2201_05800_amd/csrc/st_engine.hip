@@ -150,6 +150,15 @@ OpSeg base_opseg(const Problem& pb, double dt) {
         s.rh[a] = 2.0 / pb.h[a];
     }
     s.E = (int)pb.E;
+    // division by an invariant integer (Granlund-Montgomery): with 2^k >= d
+    // and M = ceil(2^(31+k) / d), floor(n / d) = (n M) >> (31 + k) for n < 2^31
+    for (int a = 0; a < 2; ++a) {
+        const uint64_t d = (uint64_t)pb.K[a];
+        int k = 0;
+        while (((uint64_t)1 << k) < d) ++k;
+        s.dm[a] = (unsigned)((((uint64_t)1 << (31 + k)) + d - 1) / d);
+        s.ds[a] = 31 + k;
+    }
     s.P = pb.P;
     s.dt = dt;
     s.blk0 = 0;

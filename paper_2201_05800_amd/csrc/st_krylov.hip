@@ -77,7 +77,7 @@ DI void block_sums(const double (&acc)[NV], double* smem, double* out) {
     __syncthreads();
 }
 
-// Column sums of a partial table P[b * ld + c] (b < nb <= 256, c < NVAL), in
+// Column sums of a partial table P[b * ld + c] (b < nb <= VMAXBLK, c < NVAL), in
 // the same fixed order in every block; result in s_out[0..NVAL).  Every
 // thread issues all of its loads before adding (they come from other XCDs).
 // s_tmp: VBLOCK doubles.
@@ -85,7 +85,7 @@ template <int NVAL>
 DI void reduce_table(const __attribute__((address_space(1))) double* P, int ld, int nb, double* s_tmp,
                      double* s_out) {
     constexpr int G = (VBLOCK / NVAL) < 64 ? (VBLOCK / NVAL) : 64;
-    constexpr int MAXR = (256 + G - 1) / G;
+    constexpr int MAXR = (VMAXBLK + G - 1) / G;
     const int c = threadIdx.x % NVAL, r = threadIdx.x / NVAL;
     double a = 0.0;
     if (r < G) {

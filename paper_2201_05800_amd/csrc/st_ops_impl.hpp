@@ -100,29 +100,47 @@ struct Shape {
 template <int N1, int A>
 DI int coord(int s) { return (int)(((unsigned)s / (unsigned)ipow(N1, A)) % (unsigned)N1); }
 
-// Spatial node on face (axis a, side) from its face index f: the other axes
-// in increasing order, the first one fastest.
-template <int D, int N1, int A>
-DI int face_node(int f, bool right) {
-    int s = (right ? N1 - 1 : 0) * ipow(N1, A);
-    int m = 1;
-#pragma unroll
-    for (int b = 0; b < D; ++b) {
-        if (b == A) continue;
-        s += (int)(((unsigned)f / (unsigned)m) % (unsigned)N1) * ipow(N1, b);
-        m *= N1;
-    }
-    return s;
+// Element coordinates of element e (x fastest) with the descriptor's
+// invariant-divisor constants; element indices fit 31 bits (checked when the
+// problem is made).
+struct ECoord {
+    int c[3];
+};
+DI unsigned fdiv(unsigned n, unsigned m, int sh) { return (unsigned)(((uint64_t)n * m) >> sh); }
+DI ECoord ecoord(const OpSeg& sg, int e) {
+    ECoord x;
+    const unsigned t = fdiv((unsigned)e, sg.dm[0], sg.ds[0]);
+    x.c[0] = e - (int)t * sg.K[0];
+    const unsigned z = fdiv(t, sg.dm[1], sg.ds[1]);
+    x.c[1] = (int)t - (int)z * sg.K[1];
+    x.c[2] = (int)z;
+    return x;
+}
+// Element across the face of element e (coordinates x) along axis a (periodic).
+DI int neighbour(const OpSeg& sg, int e, const ECoord& x, int a, bool right) {
+    const int es = a == 0 ? 1 : (a == 1 ? sg.K[0] : sg.K[0] * sg.K[1]);
+    const int ca = a == 0 ? x.c[0] : (a == 1 ? x.c[1] : x.c[2]);
+    const int K = a == 0 ? sg.K[0] : (a == 1 ? sg.K[1] : sg.K[2]);
+    const int step = right ? (ca + 1 == K ? 1 - K : 1) : (ca == 0 ? K - 1 : -1);
+    return e + step * es;
 }
 
-// Element across the face of element e along axis a (periodic); element
-// indices fit 31 bits (checked when the problem is made).
-DI int neighbour(const OpSeg& sg, int e, int a, bool right) {
-    const unsigned es = a == 0 ? 1u : (a == 1 ? (unsigned)sg.K[0] : (unsigned)sg.K[0] * (unsigned)sg.K[1]);
-    const int ca = (int)(((unsigned)e / es) % (unsigned)sg.K[a]);
-    const int cn = right ? (ca + 1 == sg.K[a] ? 0 : ca + 1) : (ca == 0 ? sg.K[a] - 1 : ca - 1);
-    return e + (cn - ca) * (int)es;
+// Spatial node on face (axis a, side) with face index f (the other axes in
+// increasing order, the first one fastest), for a runtime axis.
+template <int D, int N1>
+DI int face_node_rt(int a, int f, bool right) {
+    const int ia = right ? N1 - 1 : 0;
+    if constexpr (D == 1) {
+        return ia;
+    } else if constexpr (D == 2) {
+        return a == 0 ? ia + f * N1 : f + ia * N1;
+    } else {
+        const int f1 = (int)((unsigned)f % N1), f2 = (int)((unsigned)f / N1);
+        return a == 0 ? ia + f1 * N1 + f2 * N1 * N1 : (a == 1 ? f1 + ia * N1 + f2 * N1 * N1 : f1 + f2 * N1 + ia * N1 * N1);
+    }
 }
+template <int N1>
+DI int stride_rt(int a) { return a == 0 ? 1 : (a == 1 ? N1 : N1 * N1); }
 
 // ---------------------------------------------------------------------------
 // pointwise physics with the primitive variables shared by all axes
@@ -141,7 +159,7 @@ struct Flux {
     SDI Prim prim(const T* u, const EqParams& P) {
         Prim w;
         if constexpr (GAS) {
-            w.inv = S(1) / u[0];
+            w.inv = recip_(u[0]);
             T mv = make_state<T>(S(0), S(0));
 #pragma unroll
             for (int b = 0; b < D; ++b) {
@@ -169,14 +187,13 @@ struct Flux {
         }
     }
 
-    // largest characteristic speed along axis a
-    SDI T speed(int a, const T* u, const EqParams& P) {
+    // largest characteristic speed along axis a (w: the primitives of u)
+    SDI T speed(int a, const T* u, const Prim& w, const EqParams& P) {
         if constexpr (EQ == EQ_ADV || EQ == EQ_ADVDIFF) {
             return make_state<T>(S(fabs(P.a[a])), S(0));
         } else if constexpr (EQ == EQ_BURGERS) {
             return absval(u[0]);
         } else {
-            const Prim w = prim(u, P);
             const T c = sqrt_(S(P.gamma) * w.p * w.inv);
             return absval(w.vel[a]) + c;
         }
@@ -254,7 +271,7 @@ __global__ __launch_bounds__((Shape<D, N1, NT, tpt_of(EQ, NT)>::BS)) void k_op(c
     using F = Flux<EQ, D, T>;
     constexpr int R = nvars_of(EQ, D);
     constexpr int NS = SH::NS, NPE = SH::NPE, NF = SH::NF, NJ = SH::NJ, NTH = SH::NTH;
-    constexpr int EPB = SH::EPB, B = SH::B, BS = SH::BS, NN = SH::NN;
+    constexpr int EPB = SH::EPB, B = SH::B, BS = SH::BS, NN = SH::NN, NFP = SH::NFP;
     constexpr bool AD = EQ == EQ_ADVDIFF;
     constexpr bool NSV = EQ == EQ_NS;
     constexpr int TS = JVP ? 2 : 1;
@@ -262,7 +279,6 @@ __global__ __launch_bounds__((Shape<D, N1, NT, tpt_of(EQ, NT)>::BS)) void k_op(c
     constexpr int EV = R * NPE;                  // values of one element
     __shared__ CT tile[TS * R * NN];             // [plane][v][node]: value, then tangent
     __shared__ CT buf[D * R * NN];               // [a][v][node]: flux along a, then H - f
-    __shared__ int nbr[EPB * 2 * D];             // neighbour elements [el][a][side]
     __shared__ CT sD[N1 * N1], sDt[NT * NT], swt[NT];
 
     const int L = xcd_remap(blockIdx.x, G);
@@ -310,23 +326,156 @@ __global__ __launch_bounds__((Shape<D, N1, NT, tpt_of(EQ, NT)>::BS)) void k_op(c
             }
     };
 
-    // (0) tables and neighbour elements to LDS; own states -> tile; own
-    //     gradient (NS)
+    // Face points: (axis a, element, side, time group, face node), axis-major
+    // so that a wavefront mostly works on one axis.
+    struct FPI {
+        int a, pel, to0, rn0, en, stride;
+        bool right, ok;
+    };
+    auto fp_info = [&](int p) {
+        FPI fi;
+        constexpr int PER_AX = EPB * 2 * NJ * NF;
+        fi.a = (int)((unsigned)p / PER_AX);
+        int rem = p - fi.a * PER_AX;
+        fi.pel = (int)((unsigned)rem / (2 * NJ * NF));
+        rem -= fi.pel * (2 * NJ * NF);
+        fi.right = rem >= NJ * NF;
+        rem -= fi.right ? NJ * NF : 0;
+        const int jg = (int)((unsigned)rem / NF);
+        const int f = rem - jg * NF;
+        const int ep = e0 + fi.pel;
+        fi.ok = p < NFP && ep < sg.E;
+        fi.stride = stride_rt<N1>(fi.a);
+        const int so = face_node_rt<D, N1>(fi.a, f, fi.right);
+        fi.rn0 = jg * TPT * NS + so + (fi.right ? -(N1 - 1) : (N1 - 1)) * fi.stride;   // neighbour's node
+        fi.to0 = fi.pel * NPE + jg * TPT * NS + so;                                    // own block node
+        fi.en = fi.ok ? neighbour(sg, ep, ecoord(sg, ep), fi.a, fi.right) : 0;
+        return fi;
+    };
+    // neighbour data of a face point: AD the neighbour's normal line from
+    // the face node inwards; otherwise its state (and gradient)
+    struct FPD {
+        CT line[AD ? TPT : 1][AD ? N1 : 1];
+        T un[AD ? 1 : TPT][R];
+        T qn[NSV ? TPT : 1][NSV ? D * R : 1];
+    };
+    auto fp_load = [&](const FPI& fi, FPD& d) {
+        if (!fi.ok) return;
+        if constexpr (AD) {
+            const int step = fi.right ? fi.stride : -fi.stride;
+            const gptr<UT> lb = Up + (int64_t)fi.en * EV + fi.rn0;
+#pragma unroll
+            for (int jj = 0; jj < TPT; ++jj)
+#pragma unroll
+                for (int k = 0; k < N1; ++k) d.line[jj][k] = CT(lb[jj * NS + k * step]);
+        } else {
+#pragma unroll
+            for (int jj = 0; jj < TPT; ++jj) {
+                load_state(fi.en, fi.rn0 + jj * NS, d.un[jj]);
+                if constexpr (NSV) load_grad(fi.en, fi.rn0 + jj * NS, d.qn[jj]);
+            }
+        }
+    };
+    auto fp_compute = [&](const FPI& fi, const FPD& d) {
+        if (!fi.ok) return;
+        static_for<0, D>([&](auto A) {
+            constexpr int ax = decltype(A)::value;
+            if (ax != fi.a) return;
+            const bool right = fi.right;
+            if constexpr (AD) {
+                const int inb = right ? 0 : N1 - 1;
+                CT Dn[N1];
+#pragma unroll
+                for (int k = 0; k < N1; ++k) Dn[k] = sD[inb * N1 + (right ? k : N1 - 1 - k)];
+                const CT lw = right ? -iw0 : iw0;
+                const CT lam = CT(fabs(P.a[ax])), av = CT(P.a[ax]), J = CT(sg.rh[ax]), nu = CT(P.nu);
+#pragma unroll
+                for (int jj = 0; jj < TPT; ++jj) {
+                    const CT uo = tile[fi.to0 + jj * NS];
+                    const CT unv = d.line[jj][0];
+                    CT gn = Dn[0] * d.line[jj][0];
+#pragma unroll
+                    for (int k = 1; k < N1; ++k) gn += Dn[k] * d.line[jj][k];
+                    gn += lw * (CT(0.5) * (unv + uo) - unv);
+                    const CT fn = unv * av - (J * gn) * nu;
+                    const CT jump = right ? uo - unv : unv - uo;
+                    CT& slot = buf[ax * NN + fi.to0 + jj * NS];
+                    slot = CT(0.5) * (fn - slot) + (CT(0.5) * lam) * jump;
+                }
+            } else {
+#pragma unroll
+                for (int jj = 0; jj < TPT; ++jj) {
+                    const int to = fi.to0 + jj * NS;
+                    T uo[R], fn[R];
+#pragma unroll
+                    for (int v = 0; v < R; ++v) {
+                        if constexpr (JVP) uo[v] = make_state<T>(tile[v * NN + to], tile[(R + v) * NN + to]);
+                        else uo[v] = tile[v * NN + to];
+                    }
+                    const T* un = d.un[jj];
+                    const typename F::Prim w = F::prim(un, P);
+                    F::conv(ax, un, w, fn, P);
+                    if constexpr (NSV) {
+                        const typename F::Visc z = F::visc_state(w, d.qn[jj], P);
+                        F::sub_visc(ax, w, z, fn, P);
+                    }
+                    const T lo = F::speed(ax, uo, F::prim(uo, P), P), ln = F::speed(ax, un, w, P);
+                    const T lam = right ? larger(lo, ln) : larger(ln, lo);
+#pragma unroll
+                    for (int v = 0; v < R; ++v) {
+                        const T jump = right ? uo[v] - un[v] : un[v] - uo[v];      // u_L - u_R
+                        const CT pen = part((CT(0.5) * lam) * jump);
+                        CT& slot = buf[(ax * R + v) * NN + to];
+                        slot = CT(0.5) * (part(fn[v]) - slot) + pen;
+                    }
+                }
+            }
+        });
+    };
+
+    // (0) tables to LDS; every global load of the block issued at once: own
+    //     states (and NS gradient), AD neighbour face values, the data of
+    //     this thread's first face point
     if (tid < N1 * N1) sD[tid] = CT(sg.Dx[tid]);
     if (tid < NT * NT) sDt[tid] = CT(sg.Dt[tid]);
     if (tid < NT) swt[tid] = CT(sg.wt[tid]);
-    if (tid < EPB * 2 * D) {
-        const int ee = e0 + tid / (2 * D), a = (tid >> 1) % D;
-        nbr[tid] = ee < sg.E ? neighbour(sg, ee, a, tid & 1) : 0;
-    }
     T u[TPT][R];
     T q[NSV ? TPT : 1][NSV ? D * R : 1];
+    CT unb[AD ? D : 1][AD ? TPT : 1];
     if (active) {
 #pragma unroll
         for (int jj = 0; jj < TPT; ++jj) {
             load_state(e, r0 + jj * NS, u[jj]);
             if constexpr (NSV) load_grad(e, r0 + jj * NS, q[jj]);
         }
+        if constexpr (AD) {
+            const ECoord x = ecoord(sg, e);
+            static_for<0, D>([&](auto A) {
+                constexpr int a = decltype(A)::value;
+                const int ia = ic[a];
+                if (ia == 0 || ia == N1 - 1) {
+                    const bool right = ia == N1 - 1;
+                    const gptr<UT> Un = Up + (int64_t)neighbour(sg, e, x, a, right) * EV +
+                                        (r0 + ((right ? 0 : N1 - 1) - ia) * ipow(N1, a));
+#pragma unroll
+                    for (int jj = 0; jj < TPT; ++jj) unb[a][jj] = CT(Un[jj * NS]);
+                } else {
+                    // interior node: u_hat = u, the lift below vanishes exactly
+#pragma unroll
+                    for (int jj = 0; jj < TPT; ++jj) unb[a][jj] = value(u[jj][0]);
+                }
+            });
+        }
+    } else {
+#pragma unroll
+        for (int jj = 0; jj < TPT; ++jj)
+#pragma unroll
+            for (int v = 0; v < R; ++v) u[jj][v] = make_state<T>(CT(1), CT(0));
+    }
+    const FPI fi0 = fp_info(tid);
+    FPD fd0;
+    fp_load(fi0, fd0);
+    if (active) {
 #pragma unroll
         for (int jj = 0; jj < TPT; ++jj)
 #pragma unroll
@@ -334,11 +483,6 @@ __global__ __launch_bounds__((Shape<D, N1, NT, tpt_of(EQ, NT)>::BS)) void k_op(c
                 tile[v * NN + nd0 + jj * NS] = value(u[jj][v]);
                 if constexpr (JVP) tile[(R + v) * NN + nd0 + jj * NS] = part(u[jj][v]);
             }
-    } else {
-#pragma unroll
-        for (int jj = 0; jj < TPT; ++jj)
-#pragma unroll
-            for (int v = 0; v < R; ++v) u[jj][v] = make_state<T>(CT(1), CT(0));
     }
     if constexpr (AD) __syncthreads();
 
@@ -348,18 +492,6 @@ __global__ __launch_bounds__((Shape<D, N1, NT, tpt_of(EQ, NT)>::BS)) void k_op(c
             // own lifted gradient: D contraction, then the lift with the
             // neighbour's face value (u_hat = {u})
             const CT nu = CT(P.nu);
-            CT unb[D][TPT];
-            static_for<0, D>([&](auto A) {
-                constexpr int a = decltype(A)::value;
-                const int ia = ic[a];
-                if (ia == 0 || ia == N1 - 1) {
-                    const bool right = ia == N1 - 1;
-                    const gptr<UT> Un = Up + (int64_t)nbr[(el * D + a) * 2 + right] * EV +
-                                        (r0 + ((right ? 0 : N1 - 1) - ia) * ipow(N1, a));
-#pragma unroll
-                    for (int jj = 0; jj < TPT; ++jj) unb[a][jj] = CT(Un[jj * NS]);
-                }
-            });
             static_for<0, D>([&](auto A) {
                 constexpr int a = decltype(A)::value;
                 constexpr int stride = ipow(N1, a);
@@ -368,15 +500,14 @@ __global__ __launch_bounds__((Shape<D, N1, NT, tpt_of(EQ, NT)>::BS)) void k_op(c
 #pragma unroll
                 for (int k = 0; k < N1; ++k) Dr[k] = sD[ia * N1 + k];
                 const CT J = CT(sg.rh[a]), av = CT(P.a[a]);
-                const bool face = ia == 0 || ia == N1 - 1;
-                const CT lw = ia == N1 - 1 ? iw0 : -iw0;
+                const CT lw = ia == N1 - 1 ? iw0 : (ia == 0 ? -iw0 : CT(0));
 #pragma unroll
                 for (int jj = 0; jj < TPT; ++jj) {
                     const CT* ln = tile + nd0 + jj * NS - ia * stride;
                     CT g = Dr[0] * ln[0];
 #pragma unroll
                     for (int k = 1; k < N1; ++k) g += Dr[k] * ln[k * stride];
-                    if (face) g += lw * (CT(0.5) * (u[jj][0] + unb[a][jj]) - u[jj][0]);
+                    g += lw * (CT(0.5) * (u[jj][0] + unb[a][jj]) - u[jj][0]);
                     buf[a * NN + nd0 + jj * NS] = u[jj][0] * av - (J * g) * nu;
                 }
             });
@@ -429,88 +560,13 @@ __global__ __launch_bounds__((Shape<D, N1, NT, tpt_of(EQ, NT)>::BS)) void k_op(c
     __syncthreads();
 
     // (3) face points: H - f into the flux slot of the face node.  The slot
-    // of (axis, face node) belongs to exactly one face point.  Face points
-    // are numbered axis-major, so a wavefront mostly works on one axis.
-    for (int p = tid; p < SH::NFP; p += BS) {
-        constexpr int PER_AX = EPB * 2 * NJ * NF;
-        const int a = (int)((unsigned)p / PER_AX);
-        int rem = p - a * PER_AX;
-        const int pel = (int)((unsigned)rem / (2 * NJ * NF));
-        rem -= pel * (2 * NJ * NF);
-        const bool right = rem >= NJ * NF;
-        rem -= right ? NJ * NF : 0;
-        const int jg = (int)((unsigned)rem / NF);
-        const int f = rem - jg * NF;
-        if (e0 + pel >= sg.E) continue;
-        static_for<0, D>([&](auto A) {
-            constexpr int ax = decltype(A)::value;
-            if (ax != a) return;
-            constexpr int stride = ipow(N1, ax);
-            const int so = face_node<D, N1, ax>(f, right);
-            const int rn0 = jg * TPT * NS + so + (right ? -(N1 - 1) : (N1 - 1)) * stride;   // neighbour node
-            const int to0 = pel * NPE + jg * TPT * NS + so;                                  // own block node
-            const int en = nbr[(pel * D + ax) * 2 + right];
-            if constexpr (AD) {
-                // neighbour's lifted normal derivative at its face node, from
-                // its line of nodes normal to the face (all TPT time nodes),
-                // taken from the face node inwards: line[.][0] is the trace
-                const int inb = right ? 0 : N1 - 1;
-                const int step = right ? stride : -stride;
-                const gptr<UT> lb = Up + (int64_t)en * EV + rn0;
-                CT line[TPT][N1];
-#pragma unroll
-                for (int jj = 0; jj < TPT; ++jj)
-#pragma unroll
-                    for (int k = 0; k < N1; ++k) line[jj][k] = CT(lb[jj * NS + k * step]);
-                CT Dn[N1];
-#pragma unroll
-                for (int k = 0; k < N1; ++k) Dn[k] = sD[inb * N1 + (right ? k : N1 - 1 - k)];
-                const CT lw = right ? -iw0 : iw0;
-                const CT lam = CT(fabs(P.a[ax])), av = CT(P.a[ax]), J = CT(sg.rh[ax]), nu = CT(P.nu);
-#pragma unroll
-                for (int jj = 0; jj < TPT; ++jj) {
-                    const CT uo = tile[to0 + jj * NS];
-                    const CT unv = line[jj][0];
-                    CT gn = Dn[0] * line[jj][0];
-#pragma unroll
-                    for (int k = 1; k < N1; ++k) gn += Dn[k] * line[jj][k];
-                    gn += lw * (CT(0.5) * (unv + uo) - unv);
-                    const CT fn = unv * av - (J * gn) * nu;
-                    const CT jump = right ? uo - unv : unv - uo;
-                    CT& slot = buf[ax * NN + to0 + jj * NS];
-                    slot = CT(0.5) * (fn - slot) + (CT(0.5) * lam) * jump;
-                }
-            } else {
-#pragma unroll
-                for (int jj = 0; jj < TPT; ++jj) {
-                    const int to = to0 + jj * NS;
-                    T uo[R], un[R], fn[R];
-#pragma unroll
-                    for (int v = 0; v < R; ++v) {
-                        if constexpr (JVP) uo[v] = make_state<T>(tile[v * NN + to], tile[(R + v) * NN + to]);
-                        else uo[v] = tile[v * NN + to];
-                    }
-                    load_state(en, rn0 + jj * NS, un);
-                    const typename F::Prim w = F::prim(un, P);
-                    F::conv(ax, un, w, fn, P);
-                    if constexpr (NSV) {
-                        T qn[D * R];
-                        load_grad(en, rn0 + jj * NS, qn);
-                        const typename F::Visc z = F::visc_state(w, qn, P);
-                        F::sub_visc(ax, w, z, fn, P);
-                    }
-                    const T lo = F::speed(ax, uo, P), ln = F::speed(ax, un, P);
-                    const T lam = right ? larger(lo, ln) : larger(ln, lo);
-#pragma unroll
-                    for (int v = 0; v < R; ++v) {
-                        const T jump = right ? uo[v] - un[v] : un[v] - uo[v];      // u_L - u_R
-                        const CT pen = part((CT(0.5) * lam) * jump);
-                        CT& slot = buf[(ax * R + v) * NN + to];
-                        slot = CT(0.5) * (part(fn[v]) - slot) + pen;
-                    }
-                }
-            }
-        });
+    // of (axis, face node) belongs to exactly one face point.
+    fp_compute(fi0, fd0);
+    for (int p = tid + BS; p < NFP; p += BS) {
+        const FPI fi = fp_info(p);
+        FPD fd;
+        fp_load(fi, fd);
+        fp_compute(fi, fd);
     }
     __syncthreads();
 
@@ -566,7 +622,6 @@ __global__ __launch_bounds__((Shape<D, N1, NT, 1>::BS)) void k_grad(const OpSeg*
     constexpr int NS = SH::NS, NPE = SH::NPE, EPB = SH::EPB, B = SH::B;
     constexpr int EV = R * NPE;
     __shared__ CT tile[R * B];
-    __shared__ int nbr[EPB * 2 * D];
     __shared__ CT sD[N1 * N1];
     const int L = xcd_remap(blockIdx.x, G);
     const OpSeg& sg = segs[find_seg(segs, nseg, L)];
@@ -582,18 +637,26 @@ __global__ __launch_bounds__((Shape<D, N1, NT, 1>::BS)) void k_grad(const OpSeg*
     const gptr<CT> __restrict__ Qp = resolve<CT>(sg.out);
 
     if (tid < N1 * N1) sD[tid] = CT(sg.Dx[tid]);
-    if (tid < EPB * 2 * D) {
-        const int ee = e0 + tid / (2 * D), a = (tid >> 1) % D;
-        nbr[tid] = ee < sg.E ? neighbour(sg, ee, a, tid & 1) : 0;
-    }
     CT u[R];
+    CT un[D][R];
     if (active) {
         const gptr<UT> Ue = Up + (int64_t)e * EV;
 #pragma unroll
-        for (int v = 0; v < R; ++v) {
-            u[v] = CT(Ue[v * NPE + r]);
-            tile[v * B + tid] = u[v];
-        }
+        for (int v = 0; v < R; ++v) u[v] = CT(Ue[v * NPE + r]);
+        const ECoord x = ecoord(sg, e);
+        static_for<0, D>([&](auto B_) {
+            constexpr int b = decltype(B_)::value;
+            const int ib = coord<N1, b>(s);
+            if (ib == 0 || ib == N1 - 1) {
+                const bool right = ib == N1 - 1;
+                const gptr<UT> Un = Up + (int64_t)neighbour(sg, e, x, b, right) * EV +
+                                    (r + ((right ? 0 : N1 - 1) - ib) * ipow(N1, b));
+#pragma unroll
+                for (int v = 0; v < R; ++v) un[b][v] = CT(Un[v * NPE]);
+            }
+        });
+#pragma unroll
+        for (int v = 0; v < R; ++v) tile[v * B + tid] = u[v];
     }
     __syncthreads();
     if (!active) return;
@@ -604,14 +667,6 @@ __global__ __launch_bounds__((Shape<D, N1, NT, 1>::BS)) void k_grad(const OpSeg*
         constexpr int stride = ipow(N1, b);
         const int ib = coord<N1, b>(s);
         const bool face = (ib == 0 || ib == N1 - 1);
-        CT un[R];
-        if (face) {
-            const bool right = ib == N1 - 1;
-            const gptr<UT> Un = Up + (int64_t)nbr[(el * D + b) * 2 + right] * EV;
-            const int rn = r + ((right ? 0 : N1 - 1) - ib) * stride;
-#pragma unroll
-            for (int v = 0; v < R; ++v) un[v] = CT(Un[v * NPE + rn]);
-        }
         CT Drow[N1];
 #pragma unroll
         for (int k = 0; k < N1; ++k) Drow[k] = sD[ib * N1 + k];
@@ -623,7 +678,7 @@ __global__ __launch_bounds__((Shape<D, N1, NT, 1>::BS)) void k_grad(const OpSeg*
 #pragma unroll
             for (int k = 1; k < N1; ++k) g += Drow[k] * ln[k * stride];
             if (face) {
-                const CT uh = CT(0.5) * (u[v] + un[v]);
+                const CT uh = CT(0.5) * (u[v] + un[b][v]);
                 g += (ib == N1 - 1 ? wl : -wl) * (uh - u[v]);
             }
             Qe[(b * R + v) * NPE + r] = J * g;
