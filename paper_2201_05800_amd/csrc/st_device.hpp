@@ -292,6 +292,7 @@ struct OpSeg {
     int E;
     unsigned dm[2];      // e / K[a] = (e * dm[a]) >> ds[a] for e < 2^31 (a = 0, 1)
     int ds[2];
+    int tx, ty;          // block traversal tiles (elements; tx = 0: lexicographic)
     double rh[3];        // 2 / h_a
     double dt;
     int blk0;            // first logical block

@@ -159,6 +159,26 @@ OpSeg base_opseg(const Problem& pb, double dt) {
         s.dm[a] = (unsigned)((((uint64_t)1 << (31 + k)) + d - 1) / d);
         s.ds[a] = 31 + k;
     }
+    // Block traversal: columns of tx x ty elements swept through z, each
+    // column row by row, so that a face neighbour is met again within a few
+    // rows of the column (L2 reuse of halo traces) rather than a whole plane
+    // of the mesh later.  tx is a multiple of the elements per block and
+    // divides K0, ty divides K1; 2D takes whole-height strips, 3D small
+    // columns.  Lexicographic when K0 is not a multiple of the block width.
+    const int epb = pb.ops->epb;
+    s.tx = 0;
+    s.ty = 0;
+    if (pb.mesh.dim >= 2 && pb.K[0] % epb == 0) {
+        const int want_x = pb.mesh.dim == 2 ? 64 : 4, want_y = pb.mesh.dim == 2 ? pb.K[1] : 4;
+        int tx = epb;
+        for (int c = epb; c <= pb.K[0] && c <= std::max(want_x, epb); c += epb)
+            if (pb.K[0] % c == 0) tx = c;
+        int ty = 1;
+        for (int c = 1; c <= pb.K[1] && c <= want_y; ++c)
+            if (pb.K[1] % c == 0) ty = c;
+        s.tx = tx;
+        s.ty = ty;
+    }
     s.P = pb.P;
     s.dt = dt;
     s.blk0 = 0;

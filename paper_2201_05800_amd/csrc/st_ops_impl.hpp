@@ -125,6 +125,29 @@ DI int neighbour(const OpSeg& sg, int e, const ECoord& x, int a, bool right) {
     return e + step * es;
 }
 
+// First element of block b of a segment: lexicographic (tx = 0), or the
+// tiled traversal -- tiles of tx x ty elements (tile rows x-fastest), each
+// tile a column swept through z, row by row, EPB consecutive x-elements per
+// block.  Uniform per block (scalar arithmetic).
+template <int EPB>
+DI int block_elem0(const OpSeg& sg, int b) {
+    if (sg.tx == 0) return b * EPB;
+    const int bx = sg.tx / EPB;                   // blocks per tile row
+    const int per_layer = bx * sg.ty;
+    const int per_tile = per_layer * sg.K[2];
+    const int t = b / per_tile;
+    int rem = b - t * per_tile;
+    const int z = rem / per_layer;
+    rem -= z * per_layer;
+    const int yi = rem / bx;
+    const int xb = rem - yi * bx;
+    const int tiles_x = sg.K[0] / sg.tx;
+    const int tyi = t / tiles_x;
+    const int txi = t - tyi * tiles_x;
+    const int x = txi * sg.tx + xb * EPB, y = tyi * sg.ty + yi;
+    return x + sg.K[0] * (y + sg.K[1] * z);
+}
+
 // Spatial node on face (axis a, side) with face index f (the other axes in
 // increasing order, the first one fastest), for a runtime axis.
 template <int D, int N1>
@@ -289,7 +312,7 @@ __global__ __launch_bounds__((Shape<D, N1, NT, tpt_of(EQ, NT)>::BS)) void k_op(c
     const int el = (int)((unsigned)tid / NTH);
     const int jt = (int)((unsigned)(tid - el * NTH) / NS);   // time group
     const int s = tid - el * NTH - jt * NS;                  // spatial node
-    const int e0 = (L - sg.blk0) * EPB;
+    const int e0 = block_elem0<EPB>(sg, L - sg.blk0);
     const int e = e0 + el;
     const bool active = (tid < B) && (e < sg.E);
     const int nd0 = el * NPE + jt * TPT * NS + s;            // block node of time node jt*TPT
@@ -630,7 +653,7 @@ __global__ __launch_bounds__((Shape<D, N1, NT, 1>::BS)) void k_grad(const OpSeg*
     const int el = (int)((unsigned)tid / NPE);
     const int r = tid - el * NPE;
     const int s = (int)((unsigned)r % NS);
-    const int e0 = (L - sg.blk0) * EPB;
+    const int e0 = block_elem0<EPB>(sg, L - sg.blk0);
     const int e = e0 + el;
     const bool active = (tid < B) && (e < sg.E);
     const gptr<UT> __restrict__ Up = resolve<UT>(sg.U);
