@@ -66,6 +66,8 @@ def parse():
     ap.add_argument("--no-timing", action="store_true", help="run without HIP-event kernel timing")
     ap.add_argument("--serve-requests", type=int, default=96,
                     help="requests in the served-stream sample (0: skip the serving leg)")
+    ap.add_argument("--precond-leg", type=int, default=1,
+                    help="1: also time the element-block Jacobi preconditioned solves (linear equations)")
     ap.add_argument("--operators", type=int, default=1,
                     help="1: time st_residual / st_jvp on >= 1 GB working sets (0: skip)")
     ap.add_argument("--operator-reps", type=int, default=10)
@@ -389,6 +391,45 @@ def main():
     warm_total = sum(shares_w) or 1.0
     shares = {st.KERNEL_CLASSES[c]: round(shares_w[c] / warm_total, 4) for c in range(len(shares_w))}
 
+    # element-block Jacobi right preconditioning (linear equations): the same
+    # slabs, solved to the same tolerance
+    precond = None
+    if cfg["kind"] in (st.ST_ADVECTION, st.ST_ADVDIFF_BR1) and args.precond_leg:
+        opc = st.st_default_opts(restart=args.restart, cgs_passes=args.cgs_passes, inner_fp32=args.fp32_inner,
+                                 precond=1, timing=0 if args.no_timing else (1 << st.ST_K_PRECOND))
+        u.copy_(torch.as_tensor(u0))
+        step_pc = lambda uin, uout: st.st_solve_slab(h, uin, 0.0, dt, cfg["tol"], opc, U, uout, stream)
+        step_pc(u, un)                       # warm-up: assembles and inverts the element block
+        u.copy_(torch.as_tensor(u0))
+        torch.cuda.synchronize()
+        lat_pc, stats_pc = [], []
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            ts = time.perf_counter()
+            stats_pc.append(step_pc(u, un))
+            lat_pc.append(time.perf_counter() - ts)
+            u, un = un, u
+        torch.cuda.synchronize()
+        el_pc = time.perf_counter() - t0
+        us = sum(x["kernel_us"][st.ST_K_PRECOND] for x in stats_pc)
+        calls = sum(x["kernel_calls"][st.ST_K_PRECOND] for x in stats_pc)
+        by = sum(x["kernel_bytes"][st.ST_K_PRECOND] for x in stats_pc)
+        precond = dict(
+            method="element-block Jacobi, right preconditioning (B^-1 of the element diagonal block of the slab "
+                   "Jacobian, the same in every element)",
+            ms_per_step=el_pc * 1e3 / args.steps, slab_solves_per_s=args.steps / el_pc,
+            speedup_vs_plain=(elapsed / args.steps) / (el_pc / args.steps),
+            latency_ms_p50=float(np.percentile(np.array(lat_pc) * 1e3, 50)),
+            latency_ms_p99=float(np.percentile(np.array(lat_pc) * 1e3, 99)),
+            newton_its_per_slab=sum(x["newton_its"] for x in stats_pc) / len(stats_pc),
+            gmres_its_per_slab=sum(x["gmres_its"] for x in stats_pc) / len(stats_pc),
+            dof_evals_per_s=sum(x["newton_its"] + 1 + x["gmres_its"] for x in stats_pc) * n / el_pc,
+            precond_kernel=dict(kernel="k_bjacobi", avg_launch_us=round(us / max(calls, 1), 3),
+                                achieved_GBs=round(by / (us * 1e-6) / 1e9, 1) if us > 0 else None,
+                                note="algorithmic bytes: direction in, result out (B^-1 reads are L2 hits)"))
+        print(f"# preconditioned: {precond['ms_per_step']:.3f} ms/slab, {precond['gmres_its_per_slab']:.1f} "
+              f"GMRES its/slab", file=sys.stderr, flush=True)
+
     serving = serving_bench(args.serve_requests) if args.serve_requests > 0 else None
     operators = operator_bench(args.operator_reps) if args.operators else None
 
@@ -420,6 +461,7 @@ def main():
         "operator_evals": op_evals,
         "kernel_time_share_of_timed": shares,
         "roofline": roof,
+        "preconditioned": precond,
         "serving": serving,
         "operators": operators,
         "cpu_baseline": cpu,

@@ -48,7 +48,8 @@ extern "C" {
 #define ST_ERR_NONFINITE (-3)      /* NaN/Inf in an input or in a residual    */
 #define ST_ERR_NO_CONVERGENCE (-4) /* Newton/GMRES limit reached              */
 #define ST_ERR_OOM_ADMISSION (-5)  /* request larger than the server's budget */
-#define ST_ERR_UNSUPPORTED (-6)    /* (eq, dim, N, Nt) not compiled in        */
+#define ST_ERR_UNSUPPORTED (-6)    /* (eq, dim, N, Nt) not compiled in, or an  */
+                                   /* option not available for it             */
 #define ST_ERR_NOT_FOUND (-7)      /* unknown ticket                          */
 #define ST_ERR_CANCELLED (-8)      /* ticket cancelled before completion      */
 
@@ -93,6 +94,9 @@ typedef struct {
                        /* to 1e-5 at least when inner_fp32)                     */
     int timing;        /* bit mask of ST_K_* kernel classes to time with HIP    */
                        /* events on the solve's stream (0 = none)               */
+    int precond;       /* 0: none (default); 1: element-block Jacobi, right     */
+                       /* preconditioning -- linear equations only (advection,  */
+                       /* advection-diffusion), st_solve_slab only              */
 } st_solver_opts_t;
 
 /* Kernel classes of the slab solve (bits of st_solver_opts_t.timing and
@@ -105,6 +109,7 @@ enum {
     ST_K_UPDATE = 4,    /* Gram-Schmidt correction + Givens + normalisation  */
     ST_K_NORMALIZE = 5, /* first Krylov vector V_0 = -R / ||R||              */
     ST_K_NEWTON = 6,    /* Newton update U += V y, residual norm, setup      */
+    ST_K_PRECOND = 7,   /* element-block Jacobi applications                 */
     ST_K_COUNT = 8
 };
 
@@ -170,7 +175,14 @@ int st_jvp(st_handle_t h, const double* U, double t0, double dt, const double* v
  * when ||R(U)||_2 <= tol * max(1, ||R(U0)||_2).  Writes the whole slab
  * U_out (may be NULL) and the end-of-slab state u_next = (e_Nt^T (x) I) U
  * (eq. (un); may be NULL).  Synchronises `stream` once per outer iteration.
- * On ST_ERR_NO_CONVERGENCE the last iterate is written and stats filled. */
+ * On ST_ERR_NO_CONVERGENCE the last iterate is written and stats filled.
+ * opts->precond = 1 (linear equations) right-preconditions GMRES with the
+ * inverse of the element diagonal block of eq. (Jacobian_ST) -- the same
+ * block in every element of the uniform periodic mesh, assembled with the
+ * operator kernels and inverted on the host on the first solve with a given
+ * dt (device memory npe^2 doubles, npe = Nt (N+1)^d); the solution is that
+ * of the unpreconditioned system.  ST_ERR_UNSUPPORTED for the nonlinear
+ * equations. */
 int st_solve_slab(st_handle_t h, const double* u_prev, double t0, double dt, double tol,
                   const st_solver_opts_t* opts, double* U_out, double* u_next, st_stats_t* stats,
                   void* stream);

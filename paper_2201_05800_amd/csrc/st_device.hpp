@@ -24,15 +24,19 @@ struct LaunchTiming {
 LaunchTiming& launch_timing();   // thread-local
 
 template <class K, class... A>
-void launch_k(K kernel, dim3 grid, dim3 block, hipStream_t st, A... args) {
+void launch_ks(K kernel, dim3 grid, dim3 block, size_t shm, hipStream_t st, A... args) {
     LaunchTiming& lt = launch_timing();
     if (lt.start) {
         hipEvent_t e0 = lt.start, e1 = lt.stop;
         lt.start = lt.stop = nullptr;
-        hipExtLaunchKernelGGL(kernel, grid, block, 0, st, e0, e1, 0, args...);
+        hipExtLaunchKernelGGL(kernel, grid, block, shm, st, e0, e1, 0, args...);
     } else {
-        hipLaunchKernelGGL(kernel, grid, block, 0, st, args...);
+        hipLaunchKernelGGL(kernel, grid, block, shm, st, args...);
     }
+}
+template <class K, class... A>
+void launch_k(K kernel, dim3 grid, dim3 block, hipStream_t st, A... args) {
+    launch_ks(kernel, grid, block, 0, st, args...);
 }
 
 constexpr int MMAX = 32;           // largest GMRES restart length
@@ -324,6 +328,20 @@ struct VecSeg {
     float* U32;      // FP32 copy of U (FP32-inner JVPs)
     int nt;          // temporal nodes
     int ns;          // spatial nodes per element
+    int blk0;
+    int nblk;
+};
+
+// One slab inside an element-block Jacobi launch: out_e = B^-1 in_e for every
+// element e (the element's npe consecutive values), or out_e += B^-1 in_e.
+struct PcSeg {
+    DynPtr in;            // input vector (may follow the Arnoldi index)
+    double* out;
+    const double* binvT;  // B^-1 column-major: binvT[j * npe + i] = (B^-1)_{ij}
+    const int* skip;      // skip the segment when *skip != 0 (may be null)
+    int npe;              // unknowns per element
+    int E;                // elements
+    int accumulate;       // 1: out += B^-1 in
     int blk0;
     int nblk;
 };

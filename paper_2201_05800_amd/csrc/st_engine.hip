@@ -219,6 +219,12 @@ struct st_ctx {
     int m_alloc = 0;
     GState* h_st = nullptr;     // pinned host mirror of the state header
     std::vector<void*> allocs;
+    // element-block Jacobi (linear equations): B^-1 column-major, the dt it
+    // was assembled for, the preconditioned direction z, 2 descriptor slots
+    double* binvT = nullptr;
+    double pc_dt = 0.0;
+    double* pz = nullptr;
+    PcSeg* d_pc = nullptr;
 
     // optional HIP-event timing of kernel classes (st_solver_opts_t.timing)
     struct Timer {
@@ -318,6 +324,119 @@ static int ensure_solve(st_ctx* h, int m) {
     return ST_OK;
 }
 
+// In-place inverse of the row-major n x n matrix A by Gauss-Jordan
+// elimination with partial pivoting; false if a pivot vanishes.
+static bool invert_dense(std::vector<double>& A, int n) {
+    std::vector<double> I((size_t)n * n, 0.0);
+    for (int i = 0; i < n; ++i) I[(size_t)i * n + i] = 1.0;
+    for (int c = 0; c < n; ++c) {
+        int p = c;
+        for (int r = c + 1; r < n; ++r)
+            if (std::fabs(A[(size_t)r * n + c]) > std::fabs(A[(size_t)p * n + c])) p = r;
+        const double piv = A[(size_t)p * n + c];
+        if (!(std::fabs(piv) > 0.0) || !std::isfinite(piv)) return false;
+        if (p != c)
+            for (int k = 0; k < n; ++k) {
+                std::swap(A[(size_t)p * n + k], A[(size_t)c * n + k]);
+                std::swap(I[(size_t)p * n + k], I[(size_t)c * n + k]);
+            }
+        const double ip = 1.0 / piv;
+        for (int k = 0; k < n; ++k) { A[(size_t)c * n + k] *= ip; I[(size_t)c * n + k] *= ip; }
+        for (int r = 0; r < n; ++r) {
+            if (r == c) continue;
+            const double f = A[(size_t)r * n + c];
+            if (f == 0.0) continue;
+            for (int k = 0; k < n; ++k) {
+                A[(size_t)r * n + k] -= f * A[(size_t)c * n + k];
+                I[(size_t)r * n + k] -= f * I[(size_t)c * n + k];
+            }
+        }
+    }
+    A.swap(I);
+    return true;
+}
+
+// Element diagonal block B of the slab Jacobian of a linear equation and its
+// inverse, for this handle's (mesh spacing, N, Nt, equation) and dt.  B is
+// read off the operator kernel applied to the npe unit vectors of element 0
+// of a periodic 3^d-element mesh with the same spacing (so the element's
+// neighbours are distinct elements and B excludes their coupling); every
+// element of the uniform mesh has the same block.
+static int ensure_precond(st_ctx* h, double dt, hipStream_t st) {
+    const Problem& pb = h->pb;
+    if (!linear_eq(pb.eq.kind))
+        return set_error(ST_ERR_UNSUPPORTED, "element-block Jacobi is available for the linear equations only");
+    const int npe = (int)(pb.nv * pb.Nt * pb.ns);
+    if (h->binvT && h->pc_dt == dt) return ST_OK;
+    st_mesh_t m3 = pb.mesh;
+    for (int a = 0; a < 3; ++a) {
+        m3.K[a] = a < pb.mesh.dim ? 3 : 1;
+        m3.lo[a] = 0.0;
+        m3.hi[a] = a < pb.mesh.dim ? 3.0 * pb.h[a] : 1.0;
+    }
+    Problem pp;
+    CHK(make_problem(&m3, pb.N, pb.Nt, &pb.eq, pp));
+    const int Gp = op_blocks(pp);
+    const int64_t np = pp.n;
+    double *din = nullptr, *dout = nullptr;
+    OpSeg* dsegs = nullptr;
+    auto cleanup = [&] {
+        if (din) (void)hipFree(din);
+        if (dout) (void)hipFree(dout);
+        if (dsegs) (void)hipFree(dsegs);
+    };
+    std::vector<OpSeg> segs(npe);
+    for (int c = 0; c < npe; ++c) {
+        OpSeg s = base_opseg(pp, dt);
+        s.blk0 = c * Gp;
+        s.nblk = Gp;
+        segs[c] = s;
+    }
+    if (hipMalloc((void**)&din, sizeof(double) * np * npe) != hipSuccess ||
+        hipMalloc((void**)&dout, sizeof(double) * np * npe) != hipSuccess ||
+        hipMalloc((void**)&dsegs, sizeof(OpSeg) * npe) != hipSuccess) {
+        cleanup();
+        return set_error(ST_ERR_HIP, "preconditioner setup: device allocation failed");
+    }
+    for (int c = 0; c < npe; ++c) {
+        segs[c].U = dptr(din + (size_t)c * np);
+        segs[c].uprev = nullptr;
+        segs[c].out = dptr(dout + (size_t)c * np);
+    }
+    std::vector<double> B((size_t)npe * npe);
+    hipError_t e = hipMemcpyAsync(dsegs, segs.data(), sizeof(OpSeg) * npe, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipMemsetAsync(din, 0, sizeof(double) * np * npe, st);
+    if (e == hipSuccess) {
+        pc_set_units(din, np, npe, st);           // unit vector c at unknown c of element 0
+        pb.ops->res64(dsegs, npe, npe * Gp, st);  // linear: R(v) with u_prev = 0 is J v
+        e = hipGetLastError();
+    }
+    // element 0's block of every response: column c of B
+    if (e == hipSuccess)
+        e = hipMemcpy2DAsync(B.data(), sizeof(double) * npe, dout, sizeof(double) * np, sizeof(double) * npe, npe,
+                             hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    cleanup();
+    if (e != hipSuccess) return set_error(ST_ERR_HIP, std::string("preconditioner setup: ") + hipGetErrorString(e));
+    // the copy holds B^T (row c = response to unit c); transpose to row-major B
+    std::vector<double> Bm((size_t)npe * npe);
+    for (int i = 0; i < npe; ++i)
+        for (int c = 0; c < npe; ++c) Bm[(size_t)i * npe + c] = B[(size_t)c * npe + i];
+    if (!invert_dense(Bm, npe)) return set_error(ST_ERR_UNSUPPORTED, "element block of the Jacobian is singular");
+    // column-major B^-1 for the kernel
+    std::vector<double> BT((size_t)npe * npe);
+    for (int i = 0; i < npe; ++i)
+        for (int j = 0; j < npe; ++j) BT[(size_t)j * npe + i] = Bm[(size_t)i * npe + j];
+    if (!h->binvT) {
+        CHK(h->alloc(&h->binvT, (size_t)npe * npe));
+        CHK(h->alloc(&h->pz, pb.n));
+        CHK(h->alloc(&h->d_pc, 2));
+    }
+    HIPCHK(hipMemcpy(h->binvT, BT.data(), sizeof(double) * npe * npe, hipMemcpyHostToDevice));
+    h->pc_dt = dt;
+    return ST_OK;
+}
+
 extern "C" {
 
 const char* st_version(void) { return "stdg 0.1 (gfx950)"; }
@@ -331,6 +450,7 @@ void st_default_opts(st_solver_opts_t* o) {
     o->inner_fp32 = 0;
     o->gmres_rtol = 1e-3;
     o->timing = 0;
+    o->precond = 0;
 }
 
 int st_lgl(int n, double* x, double* w, double* D) {
@@ -535,12 +655,15 @@ int st_solve_slab(st_handle_t h, const double* u_prev, double t0, double dt, dou
     if (o.restart < 1 || o.restart > MMAX) return set_error(ST_ERR_BAD_ARG, "restart must be in 1..32");
     if (o.cgs_passes < 1 || o.cgs_passes > 2) return set_error(ST_ERR_BAD_ARG, "cgs_passes must be 1 or 2");
     if (o.max_newton < 1) return set_error(ST_ERR_BAD_ARG, "max_newton must be >= 1");
+    if (o.precond < 0 || o.precond > 1) return set_error(ST_ERR_BAD_ARG, "precond must be 0 or 1");
     const Problem& pb = h->pb;
     const bool fp32 = o.inner_fp32 != 0;
     const int m = o.restart;
     CHK(ensure_solve(h, m));
     if (fp32) CHK(ensure_fp32(h));
     hipStream_t st = (hipStream_t)stream;
+    const bool pc = o.precond == 1;
+    if (pc) CHK(ensure_precond(h, dt, st));
     const int kind = pb.eq.kind;
     const int Gop = op_blocks(pb);
 
@@ -593,7 +716,30 @@ int st_solve_slab(st_handle_t h, const double* u_prev, double t0, double dt, dou
     // Arnoldi index; the whole segment is skipped once the cycle is done
     const int* kp = &h->d_st->k;
     const int* skip = &h->d_st->done;
-    setup_jvp(h, h->U, dptr_k(h->V, pb.n, kp), h->w, skip, fp32, dt, 4, st);
+    // right preconditioning: the JVP takes z = B^-1 V_k, formed per step
+    setup_jvp(h, h->U, pc ? dptr(h->pz) : dptr_k(h->V, pb.n, kp), h->w, skip, fp32, dt, 4, st);
+    const int npe = (int)(pb.nv * pb.Nt * pb.ns);
+    const int Gpc = pc ? pc_blocks((int)pb.E, npe) : 0;
+    if (pc) {
+        PcSeg a;
+        std::memset(&a, 0, sizeof(a));
+        a.in = dptr_k(h->V, pb.n, kp);
+        a.out = h->pz;
+        a.binvT = h->binvT;
+        a.skip = skip;
+        a.npe = npe;
+        a.E = (int)pb.E;
+        a.accumulate = 0;
+        a.blk0 = 0;
+        a.nblk = Gpc;
+        put_pcseg(h->d_pc + 0, a, st);
+        PcSeg u = a;                     // Newton update: U += B^-1 (V y), V y staged in w
+        u.in = dptr(h->w);
+        u.out = h->U;
+        u.skip = nullptr;
+        u.accumulate = 1;
+        put_pcseg(h->d_pc + 1, u, st);
+    }
     if (fp32 && grad_pass(pb) && !linear_eq(kind)) {
         OpSeg g = base_opseg(pb, dt);
         g.U = dptr(h->U32);
@@ -632,6 +778,7 @@ int st_solve_slab(st_handle_t h, const double* u_prev, double t0, double dt, dou
         }
         T.run(ST_K_NORMALIZE, st, [&] { vk_scale_v0(h->d_vs, 1, Gv, st); });
         for (int k = 0; k < m; ++k) {
+            if (pc) T.run(ST_K_PRECOND, st, [&] { pc_apply(h->d_pc + 0, 1, Gpc, npe, st); });
             launch_jvp(h, fp32, 4, st);
             for (int p = 0; p < o.cgs_passes; ++p) {
                 T.run(ST_K_MULTIDOT, st, [&] { vk_multidot(h->d_vs, 1, Gv, k, st); });
@@ -640,7 +787,12 @@ int st_solve_slab(st_handle_t h, const double* u_prev, double t0, double dt, dou
         }
         T.run(ST_K_NEWTON, st, [&] {
             vk_finish(h->d_vs, 1, st);
-            vk_update_u(h->d_vs, 1, Gv, st);
+            if (pc) {
+                pc_combine(h->d_vs, 1, Gv, st);
+                pc_apply(h->d_pc + 1, 1, Gpc, npe, st);
+            } else {
+                vk_update_u(h->d_vs, 1, Gv, st);
+            }
         }, false);
         HIPCHK(hipGetLastError());
     }
@@ -663,6 +815,7 @@ int st_solve_slab(st_handle_t h, const double* u_prev, double t0, double dt, dou
             const double d = pb.mesh.dim;
             stats->kernel_bytes[ST_K_GRAD] = (outer + 1) * n8 * (1.0 + d) + its * n8 * (1.0 + (fp32 ? 0.5 : 1.0) * d);
         }
+        if (pc) stats->kernel_bytes[ST_K_PRECOND] = (its + outer) * 2.0 * n8;   // direction in, z out
         stats->kernel_bytes[ST_K_MULTIDOT] = h->h_st->kbytes[3] * o.cgs_passes;
         stats->kernel_bytes[ST_K_UPDATE] = h->h_st->kbytes[4] * o.cgs_passes;
         stats->newton_its = outer;

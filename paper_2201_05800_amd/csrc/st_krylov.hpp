@@ -20,6 +20,15 @@ void vk_update_u(const VecSeg* s, int nseg, int G, hipStream_t st);
 void vk_init_guess(const VecSeg* s, int nseg, int G, hipStream_t st);
 void vk_extract_last(const VecSeg* s, int nseg, int G, hipStream_t st);
 void vk_cast32(const VecSeg* s, int nseg, int G, hipStream_t st);
+// element-block Jacobi (st_precond.hip): elements per block, launch, and
+// w = sum_{i < kfinal} y_i V_i for the preconditioned Newton update
+int pc_eb(int npe);                 // elements per block for npe unknowns per element
+int pc_blocks(int E, int npe);
+// every segment of one launch has the same npe
+void pc_apply(const PcSeg* s, int nseg, int G, int npe, hipStream_t st);
+void pc_combine(const VecSeg* s, int nseg, int G, hipStream_t st);
+void pc_set_units(double* x, int64_t ld, int count, hipStream_t st);
+void put_pcseg(PcSeg* dst, const PcSeg& v, hipStream_t st);
 void put_opseg(OpSeg* dst, const OpSeg& v, hipStream_t st);
 void put_vecseg(VecSeg* dst, const VecSeg& v, hipStream_t st);
 

@@ -109,6 +109,7 @@ int check_opts(const st_solver_opts_t& o) {
     if (o.restart < 1 || o.restart > MMAX) return set_error(ST_ERR_BAD_ARG, "restart must be in 1..32");
     if (o.cgs_passes < 1 || o.cgs_passes > 2) return set_error(ST_ERR_BAD_ARG, "cgs_passes must be 1 or 2");
     if (o.max_newton < 1) return set_error(ST_ERR_BAD_ARG, "max_newton must be >= 1");
+    if (o.precond != 0) return set_error(ST_ERR_UNSUPPORTED, "preconditioning is available in st_solve_slab only");
     return ST_OK;
 }
 

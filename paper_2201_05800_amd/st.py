@@ -26,8 +26,8 @@ ST_ERR_NOT_FOUND = -7
 ST_ERR_CANCELLED = -8
 
 ST_ADVECTION, ST_ADVDIFF_BR1, ST_BURGERS, ST_EULER, ST_NS_BR1 = 1, 2, 3, 4, 5
-ST_K_RESIDUAL, ST_K_JVP, ST_K_GRAD, ST_K_MULTIDOT, ST_K_UPDATE, ST_K_NORMALIZE, ST_K_NEWTON = range(7)
-KERNEL_CLASSES = ("residual", "jvp", "grad", "multidot", "update", "normalize", "newton")
+ST_K_RESIDUAL, ST_K_JVP, ST_K_GRAD, ST_K_MULTIDOT, ST_K_UPDATE, ST_K_NORMALIZE, ST_K_NEWTON, ST_K_PRECOND = range(8)
+KERNEL_CLASSES = ("residual", "jvp", "grad", "multidot", "update", "normalize", "newton", "precond")
 
 _c_double_p = ctypes.POINTER(ctypes.c_double)
 
@@ -44,7 +44,8 @@ class Equation(ctypes.Structure):
 
 class SolverOpts(ctypes.Structure):
     _fields_ = [("restart", ctypes.c_int), ("max_newton", ctypes.c_int), ("cgs_passes", ctypes.c_int),
-                ("inner_fp32", ctypes.c_int), ("gmres_rtol", ctypes.c_double), ("timing", ctypes.c_int)]
+                ("inner_fp32", ctypes.c_int), ("gmres_rtol", ctypes.c_double), ("timing", ctypes.c_int),
+                ("precond", ctypes.c_int)]
 
 
 class Stats(ctypes.Structure):

@@ -1,0 +1,101 @@
+"""Element-block Jacobi right preconditioning of the slab GMRES (linear
+equations): the preconditioned solve reaches the oracle's slab solution
+(the same system, so the same solution within the slab tolerance) in far
+fewer Arnoldi steps, in FP64 and with FP32-inner JVPs; it is rejected for
+the nonlinear equations and by the server."""
+import sys
+
+import numpy as np
+import pytest
+
+from gpu_common import Pair, cfg, gpu_solve, rel
+from paper_2201_05800_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def fourier_init(P):
+    X = P.coords()
+    return inputs.fourier_modes(X, inputs.fourier_params(2, dim=P.c["dim"])).ravel()
+
+
+CASES = [
+    # C2 shape on a smaller periodic box with the same h, dt, N, Nt
+    ("advdiff2d-16", cfg("advdiff", 2, [16, 16], 4, 4, hi=[0.25, 0.25], a=(1.0, 0.5), nu=1e-3), 1.0 / 128),
+    # ragged sizes, other degrees
+    ("advdiff2d-11x7-N3Nt3", cfg("advdiff", 2, [11, 7], 3, 3, a=(1.0, 0.5), nu=1e-3), 1.0 / 40),
+    # 1D advection (C1 shape)
+    ("adv1d-16", cfg("adv", 1, [16], 3, 3, a=(1.0,)), 1.0 / 32),
+    # 3D, 500 unknowns per element (the 8-element-per-block kernel)
+    ("advdiff3d-4x3x5-N4Nt4", cfg("advdiff", 3, [4, 3, 5], 4, 4, a=(1.0, 0.5, -0.25), nu=1e-3), 1.0 / 64),
+]
+
+
+@pytest.mark.parametrize("name,c,dt", CASES, ids=[x[0] for x in CASES])
+@pytest.mark.parametrize("fp32", [0, 1], ids=["fp64", "fp32inner"])
+def test_preconditioned_solve_matches_oracle(orc, name, c, dt, fp32):
+    P = Pair(c)
+    try:
+        up = fourier_init(P) if c["dim"] > 1 else np.sin(2 * np.pi * P.coords()[:, 0, :]).ravel()
+        tol = 1e-11
+        say(f"[{name} fp32={fp32}] preconditioned and plain solves, n={P.n}")
+        U1, un1, s1 = gpu_solve(P, up, dt, tol, inner_fp32=fp32, precond=1)
+        U0, un0, s0 = gpu_solve(P, up, dt, tol, inner_fp32=fp32, precond=0)
+        Uo, so = orc.solve(P.p, up, dt, tol=1e-13, dense_limit=0)
+        e1, e0 = rel(U1, Uo), rel(U0, Uo)
+        say(f"  precond: outer {s1['newton_its']} gmres {s1['gmres_its']} err {e1:.2e};  "
+            f"plain: outer {s0['newton_its']} gmres {s0['gmres_its']} err {e0:.2e}")
+        assert e1 <= 1e-9 and e0 <= 1e-9
+        # the oracle's residual of the preconditioned solution meets the tolerance
+        rn = np.linalg.norm(orc.residual(P.p, U1, up, dt))
+        assert rn <= 1.01 * tol * max(1.0, s1["res0"])
+        assert s1["gmres_its"] * 2 <= s0["gmres_its"], "preconditioning should cut the Arnoldi steps"
+        assert np.array_equal(un1, U1.reshape(P.E, P.nv, c["Nt"], P.ns)[:, :, -1, :].ravel())
+    finally:
+        P.close()
+
+
+def test_preconditioned_solve_is_deterministic_and_reuses_the_block():
+    P = Pair(cfg("advdiff", 2, [16, 16], 4, 4, hi=[0.25, 0.25], a=(1.0, 0.5), nu=1e-3))
+    try:
+        up = fourier_init(P)
+        a = gpu_solve(P, up, 1.0 / 128, 1e-10, precond=1)
+        b = gpu_solve(P, up, 1.0 / 128, 1e-10, precond=1)      # block cached for this dt
+        c = gpu_solve(P, up, 1.0 / 256, 1e-10, precond=1)      # new dt: block rebuilt
+        d = gpu_solve(P, up, 1.0 / 128, 1e-10, precond=1)      # back: rebuilt again
+        assert np.array_equal(a[0], b[0]) and np.array_equal(a[0], d[0])
+        assert not np.array_equal(a[0], c[0])
+    finally:
+        P.close()
+
+
+def test_preconditioning_rejected_where_unavailable():
+    from paper_2201_05800_amd import st
+    P = Pair(cfg("burgers", 1, [16], 3, 3))
+    try:
+        up = inputs.burgers_smooth(P.coords(), inputs.burgers_params(1)).ravel()
+        with pytest.raises(st.StError) as ei:
+            gpu_solve(P, up, 0.01, 1e-10, precond=1)
+        assert ei.value.code == st.ST_ERR_UNSUPPORTED
+        with pytest.raises(st.StError) as ei:
+            gpu_solve(P, up, 0.01, 1e-10, precond=2)
+        assert ei.value.code == st.ST_ERR_BAD_ARG
+    finally:
+        P.close()
+    srv = st.st_server_create(hbm_budget_bytes=1 << 28, max_active=2)
+    try:
+        c = cfg("advdiff", 2, [8, 8], 3, 3, a=(1.0, 0.5), nu=1e-3)
+        d = c["dim"]
+        r = st.request(st.mesh(d, c["K"], c["lo"], c["hi"]), c["N"], c["Nt"],
+                       st.equation(c["kind"], a=c["a"][:d], nu=c["nu"]), np.zeros(64 * 16), 0.0, 0.01, 1e-10,
+                       st.st_default_opts(precond=1))
+        with pytest.raises(st.StError) as ei:
+            st.st_submit(srv, r)
+        assert ei.value.code == st.ST_ERR_UNSUPPORTED
+    finally:
+        st.st_server_destroy(srv)
