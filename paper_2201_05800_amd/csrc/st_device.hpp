@@ -337,7 +337,7 @@ struct VecSeg {
 struct PcSeg {
     DynPtr in;            // input vector (may follow the Arnoldi index)
     double* out;
-    const double* binvT;  // B^-1 column-major: binvT[j * npe + i] = (B^-1)_{ij}
+    const double* binvT;  // B^-1 packed by pc_pack (matrix-core operand order)
     const int* skip;      // skip the segment when *skip != 0 (may be null)
     int npe;              // unknowns per element
     int E;                // elements

@@ -367,6 +367,7 @@ static int ensure_precond(st_ctx* h, double dt, hipStream_t st) {
     if (!linear_eq(pb.eq.kind))
         return set_error(ST_ERR_UNSUPPORTED, "element-block Jacobi is available for the linear equations only");
     const int npe = (int)(pb.nv * pb.Nt * pb.ns);
+    if (npe > PC_NPE_MAX) return set_error(ST_ERR_UNSUPPORTED, "element block larger than the preconditioner supports");
     if (h->binvT && h->pc_dt == dt) return ST_OK;
     st_mesh_t m3 = pb.mesh;
     for (int a = 0; a < 3; ++a) {
@@ -423,16 +424,14 @@ static int ensure_precond(st_ctx* h, double dt, hipStream_t st) {
     for (int i = 0; i < npe; ++i)
         for (int c = 0; c < npe; ++c) Bm[(size_t)i * npe + c] = B[(size_t)c * npe + i];
     if (!invert_dense(Bm, npe)) return set_error(ST_ERR_UNSUPPORTED, "element block of the Jacobian is singular");
-    // column-major B^-1 for the kernel
-    std::vector<double> BT((size_t)npe * npe);
-    for (int i = 0; i < npe; ++i)
-        for (int j = 0; j < npe; ++j) BT[(size_t)j * npe + i] = Bm[(size_t)i * npe + j];
+    // B^-1 in the kernel's matrix-core operand order
+    const std::vector<double> packed = pc_pack(Bm, npe);
     if (!h->binvT) {
-        CHK(h->alloc(&h->binvT, (size_t)npe * npe));
+        CHK(h->alloc(&h->binvT, packed.size()));
         CHK(h->alloc(&h->pz, pb.n));
         CHK(h->alloc(&h->d_pc, 2));
     }
-    HIPCHK(hipMemcpy(h->binvT, BT.data(), sizeof(double) * npe * npe, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(h->binvT, packed.data(), sizeof(double) * packed.size(), hipMemcpyHostToDevice));
     h->pc_dt = dt;
     return ST_OK;
 }

@@ -12,6 +12,8 @@
 // pivoting); the kernels here apply B^-1 to every element of a vector.
 #include "st_krylov.hpp"
 
+#include <algorithm>
+
 namespace stdg {
 
 namespace {
@@ -32,56 +34,178 @@ DI int find_pseg(const Seg* segs, int nseg, int b) {
     }
     return lo;
 }
-constexpr int PC_BLOCK = 256;               // threads: 4 groups of 64
-constexpr int PC_NPE_LARGE = 192;           // above: 8 elements per block (LDS)
+constexpr int PC_BLOCK = 256;               // 4 wavefronts
+constexpr int PC_EB = 16;                   // elements per block (the MFMA column count)
+constexpr int PC_TW = 8;                    // row tiles per wavefront at most (npe <= 512)
+constexpr int PC_KC = 4;                    // column steps per operand chunk
+typedef double v4d __attribute__((ext_vector_type(4)));
 }  // namespace
 
-int pc_eb(int npe) { return npe <= PC_NPE_LARGE ? 16 : 8; }
-int pc_blocks(int E, int npe) { return (E + pc_eb(npe) - 1) / pc_eb(npe); }
+int pc_blocks(int E, int npe) {
+    (void)npe;
+    return (E + PC_EB - 1) / PC_EB;
+}
 
-// out_e (+)= B^-1 in_e for PC_EB elements per block.  The block's inputs are
-// staged in LDS transposed (unknown-major, element-fastest); wavefront g of
-// the block takes elements [g PC_EG, (g+1) PC_EG) and, lane by lane, the rows
-// of B^-1 (read column by column from L2, coalesced across the lanes).
-template <int PC_EB>
+// out_e (+)= B^-1 in_e for 16 elements per block, as the dense product
+// Z = B^-1 [in_e0 ... in_e15] on the FP64 matrix cores
+// (v_mfma_f64_16x16x4f64: A 16x4 with A[i][k] in lane i + 16k, B 4x16 with
+// B[k][j] in lane j + 16k, D 16x16 with D[i][j] in lane j + 16 (i mod 4),
+// register i div 4).  B^-1 comes packed per (16-row tile, 4-column step) in
+// that A-operand lane order (zero padded), so each operand is one coalesced
+// load; the block's inputs are staged in LDS in B-operand order; wavefront w
+// takes the row tiles w, w + 4, ...; the result goes back through LDS for
+// coalesced stores.
 __global__ __launch_bounds__(PC_BLOCK) void k_bjacobi(const PcSeg* __restrict__ segs, int nseg) {
-    constexpr int PC_EG = PC_EB / 4;        // elements per wavefront
-    extern __shared__ double tileT[];       // [npe][PC_EB]
+    extern __shared__ double sm[];           // [KS * 64] B operands, then [16][npe | 1] results
     const PcSeg& sg = segs[find_pseg(segs, nseg, blockIdx.x)];
     if (sg.skip && *(const __attribute__((address_space(1))) int*)sg.skip) return;
     const int npe = sg.npe;
+    const int KS = (npe + 3) >> 2, T = (npe + 15) >> 4;
     const int e0 = (blockIdx.x - sg.blk0) * PC_EB;
     const int ne = min(PC_EB, sg.E - e0);
     const double* inb = static_cast<const double*>(sg.in.base);
     if (sg.in.kp) inb += (int64_t)(*(const __attribute__((address_space(1))) int*)sg.in.kp + sg.in.koff) * sg.in.ld;
     const auto* __restrict__ in = gp(inb) + (int64_t)e0 * npe;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const auto* __restrict__ A = gp(sg.binvT);
+    const int TQ = (T - wave + 3) >> 2;      // row tiles of this wavefront
+    // A operands of column steps [ks0, ks0 + PC_KC), double buffered: the
+    // next chunk's loads are in flight while the current chunk multiplies
+    auto load_chunk = [&](int ks0, double (&a)[PC_KC][PC_TW]) {
+#pragma unroll
+        for (int c = 0; c < PC_KC; ++c)
+#pragma unroll
+            for (int q = 0; q < PC_TW; ++q) {
+                const int ks = ks0 + c, rt = wave + 4 * q;
+                a[c][q] = (q < TQ && ks < KS) ? A[((int64_t)rt * KS + ks) * 64 + lane] : 0.0;
+            }
+    };
+    v4d acc[PC_TW];
+#pragma unroll
+    for (int q = 0; q < PC_TW; ++q) acc[q] = v4d{0.0, 0.0, 0.0, 0.0};
+    auto mul_chunk = [&](int ks0, const double (&a)[PC_KC][PC_TW]) {
+#pragma unroll
+        for (int c = 0; c < PC_KC; ++c) {
+            const int ks = ks0 + c;
+            if (ks >= KS) break;
+            const double b = sm[ks * 64 + lane];
+#pragma unroll
+            for (int q = 0; q < PC_TW; ++q)
+                if (q < TQ) acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[c][q], b, acc[q], 0, 0, 0);
+        }
+    };
+    double a0[PC_KC][PC_TW], a1[PC_KC][PC_TW];
+    load_chunk(0, a0);                        // overlaps the staging below
+    for (int t = threadIdx.x; t < KS * 64; t += PC_BLOCK) sm[t] = 0.0;
+    __syncthreads();
+    // element-fastest thread order: consecutive lanes write consecutive LDS
+    // words (B-operand order), reads stay within the block's 16 elements
     for (int t = threadIdx.x; t < PC_EB * npe; t += PC_BLOCK) {
-        const int e = t / npe, j = t - e * npe;          // coalesced over the block's contiguous inputs
-        tileT[j * PC_EB + e] = e < ne ? in[t] : 0.0;
+        const int j = t & (PC_EB - 1), c = t >> 4;
+        if (j < ne) sm[(c >> 2) * 64 + j + 16 * (c & 3)] = in[(int64_t)j * npe + c];
     }
     __syncthreads();
-    const int lane = threadIdx.x & 63, g = threadIdx.x >> 6;
-    const auto* __restrict__ B = gp(sg.binvT);
-    auto* __restrict__ out = gp(sg.out) + (int64_t)e0 * npe;
-    for (int r = lane; r < npe; r += 64) {
-        double acc[PC_EG];
+    for (int ks0 = 0; ks0 < KS; ks0 += 2 * PC_KC) {
+        load_chunk(ks0 + PC_KC, a1);
+        mul_chunk(ks0, a0);
+        if (ks0 + PC_KC >= KS) break;
+        load_chunk(ks0 + 2 * PC_KC, a0);
+        mul_chunk(ks0 + PC_KC, a1);
+    }
+    __syncthreads();                         // B operands consumed: reuse sm for the results
+    const int SR = npe | 1;                  // odd row stride: no LDS bank conflicts across j
 #pragma unroll
-        for (int q = 0; q < PC_EG; ++q) acc[q] = 0.0;
-#pragma unroll 4
-        for (int j = 0; j < npe; ++j) {
-            const double b = B[(int64_t)j * npe + r];
-            const double* tv = tileT + j * PC_EB + g * PC_EG;
+    for (int q = 0; q < PC_TW; ++q) {
+        const int rt = wave + 4 * q;
+        if (rt < T) {
 #pragma unroll
-            for (int q = 0; q < PC_EG; ++q) acc[q] += b * tv[q];
-        }
-#pragma unroll
-        for (int q = 0; q < PC_EG; ++q) {
-            const int e = g * PC_EG + q;
-            if (e < ne) {
-                const int64_t i = (int64_t)e * npe + r;
-                out[i] = sg.accumulate ? out[i] + acc[q] : acc[q];
+            for (int r = 0; r < 4; ++r) {
+                const int row = rt * 16 + (lane >> 4) + 4 * r, j = lane & 15;
+                if (row < npe) sm[j * SR + row] = acc[q][r];
             }
         }
+    }
+    __syncthreads();
+    auto* __restrict__ out = gp(sg.out) + (int64_t)e0 * npe;
+    for (int t = threadIdx.x; t < ne * npe; t += PC_BLOCK) {
+        const int j = t / npe, row = t - j * npe;
+        double z = sm[j * SR + row];
+        if (sg.accumulate) z += out[t];
+        out[t] = z;
+    }
+}
+
+// Small blocks (npe <= 128, at most 8 row tiles): the 4 wavefronts split the
+// column steps instead of the row tiles, so every wavefront runs all row
+// tiles as independent accumulation chains over a quarter of the steps (short
+// dependent chains on the matrix cores), with its A operands loaded in one
+// go; the four partial products are added in a fixed order through LDS.
+__global__ __launch_bounds__(PC_BLOCK) void k_bjacobi_ks(const PcSeg* __restrict__ segs, int nseg) {
+    extern __shared__ double sm[];           // [KS * 64] B operands, then partials [4][16][16 T + 1]
+    const PcSeg& sg = segs[find_pseg(segs, nseg, blockIdx.x)];
+    if (sg.skip && *(const __attribute__((address_space(1))) int*)sg.skip) return;
+    const int npe = sg.npe;
+    const int KS = (npe + 3) >> 2, T = (npe + 15) >> 4;
+    const int KW = (KS + 3) >> 2;            // column steps per wavefront (<= 8)
+    const int e0 = (blockIdx.x - sg.blk0) * PC_EB;
+    const int ne = min(PC_EB, sg.E - e0);
+    const double* inb = static_cast<const double*>(sg.in.base);
+    if (sg.in.kp) inb += (int64_t)(*(const __attribute__((address_space(1))) int*)sg.in.kp + sg.in.koff) * sg.in.ld;
+    const auto* __restrict__ in = gp(inb) + (int64_t)e0 * npe;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const auto* __restrict__ A = gp(sg.binvT);
+    double a[8][PC_TW];
+#pragma unroll
+    for (int c = 0; c < 8; ++c)
+#pragma unroll
+        for (int q = 0; q < PC_TW; ++q) {
+            const int ks = wave * KW + c;
+            a[c][q] = (q < T && c < KW && ks < KS) ? A[((int64_t)q * KS + ks) * 64 + lane] : 0.0;
+        }
+    for (int t = threadIdx.x; t < KS * 64; t += PC_BLOCK) sm[t] = 0.0;
+    __syncthreads();
+    // element-fastest thread order: consecutive lanes write consecutive LDS
+    // words (B-operand order), reads stay within the block's 16 elements
+    for (int t = threadIdx.x; t < PC_EB * npe; t += PC_BLOCK) {
+        const int j = t & (PC_EB - 1), c = t >> 4;
+        if (j < ne) sm[(c >> 2) * 64 + j + 16 * (c & 3)] = in[(int64_t)j * npe + c];
+    }
+    __syncthreads();
+    v4d acc[PC_TW];
+#pragma unroll
+    for (int q = 0; q < PC_TW; ++q) acc[q] = v4d{0.0, 0.0, 0.0, 0.0};
+    double b[8];
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+        const int ks = wave * KW + c;
+        b[c] = (c < KW && ks < KS) ? sm[ks * 64 + lane] : 0.0;
+    }
+#pragma unroll
+    for (int c = 0; c < 8; ++c)
+#pragma unroll
+        for (int q = 0; q < PC_TW; ++q)
+            if (q < T && c < KW) acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[c][q], b[c], acc[q], 0, 0, 0);
+    __syncthreads();                         // B operands consumed: reuse sm for the partials
+    const int NR = 16 * T + 1;               // odd row stride: no LDS bank conflicts across j
+#pragma unroll
+    for (int q = 0; q < PC_TW; ++q)
+        if (q < T) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int row = q * 16 + (lane >> 4) + 4 * r, j = lane & 15;
+                sm[(wave * 16 + j) * NR + row] = acc[q][r];
+            }
+        }
+    __syncthreads();
+    auto* __restrict__ out = gp(sg.out) + (int64_t)e0 * npe;
+    for (int t = threadIdx.x; t < ne * npe; t += PC_BLOCK) {
+        const int j = t / npe, row = t - j * npe;
+        double z = sm[j * NR + row];
+        z += sm[(16 + j) * NR + row];
+        z += sm[(32 + j) * NR + row];
+        z += sm[(48 + j) * NR + row];
+        if (sg.accumulate) z += out[t];
+        out[t] = z;
     }
 }
 
@@ -120,10 +244,14 @@ __global__ void k_set_units(double* x, int64_t ld, int count) {
 __global__ void k_put_pcseg(PcSeg* dst, PcSeg v) { if (threadIdx.x == 0 && blockIdx.x == 0) *dst = v; }
 
 void pc_apply(const PcSeg* s, int nseg, int G, int npe, hipStream_t st) {
-    const int eb = pc_eb(npe);
-    const size_t shm = sizeof(double) * (size_t)eb * npe;
-    if (eb == 16) launch_ks(k_bjacobi<16>, dim3(G), dim3(PC_BLOCK), shm, st, s, nseg);
-    else launch_ks(k_bjacobi<8>, dim3(G), dim3(PC_BLOCK), shm, st, s, nseg);
+    const int KS = (npe + 3) / 4, T = (npe + 15) / 16;
+    if (T <= PC_TW && (KS + 3) / 4 <= 8) {
+        const size_t shm = sizeof(double) * std::max<size_t>(64 * (size_t)KS, 4 * 16 * (16 * (size_t)T + 1));
+        launch_ks(k_bjacobi_ks, dim3(G), dim3(PC_BLOCK), shm, st, s, nseg);
+    } else {
+        const size_t shm = sizeof(double) * std::max<size_t>(64 * (size_t)KS, 16 * (size_t)(npe | 1));
+        launch_ks(k_bjacobi, dim3(G), dim3(PC_BLOCK), shm, st, s, nseg);
+    }
 }
 void pc_combine(const VecSeg* s, int nseg, int G, hipStream_t st) {
     launch_k(k_combine, dim3(G), dim3(VBLOCK), st, s, nseg);
@@ -135,4 +263,21 @@ void put_pcseg(PcSeg* dst, const PcSeg& v, hipStream_t st) {
     launch_k(k_put_pcseg, dim3(1), dim3(64), st, dst, v);
 }
 
+}  // namespace stdg
+
+namespace stdg {
+// Operand order of k_bjacobi: for row tile rt (16 rows) and column step ks
+// (4 columns), 64 values in lane order, lane l holding
+// (B^-1)[16 rt + l mod 16][4 ks + l div 16], zero outside npe x npe.
+std::vector<double> pc_pack(const std::vector<double>& binv, int npe) {
+    const int KS = (npe + 3) / 4, T = (npe + 15) / 16;
+    std::vector<double> a((size_t)T * KS * 64, 0.0);
+    for (int rt = 0; rt < T; ++rt)
+        for (int ks = 0; ks < KS; ++ks)
+            for (int l = 0; l < 64; ++l) {
+                const int row = rt * 16 + (l & 15), col = ks * 4 + (l >> 4);
+                if (row < npe && col < npe) a[((size_t)rt * KS + ks) * 64 + l] = binv[(size_t)row * npe + col];
+            }
+    return a;
+}
 }  // namespace stdg
