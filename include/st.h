@@ -104,7 +104,7 @@ typedef struct {
 enum {
     ST_K_RESIDUAL = 0,  /* residual operator kernel                          */
     ST_K_JVP = 1,       /* Jacobian-vector product operator kernel           */
-    ST_K_GRAD = 2,      /* BR1 lifted-gradient kernels                       */
+    ST_K_GRAD = 2,      /* Navier-Stokes viscous pass (BR1 gradient, Fv)     */
     ST_K_MULTIDOT = 3,  /* Gram-Schmidt projections (fused multi-dot)        */
     ST_K_UPDATE = 4,    /* Gram-Schmidt correction + Givens + normalisation  */
     ST_K_NORMALIZE = 5, /* first Krylov vector V_0 = -R / ||R||              */
@@ -123,7 +123,7 @@ typedef struct {
     double kernel_us[8];  /* summed event time per timed kernel class */
     int kernel_calls[8];  /* timed launches per kernel class          */
     double kernel_bytes[8];  /* algorithmic bytes moved per kernel class (launches  */
-                             /* that did work; BR1 gradient: input + output)        */
+                             /* that did work; viscous pass: input + output)        */
 } st_stats_t;
 
 typedef struct st_ctx* st_handle_t;

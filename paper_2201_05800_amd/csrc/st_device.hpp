@@ -1,12 +1,9 @@
-// st_device.hpp -- device-side types and pointwise physics for the
-// space-time DG-SEM slab kernels (gfx950).
-//
-// Pointwise physics of eq. (general) without source: convective flux Fc,
-// its largest wave speed (for the Rusanov flux, eq. (flux:llf)), and the
-// viscous flux Fv(u, grad u) evaluated from the BR1 lifted gradient of the
-// conservative variables.  Everything is templated on the scalar so that the
-// same code gives residuals (double / float) and exact Jacobian-vector
-// products (forward-mode dual numbers Dual<double> / Dual<float>).
+// st_device.hpp -- device-side types of the space-time DG-SEM slab kernels
+// (gfx950): kernel timing hook, forward-mode dual numbers (the pointwise
+// physics in st_ops_impl.hpp is templated on the scalar, so the same code
+// gives residuals in double / float and exact Jacobian-vector products in
+// Dual<double> / Dual<float>), equation parameters, launch descriptors and
+// the device-resident GMRES state.
 #pragma once
 #include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
@@ -146,107 +143,6 @@ struct EqParams {
 };
 
 // ---------------------------------------------------------------------------
-// pointwise physics
-// ---------------------------------------------------------------------------
-template <int EQ, int D, class T>
-struct Phys {
-    using S = typename BaseOf<T>::type;
-    static constexpr int R = nvars_of(EQ, D);
-
-    // convective flux along axis a
-    SDI void conv(int a, const T* u, T* f, const EqParams& P) {
-        if constexpr (EQ == EQ_ADV || EQ == EQ_ADVDIFF) {
-            f[0] = u[0] * S(P.a[a]);
-        } else if constexpr (EQ == EQ_BURGERS) {
-            f[0] = S(0.5) * (u[0] * u[0]);
-        } else {
-            const S gm1 = S(P.gamma) - S(1);
-            T rinv = S(1) / u[0];
-            T ke = u[1] * u[1];
-#pragma unroll
-            for (int b = 1; b < D; ++b) ke = ke + u[1 + b] * u[1 + b];
-            T p = gm1 * (u[D + 1] - S(0.5) * (ke * rinv));
-            T va = u[1 + a] * rinv;
-#pragma unroll
-            for (int b = 0; b < D; ++b) f[1 + b] = va * u[1 + b];
-            f[1 + a] = f[1 + a] + p;
-            f[0] = u[1 + a];
-            f[D + 1] = (u[D + 1] + p) * va;
-        }
-    }
-
-    // largest characteristic speed along axis a
-    SDI T speed(int a, const T* u, const EqParams& P) {
-        if constexpr (EQ == EQ_ADV || EQ == EQ_ADVDIFF) {
-            T r;
-            r = make_state<T>(S(fabs(P.a[a])), S(0));
-            return r;
-        } else if constexpr (EQ == EQ_BURGERS) {
-            return absval(u[0]);
-        } else {
-            const S g = S(P.gamma);
-            T rinv = S(1) / u[0];
-            T ke = u[1] * u[1];
-#pragma unroll
-            for (int b = 1; b < D; ++b) ke = ke + u[1 + b] * u[1 + b];
-            T p = (g - S(1)) * (u[D + 1] - S(0.5) * (ke * rinv));
-            T c = sqrt_(g * p * rinv);
-            return absval(u[1 + a] * rinv) + c;
-        }
-    }
-
-    // viscous flux along axis a; q[b * R + v] = d u_v / d x_b
-    SDI void visc(int a, const T* u, const T* q, T* f, const EqParams& P) {
-        if constexpr (EQ == EQ_ADVDIFF) {
-            f[0] = q[a] * S(P.nu);
-        } else if constexpr (EQ == EQ_NS) {
-            const S g = S(P.gamma);
-            const S mu = S(P.mu);
-            T rinv = S(1) / u[0];
-            T vel[D];
-#pragma unroll
-            for (int b = 0; b < D; ++b) vel[b] = u[1 + b] * rinv;
-            T ke = vel[0] * u[1];
-#pragma unroll
-            for (int b = 1; b < D; ++b) ke = ke + vel[b] * u[1 + b];
-            T p = (g - S(1)) * (u[D + 1] - S(0.5) * ke);
-            T Tm = p * rinv;
-            T v2 = vel[0] * vel[0];
-#pragma unroll
-            for (int b = 1; b < D; ++b) v2 = v2 + vel[b] * vel[b];
-            // velocity gradient gv[b][c] = d v_c / d x_b and temperature gradient
-            T gv[D][D];
-            T gT[D];
-#pragma unroll
-            for (int b = 0; b < D; ++b) {
-                const T gr = q[b * R];
-                T vgm = vel[0] * q[b * R + 1];
-#pragma unroll
-                for (int c = 0; c < D; ++c) {
-                    gv[b][c] = (q[b * R + 1 + c] - vel[c] * gr) * rinv;
-                    if (c > 0) vgm = vgm + vel[c] * q[b * R + 1 + c];
-                }
-                T gp = (g - S(1)) * (q[b * R + D + 1] - vgm + S(0.5) * (v2 * gr));
-                gT[b] = (gp - Tm * gr) * rinv;
-            }
-            T div = gv[0][0];
-#pragma unroll
-            for (int c = 1; c < D; ++c) div = div + gv[c][c];
-            f[0] = make_state<T>(S(0), S(0));
-            T work = make_state<T>(S(0), S(0));
-#pragma unroll
-            for (int c = 0; c < D; ++c) {
-                T tau = mu * (gv[a][c] + gv[c][a]);
-                if (c == a) tau = tau - (S(2) / S(3)) * mu * div;
-                f[1 + c] = tau;
-                work = work + tau * vel[c];
-            }
-            f[D + 1] = work + S(P.kappa) * gT[a];
-        }
-    }
-};
-
-// ---------------------------------------------------------------------------
 // launch descriptors
 // ---------------------------------------------------------------------------
 // GMRES state of one slab solve (device resident).
@@ -288,8 +184,9 @@ struct OpSeg {
     DynPtr U;            // state (double or float)
     DynPtr V;            // direction (JVP only), double
     const double* uprev; // previous-slab state (residual), may be null = 0
-    DynPtr Q;            // gradient of U (viscous)
-    DynPtr dQ;           // gradient of V (viscous JVP)
+    DynPtr Q;            // NS: -Fv along every axis from the viscous pass (its
+                         // tangent for a JVP)
+    DynPtr dQ;           // unused
     DynPtr out;          // double output
     const int* skip;     // skip the segment when *skip != 0 (may be null)
     int K[3];

@@ -207,10 +207,9 @@ struct st_ctx {
     VecSeg* d_vs = nullptr;     // 1 vector descriptor slot
     GState* d_st = nullptr;
     double* d_part = nullptr;
-    double* Q = nullptr;        // gradient of U (viscous)
-    double* dQ = nullptr;       // gradient of the direction (viscous JVP)
+    double* Q = nullptr;        // NS: -Fv of U along every axis (residual)
+    double* dQ = nullptr;       // NS: its tangent in the JVP direction
     float* U32 = nullptr;
-    float* Q32 = nullptr;
     float* dQ32 = nullptr;
     double* V = nullptr;        // Krylov basis (m vectors)
     double* w = nullptr;
@@ -297,10 +296,7 @@ static int ensure_fp32(st_ctx* h) {
     const Problem& pb = h->pb;
     if (h->U32) return ST_OK;
     CHK(h->alloc(&h->U32, pb.n));
-    if (grad_pass(pb)) {
-        CHK(h->alloc(&h->Q32, (size_t)pb.n * pb.mesh.dim));
-        CHK(h->alloc(&h->dQ32, (size_t)pb.n * pb.mesh.dim));
-    }
+    if (grad_pass(pb)) CHK(h->alloc(&h->dQ32, (size_t)pb.n * pb.mesh.dim));
     return ST_OK;
 }
 
@@ -531,7 +527,7 @@ int st_residual(st_handle_t h, const double* U, const double* u_prev, double t0,
         g.U = dptr(U);
         g.out = dptr(h->Q);
         put_opseg(h->d_op + 0, g, st);
-        pb.ops->grad64(h->d_op + 0, 1, G, st);
+        pb.ops->visc_res64(h->d_op + 0, 1, G, st);
         s.Q = dptr(h->Q);
     }
     s.U = dptr(U);
@@ -548,9 +544,10 @@ int st_residual(st_handle_t h, const double* U, const double* u_prev, double t0,
 namespace stdg {
 
 // Jv for the handle's problem, in two halves: upload the descriptors (slots
-// `slot`, `slot + 1`) and launch the kernels.  U: double state (U32 / Q32 must
-// hold the FP32 copies when inner_fp32 and the equation is nonlinear, Q must
-// hold grad U for NS); the direction may follow the Arnoldi index.
+// `slot`, `slot + 1`) and launch the kernels.  U: double state (U32 must hold
+// the FP32 copy when inner_fp32 and the equation is nonlinear); the direction
+// may follow the Arnoldi index.  NS: the viscous pass writes the tangent of
+// -Fv at (U, v) to dQ (dQ32), which the JVP kernel reads.
 void setup_jvp(st_ctx* h, const double* U, DynPtr V, double* out, const int* skip, bool fp32, double dt,
                int slot, hipStream_t st) {
     const Problem& pb = h->pb;
@@ -558,9 +555,11 @@ void setup_jvp(st_ctx* h, const double* U, DynPtr V, double* out, const int* ski
     OpSeg s = base_opseg(pb, dt);
     s.skip = skip;
     s.out = dptr(out);
+    const DynPtr state = dptr(fp32 ? (const void*)h->U32 : (const void*)U);
     if (grad_pass(pb)) {
         OpSeg g = s;
-        g.U = V;
+        g.U = state;
+        g.V = V;
         g.out = dptr(fp32 ? (void*)h->dQ32 : (void*)h->dQ);
         put_opseg(h->d_op + slot, g, st);
     }
@@ -568,14 +567,10 @@ void setup_jvp(st_ctx* h, const double* U, DynPtr V, double* out, const int* ski
         // J v = R(v) with u_prev = 0
         s.U = V;
         s.uprev = nullptr;
-        if (grad_pass(pb)) s.Q = dptr(fp32 ? (void*)h->dQ32 : (void*)h->dQ);
     } else {
-        s.U = dptr(fp32 ? (const void*)h->U32 : (const void*)U);
+        s.U = state;
         s.V = V;
-        if (grad_pass(pb)) {
-            s.Q = dptr(fp32 ? (void*)h->Q32 : (void*)h->Q);
-            s.dQ = dptr(fp32 ? (void*)h->dQ32 : (void*)h->dQ);
-        }
+        if (grad_pass(pb)) s.Q = dptr(fp32 ? (void*)h->dQ32 : (void*)h->dQ);
     }
     put_opseg(h->d_op + slot + 1, s, st);
 }
@@ -585,38 +580,27 @@ void launch_jvp(st_ctx* h, bool fp32, int slot, hipStream_t st) {
     const int G = op_blocks(pb);
     const int kind = pb.eq.kind;
     if (grad_pass(pb))
-        h->timer.run(ST_K_GRAD, st, [&] { (fp32 ? pb.ops->grad64to32 : pb.ops->grad64)(h->d_op + slot, 1, G, st); });
+        h->timer.run(ST_K_GRAD, st, [&] { (fp32 ? pb.ops->visc_jvp32 : pb.ops->visc_jvp64)(h->d_op + slot, 1, G, st); });
     h->timer.run(ST_K_JVP, st, [&] {
         if (linear_eq(kind)) (fp32 ? pb.ops->lin32 : pb.ops->res64)(h->d_op + slot + 1, 1, G, st);
         else (fp32 ? pb.ops->jvp32 : pb.ops->jvp64)(h->d_op + slot + 1, 1, G, st);
     });
 }
 
-// FP32 copies of U (and grad U for NS) for FP32-inner JVPs; grad U (FP64) for
-// the FP64 NS JVP.  Uses the vector slot for the cast.
-void enqueue_jvp_prepare(st_ctx* h, const double* U, bool fp32, double dt, int slot, hipStream_t st) {
+// FP32 copy of U for FP32-inner JVPs of the nonlinear equations (uses the
+// vector slot for the cast).
+void enqueue_jvp_prepare(st_ctx* h, const double* U, bool fp32, hipStream_t st) {
     const Problem& pb = h->pb;
-    const int kind = pb.eq.kind;
-    if (linear_eq(kind)) return;
-    const int G = op_blocks(pb);
-    if (fp32) {
-        VecSeg v;
-        std::memset(&v, 0, sizeof(v));
-        v.U = const_cast<double*>(U);
-        v.U32 = h->U32;
-        v.n = pb.n;
-        v.nblk = vec_blocks(pb.n);
-        v.st = h->d_st;
-        put_vecseg(h->d_vs, v, st);
-        vk_cast32(h->d_vs, 1, v.nblk, st);
-    }
-    if (grad_pass(pb)) {
-        OpSeg g = base_opseg(pb, dt);
-        g.U = dptr(fp32 ? (const void*)h->U32 : (const void*)U);
-        g.out = dptr(fp32 ? (void*)h->Q32 : (void*)h->Q);
-        put_opseg(h->d_op + slot, g, st);
-        (fp32 ? pb.ops->grad32 : pb.ops->grad64)(h->d_op + slot, 1, G, st);
-    }
+    if (linear_eq(pb.eq.kind) || !fp32) return;
+    VecSeg v;
+    std::memset(&v, 0, sizeof(v));
+    v.U = const_cast<double*>(U);
+    v.U32 = h->U32;
+    v.n = pb.n;
+    v.nblk = vec_blocks(pb.n);
+    v.st = h->d_st;
+    put_vecseg(h->d_vs, v, st);
+    vk_cast32(h->d_vs, 1, v.nblk, st);
 }
 
 }  // namespace stdg
@@ -633,7 +617,7 @@ int st_jvp(st_handle_t h, const double* U, double t0, double dt, const double* v
     const bool fp32 = inner_fp32 != 0;
     if (fp32) CHK(ensure_fp32(h));
     h->timer.reset(0);
-    enqueue_jvp_prepare(h, U, fp32, dt, 2, st);
+    enqueue_jvp_prepare(h, U, fp32, st);
     setup_jvp(h, U, dptr(v), Jv, nullptr, fp32, dt, 3, st);
     launch_jvp(h, fp32, 3, st);
     HIPCHK(hipGetLastError());
@@ -739,12 +723,6 @@ int st_solve_slab(st_handle_t h, const double* u_prev, double t0, double dt, dou
         u.accumulate = 1;
         put_pcseg(h->d_pc + 1, u, st);
     }
-    if (fp32 && grad_pass(pb) && !linear_eq(kind)) {
-        OpSeg g = base_opseg(pb, dt);
-        g.U = dptr(h->U32);
-        g.out = dptr(h->Q32);
-        put_opseg(h->d_op + 2, g, st);
-    }
 
     int status = ST_ERR_NO_CONVERGENCE;
     int outer = 0;
@@ -752,7 +730,7 @@ int st_solve_slab(st_handle_t h, const double* u_prev, double t0, double dt, dou
     int stall = 0;
     auto& T = h->timer;
     for (;;) {
-        if (grad_pass(pb)) T.run(ST_K_GRAD, st, [&] { pb.ops->grad64(h->d_op + 0, 1, Gop, st); });
+        if (grad_pass(pb)) T.run(ST_K_GRAD, st, [&] { pb.ops->visc_res64(h->d_op + 0, 1, Gop, st); });
         T.run(ST_K_RESIDUAL, st, [&] { pb.ops->res64(h->d_op + 1, 1, Gop, st); });
         T.run(ST_K_NEWTON, st, [&] {
             vk_rnorm(h->d_vs, 1, Gv, st);
@@ -769,12 +747,8 @@ int st_solve_slab(st_handle_t h, const double* u_prev, double t0, double dt, dou
         if (rn < 0.9 * best) { best = rn; stall = 0; }
         else if (++stall >= 8) break;     // no progress over 8 outer iterations
         ++outer;
-        // Jacobian base point: the FP32 copy of U (and grad U32 for NS); the
-        // FP64 NS JVP reuses grad U from the residual evaluation above
-        if (fp32 && !linear_eq(kind)) {
-            T.run(ST_K_NEWTON, st, [&] { vk_cast32(h->d_vs, 1, Gv, st); });
-            if (grad_pass(pb)) T.run(ST_K_GRAD, st, [&] { pb.ops->grad32(h->d_op + 2, 1, Gop, st); });
-        }
+        // Jacobian base point of FP32-inner JVPs: the FP32 copy of U
+        if (fp32 && !linear_eq(kind)) T.run(ST_K_NEWTON, st, [&] { vk_cast32(h->d_vs, 1, Gv, st); });
         T.run(ST_K_NORMALIZE, st, [&] { vk_scale_v0(h->d_vs, 1, Gv, st); });
         for (int k = 0; k < m; ++k) {
             if (pc) T.run(ST_K_PRECOND, st, [&] { pc_apply(h->d_pc + 0, 1, Gpc, npe, st); });
@@ -812,7 +786,10 @@ int st_solve_slab(st_handle_t h, const double* u_prev, double t0, double dt, dou
         stats->kernel_bytes[ST_K_JVP] = its * jvp_b;
         if (visc) {
             const double d = pb.mesh.dim;
-            stats->kernel_bytes[ST_K_GRAD] = (outer + 1) * n8 * (1.0 + d) + its * n8 * (1.0 + (fp32 ? 0.5 : 1.0) * d);
+            // viscous pass: residual reads U, writes d values per unknown; JVP
+            // reads U and v, writes d tangent values per unknown
+            stats->kernel_bytes[ST_K_GRAD] =
+                (outer + 1) * n8 * (1.0 + d) + its * n8 * ((fp32 ? 1.5 : 2.0) + (fp32 ? 0.5 : 1.0) * d);
         }
         if (pc) stats->kernel_bytes[ST_K_PRECOND] = (its + outer) * 2.0 * n8;   // direction in, z out
         stats->kernel_bytes[ST_K_MULTIDOT] = h->h_st->kbytes[3] * o.cgs_passes;

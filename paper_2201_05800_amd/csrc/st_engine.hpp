@@ -20,8 +20,8 @@ struct Problem {
     double Dx[64], wx[8], xi[8], Dt[16], wt[4];
 };
 
-// the operator needs a separate lifted-gradient pass (Navier-Stokes BR1)
-inline bool grad_pass(const Problem& pb) { return pb.ops->grad64 != nullptr; }
+// the operator needs the viscous pass first (Navier-Stokes BR1)
+inline bool grad_pass(const Problem& pb) { return pb.ops->visc_res64 != nullptr; }
 
 inline int op_blocks(const Problem& pb) {
     return (int)((pb.E + pb.ops->epb - 1) / pb.ops->epb);

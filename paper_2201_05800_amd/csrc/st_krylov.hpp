@@ -43,9 +43,10 @@ struct OpTable {
     OpLaunch lin32;      // linear equations: R(v) with u_prev = 0 in FP32 (FP32-inner JVP)
     OpLaunch jvp64;      // nonlinear JVP, FP64
     OpLaunch jvp32;      // nonlinear JVP, FP32 state and arithmetic
-    OpLaunch grad64;     // BR1 gradient double -> double
-    OpLaunch grad32;     // BR1 gradient float -> float
-    OpLaunch grad64to32; // BR1 gradient double -> float
+    // Navier-Stokes viscous pass (BR1 gradient, then -Fv along every axis):
+    OpLaunch visc_res64; // of U (double), for the residual
+    OpLaunch visc_jvp64; // its tangent at (U, v), double
+    OpLaunch visc_jvp32; // its tangent at (U32, v), float
 };
 
 void register_ops_adv(std::vector<OpTable>& t);

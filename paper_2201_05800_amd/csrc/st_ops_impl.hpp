@@ -1,5 +1,8 @@
 // st_ops_impl.hpp -- slab operator kernels: residual, Jacobian-vector
-// product and BR1 lifted gradient, for one (equation, dim, N+1, Nt).
+// product and the Navier-Stokes viscous pass, for one (equation, dim, N+1,
+// Nt); pointwise physics of eq. (general) without source (convective flux,
+// its largest wave speed for the Rusanov flux, viscous flux from the BR1
+// lifted gradient of the conservative variables).
 //
 // Thread mapping: one thread per space-time node (element, time node,
 // spatial node), so a thread holds one state of R variables.  A block holds
@@ -283,7 +286,8 @@ struct Flux {
 // central viscous flux through a face needs only the neighbour's normal
 // derivative at the face node, which the face-point thread forms from the
 // neighbour's line of nodes normal to the face.  Navier-Stokes reads the
-// lifted gradient of U (and of v) from the gradient pass (k_grad).
+// viscous part of the total flux, own and the neighbours' at face nodes,
+// from the viscous pass (k_visc).
 // ---------------------------------------------------------------------------
 template <int EQ, int D, int N1, int NT, class CT, class UT, bool JVP>
 __global__ __launch_bounds__((Shape<D, N1, NT, tpt_of(EQ, NT)>::BS)) void k_op(const OpSeg* __restrict__ segs,
@@ -323,8 +327,9 @@ __global__ __launch_bounds__((Shape<D, N1, NT, tpt_of(EQ, NT)>::BS)) void k_op(c
 
     const gptr<UT> __restrict__ Up = resolve<UT>(sg.U);
     const gptr<double> __restrict__ Vp = JVP ? resolve<double>(sg.V) : nullptr;
+    // NS: the viscous part of the total flux, -Fv along every axis (its
+    // tangent for a JVP), from the viscous pass (k_visc)
     const gptr<CT> __restrict__ Qp = NSV ? resolve<CT>(sg.Q) : nullptr;
-    const gptr<CT> __restrict__ dQp = (NSV && JVP) ? resolve<CT>(sg.dQ) : nullptr;
     const gptr<double> __restrict__ out = resolve<double>(sg.out);
     const gptr<const double> __restrict__ upv = (gptr<const double>)sg.uprev;
 
@@ -337,16 +342,16 @@ __global__ __launch_bounds__((Shape<D, N1, NT, tpt_of(EQ, NT)>::BS)) void k_op(c
             else u[v] = CT(Ue[v * NPE + rr]);
         }
     };
-    auto load_grad = [&](int ee, int rr, T* q) {
-        const int64_t base = (int64_t)ee * (D * EV);
+    // add to the stored part of x (the value for a residual, the tangent for a JVP)
+    auto add_part = [](T& x, CT g) {
+        if constexpr (JVP) x.d += g;
+        else x += g;
+    };
+    // -Fv along axis a at element node rr of element ee
+    auto load_visc = [&](int ee, int rr, int a, CT* g) {
+        const gptr<CT> Qe = Qp + (int64_t)ee * (D * EV);
 #pragma unroll
-        for (int b = 0; b < D; ++b)
-#pragma unroll
-            for (int v = 0; v < R; ++v) {
-                const int off = (b * R + v) * NPE + rr;
-                if constexpr (JVP) q[b * R + v] = make_state<T>((Qp + base)[off], (dQp + base)[off]);
-                else q[b * R + v] = (Qp + base)[off];
-            }
+        for (int v = 0; v < R; ++v) g[v] = Qe[(a * R + v) * NPE + rr];
     };
 
     // Face points: (axis a, element, side, time group, face node), axis-major
@@ -376,11 +381,12 @@ __global__ __launch_bounds__((Shape<D, N1, NT, tpt_of(EQ, NT)>::BS)) void k_op(c
         return fi;
     };
     // neighbour data of a face point: AD the neighbour's normal line from
-    // the face node inwards; otherwise its state (and gradient)
+    // the face node inwards; otherwise its state (and NS: its -Fv along the
+    // face axis)
     struct FPD {
         CT line[AD ? TPT : 1][AD ? N1 : 1];
         T un[AD ? 1 : TPT][R];
-        T qn[NSV ? TPT : 1][NSV ? D * R : 1];
+        CT gn[NSV ? TPT : 1][NSV ? R : 1];
     };
     auto fp_load = [&](const FPI& fi, FPD& d) {
         if (!fi.ok) return;
@@ -395,7 +401,7 @@ __global__ __launch_bounds__((Shape<D, N1, NT, tpt_of(EQ, NT)>::BS)) void k_op(c
 #pragma unroll
             for (int jj = 0; jj < TPT; ++jj) {
                 load_state(fi.en, fi.rn0 + jj * NS, d.un[jj]);
-                if constexpr (NSV) load_grad(fi.en, fi.rn0 + jj * NS, d.qn[jj]);
+                if constexpr (NSV) load_visc(fi.en, fi.rn0 + jj * NS, fi.a, d.gn[jj]);
             }
         }
     };
@@ -439,8 +445,8 @@ __global__ __launch_bounds__((Shape<D, N1, NT, tpt_of(EQ, NT)>::BS)) void k_op(c
                     const typename F::Prim w = F::prim(un, P);
                     F::conv(ax, un, w, fn, P);
                     if constexpr (NSV) {
-                        const typename F::Visc z = F::visc_state(w, d.qn[jj], P);
-                        F::sub_visc(ax, w, z, fn, P);
+#pragma unroll
+                        for (int v = 0; v < R; ++v) add_part(fn[v], d.gn[jj][v]);
                     }
                     const T lo = F::speed(ax, uo, F::prim(uo, P), P), ln = F::speed(ax, un, w, P);
                     const T lam = right ? larger(lo, ln) : larger(ln, lo);
@@ -457,19 +463,21 @@ __global__ __launch_bounds__((Shape<D, N1, NT, tpt_of(EQ, NT)>::BS)) void k_op(c
     };
 
     // (0) tables to LDS; every global load of the block issued at once: own
-    //     states (and NS gradient), AD neighbour face values, the data of
+    //     states (and NS: own -Fv), AD neighbour face values, the data of
     //     this thread's first face point
     if (tid < N1 * N1) sD[tid] = CT(sg.Dx[tid]);
     if (tid < NT * NT) sDt[tid] = CT(sg.Dt[tid]);
     if (tid < NT) swt[tid] = CT(sg.wt[tid]);
     T u[TPT][R];
-    T q[NSV ? TPT : 1][NSV ? D * R : 1];
+    CT gv[NSV ? TPT : 1][NSV ? D : 1][NSV ? R : 1];    // own -Fv, every axis
     CT unb[AD ? D : 1][AD ? TPT : 1];
     if (active) {
 #pragma unroll
         for (int jj = 0; jj < TPT; ++jj) {
             load_state(e, r0 + jj * NS, u[jj]);
-            if constexpr (NSV) load_grad(e, r0 + jj * NS, q[jj]);
+            if constexpr (NSV)
+#pragma unroll
+                for (int a = 0; a < D; ++a) load_visc(e, r0 + jj * NS, a, gv[jj][a]);
         }
         if constexpr (AD) {
             const ECoord x = ecoord(sg, e);
@@ -538,13 +546,13 @@ __global__ __launch_bounds__((Shape<D, N1, NT, tpt_of(EQ, NT)>::BS)) void k_op(c
 #pragma unroll
             for (int jj = 0; jj < TPT; ++jj) {
                 const typename F::Prim w = F::prim(u[jj], P);
-                typename F::Visc z;
-                if constexpr (NSV) z = F::visc_state(w, q[jj], P);
                 static_for<0, D>([&](auto A) {
                     constexpr int a = decltype(A)::value;
                     T f[R];
                     F::conv(a, u[jj], w, f, P);
-                    if constexpr (NSV) F::sub_visc(a, w, z, f, P);
+                    if constexpr (NSV)
+#pragma unroll
+                        for (int v = 0; v < R; ++v) add_part(f[v], gv[jj][a][v]);
 #pragma unroll
                     for (int v = 0; v < R; ++v) buf[(a * R + v) * NN + nd0 + jj * NS] = part(f[v]);
                 });
@@ -634,21 +642,31 @@ __global__ __launch_bounds__((Shape<D, N1, NT, tpt_of(EQ, NT)>::BS)) void k_op(c
 }
 
 // ---------------------------------------------------------------------------
-// BR1 lifted gradient of the conservative variables (strong form):
+// Navier-Stokes viscous pass.  The BR1 lifted gradient of the conservative
+// variables (strong form),
 //   q_b = (2/h_b) [ sum_k D_{i_b,k} u_k + M^-1 B (u_hat - u) ],  u_hat = {u},
-// for every time node (no viscous flux in time).  Same block shape as k_op.
-// Output layout Q[((e * D + b) * R + v) * Nt + j) * ns + s], type CT.
+// for every time node (no viscous flux in time), and from it the viscous part
+// of the total flux, -Fv(u, q), along every axis, which k_op adds to the
+// convective flux at its own nodes and reads for the neighbours' face nodes.
+// JVP = true: the tangent of -Fv at (U, v) by dual numbers (U of type UT, v
+// double).  Output out[((e * D + a) * R + v) * Nt + j) * ns + s], type CT.
+// Same block shape and traversal as k_op.
 // ---------------------------------------------------------------------------
-template <int D, int N1, int NT, int R, class CT, class UT>
-__global__ __launch_bounds__((Shape<D, N1, NT, 1>::BS)) void k_grad(const OpSeg* __restrict__ segs, int nseg, int G) {
+template <int D, int N1, int NT, class CT, class UT, bool JVP>
+__global__ __launch_bounds__((Shape<D, N1, NT, 1>::BS)) void k_visc(const OpSeg* __restrict__ segs, int nseg, int G) {
     using SH = Shape<D, N1, NT, 1>;
+    using T = typename std::conditional<JVP, Dual<CT>, CT>::type;
+    using F = Flux<EQ_NS, D, T>;
+    constexpr int R = D + 2;
     constexpr int NS = SH::NS, NPE = SH::NPE, EPB = SH::EPB, B = SH::B;
     constexpr int EV = R * NPE;
-    __shared__ CT tile[R * B];
+    constexpr int TS = JVP ? 2 : 1;
+    __shared__ CT tile[TS * R * B];             // [plane][v][node]
     __shared__ CT sD[N1 * N1];
     const int L = xcd_remap(blockIdx.x, G);
     const OpSeg& sg = segs[find_seg(segs, nseg, L)];
     if (sg.skip && *(const gptr<const int>)sg.skip) return;
+    const EqParams& P = sg.P;
     const int tid = threadIdx.x;
     const int el = (int)((unsigned)tid / NPE);
     const int r = tid - el * NPE;
@@ -657,55 +675,84 @@ __global__ __launch_bounds__((Shape<D, N1, NT, 1>::BS)) void k_grad(const OpSeg*
     const int e = e0 + el;
     const bool active = (tid < B) && (e < sg.E);
     const gptr<UT> __restrict__ Up = resolve<UT>(sg.U);
+    const gptr<double> __restrict__ Vp = JVP ? resolve<double>(sg.V) : nullptr;
     const gptr<CT> __restrict__ Qp = resolve<CT>(sg.out);
+    auto load_state = [&](int ee, int rr, T* u) {
+        const gptr<UT> Ue = Up + (int64_t)ee * EV;
+#pragma unroll
+        for (int v = 0; v < R; ++v) {
+            if constexpr (JVP) u[v] = make_state<T>(CT(Ue[v * NPE + rr]), CT((Vp + (int64_t)ee * EV)[v * NPE + rr]));
+            else u[v] = CT(Ue[v * NPE + rr]);
+        }
+    };
 
     if (tid < N1 * N1) sD[tid] = CT(sg.Dx[tid]);
-    CT u[R];
-    CT un[D][R];
+    T u[R];
+    T un[D][R];
     if (active) {
-        const gptr<UT> Ue = Up + (int64_t)e * EV;
-#pragma unroll
-        for (int v = 0; v < R; ++v) u[v] = CT(Ue[v * NPE + r]);
+        load_state(e, r, u);
         const ECoord x = ecoord(sg, e);
         static_for<0, D>([&](auto B_) {
             constexpr int b = decltype(B_)::value;
             const int ib = coord<N1, b>(s);
             if (ib == 0 || ib == N1 - 1) {
                 const bool right = ib == N1 - 1;
-                const gptr<UT> Un = Up + (int64_t)neighbour(sg, e, x, b, right) * EV +
-                                    (r + ((right ? 0 : N1 - 1) - ib) * ipow(N1, b));
+                load_state(neighbour(sg, e, x, b, right), r + ((right ? 0 : N1 - 1) - ib) * ipow(N1, b), un[b]);
+            } else {
 #pragma unroll
-                for (int v = 0; v < R; ++v) un[b][v] = CT(Un[v * NPE]);
+                for (int v = 0; v < R; ++v) un[b][v] = u[v];   // interior: the lift below vanishes exactly
             }
         });
 #pragma unroll
-        for (int v = 0; v < R; ++v) tile[v * B + tid] = u[v];
+        for (int v = 0; v < R; ++v) {
+            tile[v * B + tid] = value(u[v]);
+            if constexpr (JVP) tile[(R + v) * B + tid] = part(u[v]);
+        }
     }
     __syncthreads();
     if (!active) return;
-    const CT wl = CT(1) / CT(sg.wx[0]);
-    const gptr<CT> Qe = Qp + (int64_t)e * (D * EV);
+    const CT iw0 = CT(1) / CT(sg.wx[0]);
+    T q[D * R];
     static_for<0, D>([&](auto B_) {
         constexpr int b = decltype(B_)::value;
         constexpr int stride = ipow(N1, b);
         const int ib = coord<N1, b>(s);
-        const bool face = (ib == 0 || ib == N1 - 1);
         CT Drow[N1];
 #pragma unroll
         for (int k = 0; k < N1; ++k) Drow[k] = sD[ib * N1 + k];
         const CT J = CT(sg.rh[b]);
+        const CT lw = ib == N1 - 1 ? iw0 : (ib == 0 ? -iw0 : CT(0));
 #pragma unroll
         for (int v = 0; v < R; ++v) {
             const CT* ln = tile + v * B + tid - ib * stride;
-            CT g = Drow[0] * ln[0];
+            CT gv = Drow[0] * ln[0];
 #pragma unroll
-            for (int k = 1; k < N1; ++k) g += Drow[k] * ln[k * stride];
-            if (face) {
-                const CT uh = CT(0.5) * (u[v] + un[b][v]);
-                g += (ib == N1 - 1 ? wl : -wl) * (uh - u[v]);
+            for (int k = 1; k < N1; ++k) gv += Drow[k] * ln[k * stride];
+            T g;
+            if constexpr (JVP) {
+                const CT* lt = ln + R * B;
+                CT gt = Drow[0] * lt[0];
+#pragma unroll
+                for (int k = 1; k < N1; ++k) gt += Drow[k] * lt[k * stride];
+                g = make_state<T>(gv, gt);
+            } else {
+                g = gv;
             }
-            Qe[(b * R + v) * NPE + r] = J * g;
+            g = g + lw * (CT(0.5) * (u[v] + un[b][v]) - u[v]);
+            q[b * R + v] = J * g;
         }
+    });
+    const typename F::Prim w = F::prim(u, P);
+    const typename F::Visc z = F::visc_state(w, q, P);
+    const gptr<CT> Qe = Qp + (int64_t)e * (D * EV);
+    static_for<0, D>([&](auto A) {
+        constexpr int a = decltype(A)::value;
+        T f[R];
+#pragma unroll
+        for (int v = 0; v < R; ++v) f[v] = make_state<T>(CT(0), CT(0));
+        F::sub_visc(a, w, z, f, P);
+#pragma unroll
+        for (int v = 0; v < R; ++v) Qe[(a * R + v) * NPE + r] = part(f[v]);
     });
 }
 
@@ -716,14 +763,13 @@ template <int EQ, int D, int N1, int NT, class CT, class UT, bool JVP>
 void launch_op(const OpSeg* segs, int nseg, int G, hipStream_t st) {
     launch_k(k_op<EQ, D, N1, NT, CT, UT, JVP>, dim3(G), dim3(Shape<D, N1, NT, tpt_of(EQ, NT)>::BS), st, segs, nseg, G);
 }
-template <int D, int N1, int NT, int R, class CT, class UT>
-void launch_grad(const OpSeg* segs, int nseg, int G, hipStream_t st) {
-    launch_k(k_grad<D, N1, NT, R, CT, UT>, dim3(G), dim3(Shape<D, N1, NT, 1>::BS), st, segs, nseg, G);
+template <int D, int N1, int NT, class CT, class UT, bool JVP>
+void launch_visc(const OpSeg* segs, int nseg, int G, hipStream_t st) {
+    launch_k(k_visc<D, N1, NT, CT, UT, JVP>, dim3(G), dim3(Shape<D, N1, NT, 1>::BS), st, segs, nseg, G);
 }
 
 template <int EQ, int D, int N1, int NT>
 OpTable make_table() {
-    constexpr int R = nvars_of(EQ, D);
     OpTable t{};
     t.eq = EQ; t.dim = D; t.n1 = N1; t.nt = NT; t.epb = Shape<D, N1, NT, tpt_of(EQ, NT)>::EPB;
     t.res64 = launch_op<EQ, D, N1, NT, double, double, false>;
@@ -734,9 +780,9 @@ OpTable make_table() {
         t.jvp32 = launch_op<EQ, D, N1, NT, float, float, true>;
     }
     if constexpr (EQ == EQ_NS) {
-        t.grad64 = launch_grad<D, N1, NT, R, double, double>;
-        t.grad32 = launch_grad<D, N1, NT, R, float, float>;
-        t.grad64to32 = launch_grad<D, N1, NT, R, float, double>;
+        t.visc_res64 = launch_visc<D, N1, NT, double, double, false>;
+        t.visc_jvp64 = launch_visc<D, N1, NT, double, double, true>;
+        t.visc_jvp32 = launch_visc<D, N1, NT, float, float, true>;
     }
     return t;
 }

@@ -80,7 +80,7 @@ struct Arena {
 };
 
 struct Layout {
-    int64_t U, R, w, V, uprev, unext, Q, dQ, U32, Q32, dQ32, part, total;
+    int64_t U, R, w, V, uprev, unext, Q, dQ, U32, dQ32, part, total;
 };
 
 Layout layout_of(const Problem& pb, const st_solver_opts_t& o) {
@@ -98,7 +98,6 @@ Layout layout_of(const Problem& pb, const st_solver_opts_t& o) {
     L.Q = visc ? take(8 * d * n) : -1;
     L.dQ = visc ? take(8 * d * n) : -1;
     L.U32 = (fp32 && nonlin) ? take(4 * n) : -1;
-    L.Q32 = (fp32 && visc && nonlin) ? take(4 * d * n) : -1;
     L.dQ32 = (fp32 && visc) ? take(4 * d * n) : -1;
     L.part = take(8 * (int64_t)vec_blocks(n) * (NPART_SLOTS + 1));
     L.total = off;
@@ -304,23 +303,22 @@ std::vector<OpGroup> build_jvp_groups(st_srv* s, const std::vector<Req*>& rs) {
         b.out = dptr(r->dp(r->lay.w));
         const int kind = pb.eq.kind;
         void* dQ = f32 ? (void*)r->fp(r->lay.dQ32) : (void*)r->dp(r->lay.dQ);
+        const DynPtr state = dptr(f32 ? (const void*)r->fp(r->lay.U32) : (const void*)r->dp(r->lay.U));
         if (grad_pass(pb)) {
+            // NS viscous pass: tangent of -Fv at (U, v)
             OpSeg gr = b;
-            gr.U = Vk;
+            gr.U = state;
+            gr.V = Vk;
             gr.out = dptr(dQ);
             g->grad.push_back(gr);
         }
         if (linear_eq(kind)) {
             b.U = Vk;
             b.uprev = nullptr;
-            if (grad_pass(pb)) b.Q = dptr(dQ);
         } else {
-            b.U = dptr(f32 ? (const void*)r->fp(r->lay.U32) : (const void*)r->dp(r->lay.U));
+            b.U = state;
             b.V = Vk;
-            if (grad_pass(pb)) {
-                b.Q = dptr(f32 ? (void*)r->fp(r->lay.Q32) : (void*)r->dp(r->lay.Q));
-                b.dQ = dptr(dQ);
-            }
+            if (grad_pass(pb)) b.Q = dptr(dQ);
         }
         g->op.push_back(b);
     }
@@ -409,7 +407,7 @@ bool tick(st_srv* s) {
     char* D0 = s->d_stage[0];
     if (!vfresh.empty()) vk_init_guess((VecSeg*)(D0 + off_vfresh), (int)vfresh.size(), Gfresh, st);
     for (auto& g : rgroups) {
-        if (!g.grad.empty()) g.ops->grad64((OpSeg*)(D0 + g.off_grad), (int)g.grad.size(), g.G, st);
+        if (!g.grad.empty()) g.ops->visc_res64((OpSeg*)(D0 + g.off_grad), (int)g.grad.size(), g.G, st);
         g.ops->res64((OpSeg*)(D0 + g.off_op), (int)g.op.size(), g.G, st);
     }
     vk_rnorm((VecSeg*)(D0 + off_vall), (int)vall.size(), Gall, st);
@@ -477,20 +475,6 @@ bool tick(st_srv* s) {
     for (Req* r : c32) v32.push_back(vecseg_of(s, r));
     const int G32 = assign_blocks(v32);
     const int64_t off_v32 = pb.add(v32);
-    // FP32 gradient of U32 for FP32 NS requests
-    std::vector<OpGroup> g32;
-    for (Req* r : c32) {
-        if (!grad_pass(r->pb)) continue;
-        OpGroup* g = nullptr;
-        for (auto& x : g32)
-            if (x.ops == r->pb.ops) g = &x;
-        if (!g) { g32.push_back(OpGroup{r->pb.ops, true, {}, {}, 0, 0, 0}); g = &g32.back(); }
-        OpSeg gr = base_opseg(r->pb, r->dt);
-        gr.U = dptr(r->fp(r->lay.U32));
-        gr.out = dptr(r->fp(r->lay.Q32));
-        g->grad.push_back(gr);
-    }
-    for (auto& g : g32) { g.G = assign_blocks(g.grad); g.off_grad = pb.add(g.grad); }
     auto jgroups = build_jvp_groups(s, cont);
     for (auto& g : jgroups) {
         g.off_grad = pb.add(g.grad);
@@ -499,7 +483,6 @@ bool tick(st_srv* s) {
     if (upload(s, 1, pb) != ST_OK) return true;
     char* D1 = s->d_stage[1];
     if (!v32.empty()) vk_cast32((VecSeg*)(D1 + off_v32), (int)v32.size(), G32, st);
-    for (auto& g : g32) g.ops->grad32((OpSeg*)(D1 + g.off_grad), (int)g.grad.size(), g.G, st);
     VecSeg* dvc = (VecSeg*)(D1 + off_vc);
     const int nc = (int)vc.size();
     int mmax = 0, passes = 1;
@@ -508,7 +491,7 @@ bool tick(st_srv* s) {
     for (int k = 0; k < mmax; ++k) {
         for (auto& g : jgroups) {
             if (!g.grad.empty())
-                (g.fp32 ? g.ops->grad64to32 : g.ops->grad64)((OpSeg*)(D1 + g.off_grad), (int)g.grad.size(), g.G, st);
+                (g.fp32 ? g.ops->visc_jvp32 : g.ops->visc_jvp64)((OpSeg*)(D1 + g.off_grad), (int)g.grad.size(), g.G, st);
             OpLaunch f = linear_eq(g.ops->eq) ? (g.fp32 ? g.ops->lin32 : g.ops->res64)
                                               : (g.fp32 ? g.ops->jvp32 : g.ops->jvp64);
             f((OpSeg*)(D1 + g.off_op), (int)g.op.size(), g.G, st);
