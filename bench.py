@@ -384,7 +384,7 @@ def main():
                     frac=round(ach / HBM_PEAK_GBS, 4), traffic=None, avg_launch_us=round(us / max(calls, 1), 3),
                     launches=calls, algorithmic_bytes_per_launch=round(by / max(calls, 1)))
 
-    names = {st.ST_K_RESIDUAL: "k_op (residual)", st.ST_K_JVP: "k_op / k_advdiff (JVP)", st.ST_K_GRAD: "k_grad",
+    names = {st.ST_K_RESIDUAL: "k_op (residual)", st.ST_K_JVP: "k_op (JVP)", st.ST_K_GRAD: "k_visc",
              st.ST_K_MULTIDOT: "k_multidot", st.ST_K_UPDATE: "k_update", st.ST_K_NORMALIZE: "k_scale_v0"}
     roof = roof_of(dom, names.get(dom, st.KERNEL_CLASSES[dom]))
     roof["traffic"] = measured_traffic(args.config, roof["kernel"].split(" ")[0])

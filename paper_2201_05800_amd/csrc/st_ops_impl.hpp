@@ -4,8 +4,10 @@
 // its largest wave speed for the Rusanov flux, viscous flux from the BR1
 // lifted gradient of the conservative variables).
 //
-// Thread mapping: one thread per space-time node (element, time node,
-// spatial node), so a thread holds one state of R variables.  A block holds
+// Thread mapping: for the systems one thread per space-time node (element,
+// time node, spatial node), so a thread holds one state of R variables; for
+// the scalar equations one thread per spatial node holds all Nt time nodes
+// (TPT time nodes per thread, tpt_of below).  A block holds
 // EPB consecutive elements, chosen so that the block is a whole number of
 // wavefronts with few idle lanes.  The kernel runs in phases separated by
 // block barriers:
