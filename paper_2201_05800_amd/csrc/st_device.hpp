@@ -48,7 +48,11 @@ __host__ __device__ constexpr int nvars_of(int eq, int dim) {
 }
 __host__ __device__ constexpr bool viscous_eq(int eq) { return eq == EQ_ADVDIFF || eq == EQ_NS; }
 __host__ __device__ constexpr bool linear_eq(int eq) { return eq == EQ_ADV || eq == EQ_ADVDIFF; }
-__host__ __device__ constexpr int ipow(int b, int e) { return e == 0 ? 1 : b * ipow(b, e - 1); }
+__host__ __device__ __forceinline__ constexpr int ipow(int b, int e) {
+    int r = 1;
+    for (int i = 0; i < e; ++i) r *= b;
+    return r;
+}
 
 // ---------------------------------------------------------------------------
 // forward-mode dual numbers  x + x' eps,  eps^2 = 0
@@ -194,7 +198,12 @@ struct OpSeg {
     unsigned dm[2];      // e / K[a] = (e * dm[a]) >> ds[a] for e < 2^31 (a = 0, 1)
     int ds[2];
     int tx, ty;          // block traversal tiles (elements; tx = 0: lexicographic)
+    int tk[4];           // traversal divisors: blocks per tile, per tile layer,
+                         // per tile row; tiles along x
+    unsigned tm[4];      // n / tk[i] = (n * tm[i]) >> ts[i] for n < 2^31
+    int ts[4];
     double rh[3];        // 2 / h_a
+    double iw0;          // 1 / wx[0]: M^-1 B weight of the end nodes
     double dt;
     int blk0;            // first logical block
     int nblk;

@@ -142,6 +142,15 @@ int make_problem(const st_mesh_t* mesh, int N, int Nt, const st_equation_t* eq, 
     return ST_OK;
 }
 
+// division by an invariant integer (Granlund-Montgomery): with 2^k >= d and
+// M = ceil(2^(31+k) / d), floor(n / d) = (n M) >> (31 + k) for 0 <= n < 2^31
+static void div_magic(int d, unsigned& m, int& sh) {
+    int k = 0;
+    while (((uint64_t)1 << k) < (uint64_t)d) ++k;
+    m = (unsigned)((((uint64_t)1 << (31 + k)) + (uint64_t)d - 1) / (uint64_t)d);
+    sh = 31 + k;
+}
+
 OpSeg base_opseg(const Problem& pb, double dt) {
     OpSeg s;
     std::memset(&s, 0, sizeof(s));
@@ -150,15 +159,7 @@ OpSeg base_opseg(const Problem& pb, double dt) {
         s.rh[a] = 2.0 / pb.h[a];
     }
     s.E = (int)pb.E;
-    // division by an invariant integer (Granlund-Montgomery): with 2^k >= d
-    // and M = ceil(2^(31+k) / d), floor(n / d) = (n M) >> (31 + k) for n < 2^31
-    for (int a = 0; a < 2; ++a) {
-        const uint64_t d = (uint64_t)pb.K[a];
-        int k = 0;
-        while (((uint64_t)1 << k) < d) ++k;
-        s.dm[a] = (unsigned)((((uint64_t)1 << (31 + k)) + d - 1) / d);
-        s.ds[a] = 31 + k;
-    }
+    for (int a = 0; a < 2; ++a) div_magic(pb.K[a], s.dm[a], s.ds[a]);
     // Block traversal: columns of tx x ty elements swept through z, each
     // column row by row, so that a face neighbour is met again within a few
     // rows of the column (L2 reuse of halo traces) rather than a whole plane
@@ -178,7 +179,14 @@ OpSeg base_opseg(const Problem& pb, double dt) {
             if (pb.K[1] % c == 0) ty = c;
         s.tx = tx;
         s.ty = ty;
+        const int bx = tx / epb;
+        s.tk[2] = bx;                         // blocks per tile row
+        s.tk[1] = bx * ty;                    // per tile layer
+        s.tk[0] = bx * ty * pb.K[2];          // per tile
+        s.tk[3] = pb.K[0] / tx;               // tiles along x
+        for (int i = 0; i < 4; ++i) div_magic(s.tk[i], s.tm[i], s.ts[i]);
     }
+    s.iw0 = 1.0 / pb.wx[0];
     s.P = pb.P;
     s.dt = dt;
     s.blk0 = 0;

@@ -64,10 +64,16 @@ DI int find_seg(const Seg* segs, int nseg, int L) {
 template <class P>
 using gptr = __attribute__((address_space(1))) P*;
 
+// A flag or index in device memory; a null pointer reads as zero.  Branch
+// free (the pointer is selected, then always loaded), so that a kernel
+// issues the loads of all its descriptor indirections together.
+static __device__ const int k_zero_index = 0;
+DI int load_index(const int* p) { return *(gptr<const int>)(p ? p : &k_zero_index); }
+
 template <class P>
 DI gptr<P> resolve(const DynPtr& d) {
     const P* b = static_cast<const P*>(d.base);
-    if (d.kp) b += (int64_t)(*d.kp + d.koff) * d.ld;
+    b += (int64_t)(load_index(d.kp) + d.koff) * d.ld;       // kp null: koff = 0
     return (gptr<P>)const_cast<P*>(b);
 }
 
@@ -83,10 +89,21 @@ constexpr int best_epb(int npe) {
     return best;
 }
 
+// LDS pitch of one element's NPE nodes in the operator kernels' tiles
+#ifndef ST_LDS_PAD
+#define ST_LDS_PAD 0
+#endif
+constexpr int lds_pitch(int npe) { return npe + ST_LDS_PAD; }
+
 // Time nodes per thread: the scalar equations keep all Nt time nodes of a
 // spatial node in one thread (few registers, index work shared by Nt
 // nodes); the systems take one space-time node per thread (registers).
-__host__ __device__ constexpr int tpt_of(int eq, int nt) { return nvars_of(eq, 1) == 1 ? nt : 1; }
+#ifndef ST_TPT_SCALAR
+#define ST_TPT_SCALAR 0
+#endif
+__host__ __device__ constexpr int tpt_of(int eq, int nt) {
+    return nvars_of(eq, 1) == 1 ? ((ST_TPT_SCALAR > 0 && nt % ST_TPT_SCALAR == 0) ? ST_TPT_SCALAR : nt) : 1;
+}
 
 template <int D, int N1, int NT, int TPT>
 struct Shape {
@@ -102,8 +119,10 @@ struct Shape {
     static constexpr int NFP = EPB * D * 2 * NJ * NF; // face points per block (TPT time nodes each)
 };
 
+template <int B, int E>
+constexpr int ipow_c = ipow(B, E);
 template <int N1, int A>
-DI int coord(int s) { return (int)(((unsigned)s / (unsigned)ipow(N1, A)) % (unsigned)N1); }
+DI int coord(int s) { return (int)(((unsigned)s / (unsigned)ipow_c<N1, A>) % (unsigned)N1); }
 
 // Element coordinates of element e (x fastest) with the descriptor's
 // invariant-divisor constants; element indices fit 31 bits (checked when the
@@ -137,18 +156,15 @@ DI int neighbour(const OpSeg& sg, int e, const ECoord& x, int a, bool right) {
 template <int EPB>
 DI int block_elem0(const OpSeg& sg, int b) {
     if (sg.tx == 0) return b * EPB;
-    const int bx = sg.tx / EPB;                   // blocks per tile row
-    const int per_layer = bx * sg.ty;
-    const int per_tile = per_layer * sg.K[2];
-    const int t = b / per_tile;
-    int rem = b - t * per_tile;
-    const int z = rem / per_layer;
-    rem -= z * per_layer;
-    const int yi = rem / bx;
-    const int xb = rem - yi * bx;
-    const int tiles_x = sg.K[0] / sg.tx;
-    const int tyi = t / tiles_x;
-    const int txi = t - tyi * tiles_x;
+    // divisions by the descriptor's invariant divisors (tk, with tm/ts)
+    const int t = (int)fdiv((unsigned)b, sg.tm[0], sg.ts[0]);      // tile
+    int rem = b - t * sg.tk[0];
+    const int z = (int)fdiv((unsigned)rem, sg.tm[1], sg.ts[1]);    // layer of the tile
+    rem -= z * sg.tk[1];
+    const int yi = (int)fdiv((unsigned)rem, sg.tm[2], sg.ts[2]);   // row of the layer
+    const int xb = rem - yi * sg.tk[2];
+    const int tyi = (int)fdiv((unsigned)t, sg.tm[3], sg.ts[3]);
+    const int txi = t - tyi * sg.tk[3];
     const int x = txi * sg.tx + xb * EPB, y = tyi * sg.ty + yi;
     return x + sg.K[0] * (y + sg.K[1] * z);
 }
@@ -228,38 +244,43 @@ struct Flux {
     }
 
     // Navier-Stokes viscous quantities from the conservative gradient
-    // q[b * R + v] = d u_v / d x_b: velocity gradient gv[b][c] = d v_c / d x_b,
-    // temperature gradient (T = p / rho), divergence.
+    // qb[v] = d u_v / d x_b, one axis b at a time: velocity gradient
+    // gv[b][c] = d v_c / d x_b, temperature gradient (T = p / rho), and at
+    // the end the divergence.  Tm = p / rho and v2 = |v|^2 from visc_pre.
     struct Visc {
         T gv[D][D];
         T gT[D];
         T div;
+        T Tm, v2;
     };
-    SDI Visc visc_state(const Prim& w, const T* q, const EqParams& P) {
-        Visc z;
+    SDI void visc_pre(const Prim& w, Visc& z) {
+        if constexpr (EQ == EQ_NS) {
+            z.Tm = w.p * w.inv;
+            z.v2 = w.vel[0] * w.vel[0];
+#pragma unroll
+            for (int b = 1; b < D; ++b) z.v2 = z.v2 + w.vel[b] * w.vel[b];
+        }
+    }
+    SDI void visc_axis(int b, const Prim& w, const T* qb, Visc& z, const EqParams& P) {
         if constexpr (EQ == EQ_NS) {
             const S gm1 = S(P.gamma) - S(1);
-            const T Tm = w.p * w.inv;
-            T v2 = w.vel[0] * w.vel[0];
+            const T gr = qb[0];
+            T vgm = w.vel[0] * qb[1];
 #pragma unroll
-            for (int b = 1; b < D; ++b) v2 = v2 + w.vel[b] * w.vel[b];
-#pragma unroll
-            for (int b = 0; b < D; ++b) {
-                const T gr = q[b * R];
-                T vgm = w.vel[0] * q[b * R + 1];
-#pragma unroll
-                for (int c = 0; c < D; ++c) {
-                    z.gv[b][c] = (q[b * R + 1 + c] - w.vel[c] * gr) * w.inv;
-                    if (c > 0) vgm = vgm + w.vel[c] * q[b * R + 1 + c];
-                }
-                const T gp = gm1 * (q[b * R + D + 1] - vgm + S(0.5) * (v2 * gr));
-                z.gT[b] = (gp - Tm * gr) * w.inv;
+            for (int c = 0; c < D; ++c) {
+                z.gv[b][c] = (qb[1 + c] - w.vel[c] * gr) * w.inv;
+                if (c > 0) vgm = vgm + w.vel[c] * qb[1 + c];
             }
+            const T gp = gm1 * (qb[D + 1] - vgm + S(0.5) * (z.v2 * gr));
+            z.gT[b] = (gp - z.Tm * gr) * w.inv;
+        }
+    }
+    SDI void visc_div(Visc& z) {
+        if constexpr (EQ == EQ_NS) {
             z.div = z.gv[0][0];
 #pragma unroll
             for (int c = 1; c < D; ++c) z.div = z.div + z.gv[c][c];
         }
-        return z;
     }
     // subtract the viscous flux along axis a from f (total flux = Fc - Fv)
     SDI void sub_visc(int a, const Prim& w, const Visc& z, T* f, const EqParams& P) {
@@ -300,19 +321,30 @@ __global__ __launch_bounds__((Shape<D, N1, NT, tpt_of(EQ, NT)>::BS)) void k_op(c
     using F = Flux<EQ, D, T>;
     constexpr int R = nvars_of(EQ, D);
     constexpr int NS = SH::NS, NPE = SH::NPE, NF = SH::NF, NJ = SH::NJ, NTH = SH::NTH;
-    constexpr int EPB = SH::EPB, B = SH::B, BS = SH::BS, NN = SH::NN, NFP = SH::NFP;
+    constexpr int EPB = SH::EPB, B = SH::B, BS = SH::BS, NFP = SH::NFP;
     constexpr bool AD = EQ == EQ_ADVDIFF;
     constexpr bool NSV = EQ == EQ_NS;
     constexpr int TS = JVP ? 2 : 1;
     constexpr int PL = JVP ? R : 0;             // tile plane of the stored part
     constexpr int EV = R * NPE;                  // values of one element
-    __shared__ CT tile[TS * R * NN];             // [plane][v][node]: value, then tangent
-    __shared__ CT buf[D * R * NN];               // [a][v][node]: flux along a, then H - f
+    constexpr int LP = lds_pitch(NPE);           // LDS pitch of one element's nodes
+    constexpr int NL = EPB * LP;                 // LDS plane: the block's nodes of one variable
+    __shared__ CT tile[TS * R * NL];             // [plane][v][node]: value, then tangent
+    __shared__ CT buf[D * R * NL];               // [a][v][node]: flux along a, then H - f
     __shared__ CT sD[N1 * N1], sDt[NT * NT], swt[NT];
 
     const int L = xcd_remap(blockIdx.x, G);
     const OpSeg& sg = segs[find_seg(segs, nseg, L)];
-    if (sg.skip && *(const gptr<const int>)sg.skip) return;
+    // the skip flag and the Arnoldi indices behind the pointers: one round
+    // of loads before the segment is skipped or its data is read
+    const int skip = load_index(sg.skip);
+    const gptr<UT> __restrict__ Up = resolve<UT>(sg.U);
+    const gptr<double> __restrict__ Vp = JVP ? resolve<double>(sg.V) : nullptr;
+    // NS: the viscous part of the total flux, -Fv along every axis (its
+    // tangent for a JVP), from the viscous pass (k_visc)
+    const gptr<CT> __restrict__ Qp = NSV ? resolve<CT>(sg.Q) : nullptr;
+    const gptr<double> __restrict__ out = resolve<double>(sg.out);
+    if (skip) return;
     const EqParams& P = sg.P;
     const int tid = threadIdx.x;
     const int el = (int)((unsigned)tid / NTH);
@@ -321,18 +353,11 @@ __global__ __launch_bounds__((Shape<D, N1, NT, tpt_of(EQ, NT)>::BS)) void k_op(c
     const int e0 = block_elem0<EPB>(sg, L - sg.blk0);
     const int e = e0 + el;
     const bool active = (tid < B) && (e < sg.E);
-    const int nd0 = el * NPE + jt * TPT * NS + s;            // block node of time node jt*TPT
+    const int nd0 = el * LP + jt * TPT * NS + s;             // block node of time node jt*TPT
     const int r0 = jt * TPT * NS + s;                        // element node of time node jt*TPT
     int ic[D];                                               // coordinates of the spatial node
     static_for<0, D>([&](auto A) { ic[decltype(A)::value] = coord<N1, decltype(A)::value>(s); });
-    const CT iw0 = CT(1) / CT(sg.wx[0]);                     // M^-1 B weight of the end nodes
-
-    const gptr<UT> __restrict__ Up = resolve<UT>(sg.U);
-    const gptr<double> __restrict__ Vp = JVP ? resolve<double>(sg.V) : nullptr;
-    // NS: the viscous part of the total flux, -Fv along every axis (its
-    // tangent for a JVP), from the viscous pass (k_visc)
-    const gptr<CT> __restrict__ Qp = NSV ? resolve<CT>(sg.Q) : nullptr;
-    const gptr<double> __restrict__ out = resolve<double>(sg.out);
+    const CT iw0 = CT(sg.iw0);                               // M^-1 B weight of the end nodes
     const gptr<const double> __restrict__ upv = (gptr<const double>)sg.uprev;
 
     // state of element node rr (= j * NS + s) of element ee
@@ -378,7 +403,7 @@ __global__ __launch_bounds__((Shape<D, N1, NT, tpt_of(EQ, NT)>::BS)) void k_op(c
         fi.stride = stride_rt<N1>(fi.a);
         const int so = face_node_rt<D, N1>(fi.a, f, fi.right);
         fi.rn0 = jg * TPT * NS + so + (fi.right ? -(N1 - 1) : (N1 - 1)) * fi.stride;   // neighbour's node
-        fi.to0 = fi.pel * NPE + jg * TPT * NS + so;                                    // own block node
+        fi.to0 = fi.pel * LP + jg * TPT * NS + so;                                     // own block node
         fi.en = fi.ok ? neighbour(sg, ep, ecoord(sg, ep), fi.a, fi.right) : 0;
         return fi;
     };
@@ -430,7 +455,7 @@ __global__ __launch_bounds__((Shape<D, N1, NT, tpt_of(EQ, NT)>::BS)) void k_op(c
                     gn += lw * (CT(0.5) * (unv + uo) - unv);
                     const CT fn = unv * av - (J * gn) * nu;
                     const CT jump = right ? uo - unv : unv - uo;
-                    CT& slot = buf[ax * NN + fi.to0 + jj * NS];
+                    CT& slot = buf[ax * NL + fi.to0 + jj * NS];
                     slot = CT(0.5) * (fn - slot) + (CT(0.5) * lam) * jump;
                 }
             } else {
@@ -440,8 +465,8 @@ __global__ __launch_bounds__((Shape<D, N1, NT, tpt_of(EQ, NT)>::BS)) void k_op(c
                     T uo[R], fn[R];
 #pragma unroll
                     for (int v = 0; v < R; ++v) {
-                        if constexpr (JVP) uo[v] = make_state<T>(tile[v * NN + to], tile[(R + v) * NN + to]);
-                        else uo[v] = tile[v * NN + to];
+                        if constexpr (JVP) uo[v] = make_state<T>(tile[v * NL + to], tile[(R + v) * NL + to]);
+                        else uo[v] = tile[v * NL + to];
                     }
                     const T* un = d.un[jj];
                     const typename F::Prim w = F::prim(un, P);
@@ -456,7 +481,7 @@ __global__ __launch_bounds__((Shape<D, N1, NT, tpt_of(EQ, NT)>::BS)) void k_op(c
                     for (int v = 0; v < R; ++v) {
                         const T jump = right ? uo[v] - un[v] : un[v] - uo[v];      // u_L - u_R
                         const CT pen = part((CT(0.5) * lam) * jump);
-                        CT& slot = buf[(ax * R + v) * NN + to];
+                        CT& slot = buf[(ax * R + v) * NL + to];
                         slot = CT(0.5) * (part(fn[v]) - slot) + pen;
                     }
                 }
@@ -464,12 +489,14 @@ __global__ __launch_bounds__((Shape<D, N1, NT, tpt_of(EQ, NT)>::BS)) void k_op(c
         });
     };
 
-    // (0) tables to LDS; every global load of the block issued at once: own
+    // (0) every global load of the block issued at once: the tables, own
     //     states (and NS: own -Fv), AD neighbour face values, the data of
-    //     this thread's first face point
-    if (tid < N1 * N1) sD[tid] = CT(sg.Dx[tid]);
-    if (tid < NT * NT) sDt[tid] = CT(sg.Dt[tid]);
-    if (tid < NT) swt[tid] = CT(sg.wt[tid]);
+    //     this thread's first face point; then the tables and the tile to
+    //     LDS (the tables were requested first, so waiting for them does not
+    //     wait for the rest)
+    const CT tD = CT(sg.Dx[tid < N1 * N1 ? tid : 0]);
+    const CT tDt = CT(sg.Dt[tid < NT * NT ? tid : 0]);
+    const CT twt = CT(sg.wt[tid < NT ? tid : 0]);
     T u[TPT][R];
     CT gv[NSV ? TPT : 1][NSV ? D : 1][NSV ? R : 1];    // own -Fv, every axis
     CT unb[AD ? D : 1][AD ? TPT : 1];
@@ -489,7 +516,7 @@ __global__ __launch_bounds__((Shape<D, N1, NT, tpt_of(EQ, NT)>::BS)) void k_op(c
                 if (ia == 0 || ia == N1 - 1) {
                     const bool right = ia == N1 - 1;
                     const gptr<UT> Un = Up + (int64_t)neighbour(sg, e, x, a, right) * EV +
-                                        (r0 + ((right ? 0 : N1 - 1) - ia) * ipow(N1, a));
+                                        (r0 + ((right ? 0 : N1 - 1) - ia) * ipow_c<N1, a>);
 #pragma unroll
                     for (int jj = 0; jj < TPT; ++jj) unb[a][jj] = CT(Un[jj * NS]);
                 } else {
@@ -508,13 +535,16 @@ __global__ __launch_bounds__((Shape<D, N1, NT, tpt_of(EQ, NT)>::BS)) void k_op(c
     const FPI fi0 = fp_info(tid);
     FPD fd0;
     fp_load(fi0, fd0);
+    if (tid < N1 * N1) sD[tid] = tD;
+    if (tid < NT * NT) sDt[tid] = tDt;
+    if (tid < NT) swt[tid] = twt;
     if (active) {
 #pragma unroll
         for (int jj = 0; jj < TPT; ++jj)
 #pragma unroll
             for (int v = 0; v < R; ++v) {
-                tile[v * NN + nd0 + jj * NS] = value(u[jj][v]);
-                if constexpr (JVP) tile[(R + v) * NN + nd0 + jj * NS] = part(u[jj][v]);
+                tile[v * NL + nd0 + jj * NS] = value(u[jj][v]);
+                if constexpr (JVP) tile[(R + v) * NL + nd0 + jj * NS] = part(u[jj][v]);
             }
     }
     if constexpr (AD) __syncthreads();
@@ -541,7 +571,7 @@ __global__ __launch_bounds__((Shape<D, N1, NT, tpt_of(EQ, NT)>::BS)) void k_op(c
 #pragma unroll
                     for (int k = 1; k < N1; ++k) g += Dr[k] * ln[k * stride];
                     g += lw * (CT(0.5) * (u[jj][0] + unb[a][jj]) - u[jj][0]);
-                    buf[a * NN + nd0 + jj * NS] = u[jj][0] * av - (J * g) * nu;
+                    buf[a * NL + nd0 + jj * NS] = u[jj][0] * av - (J * g) * nu;
                 }
             });
         } else {
@@ -556,7 +586,7 @@ __global__ __launch_bounds__((Shape<D, N1, NT, tpt_of(EQ, NT)>::BS)) void k_op(c
 #pragma unroll
                         for (int v = 0; v < R; ++v) add_part(f[v], gv[jj][a][v]);
 #pragma unroll
-                    for (int v = 0; v < R; ++v) buf[(a * R + v) * NN + nd0 + jj * NS] = part(f[v]);
+                    for (int v = 0; v < R; ++v) buf[(a * R + v) * NL + nd0 + jj * NS] = part(f[v]);
                 });
             }
         }
@@ -582,7 +612,7 @@ __global__ __launch_bounds__((Shape<D, N1, NT, tpt_of(EQ, NT)>::BS)) void k_op(c
             for (int jj = 0; jj < TPT; ++jj)
 #pragma unroll
                 for (int v = 0; v < R; ++v) {
-                    const CT* ln = buf + (a * R + v) * NN + nd0 + jj * NS - ia * stride;
+                    const CT* ln = buf + (a * R + v) * NL + nd0 + jj * NS - ia * stride;
                     CT sum = Drow[0] * ln[0];
 #pragma unroll
                     for (int k = 1; k < N1; ++k) sum += Drow[k] * ln[k * stride];
@@ -614,7 +644,7 @@ __global__ __launch_bounds__((Shape<D, N1, NT, tpt_of(EQ, NT)>::BS)) void k_op(c
 #pragma unroll
                 for (int jj = 0; jj < TPT; ++jj)
 #pragma unroll
-                    for (int v = 0; v < R; ++v) acc[jj][v] -= wl * buf[(a * R + v) * NN + nd0 + jj * NS];
+                    for (int v = 0; v < R; ++v) acc[jj][v] -= wl * buf[(a * R + v) * NL + nd0 + jj * NS];
             }
         });
         const CT hdt = CT(0.5 * sg.dt);
@@ -627,7 +657,7 @@ __global__ __launch_bounds__((Shape<D, N1, NT, tpt_of(EQ, NT)>::BS)) void k_op(c
                 // the stored part at time node k of this spatial node
                 auto tv = [&](int k) -> CT {
                     if constexpr (TPT == NT) return part(u[k][v]);
-                    else return tile[(PL + v) * NN + el * NPE + k * NS + s];
+                    else return tile[(PL + v) * NL + el * LP + k * NS + s];
                 };
                 CT dtu = sDt[j * NT] * tv(0);
 #pragma unroll
@@ -654,8 +684,10 @@ __global__ __launch_bounds__((Shape<D, N1, NT, tpt_of(EQ, NT)>::BS)) void k_op(c
 // double).  Output out[((e * D + a) * R + v) * Nt + j) * ns + s], type CT.
 // Same block shape and traversal as k_op.
 // ---------------------------------------------------------------------------
+// Two waves per SIMD are asked for: the FP64 tangent pass would otherwise
+// take all 512 registers of a lane and run one wave per SIMD.
 template <int D, int N1, int NT, class CT, class UT, bool JVP>
-__global__ __launch_bounds__((Shape<D, N1, NT, 1>::BS)) void k_visc(const OpSeg* __restrict__ segs, int nseg, int G) {
+__global__ __attribute__((amdgpu_waves_per_eu(2))) __launch_bounds__((Shape<D, N1, NT, 1>::BS)) void k_visc(const OpSeg* __restrict__ segs, int nseg, int G) {
     using SH = Shape<D, N1, NT, 1>;
     using T = typename std::conditional<JVP, Dual<CT>, CT>::type;
     using F = Flux<EQ_NS, D, T>;
@@ -667,7 +699,11 @@ __global__ __launch_bounds__((Shape<D, N1, NT, 1>::BS)) void k_visc(const OpSeg*
     __shared__ CT sD[N1 * N1];
     const int L = xcd_remap(blockIdx.x, G);
     const OpSeg& sg = segs[find_seg(segs, nseg, L)];
-    if (sg.skip && *(const gptr<const int>)sg.skip) return;
+    const int skip = load_index(sg.skip);
+    const gptr<UT> __restrict__ Up = resolve<UT>(sg.U);
+    const gptr<double> __restrict__ Vp = JVP ? resolve<double>(sg.V) : nullptr;
+    const gptr<CT> __restrict__ Qp = resolve<CT>(sg.out);
+    if (skip) return;
     const EqParams& P = sg.P;
     const int tid = threadIdx.x;
     const int el = (int)((unsigned)tid / NPE);
@@ -676,9 +712,6 @@ __global__ __launch_bounds__((Shape<D, N1, NT, 1>::BS)) void k_visc(const OpSeg*
     const int e0 = block_elem0<EPB>(sg, L - sg.blk0);
     const int e = e0 + el;
     const bool active = (tid < B) && (e < sg.E);
-    const gptr<UT> __restrict__ Up = resolve<UT>(sg.U);
-    const gptr<double> __restrict__ Vp = JVP ? resolve<double>(sg.V) : nullptr;
-    const gptr<CT> __restrict__ Qp = resolve<CT>(sg.out);
     auto load_state = [&](int ee, int rr, T* u) {
         const gptr<UT> Ue = Up + (int64_t)ee * EV;
 #pragma unroll
@@ -688,23 +721,11 @@ __global__ __launch_bounds__((Shape<D, N1, NT, 1>::BS)) void k_visc(const OpSeg*
         }
     };
 
-    if (tid < N1 * N1) sD[tid] = CT(sg.Dx[tid]);
+    const CT tD = CT(sg.Dx[tid < N1 * N1 ? tid : 0]);
     T u[R];
-    T un[D][R];
+    if (active) load_state(e, r, u);
+    if (tid < N1 * N1) sD[tid] = tD;
     if (active) {
-        load_state(e, r, u);
-        const ECoord x = ecoord(sg, e);
-        static_for<0, D>([&](auto B_) {
-            constexpr int b = decltype(B_)::value;
-            const int ib = coord<N1, b>(s);
-            if (ib == 0 || ib == N1 - 1) {
-                const bool right = ib == N1 - 1;
-                load_state(neighbour(sg, e, x, b, right), r + ((right ? 0 : N1 - 1) - ib) * ipow(N1, b), un[b]);
-            } else {
-#pragma unroll
-                for (int v = 0; v < R; ++v) un[b][v] = u[v];   // interior: the lift below vanishes exactly
-            }
-        });
 #pragma unroll
         for (int v = 0; v < R; ++v) {
             tile[v * B + tid] = value(u[v]);
@@ -713,17 +734,32 @@ __global__ __launch_bounds__((Shape<D, N1, NT, 1>::BS)) void k_visc(const OpSeg*
     }
     __syncthreads();
     if (!active) return;
-    const CT iw0 = CT(1) / CT(sg.wx[0]);
-    T q[D * R];
+    const CT iw0 = CT(sg.iw0);
+    const ECoord x = ecoord(sg, e);
+    const typename F::Prim w = F::prim(u, P);
+    typename F::Visc z;
+    F::visc_pre(w, z);
+    // lifted gradient along each axis b, folded into the viscous state at
+    // once; the neighbour across the face of a face node is read per axis
+    // (few registers held: this pass carries the whole viscous state)
     static_for<0, D>([&](auto B_) {
         constexpr int b = decltype(B_)::value;
         constexpr int stride = ipow(N1, b);
         const int ib = coord<N1, b>(s);
+        T un[R];
+        if (ib == 0 || ib == N1 - 1) {
+            const bool right = ib == N1 - 1;
+            load_state(neighbour(sg, e, x, b, right), r + ((right ? 0 : N1 - 1) - ib) * stride, un);
+        } else {
+#pragma unroll
+            for (int v = 0; v < R; ++v) un[v] = u[v];   // interior: the lift below vanishes exactly
+        }
         CT Drow[N1];
 #pragma unroll
         for (int k = 0; k < N1; ++k) Drow[k] = sD[ib * N1 + k];
         const CT J = CT(sg.rh[b]);
         const CT lw = ib == N1 - 1 ? iw0 : (ib == 0 ? -iw0 : CT(0));
+        T qb[R];
 #pragma unroll
         for (int v = 0; v < R; ++v) {
             const CT* ln = tile + v * B + tid - ib * stride;
@@ -740,12 +776,12 @@ __global__ __launch_bounds__((Shape<D, N1, NT, 1>::BS)) void k_visc(const OpSeg*
             } else {
                 g = gv;
             }
-            g = g + lw * (CT(0.5) * (u[v] + un[b][v]) - u[v]);
-            q[b * R + v] = J * g;
+            g = g + lw * (CT(0.5) * (u[v] + un[v]) - u[v]);
+            qb[v] = J * g;
         }
+        F::visc_axis(b, w, qb, z, P);
     });
-    const typename F::Prim w = F::prim(u, P);
-    const typename F::Visc z = F::visc_state(w, q, P);
+    F::visc_div(z);
     const gptr<CT> Qe = Qp + (int64_t)e * (D * EV);
     static_for<0, D>([&](auto A) {
         constexpr int a = decltype(A)::value;
