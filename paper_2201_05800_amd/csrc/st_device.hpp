@@ -183,6 +183,9 @@ struct DynPtr {
     int koff;
 };
 
+// entries per axis of the linear line operator: n1^2 + 4 n1 for n1 <= 8
+constexpr int LIN_AXIS = 8 * 8 + 4 * 8;
+
 // One slab instance inside an operator launch.
 struct OpSeg {
     DynPtr U;            // state (double or float)
@@ -213,6 +216,12 @@ struct OpSeg {
     double wx[8];
     double Dt[16];
     double wt[4];
+    // Linear equations: the spatial operator along one axis as a map of a
+    // line of n1 nodes and the neighbours' lines across its two end faces,
+    // per axis a at lin[a * LIN_AXIS]: A[i * n1 + k] (own line), HL[i] and
+    // HR[i] (the neighbours' face values), FL[m] and FR[m] (the left and the
+    // right neighbour's node at distance m >= 1 from its face, end rows only)
+    double lin[3 * LIN_AXIS];
 };
 
 // One slab instance inside a vector (Krylov) launch.

@@ -151,6 +151,77 @@ static void div_magic(int d, unsigned& m, int& sh) {
     sh = 31 + k;
 }
 
+// Spatial operator of a linear equation (advection, advection-diffusion with
+// BR1) along axis a, restricted to one line of n1 nodes: the contribution
+// F_i = -(2/h) [D f]_i - (2/h) M^-1 B (H - f) at node i of the line is linear
+// in the line's values u, the left neighbour's line uL and the right one's uR
+// (eqs. elementint, surfaceint in strong form, flux:llf; BR1 lifted gradient
+// with u_hat = {u}, central viscous flux).  Evaluated here for the unit
+// vectors, it gives F = A u + BL uL + BR uR; BL is nonzero only in its last
+// column (the neighbour's face value enters every node through the lift) and
+// its first row (the face flux needs the neighbour's normal derivative), BR
+// likewise in its first column and last row.
+static void line_operator(const Problem& pb, int a, double* out) {
+    const int n1 = pb.n1, N = n1 - 1;
+    const double J = 2.0 / pb.h[a], av = pb.P.a[a], lam = std::fabs(av);
+    const double nu = pb.eq.kind == ST_ADVDIFF_BR1 ? pb.P.nu : 0.0;
+    const double iw0 = 1.0 / pb.wx[0];
+    const double* D = pb.Dx;
+    auto apply = [&](const double* u, const double* uL, const double* uR, double* acc) {
+        double g[8], f[8];
+        for (int i = 0; i < n1; ++i) {
+            g[i] = 0.0;
+            for (int k = 0; k < n1; ++k) g[i] += D[i * n1 + k] * u[k];
+        }
+        g[0] += -iw0 * (0.5 * (u[0] + uL[N]) - u[0]);
+        g[N] += iw0 * (0.5 * (u[N] + uR[0]) - u[N]);
+        for (int i = 0; i < n1; ++i) f[i] = u[i] * av - (J * g[i]) * nu;
+        for (int i = 0; i < n1; ++i) {
+            double sv = 0.0;
+            for (int k = 0; k < n1; ++k) sv += D[i * n1 + k] * f[k];
+            acc[i] = -J * sv;
+        }
+        // right face: the neighbour's gradient at its face node, its flux,
+        // the Rusanov flux with u_L = u_N, u_R = uR_0
+        double gn = 0.0;
+        for (int k = 0; k < n1; ++k) gn += D[k] * uR[k];
+        gn += -iw0 * (0.5 * (uR[0] + u[N]) - uR[0]);
+        const double fnr = uR[0] * av - (J * gn) * nu;
+        acc[N] -= J * iw0 * (0.5 * (fnr - f[N]) + 0.5 * lam * (u[N] - uR[0]));
+        // left face: u_L = uL_N, u_R = u_0
+        gn = 0.0;
+        for (int k = 0; k < n1; ++k) gn += D[N * n1 + k] * uL[k];
+        gn += iw0 * (0.5 * (uL[N] + u[0]) - uL[N]);
+        const double fnl = uL[N] * av - (J * gn) * nu;
+        acc[0] += J * iw0 * (0.5 * (fnl - f[0]) + 0.5 * lam * (uL[N] - u[0]));
+    };
+    double M[3][8][8];   // [input line][row i][column k]
+    for (int which = 0; which < 3; ++which)
+        for (int k = 0; k < n1; ++k) {
+            double in[3][8] = {};
+            in[which][k] = 1.0;
+            double acc[8];
+            apply(in[0], in[1], in[2], acc);
+            for (int i = 0; i < n1; ++i) M[which][i][k] = acc[i];
+        }
+    double* A = out;
+    double* HL = A + n1 * n1;
+    double* HR = HL + n1;
+    double* FL = HR + n1;
+    double* FR = FL + n1;
+    for (int i = 0; i < n1; ++i)
+        for (int k = 0; k < n1; ++k) A[i * n1 + k] = M[0][i][k];
+    for (int i = 0; i < n1; ++i) {
+        HL[i] = M[1][i][N];
+        HR[i] = M[2][i][0];
+    }
+    FL[0] = FR[0] = 0.0;
+    for (int m = 1; m < n1; ++m) {
+        FL[m] = M[1][0][N - m];   // row 0: left neighbour's node at distance m from its face
+        FR[m] = M[2][N][m];       // row N: right neighbour's node at distance m
+    }
+}
+
 OpSeg base_opseg(const Problem& pb, double dt) {
     OpSeg s;
     std::memset(&s, 0, sizeof(s));
@@ -187,6 +258,8 @@ OpSeg base_opseg(const Problem& pb, double dt) {
         for (int i = 0; i < 4; ++i) div_magic(s.tk[i], s.tm[i], s.ts[i]);
     }
     s.iw0 = 1.0 / pb.wx[0];
+    if (linear_eq(pb.eq.kind))
+        for (int a = 0; a < pb.mesh.dim; ++a) line_operator(pb, a, s.lin + a * LIN_AXIS);
     s.P = pb.P;
     s.dt = dt;
     s.blk0 = 0;

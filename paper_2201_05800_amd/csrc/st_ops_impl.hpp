@@ -674,6 +674,230 @@ __global__ __launch_bounds__((Shape<D, N1, NT, tpt_of(EQ, NT)>::BS)) void k_op(c
 }
 
 // ---------------------------------------------------------------------------
+// Residual kernel of the linear scalar equations (advection; advection-
+// diffusion with BR1).  Along every axis the spatial operator of a line of
+// n1 nodes is the descriptor's line operator: A on the own line, HL/HR on the
+// two neighbours' face values, and on the two end rows FL/FR on the
+// neighbours' lines -- k_op's fluxes, lifted gradient and face terms folded
+// into small matrices, so a node needs n1 + 2 values per axis and no flux
+// staging.  One thread per spatial node holds all Nt time nodes.  Phases:
+//   0. every global load issued: own values, on end nodes the neighbours'
+//      face values, the neighbour line of this thread's first face point;
+//      own values and face values to LDS;
+//   1. every node: A and HL/HR along every axis (into registers); face
+//      points (axis, element, side, face node): FL/FR on the neighbour's
+//      line, into LDS;
+//   2. end nodes add their face-point terms; DG in time (eq. DG_in_time);
+//      store.
+// The JVP of these equations is this kernel on v with u_prev = 0.
+// ---------------------------------------------------------------------------
+template <int EQ, int D, int N1, int NT, class CT, class UT>
+__global__ __launch_bounds__((Shape<D, N1, NT, NT>::BS)) void k_lin(const OpSeg* __restrict__ segs, int nseg, int G) {
+    using SH = Shape<D, N1, NT, NT>;
+    constexpr int NS = SH::NS, NPE = SH::NPE, NF = SH::NF;
+    constexpr int EPB = SH::EPB, B = SH::B, BS = SH::BS;
+    constexpr int N = N1 - 1;
+    constexpr int LP = lds_pitch(NPE), NL = EPB * LP;
+    constexpr int PER_AX = EPB * 2 * NF;            // face points per axis
+    constexpr int NFP = D * PER_AX;                 // (axis, element, side, face node)
+    constexpr int NH = NFP * NT;                    // face-point values, all time nodes
+    constexpr int LA = N1 * N1 + 4 * N1;            // line-operator entries per axis
+    constexpr int NTAB = D * LA;
+    constexpr int NQ = (NTAB + BS - 1) / BS;
+    __shared__ CT tile[NL];                         // [element][time][spatial node]
+    __shared__ CT halo[NH];                         // [face point][j]: neighbour's face value
+    __shared__ CT fsum[NH];                         // [face point][j]: FL/FR term
+    __shared__ CT sL[NTAB], sDt[NT * NT], swt[NT];
+
+    const int L = xcd_remap(blockIdx.x, G);
+    const OpSeg& sg = segs[find_seg(segs, nseg, L)];
+    const int skip = load_index(sg.skip);
+    const gptr<UT> __restrict__ Up = resolve<UT>(sg.U);
+    const gptr<double> __restrict__ out = resolve<double>(sg.out);
+    if (skip) return;
+    const gptr<const double> __restrict__ upv = (gptr<const double>)sg.uprev;
+    const int tid = threadIdx.x;
+    const int el = (int)((unsigned)tid / NS);
+    const int s = tid - el * NS;
+    const int e0 = block_elem0<EPB>(sg, L - sg.blk0);
+    const int e = e0 + el;
+    const bool active = (tid < B) && (e < sg.E);
+    int ic[D];                                      // coordinates of the spatial node
+    static_for<0, D>([&](auto A) { ic[decltype(A)::value] = coord<N1, decltype(A)::value>(s); });
+    // face index of the node's line along axis a: the other coordinates,
+    // in increasing axis order, the first fastest
+    auto face_of = [&](int a) -> int {
+        if constexpr (D == 1) return 0;
+        else if constexpr (D == 2) return a == 0 ? ic[1] : ic[0];
+        else return a == 0 ? ic[1] + N1 * ic[2] : (a == 1 ? ic[0] + N1 * ic[2] : ic[0] + N1 * ic[1]);
+    };
+    auto fpi = [&](int a, int pel, int side, int f) { return ((a * EPB + pel) * 2 + side) * NF + f; };
+
+    // face point p = ((a * EPB + pel) * 2 + side) * NF + f: the neighbour
+    // across face (a, side) of element e0 + pel, and its line at face index f
+    // from the face inwards
+    struct FPI {
+        int a, side, rn, step, en;
+        bool ok;
+    };
+    auto fp_info = [&](int p) {
+        FPI fi;
+        fi.a = (int)((unsigned)p / PER_AX);
+        int rem = p - fi.a * PER_AX;
+        const int pel = (int)((unsigned)rem / (2 * NF));
+        rem -= pel * (2 * NF);
+        fi.side = rem >= NF ? 1 : 0;
+        const int f = rem - fi.side * NF;
+        const int ep = e0 + pel;
+        fi.ok = p < NFP && ep < sg.E;
+        const bool right = fi.side == 1;
+        const int stride = stride_rt<N1>(fi.a);
+        fi.rn = face_node_rt<D, N1>(fi.a, f, right) + (right ? -N : N) * stride;   // neighbour's face node
+        fi.step = right ? stride : -stride;
+        fi.en = fi.ok ? neighbour(sg, ep, ecoord(sg, ep), fi.a, right) : 0;
+        return fi;
+    };
+    auto fp_load = [&](const FPI& fi, CT (&nl)[NT][N]) {
+        if (!fi.ok) return;
+        const gptr<UT> lb = Up + (int64_t)fi.en * NPE + fi.rn;
+#pragma unroll
+        for (int j = 0; j < NT; ++j)
+#pragma unroll
+            for (int m = 1; m <= N; ++m) nl[j][m - 1] = CT(lb[j * NS + m * fi.step]);
+    };
+    auto fp_compute = [&](int p, const FPI& fi, const CT (&nl)[NT][N]) {
+        if (!fi.ok) return;
+        const CT* Fs = sL + fi.a * LA + N1 * N1 + 2 * N1 + fi.side * N1;   // FL or FR
+#pragma unroll
+        for (int j = 0; j < NT; ++j) {
+            CT c = Fs[1] * nl[j][0];
+#pragma unroll
+            for (int m = 2; m <= N; ++m) c += Fs[m] * nl[j][m - 1];
+            fsum[p * NT + j] = c;
+        }
+    };
+
+    // (0) the tables (requested first), own values, the neighbours' face
+    //     values of end nodes, the first face point's neighbour line
+    CT tL[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        const int t = tid + q * BS;
+        const int a = t < NTAB ? (int)((unsigned)t / LA) : 0;
+        tL[q] = CT(sg.lin[t < NTAB ? a * LIN_AXIS + (t - a * LA) : 0]);
+    }
+    const CT tDt = CT(sg.Dt[tid < NT * NT ? tid : 0]);
+    const CT twt = CT(sg.wt[tid < NT ? tid : 0]);
+    CT u[NT];
+    CT unb[D][NT];
+    if (active) {
+        const gptr<UT> Ue = Up + (int64_t)e * NPE + s;
+#pragma unroll
+        for (int j = 0; j < NT; ++j) u[j] = CT(Ue[j * NS]);
+        const ECoord x = ecoord(sg, e);
+        static_for<0, D>([&](auto A) {
+            constexpr int a = decltype(A)::value;
+            constexpr int stride = ipow_c<N1, a>;
+            const int ia = ic[a];
+            if (ia == 0 || ia == N) {
+                const bool right = ia == N;
+                const gptr<UT> Un = Up + (int64_t)neighbour(sg, e, x, a, right) * NPE + s + ((right ? 0 : N) - ia) * stride;
+#pragma unroll
+                for (int j = 0; j < NT; ++j) unb[a][j] = CT(Un[j * NS]);
+            }
+        });
+    }
+    const FPI fi0 = fp_info(tid);
+    CT nl0[NT][N];
+    fp_load(fi0, nl0);
+#pragma unroll
+    for (int q = 0; q < NQ; ++q)
+        if (tid + q * BS < NTAB) sL[tid + q * BS] = tL[q];
+    if (tid < NT * NT) sDt[tid] = tDt;
+    if (tid < NT) swt[tid] = twt;
+    if (active) {
+#pragma unroll
+        for (int j = 0; j < NT; ++j) tile[el * LP + j * NS + s] = u[j];
+        static_for<0, D>([&](auto A) {
+            constexpr int a = decltype(A)::value;
+            const int ia = ic[a];
+            if (ia == 0 || ia == N) {
+                const int h = fpi(a, el, ia == N ? 1 : 0, face_of(a)) * NT;
+#pragma unroll
+                for (int j = 0; j < NT; ++j) halo[h + j] = unb[a][j];
+            }
+        });
+    }
+    __syncthreads();
+
+    // (1) A and HL/HR along every axis; then the face points
+    CT acc[NT];
+#pragma unroll
+    for (int j = 0; j < NT; ++j) acc[j] = CT(0);
+    if (active) {
+        static_for<0, D>([&](auto A) {
+            constexpr int a = decltype(A)::value;
+            constexpr int stride = ipow_c<N1, a>;
+            const int ia = ic[a];
+            const CT* La = sL + a * LA;
+            CT Ar[N1];
+#pragma unroll
+            for (int k = 0; k < N1; ++k) Ar[k] = La[ia * N1 + k];
+            const CT hl = La[N1 * N1 + ia], hr = La[N1 * N1 + N1 + ia];
+            const int f = face_of(a);
+            const CT* hL = halo + fpi(a, el, 0, f) * NT;
+            const CT* hR = halo + fpi(a, el, 1, f) * NT;
+#pragma unroll
+            for (int j = 0; j < NT; ++j) {
+                const CT* ln = tile + el * LP + j * NS + s - ia * stride;
+                CT sum = Ar[0] * ln[0];
+#pragma unroll
+                for (int k = 1; k < N1; ++k) sum += Ar[k] * ln[k * stride];
+                sum += hl * hL[j];
+                sum += hr * hR[j];
+                acc[j] += sum;
+            }
+        });
+    }
+    fp_compute(tid, fi0, nl0);
+    for (int p = tid + BS; p < NFP; p += BS) {
+        const FPI fi = fp_info(p);
+        CT nl[NT][N];
+        fp_load(fi, nl);
+        fp_compute(p, fi, nl);
+    }
+    __syncthreads();
+
+    // (2) end rows: the face-point terms; DG in time
+    //   R_j = w_j (dt/2 F_j - (D_tau U)_j) - delta_{j1} (u^1 - u^n)
+    if (active) {
+        static_for<0, D>([&](auto A) {
+            constexpr int a = decltype(A)::value;
+            const int ia = ic[a];
+            if (ia == 0 || ia == N) {
+                const CT* fs = fsum + fpi(a, el, ia == N ? 1 : 0, face_of(a)) * NT;
+#pragma unroll
+                for (int j = 0; j < NT; ++j) acc[j] += fs[j];
+            }
+        });
+        const CT hdt = CT(0.5 * sg.dt);
+        const gptr<double> oe = out + (int64_t)e * NPE + s;
+#pragma unroll
+        for (int j = 0; j < NT; ++j) {
+            CT dtu = sDt[j * NT] * u[0];
+#pragma unroll
+            for (int k = 1; k < NT; ++k) dtu += sDt[j * NT + k] * u[k];
+            CT res = swt[j] * (hdt * acc[j] - dtu);
+            if (j == 0) {
+                const CT up = upv ? CT(upv[(int64_t)e * NS + s]) : CT(0);
+                res -= u[0] - up;
+            }
+            oe[j * NS] = double(res);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Navier-Stokes viscous pass.  The BR1 lifted gradient of the conservative
 // variables (strong form),
 //   q_b = (2/h_b) [ sum_k D_{i_b,k} u_k + M^-1 B (u_hat - u) ],  u_hat = {u},
@@ -801,6 +1025,10 @@ template <int EQ, int D, int N1, int NT, class CT, class UT, bool JVP>
 void launch_op(const OpSeg* segs, int nseg, int G, hipStream_t st) {
     launch_k(k_op<EQ, D, N1, NT, CT, UT, JVP>, dim3(G), dim3(Shape<D, N1, NT, tpt_of(EQ, NT)>::BS), st, segs, nseg, G);
 }
+template <int EQ, int D, int N1, int NT, class CT, class UT>
+void launch_lin(const OpSeg* segs, int nseg, int G, hipStream_t st) {
+    launch_k(k_lin<EQ, D, N1, NT, CT, UT>, dim3(G), dim3(Shape<D, N1, NT, NT>::BS), st, segs, nseg, G);
+}
 template <int D, int N1, int NT, class CT, class UT, bool JVP>
 void launch_visc(const OpSeg* segs, int nseg, int G, hipStream_t st) {
     launch_k(k_visc<D, N1, NT, CT, UT, JVP>, dim3(G), dim3(Shape<D, N1, NT, 1>::BS), st, segs, nseg, G);
@@ -810,10 +1038,11 @@ template <int EQ, int D, int N1, int NT>
 OpTable make_table() {
     OpTable t{};
     t.eq = EQ; t.dim = D; t.n1 = N1; t.nt = NT; t.epb = Shape<D, N1, NT, tpt_of(EQ, NT)>::EPB;
-    t.res64 = launch_op<EQ, D, N1, NT, double, double, false>;
     if constexpr (linear_eq(EQ)) {
-        t.lin32 = launch_op<EQ, D, N1, NT, float, double, false>;
+        t.res64 = launch_lin<EQ, D, N1, NT, double, double>;
+        t.lin32 = launch_lin<EQ, D, N1, NT, float, double>;
     } else {
+        t.res64 = launch_op<EQ, D, N1, NT, double, double, false>;
         t.jvp64 = launch_op<EQ, D, N1, NT, double, double, true>;
         t.jvp32 = launch_op<EQ, D, N1, NT, float, float, true>;
     }
