@@ -300,17 +300,13 @@ struct Flux {
 };
 
 // ---------------------------------------------------------------------------
-// Residual / JVP kernel.
+// Residual / JVP kernel of the nonlinear equations (the linear ones use
+// k_lin below).
 //   JVP = false: out = R(U) with u_prev (null = 0); CT compute type, UT storage
-//                type of U.  With U := v and u_prev = 0 this is also the JVP of
-//                the linear equations.
+//                type of U.
 //   JVP = true : out = J(U) v by dual numbers (U of type UT, v double).
-// Advection-diffusion computes its BR1 lifted gradient in the kernel: the
-// central viscous flux through a face needs only the neighbour's normal
-// derivative at the face node, which the face-point thread forms from the
-// neighbour's line of nodes normal to the face.  Navier-Stokes reads the
-// viscous part of the total flux, own and the neighbours' at face nodes,
-// from the viscous pass (k_visc).
+// Navier-Stokes reads the viscous part of the total flux, own and the
+// neighbours' at face nodes, from the viscous pass (k_visc).
 // ---------------------------------------------------------------------------
 template <int EQ, int D, int N1, int NT, class CT, class UT, bool JVP>
 __global__ __launch_bounds__((Shape<D, N1, NT, tpt_of(EQ, NT)>::BS)) void k_op(const OpSeg* __restrict__ segs,
@@ -322,7 +318,7 @@ __global__ __launch_bounds__((Shape<D, N1, NT, tpt_of(EQ, NT)>::BS)) void k_op(c
     constexpr int R = nvars_of(EQ, D);
     constexpr int NS = SH::NS, NPE = SH::NPE, NF = SH::NF, NJ = SH::NJ, NTH = SH::NTH;
     constexpr int EPB = SH::EPB, B = SH::B, BS = SH::BS, NFP = SH::NFP;
-    constexpr bool AD = EQ == EQ_ADVDIFF;
+    static_assert(!linear_eq(EQ), "the linear equations use k_lin");
     constexpr bool NSV = EQ == EQ_NS;
     constexpr int TS = JVP ? 2 : 1;
     constexpr int PL = JVP ? R : 0;             // tile plane of the stored part
@@ -407,29 +403,18 @@ __global__ __launch_bounds__((Shape<D, N1, NT, tpt_of(EQ, NT)>::BS)) void k_op(c
         fi.en = fi.ok ? neighbour(sg, ep, ecoord(sg, ep), fi.a, fi.right) : 0;
         return fi;
     };
-    // neighbour data of a face point: AD the neighbour's normal line from
-    // the face node inwards; otherwise its state (and NS: its -Fv along the
+    // neighbour data of a face point: its state (and NS: its -Fv along the
     // face axis)
     struct FPD {
-        CT line[AD ? TPT : 1][AD ? N1 : 1];
-        T un[AD ? 1 : TPT][R];
+        T un[TPT][R];
         CT gn[NSV ? TPT : 1][NSV ? R : 1];
     };
     auto fp_load = [&](const FPI& fi, FPD& d) {
         if (!fi.ok) return;
-        if constexpr (AD) {
-            const int step = fi.right ? fi.stride : -fi.stride;
-            const gptr<UT> lb = Up + (int64_t)fi.en * EV + fi.rn0;
 #pragma unroll
-            for (int jj = 0; jj < TPT; ++jj)
-#pragma unroll
-                for (int k = 0; k < N1; ++k) d.line[jj][k] = CT(lb[jj * NS + k * step]);
-        } else {
-#pragma unroll
-            for (int jj = 0; jj < TPT; ++jj) {
-                load_state(fi.en, fi.rn0 + jj * NS, d.un[jj]);
-                if constexpr (NSV) load_visc(fi.en, fi.rn0 + jj * NS, fi.a, d.gn[jj]);
-            }
+        for (int jj = 0; jj < TPT; ++jj) {
+            load_state(fi.en, fi.rn0 + jj * NS, d.un[jj]);
+            if constexpr (NSV) load_visc(fi.en, fi.rn0 + jj * NS, fi.a, d.gn[jj]);
         }
     };
     auto fp_compute = [&](const FPI& fi, const FPD& d) {
@@ -438,27 +423,7 @@ __global__ __launch_bounds__((Shape<D, N1, NT, tpt_of(EQ, NT)>::BS)) void k_op(c
             constexpr int ax = decltype(A)::value;
             if (ax != fi.a) return;
             const bool right = fi.right;
-            if constexpr (AD) {
-                const int inb = right ? 0 : N1 - 1;
-                CT Dn[N1];
-#pragma unroll
-                for (int k = 0; k < N1; ++k) Dn[k] = sD[inb * N1 + (right ? k : N1 - 1 - k)];
-                const CT lw = right ? -iw0 : iw0;
-                const CT lam = CT(fabs(P.a[ax])), av = CT(P.a[ax]), J = CT(sg.rh[ax]), nu = CT(P.nu);
-#pragma unroll
-                for (int jj = 0; jj < TPT; ++jj) {
-                    const CT uo = tile[fi.to0 + jj * NS];
-                    const CT unv = d.line[jj][0];
-                    CT gn = Dn[0] * d.line[jj][0];
-#pragma unroll
-                    for (int k = 1; k < N1; ++k) gn += Dn[k] * d.line[jj][k];
-                    gn += lw * (CT(0.5) * (unv + uo) - unv);
-                    const CT fn = unv * av - (J * gn) * nu;
-                    const CT jump = right ? uo - unv : unv - uo;
-                    CT& slot = buf[ax * NL + fi.to0 + jj * NS];
-                    slot = CT(0.5) * (fn - slot) + (CT(0.5) * lam) * jump;
-                }
-            } else {
+            {
 #pragma unroll
                 for (int jj = 0; jj < TPT; ++jj) {
                     const int to = fi.to0 + jj * NS;
@@ -490,8 +455,8 @@ __global__ __launch_bounds__((Shape<D, N1, NT, tpt_of(EQ, NT)>::BS)) void k_op(c
     };
 
     // (0) every global load of the block issued at once: the tables, own
-    //     states (and NS: own -Fv), AD neighbour face values, the data of
-    //     this thread's first face point; then the tables and the tile to
+    //     states (and NS: own -Fv), the data of this thread's first face
+    //     point; then the tables and the tile to
     //     LDS (the tables were requested first, so waiting for them does not
     //     wait for the rest)
     const CT tD = CT(sg.Dx[tid < N1 * N1 ? tid : 0]);
@@ -499,7 +464,6 @@ __global__ __launch_bounds__((Shape<D, N1, NT, tpt_of(EQ, NT)>::BS)) void k_op(c
     const CT twt = CT(sg.wt[tid < NT ? tid : 0]);
     T u[TPT][R];
     CT gv[NSV ? TPT : 1][NSV ? D : 1][NSV ? R : 1];    // own -Fv, every axis
-    CT unb[AD ? D : 1][AD ? TPT : 1];
     if (active) {
 #pragma unroll
         for (int jj = 0; jj < TPT; ++jj) {
@@ -507,24 +471,6 @@ __global__ __launch_bounds__((Shape<D, N1, NT, tpt_of(EQ, NT)>::BS)) void k_op(c
             if constexpr (NSV)
 #pragma unroll
                 for (int a = 0; a < D; ++a) load_visc(e, r0 + jj * NS, a, gv[jj][a]);
-        }
-        if constexpr (AD) {
-            const ECoord x = ecoord(sg, e);
-            static_for<0, D>([&](auto A) {
-                constexpr int a = decltype(A)::value;
-                const int ia = ic[a];
-                if (ia == 0 || ia == N1 - 1) {
-                    const bool right = ia == N1 - 1;
-                    const gptr<UT> Un = Up + (int64_t)neighbour(sg, e, x, a, right) * EV +
-                                        (r0 + ((right ? 0 : N1 - 1) - ia) * ipow_c<N1, a>);
-#pragma unroll
-                    for (int jj = 0; jj < TPT; ++jj) unb[a][jj] = CT(Un[jj * NS]);
-                } else {
-                    // interior node: u_hat = u, the lift below vanishes exactly
-#pragma unroll
-                    for (int jj = 0; jj < TPT; ++jj) unb[a][jj] = value(u[jj][0]);
-                }
-            });
         }
     } else {
 #pragma unroll
@@ -547,48 +493,22 @@ __global__ __launch_bounds__((Shape<D, N1, NT, tpt_of(EQ, NT)>::BS)) void k_op(c
                 if constexpr (JVP) tile[(R + v) * NL + nd0 + jj * NS] = part(u[jj][v]);
             }
     }
-    if constexpr (AD) __syncthreads();
 
     // (1) total flux along every axis at the own nodes -> buf
     if (active) {
-        if constexpr (AD) {
-            // own lifted gradient: D contraction, then the lift with the
-            // neighbour's face value (u_hat = {u})
-            const CT nu = CT(P.nu);
+#pragma unroll
+        for (int jj = 0; jj < TPT; ++jj) {
+            const typename F::Prim w = F::prim(u[jj], P);
             static_for<0, D>([&](auto A) {
                 constexpr int a = decltype(A)::value;
-                constexpr int stride = ipow(N1, a);
-                const int ia = ic[a];
-                CT Dr[N1];
+                T f[R];
+                F::conv(a, u[jj], w, f, P);
+                if constexpr (NSV)
 #pragma unroll
-                for (int k = 0; k < N1; ++k) Dr[k] = sD[ia * N1 + k];
-                const CT J = CT(sg.rh[a]), av = CT(P.a[a]);
-                const CT lw = ia == N1 - 1 ? iw0 : (ia == 0 ? -iw0 : CT(0));
+                    for (int v = 0; v < R; ++v) add_part(f[v], gv[jj][a][v]);
 #pragma unroll
-                for (int jj = 0; jj < TPT; ++jj) {
-                    const CT* ln = tile + nd0 + jj * NS - ia * stride;
-                    CT g = Dr[0] * ln[0];
-#pragma unroll
-                    for (int k = 1; k < N1; ++k) g += Dr[k] * ln[k * stride];
-                    g += lw * (CT(0.5) * (u[jj][0] + unb[a][jj]) - u[jj][0]);
-                    buf[a * NL + nd0 + jj * NS] = u[jj][0] * av - (J * g) * nu;
-                }
+                for (int v = 0; v < R; ++v) buf[(a * R + v) * NL + nd0 + jj * NS] = part(f[v]);
             });
-        } else {
-#pragma unroll
-            for (int jj = 0; jj < TPT; ++jj) {
-                const typename F::Prim w = F::prim(u[jj], P);
-                static_for<0, D>([&](auto A) {
-                    constexpr int a = decltype(A)::value;
-                    T f[R];
-                    F::conv(a, u[jj], w, f, P);
-                    if constexpr (NSV)
-#pragma unroll
-                        for (int v = 0; v < R; ++v) add_part(f[v], gv[jj][a][v]);
-#pragma unroll
-                    for (int v = 0; v < R; ++v) buf[(a * R + v) * NL + nd0 + jj * NS] = part(f[v]);
-                });
-            }
         }
     }
     __syncthreads();
