@@ -95,8 +95,8 @@ typedef struct {
     int timing;        /* bit mask of ST_K_* kernel classes to time with HIP    */
                        /* events on the solve's stream (0 = none)               */
     int precond;       /* 0: none (default); 1: element-block Jacobi, right     */
-                       /* preconditioning -- linear equations only (advection,  */
-                       /* advection-diffusion), st_solve_slab only              */
+                       /* preconditioning (st_solve_slab only; element blocks   */
+                       /* of at most 512 unknowns, nv Nt (N+1)^d)               */
 } st_solver_opts_t;
 
 /* Kernel classes of the slab solve (bits of st_solver_opts_t.timing and
@@ -176,13 +176,16 @@ int st_jvp(st_handle_t h, const double* U, double t0, double dt, const double* v
  * U_out (may be NULL) and the end-of-slab state u_next = (e_Nt^T (x) I) U
  * (eq. (un); may be NULL).  Synchronises `stream` once per outer iteration.
  * On ST_ERR_NO_CONVERGENCE the last iterate is written and stats filled.
- * opts->precond = 1 (linear equations) right-preconditions GMRES with the
- * inverse of the element diagonal block of eq. (Jacobian_ST) -- the same
- * block in every element of the uniform periodic mesh, assembled with the
- * operator kernels and inverted on the host on the first solve with a given
- * dt (device memory npe^2 doubles, npe = Nt (N+1)^d); the solution is that
- * of the unpreconditioned system.  ST_ERR_UNSUPPORTED for the nonlinear
- * equations. */
+ * opts->precond = 1 right-preconditions GMRES with the inverse of an element
+ * diagonal block of eq. (Jacobian_ST), the same in every element: for the
+ * linear equations the exact block of the uniform periodic mesh; for the
+ * nonlinear ones the block of the Jacobian at the constant state u_bar, the
+ * quadrature-weighted mean of u_prev (conserved on the periodic mesh, so the
+ * same for every slab of a run).  Assembled with the JVP kernels and
+ * inverted on the host on the first preconditioned solve with a given dt
+ * (a copy of u_prev to the host for u_bar; device memory npe^2 doubles,
+ * npe = nv Nt (N+1)^d <= 512, else ST_ERR_UNSUPPORTED); the solution is that
+ * of the unpreconditioned system. */
 int st_solve_slab(st_handle_t h, const double* u_prev, double t0, double dt, double tol,
                   const st_solver_opts_t* opts, double* U_out, double* u_next, st_stats_t* stats,
                   void* stream);

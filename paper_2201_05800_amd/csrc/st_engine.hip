@@ -433,16 +433,19 @@ static bool invert_dense(std::vector<double>& A, int n) {
     return true;
 }
 
-// Element diagonal block B of the slab Jacobian of a linear equation and its
-// inverse, for this handle's (mesh spacing, N, Nt, equation) and dt.  B is
-// read off the operator kernel applied to the npe unit vectors of element 0
-// of a periodic 3^d-element mesh with the same spacing (so the element's
-// neighbours are distinct elements and B excludes their coupling); every
-// element of the uniform mesh has the same block.
-static int ensure_precond(st_ctx* h, double dt, hipStream_t st) {
+// Element diagonal block B of the slab Jacobian and its inverse, for this
+// handle's (mesh spacing, N, Nt, equation) and dt.  B is read off the JVP
+// applied to the npe unit vectors of element 0 of a periodic 3^d-element mesh
+// with the same spacing (so the element's neighbours are distinct elements
+// and B excludes their coupling).  Linear equations: the Jacobian is the same
+// in every element.  Nonlinear equations: the Jacobian at the constant state
+// u_bar, the quadrature-weighted mean of u_prev (the mean of the conserved
+// variables, which the scheme conserves on the periodic mesh, so every slab
+// of a run has the same u_bar); a frozen-coefficient approximation of every
+// element's block.
+static int ensure_precond(st_ctx* h, const double* u_prev, double dt, hipStream_t st) {
     const Problem& pb = h->pb;
-    if (!linear_eq(pb.eq.kind))
-        return set_error(ST_ERR_UNSUPPORTED, "element-block Jacobi is available for the linear equations only");
+    const bool lin = linear_eq(pb.eq.kind);
     const int npe = (int)(pb.nv * pb.Nt * pb.ns);
     if (npe > PC_NPE_MAX) return set_error(ST_ERR_UNSUPPORTED, "element block larger than the preconditioner supports");
     if (h->binvT && h->pc_dt == dt) return ST_OK;
@@ -456,14 +459,48 @@ static int ensure_precond(st_ctx* h, double dt, hipStream_t st) {
     CHK(make_problem(&m3, pb.N, pb.Nt, &pb.eq, pp));
     const int Gp = op_blocks(pp);
     const int64_t np = pp.n;
-    double *din = nullptr, *dout = nullptr;
+    const int d = pb.mesh.dim;
+    const bool visc = grad_pass(pb);
+    double *din = nullptr, *dout = nullptr, *dstate = nullptr, *dq = nullptr;
     OpSeg* dsegs = nullptr;
     auto cleanup = [&] {
         if (din) (void)hipFree(din);
         if (dout) (void)hipFree(dout);
+        if (dstate) (void)hipFree(dstate);
+        if (dq) (void)hipFree(dq);
         if (dsegs) (void)hipFree(dsegs);
     };
-    std::vector<OpSeg> segs(npe);
+    // nonlinear: the reference state u_bar at every node of the probe mesh
+    std::vector<double> ref;
+    if (!lin) {
+        const int64_t nprev = pb.E * pb.nv * pb.ns;
+        std::vector<double> up((size_t)nprev);
+        HIPCHK(hipMemcpyAsync(up.data(), u_prev, sizeof(double) * nprev, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        std::vector<double> W(pb.ns);
+        for (int sn = 0; sn < pb.ns; ++sn) {
+            W[sn] = 1.0;
+            for (int a = 0, q = sn; a < d; ++a, q /= pb.n1) W[sn] *= pb.wx[q % pb.n1];
+        }
+        std::vector<double> ubar(pb.nv, 0.0);
+        double wsum = 0.0;
+        for (int sn = 0; sn < pb.ns; ++sn) wsum += W[sn];
+        for (int64_t e = 0; e < pb.E; ++e)
+            for (int v = 0; v < pb.nv; ++v) {
+                const double* ue = up.data() + (e * pb.nv + v) * pb.ns;
+                double t = 0.0;
+                for (int sn = 0; sn < pb.ns; ++sn) t += W[sn] * ue[sn];
+                ubar[v] += t;
+            }
+        for (int v = 0; v < pb.nv; ++v) {
+            ubar[v] /= wsum * (double)pb.E;
+            if (!std::isfinite(ubar[v])) return set_error(ST_ERR_BAD_ARG, "preconditioner setup: u_prev is not finite");
+        }
+        ref.resize((size_t)np);
+        const int epe = pb.nv * pb.Nt * pb.ns;   // values of one element, [v][j][s]
+        for (int64_t i = 0; i < np; ++i) ref[(size_t)i] = ubar[(i % epe) / (pb.Nt * pb.ns)];
+    }
+    std::vector<OpSeg> segs(npe), gsegs(visc ? npe : 0);
     for (int c = 0; c < npe; ++c) {
         OpSeg s = base_opseg(pp, dt);
         s.blk0 = c * Gp;
@@ -472,21 +509,44 @@ static int ensure_precond(st_ctx* h, double dt, hipStream_t st) {
     }
     if (hipMalloc((void**)&din, sizeof(double) * np * npe) != hipSuccess ||
         hipMalloc((void**)&dout, sizeof(double) * np * npe) != hipSuccess ||
-        hipMalloc((void**)&dsegs, sizeof(OpSeg) * npe) != hipSuccess) {
+        hipMalloc((void**)&dsegs, sizeof(OpSeg) * npe * (visc ? 2 : 1)) != hipSuccess ||
+        (!lin && hipMalloc((void**)&dstate, sizeof(double) * np) != hipSuccess) ||
+        (visc && hipMalloc((void**)&dq, sizeof(double) * np * d * npe) != hipSuccess)) {
         cleanup();
         return set_error(ST_ERR_HIP, "preconditioner setup: device allocation failed");
     }
     for (int c = 0; c < npe; ++c) {
-        segs[c].U = dptr(din + (size_t)c * np);
+        const DynPtr unit = dptr(din + (size_t)c * np);
         segs[c].uprev = nullptr;
         segs[c].out = dptr(dout + (size_t)c * np);
+        if (lin) {
+            segs[c].U = unit;                      // R(v) with u_prev = 0 is J v
+        } else {
+            segs[c].U = dptr(dstate);
+            segs[c].V = unit;
+            if (visc) {
+                OpSeg g = segs[c];
+                g.out = dptr(dq + (size_t)c * d * np);
+                gsegs[c] = g;
+                segs[c].Q = dptr(dq + (size_t)c * d * np);
+            }
+        }
     }
     std::vector<double> B((size_t)npe * npe);
     hipError_t e = hipMemcpyAsync(dsegs, segs.data(), sizeof(OpSeg) * npe, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess && visc)
+        e = hipMemcpyAsync(dsegs + npe, gsegs.data(), sizeof(OpSeg) * npe, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess && !lin)
+        e = hipMemcpyAsync(dstate, ref.data(), sizeof(double) * np, hipMemcpyHostToDevice, st);
     if (e == hipSuccess) e = hipMemsetAsync(din, 0, sizeof(double) * np * npe, st);
     if (e == hipSuccess) {
         pc_set_units(din, np, npe, st);           // unit vector c at unknown c of element 0
-        pb.ops->res64(dsegs, npe, npe * Gp, st);  // linear: R(v) with u_prev = 0 is J v
+        if (lin) {
+            pb.ops->res64(dsegs, npe, npe * Gp, st);
+        } else {
+            if (visc) pb.ops->visc_jvp64(dsegs + npe, npe, npe * Gp, st);
+            pb.ops->jvp64(dsegs, npe, npe * Gp, st);
+        }
         e = hipGetLastError();
     }
     // element 0's block of every response: column c of B
@@ -727,7 +787,7 @@ int st_solve_slab(st_handle_t h, const double* u_prev, double t0, double dt, dou
     if (fp32) CHK(ensure_fp32(h));
     hipStream_t st = (hipStream_t)stream;
     const bool pc = o.precond == 1;
-    if (pc) CHK(ensure_precond(h, dt, st));
+    if (pc) CHK(ensure_precond(h, u_prev, dt, st));
     const int kind = pb.eq.kind;
     const int Gop = op_blocks(pb);
 

@@ -1,8 +1,9 @@
-"""Element-block Jacobi right preconditioning of the slab GMRES (linear
-equations): the preconditioned solve reaches the oracle's slab solution
-(the same system, so the same solution within the slab tolerance) in far
-fewer Arnoldi steps, in FP64 and with FP32-inner JVPs; it is rejected for
-the nonlinear equations and by the server."""
+"""Element-block Jacobi right preconditioning of the slab GMRES: the
+preconditioned solve reaches the oracle's slab solution (the same system, so
+the same solution within the slab tolerance) in fewer Arnoldi steps, in FP64
+and with FP32-inner JVPs -- the linear equations with their exact element
+block, the nonlinear ones with the block of the Jacobian at the mean state;
+element blocks above 512 unknowns and the server reject it."""
 import sys
 
 import numpy as np
@@ -60,6 +61,53 @@ def test_preconditioned_solve_matches_oracle(orc, name, c, dt, fp32):
         P.close()
 
 
+NONLIN = [
+    ("burgers1d-48", cfg("burgers", 1, [48], 3, 3), "burgers"),
+    ("euler2d-vortex-12", cfg("euler", 2, [12, 12], 3, 3, lo=[-5, -5], hi=[5, 5]), "vortex"),
+    ("ns3d-tgv-3-N2Nt2", cfg("ns", 3, [3, 3, 3], 2, 2, lo=[0, 0, 0], hi=[6.283185307179586] * 3, mu=1.0 / 1600),
+     "tgv"),
+]
+
+
+def nonlin_init(P, kind):
+    X = P.coords()
+    if kind == "vortex":
+        return inputs.isentropic_vortex(X, seed=3).ravel()
+    if kind == "burgers":
+        return inputs.burgers_smooth(X, inputs.burgers_params(4)).ravel()
+    return inputs.taylor_green(X).ravel()
+
+
+@pytest.mark.parametrize("name,c,init", NONLIN, ids=[x[0] for x in NONLIN])
+@pytest.mark.parametrize("fp32", [0, 1], ids=["fp64", "fp32inner"])
+def test_preconditioned_nonlinear_solve_matches_oracle(orc, name, c, init, fp32):
+    P = Pair(c)
+    try:
+        up = nonlin_init(P, init)
+        h = min((c["hi"][a] - c["lo"][a]) / c["K"][a] for a in range(c["dim"]))
+        if init == "vortex":
+            lam = inputs.euler_max_speed(up.reshape(P.E, P.nv, P.ns), c["gamma"])
+        elif init == "burgers":
+            lam = np.abs(up).max()
+        else:
+            lam = None
+        dt = 0.05 if lam is None else inputs.cfl_dt(5.0, h, c["N"], lam)
+        tol = 1e-11
+        say(f"[{name} fp32={fp32}] preconditioned and plain solves, n={P.n}, dt={dt:.4g}")
+        U1, un1, s1 = gpu_solve(P, up, dt, tol, inner_fp32=fp32, precond=1)
+        U0, un0, s0 = gpu_solve(P, up, dt, tol, inner_fp32=fp32, precond=0)
+        Uo, so = orc.solve(P.p, up, dt, tol=1e-13, dense_limit=0)
+        e1, e0 = rel(U1, Uo), rel(U0, Uo)
+        say(f"  precond: outer {s1['newton_its']} gmres {s1['gmres_its']} err {e1:.2e};  "
+            f"plain: outer {s0['newton_its']} gmres {s0['gmres_its']} err {e0:.2e}")
+        assert e1 <= 1e-9 and e0 <= 1e-9
+        rn = np.linalg.norm(orc.residual(P.p, U1, up, dt))
+        assert rn <= 1.01 * tol * max(1.0, s1["res0"])
+        assert s1["gmres_its"] < s0["gmres_its"], "preconditioning should cut the Arnoldi steps"
+    finally:
+        P.close()
+
+
 def test_preconditioned_solve_is_deterministic_and_reuses_the_block():
     P = Pair(cfg("advdiff", 2, [16, 16], 4, 4, hi=[0.25, 0.25], a=(1.0, 0.5), nu=1e-3))
     try:
@@ -76,14 +124,15 @@ def test_preconditioned_solve_is_deterministic_and_reuses_the_block():
 
 def test_preconditioning_rejected_where_unavailable():
     from paper_2201_05800_amd import st
-    P = Pair(cfg("burgers", 1, [16], 3, 3))
+    # an element block of 5 * 3 * 4^3 = 960 unknowns is above the limit
+    P = Pair(cfg("ns", 3, [2, 2, 2], 3, 3, lo=[0, 0, 0], hi=[6.283185307179586] * 3, mu=1.0 / 1600))
     try:
-        up = inputs.burgers_smooth(P.coords(), inputs.burgers_params(1)).ravel()
+        up = inputs.taylor_green(P.coords()).ravel()
         with pytest.raises(st.StError) as ei:
-            gpu_solve(P, up, 0.01, 1e-10, precond=1)
+            gpu_solve(P, up, 0.05, 1e-10, precond=1)
         assert ei.value.code == st.ST_ERR_UNSUPPORTED
         with pytest.raises(st.StError) as ei:
-            gpu_solve(P, up, 0.01, 1e-10, precond=2)
+            gpu_solve(P, up, 0.05, 1e-10, precond=2)
         assert ei.value.code == st.ST_ERR_BAD_ARG
     finally:
         P.close()
