@@ -1,14 +1,16 @@
-// st_precond.hip -- element-block Jacobi preconditioner for the slab GMRES of
-// the linear equations (right preconditioning).
+// st_precond.hip -- element-block Jacobi preconditioner for the slab GMRES
+// (right preconditioning).
 //
-// For advection and advection-diffusion on the uniform periodic mesh the
-// slab Jacobian (eq. (Jacobian_ST)) is the same operator in every element:
-// its diagonal block B (the coupling of an element's space-time unknowns to
+// One npe x npe matrix B serves every element: for advection and
+// advection-diffusion on the uniform periodic mesh the slab Jacobian (eq.
+// (Jacobian_ST)) is the same operator in every element, and B is its exact
+// diagonal block (the coupling of an element's space-time unknowns to
 // themselves, through the DG time discretisation, the volume terms and the
-// element's own share of its face fluxes) is one npe x npe matrix.  GMRES
-// then solves (J B^-1) y = -R and the Newton update is B^-1 (V y).  The
-// host assembles B once per (handle, dt) by applying the operator kernel to
-// unit vectors on a 3^d-element copy of the mesh, and inverts it (partial
+// element's own share of its face fluxes); for the nonlinear equations B is
+// that block of the Jacobian at a constant reference state.  GMRES then
+// solves (J B^-1) y = -R and the Newton update is B^-1 (V y).  The host
+// assembles B once per (handle, dt) by applying the JVP kernels to unit
+// vectors on a 3^d-element copy of the mesh, and inverts it (partial
 // pivoting); the kernels here apply B^-1 to every element of a vector.
 #include "st_krylov.hpp"
 
