@@ -130,7 +130,11 @@ DI int coord(int s) { return (int)(((unsigned)s / (unsigned)ipow_c<N1, A>) % (un
 struct ECoord {
     int c[3];
 };
-DI unsigned fdiv(unsigned n, unsigned m, int sh) { return (unsigned)(((uint64_t)n * m) >> sh); }
+DI unsigned fdiv(unsigned n, unsigned m, int sh) {
+    // sh = 31 only for the divisor 1 (m = 2^31); otherwise the high word of
+    // the product, shifted by sh - 32
+    return sh == 31 ? n : __umulhi(n, m) >> (sh - 32);
+}
 DI ECoord ecoord(const OpSeg& sg, int e) {
     ECoord x;
     const unsigned t = fdiv((unsigned)e, sg.dm[0], sg.ds[0]);
@@ -141,10 +145,15 @@ DI ECoord ecoord(const OpSeg& sg, int e) {
     return x;
 }
 // Element across the face of element e (coordinates x) along axis a (periodic).
+// The mesh sizes are read as uniform values first, so that a lane-varying
+// axis selects among registers (not among descriptor addresses).
 DI int neighbour(const OpSeg& sg, int e, const ECoord& x, int a, bool right) {
-    const int es = a == 0 ? 1 : (a == 1 ? sg.K[0] : sg.K[0] * sg.K[1]);
+    const int K0 = __builtin_amdgcn_readfirstlane(sg.K[0]);
+    const int K1 = __builtin_amdgcn_readfirstlane(sg.K[1]);
+    const int K2 = __builtin_amdgcn_readfirstlane(sg.K[2]);
+    const int es = a == 0 ? 1 : (a == 1 ? K0 : K0 * K1);
     const int ca = a == 0 ? x.c[0] : (a == 1 ? x.c[1] : x.c[2]);
-    const int K = a == 0 ? sg.K[0] : (a == 1 ? sg.K[1] : sg.K[2]);
+    const int K = a == 0 ? K0 : (a == 1 ? K1 : K2);
     const int step = right ? (ca + 1 == K ? 1 - K : 1) : (ca == 0 ? K - 1 : -1);
     return e + step * es;
 }
