@@ -96,7 +96,7 @@ typedef struct {
                        /* events on the solve's stream (0 = none)               */
     int precond;       /* 0: none (default); 1: element-block Jacobi, right     */
                        /* preconditioning (st_solve_slab only; element blocks   */
-                       /* of at most 512 unknowns, nv Nt (N+1)^d)               */
+                       /* of at most 1024 unknowns, nv Nt (N+1)^d)              */
 } st_solver_opts_t;
 
 /* Kernel classes of the slab solve (bits of st_solver_opts_t.timing and
@@ -184,7 +184,7 @@ int st_jvp(st_handle_t h, const double* U, double t0, double dt, const double* v
  * same for every slab of a run).  Assembled with the JVP kernels and
  * inverted on the host on the first preconditioned solve with a given dt
  * (a copy of u_prev to the host for u_bar; device memory npe^2 doubles,
- * npe = nv Nt (N+1)^d <= 512, else ST_ERR_UNSUPPORTED); the solution is that
+ * npe = nv Nt (N+1)^d <= 1024, else ST_ERR_UNSUPPORTED); the solution is that
  * of the unpreconditioned system. */
 int st_solve_slab(st_handle_t h, const double* u_prev, double t0, double dt, double tol,
                   const st_solver_opts_t* opts, double* U_out, double* u_next, st_stats_t* stats,

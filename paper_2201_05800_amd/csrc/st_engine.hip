@@ -418,15 +418,15 @@ static bool invert_dense(std::vector<double>& A, int n) {
                 std::swap(I[(size_t)p * n + k], I[(size_t)c * n + k]);
             }
         const double ip = 1.0 / piv;
-        for (int k = 0; k < n; ++k) { A[(size_t)c * n + k] *= ip; I[(size_t)c * n + k] *= ip; }
+        // columns < c of A are already unit columns: row operations start at c
+        for (int k = c; k < n; ++k) A[(size_t)c * n + k] *= ip;
+        for (int k = 0; k < n; ++k) I[(size_t)c * n + k] *= ip;
         for (int r = 0; r < n; ++r) {
             if (r == c) continue;
             const double f = A[(size_t)r * n + c];
             if (f == 0.0) continue;
-            for (int k = 0; k < n; ++k) {
-                A[(size_t)r * n + k] -= f * A[(size_t)c * n + k];
-                I[(size_t)r * n + k] -= f * I[(size_t)c * n + k];
-            }
+            for (int k = c; k < n; ++k) A[(size_t)r * n + k] -= f * A[(size_t)c * n + k];
+            for (int k = 0; k < n; ++k) I[(size_t)r * n + k] -= f * I[(size_t)c * n + k];
         }
     }
     A.swap(I);
@@ -449,6 +449,8 @@ static int ensure_precond(st_ctx* h, const double* u_prev, double dt, hipStream_
     const int npe = (int)(pb.nv * pb.Nt * pb.ns);
     if (npe > PC_NPE_MAX) return set_error(ST_ERR_UNSUPPORTED, "element block larger than the preconditioner supports");
     if (h->binvT && h->pc_dt == dt) return ST_OK;
+    if (pc_prepare(npe) != hipSuccess)
+        return set_error(ST_ERR_UNSUPPORTED, "element block needs more LDS than the device grants");
     st_mesh_t m3 = pb.mesh;
     for (int a = 0; a < 3; ++a) {
         m3.K[a] = a < pb.mesh.dim ? 3 : 1;

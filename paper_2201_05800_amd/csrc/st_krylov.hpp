@@ -22,8 +22,10 @@ void vk_extract_last(const VecSeg* s, int nseg, int G, hipStream_t st);
 void vk_cast32(const VecSeg* s, int nseg, int G, hipStream_t st);
 // element-block Jacobi (st_precond.hip): elements per block, launch, and
 // w = sum_{i < kfinal} y_i V_i for the preconditioned Newton update
-constexpr int PC_NPE_MAX = 512;     // largest element block (unknowns per element)
+constexpr int PC_NPE_MAX = 1024;    // largest element block (unknowns per element)
 int pc_blocks(int E, int npe);
+// launch set-up for blocks of npe unknowns (LDS above 64 KB)
+hipError_t pc_prepare(int npe);
 // B^-1 (row-major, npe x npe) packed as the kernel's matrix-core operand
 std::vector<double> pc_pack(const std::vector<double>& binv, int npe);
 // every segment of one launch has the same npe

@@ -38,7 +38,7 @@ DI int find_pseg(const Seg* segs, int nseg, int b) {
 }
 constexpr int PC_BLOCK = 256;               // 4 wavefronts
 constexpr int PC_EB = 16;                   // elements per block (the MFMA column count)
-constexpr int PC_TW = 8;                    // row tiles per wavefront at most (npe <= 512)
+constexpr int PC_TW = 8;                    // row tiles per wavefront and row group
 constexpr int PC_KC = 4;                    // column steps per operand chunk
 typedef double v4d __attribute__((ext_vector_type(4)));
 }  // namespace
@@ -55,8 +55,11 @@ int pc_blocks(int E, int npe) {
 // register i div 4).  B^-1 comes packed per (16-row tile, 4-column step) in
 // that A-operand lane order (zero padded), so each operand is one coalesced
 // load; the block's inputs are staged in LDS in B-operand order; wavefront w
-// takes the row tiles w, w + 4, ...; the result goes back through LDS for
-// coalesced stores.
+// takes the row tiles w, w + 4, ... of a group of at most 4 PC_TW tiles.
+// Up to 512 rows (one group) the result goes back through LDS for coalesced
+// stores; larger blocks (up to 1024 rows) run the groups one after the other
+// on the same staged inputs and store each group's tiles directly.
+template <bool GROUPED>
 __global__ __launch_bounds__(PC_BLOCK) void k_bjacobi(const PcSeg* __restrict__ segs, int nseg) {
     extern __shared__ double sm[];           // [KS * 64] B operands, then [16][npe | 1] results
     const PcSeg& sg = segs[find_pseg(segs, nseg, blockIdx.x)];
@@ -70,7 +73,8 @@ __global__ __launch_bounds__(PC_BLOCK) void k_bjacobi(const PcSeg* __restrict__ 
     const auto* __restrict__ in = gp(inb) + (int64_t)e0 * npe;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const auto* __restrict__ A = gp(sg.binvT);
-    const int TQ = (T - wave + 3) >> 2;      // row tiles of this wavefront
+    constexpr int GT = 4 * PC_TW;            // row tiles per group
+    int g0 = 0;                              // first row tile of the group
     // A operands of column steps [ks0, ks0 + PC_KC), double buffered: the
     // next chunk's loads are in flight while the current chunk multiplies
     auto load_chunk = [&](int ks0, double (&a)[PC_KC][PC_TW]) {
@@ -78,13 +82,11 @@ __global__ __launch_bounds__(PC_BLOCK) void k_bjacobi(const PcSeg* __restrict__ 
         for (int c = 0; c < PC_KC; ++c)
 #pragma unroll
             for (int q = 0; q < PC_TW; ++q) {
-                const int ks = ks0 + c, rt = wave + 4 * q;
-                a[c][q] = (q < TQ && ks < KS) ? A[((int64_t)rt * KS + ks) * 64 + lane] : 0.0;
+                const int ks = ks0 + c, rt = g0 + wave + 4 * q;
+                a[c][q] = (rt < T && ks < KS) ? A[((int64_t)rt * KS + ks) * 64 + lane] : 0.0;
             }
     };
     v4d acc[PC_TW];
-#pragma unroll
-    for (int q = 0; q < PC_TW; ++q) acc[q] = v4d{0.0, 0.0, 0.0, 0.0};
     auto mul_chunk = [&](int ks0, const double (&a)[PC_KC][PC_TW]) {
 #pragma unroll
         for (int c = 0; c < PC_KC; ++c) {
@@ -93,7 +95,7 @@ __global__ __launch_bounds__(PC_BLOCK) void k_bjacobi(const PcSeg* __restrict__ 
             const double b = sm[ks * 64 + lane];
 #pragma unroll
             for (int q = 0; q < PC_TW; ++q)
-                if (q < TQ) acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[c][q], b, acc[q], 0, 0, 0);
+                if (g0 + wave + 4 * q < T) acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[c][q], b, acc[q], 0, 0, 0);
         }
     };
     double a0[PC_KC][PC_TW], a1[PC_KC][PC_TW];
@@ -107,12 +109,41 @@ __global__ __launch_bounds__(PC_BLOCK) void k_bjacobi(const PcSeg* __restrict__ 
         if (j < ne) sm[(c >> 2) * 64 + j + 16 * (c & 3)] = in[(int64_t)j * npe + c];
     }
     __syncthreads();
-    for (int ks0 = 0; ks0 < KS; ks0 += 2 * PC_KC) {
-        load_chunk(ks0 + PC_KC, a1);
-        mul_chunk(ks0, a0);
-        if (ks0 + PC_KC >= KS) break;
-        load_chunk(ks0 + 2 * PC_KC, a0);
-        mul_chunk(ks0 + PC_KC, a1);
+    auto* __restrict__ out = gp(sg.out) + (int64_t)e0 * npe;
+    for (;;) {
+#pragma unroll
+        for (int q = 0; q < PC_TW; ++q) acc[q] = v4d{0.0, 0.0, 0.0, 0.0};
+        for (int ks0 = 0; ks0 < KS; ks0 += 2 * PC_KC) {
+            load_chunk(ks0 + PC_KC, a1);
+            mul_chunk(ks0, a0);
+            if (ks0 + PC_KC >= KS) break;
+            load_chunk(ks0 + 2 * PC_KC, a0);
+            mul_chunk(ks0 + PC_KC, a1);
+        }
+        if constexpr (!GROUPED) break;
+        // this group's tiles straight to memory: element j = lane & 15,
+        // rows 16 rt + (lane >> 4) + 4 r
+        const int j = lane & 15;
+#pragma unroll
+        for (int q = 0; q < PC_TW; ++q) {
+            const int rt = g0 + wave + 4 * q;
+            if (rt < T && j < ne) {
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int row = rt * 16 + (lane >> 4) + 4 * r;
+                    if (row < npe) {
+                        double z = acc[q][r];
+                        if (sg.accumulate) z += out[(int64_t)j * npe + row];
+                        out[(int64_t)j * npe + row] = z;
+                    }
+                }
+            }
+        }
+        if constexpr (GROUPED) {
+            g0 += GT;
+            if (g0 >= T) return;
+            load_chunk(0, a0);
+        }
     }
     __syncthreads();                         // B operands consumed: reuse sm for the results
     const int SR = npe | 1;                  // odd row stride: no LDS bank conflicts across j
@@ -128,7 +159,6 @@ __global__ __launch_bounds__(PC_BLOCK) void k_bjacobi(const PcSeg* __restrict__ 
         }
     }
     __syncthreads();
-    auto* __restrict__ out = gp(sg.out) + (int64_t)e0 * npe;
     for (int t = threadIdx.x; t < ne * npe; t += PC_BLOCK) {
         const int j = t / npe, row = t - j * npe;
         double z = sm[j * SR + row];
@@ -245,14 +275,30 @@ __global__ void k_set_units(double* x, int64_t ld, int count) {
 
 __global__ void k_put_pcseg(PcSeg* dst, PcSeg v) { if (threadIdx.x == 0 && blockIdx.x == 0) *dst = v; }
 
+// dynamic LDS of k_bjacobi for element blocks of npe unknowns
+static size_t bjacobi_lds(int npe) {
+    const int KS = (npe + 3) / 4, T = (npe + 15) / 16;
+    if (T > 4 * PC_TW) return sizeof(double) * 64 * (size_t)KS;    // grouped rows: inputs only
+    return sizeof(double) * std::max<size_t>(64 * (size_t)KS, 16 * (size_t)(npe | 1));
+}
+
+hipError_t pc_prepare(int npe) {
+    if (npe < 1 || npe > PC_NPE_MAX) return hipErrorInvalidValue;
+    const size_t shm = bjacobi_lds(npe);
+    if (shm <= 64 * 1024) return hipSuccess;
+    return hipFuncSetAttribute((const void*)k_bjacobi<true>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+}
+
 void pc_apply(const PcSeg* s, int nseg, int G, int npe, hipStream_t st) {
     const int KS = (npe + 3) / 4, T = (npe + 15) / 16;
     if (T <= PC_TW && (KS + 3) / 4 <= 8) {
         const size_t shm = sizeof(double) * std::max<size_t>(64 * (size_t)KS, 4 * 16 * (16 * (size_t)T + 1));
         launch_ks(k_bjacobi_ks, dim3(G), dim3(PC_BLOCK), shm, st, s, nseg);
     } else {
-        const size_t shm = sizeof(double) * std::max<size_t>(64 * (size_t)KS, 16 * (size_t)(npe | 1));
-        launch_ks(k_bjacobi, dim3(G), dim3(PC_BLOCK), shm, st, s, nseg);
+        if (T > 4 * PC_TW)
+            launch_ks(k_bjacobi<true>, dim3(G), dim3(PC_BLOCK), bjacobi_lds(npe), st, s, nseg);
+        else
+            launch_ks(k_bjacobi<false>, dim3(G), dim3(PC_BLOCK), bjacobi_lds(npe), st, s, nseg);
     }
 }
 void pc_combine(const VecSeg* s, int nseg, int G, hipStream_t st) {

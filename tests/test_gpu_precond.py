@@ -66,6 +66,10 @@ NONLIN = [
     ("euler2d-vortex-12", cfg("euler", 2, [12, 12], 3, 3, lo=[-5, -5], hi=[5, 5]), "vortex"),
     ("ns3d-tgv-3-N2Nt2", cfg("ns", 3, [3, 3, 3], 2, 2, lo=[0, 0, 0], hi=[6.283185307179586] * 3, mu=1.0 / 1600),
      "tgv"),
+    # the 3D Navier-Stokes workload's element: 5 * 3 * 4^3 = 960 unknowns
+    # (row groups of the matrix-core kernel, LDS above 64 KB)
+    ("ns3d-tgv-3-N3Nt3", cfg("ns", 3, [3, 3, 3], 3, 3, lo=[0, 0, 0], hi=[6.283185307179586] * 3, mu=1.0 / 1600),
+     "tgv"),
 ]
 
 
@@ -124,8 +128,8 @@ def test_preconditioned_solve_is_deterministic_and_reuses_the_block():
 
 def test_preconditioning_rejected_where_unavailable():
     from paper_2201_05800_amd import st
-    # an element block of 5 * 3 * 4^3 = 960 unknowns is above the limit
-    P = Pair(cfg("ns", 3, [2, 2, 2], 3, 3, lo=[0, 0, 0], hi=[6.283185307179586] * 3, mu=1.0 / 1600))
+    # an element block of 5 * 2 * 5^3 = 1250 unknowns is above the limit
+    P = Pair(cfg("ns", 3, [2, 2, 2], 4, 2, lo=[0, 0, 0], hi=[6.283185307179586] * 3, mu=1.0 / 1600))
     try:
         up = inputs.taylor_green(P.coords()).ravel()
         with pytest.raises(st.StError) as ei:
