@@ -212,15 +212,24 @@ def serving_bench(n_requests, seed=4, budget_gib=64, max_active=64, load=0.7):
     unknowns = sum(st.st_request_footprint(r) for _, r, _ in reqs)
     wall_sat, lat_sat, ok_sat, _ = run(reqs, [0.0] * len(reqs))
     thr = len(reqs) / wall_sat
-    rate = load * thr
-    g = np.random.default_rng(seed + 1)
-    arr = np.cumsum(g.exponential(1.0 / rate, size=len(reqs)))
-    wall_p, lat_p, ok_p, stats_p = run(reqs, arr)
+    # Poisson arrivals at 50 / 70 / 90 % of the saturated throughput, and at
+    # a fixed 4096 requests/s (beyond saturation: the queue absorbs it)
+    sweep, ok_all, stats_p, lat_p, rate = [], ok_sat, None, None, load * thr
+    for frac, fixed in ((0.5, None), (load, None), (0.9, None), (None, 4096.0)):
+        r_s = fixed if fixed else frac * thr
+        g = np.random.default_rng(seed + 1)
+        arr = np.cumsum(g.exponential(1.0 / r_s, size=len(reqs)))
+        wall_i, lat_i, ok_i, stats_i = run(reqs, arr)
+        ok_all = min(ok_all, ok_i)
+        sweep.append(dict(load=frac, rate_per_s=r_s, latency_ms_p50=float(np.percentile(lat_i, 50)),
+                          latency_ms_p99=float(np.percentile(lat_i, 99)), solves_per_s=len(reqs) / wall_i, ok=ok_i))
+        if frac == load:
+            stats_p, lat_p = stats_i, lat_i
     return dict(requests=len(reqs), saturated_solves_per_s=thr, saturated_wall_s=wall_sat,
                 poisson_rate_per_s=rate, load=load, latency_ms_p50=float(np.percentile(lat_p, 50)),
                 latency_ms_p99=float(np.percentile(lat_p, 99)), latency_ms_p50_saturated=float(np.percentile(lat_sat, 50)),
-                latency_ms_p99_saturated=float(np.percentile(lat_sat, 99)), ok=min(ok_sat, ok_p),
-                ticks=stats_p["ticks"], footprint_bytes_total=unknowns,
+                latency_ms_p99_saturated=float(np.percentile(lat_sat, 99)), ok=ok_all,
+                loads=sweep, ticks=stats_p["ticks"], footprint_bytes_total=unknowns,
                 mix="1D Burgers + 2D advection-diffusion, K 8..256, N 2..5, Nt 2..4, FP64/FP32-inner 50/50, CFL 5")
 
 
