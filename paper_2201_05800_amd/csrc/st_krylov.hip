@@ -109,10 +109,12 @@ DI void reduce_table(const __attribute__((address_space(1))) double* P, int ld, 
     __syncthreads();
 }
 
-// Elements per thread and loop step of the Gram-Schmidt sweeps: two while
-// the basis entries of both fit in registers, else one.
+// Elements per thread and loop step of the Gram-Schmidt sweeps: as many as
+// keep the basis entries of all of them in registers at two waves per SIMD
+// (the launches hold at most two blocks per CU), so that a thread issues its
+// loads in few rounds.
 template <int NV>
-constexpr int sweep_unroll() { return NV <= 24 ? 2 : 1; }
+constexpr int sweep_unroll() { return NV <= 13 ? 4 : (NV <= 18 ? 3 : (NV <= 27 ? 2 : 1)); }
 
 // Basis entries V_i[t + q stride] (i < NV, q < UN) and w[t + q stride]; zero
 // past the end.  All loads are issued before any is used.
