@@ -90,20 +90,13 @@ constexpr int best_epb(int npe) {
 }
 
 // LDS pitch of one element's NPE nodes in the operator kernels' tiles
-#ifndef ST_LDS_PAD
-#define ST_LDS_PAD 0
-#endif
-constexpr int lds_pitch(int npe) { return npe + ST_LDS_PAD; }
+// (padding measured: bank conflicts fall, run time does not)
+constexpr int lds_pitch(int npe) { return npe; }
 
 // Time nodes per thread: the scalar equations keep all Nt time nodes of a
 // spatial node in one thread (few registers, index work shared by Nt
 // nodes); the systems take one space-time node per thread (registers).
-#ifndef ST_TPT_SCALAR
-#define ST_TPT_SCALAR 0
-#endif
-__host__ __device__ constexpr int tpt_of(int eq, int nt) {
-    return nvars_of(eq, 1) == 1 ? ((ST_TPT_SCALAR > 0 && nt % ST_TPT_SCALAR == 0) ? ST_TPT_SCALAR : nt) : 1;
-}
+__host__ __device__ constexpr int tpt_of(int eq, int nt) { return nvars_of(eq, 1) == 1 ? nt : 1; }
 
 template <int D, int N1, int NT, int TPT>
 struct Shape {
