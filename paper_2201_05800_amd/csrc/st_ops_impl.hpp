@@ -660,7 +660,7 @@ __global__ __launch_bounds__((Shape<D, N1, NT, NT>::BS)) void k_lin(const OpSeg*
     // from the face inwards
     struct FPI {
         int a, side, rn, step, en;
-        bool ok;
+        bool ok, local;      // local: the neighbour is one of the block's elements (read from the tile)
     };
     auto fp_info = [&](int p) {
         FPI fi;
@@ -677,10 +677,11 @@ __global__ __launch_bounds__((Shape<D, N1, NT, NT>::BS)) void k_lin(const OpSeg*
         fi.rn = face_node_rt<D, N1>(fi.a, f, right) + (right ? -N : N) * stride;   // neighbour's face node
         fi.step = right ? stride : -stride;
         fi.en = fi.ok ? neighbour(sg, ep, ecoord(sg, ep), fi.a, right) : 0;
+        fi.local = fi.ok && fi.en >= e0 && fi.en < e0 + EPB;
         return fi;
     };
     auto fp_load = [&](const FPI& fi, CT (&nl)[NT][N]) {
-        if (!fi.ok) return;
+        if (!fi.ok || fi.local) return;
         const gptr<UT> lb = Up + (int64_t)fi.en * NPE + fi.rn;
 #pragma unroll
         for (int j = 0; j < NT; ++j)
@@ -690,6 +691,18 @@ __global__ __launch_bounds__((Shape<D, N1, NT, NT>::BS)) void k_lin(const OpSeg*
     auto fp_compute = [&](int p, const FPI& fi, const CT (&nl)[NT][N]) {
         if (!fi.ok) return;
         const CT* Fs = sL + fi.a * LA + N1 * N1 + 2 * N1 + fi.side * N1;   // FL or FR
+        if (fi.local) {
+            // the neighbour's line from the tile (after the first barrier)
+            const CT* ln = tile + (fi.en - e0) * LP + fi.rn;
+#pragma unroll
+            for (int j = 0; j < NT; ++j) {
+                CT c = Fs[1] * ln[j * NS + fi.step];
+#pragma unroll
+                for (int m = 2; m <= N; ++m) c += Fs[m] * ln[j * NS + m * fi.step];
+                fsum[p * NT + j] = c;
+            }
+            return;
+        }
 #pragma unroll
         for (int j = 0; j < NT; ++j) {
             CT c = Fs[1] * nl[j][0];
