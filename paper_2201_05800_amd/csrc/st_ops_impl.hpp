@@ -383,7 +383,7 @@ __global__ __launch_bounds__((Shape<D, N1, NT, tpt_of(EQ, NT)>::BS)) void k_op(c
     // so that a wavefront mostly works on one axis.
     struct FPI {
         int a, pel, to0, rn0, en, stride;
-        bool right, ok;
+        bool right, ok, local;   // local: the neighbour is one of the block's elements (state from the tile)
     };
     auto fp_info = [&](int p) {
         FPI fi;
@@ -403,6 +403,7 @@ __global__ __launch_bounds__((Shape<D, N1, NT, tpt_of(EQ, NT)>::BS)) void k_op(c
         fi.rn0 = jg * TPT * NS + so + (fi.right ? -(N1 - 1) : (N1 - 1)) * fi.stride;   // neighbour's node
         fi.to0 = fi.pel * LP + jg * TPT * NS + so;                                     // own block node
         fi.en = fi.ok ? neighbour(sg, ep, ecoord(sg, ep), fi.a, fi.right) : 0;
+        fi.local = fi.ok && fi.en >= e0 && fi.en < e0 + EPB;
         return fi;
     };
     // neighbour data of a face point: its state (and NS: its -Fv along the
@@ -415,7 +416,7 @@ __global__ __launch_bounds__((Shape<D, N1, NT, tpt_of(EQ, NT)>::BS)) void k_op(c
         if (!fi.ok) return;
 #pragma unroll
         for (int jj = 0; jj < TPT; ++jj) {
-            load_state(fi.en, fi.rn0 + jj * NS, d.un[jj]);
+            if (!fi.local) load_state(fi.en, fi.rn0 + jj * NS, d.un[jj]);
             if constexpr (NSV) load_visc(fi.en, fi.rn0 + jj * NS, fi.a, d.gn[jj]);
         }
     };
@@ -435,7 +436,20 @@ __global__ __launch_bounds__((Shape<D, N1, NT, tpt_of(EQ, NT)>::BS)) void k_op(c
                         if constexpr (JVP) uo[v] = make_state<T>(tile[v * NL + to], tile[(R + v) * NL + to]);
                         else uo[v] = tile[v * NL + to];
                     }
-                    const T* un = d.un[jj];
+                    T unl[R];
+                    if (fi.local) {
+                        // the neighbour's state from the tile (after the first barrier)
+                        const int tn = (fi.en - e0) * LP + fi.rn0 + jj * NS;
+#pragma unroll
+                        for (int v = 0; v < R; ++v) {
+                            if constexpr (JVP) unl[v] = make_state<T>(tile[v * NL + tn], tile[(R + v) * NL + tn]);
+                            else unl[v] = tile[v * NL + tn];
+                        }
+                    } else {
+#pragma unroll
+                        for (int v = 0; v < R; ++v) unl[v] = d.un[jj][v];
+                    }
+                    const T* un = unl;
                     const typename F::Prim w = F::prim(un, P);
                     F::conv(ax, un, w, fn, P);
                     if constexpr (NSV) {
