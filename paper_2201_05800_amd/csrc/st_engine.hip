@@ -222,26 +222,20 @@ static void line_operator(const Problem& pb, int a, double* out) {
     }
 }
 
-OpSeg base_opseg(const Problem& pb, double dt) {
-    OpSeg s;
-    std::memset(&s, 0, sizeof(s));
-    for (int a = 0; a < 3; ++a) {
-        s.K[a] = pb.K[a];
-        s.rh[a] = 2.0 / pb.h[a];
-    }
-    s.E = (int)pb.E;
-    for (int a = 0; a < 2; ++a) div_magic(pb.K[a], s.dm[a], s.ds[a]);
-    // Block traversal: columns of tx x ty elements swept through z, each
-    // column row by row, so that a face neighbour is met again within a few
-    // rows of the column (L2 reuse of halo traces) rather than a whole plane
-    // of the mesh later.  tx is a multiple of the elements per block and
-    // divides K0, ty divides K1; 2D takes whole-height strips, 3D small
-    // columns.  Lexicographic when K0 is not a multiple of the block width.
+// Block traversal: columns of tx x ty elements swept through z, each column
+// row by row, so that a face neighbour is met again within a few rows of the
+// column (L2 reuse of halo traces) rather than a whole plane of the mesh
+// later.  tx is a multiple of the elements per block and divides K0, ty
+// divides K1; 2D takes whole-height strips 64 elements wide, 3D columns of
+// about want3d x want3d elements (measured best: about 10 x 10 for the
+// operator kernels, 4 x 4 for the viscous pass).  Lexicographic when K0 is
+// not a multiple of the block width.
+static void set_tiles(OpSeg& s, const Problem& pb, int want3d) {
     const int epb = pb.ops->epb;
     s.tx = 0;
     s.ty = 0;
     if (pb.mesh.dim >= 2 && pb.K[0] % epb == 0) {
-        const int want_x = pb.mesh.dim == 2 ? 64 : 4, want_y = pb.mesh.dim == 2 ? pb.K[1] : 4;
+        const int want_x = pb.mesh.dim == 2 ? 64 : want3d, want_y = pb.mesh.dim == 2 ? pb.K[1] : want3d;
         int tx = epb;
         for (int c = epb; c <= pb.K[0] && c <= std::max(want_x, epb); c += epb)
             if (pb.K[0] % c == 0) tx = c;
@@ -257,6 +251,20 @@ OpSeg base_opseg(const Problem& pb, double dt) {
         s.tk[3] = pb.K[0] / tx;               // tiles along x
         for (int i = 0; i < 4; ++i) div_magic(s.tk[i], s.tm[i], s.ts[i]);
     }
+}
+
+void visc_tiles(OpSeg& s, const Problem& pb) { set_tiles(s, pb, 4); }
+
+OpSeg base_opseg(const Problem& pb, double dt) {
+    OpSeg s;
+    std::memset(&s, 0, sizeof(s));
+    for (int a = 0; a < 3; ++a) {
+        s.K[a] = pb.K[a];
+        s.rh[a] = 2.0 / pb.h[a];
+    }
+    s.E = (int)pb.E;
+    for (int a = 0; a < 2; ++a) div_magic(pb.K[a], s.dm[a], s.ds[a]);
+    set_tiles(s, pb, 12);
     s.iw0 = 1.0 / pb.wx[0];
     if (linear_eq(pb.eq.kind))
         for (int a = 0; a < pb.mesh.dim; ++a) line_operator(pb, a, s.lin + a * LIN_AXIS);
@@ -528,6 +536,7 @@ static int ensure_precond(st_ctx* h, const double* u_prev, double dt, hipStream_
             segs[c].V = unit;
             if (visc) {
                 OpSeg g = segs[c];
+                visc_tiles(g, pp);
                 g.out = dptr(dq + (size_t)c * d * np);
                 gsegs[c] = g;
                 segs[c].Q = dptr(dq + (size_t)c * d * np);
@@ -667,6 +676,7 @@ int st_residual(st_handle_t h, const double* U, const double* u_prev, double t0,
     OpSeg s = base_opseg(pb, dt);
     if (grad_pass(pb)) {
         OpSeg g = s;
+        visc_tiles(g, pb);
         g.U = dptr(U);
         g.out = dptr(h->Q);
         put_opseg(h->d_op + 0, g, st);
@@ -701,6 +711,7 @@ void setup_jvp(st_ctx* h, const double* U, DynPtr V, double* out, const int* ski
     const DynPtr state = dptr(fp32 ? (const void*)h->U32 : (const void*)U);
     if (grad_pass(pb)) {
         OpSeg g = s;
+        visc_tiles(g, pb);
         g.U = state;
         g.V = V;
         g.out = dptr(fp32 ? (void*)h->dQ32 : (void*)h->dQ);
@@ -828,6 +839,7 @@ int st_solve_slab(st_handle_t h, const double* u_prev, double t0, double dt, dou
     OpSeg rs = base_opseg(pb, dt);
     if (grad_pass(pb)) {
         OpSeg g = rs;
+        visc_tiles(g, pb);
         g.U = dptr(h->U);
         g.out = dptr(h->Q);
         put_opseg(h->d_op + 0, g, st);

@@ -32,6 +32,8 @@ void lgl_tables(int n, double* x, double* w, double* D);
 const OpTable* find_table(int eq, int dim, int n1, int nt);
 int make_problem(const st_mesh_t* mesh, int N, int Nt, const st_equation_t* eq, Problem& pb);
 OpSeg base_opseg(const Problem& pb, double dt);
+// the viscous pass's block traversal (narrower 3D columns than the operator's)
+void visc_tiles(OpSeg& s, const Problem& pb);
 DynPtr dptr(const void* p);
 DynPtr dptr_k(const void* base, int64_t ld, const int* kp);
 

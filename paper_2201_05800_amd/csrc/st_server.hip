@@ -265,6 +265,7 @@ std::vector<OpGroup> build_res_groups(st_srv* s, const std::vector<Req*>& rs) {
         OpSeg base = base_opseg(pb, r->dt);
         if (grad_pass(pb)) {
             OpSeg gr = base;
+            visc_tiles(gr, pb);
             gr.U = dptr(r->dp(r->lay.U));
             gr.out = dptr(r->dp(r->lay.Q));
             g->grad.push_back(gr);
@@ -307,6 +308,7 @@ std::vector<OpGroup> build_jvp_groups(st_srv* s, const std::vector<Req*>& rs) {
         if (grad_pass(pb)) {
             // NS viscous pass: tangent of -Fv at (U, v)
             OpSeg gr = b;
+            visc_tiles(gr, pb);
             gr.U = state;
             gr.V = Vk;
             gr.out = dptr(dQ);
