@@ -454,8 +454,18 @@ __global__ __launch_bounds__(VBLOCK) void k_cast32(const VecSeg* __restrict__ se
     }
 }
 
-__global__ void k_put_opseg(OpSeg* dst, OpSeg v) { if (threadIdx.x == 0 && blockIdx.x == 0) *dst = v; }
-__global__ void k_put_vecseg(VecSeg* dst, VecSeg v) { if (threadIdx.x == 0 && blockIdx.x == 0) *dst = v; }
+// Descriptor uploads in stream order: the descriptor is the kernel's first
+// argument, so it sits at the start of the kernel-argument segment, and the
+// threads copy its 8-byte words in parallel (one thread copying a 3 KB
+// operator descriptor took about 8 us).
+template <class S>
+__global__ void k_put_desc(S v, S* dst) {
+    static_assert(sizeof(S) % 8 == 0, "descriptor of whole 8-byte words");
+    (void)v;
+    const auto* src = (const __attribute__((address_space(4))) uint64_t*)__builtin_amdgcn_kernarg_segment_ptr();
+    auto* d = (__attribute__((address_space(1))) uint64_t*)dst;
+    for (int i = threadIdx.x; i < (int)(sizeof(S) / 8); i += blockDim.x) d[i] = src[i];
+}
 
 // ---------------------------------------------------------------------------
 // host launchers
@@ -500,10 +510,10 @@ void vk_init_guess(const VecSeg* s, int nseg, int G, hipStream_t st) { LAUNCH_V(
 void vk_extract_last(const VecSeg* s, int nseg, int G, hipStream_t st) { LAUNCH_V(k_extract_last, G, s, nseg); }
 void vk_cast32(const VecSeg* s, int nseg, int G, hipStream_t st) { LAUNCH_V(k_cast32, G, s, nseg); }
 void put_opseg(OpSeg* dst, const OpSeg& v, hipStream_t st) {
-    launch_k(k_put_opseg, dim3(1), dim3(64), st, dst, v);
+    launch_k(k_put_desc<OpSeg>, dim3(1), dim3(256), st, v, dst);
 }
 void put_vecseg(VecSeg* dst, const VecSeg& v, hipStream_t st) {
-    launch_k(k_put_vecseg, dim3(1), dim3(64), st, dst, v);
+    launch_k(k_put_desc<VecSeg>, dim3(1), dim3(64), st, v, dst);
 }
 
 }  // namespace stdg
