@@ -81,6 +81,10 @@ MID = [
     cfg("euler", 3, [5, 4, 3], 3, 3),
     cfg("ns", 3, [5, 3, 4], 3, 3, lo=[0, 0, 0], hi=[6.283185307179586] * 3, mu=1.0 / 1600),
     cfg("ns", 2, [17, 9], 4, 2),
+    # tiled block traversals: a 2D strip of whole blocks (K0 a multiple of the
+    # 5 elements per block), and 3D operator columns of 10 x 10 elements
+    cfg("advdiff", 2, [20, 6], 4, 4, nu=1e-3),
+    cfg("ns", 3, [10, 10, 2], 3, 3, lo=[0, 0, 0], hi=[6.283185307179586] * 3, mu=1.0 / 1600),
 ]
 
 
