@@ -857,8 +857,8 @@ __global__ __launch_bounds__((Shape<D, N1, NT, NT>::BS)) void k_lin(const OpSeg*
 // double).  Output out[((e * D + a) * R + v) * Nt + j) * ns + s], type CT.
 // Same block shape and traversal as k_op.
 // ---------------------------------------------------------------------------
-// Two waves per SIMD are asked for: the FP64 tangent pass would otherwise
-// take all 512 registers of a lane and run one wave per SIMD.
+// At least two waves per SIMD are asked for; the FP64 tangent pass keeps
+// within that by parking the viscous state in LDS (below).
 template <int D, int N1, int NT, class CT, class UT, bool JVP>
 __global__ __attribute__((amdgpu_waves_per_eu(2))) __launch_bounds__((Shape<D, N1, NT, 1>::BS)) void k_visc(const OpSeg* __restrict__ segs, int nseg, int G) {
     using SH = Shape<D, N1, NT, 1>;
@@ -869,6 +869,11 @@ __global__ __attribute__((amdgpu_waves_per_eu(2))) __launch_bounds__((Shape<D, N
     constexpr int EV = R * NPE;
     constexpr int TS = JVP ? 2 : 1;
     __shared__ CT tile[TS * R * B];             // [plane][v][node]
+    // JVP: the velocity and temperature gradients (value, tangent) parked in
+    // LDS while the next axes are differentiated, so the tangent pass holds
+    // fewer registers ([plane][b * D + c | D * D + b][node])
+    constexpr int NZ = D * D + D;
+    __shared__ CT zs[JVP ? 2 * NZ * B : 1];
     __shared__ CT sD[N1 * N1];
     const int L = xcd_remap(blockIdx.x, G);
     const OpSeg& sg = segs[find_seg(segs, nseg, L)];
@@ -953,7 +958,28 @@ __global__ __attribute__((amdgpu_waves_per_eu(2))) __launch_bounds__((Shape<D, N
             qb[v] = J * g;
         }
         F::visc_axis(b, w, qb, z, P);
+        if constexpr (JVP) {
+#pragma unroll
+            for (int c = 0; c < D; ++c) {
+                zs[(b * D + c) * B + tid] = value(z.gv[b][c]);
+                zs[(NZ + b * D + c) * B + tid] = part(z.gv[b][c]);
+            }
+            zs[(D * D + b) * B + tid] = value(z.gT[b]);
+            zs[(NZ + D * D + b) * B + tid] = part(z.gT[b]);
+        }
     });
+    if constexpr (JVP) {
+        // reload (the asm keeps the compiler from carrying the values in
+        // registers across the axes instead)
+        __asm__ volatile("" ::: "memory");
+#pragma unroll
+        for (int b = 0; b < D; ++b) {
+#pragma unroll
+            for (int c = 0; c < D; ++c)
+                z.gv[b][c] = make_state<T>(zs[(b * D + c) * B + tid], zs[(NZ + b * D + c) * B + tid]);
+            z.gT[b] = make_state<T>(zs[(D * D + b) * B + tid], zs[(NZ + D * D + b) * B + tid]);
+        }
+    }
     F::visc_div(z);
     const gptr<CT> Qe = Qp + (int64_t)e * (D * EV);
     static_for<0, D>([&](auto A) {
