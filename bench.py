@@ -479,6 +479,10 @@ def main():
         "gmres_its_per_slab": sum(s["gmres_its"] for s in stats) / len(stats),
         "operator_evals": op_evals,
         "kernel_time_share_of_timed": shares,
+        # algorithmic bytes of the timed steps per kernel class (the library's
+        # per-launch byte model, summed)
+        "kernel_bytes_of_timed": {st.KERNEL_CLASSES[c]: sum(s["kernel_bytes"][c] for s in stats)
+                                  for c in range(len(st.KERNEL_CLASSES))},
         "roofline": roof,
         "preconditioned": precond,
         "serving": serving,

@@ -56,6 +56,53 @@ DI int find_vseg(const VecSeg* segs, int nseg, int b) {
 
 constexpr int VWAVES = VBLOCK / 64;
 
+// Element-wise sweeps y_i = f(x_i) over one slab's vector: pairs of elements
+// per 16-byte access where n is even and both vectors allow it (at most
+// VMAXBLK blocks of a slab are resident, and with 8-byte accesses they leave
+// the memory pipeline half idle: measured 3.4 against 5.4 TB/s for the FP32
+// cast of 50 M values), else one element per access; UNP accesses per thread
+// and loop step.  Either way each y_i is f(x_i), bit for bit.
+constexpr int UNP = 4;
+typedef double v2d __attribute__((ext_vector_type(2)));    // a pair of elements (16 bytes)
+typedef float v2f __attribute__((ext_vector_type(2)));
+template <class X, class Y, class F>
+DI void map_sweep(const X* x, Y* y, int64_t n, int64_t t0, int64_t stride, F f) {
+    using X2 = typename std::conditional<sizeof(X) == 8, v2d, v2f>::type;
+    using Y2 = typename std::conditional<sizeof(Y) == 8, v2d, v2f>::type;
+    const bool pairs = (n & 1) == 0 && ((uintptr_t)x % sizeof(X2)) == 0 && ((uintptr_t)y % sizeof(Y2)) == 0;
+    if (pairs) {
+        const auto* __restrict__ x2 = gl((const X2*)x);
+        auto* __restrict__ y2 = gl((Y2*)y);
+        const int64_t np = n >> 1;
+        for (int64_t i = t0; i < np; i += UNP * stride) {
+            X2 a[UNP];
+#pragma unroll
+            for (int q = 0; q < UNP; ++q)
+                if (i + q * stride < np) a[q] = x2[i + q * stride];
+#pragma unroll
+            for (int q = 0; q < UNP; ++q)
+                if (i + q * stride < np) {
+                    Y2 b;
+                    b.x = f(a[q].x);
+                    b.y = f(a[q].y);
+                    y2[i + q * stride] = b;
+                }
+        }
+    } else {
+        const auto* __restrict__ x1 = gl(x);
+        auto* __restrict__ y1 = gl(y);
+        for (int64_t i = t0; i < n; i += UNP * stride) {
+            X a[UNP];
+#pragma unroll
+            for (int q = 0; q < UNP; ++q)
+                if (i + q * stride < n) a[q] = x1[i + q * stride];
+#pragma unroll
+            for (int q = 0; q < UNP; ++q)
+                if (i + q * stride < n) y1[i + q * stride] = f(a[q]);
+        }
+    }
+}
+
 // Block reduction of NV per-thread values; returns with sums in out[0..NV)
 // (waves added in a fixed order).  smem: VWAVES * NV doubles.
 template <int NV>
@@ -116,19 +163,41 @@ DI void reduce_table(const __attribute__((address_space(1))) double* P, int ld, 
 template <int NV>
 constexpr int sweep_unroll() { return NV <= 13 ? 4 : (NV <= 18 ? 3 : (NV <= 27 ? 2 : 1)); }
 
-// Basis entries V_i[t + q stride] (i < NV, q < UN) and w[t + q stride]; zero
-// past the end.  All loads are issued before any is used.
-template <int NV, int UN>
-DI void load_group(const __attribute__((address_space(1))) double* V, const __attribute__((address_space(1))) double* w,
-                   int64_t n, int64_t t, int64_t stride, double (&a)[UN][NV], double (&wv)[UN]) {
+// The Gram-Schmidt sweeps move one element (double) or, where n is even
+// and the vectors allow 16-byte accesses, a pair of elements (v2d) per
+// access: a wave then moves 1 KB per load instruction, which the at most
+// VMAXBLK blocks of a slab need to keep HBM busy.  Pairs per thread and loop
+// step: half the elements, rounded up; none (element accesses) where a thread
+// takes one element per step, since a pair would double its registers.
+template <int NV>
+constexpr int sweep_unroll_pairs() { return sweep_unroll<NV>() >= 2 ? (sweep_unroll<NV>() + 1) / 2 : 0; }
+DI double zero_of(double) { return 0.0; }
+DI v2d zero_of(v2d) { return v2d{0.0, 0.0}; }
+DI double dot_of(double a, double b) { return a * b; }
+DI double dot_of(v2d a, v2d b) { return a.x * b.x + a.y * b.y; }
+DI void sub_scaled(double& w, double h, double a) { w -= h * a; }
+DI void sub_scaled(v2d& w, double h, v2d a) { w.x -= h * a.x; w.y -= h * a.y; }
+DI double scaled(double s, double w) { return s * w; }
+DI v2d scaled(double s, v2d w) { return v2d{s * w.x, s * w.y}; }
+
+// Basis entries V_i[t + q stride] (i < NV, q < UN) and w[t + q stride], in
+// units of E (n of them per vector); zero past the end.  All loads are
+// issued before any is used.
+template <int NV, int UN, class E>
+DI void load_group(const __attribute__((address_space(1))) E* V, const __attribute__((address_space(1))) E* w,
+                   int64_t n, int64_t t, int64_t stride, E (&a)[UN][NV], E (&wv)[UN]) {
 #pragma unroll
     for (int q = 0; q < UN; ++q) {
         const int64_t tq = t + q * stride;
         const bool p = tq < n;
 #pragma unroll
-        for (int i = 0; i < NV; ++i) a[q][i] = p ? V[(int64_t)i * n + tq] : 0.0;
-        wv[q] = p ? w[tq] : 0.0;
+        for (int i = 0; i < NV; ++i) a[q][i] = p ? V[(int64_t)i * n + tq] : zero_of(E{});
+        wv[q] = p ? w[tq] : zero_of(E{});
     }
+}
+// pairs where n is even and the vectors are 16-byte aligned
+DI bool use_pairs(int64_t n, const void* V, const void* w) {
+    return (n & 1) == 0 && ((uintptr_t)V & 15) == 0 && ((uintptr_t)w & 15) == 0;
 }
 
 }  // namespace
@@ -186,10 +255,9 @@ __global__ __launch_bounds__(VBLOCK) void k_scale_v0(const VecSeg* __restrict__ 
     if (sg.st->done) return;
     const int lb = blockIdx.x - sg.blk0;
     const double s = -1.0 / sg.st->beta;
-    const auto* __restrict__ R = gl((const double*)sg.R);
-    auto* __restrict__ V = gl(sg.V);
     const int64_t stride = (int64_t)sg.nblk * VBLOCK;
-    for (int64_t i = (int64_t)lb * VBLOCK + threadIdx.x; i < sg.n; i += stride) V[i] = s * R[i];
+    map_sweep((const double*)sg.R, sg.V, sg.n, (int64_t)lb * VBLOCK + threadIdx.x, stride,
+              [s](double r) { return s * r; });
 }
 
 // Projections V_i . w (i < NV) and w . w of one Gram-Schmidt pass, as one
@@ -201,35 +269,51 @@ __global__ __launch_bounds__(VBLOCK) void k_multidot(const VecSeg* __restrict__ 
     __shared__ double s_out[NV + 1];
     const VecSeg& sg = segs[find_vseg(segs, nseg, blockIdx.x)];
     const int lb = blockIdx.x - sg.blk0;
-    const int64_t n = sg.n;
     const int64_t stride = (int64_t)sg.nblk * VBLOCK;
-    const auto* __restrict__ V = gl((const double*)sg.V);
-    const auto* __restrict__ w = gl((const double*)sg.w);
-    constexpr int UN = sweep_unroll<NV>();
-    int64_t t = (int64_t)lb * VBLOCK + threadIdx.x;
-    double a[UN][NV], wv[UN];
-    load_group<NV, UN>(V, w, n, t, stride, a, wv);
     const GState* st = sg.st;
-    if (st->done || st->k != NV - 1) return;
     double acc[NV + 1];
-    auto accumulate = [&](bool first) {
-#pragma unroll
-        for (int i = 0; i < NV; ++i) {
-            double s = a[0][i] * wv[0];
-#pragma unroll
-            for (int q = 1; q < UN; ++q) s += a[q][i] * wv[q];
-            acc[i] = first ? s : acc[i] + s;
-        }
-        double s = wv[0] * wv[0];
-#pragma unroll
-        for (int q = 1; q < UN; ++q) s += wv[q] * wv[q];
-        acc[NV] = first ? s : acc[NV] + s;
-    };
-    accumulate(true);
-    for (t += UN * stride; t < n; t += UN * stride) {
+    // the loads of every thread's first elements are issued before the
+    // cycle state is read
+    auto sweep = [&](auto e_tag, auto un_tag) -> bool {
+        using E = decltype(e_tag);
+        constexpr int UN = decltype(un_tag)::value;
+        constexpr int W = sizeof(E) / sizeof(double);
+        const int64_t n = sg.n / W;
+        const auto* __restrict__ V = gl((const E*)sg.V);
+        const auto* __restrict__ w = gl((const E*)sg.w);
+        int64_t t = (int64_t)lb * VBLOCK + threadIdx.x;
+        E a[UN][NV], wv[UN];
         load_group<NV, UN>(V, w, n, t, stride, a, wv);
-        accumulate(false);
+        if (st->done || st->k != NV - 1) return false;
+        auto accumulate = [&](bool first) {
+#pragma unroll
+            for (int i = 0; i < NV; ++i) {
+                double s = dot_of(a[0][i], wv[0]);
+#pragma unroll
+                for (int q = 1; q < UN; ++q) s += dot_of(a[q][i], wv[q]);
+                acc[i] = first ? s : acc[i] + s;
+            }
+            double s = dot_of(wv[0], wv[0]);
+#pragma unroll
+            for (int q = 1; q < UN; ++q) s += dot_of(wv[q], wv[q]);
+            acc[NV] = first ? s : acc[NV] + s;
+        };
+        accumulate(true);
+        for (t += UN * stride; t < n; t += UN * stride) {
+            load_group<NV, UN>(V, w, n, t, stride, a, wv);
+            accumulate(false);
+        }
+        return true;
+    };
+    constexpr int UP = sweep_unroll_pairs<NV>();
+    bool run;
+    if constexpr (UP > 0) {
+        run = use_pairs(sg.n, sg.V, sg.w) ? sweep(v2d{}, std::integral_constant<int, UP>{})
+                                          : sweep(double{}, std::integral_constant<int, sweep_unroll<NV>()>{});
+    } else {
+        run = sweep(double{}, std::integral_constant<int, sweep_unroll<NV>()>{});
     }
+    if (!run) return;
     block_sums<NV + 1>(acc, smem, s_out);
     if (threadIdx.x <= NV) gl(sg.part)[(int64_t)lb * NPART + threadIdx.x] = s_out[threadIdx.x];
 }
@@ -248,24 +332,18 @@ __global__ __launch_bounds__(VBLOCK) void k_multidot(const VecSeg* __restrict__ 
 // by another block of this kernel; a block that sees done = 1 set here skips
 // a sweep whose result is not needed.  Every thread's first elements are
 // loaded while the table is reduced.
-template <int NV>
-__global__ __launch_bounds__(VBLOCK) void k_update(const VecSeg* __restrict__ segs, int nseg, int pass,
-                                                   int last) {
-    __shared__ double s_tmp[VBLOCK];
-    __shared__ double s_h[NV + 1];
-    __shared__ double s_col[NV + 1];
-    const VecSeg& sg = segs[find_vseg(segs, nseg, blockIdx.x)];
-    GState* st = sg.st;
+template <int NV, class E, int UN>
+DI void update_body(const VecSeg& sg, GState* st, int lb, int64_t stride, int pass, int last, double* s_tmp,
+                    double* s_h, double* s_col) {
     constexpr int k = NV - 1;
-    const int lb = blockIdx.x - sg.blk0;
-    const int64_t n = sg.n;
-    const int64_t stride = (int64_t)sg.nblk * VBLOCK;
-    const auto* __restrict__ V = gl((const double*)sg.V);
-    auto* __restrict__ w = gl(sg.w);
-    constexpr int UN = sweep_unroll<NV>();
+    constexpr int W = sizeof(E) / sizeof(double);
+    const int64_t n = sg.n;                // elements
+    const int64_t ne = n / W;              // units of E
+    const auto* __restrict__ V = gl((const E*)sg.V);
+    auto* __restrict__ w = gl((E*)sg.w);
     int64_t t = (int64_t)lb * VBLOCK + threadIdx.x;
-    double a[UN][NV], wv[UN];
-    load_group<NV, UN>(V, w, n, t, stride, a, wv);
+    E a[UN][NV], wv[UN];
+    load_group<NV, UN>(V, w, ne, t, stride, a, wv);
     if (st->done) return;
     reduce_table<NV + 1>(gl((const double*)sg.part), NPART, sg.nblk, s_tmp, s_h);
     double h[NV];
@@ -274,7 +352,7 @@ __global__ __launch_bounds__(VBLOCK) void k_update(const VecSeg* __restrict__ se
     const double ww = s_h[NV];
 
     double scale = 1.0;                 // 1 / h_{k+1,k} on the last pass
-    auto* __restrict__ dst = w;         // where the corrected vector goes
+    auto* __restrict__ dst = w;         // where the corrected vector goes (units of E)
     if (!last) {
         if (lb == 0 && threadIdx.x <= NV) {
             const int i = threadIdx.x;
@@ -336,21 +414,42 @@ __global__ __launch_bounds__(VBLOCK) void k_update(const VecSeg* __restrict__ se
         }
         if (stop) return;
         scale = 1.0 / hn;
-        dst = gl(sg.V + (int64_t)(k + 1) * n);
+        dst = gl((E*)(sg.V + (int64_t)(k + 1) * n));
     }
     auto correct = [&]() {
 #pragma unroll
         for (int q = 0; q < UN; ++q) {
 #pragma unroll
-            for (int i = 0; i < NV; ++i) wv[q] -= h[i] * a[q][i];
-            if (t + q * stride < n) dst[t + q * stride] = scale * wv[q];
+            for (int i = 0; i < NV; ++i) sub_scaled(wv[q], h[i], a[q][i]);
+            if (t + q * stride < ne) dst[t + q * stride] = scaled(scale, wv[q]);
         }
     };
     correct();
-    for (t += UN * stride; t < n; t += UN * stride) {
-        load_group<NV, UN>(V, w, n, t, stride, a, wv);
+    for (t += UN * stride; t < ne; t += UN * stride) {
+        load_group<NV, UN>(V, w, ne, t, stride, a, wv);
         correct();
     }
+}
+
+template <int NV>
+__global__ __launch_bounds__(VBLOCK) void k_update(const VecSeg* __restrict__ segs, int nseg, int pass,
+                                                   int last) {
+    __shared__ double s_tmp[VBLOCK];
+    __shared__ double s_h[NV + 1];
+    __shared__ double s_col[NV + 1];
+    const VecSeg& sg = segs[find_vseg(segs, nseg, blockIdx.x)];
+    GState* st = sg.st;
+    const int lb = blockIdx.x - sg.blk0;
+    const int64_t n = sg.n;
+    const int64_t stride = (int64_t)sg.nblk * VBLOCK;
+    constexpr int UP = sweep_unroll_pairs<NV>();
+    if constexpr (UP > 0) {
+        if (use_pairs(n, sg.V, sg.w)) {
+            update_body<NV, v2d, UP>(sg, st, lb, stride, pass, last, s_tmp, s_h, s_col);
+            return;
+        }
+    }
+    update_body<NV, double, sweep_unroll<NV>()>(sg, st, lb, stride, pass, last, s_tmp, s_h, s_col);
 }
 
 // y = H(0:kf, 0:kf)^-1 gr(0:kf) by back substitution; one block per segment
@@ -444,14 +543,8 @@ __global__ __launch_bounds__(VBLOCK) void k_cast32(const VecSeg* __restrict__ se
     const VecSeg& sg = segs[find_vseg(segs, nseg, blockIdx.x)];
     const int lb = blockIdx.x - sg.blk0;
     const int64_t stride = (int64_t)sg.nblk * VBLOCK;
-    for (int64_t i = (int64_t)lb * VBLOCK + threadIdx.x; i < sg.n; i += 4 * stride) {
-        double u[4];
-#pragma unroll
-        for (int q = 0; q < 4; ++q) u[q] = i + q * stride < sg.n ? sg.U[i + q * stride] : 0.0;
-#pragma unroll
-        for (int q = 0; q < 4; ++q)
-            if (i + q * stride < sg.n) sg.U32[i + q * stride] = (float)u[q];
-    }
+    map_sweep((const double*)sg.U, sg.U32, sg.n, (int64_t)lb * VBLOCK + threadIdx.x, stride,
+              [](double u) { return (float)u; });
 }
 
 // Descriptor uploads in stream order: the descriptor is the kernel's first
