@@ -41,11 +41,22 @@ constexpr int PC_EB = 16;                   // elements per block (the MFMA colu
 constexpr int PC_TW = 8;                    // row tiles per wavefront and row group
 constexpr int PC_KC = 4;                    // column steps per operand chunk
 typedef double v4d __attribute__((ext_vector_type(4)));
+// a flag or index in device memory, zero for a null pointer (branch free: the
+// pointer is selected, then always loaded); every lane reads the same word
+__device__ const int pc_zero = 0;
+DI int pc_index(const int* p) {
+    return __builtin_amdgcn_readfirstlane(*(const __attribute__((address_space(1))) int*)(p ? p : &pc_zero));
+}
 }  // namespace
 
+// the small-block kernel (k_bjacobi_ks) runs one 16-row tile of B^-1 per block
+static bool pc_small(int npe) {
+    const int KS = (npe + 3) / 4, T = (npe + 15) / 16;
+    return T <= PC_TW && (KS + 3) / 4 <= 8;
+}
 int pc_blocks(int E, int npe) {
-    (void)npe;
-    return (E + PC_EB - 1) / PC_EB;
+    const int groups = (E + PC_EB - 1) / PC_EB;
+    return pc_small(npe) ? groups * ((npe + 15) / 16) : groups;
 }
 
 // out_e (+)= B^-1 in_e for 16 elements per block, as the dense product
@@ -167,75 +178,84 @@ __global__ __launch_bounds__(PC_BLOCK) void k_bjacobi(const PcSeg* __restrict__ 
     }
 }
 
-// Small blocks (npe <= 128, at most 8 row tiles): the 4 wavefronts split the
-// column steps instead of the row tiles, so every wavefront runs all row
-// tiles as independent accumulation chains over a quarter of the steps (short
-// dependent chains on the matrix cores), with its A operands loaded in one
-// go; the four partial products are added in a fixed order through LDS.
+// Small blocks (npe <= 128, at most 8 row tiles): one block per (16
+// elements, 16-row tile of B^-1), so that a slab of a few thousand elements
+// still gives every CU several blocks; the 4 wavefronts split the column
+// steps of the tile (short dependent chains on the matrix cores), with their
+// A operands loaded in one go, and the four partial products are added in a
+// fixed order through LDS.
 __global__ __launch_bounds__(PC_BLOCK) void k_bjacobi_ks(const PcSeg* __restrict__ segs, int nseg) {
-    extern __shared__ double sm[];           // [KS * 64] B operands, then partials [4][16][16 T + 1]
+    extern __shared__ double sm[];           // [KS * 64] B operands, then partials [4][16][17]
     const PcSeg& sg = segs[find_pseg(segs, nseg, blockIdx.x)];
-    if (sg.skip && *(const __attribute__((address_space(1))) int*)sg.skip) return;
+    // the skip flag, the Arnoldi index behind the input pointer and the
+    // block's A operands are requested together, before the flag is tested
+    const int skip = pc_index(sg.skip);
+    const int kin = pc_index(sg.in.kp);
     const int npe = sg.npe;
     const int KS = (npe + 3) >> 2, T = (npe + 15) >> 4;
     const int KW = (KS + 3) >> 2;            // column steps per wavefront (<= 8)
-    const int e0 = (blockIdx.x - sg.blk0) * PC_EB;
-    const int ne = min(PC_EB, sg.E - e0);
-    const double* inb = static_cast<const double*>(sg.in.base);
-    if (sg.in.kp) inb += (int64_t)(*(const __attribute__((address_space(1))) int*)sg.in.kp + sg.in.koff) * sg.in.ld;
-    const auto* __restrict__ in = gp(inb) + (int64_t)e0 * npe;
+    const int b = blockIdx.x - sg.blk0;
+    const int eg = b / T, rt = b - eg * T;   // element group, row tile
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const auto* __restrict__ A = gp(sg.binvT);
-    double a[8][PC_TW];
-#pragma unroll
-    for (int c = 0; c < 8; ++c)
-#pragma unroll
-        for (int q = 0; q < PC_TW; ++q) {
-            const int ks = wave * KW + c;
-            a[c][q] = (q < T && c < KW && ks < KS) ? A[((int64_t)q * KS + ks) * 64 + lane] : 0.0;
-        }
-    for (int t = threadIdx.x; t < KS * 64; t += PC_BLOCK) sm[t] = 0.0;
-    __syncthreads();
-    // element-fastest thread order: consecutive lanes write consecutive LDS
-    // words (B-operand order), reads stay within the block's 16 elements
-    for (int t = threadIdx.x; t < PC_EB * npe; t += PC_BLOCK) {
-        const int j = t & (PC_EB - 1), c = t >> 4;
-        if (j < ne) sm[(c >> 2) * 64 + j + 16 * (c & 3)] = in[(int64_t)j * npe + c];
-    }
-    __syncthreads();
-    v4d acc[PC_TW];
-#pragma unroll
-    for (int q = 0; q < PC_TW; ++q) acc[q] = v4d{0.0, 0.0, 0.0, 0.0};
-    double b[8];
+    double a[8];
 #pragma unroll
     for (int c = 0; c < 8; ++c) {
         const int ks = wave * KW + c;
-        b[c] = (c < KW && ks < KS) ? sm[ks * 64 + lane] : 0.0;
+        a[c] = (c < KW && ks < KS) ? A[((int64_t)rt * KS + ks) * 64 + lane] : 0.0;
+    }
+    if (skip) return;
+    const int e0 = eg * PC_EB;
+    const int ne = min(PC_EB, sg.E - e0);
+    const double* inb = static_cast<const double*>(sg.in.base);
+    if (sg.in.kp) inb += (int64_t)(kin + sg.in.koff) * sg.in.ld;
+    const auto* __restrict__ in = gp(inb) + (int64_t)e0 * npe;
+    // the block's inputs, every load issued before the first is used
+    // (element-fastest thread order: consecutive lanes write consecutive LDS
+    // words, B-operand order); columns past npe and elements past the end
+    // stage zeros, so no LDS clearing pass is needed
+    constexpr int NIN = PC_EB * 128 / PC_BLOCK;
+    double v[NIN];
+#pragma unroll
+    for (int q = 0; q < NIN; ++q) {
+        const int t = threadIdx.x + q * PC_BLOCK;
+        const int j = t & (PC_EB - 1), c = t >> 4;
+        v[q] = (j < ne && c < npe) ? in[(int64_t)j * npe + c] : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < NIN; ++q) {
+        const int t = threadIdx.x + q * PC_BLOCK;
+        const int j = t & (PC_EB - 1), c = t >> 4;
+        if (c < 4 * KS) sm[(c >> 2) * 64 + j + 16 * (c & 3)] = v[q];
+    }
+    __syncthreads();
+    v4d acc = v4d{0.0, 0.0, 0.0, 0.0};
+    double bo[8];
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+        const int ks = wave * KW + c;
+        bo[c] = (c < KW && ks < KS) ? sm[ks * 64 + lane] : 0.0;
     }
 #pragma unroll
     for (int c = 0; c < 8; ++c)
-#pragma unroll
-        for (int q = 0; q < PC_TW; ++q)
-            if (q < T && c < KW) acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[c][q], b[c], acc[q], 0, 0, 0);
+        if (c < KW) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[c], bo[c], acc, 0, 0, 0);
     __syncthreads();                         // B operands consumed: reuse sm for the partials
-    const int NR = 16 * T + 1;               // odd row stride: no LDS bank conflicts across j
+    constexpr int NR = 17;                   // odd row stride: no LDS bank conflicts across j
 #pragma unroll
-    for (int q = 0; q < PC_TW; ++q)
-        if (q < T) {
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int row = q * 16 + (lane >> 4) + 4 * r, j = lane & 15;
-                sm[(wave * 16 + j) * NR + row] = acc[q][r];
-            }
-        }
+    for (int r = 0; r < 4; ++r) {
+        const int row = (lane >> 4) + 4 * r, j = lane & 15;
+        sm[(wave * 16 + j) * NR + row] = acc[r];
+    }
     __syncthreads();
+    // the tile's rows of the block's elements: 16 x 16 values
     auto* __restrict__ out = gp(sg.out) + (int64_t)e0 * npe;
-    for (int t = threadIdx.x; t < ne * npe; t += PC_BLOCK) {
-        const int j = t / npe, row = t - j * npe;
-        double z = sm[j * NR + row];
-        z += sm[(16 + j) * NR + row];
-        z += sm[(32 + j) * NR + row];
-        z += sm[(48 + j) * NR + row];
+    const int j = threadIdx.x >> 4, r = threadIdx.x & 15, row = rt * 16 + r;
+    if (j < ne && row < npe) {
+        double z = sm[j * NR + r];
+        z += sm[(16 + j) * NR + r];
+        z += sm[(32 + j) * NR + r];
+        z += sm[(48 + j) * NR + r];
+        const int64_t t = (int64_t)j * npe + row;
         if (sg.accumulate) z += out[t];
         out[t] = z;
     }
@@ -291,8 +311,8 @@ hipError_t pc_prepare(int npe) {
 
 void pc_apply(const PcSeg* s, int nseg, int G, int npe, hipStream_t st) {
     const int KS = (npe + 3) / 4, T = (npe + 15) / 16;
-    if (T <= PC_TW && (KS + 3) / 4 <= 8) {
-        const size_t shm = sizeof(double) * std::max<size_t>(64 * (size_t)KS, 4 * 16 * (16 * (size_t)T + 1));
+    if (pc_small(npe)) {
+        const size_t shm = sizeof(double) * std::max<size_t>(64 * (size_t)KS, 4 * 16 * 17);
         launch_ks(k_bjacobi_ks, dim3(G), dim3(PC_BLOCK), shm, st, s, nseg);
     } else {
         if (T > 4 * PC_TW)
