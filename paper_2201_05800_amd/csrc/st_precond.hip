@@ -74,13 +74,16 @@ template <bool GROUPED>
 __global__ __launch_bounds__(PC_BLOCK) void k_bjacobi(const PcSeg* __restrict__ segs, int nseg) {
     extern __shared__ double sm[];           // [KS * 64] B operands, then [16][npe | 1] results
     const PcSeg& sg = segs[find_pseg(segs, nseg, blockIdx.x)];
-    if (sg.skip && *(const __attribute__((address_space(1))) int*)sg.skip) return;
+    // the skip flag and the Arnoldi index behind the input pointer in one round
+    const int skip = pc_index(sg.skip);
+    const int kin = pc_index(sg.in.kp);
+    if (skip) return;
     const int npe = sg.npe;
     const int KS = (npe + 3) >> 2, T = (npe + 15) >> 4;
     const int e0 = (blockIdx.x - sg.blk0) * PC_EB;
     const int ne = min(PC_EB, sg.E - e0);
     const double* inb = static_cast<const double*>(sg.in.base);
-    if (sg.in.kp) inb += (int64_t)(*(const __attribute__((address_space(1))) int*)sg.in.kp + sg.in.koff) * sg.in.ld;
+    if (sg.in.kp) inb += (int64_t)(kin + sg.in.koff) * sg.in.ld;
     const auto* __restrict__ in = gp(inb) + (int64_t)e0 * npe;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const auto* __restrict__ A = gp(sg.binvT);
@@ -114,10 +117,23 @@ __global__ __launch_bounds__(PC_BLOCK) void k_bjacobi(const PcSeg* __restrict__ 
     for (int t = threadIdx.x; t < KS * 64; t += PC_BLOCK) sm[t] = 0.0;
     __syncthreads();
     // element-fastest thread order: consecutive lanes write consecutive LDS
-    // words (B-operand order), reads stay within the block's 16 elements
-    for (int t = threadIdx.x; t < PC_EB * npe; t += PC_BLOCK) {
-        const int j = t & (PC_EB - 1), c = t >> 4;
-        if (j < ne) sm[(c >> 2) * 64 + j + 16 * (c & 3)] = in[(int64_t)j * npe + c];
+    // words (B-operand order), reads stay within the block's 16 elements;
+    // eight loads per thread in flight before they are staged
+    constexpr int SQ = 8;
+    for (int t0 = threadIdx.x; t0 < PC_EB * npe; t0 += SQ * PC_BLOCK) {
+        double v[SQ];
+#pragma unroll
+        for (int q = 0; q < SQ; ++q) {
+            const int t = t0 + q * PC_BLOCK;
+            const int j = t & (PC_EB - 1), c = t >> 4;
+            v[q] = (t < PC_EB * npe && j < ne) ? in[(int64_t)j * npe + c] : 0.0;
+        }
+#pragma unroll
+        for (int q = 0; q < SQ; ++q) {
+            const int t = t0 + q * PC_BLOCK;
+            const int j = t & (PC_EB - 1), c = t >> 4;
+            if (t < PC_EB * npe) sm[(c >> 2) * 64 + j + 16 * (c & 3)] = v[q];
+        }
     }
     __syncthreads();
     auto* __restrict__ out = gp(sg.out) + (int64_t)e0 * npe;
