@@ -167,10 +167,11 @@ constexpr int sweep_unroll() { return NV <= 13 ? 4 : (NV <= 18 ? 3 : (NV <= 27 ?
 // and the vectors allow 16-byte accesses, a pair of elements (v2d) per
 // access: a wave then moves 1 KB per load instruction, which the at most
 // VMAXBLK blocks of a slab need to keep HBM busy.  Pairs per thread and loop
-// step: half the elements, rounded up; none (element accesses) where a thread
-// takes one element per step, since a pair would double its registers.
+// step: two pairs up to 16 basis vectors, one pair up to 27 (about the
+// registers of the element sweeps), none (element accesses) beyond, where a
+// thread takes one element per step and a pair would double its registers.
 template <int NV>
-constexpr int sweep_unroll_pairs() { return sweep_unroll<NV>() >= 2 ? (sweep_unroll<NV>() + 1) / 2 : 0; }
+constexpr int sweep_unroll_pairs() { return NV <= 16 ? 2 : (NV <= 27 ? 1 : 0); }
 DI double zero_of(double) { return 0.0; }
 DI v2d zero_of(v2d) { return v2d{0.0, 0.0}; }
 DI double dot_of(double a, double b) { return a * b; }
@@ -334,18 +335,36 @@ __global__ __launch_bounds__(VBLOCK) void k_multidot(const VecSeg* __restrict__ 
 // loaded while the table is reduced.
 template <int NV, class E, int UN>
 DI void update_body(const VecSeg& sg, GState* st, int lb, int64_t stride, int pass, int last, double* s_tmp,
-                    double* s_h, double* s_col) {
+                    double* s_h, double* s_col, double* s_cs, double* s_sn, double* s_hacc, double* s_misc) {
     constexpr int k = NV - 1;
     constexpr int W = sizeof(E) / sizeof(double);
     const int64_t n = sg.n;                // elements
     const int64_t ne = n / W;              // units of E
     const auto* __restrict__ V = gl((const E*)sg.V);
     auto* __restrict__ w = gl((E*)sg.w);
-    int64_t t = (int64_t)lb * VBLOCK + threadIdx.x;
+    const int ti = threadIdx.x;
+    // The cycle state this kernel reads is requested before the vectors:
+    // loads complete in order, so waiting for the state then does not wait
+    // for the vectors, and the table loads below go out while the vectors
+    // are still in flight.
+    const auto* sr = gl((const GState*)st);
+    const int done = sr->done;
+    // g_k, the absolute tolerance and ||w||^2 of pass 0, one per thread
+    const double misc_i = !last ? 0.0 : (ti == 0 ? sr->g[k] : (ti == 1 ? sr->eta_abs : (ti == 2 && pass > 0 ? sr->wn0 : 0.0)));
+    const double cs_i = (last && ti < k) ? sr->cs[ti] : 0.0;
+    const double sn_i = (last && ti < k) ? sr->sn[ti] : 0.0;
+    const double hacc_i = (pass > 0 && ti < NV) ? sr->hacc[ti] : 0.0;
+    int64_t t = (int64_t)lb * VBLOCK + ti;
     E a[UN][NV], wv[UN];
     load_group<NV, UN>(V, w, ne, t, stride, a, wv);
-    if (st->done) return;
-    reduce_table<NV + 1>(gl((const double*)sg.part), NPART, sg.nblk, s_tmp, s_h);
+    if (done) return;
+    if (ti < NV) {
+        s_cs[ti] = cs_i;
+        s_sn[ti] = sn_i;
+        s_hacc[ti] = hacc_i;
+    }
+    if (ti < 3) s_misc[ti] = misc_i;
+    reduce_table<NV + 1>(gl((const double*)sg.part), NPART, sg.nblk, s_tmp, s_h);   // (block barriers)
     double h[NV];
 #pragma unroll
     for (int i = 0; i < NV; ++i) h[i] = s_h[i];
@@ -354,9 +373,8 @@ DI void update_body(const VecSeg& sg, GState* st, int lb, int64_t stride, int pa
     double scale = 1.0;                 // 1 / h_{k+1,k} on the last pass
     auto* __restrict__ dst = w;         // where the corrected vector goes (units of E)
     if (!last) {
-        if (lb == 0 && threadIdx.x <= NV) {
-            const int i = threadIdx.x;
-            if (i < NV) st->hacc[i] = (pass == 0 ? 0.0 : st->hacc[i]) + s_h[i];
+        if (lb == 0 && ti <= NV) {
+            if (ti < NV) st->hacc[ti] = s_hacc[ti] + s_h[ti];
             else if (pass == 0) st->wn0 = ww;
         }
     } else {
@@ -364,17 +382,17 @@ DI void update_body(const VecSeg& sg, GState* st, int lb, int64_t stride, int pa
         double hn2 = ww;
 #pragma unroll
         for (int i = 0; i < NV; ++i) hn2 -= h[i] * h[i];
-        const double wn0 = pass == 0 ? ww : st->wn0;
+        const double wn0 = pass == 0 ? ww : s_misc[2];
         const bool cancel = !(hn2 > 1e-12 * ww);       // Pythagoras lost to round-off
         const double hn = cancel ? 0.0 : sqrt(hn2);
-        if (threadIdx.x == 0) {
+        if (ti == 0) {
             double col[NV + 1];
-            for (int i = 0; i < NV; ++i) col[i] = (pass == 0 ? 0.0 : st->hacc[i]) + h[i];
+            for (int i = 0; i < NV; ++i) col[i] = s_hacc[i] + h[i];
             col[NV] = hn;
             for (int i = 0; i < k; ++i) {
                 const double a = col[i], b = col[i + 1];
-                col[i] = st->cs[i] * a + st->sn[i] * b;
-                col[i + 1] = -st->sn[i] * a + st->cs[i] * b;
+                col[i] = s_cs[i] * a + s_sn[i] * b;
+                col[i + 1] = -s_sn[i] * a + s_cs[i] * b;
             }
             for (int i = 0; i <= NV; ++i) s_col[i] = col[i];
         }
@@ -383,13 +401,13 @@ DI void update_body(const VecSeg& sg, GState* st, int lb, int64_t stride, int pa
         const double den = sqrt(a * a + hn * hn);
         const double c = den > 0.0 ? a / den : 1.0;
         const double sn = den > 0.0 ? hn / den : 0.0;
-        const double gk = st->g[k];
+        const double gk = s_misc[0];
         const double gk1 = -sn * gk;
         const double res = fabs(gk1);
         const bool nonfin = !isfinite(ww) || !isfinite(res) || !isfinite(den);
         const bool breakdown = cancel || hn <= 1e-14 * sqrt(wn0);
-        const bool stop = nonfin || res <= st->eta_abs || breakdown || k + 1 >= sg.m;
-        if (lb == 0 && threadIdx.x == 0) {
+        const bool stop = nonfin || res <= s_misc[1] || breakdown || k + 1 >= sg.m;
+        if (lb == 0 && ti == 0) {
             double* H = st->H;
             for (int i = 0; i < k; ++i) H[i * MMAX + k] = s_col[i];
             H[k * MMAX + k] = den;
@@ -437,6 +455,8 @@ __global__ __launch_bounds__(VBLOCK) void k_update(const VecSeg* __restrict__ se
     __shared__ double s_tmp[VBLOCK];
     __shared__ double s_h[NV + 1];
     __shared__ double s_col[NV + 1];
+    __shared__ double s_cs[NV], s_sn[NV], s_hacc[NV];     // Givens rotations and the Arnoldi column so far
+    __shared__ double s_misc[3];                          // g_k, eta_abs, ||w||^2 of pass 0
     const VecSeg& sg = segs[find_vseg(segs, nseg, blockIdx.x)];
     GState* st = sg.st;
     const int lb = blockIdx.x - sg.blk0;
@@ -445,11 +465,13 @@ __global__ __launch_bounds__(VBLOCK) void k_update(const VecSeg* __restrict__ se
     constexpr int UP = sweep_unroll_pairs<NV>();
     if constexpr (UP > 0) {
         if (use_pairs(n, sg.V, sg.w)) {
-            update_body<NV, v2d, UP>(sg, st, lb, stride, pass, last, s_tmp, s_h, s_col);
+            update_body<NV, v2d, UP>(sg, st, lb, stride, pass, last, s_tmp, s_h, s_col, s_cs, s_sn, s_hacc,
+                                     s_misc);
             return;
         }
     }
-    update_body<NV, double, sweep_unroll<NV>()>(sg, st, lb, stride, pass, last, s_tmp, s_h, s_col);
+    update_body<NV, double, sweep_unroll<NV>()>(sg, st, lb, stride, pass, last, s_tmp, s_h, s_col, s_cs, s_sn,
+                                                s_hacc, s_misc);
 }
 
 // y = H(0:kf, 0:kf)^-1 gr(0:kf) by back substitution; one block per segment
