@@ -183,6 +183,10 @@ SOLVES = [
     ("euler2d-vortex", cfg("euler", 2, [12, 12], 3, 3, lo=[-5, -5], hi=[5, 5]), None, "vortex"),
     ("burgers", cfg("burgers", 1, [48], 3, 3), None, "burgers"),
     ("ns3d-tgv", cfg("ns", 3, [3, 3, 3], 3, 3, lo=[0, 0, 0], hi=[6.283185307179586] * 3, mu=1.0 / 1600), 0.05, "tgv"),
+    # an odd number of unknowns (7 x 3 x 3 = 63, 9 x 3 x 3 = 81): the vector kernels take their
+    # element-wise paths instead of the paired ones
+    ("burgers-odd-n", cfg("burgers", 1, [7], 2, 3), None, "burgers"),
+    ("adv1d-odd-n", cfg("adv", 1, [9], 2, 3, a=(1.0,)), 1.0 / 32, "burgers"),
 ]
 
 

@@ -61,7 +61,8 @@ def test_alone_vs_mix_bitwise(orc):
     from paper_2201_05800_amd import st
     cases = [("burgers", burgers_case(40, 3, 3, 1), 0), ("advdiff", advdiff_case(10, 3, 2), 0),
              ("burgers", burgers_case(23, 5, 4, 2), 1), ("advdiff", advdiff_case(8, 4, 4), 1),
-             ("burgers", burgers_case(64, 2, 2, 3), 0), ("advdiff", advdiff_case(12, 2, 3), 1)]
+             ("burgers", burgers_case(64, 2, 2, 3), 0), ("advdiff", advdiff_case(12, 2, 3), 1),
+             ("burgers", burgers_case(7, 2, 3, 4), 1)]     # 63 unknowns: element-wise vector paths
     pairs = [Pair(c) for _, c, _ in cases]
     try:
         reqs, ups, dts = [], [], []
