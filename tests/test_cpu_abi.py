@@ -94,3 +94,54 @@ def test_create_fails_loudly_without_gpu():
     from paper_2201_05800_amd import st
     with pytest.raises(st.StError):
         st.st_create(st.mesh(1, [4], [0], [1]), 3, 3, st.equation(st.ST_ADVECTION, a=(1.0,)))
+
+
+@pytest.mark.parametrize("case", ["ok", "dim0", "dim4", "N0", "Nt1", "K0", "hi_le_lo", "too_many_elements",
+                                  "kind0", "kind9", "burgers2d", "gamma1", "prandtl0", "N_unsupported",
+                                  "max_supported"])
+def test_problem_validation_edges(case):
+    """The problem checks st_create applies, exercised on the host through the
+    footprint query (same validation, no device): degenerate and out-of-range
+    meshes, orders and equation parameters give -1; the largest supported
+    sizes are accepted."""
+    from paper_2201_05800_amd import st
+    d, K, lo, hi, N, Nt = 2, [8, 8], [0, 0], [1, 1], 3, 3
+    eq = st.equation(st.ST_EULER, gamma=1.4)
+    if case == "dim0":
+        d = 0
+    elif case == "dim4":
+        d = 4
+    elif case == "N0":
+        N = 0
+    elif case == "Nt1":
+        Nt = 1
+    elif case == "K0":
+        K = [0, 8]
+    elif case == "hi_le_lo":
+        hi = [1, 0]
+    elif case == "too_many_elements":
+        d, K, lo, hi = 3, [2048, 1024, 1024], [0, 0, 0], [1, 1, 1]     # 2^31 elements
+    elif case == "kind0":
+        eq = st.equation(0)
+    elif case == "kind9":
+        eq = st.equation(9)
+    elif case == "burgers2d":
+        eq = st.equation(st.ST_BURGERS)
+    elif case == "gamma1":
+        eq = st.equation(st.ST_EULER, gamma=1.0)
+    elif case == "prandtl0":
+        d, K, lo, hi = 3, [4, 4, 4], [0, 0, 0], [1, 1, 1]
+        eq = st.equation(st.ST_NS_BR1, gamma=1.4, mu=1e-3, prandtl=0.0)
+    elif case == "N_unsupported":
+        N = 6                                                             # 7 nodes per axis: not compiled for Euler
+    elif case == "max_supported":
+        d, K, lo, hi, N, Nt = 3, [1024, 1024, 1024], [0, 0, 0], [1, 1, 1], 1, 2   # 2^30 elements
+        eq = st.equation(st.ST_ADVECTION, a=(1.0, 0.0, 0.0))
+    m = st.mesh(max(1, min(d, 3)), K + [1] * (3 - len(K)), lo + [0] * (3 - len(lo)), hi + [1] * (3 - len(hi)))
+    m.dim = d
+    r = st.request(m, N, Nt, eq, np.zeros(1), 0.0, 0.01, 1e-10)
+    fp = st.st_request_footprint(r)
+    if case in ("ok", "max_supported"):
+        assert fp > 0
+    else:
+        assert fp == -1, case
