@@ -225,3 +225,47 @@ def last_time_node(p, U) -> np.ndarray:
     nv = nvars(p.eq, p.dim)
     ns = (p.N + 1) ** p.dim
     return np.ascontiguousarray(np.asarray(U).reshape(-1, nv, p.Nt, ns)[:, :, -1, :]).reshape(-1)
+
+
+# ---------------------------------------------------------------------------
+# Embedded error estimate (Sec. "Algorithmic Aspects", adaptive time-stepping;
+# eqs. RK_stage_equations and RK_solution).  The paper leaves the embedded
+# weights open; the reading taken here: b_hat is the interpolatory quadrature
+# on [0, 1] through the first Nt - 1 stage nodes (b_hat_Nt = 0), exact for
+# polynomials of degree Nt - 2, so the embedded solution has order Nt - 1
+# (the stage order of Lobatto IIIC) against 2 Nt - 2 for u^{n+1}.
+# ---------------------------------------------------------------------------
+def embedded_weights(Nt: int):
+    """(A, b, b_hat, c): the Appendix B tableau and the embedded weights."""
+    A, b, c = butcher_appendix_b(Nt)
+    m = Nt - 1
+    # moment conditions sum_l b_hat_l c_l^q = 1 / (q + 1), q = 0 .. m - 1
+    M = np.array([[c[l] ** q for l in range(m)] for q in range(m)])
+    rhs = np.array([1.0 / (q + 1) for q in range(m)])
+    bh = np.zeros(Nt)
+    bh[:m] = np.linalg.solve(M, rhs)
+    return A, b, bh, c
+
+
+def error_estimate(p, U, uprev, dt, atol, rtol):
+    """Local error estimate of a solved slab.
+
+    Stage derivatives from the stage equations, dt K = (A^-1 (x) I)(U - 1 (x) u^n);
+    u^{n+1} = u^n + dt sum_l b_l K_l and u_hat = u^n + dt sum_l b_hat_l K_l
+    (eq. RK_solution with b and b_hat); e = u^{n+1} - u_hat.  The scalar is the
+    root mean square over every spatial node and variable of
+    e / (atol + rtol max(|u^n|, |u^{n+1}|)).  Returns (err, e) with e in the
+    spatial layout [E][nv][ns]."""
+    nv = nvars(p.eq, p.dim)
+    ns = (p.N + 1) ** p.dim
+    A, b, bh, _ = embedded_weights(p.Nt)
+    Us = np.asarray(U, dtype=np.float64).reshape(-1, nv, p.Nt, ns)
+    un = np.asarray(uprev, dtype=np.float64).reshape(-1, nv, ns)
+    D = Us - un[:, :, None, :]                                   # U_j - u^n
+    hK = np.einsum("lj,evjs->evls", np.linalg.inv(A), D)         # dt K_l
+    u1 = un + np.einsum("l,evls->evs", b, hK)
+    uh = un + np.einsum("l,evls->evs", bh, hK)
+    e = u1 - uh
+    sc = atol + rtol * np.maximum(np.abs(un), np.abs(u1))
+    err = float(np.sqrt(np.mean((e / sc) ** 2)))
+    return err, e.reshape(-1)

@@ -604,3 +604,65 @@ def test_jacobian_block_structure(orc, name):
     assert np.abs(Jfull - pred).max() < 1e-7 * np.abs(Jfull).max()
     # same sparsity (entries below 1e-8 are finite-difference noise in pred)
     assert np.array_equal(np.abs(Jfull) > 1e-8, np.abs(pred) > 1e-8)
+
+
+# ---------------------------------------------------------------------------
+# Embedded error estimate (Sec. "Algorithmic Aspects", adaptive time-stepping)
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("Nt", [2, 3, 4])
+def test_embedded_weights_order(orc, Nt):
+    """b_hat integrates polynomials up to degree Nt - 2 exactly on [0, 1]
+    (Nt = 2: the left rectangle rule, Nt = 3: the midpoint rule), has
+    b_hat_Nt = 0, and is not exact for degree Nt - 1 (so it differs from b)."""
+    A, b, bh, c = orc.embedded_weights(Nt)
+    for q in range(Nt - 1):
+        assert abs(sum(bh[l] * c[l] ** q for l in range(Nt)) - 1.0 / (q + 1)) < 1e-14
+    assert bh[-1] == 0.0
+    assert abs(sum(bh[l] * c[l] ** (Nt - 1) for l in range(Nt)) - 1.0 / Nt) > 1e-3
+    if Nt == 2:
+        assert np.allclose(bh, [1.0, 0.0], atol=1e-15)
+    if Nt == 3:
+        assert np.allclose(bh, [0.0, 1.0, 0.0], atol=1e-15)
+
+
+@pytest.mark.parametrize("Nt", [2, 3, 4])
+def test_error_estimate_linear_test_equation(orc, Nt):
+    """y' = -y on one element (the reaction term, no transport): the slab's
+    estimate equals the closed form h lambda (b - b_hat) . Y with the stages
+    Y = (I - h lambda A)^-1 1 y0, and falls like h^Nt (local error of an
+    order Nt - 1 embedding)."""
+    lam, y0 = -1.0, 2.0
+    A, b, bh, _ = orc.embedded_weights(Nt)
+    ests = []
+    for h in (0.2, 0.1, 0.05):
+        p = orc.problem(1, [1], [0], [1], 1, Nt, orc.ADVECTION, a=(0.0,), react=lam)
+        up = np.full(2, y0)
+        U, st = orc.solve(p, up, h, tol=1e-15)
+        err, e = orc.error_estimate(p, U, up, h, atol=1.0, rtol=0.0)
+        Y = np.linalg.solve(np.eye(Nt) - h * lam * A, np.ones(Nt)) * y0
+        closed = h * lam * float(np.dot(b - bh, Y))
+        assert np.allclose(e, closed, rtol=1e-11, atol=1e-15), (Nt, h, e, closed)
+        ests.append(abs(closed))
+    for e1, e2 in zip(ests, ests[1:]):
+        assert abs(math.log2(e1 / e2) - Nt) < 0.15, (Nt, ests)
+
+
+def test_error_estimate_matches_stage_fluxes(orc):
+    """On a solved PDE slab the estimate, formed from the stage values through
+    A^-1, equals u^{Nt} - (u^n + dt sum_l b_hat_l F(U_l)) with F the oracle's
+    spatial operator evaluated at every stage."""
+    p = orc.problem(1, [8], [0], [1], 3, 3, orc.ADVDIFF_BR1, a=(1.0,), nu=0.01)
+    X = orc.node_coords(p)
+    up = np.sin(2 * np.pi * X[:, 0, :]).ravel()
+    dt = 0.02
+    U, st = orc.solve(p, up, dt, tol=1e-15)
+    _, e = orc.error_estimate(p, U, up, dt, atol=1.0, rtol=0.0)
+    _, _, bh, _ = orc.embedded_weights(3)
+    Us = U.reshape(8, 1, 3, 4)
+    uh = up.reshape(8, 1, 4).copy()
+    for l in range(3):
+        F = orc.spatial_op(p, np.ascontiguousarray(Us[:, :, l, :]).ravel()).reshape(8, 1, 4)
+        uh += dt * bh[l] * F
+    direct = (Us[:, :, -1, :] - uh).ravel()
+    assert np.abs(e - direct).max() <= 1e-11 * np.abs(up).max()
+    assert np.abs(e).max() > 1e-8            # a real estimate, not round-off
