@@ -246,8 +246,9 @@ OPERATOR_WORKLOADS = {
 def operator_bench(reps, fp32_too=True):
     """st_residual and st_jvp on >= 1 GB working sets, timed with HIP events
     on the calling stream (the whole API call: for Navier-Stokes it includes
-    the BR1 gradient passes).  Rates use the algorithmic bytes: residual
-    (2 + 1/Nt) n 8, JVP 24 n (linear equations 16 n, FP32-inner 20 n)."""
+    the BR1 gradient passes), and the embedded error estimate of a slab.
+    Rates use the algorithmic bytes: residual (2 + 1/Nt) n 8, JVP 24 n
+    (linear equations 16 n, FP32-inner 20 n), estimate 3 n_space 8."""
     import numpy as np
     import torch
     from paper_2201_05800_amd import inputs, st
@@ -281,6 +282,9 @@ def operator_bench(reps, fp32_too=True):
             if fp32_too:
                 calls.append(("st_jvp fp32-inner", lambda: st.st_jvp(h, U, 0.0, dt, v, R, 1, stream),
                               16.0 if lin else 20.0))
+            # embedded error estimate: reads U_1, U_Nt and u_prev (3 spatial vectors)
+            calls.append(("st_error_estimate", lambda: st.st_error_estimate(h, U, up, 1e-6, 1e-6, stream),
+                          24.0 / cfg["Nt"]))
             for op, fn, bpu in calls:
                 fn()
                 fn()

@@ -190,6 +190,30 @@ int st_solve_slab(st_handle_t h, const double* u_prev, double t0, double dt, dou
                   const st_solver_opts_t* opts, double* U_out, double* u_next, st_stats_t* stats,
                   void* stream);
 
+/* Local error estimate of a solved slab by an embedded solution (Sec.
+ * "Algorithmic Aspects", adaptive time-stepping; eqs. (RK_stage_equations),
+ * (RK_solution), with the tableau of eq. (SBP_to_RK)).  The stage derivatives
+ * follow from the stage values, dt K = (A^-1 (x) I)(U - 1 (x) u_prev); the
+ * embedded solution uses weights b_hat, the interpolatory quadrature on [0, 1]
+ * through the first Nt - 1 stage nodes (order Nt - 1; the paper names the
+ * technique and leaves b_hat open), so e = u^{n+1} - u_hat^{n+1} =
+ * dt sum_l (b_l - b_hat_l) K_l.  For this b_hat, b - b_hat is (up to sign) the
+ * first row of A, and the first stage equation makes e = +-(U_1 - u_prev): the
+ * jump of the slab solution at its inflow time, which is what the kernel
+ * forms.  *err (host) = sqrt(mean over the n_space
+ * values of (e / (atol + rtol max(|u_prev|, |u^{n+1}|)))^2).  U: device, slab
+ * layout; u_prev: device, spatial layout.  atol, rtol >= 0, atol + rtol > 0,
+ * else ST_ERR_BAD_ARG.  Synchronises `stream` (the value is copied to the
+ * host); the first call allocates about 4 KB of device memory. */
+int st_error_estimate(st_handle_t h, const double* U, const double* u_prev, double atol, double rtol,
+                      double* err, void* stream);
+
+/* Host only: the next step size of an embedded pair whose local error scales
+ * like dt^Nt: dt_next = dt min(5, max(0.2, 0.9 err^(-1/Nt))) (5 when err = 0);
+ * a step is accepted when err <= 1.  Nt in 2..4, dt > 0, err >= 0, else
+ * ST_ERR_BAD_ARG.  No GPU needed. */
+int st_next_dt(int Nt, double dt, double err, double* dt_next);
+
 /* ---------------------------------------------------------------------------
  * Serving: continuous batching of independent slab solves.
  * A server owns one HIP stream and a scheduler thread.  Requests are admitted

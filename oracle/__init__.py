@@ -264,8 +264,10 @@ def error_estimate(p, U, uprev, dt, atol, rtol):
     D = Us - un[:, :, None, :]                                   # U_j - u^n
     hK = np.einsum("lj,evjs->evls", np.linalg.inv(A), D)         # dt K_l
     u1 = un + np.einsum("l,evls->evs", b, hK)
-    uh = un + np.einsum("l,evls->evs", bh, hK)
-    e = u1 - uh
+    # e = u^{n+1} - u_hat = dt sum_l (b_l - b_hat_l) K_l, formed from the
+    # difference of the weights (the difference of the two solutions would
+    # lose the digits e has below |u|)
+    e = np.einsum("l,evls->evs", b - bh, hK)
     sc = atol + rtol * np.maximum(np.abs(un), np.abs(u1))
     err = float(np.sqrt(np.mean((e / sc) ** 2)))
     return err, e.reshape(-1)

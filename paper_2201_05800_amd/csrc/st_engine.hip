@@ -313,6 +313,8 @@ struct st_ctx {
     double pc_dt = 0.0;
     double* pz = nullptr;
     PcSeg* d_pc = nullptr;
+    // embedded error estimate: partial sums + result
+    double* d_est = nullptr;
 
     // optional HIP-event timing of kernel classes (st_solver_opts_t.timing)
     struct Timer {
@@ -775,6 +777,45 @@ int st_jvp(st_handle_t h, const double* U, double t0, double dt, const double* v
     setup_jvp(h, U, dptr(v), Jv, nullptr, fp32, dt, 3, st);
     launch_jvp(h, fp32, 3, st);
     HIPCHK(hipGetLastError());
+    return ST_OK;
+}
+
+int st_error_estimate(st_handle_t h, const double* U, const double* u_prev, double atol, double rtol, double* err,
+                      void* stream) {
+    if (!h || !U || !u_prev || !err) return set_error(ST_ERR_BAD_ARG, "st_error_estimate: null argument");
+    if (!(atol >= 0.0) || !(rtol >= 0.0) || !(atol + rtol > 0.0))
+        return set_error(ST_ERR_BAD_ARG, "st_error_estimate: need atol, rtol >= 0 and atol + rtol > 0");
+    const Problem& pb = h->pb;
+    hipStream_t st = (hipStream_t)stream;
+    if (!h->d_est) CHK(h->alloc(&h->d_est, (size_t)VMAXBLK + 1));
+    EstArgs a;
+    a.U = U;
+    a.up = u_prev;
+    a.part = h->d_est + 1;
+    a.out = h->d_est;
+    a.nsp = pb.nsp;
+    a.nt = pb.Nt;
+    a.ns = pb.ns;
+    a.nblk = vec_blocks(pb.nsp);
+    a.atol = atol;
+    a.rtol = rtol;
+    vk_error_estimate(a, st);
+    HIPCHK(hipMemcpyAsync(err, h->d_est, sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    return ST_OK;
+}
+
+int st_next_dt(int Nt, double dt, double err, double* dt_next) {
+    if (!dt_next || Nt < 2 || Nt > 4 || !(dt > 0.0) || !(err >= 0.0))
+        return set_error(ST_ERR_BAD_ARG, "st_next_dt: need Nt in 2..4, dt > 0, err >= 0 and an output");
+    // step-size control of an embedded pair (the estimate is of order Nt - 1,
+    // so the local error scales like dt^Nt): safety factor 0.9, growth in
+    // [0.2, 5]
+    constexpr double fac = 0.9, facmin = 0.2, facmax = 5.0;
+    double f = err > 0.0 ? fac * std::pow(1.0 / err, 1.0 / Nt) : facmax;
+    if (!std::isfinite(f)) f = facmin;
+    f = std::min(facmax, std::max(facmin, f));
+    *dt_next = dt * f;
     return ST_OK;
 }
 

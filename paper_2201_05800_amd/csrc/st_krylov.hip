@@ -569,6 +569,45 @@ __global__ __launch_bounds__(VBLOCK) void k_cast32(const VecSeg* __restrict__ se
               [](double u) { return (float)u; });
 }
 
+// Embedded error estimate (Sec. "Algorithmic Aspects", adaptive time-stepping;
+// eqs. RK_stage_equations, RK_solution).  With the embedded weights b_hat of
+// the interpolatory quadrature through the first Nt - 1 stage nodes, b - b_hat
+// is (up to sign) the first row of the Lobatto IIIC matrix A: both sum the
+// moments c^q, q <= Nt - 2, to zero (A satisfies the simplifying condition
+// C(Nt - 1) and c_1 = 0), and for Nt = 2, 3, 4 their last entries agree in
+// magnitude.  The
+// first stage equation, U_1 = u^n + dt sum_j a_1j K_j, then gives
+// u^{n+1} - u_hat^{n+1} = +-(U_1 - u^n): the estimate is the jump of the slab
+// solution at its inflow time, formed here without cancellation.  Partial
+// sums of its squared scaled values per block.
+__global__ __launch_bounds__(VBLOCK) void k_errest(EstArgs a) {
+    __shared__ double smem[VWAVES];
+    __shared__ double s_out[1];
+    const auto* __restrict__ U = gl(a.U);
+    const auto* __restrict__ up = gl(a.up);
+    double acc[1] = {0.0};
+    const int64_t stride = (int64_t)a.nblk * VBLOCK;
+    for (int64_t i = (int64_t)blockIdx.x * VBLOCK + threadIdx.x; i < a.nsp; i += stride) {
+        const int64_t ev = i / a.ns, s = i - ev * a.ns;
+        const int64_t base = ev * a.nt * a.ns + s;
+        const double u1 = U[base];                               // first time node
+        const double uN = U[base + (int64_t)(a.nt - 1) * a.ns];  // u^{n+1}
+        const double un = up[i];
+        const double sc = a.atol + a.rtol * fmax(fabs(un), fabs(uN));
+        const double r = (u1 - un) / sc;
+        acc[0] += r * r;
+    }
+    block_sums<1>(acc, smem, s_out);
+    if (threadIdx.x == 0) gl(a.part)[blockIdx.x] = s_out[0];
+}
+// the partial sums in a fixed order, then the root mean square
+__global__ __launch_bounds__(VBLOCK) void k_errest_final(EstArgs a) {
+    __shared__ double s_tmp[VBLOCK];
+    __shared__ double s_out[1];
+    reduce_table<1>(gl((const double*)a.part), 1, a.nblk, s_tmp, s_out);
+    if (threadIdx.x == 0) gl(a.out)[0] = sqrt(s_out[0] / (double)a.nsp);
+}
+
 // Descriptor uploads in stream order: the descriptor is the kernel's first
 // argument, so it sits at the start of the kernel-argument segment, and the
 // threads copy its 8-byte words in parallel (one thread copying a 3 KB
@@ -624,6 +663,10 @@ void vk_update_u(const VecSeg* s, int nseg, int G, hipStream_t st) { LAUNCH_V(k_
 void vk_init_guess(const VecSeg* s, int nseg, int G, hipStream_t st) { LAUNCH_V(k_init_guess, G, s, nseg); }
 void vk_extract_last(const VecSeg* s, int nseg, int G, hipStream_t st) { LAUNCH_V(k_extract_last, G, s, nseg); }
 void vk_cast32(const VecSeg* s, int nseg, int G, hipStream_t st) { LAUNCH_V(k_cast32, G, s, nseg); }
+void vk_error_estimate(const EstArgs& a, hipStream_t st) {
+    LAUNCH_V(k_errest, a.nblk, a);
+    LAUNCH_V(k_errest_final, 1, a);
+}
 void put_opseg(OpSeg* dst, const OpSeg& v, hipStream_t st) {
     launch_k(k_put_desc<OpSeg>, dim3(1), dim3(256), st, v, dst);
 }

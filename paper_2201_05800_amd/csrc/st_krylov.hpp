@@ -20,6 +20,19 @@ void vk_update_u(const VecSeg* s, int nseg, int G, hipStream_t st);
 void vk_init_guess(const VecSeg* s, int nseg, int G, hipStream_t st);
 void vk_extract_last(const VecSeg* s, int nseg, int G, hipStream_t st);
 void vk_cast32(const VecSeg* s, int nseg, int G, hipStream_t st);
+// embedded error estimate of a solved slab: err = rms over the nsp spatial
+// values of e / (atol + rtol max(|u^n|, |u^{n+1}|)) with e = U_1 - u^n;
+// part: nblk partial sums, out: the estimate (device)
+struct EstArgs {
+    const double* U;
+    const double* up;
+    double* part;
+    double* out;
+    int64_t nsp;          // E nv ns spatial values
+    int nt, ns, nblk;
+    double atol, rtol;
+};
+void vk_error_estimate(const EstArgs& a, hipStream_t st);
 // element-block Jacobi (st_precond.hip): elements per block, launch, and
 // w = sum_{i < kfinal} y_i V_i for the preconditioned Newton update
 constexpr int PC_NPE_MAX = 1024;    // largest element block (unknowns per element)

@@ -97,6 +97,9 @@ _SIGS = [
     ("st_solve_slab", ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double, ctypes.c_double,
                                      ctypes.c_double, ctypes.POINTER(SolverOpts), ctypes.c_void_p,
                                      ctypes.c_void_p, ctypes.POINTER(Stats), ctypes.c_void_p]),
+    ("st_error_estimate", ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double,
+                                         ctypes.c_double, _c_double_p, ctypes.c_void_p]),
+    ("st_next_dt", ctypes.c_int, [ctypes.c_int, ctypes.c_double, ctypes.c_double, _c_double_p]),
     ("st_server_create", ctypes.c_int, [ctypes.POINTER(ServerOpts), ctypes.POINTER(ctypes.c_void_p)]),
     ("st_server_destroy", ctypes.c_int, [ctypes.c_void_p]),
     ("st_submit", ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Request), ctypes.POINTER(ctypes.c_uint64)]),
@@ -232,6 +235,19 @@ def st_residual(h, U, u_prev, t0, dt, R, stream=None) -> None:
 def st_jvp(h, U, t0, dt, v, Jv, inner_fp32=0, stream=None) -> None:
     _check(lib().st_jvp(h, _dev(U, "U"), float(t0), float(dt), _dev(v, "v"), _dev(Jv, "Jv"), int(inner_fp32),
                         _stream(stream)))
+
+
+def st_error_estimate(h, U, u_prev, atol, rtol, stream=None) -> float:
+    err = ctypes.c_double(0.0)
+    _check(lib().st_error_estimate(h, _dev(U, "U"), _dev(u_prev, "u_prev"), float(atol), float(rtol),
+                                   ctypes.byref(err), _stream(stream)))
+    return err.value
+
+
+def st_next_dt(Nt, dt, err) -> float:
+    out = ctypes.c_double(0.0)
+    _check(lib().st_next_dt(int(Nt), float(dt), float(err), ctypes.byref(out)))
+    return out.value
 
 
 def st_solve_slab(h, u_prev, t0, dt, tol, opts=None, U_out=None, u_next=None, stream=None, check=True):

@@ -1,0 +1,129 @@
+"""GPU parity of the embedded error estimate (Sec. "Algorithmic Aspects",
+adaptive time-stepping) against the oracle, and a run with adaptive step
+sizes driven by it."""
+import sys
+
+import numpy as np
+import pytest
+
+from gpu_common import Pair, cfg, dev, gpu_solve
+from paper_2201_05800_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+EST_TOL = 1e-12      # relative, the same FP64 arithmetic in another order
+
+
+def round_off_bound(orc, P, U, up, atol, rtol):
+    """The oracle forms e = (b - b_hat) . (A^-1 (U - 1 u^n)) as written, the
+    kernel the equal jump U_1 - u^n; the oracle's route rounds at the scale of
+    |b - b_hat|^T |A^-1| |U - 1 u^n|, which can exceed |e| by orders of
+    magnitude for small steps: 50 eps of the scaled root mean square of that."""
+    c = P.c
+    A, b, bh, _ = orc.embedded_weights(c["Nt"])
+    g = np.abs(b - bh) @ np.abs(np.linalg.inv(A))
+    Us = np.asarray(U).reshape(-1, P.nv, c["Nt"], P.ns)
+    un = np.asarray(up).reshape(-1, P.nv, P.ns)
+    s = np.einsum("j,evjs->evs", g, np.abs(Us - un[:, :, None, :]))
+    sc = atol + rtol * np.maximum(np.abs(un), np.abs(Us[:, :, -1, :]))
+    return 50 * np.finfo(float).eps * float(np.sqrt(np.mean((s / sc) ** 2)))
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+CASES = [
+    ("adv1d-Nt3", cfg("adv", 1, [16], 3, 3, a=(1.0,)), 1.0 / 32),
+    ("adv1d-Nt2", cfg("adv", 1, [10], 4, 2, a=(1.0,)), 1.0 / 20),
+    ("advdiff2d-Nt4", cfg("advdiff", 2, [12, 10], 4, 4, a=(1.0, 0.5), nu=1e-3), 1.0 / 64),
+    ("burgers-odd-n", cfg("burgers", 1, [7], 2, 3), 0.02),
+    ("euler2d", cfg("euler", 2, [6, 6], 3, 3, lo=[-5, -5], hi=[5, 5]), 0.05),
+    ("ns3d-Nt2", cfg("ns", 3, [2, 2, 2], 2, 2, lo=[0, 0, 0], hi=[6.283185307179586] * 3, mu=1.0 / 1600), 0.05),
+]
+
+
+def _initial(P, c):
+    X = P.coords()
+    k = c["kind"]
+    if k == 4:
+        return inputs.isentropic_vortex(X, seed=3).ravel()
+    if k == 5:
+        return inputs.taylor_green(X).ravel()
+    if k == 3:
+        return inputs.burgers_smooth(X, inputs.burgers_params(4)).ravel()
+    if c["dim"] == 2:
+        return inputs.fourier_modes(X, inputs.fourier_params(2)).ravel()
+    return np.sin(2 * np.pi * X[:, 0, :]).ravel()
+
+
+@pytest.mark.parametrize("name,c,dt", CASES, ids=[x[0] for x in CASES])
+def test_error_estimate_matches_oracle(orc, name, c, dt):
+    """On solved slabs (and on a random slab, where the estimate is large) the
+    GPU estimate equals the oracle's for absolute, relative and mixed scales."""
+    P = Pair(c)
+    try:
+        up = _initial(P, c)
+        U, _, _ = gpu_solve(P, up, dt, 1e-12)
+        Ur, upr, _ = P.random(seed=5)
+        for (UU, uu) in ((U, up), (Ur, upr)):
+            for atol, rtol in ((1.0, 0.0), (0.0, 1e-3), (1e-6, 1e-6)):
+                g = P.st.st_error_estimate(P.h, dev(UU), dev(uu), atol, rtol)
+                o, _ = orc.error_estimate(P.p, UU, uu, dt, atol, rtol)
+                say(f"{name} atol={atol} rtol={rtol}: gpu {g:.6e} oracle {o:.6e}")
+                assert abs(g - o) <= EST_TOL * abs(o) + round_off_bound(orc, P, UU, uu, atol, rtol), \
+                    (name, atol, rtol, g, o)
+    finally:
+        P.close()
+
+
+def test_error_estimate_rejects_bad_scales():
+    P = Pair(cfg("adv", 1, [4], 2, 3, a=(1.0,)))
+    try:
+        U, up, _ = P.random(seed=1)
+        for atol, rtol in ((0.0, 0.0), (-1.0, 1.0), (1.0, -1e-3)):
+            with pytest.raises(P.st.StError):
+                P.st.st_error_estimate(P.h, dev(U), dev(up), atol, rtol)
+    finally:
+        P.close()
+
+
+def test_adaptive_steps(orc):
+    """1D advection of sin(2 pi x) to T = 1 with step sizes chosen from the
+    estimate: every accepted step meets the tolerance, a tighter tolerance
+    takes more steps, and the end state matches the exact solution to the
+    accuracy the spatial resolution allows.  The estimate of every accepted
+    slab is checked against the oracle's on the same stage values."""
+    c = cfg("adv", 1, [16], 5, 3, a=(1.0,))
+    P = Pair(c)
+    try:
+        X = P.coords()
+        u0 = np.sin(2 * np.pi * X[:, 0, :]).ravel()
+        counts = {}
+        for rtol in (1e-4, 1e-7):
+            atol = rtol
+            t, dt, u = 0.0, 0.01, u0.copy()
+            acc = rej = 0
+            while t < 1.0 - 1e-14:
+                dt = min(dt, 1.0 - t)
+                U, un, _ = gpu_solve(P, u, dt, 1e-13)
+                err = P.st.st_error_estimate(P.h, dev(U), dev(u), atol, rtol)
+                o, _ = orc.error_estimate(P.p, U, u, dt, atol, rtol)
+                assert abs(err - o) <= EST_TOL * abs(o) + round_off_bound(orc, P, U, u, atol, rtol)
+                if err <= 1.0:
+                    t += dt
+                    u = un
+                    acc += 1
+                else:
+                    rej += 1
+                dt = P.st.st_next_dt(c["Nt"], dt, err)
+                assert acc + rej < 2000
+            ex = np.sin(2 * np.pi * (X[:, 0, :] - 1.0)).ravel()
+            e_end = np.abs(u - ex).max()
+            say(f"adaptive rtol={rtol}: {acc} accepted, {rej} rejected, max error at T=1 {e_end:.2e}")
+            counts[rtol] = acc
+            assert e_end < 1e-3
+        assert counts[1e-7] > counts[1e-4]
+    finally:
+        P.close()

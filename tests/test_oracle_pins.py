@@ -666,3 +666,22 @@ def test_error_estimate_matches_stage_fluxes(orc):
     direct = (Us[:, :, -1, :] - uh).ravel()
     assert np.abs(e - direct).max() <= 1e-11 * np.abs(up).max()
     assert np.abs(e).max() > 1e-8            # a real estimate, not round-off
+
+
+@pytest.mark.parametrize("Nt", [2, 3, 4])
+def test_error_estimate_is_inflow_jump(orc, Nt):
+    """With this embedding b - b_hat is +-(first row of A) (both annihilate the
+    moments c^q, q <= Nt - 2, since A satisfies C(Nt - 1) with c_1 = 0), so the
+    first stage equation turns the estimate into +-(U_1 - u^n) for any slab
+    values, solved or not."""
+    A, b, bh, c = orc.embedded_weights(Nt)
+    s = float(np.sign(np.dot(b - bh, A[0])))
+    assert np.allclose(b - bh, s * A[0], atol=1e-15)
+    p = orc.problem(2, [3, 2], [0, 0], [1, 1], 2, Nt, orc.EULER)
+    rng = np.random.default_rng(Nt)
+    n, nsp = orc.slab_size(p), orc.space_size(p)
+    U = 1.0 + 0.1 * rng.standard_normal(n)
+    up = 1.0 + 0.1 * rng.standard_normal(nsp)
+    _, e = orc.error_estimate(p, U, up, 0.1, atol=1.0, rtol=0.0)
+    U1 = U.reshape(6, 4, Nt, 9)[:, :, 0, :].ravel()
+    assert np.abs(e - s * (U1 - up)).max() < 1e-13
