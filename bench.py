@@ -151,6 +151,29 @@ def lgl_coords(st, dim, K, lo, hi, N):
     return X
 
 
+def served_vs_fp64(st, reqs, served):
+    """Every served end-of-slab state against a plain FP64 st_solve_slab of the
+    same slab on the same GPU (tolerance 1e-10 on both sides): largest relative
+    2-norm difference, over the FP64 and the FP32-inner requests."""
+    import numpy as np
+    import torch
+    worst = {0: 0.0, 1: 0.0}
+    for j, (q, r, nsp) in enumerate(reqs):
+        h = st.st_create(r.mesh, r.N, r.Nt, r.eq)
+        try:
+            up = torch.as_tensor(np.ctypeslib.as_array(r.u_prev, shape=(nsp,)).copy()).cuda()
+            un = torch.empty(nsp, dtype=torch.float64, device="cuda")
+            st.st_solve_slab(h, up, 0.0, r.dt, r.tol, st.st_default_opts(), None, un)
+            ref = un.cpu().numpy()
+        finally:
+            st.st_destroy(h)
+        d = float(np.linalg.norm(served[j] - ref) / max(np.linalg.norm(ref), 1e-300))
+        f = int(q["inner_fp32"])
+        worst[f] = max(worst[f], d)
+    return dict(reference="plain FP64 st_solve_slab of the same slab, same GPU",
+                max_rel_diff_fp64_requests=worst[0], max_rel_diff_fp32_inner_requests=worst[1])
+
+
 def serving_bench(n_requests, seed=4, budget_gib=64, max_active=64, load=0.7):
     """Served mix of 1D Burgers and 2D advection-diffusion slab solves (K in
     8..256 per axis, N in 2..5, Nt in 2..4, FP64 / FP32-inner 50/50, CFL 5):
@@ -197,7 +220,7 @@ def serving_bench(n_requests, seed=4, budget_gib=64, max_active=64, load=0.7):
                     buf = np.empty(nsp)
                     rc, info = st.st_poll(srv, t, buf)
                     if rc != st.ST_PENDING:
-                        done[j] = (rc, info)
+                        done[j] = (rc, info, buf)
                 time.sleep(0.0002)
             wall = time.perf_counter() - t0
             stats = st.st_server_stats(srv)
@@ -205,13 +228,14 @@ def serving_bench(n_requests, seed=4, budget_gib=64, max_active=64, load=0.7):
             st.st_server_destroy(srv)
         lat = np.array([(done[j][1]["done_us"] - done[j][1]["submit_us"]) * 1e-3 for j in range(len(reqs))])
         ok = sum(1 for j in done if done[j][0] == st.ST_OK)
-        return wall, lat, ok, stats
+        return wall, lat, ok, stats, {j: done[j][2] for j in done}
 
     stream = inputs.serving_stream(seed, n_requests, rate=0.0)
     reqs = build(stream)
     unknowns = sum(st.st_request_footprint(r) for _, r, _ in reqs)
-    wall_sat, lat_sat, ok_sat, _ = run(reqs, [0.0] * len(reqs))
+    wall_sat, lat_sat, ok_sat, _, served = run(reqs, [0.0] * len(reqs))
     thr = len(reqs) / wall_sat
+    accuracy = served_vs_fp64(st, reqs, served)
     # Poisson arrivals at 50 / 70 / 90 % of the saturated throughput, and at
     # a fixed 4096 requests/s (beyond saturation: the queue absorbs it)
     sweep, ok_all, stats_p, lat_p, rate = [], ok_sat, None, None, load * thr
@@ -219,7 +243,7 @@ def serving_bench(n_requests, seed=4, budget_gib=64, max_active=64, load=0.7):
         r_s = fixed if fixed else frac * thr
         g = np.random.default_rng(seed + 1)
         arr = np.cumsum(g.exponential(1.0 / r_s, size=len(reqs)))
-        wall_i, lat_i, ok_i, stats_i = run(reqs, arr)
+        wall_i, lat_i, ok_i, stats_i, _ = run(reqs, arr)
         ok_all = min(ok_all, ok_i)
         sweep.append(dict(load=frac, rate_per_s=r_s, latency_ms_p50=float(np.percentile(lat_i, 50)),
                           latency_ms_p99=float(np.percentile(lat_i, 99)), solves_per_s=len(reqs) / wall_i, ok=ok_i))
@@ -229,7 +253,7 @@ def serving_bench(n_requests, seed=4, budget_gib=64, max_active=64, load=0.7):
                 poisson_rate_per_s=rate, load=load, latency_ms_p50=float(np.percentile(lat_p, 50)),
                 latency_ms_p99=float(np.percentile(lat_p, 99)), latency_ms_p50_saturated=float(np.percentile(lat_sat, 50)),
                 latency_ms_p99_saturated=float(np.percentile(lat_sat, 99)), ok=ok_all,
-                loads=sweep, ticks=stats_p["ticks"], footprint_bytes_total=unknowns,
+                loads=sweep, ticks=stats_p["ticks"], footprint_bytes_total=unknowns, accuracy=accuracy,
                 mix="1D Burgers + 2D advection-diffusion, K 8..256, N 2..5, Nt 2..4, FP64/FP32-inner 50/50, CFL 5")
 
 
@@ -386,6 +410,17 @@ def main():
     value = op_evals * n / elapsed
     lat_ms = np.array(lat) * 1e3
 
+    # the other precision form on the first slab, against the form timed
+    # (both on this GPU, same tolerance): relative 2-norm difference of U
+    def first_slab(fp32):
+        o2 = st.st_default_opts(restart=args.restart, cgs_passes=args.cgs_passes, inner_fp32=fp32)
+        Ux = torch.empty(n, dtype=torch.float64, device="cuda")
+        st.st_solve_slab(h, torch.as_tensor(u0).cuda(), 0.0, dt, cfg["tol"], o2, Ux, None, stream)
+        return Ux.cpu().numpy()
+    U64, U32 = first_slab(0), first_slab(1)
+    precision_split = dict(slab="the first slab of the workload",
+                           fp32_inner_vs_fp64_rel_diff=float(np.linalg.norm(U32 - U64) / np.linalg.norm(U64)))
+
     # roofline of the dominant kernel: algorithmic bytes (accumulated by the
     # library per kernel class) over the HIP-event time of its launches
     def roof_of(cls, name, bound="hbm"):
@@ -483,6 +518,7 @@ def main():
         "gmres_its_per_slab": sum(s["gmres_its"] for s in stats) / len(stats),
         "operator_evals": op_evals,
         "kernel_time_share_of_timed": shares,
+        "precision_split": precision_split,
         # algorithmic bytes of the timed steps per kernel class (the library's
         # per-launch byte model, summed)
         "kernel_bytes_of_timed": {st.KERNEL_CLASSES[c]: sum(s["kernel_bytes"][c] for s in stats)
