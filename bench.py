@@ -118,18 +118,36 @@ def cpu_baseline(cfg, u0, U, dt, seconds):
                        mu=cfg.get("mu", 0.0), prandtl=cfg.get("prandtl", 0.72))
     n = U.size
     oracle.residual(p, U, u0, dt)         # warm (page-in, thread start)
-    t0 = time.perf_counter()
-    evals = 0
-    while True:
-        oracle.residual(p, U, u0, dt)
-        evals += 1
-        el = time.perf_counter() - t0
-        if el >= seconds:
-            break
-    return dict(value=evals * n / el, unit="space-time DOF residual evals/s", cores=oracle.get_threads(),
+
+    def rate(budget):
+        t0 = time.perf_counter()
+        evals = 0
+        while True:
+            oracle.residual(p, U, u0, dt)
+            evals += 1
+            el = time.perf_counter() - t0
+            if el >= budget:
+                return evals, el
+
+    evals, el = rate(seconds)
+    threads = oracle.get_threads()
+    # the same on one host core (a shorter sample), and the host's CPU model
+    oracle.set_threads(1)
+    try:
+        e1, el1 = rate(max(2.0, seconds / 4))
+    finally:
+        oracle.set_threads(threads)
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")), "")
+    except OSError:
+        pass
+    return dict(value=evals * n / el, unit="space-time DOF residual evals/s", cores=threads,
                 kind="oracle",
                 sample=f"{evals} oracle residual evaluations of one {n}-unknown slab of the same workload "
-                       f"({el:.1f} s)")
+                       f"({el:.1f} s)",
+                one_core_value=e1 * n / el1, cpu_model=model)
 
 
 def lgl_coords(st, dim, K, lo, hi, N):
