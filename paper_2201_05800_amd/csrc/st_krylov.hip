@@ -587,8 +587,10 @@ __global__ __launch_bounds__(VBLOCK) void k_errest(EstArgs a) {
     const auto* __restrict__ up = gl(a.up);
     double acc[1] = {0.0};
     const int64_t stride = (int64_t)a.nblk * VBLOCK;
+    const bool narrow = a.nsp <= 0xffffffffLL;     // 32-bit division suffices
     for (int64_t i = (int64_t)blockIdx.x * VBLOCK + threadIdx.x; i < a.nsp; i += stride) {
-        const int64_t ev = i / a.ns, s = i - ev * a.ns;
+        const int64_t ev = narrow ? (int64_t)((uint32_t)i / (uint32_t)a.ns) : i / a.ns;
+        const int64_t s = i - ev * a.ns;
         const int64_t base = ev * a.nt * a.ns + s;
         const double u1 = U[base];                               // first time node
         const double uN = U[base + (int64_t)(a.nt - 1) * a.ns];  // u^{n+1}
