@@ -51,6 +51,8 @@ extern "C" {
 #define ST_ERR_UNSUPPORTED (-6)    /* (eq, dim, N, Nt) not compiled in, or an  */
                                    /* option not available for it             */
 #define ST_ERR_NOT_FOUND (-7)      /* unknown ticket                          */
+
+#define ST_MAX_SLABS 64            /* slabs of one multi-slab system           */
 #define ST_ERR_CANCELLED (-8)      /* ticket cancelled before completion      */
 
 /* Periodic Cartesian mesh, cf. cartesianDomain(lower, upper, counts) in
@@ -95,7 +97,7 @@ typedef struct {
     int timing;        /* bit mask of ST_K_* kernel classes to time with HIP    */
                        /* events on the solve's stream (0 = none)               */
     int precond;       /* 0: none (default); 1: element-block Jacobi, right     */
-                       /* preconditioning (st_solve_slab only; element blocks   */
+                       /* preconditioning (slab solves only; element blocks     */
                        /* of at most 1024 unknowns, nv Nt (N+1)^d)              */
 } st_solver_opts_t;
 
@@ -189,6 +191,31 @@ int st_jvp(st_handle_t h, const double* U, double t0, double dt, const double* v
 int st_solve_slab(st_handle_t h, const double* u_prev, double t0, double dt, double tol,
                   const st_solver_opts_t* opts, double* U_out, double* u_next, st_stats_t* stats,
                   void* stream);
+
+/* Several consecutive slabs as one system (the space-time mesh with M
+ * elements in time; Sec. "Merits" notes that solving for several time steps
+ * at once opens parallelism in time, and Sec. "Adaptive Mesh Refinement" sets
+ * up such a system of coupled time elements).  Slab m covers
+ * [t0 + m dt, t0 + (m+1) dt]; vectors hold the M slabs one after another, each
+ * in the layout of a single slab (M n_slab doubles).  Slab 0 takes u_prev as
+ * its upwind inflow, slab m >= 1 the last time node of slab m - 1, so the
+ * residual of slab m is st_residual's with u_prev = (e_Nt^T (x) I) U_{m-1},
+ * and the Jacobian is block lower bidiagonal: diagonal blocks those of
+ * eq. (Jacobian_ST), below them the inflow coupling (unit weight at the first
+ * time node).  Its exact solution is that of M sequential slab solves.
+ * 1 <= M <= ST_MAX_SLABS, else ST_ERR_BAD_ARG.  The handle's buffers grow to
+ * hold M slabs on first use (waits for the device). */
+int st_residual_slabs(st_handle_t h, int M, const double* U, const double* u_prev, double t0,
+                      double dt, double* R, void* stream);
+int st_jvp_slabs(st_handle_t h, int M, const double* U, double t0, double dt, const double* v,
+                 double* Jv, int inner_fp32, void* stream);
+/* Newton-GMRES on the coupled system of M slabs, as st_solve_slab (same
+ * options, preconditioner block in every element of every slab, stopping
+ * test on the 2-norm of the whole residual); U_out receives M n_slab values,
+ * u_next the end state of the last slab. */
+int st_solve_slabs(st_handle_t h, int M, const double* u_prev, double t0, double dt, double tol,
+                   const st_solver_opts_t* opts, double* U_out, double* u_next, st_stats_t* stats,
+                   void* stream);
 
 /* Local error estimate of a solved slab by an embedded solution (Sec.
  * "Algorithmic Aspects", adaptive time-stepping; eqs. (RK_stage_equations),

@@ -271,3 +271,62 @@ def error_estimate(p, U, uprev, dt, atol, rtol):
     sc = atol + rtol * np.maximum(np.abs(un), np.abs(u1))
     err = float(np.sqrt(np.mean((e / sc) ** 2)))
     return err, e.reshape(-1)
+
+
+# ---------------------------------------------------------------------------
+# Several time elements in one system (Sec. "Merits": solving for several time
+# steps at once; Sec. "Adaptive Mesh Refinement": one system of several
+# coupled time elements).  Slab m covers [t0 + m dt, t0 + (m+1) dt]; the
+# vector holds the slabs one after another, each in the single-slab layout.
+# The upwind trace at tau = -1 of slab m (eq. upwind_flux) is the last time
+# node of slab m - 1; slab 0's is u^n.
+# ---------------------------------------------------------------------------
+def inflow_term(p, w) -> np.ndarray:
+    """How the inflow state w enters a slab residual: -(B_tau (x) I) U* with
+    B_tau = diag(-1, 0, ..., 0, 1) and U*(tau = -1) = w (eq. DG_in_time) puts
+    +w at the first time node and nothing elsewhere."""
+    nv = nvars(p.eq, p.dim)
+    ns = (p.N + 1) ** p.dim
+    out = np.zeros((slab_size(p) // (nv * p.Nt * ns), nv, p.Nt, ns))
+    out[:, :, 0, :] = np.asarray(w, dtype=np.float64).reshape(-1, nv, ns)
+    return out.reshape(-1)
+
+
+def residual_slabs(p, U, uprev, dt, M) -> np.ndarray:
+    """Residual of M coupled slabs: slab m's residual with its inflow taken
+    from the last time node of slab m - 1."""
+    Us = np.asarray(U, dtype=np.float64).reshape(M, -1)
+    out, inflow = [], np.asarray(uprev, dtype=np.float64)
+    for m in range(M):
+        out.append(residual(p, Us[m], inflow, dt))
+        inflow = last_time_node(p, Us[m])
+    return np.concatenate(out)
+
+
+def jvp_slabs(p, U, dt, V, M) -> np.ndarray:
+    """Jacobian of residual_slabs times V: block lower bidiagonal, the slab
+    Jacobians on the diagonal and the inflow dependence below them."""
+    Us = np.asarray(U, dtype=np.float64).reshape(M, -1)
+    Vs = np.asarray(V, dtype=np.float64).reshape(M, -1)
+    out = []
+    for m in range(M):
+        j = jvp(p, Us[m], dt, Vs[m])
+        if m > 0:
+            j = j + inflow_term(p, last_time_node(p, Vs[m - 1]))
+        out.append(j)
+    return np.concatenate(out)
+
+
+def solve_slabs(p, uprev, dt, M, tol=1e-13):
+    """Solution of the M-slab system.  The Jacobian is block lower triangular
+    and slab m depends on the earlier slabs only through its inflow, so the
+    system is solved exactly by forward substitution: one slab solve after
+    another, each taking the previous slab's last time node as inflow."""
+    out, inflow = [], np.asarray(uprev, dtype=np.float64)
+    for _ in range(M):
+        U, st = solve(p, inflow, dt, tol=tol)
+        if not st["converged"]:
+            raise RuntimeError(f"oracle slab solve did not converge: {st}")
+        out.append(U)
+        inflow = last_time_node(p, U)
+    return np.concatenate(out)

@@ -315,6 +315,13 @@ struct st_ctx {
     PcSeg* d_pc = nullptr;
     // embedded error estimate: partial sums + result
     double* d_est = nullptr;
+    // vector buffers (V, w, R, U, pz, Q, dQ, U32, dQ32, d_part) hold `cap`
+    // consecutive slabs; the solve's descriptors: 4 cap operator segments
+    // (residual viscous pass, residual, JVP viscous pass, JVP) and cap + 2
+    // vector segments (Krylov, per-slab initial guess, extraction)
+    int cap = 1;
+    OpSeg* d_opm = nullptr;
+    VecSeg* d_vsm = nullptr;
 
     // optional HIP-event timing of kernel classes (st_solver_opts_t.timing)
     struct Timer {
@@ -365,6 +372,12 @@ struct st_ctx {
         allocs.push_back(*p);
         return ST_OK;
     }
+    void release(void* p) {
+        if (!p) return;
+        auto it = std::find(allocs.begin(), allocs.end(), p);
+        if (it != allocs.end()) allocs.erase(it);
+        (void)hipFree(p);
+    }
     ~st_ctx() {
         for (hipEvent_t e : timer.pool) (void)hipEventDestroy(e);
         for (void* p : allocs) (void)hipFree(p);
@@ -383,29 +396,54 @@ struct st_ctx {
         if (e_ != hipSuccess) return set_error(ST_ERR_HIP, std::string(#x) + ": " + hipGetErrorString(e_)); \
     } while (0)
 
+// Vector buffers for M consecutive slabs.  Growing waits for the device and
+// drops the buffers' contents (and the Krylov basis size).
+static int ensure_cap(st_ctx* h, int M) {
+    const Problem& pb = h->pb;
+    if (M <= h->cap && h->d_opm) return ST_OK;
+    const int c = std::max(M, h->cap);
+    HIPCHK(hipDeviceSynchronize());
+    for (void* p : {(void*)h->V, (void*)h->w, (void*)h->R, (void*)h->U, (void*)h->pz, (void*)h->Q, (void*)h->dQ,
+                    (void*)h->U32, (void*)h->dQ32, (void*)h->d_part, (void*)h->d_opm, (void*)h->d_vsm})
+        h->release(p);
+    h->V = h->w = h->R = h->U = h->pz = h->Q = h->dQ = h->d_part = nullptr;
+    h->U32 = h->dQ32 = nullptr;
+    h->d_opm = nullptr;
+    h->d_vsm = nullptr;
+    h->m_alloc = 0;
+    h->cap = c;
+    const size_t n = (size_t)pb.n * c;
+    CHK(h->alloc(&h->d_part, (size_t)vec_blocks((int64_t)n) * (NPART_SLOTS + 1)));
+    CHK(h->alloc(&h->d_opm, (size_t)4 * c));
+    CHK(h->alloc(&h->d_vsm, (size_t)c + 2));
+    if (grad_pass(pb)) {
+        CHK(h->alloc(&h->Q, n * pb.mesh.dim));
+        CHK(h->alloc(&h->dQ, n * pb.mesh.dim));
+    }
+    return ST_OK;
+}
+
 static int ensure_fp32(st_ctx* h) {
     const Problem& pb = h->pb;
     if (h->U32) return ST_OK;
-    CHK(h->alloc(&h->U32, pb.n));
-    if (grad_pass(pb)) CHK(h->alloc(&h->dQ32, (size_t)pb.n * pb.mesh.dim));
+    const size_t n = (size_t)pb.n * h->cap;
+    CHK(h->alloc(&h->U32, n));
+    if (grad_pass(pb)) CHK(h->alloc(&h->dQ32, n * pb.mesh.dim));
     return ST_OK;
 }
 
 static int ensure_solve(st_ctx* h, int m) {
     const Problem& pb = h->pb;
-    if (h->m_alloc >= m) return ST_OK;
-    if (h->V) {
-        // grow: drop the old basis
-        auto it = std::find(h->allocs.begin(), h->allocs.end(), (void*)h->V);
-        if (it != h->allocs.end()) h->allocs.erase(it);
-        (void)hipFree(h->V);
-        h->V = nullptr;
-    }
-    CHK(h->alloc(&h->V, (size_t)pb.n * m));
+    if (h->m_alloc >= m && h->V) return ST_OK;
+    const size_t n = (size_t)pb.n * h->cap;
+    // grow: drop the old basis
+    h->release(h->V);
+    h->V = nullptr;
+    CHK(h->alloc(&h->V, n * m));
     if (!h->w) {
-        CHK(h->alloc(&h->w, pb.n));
-        CHK(h->alloc(&h->R, pb.n));
-        CHK(h->alloc(&h->U, pb.n));
+        CHK(h->alloc(&h->w, n));
+        CHK(h->alloc(&h->R, n));
+        CHK(h->alloc(&h->U, n));
     }
     h->m_alloc = m;
     return ST_OK;
@@ -458,6 +496,7 @@ static int ensure_precond(st_ctx* h, const double* u_prev, double dt, hipStream_
     const bool lin = linear_eq(pb.eq.kind);
     const int npe = (int)(pb.nv * pb.Nt * pb.ns);
     if (npe > PC_NPE_MAX) return set_error(ST_ERR_UNSUPPORTED, "element block larger than the preconditioner supports");
+    if (!h->pz) CHK(h->alloc(&h->pz, (size_t)pb.n * h->cap));
     if (h->binvT && h->pc_dt == dt) return ST_OK;
     if (pc_prepare(npe) != hipSuccess)
         return set_error(ST_ERR_UNSUPPORTED, "element block needs more LDS than the device grants");
@@ -578,13 +617,20 @@ static int ensure_precond(st_ctx* h, const double* u_prev, double dt, hipStream_
     const std::vector<double> packed = pc_pack(Bm, npe);
     if (!h->binvT) {
         CHK(h->alloc(&h->binvT, packed.size()));
-        CHK(h->alloc(&h->pz, pb.n));
         CHK(h->alloc(&h->d_pc, 2));
     }
     HIPCHK(hipMemcpy(h->binvT, packed.data(), sizeof(double) * packed.size(), hipMemcpyHostToDevice));
     h->pc_dt = dt;
     return ST_OK;
 }
+
+namespace stdg {
+void setup_residual(st_ctx* h, int M, const double* U, const double* u_prev, double* R, double dt, OpSeg* dv,
+                    OpSeg* dop, hipStream_t st);
+CoupleArgs couple_args(const Problem& pb, int M, const double* in0, const int* kp, int64_t ld, double* out,
+                       const int* skip);
+void launch_residual(st_ctx* h, int M, const OpSeg* dv, const OpSeg* dop, const CoupleArgs& cp, hipStream_t st);
+}  // namespace stdg
 
 extern "C" {
 
@@ -616,20 +662,12 @@ int st_create(const st_mesh_t* mesh, int N, int Nt, const st_equation_t* eq, st_
     if (rc != ST_OK) { delete h; return rc; }
     hipError_t e = hipGetDevice(&h->device);
     if (e != hipSuccess) { delete h; return set_error(ST_ERR_HIP, std::string("hipGetDevice: ") + hipGetErrorString(e)); }
-    const Problem& pb = h->pb;
     if ((rc = h->alloc(&h->d_op, 8)) != ST_OK ||
         (rc = h->alloc(&h->d_vs, 1)) != ST_OK ||
         (rc = h->alloc(&h->d_st, 1)) != ST_OK ||
-        (rc = h->alloc(&h->d_part, (size_t)vec_blocks(pb.n) * (NPART_SLOTS + 1))) != ST_OK) {
+        (rc = ensure_cap(h, 1)) != ST_OK) {
         delete h;
         return rc;
-    }
-    if (grad_pass(pb)) {
-        if ((rc = h->alloc(&h->Q, (size_t)pb.n * pb.mesh.dim)) != ST_OK ||
-            (rc = h->alloc(&h->dQ, (size_t)pb.n * pb.mesh.dim)) != ST_OK) {
-            delete h;
-            return rc;
-        }
     }
     e = hipHostMalloc((void**)&h->h_st, sizeof(GState), hipHostMallocDefault);
     if (e != hipSuccess) { delete h; return set_error(ST_ERR_HIP, std::string("hipHostMalloc: ") + hipGetErrorString(e)); }
@@ -669,27 +707,23 @@ int st_node_coords(st_handle_t h, double* X) {
 
 int st_residual(st_handle_t h, const double* U, const double* u_prev, double t0, double dt, double* R,
                 void* stream) {
+    return st_residual_slabs(h, 1, U, u_prev, t0, dt, R, stream);
+}
+
+int st_residual_slabs(st_handle_t h, int M, const double* U, const double* u_prev, double t0, double dt, double* R,
+                      void* stream) {
     (void)t0;
     if (!h || !U || !u_prev || !R) return set_error(ST_ERR_BAD_ARG, "st_residual: null argument");
+    if (M < 1 || M > ST_MAX_SLABS) return set_error(ST_ERR_BAD_ARG, "st_residual_slabs: slabs must be in 1..64");
     if (!(dt > 0.0) || !std::isfinite(dt)) return set_error(ST_ERR_BAD_ARG, "st_residual: dt must be positive");
+    CHK(ensure_cap(h, M));
     const Problem& pb = h->pb;
     hipStream_t st = (hipStream_t)stream;
-    const int G = op_blocks(pb);
-    OpSeg s = base_opseg(pb, dt);
-    if (grad_pass(pb)) {
-        OpSeg g = s;
-        visc_tiles(g, pb);
-        g.U = dptr(U);
-        g.out = dptr(h->Q);
-        put_opseg(h->d_op + 0, g, st);
-        pb.ops->visc_res64(h->d_op + 0, 1, G, st);
-        s.Q = dptr(h->Q);
-    }
-    s.U = dptr(U);
-    s.uprev = u_prev;
-    s.out = dptr(R);
-    put_opseg(h->d_op + 1, s, st);
-    pb.ops->res64(h->d_op + 1, 1, G, st);
+    OpSeg* dv = M == 1 ? h->d_op + 0 : h->d_opm;
+    OpSeg* dop = M == 1 ? h->d_op + 1 : h->d_opm + M;
+    h->timer.reset(0);
+    setup_residual(h, M, U, u_prev, R, dt, dv, dop, st);
+    launch_residual(h, M, dv, dop, couple_args(pb, M, U, nullptr, 0, R, nullptr), st);
     HIPCHK(hipGetLastError());
     return ST_OK;
 }
@@ -698,62 +732,133 @@ int st_residual(st_handle_t h, const double* U, const double* u_prev, double t0,
 
 namespace stdg {
 
-// Jv for the handle's problem, in two halves: upload the descriptors (slots
-// `slot`, `slot + 1`) and launch the kernels.  U: double state (U32 must hold
-// the FP32 copy when inner_fp32 and the equation is nonlinear); the direction
-// may follow the Arnoldi index.  NS: the viscous pass writes the tangent of
-// -Fv at (U, v) to dQ (dQ32), which the JVP kernel reads.
-void setup_jvp(st_ctx* h, const double* U, DynPtr V, double* out, const int* skip, bool fp32, double dt,
-               int slot, hipStream_t st) {
-    const Problem& pb = h->pb;
-    const int kind = pb.eq.kind;
-    OpSeg s = base_opseg(pb, dt);
-    s.skip = skip;
-    s.out = dptr(out);
-    const DynPtr state = dptr(fp32 ? (const void*)h->U32 : (const void*)U);
-    if (grad_pass(pb)) {
-        OpSeg g = s;
-        visc_tiles(g, pb);
-        g.U = state;
-        g.V = V;
-        g.out = dptr(fp32 ? (void*)h->dQ32 : (void*)h->dQ);
-        put_opseg(h->d_op + slot, g, st);
+// Descriptors of M consecutive slabs: segment m covers blocks [m G, (m+1) G)
+// of one launch; `make(m, seg)` fills slab m's pointers.
+template <class F>
+static void put_slab_segs(OpSeg* dst, int M, const OpSeg& proto, hipStream_t st, F&& make) {
+    for (int m = 0; m < M; ++m) {
+        OpSeg s = proto;
+        s.blk0 = m * proto.nblk;
+        make(m, s);
+        put_opseg(dst + m, s, st);
     }
-    if (linear_eq(kind)) {
-        // J v = R(v) with u_prev = 0
-        s.U = V;
-        s.uprev = nullptr;
-    } else {
-        s.U = state;
-        s.V = V;
-        if (grad_pass(pb)) s.Q = dptr(fp32 ? (void*)h->dQ32 : (void*)h->dQ);
-    }
-    put_opseg(h->d_op + slot + 1, s, st);
 }
 
-void launch_jvp(st_ctx* h, bool fp32, int slot, hipStream_t st) {
+// Residual of M consecutive slabs at U, in two halves: upload the
+// descriptors (viscous pass to dv[0..M), operator to dop[0..M)) and launch.
+// Slab 0 takes u_prev as inflow, the others none: the coupling kernel adds
+// theirs.
+void setup_residual(st_ctx* h, int M, const double* U, const double* u_prev, double* R, double dt, OpSeg* dv,
+                    OpSeg* dop, hipStream_t st) {
     const Problem& pb = h->pb;
-    const int G = op_blocks(pb);
+    const int64_t n = pb.n, nq = pb.n * pb.mesh.dim;
+    const OpSeg base = base_opseg(pb, dt);
+    if (grad_pass(pb)) {
+        OpSeg g = base;
+        visc_tiles(g, pb);
+        put_slab_segs(dv, M, g, st, [&](int m, OpSeg& x) {
+            x.U = dptr(U + m * n);
+            x.out = dptr(h->Q + m * nq);
+        });
+    }
+    put_slab_segs(dop, M, base, st, [&](int m, OpSeg& x) {
+        if (grad_pass(pb)) x.Q = dptr(h->Q + m * nq);
+        x.U = dptr(U + m * n);
+        x.uprev = m == 0 ? u_prev : nullptr;
+        x.out = dptr(R + m * n);
+    });
+}
+
+CoupleArgs couple_args(const Problem& pb, int M, const double* in0, const int* kp, int64_t ld, double* out,
+                       const int* skip) {
+    CoupleArgs a;
+    a.in0 = in0;
+    a.kp = kp;
+    a.ld = ld;
+    a.out = out;
+    a.skip = skip;
+    a.n = pb.n;
+    a.nsp = pb.nsp;
+    a.slabs = M;
+    a.nt = pb.Nt;
+    a.ns = pb.ns;
+    a.nblk = vec_blocks((int64_t)(M > 1 ? M - 1 : 1) * pb.nsp);
+    return a;
+}
+
+void launch_residual(st_ctx* h, int M, const OpSeg* dv, const OpSeg* dop, const CoupleArgs& cp, hipStream_t st) {
+    const Problem& pb = h->pb;
+    const int G = M * op_blocks(pb);
+    auto& T = h->timer;
+    if (grad_pass(pb)) T.run(ST_K_GRAD, st, [&] { pb.ops->visc_res64(dv, M, G, st); });
+    T.run(ST_K_RESIDUAL, st, [&] { pb.ops->res64(dop, M, G, st); });
+    if (M > 1) T.run(ST_K_RESIDUAL, st, [&] { vk_couple(cp, st); });
+}
+
+// Jv of M consecutive slabs (decoupled; the coupling kernel completes it),
+// in two halves: upload the descriptors and launch the kernels.  U: double
+// state (U32 must hold the FP32 copy when inner_fp32 and the equation is
+// nonlinear).  The direction of slab m is dir + m n, moved by ld * (*kp)
+// when kp is set (the Arnoldi index).  NS: the viscous pass writes the
+// tangent of -Fv at (U, v) to dQ (dQ32), which the JVP kernel reads.
+void setup_jvp(st_ctx* h, int M, const double* U, const double* dir, const int* kp, int64_t ld, double* out,
+               const int* skip, bool fp32, double dt, OpSeg* dv, OpSeg* dop, hipStream_t st) {
+    const Problem& pb = h->pb;
+    const int kind = pb.eq.kind;
+    const int64_t n = pb.n, nq = pb.n * pb.mesh.dim;
+    OpSeg base = base_opseg(pb, dt);
+    base.skip = skip;
+    auto dirp = [&](int m) { return DynPtr{dir + m * n, ld, kp, 0}; };
+    auto state = [&](int m) { return dptr(fp32 ? (const void*)(h->U32 + m * n) : (const void*)(U + m * n)); };
+    auto dq = [&](int m) { return dptr(fp32 ? (void*)(h->dQ32 + m * nq) : (void*)(h->dQ + m * nq)); };
+    if (grad_pass(pb)) {
+        OpSeg g = base;
+        visc_tiles(g, pb);
+        put_slab_segs(dv, M, g, st, [&](int m, OpSeg& x) {
+            x.U = state(m);
+            x.V = dirp(m);
+            x.out = dq(m);
+        });
+    }
+    put_slab_segs(dop, M, base, st, [&](int m, OpSeg& x) {
+        x.out = dptr(out + m * n);
+        if (linear_eq(kind)) {
+            // J v = R(v) with u_prev = 0
+            x.U = dirp(m);
+            x.uprev = nullptr;
+        } else {
+            x.U = state(m);
+            x.V = dirp(m);
+            if (grad_pass(pb)) x.Q = dq(m);
+        }
+    });
+}
+
+void launch_jvp(st_ctx* h, int M, bool fp32, const OpSeg* dv, const OpSeg* dop, const CoupleArgs& cp,
+                hipStream_t st) {
+    const Problem& pb = h->pb;
+    const int G = M * op_blocks(pb);
     const int kind = pb.eq.kind;
     if (grad_pass(pb))
-        h->timer.run(ST_K_GRAD, st, [&] { (fp32 ? pb.ops->visc_jvp32 : pb.ops->visc_jvp64)(h->d_op + slot, 1, G, st); });
+        h->timer.run(ST_K_GRAD, st, [&] { (fp32 ? pb.ops->visc_jvp32 : pb.ops->visc_jvp64)(dv, M, G, st); });
     h->timer.run(ST_K_JVP, st, [&] {
-        if (linear_eq(kind)) (fp32 ? pb.ops->lin32 : pb.ops->res64)(h->d_op + slot + 1, 1, G, st);
-        else (fp32 ? pb.ops->jvp32 : pb.ops->jvp64)(h->d_op + slot + 1, 1, G, st);
+        if (linear_eq(kind)) (fp32 ? pb.ops->lin32 : pb.ops->res64)(dop, M, G, st);
+        else (fp32 ? pb.ops->jvp32 : pb.ops->jvp64)(dop, M, G, st);
     });
+    if (M > 1) h->timer.run(ST_K_JVP, st, [&] { vk_couple(cp, st); });
 }
 
 // FP32 copy of U for FP32-inner JVPs of the nonlinear equations (uses the
 // vector slot for the cast).
-void enqueue_jvp_prepare(st_ctx* h, const double* U, bool fp32, hipStream_t st) {
+void enqueue_jvp_prepare(st_ctx* h, int M, const double* U, bool fp32, hipStream_t st) {
     const Problem& pb = h->pb;
     if (linear_eq(pb.eq.kind) || !fp32) return;
     VecSeg v;
     std::memset(&v, 0, sizeof(v));
     v.U = const_cast<double*>(U);
     v.U32 = h->U32;
-    v.n = pb.n;
-    v.nblk = vec_blocks(pb.n);
+    v.n = pb.n * M;
+    v.nblk = vec_blocks(v.n);
     v.st = h->d_st;
     put_vecseg(h->d_vs, v, st);
     vk_cast32(h->d_vs, 1, v.nblk, st);
@@ -765,17 +870,26 @@ extern "C" {
 
 int st_jvp(st_handle_t h, const double* U, double t0, double dt, const double* v, double* Jv, int inner_fp32,
            void* stream) {
+    return st_jvp_slabs(h, 1, U, t0, dt, v, Jv, inner_fp32, stream);
+}
+
+int st_jvp_slabs(st_handle_t h, int M, const double* U, double t0, double dt, const double* v, double* Jv,
+                 int inner_fp32, void* stream) {
     (void)t0;
     if (!h || !v || !Jv) return set_error(ST_ERR_BAD_ARG, "st_jvp: null argument");
+    if (M < 1 || M > ST_MAX_SLABS) return set_error(ST_ERR_BAD_ARG, "st_jvp_slabs: slabs must be in 1..64");
     if (!linear_eq(h->pb.eq.kind) && !U) return set_error(ST_ERR_BAD_ARG, "st_jvp: null state");
     if (!(dt > 0.0) || !std::isfinite(dt)) return set_error(ST_ERR_BAD_ARG, "st_jvp: dt must be positive");
     hipStream_t st = (hipStream_t)stream;
     const bool fp32 = inner_fp32 != 0;
+    CHK(ensure_cap(h, M));
     if (fp32) CHK(ensure_fp32(h));
+    OpSeg* dv = M == 1 ? h->d_op + 3 : h->d_opm + 2 * M;
+    OpSeg* dop = M == 1 ? h->d_op + 4 : h->d_opm + 3 * M;
     h->timer.reset(0);
-    enqueue_jvp_prepare(h, U, fp32, st);
-    setup_jvp(h, U, dptr(v), Jv, nullptr, fp32, dt, 3, st);
-    launch_jvp(h, fp32, 3, st);
+    enqueue_jvp_prepare(h, M, U, fp32, st);
+    setup_jvp(h, M, U, v, nullptr, 0, Jv, nullptr, fp32, dt, dv, dop, st);
+    launch_jvp(h, M, fp32, dv, dop, couple_args(h->pb, M, v, nullptr, 0, Jv, nullptr), st);
     HIPCHK(hipGetLastError());
     return ST_OK;
 }
@@ -822,9 +936,16 @@ int st_next_dt(int Nt, double dt, double err, double* dt_next) {
 int st_solve_slab(st_handle_t h, const double* u_prev, double t0, double dt, double tol,
                   const st_solver_opts_t* opts_in, double* U_out, double* u_next, st_stats_t* stats,
                   void* stream) {
+    return st_solve_slabs(h, 1, u_prev, t0, dt, tol, opts_in, U_out, u_next, stats, stream);
+}
+
+int st_solve_slabs(st_handle_t h, int M, const double* u_prev, double t0, double dt, double tol,
+                   const st_solver_opts_t* opts_in, double* U_out, double* u_next, st_stats_t* stats,
+                   void* stream) {
     (void)t0;
     auto t_start = std::chrono::steady_clock::now();
     if (!h || !u_prev) return set_error(ST_ERR_BAD_ARG, "st_solve_slab: null argument");
+    if (M < 1 || M > ST_MAX_SLABS) return set_error(ST_ERR_BAD_ARG, "st_solve_slabs: slabs must be in 1..64");
     if (!(dt > 0.0) || !std::isfinite(dt)) return set_error(ST_ERR_BAD_ARG, "st_solve_slab: dt must be positive");
     if (!(tol > 0.0)) return set_error(ST_ERR_BAD_ARG, "st_solve_slab: tol must be positive");
     st_solver_opts_t o;
@@ -837,13 +958,14 @@ int st_solve_slab(st_handle_t h, const double* u_prev, double t0, double dt, dou
     const Problem& pb = h->pb;
     const bool fp32 = o.inner_fp32 != 0;
     const int m = o.restart;
+    CHK(ensure_cap(h, M));
     CHK(ensure_solve(h, m));
     if (fp32) CHK(ensure_fp32(h));
     hipStream_t st = (hipStream_t)stream;
     const bool pc = o.precond == 1;
     if (pc) CHK(ensure_precond(h, u_prev, dt, st));
     const int kind = pb.eq.kind;
-    const int Gop = op_blocks(pb);
+    const int64_t nM = pb.n * M;             // unknowns of the (multi-slab) system
 
     // forcing: linear equations solve each cycle as far as the outer tolerance
     double eta_rel = linear_eq(kind) ? 0.0 : std::max(o.gmres_rtol, 0.0);
@@ -855,10 +977,10 @@ int st_solve_slab(st_handle_t h, const double* u_prev, double t0, double dt, dou
     vs.w = h->w;
     vs.R = h->R;
     vs.U = h->U;
-    vs.n = pb.n;
+    vs.n = nM;
     vs.st = h->d_st;
     vs.part = h->d_part;
-    vs.part2 = h->d_part + (size_t)vec_blocks(pb.n) * NPART_SLOTS;
+    vs.part2 = h->d_part + (size_t)vec_blocks(nM) * NPART_SLOTS;
     vs.eta_rel = eta_rel;
     vs.eta_tgt = 0.5;
     vs.tol = tol;
@@ -869,45 +991,54 @@ int st_solve_slab(st_handle_t h, const double* u_prev, double t0, double dt, dou
     vs.nt = pb.Nt;
     vs.ns = pb.ns;
     vs.blk0 = 0;
-    vs.nblk = vec_blocks(pb.n);
+    vs.nblk = vec_blocks(nM);
     const int Gv = vs.nblk;
     h->timer.reset(o.timing);
     HIPCHK(hipMemsetAsync(h->d_st, 0, sizeof(GState), st));
-    put_vecseg(h->d_vs, vs, st);
-    vk_init_guess(h->d_vs, 1, Gv, st);
-
-    // residual descriptors (slots 0, 1), fixed for the whole solve
-    OpSeg rs = base_opseg(pb, dt);
-    if (grad_pass(pb)) {
-        OpSeg g = rs;
-        visc_tiles(g, pb);
-        g.U = dptr(h->U);
-        g.out = dptr(h->Q);
-        put_opseg(h->d_op + 0, g, st);
-        rs.Q = dptr(h->Q);
+    VecSeg* dvs = h->d_vsm;                  // [0]: the system, [1, M]: per-slab guess, [M + 1]: extraction
+    put_vecseg(dvs, vs, st);
+    // initial guess 1 (x) u_prev in every slab
+    const int Gs = vec_blocks(pb.n);
+    for (int sl = 0; sl < M; ++sl) {
+        VecSeg g = vs;
+        g.U = h->U + sl * pb.n;
+        g.n = pb.n;
+        g.blk0 = sl * Gs;
+        g.nblk = Gs;
+        put_vecseg(dvs + 1 + sl, g, st);
     }
-    rs.U = dptr(h->U);
-    rs.uprev = u_prev;
-    rs.out = dptr(h->R);
-    put_opseg(h->d_op + 1, rs, st);
+    vk_init_guess(dvs + 1, M, M * Gs, st);
 
-    // JVP descriptors (slots 4, 5): the direction V_k follows the device
-    // Arnoldi index; the whole segment is skipped once the cycle is done
+    // residual descriptors, fixed for the whole solve
+    OpSeg* d_rv = h->d_opm;
+    OpSeg* d_rop = h->d_opm + M;
+    setup_residual(h, M, h->U, u_prev, h->R, dt, d_rv, d_rop, st);
+    const CoupleArgs cp_res = couple_args(pb, M, h->U, nullptr, 0, h->R, nullptr);
+
+    // JVP descriptors: the direction V_k follows the device Arnoldi index;
+    // the whole segment is skipped once the cycle is done
     const int* kp = &h->d_st->k;
     const int* skip = &h->d_st->done;
+    OpSeg* d_jv = h->d_opm + 2 * M;
+    OpSeg* d_jop = h->d_opm + 3 * M;
     // right preconditioning: the JVP takes z = B^-1 V_k, formed per step
-    setup_jvp(h, h->U, pc ? dptr(h->pz) : dptr_k(h->V, pb.n, kp), h->w, skip, fp32, dt, 4, st);
+    const double* dir = pc ? h->pz : h->V;
+    const int* dkp = pc ? nullptr : kp;
+    const int64_t dld = pc ? 0 : nM;
+    setup_jvp(h, M, h->U, dir, dkp, dld, h->w, skip, fp32, dt, d_jv, d_jop, st);
+    const CoupleArgs cp_jvp = couple_args(pb, M, dir, dkp, dld, h->w, skip);
     const int npe = (int)(pb.nv * pb.Nt * pb.ns);
-    const int Gpc = pc ? pc_blocks((int)pb.E, npe) : 0;
+    const int64_t Eall = pb.E * M;           // element blocks of all slabs (B^-1 is the same in each)
+    const int Gpc = pc ? pc_blocks((int)Eall, npe) : 0;
     if (pc) {
         PcSeg a;
         std::memset(&a, 0, sizeof(a));
-        a.in = dptr_k(h->V, pb.n, kp);
+        a.in = dptr_k(h->V, nM, kp);
         a.out = h->pz;
         a.binvT = h->binvT;
         a.skip = skip;
         a.npe = npe;
-        a.E = (int)pb.E;
+        a.E = (int)Eall;
         a.accumulate = 0;
         a.blk0 = 0;
         a.nblk = Gpc;
@@ -926,11 +1057,10 @@ int st_solve_slab(st_handle_t h, const double* u_prev, double t0, double dt, dou
     int stall = 0;
     auto& T = h->timer;
     for (;;) {
-        if (grad_pass(pb)) T.run(ST_K_GRAD, st, [&] { pb.ops->visc_res64(h->d_op + 0, 1, Gop, st); });
-        T.run(ST_K_RESIDUAL, st, [&] { pb.ops->res64(h->d_op + 1, 1, Gop, st); });
+        launch_residual(h, M, d_rv, d_rop, cp_res, st);
         T.run(ST_K_NEWTON, st, [&] {
-            vk_rnorm(h->d_vs, 1, Gv, st);
-            vk_begin(h->d_vs, 1, st);
+            vk_rnorm(dvs, 1, Gv, st);
+            vk_begin(dvs, 1, st);
         }, false);
         HIPCHK(hipMemcpyAsync(h->h_st, h->d_st, offsetof(GState, hacc), hipMemcpyDeviceToHost, st));
         HIPCHK(hipStreamSynchronize(st));
@@ -944,42 +1074,52 @@ int st_solve_slab(st_handle_t h, const double* u_prev, double t0, double dt, dou
         else if (++stall >= 8) break;     // no progress over 8 outer iterations
         ++outer;
         // Jacobian base point of FP32-inner JVPs: the FP32 copy of U
-        if (fp32 && !linear_eq(kind)) T.run(ST_K_NEWTON, st, [&] { vk_cast32(h->d_vs, 1, Gv, st); });
-        T.run(ST_K_NORMALIZE, st, [&] { vk_scale_v0(h->d_vs, 1, Gv, st); });
+        if (fp32 && !linear_eq(kind)) T.run(ST_K_NEWTON, st, [&] { vk_cast32(dvs, 1, Gv, st); });
+        T.run(ST_K_NORMALIZE, st, [&] { vk_scale_v0(dvs, 1, Gv, st); });
         for (int k = 0; k < m; ++k) {
             if (pc) T.run(ST_K_PRECOND, st, [&] { pc_apply(h->d_pc + 0, 1, Gpc, npe, st); });
-            launch_jvp(h, fp32, 4, st);
+            launch_jvp(h, M, fp32, d_jv, d_jop, cp_jvp, st);
             for (int p = 0; p < o.cgs_passes; ++p) {
-                T.run(ST_K_MULTIDOT, st, [&] { vk_multidot(h->d_vs, 1, Gv, k, st); });
-                T.run(ST_K_UPDATE, st, [&] { vk_update(h->d_vs, 1, Gv, p, p == o.cgs_passes - 1, k, st); });
+                T.run(ST_K_MULTIDOT, st, [&] { vk_multidot(dvs, 1, Gv, k, st); });
+                T.run(ST_K_UPDATE, st, [&] { vk_update(dvs, 1, Gv, p, p == o.cgs_passes - 1, k, st); });
             }
         }
         T.run(ST_K_NEWTON, st, [&] {
-            vk_finish(h->d_vs, 1, st);
+            vk_finish(dvs, 1, st);
             if (pc) {
-                pc_combine(h->d_vs, 1, Gv, st);
+                pc_combine(dvs, 1, Gv, st);
                 pc_apply(h->d_pc + 1, 1, Gpc, npe, st);
             } else {
-                vk_update_u(h->d_vs, 1, Gv, st);
+                vk_update_u(dvs, 1, Gv, st);
             }
         }, false);
         HIPCHK(hipGetLastError());
     }
-    if (u_next) vk_extract_last(h->d_vs, 1, Gv, st);
-    if (U_out) HIPCHK(hipMemcpyAsync(U_out, h->U, sizeof(double) * pb.n, hipMemcpyDeviceToDevice, st));
+    if (u_next) {
+        // u_next = (e_Nt^T (x) I) U of the last slab
+        VecSeg x = vs;
+        x.U = h->U + (M - 1) * pb.n;
+        x.n = pb.n;
+        x.nblk = Gs;
+        put_vecseg(dvs + M + 1, x, st);
+        vk_extract_last(dvs + M + 1, 1, Gs, st);
+    }
+    if (U_out) HIPCHK(hipMemcpyAsync(U_out, h->U, sizeof(double) * nM, hipMemcpyDeviceToDevice, st));
     HIPCHK(hipMemcpyAsync(h->h_st, h->d_st, offsetof(GState, hacc), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
     if (stats) {
         h->timer.collect(stats);
         // algorithmic bytes: operator kernels from launch counts, Krylov
         // kernels accumulated on the device
-        const double n8 = 8.0 * (double)pb.n;
+        const double n8 = 8.0 * (double)nM;
         const int its = h->h_st->iters_total;
         const bool visc = grad_pass(pb), lin = linear_eq(kind);
         for (int c = 0; c < ST_K_COUNT; ++c) stats->kernel_bytes[c] = 0.0;
-        stats->kernel_bytes[ST_K_RESIDUAL] = (outer + 1) * n8 * (2.0 + 1.0 / pb.Nt);
+        // coupling of M slabs: 3 (M - 1) spatial vectors of a slab per launch
+        const double cpl = 24.0 * (double)(M - 1) * (double)pb.nsp;
+        stats->kernel_bytes[ST_K_RESIDUAL] = (outer + 1) * (2.0 * n8 + 8.0 * (double)pb.nsp + cpl);
         const double jvp_b = lin ? 2.0 * n8 : (fp32 ? 2.5 : 3.0) * n8;   // [U,] v in, Jv out
-        stats->kernel_bytes[ST_K_JVP] = its * jvp_b;
+        stats->kernel_bytes[ST_K_JVP] = its * (jvp_b + cpl);
         if (visc) {
             const double d = pb.mesh.dim;
             // viscous pass: residual reads U, writes d values per unknown; JVP

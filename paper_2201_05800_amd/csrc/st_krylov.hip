@@ -610,6 +610,23 @@ __global__ __launch_bounds__(VBLOCK) void k_errest_final(EstArgs a) {
     if (threadIdx.x == 0) gl(a.out)[0] = sqrt(s_out[0] / (double)a.nsp);
 }
 
+// out_m(first time node) += in_{m-1}(last time node), m = 1 .. slabs - 1
+__global__ __launch_bounds__(VBLOCK) void k_couple(CoupleArgs a) {
+    if (a.skip && *gl(a.skip)) return;
+    const int64_t k = a.kp ? (int64_t)*gl(a.kp) : 0;
+    const auto* __restrict__ in = gl(a.in0 + k * a.ld);
+    auto* __restrict__ out = gl(a.out);
+    const int64_t total = (int64_t)(a.slabs - 1) * a.nsp;
+    const int64_t blk = (int64_t)a.nt * a.ns;
+    for (int64_t i = (int64_t)blockIdx.x * VBLOCK + threadIdx.x; i < total; i += (int64_t)a.nblk * VBLOCK) {
+        const int64_t m = i / a.nsp;                    // source slab
+        const int64_t r = i - m * a.nsp;
+        const int64_t ev = r / a.ns;                    // (element, variable)
+        const int64_t s = r - ev * a.ns;
+        out[(m + 1) * a.n + ev * blk + s] += in[m * a.n + ev * blk + (a.nt - 1) * a.ns + s];
+    }
+}
+
 // Descriptor uploads in stream order: the descriptor is the kernel's first
 // argument, so it sits at the start of the kernel-argument segment, and the
 // threads copy its 8-byte words in parallel (one thread copying a 3 KB
@@ -668,6 +685,9 @@ void vk_cast32(const VecSeg* s, int nseg, int G, hipStream_t st) { LAUNCH_V(k_ca
 void vk_error_estimate(const EstArgs& a, hipStream_t st) {
     LAUNCH_V(k_errest, a.nblk, a);
     LAUNCH_V(k_errest_final, 1, a);
+}
+void vk_couple(const CoupleArgs& a, hipStream_t st) {
+    if (a.slabs > 1) LAUNCH_V(k_couple, a.nblk, a);
 }
 void put_opseg(OpSeg* dst, const OpSeg& v, hipStream_t st) {
     launch_k(k_put_desc<OpSeg>, dim3(1), dim3(256), st, v, dst);

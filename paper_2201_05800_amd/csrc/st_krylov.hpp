@@ -33,6 +33,25 @@ struct EstArgs {
     double atol, rtol;
 };
 void vk_error_estimate(const EstArgs& a, hipStream_t st);
+// Coupling of consecutive slabs of a multi-slab system: slab m >= 1 takes
+// the last time node of slab m - 1, (e_Nt^T (x) I) U_{m-1}, as its upwind
+// inflow u^n, which enters the first time node of the slab residual with
+// unit weight (the residual is affine in u^n).  out_m += that node of in_{m-1}
+// for m = 1 .. slabs - 1; in is in0 + ld * (*kp) when kp is set (the Arnoldi
+// direction), else in0.  Applied to the residual of the slabs with no inflow
+// beyond slab 0, and to the JVP of the decoupled slabs, it gives those of
+// the coupled system.
+struct CoupleArgs {
+    const double* in0;
+    const int* kp;        // may be null
+    int64_t ld;
+    double* out;
+    const int* skip;      // skip when *skip != 0 (may be null)
+    int64_t n;            // unknowns per slab
+    int64_t nsp;          // spatial values per slab (E nv ns)
+    int slabs, nt, ns, nblk;
+};
+void vk_couple(const CoupleArgs& a, hipStream_t st);
 // element-block Jacobi (st_precond.hip): elements per block, launch, and
 // w = sum_{i < kfinal} y_i V_i for the preconditioned Newton update
 constexpr int PC_NPE_MAX = 1024;    // largest element block (unknowns per element)

@@ -97,6 +97,14 @@ _SIGS = [
     ("st_solve_slab", ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double, ctypes.c_double,
                                      ctypes.c_double, ctypes.POINTER(SolverOpts), ctypes.c_void_p,
                                      ctypes.c_void_p, ctypes.POINTER(Stats), ctypes.c_void_p]),
+    ("st_residual_slabs", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
+                                         ctypes.c_double, ctypes.c_double, ctypes.c_void_p, ctypes.c_void_p]),
+    ("st_jvp_slabs", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_double,
+                                    ctypes.c_double, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
+                                    ctypes.c_void_p]),
+    ("st_solve_slabs", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_double,
+                                      ctypes.c_double, ctypes.c_double, ctypes.POINTER(SolverOpts),
+                                      ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(Stats), ctypes.c_void_p]),
     ("st_error_estimate", ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double,
                                          ctypes.c_double, _c_double_p, ctypes.c_void_p]),
     ("st_next_dt", ctypes.c_int, [ctypes.c_int, ctypes.c_double, ctypes.c_double, _c_double_p]),
@@ -237,6 +245,16 @@ def st_jvp(h, U, t0, dt, v, Jv, inner_fp32=0, stream=None) -> None:
                         _stream(stream)))
 
 
+def st_residual_slabs(h, M, U, u_prev, t0, dt, R, stream=None) -> None:
+    _check(lib().st_residual_slabs(h, int(M), _dev(U, "U"), _dev(u_prev, "u_prev"), float(t0), float(dt),
+                                   _dev(R, "R"), _stream(stream)))
+
+
+def st_jvp_slabs(h, M, U, t0, dt, v, Jv, inner_fp32=0, stream=None) -> None:
+    _check(lib().st_jvp_slabs(h, int(M), _dev(U, "U"), float(t0), float(dt), _dev(v, "v"), _dev(Jv, "Jv"),
+                              int(inner_fp32), _stream(stream)))
+
+
 def st_error_estimate(h, U, u_prev, atol, rtol, stream=None) -> float:
     err = ctypes.c_double(0.0)
     _check(lib().st_error_estimate(h, _dev(U, "U"), _dev(u_prev, "u_prev"), float(atol), float(rtol),
@@ -255,6 +273,18 @@ def st_solve_slab(h, u_prev, t0, dt, tol, opts=None, U_out=None, u_next=None, st
     rc = lib().st_solve_slab(h, _dev(u_prev, "u_prev"), float(t0), float(dt), float(tol),
                              ctypes.byref(opts) if opts is not None else None, _dev(U_out, "U_out"),
                              _dev(u_next, "u_next"), ctypes.byref(st), _stream(stream))
+    return _solve_result(rc, st, check)
+
+
+def st_solve_slabs(h, M, u_prev, t0, dt, tol, opts=None, U_out=None, u_next=None, stream=None, check=True):
+    st = Stats()
+    rc = lib().st_solve_slabs(h, int(M), _dev(u_prev, "u_prev"), float(t0), float(dt), float(tol),
+                              ctypes.byref(opts) if opts is not None else None, _dev(U_out, "U_out"),
+                              _dev(u_next, "u_next"), ctypes.byref(st), _stream(stream))
+    return _solve_result(rc, st, check)
+
+
+def _solve_result(rc, st, check):
     out = dict(rc=rc, newton_its=st.newton_its, gmres_its=st.gmres_its, res0=st.res0, res_final=st.res_final,
                usec=st.usec, status=st.status, kernel_us=list(st.kernel_us), kernel_calls=list(st.kernel_calls),
                kernel_bytes=list(st.kernel_bytes))
