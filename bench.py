@@ -71,6 +71,11 @@ def parse():
     ap.add_argument("--operators", type=int, default=1,
                     help="1: time st_residual / st_jvp on >= 1 GB working sets (0: skip)")
     ap.add_argument("--operator-reps", type=int, default=10)
+    ap.add_argument("--slabs-leg", type=int, default=1,
+                    help="time M coupled slabs solved as one system against M sequential slab solves")
+    ap.add_argument("--bubble-leg", type=int, default=1,
+                    help="the 3D Euler bubble (20^3 hexes, Nt=3, dt 0.2 and 0.05 to t=0.6): time per slab, "
+                         "iterations and the density L2 error at the end")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (3 times) for counter calibration")
     return ap.parse_args()
@@ -283,6 +288,108 @@ OPERATOR_WORKLOADS = {
     "euler2d": dict(K=[512, 512], label="2D Euler vortex, 512x512 quads on [-5,5]^2, N=3, Nt=3"),
     "ns3d": dict(K=[40, 40, 40], label="3D Navier-Stokes TGV, 40^3 hexes, N=3, Nt=3"),
 }
+
+
+def make_handle(c):
+    from paper_2201_05800_amd import st
+    d = c["dim"]
+    m = st.mesh(d, c["K"], c["lo"], c["hi"])
+    eq = st.equation(c["kind"], a=c.get("a", (0, 0, 0)), nu=c.get("nu", 0.0), gamma=c.get("gamma", 1.4),
+                     mu=c.get("mu", 0.0), prandtl=c.get("prandtl", 0.72))
+    return st.st_create(m, c["N"], c["Nt"], eq)
+
+
+def multi_slab_bench(c, u0, dt, M, precond):
+    """M consecutive slabs from u0: one coupled solve (st_solve_slabs) against
+    M sequential st_solve_slab calls, same tolerance; the first call of each
+    kind is a warm-up (the coupled one grows the handle's buffers)."""
+    import torch
+    from paper_2201_05800_amd import st
+    h = make_handle(c)
+    n, nsp, _ = st.st_sizes(h)
+    o = st.st_default_opts(precond=precond, max_newton=100)
+    up = torch.as_tensor(u0).cuda()
+    Uc = torch.empty(n * M, dtype=torch.float64, device="cuda")
+    unc = torch.empty(nsp, dtype=torch.float64, device="cuda")
+    Us = torch.empty(n, dtype=torch.float64, device="cuda")
+    a, b = torch.empty_like(unc), torch.empty_like(unc)
+
+    def sequential():
+        x = up
+        its = [0, 0]
+        for i in range(M):
+            y = a if i % 2 == 0 else b
+            r = st.st_solve_slab(h, x, 0.0, dt, c["tol"], o, Us, y)
+            its[0] += r["newton_its"]
+            its[1] += r["gmres_its"]
+            x = y
+        return x, its
+
+    st.st_solve_slabs(h, M, up, 0.0, dt, c["tol"], o, Uc, unc)
+    sequential()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rc = st.st_solve_slabs(h, M, up, 0.0, dt, c["tol"], o, Uc, unc)
+    torch.cuda.synchronize()
+    t_c = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    last, its = sequential()
+    torch.cuda.synchronize()
+    t_s = time.perf_counter() - t0
+    diff = float(torch.linalg.norm(unc - last) / torch.linalg.norm(last))
+    st.st_destroy(h)
+    return dict(slabs=M, unknowns_per_slab=n, precond=precond,
+                coupled_ms_per_slab=t_c * 1e3 / M, sequential_ms_per_slab=t_s * 1e3 / M,
+                coupled_newton_its=rc["newton_its"], coupled_gmres_its=rc["gmres_its"],
+                sequential_newton_its=its[0], sequential_gmres_its=its[1],
+                u_next_rel_diff=diff)
+
+
+def bubble_bench(N=3, dts=(0.2, 0.05), T=0.6):
+    """3D Euler smooth bubble on [0,1]^3, 20^3 hexes, Nt=3 (the 4D space-time
+    test of the paper's numerical results), element-block Jacobi GMRES, slabs
+    solved one after another to t = T; density L2 error at T against the
+    exactly advected bubble (LGL quadrature on every element)."""
+    import numpy as np
+    import torch
+    from paper_2201_05800_amd import inputs, st
+    c = dict(kind=4, dim=3, K=[20, 20, 20], lo=[0.0] * 3, hi=[1.0] * 3, N=N, Nt=3, gamma=1.4, tol=1e-8)
+    h = make_handle(c)
+    n, nsp, nv = st.st_sizes(h)
+    ns = (N + 1) ** 3
+    X = st.st_node_coords(h, 3, ns)
+    x, w, _ = st.st_lgl(N + 1)
+    W = np.ones(ns)
+    for s_ in range(ns):
+        for a in range(3):
+            W[s_] *= w[(s_ // (N + 1) ** a) % (N + 1)] * 0.5 / 20
+    rho_ex = inputs.euler_bubble_3d(X, T)[:, 0, :]
+    u0 = inputs.euler_bubble_3d(X, 0.0).ravel()
+    o = st.st_default_opts(precond=1, max_newton=50)
+    U = torch.empty(n, dtype=torch.float64, device="cuda")
+    out = []
+    for dt in dts:
+        steps = int(round(T / dt))
+        u = torch.as_tensor(u0).cuda()
+        un = torch.empty_like(u)
+        res = []
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            res.append(st.st_solve_slab(h, u, 0.0, dt, c["tol"], o, U, un))
+            u, un = un, u
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        rho = u.cpu().numpy().reshape(-1, nv, ns)[:, 0, :]
+        l2 = float(np.sqrt(np.sum(W[None, :] * (rho - rho_ex) ** 2)))
+        out.append(dict(dt=dt, slabs=steps, ms_per_slab=el * 1e3 / steps,
+                        newton_its_per_slab=sum(r["newton_its"] for r in res) / steps,
+                        gmres_its_per_slab=sum(r["gmres_its"] for r in res) / steps,
+                        rho_l2_error_at_t=l2))
+        print(f"# bubble dt={dt}: {out[-1]}", file=sys.stderr, flush=True)
+    st.st_destroy(h)
+    return dict(workload="3D Euler smooth bubble, periodic [0,1]^3, 20^3 hexes, N=%d, Nt=3, to t=0.6, "
+                         "element-block Jacobi" % N, unknowns_per_slab=n, runs=out)
 
 
 def operator_bench(reps, fp32_too=True):
@@ -506,6 +613,21 @@ def main():
         print(f"# preconditioned: {precond['ms_per_step']:.3f} ms/slab, {precond['gmres_its_per_slab']:.1f} "
               f"GMRES its/slab", file=sys.stderr, flush=True)
 
+    slabs = None
+    if args.slabs_leg:
+        small = dict(CONFIGS["advdiff2d"], K=[16, 16])
+        hs = make_handle(small)
+        Xs = st.st_node_coords(hs, 2, (small["N"] + 1) ** 2)
+        st.st_destroy(hs)
+        u_small = initial_state(small, Xs).ravel()
+        slabs = dict(note="M slabs from the same u^n: one coupled Newton-GMRES solve against M sequential "
+                          "slab solves, both to the workload's tolerance",
+                     workload=[multi_slab_bench(cfg, u0, dt, 4, 0), multi_slab_bench(cfg, u0, dt, 4, 1)],
+                     small_16x16=[multi_slab_bench(small, u_small, dt, 8, 0),
+                                  multi_slab_bench(small, u_small, dt, 8, 1)])
+        print(f"# slabs: {slabs}", file=sys.stderr, flush=True)
+    bubble = bubble_bench() if args.bubble_leg else None
+
     serving = serving_bench(args.serve_requests) if args.serve_requests > 0 else None
     operators = operator_bench(args.operator_reps) if args.operators else None
 
@@ -544,6 +666,8 @@ def main():
         "roofline": roof,
         "preconditioned": precond,
         "serving": serving,
+        "multi_slab": slabs,
+        "euler3d_bubble": bubble,
         "operators": operators,
         "cpu_baseline": cpu,
     }

@@ -19,6 +19,8 @@ Workloads (the recipes are also listed in the design notes):
 """
 from __future__ import annotations
 
+import math
+
 import numpy as np
 
 
@@ -102,6 +104,19 @@ def taylor_green(X: np.ndarray, mach=0.1, gamma=1.4) -> np.ndarray:
     p = p0 + (np.cos(2 * x) + np.cos(2 * y)) * (np.cos(2 * z) + 2.0) / 16.0
     rho = p / p0
     return euler_conservative(rho, [u, v, w], p, gamma)
+
+
+def euler_bubble_3d(X: np.ndarray, t=0.0, gamma=1.4) -> np.ndarray:
+    """Smooth density bubble advected by a uniform flow (the 3D Euler test of
+    Sec. "Numerical Results", 4D space-time): constant pressure 0.3, velocity
+    (cos(pi/5), sin(pi/5), sin(pi/5)), density 0.5 outside the ball of radius
+    1/4 around the moving centre 0.25 + t v, 0.25 (cos(pi r) + 1)^2 + 0.5 inside
+    with r = 16 |x - 0.25 - t v|^2.  The exact solution at any t; shape
+    (E, 5, ns)."""
+    vel = [math.cos(math.pi / 5), math.sin(math.pi / 5), math.sin(math.pi / 5)]
+    r = sum((X[:, a, :] - 0.25 - t * vel[a]) ** 2 for a in range(3)) * 16.0
+    rho = np.where(r > 1.0, 0.5, 0.25 * (np.cos(np.minimum(r, 1.0) * math.pi) + 1.0) ** 2 + 0.5)
+    return euler_conservative(rho, [vel[a] + 0.0 * rho for a in range(3)], 0.3 + 0.0 * rho, gamma)
 
 
 def cfl_dt(cfl: float, h_min: float, N: int, lam_max: float) -> float:

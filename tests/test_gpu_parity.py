@@ -187,6 +187,8 @@ SOLVES = [
     # element-wise paths instead of the paired ones
     ("burgers-odd-n", cfg("burgers", 1, [7], 2, 3), None, "burgers"),
     ("adv1d-odd-n", cfg("adv", 1, [9], 2, 3, a=(1.0,)), 1.0 / 32, "burgers"),
+    # the 3D Euler bubble of the 4D space-time test, on a coarse mesh
+    ("euler3d-bubble", cfg("euler", 3, [4, 4, 4], 2, 3), 0.05, "bubble"),
 ]
 
 
@@ -200,6 +202,8 @@ def initial(P, kind):
         return inputs.burgers_smooth(X, inputs.burgers_params(4)).ravel()
     if kind == "tgv":
         return inputs.taylor_green(X).ravel()
+    if kind == "bubble":
+        return inputs.euler_bubble_3d(X).ravel()
     raise ValueError(kind)
 
 
