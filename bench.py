@@ -26,6 +26,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0      # MI355X HBM3E, GB/s
+TIME_EVERY = 8             # kernel timing on one slab in eight of the timed region
 
 CONFIGS = {
     # 2D advection-diffusion, BR1
@@ -71,6 +72,9 @@ def parse():
     ap.add_argument("--operators", type=int, default=1,
                     help="1: time st_residual / st_jvp on >= 1 GB working sets (0: skip)")
     ap.add_argument("--operator-reps", type=int, default=10)
+    ap.add_argument("--precision-split", type=int, default=1,
+                    help="solve the first slab in both precision forms after the timed steps (0: skip, so that a "
+                         "counter run sees the timed steps' kernels only)")
     ap.add_argument("--slabs-leg", type=int, default=1,
                     help="time M coupled slabs solved as one system against M sequential slab solves")
     ap.add_argument("--bubble-leg", type=int, default=1,
@@ -495,8 +499,10 @@ def main():
     u0 = u0.ravel()
 
     # HIP-event timing: the warm-up times every kernel class to find the
-    # dominant one; the timed region times only that class (two events per
-    # launch of it), so the measured steps are barely perturbed
+    # dominant one; in the timed region only that class is timed (two events
+    # per launch of it), and only on every TIME_EVERY-th slab: event pairs on
+    # every launch of every slab made the slabs 17 % slower (35 % for the
+    # preconditioned ones)
     every = sum(1 << c for c in (st.ST_K_RESIDUAL, st.ST_K_JVP, st.ST_K_GRAD, st.ST_K_MULTIDOT, st.ST_K_UPDATE,
                                  st.ST_K_NORMALIZE))
     opts = st.st_default_opts(restart=args.restart, cgs_passes=args.cgs_passes, inner_fp32=args.fp32_inner,
@@ -515,14 +521,13 @@ def main():
         u, un = un, u
     shares_w = [sum(s["kernel_us"][c] for s in warm) for c in range(len(st.KERNEL_CLASSES))]
     dom = max(range(len(shares_w)), key=lambda c: shares_w[c]) if warm else st.ST_K_MULTIDOT
-    if not args.no_timing:
-        opts.timing = 1 << dom
     u.copy_(torch.as_tensor(u0))
     torch.cuda.synchronize()
 
     lat, stats = [], []
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    for i in range(args.steps):
+        opts.timing = 0 if args.no_timing or i % TIME_EVERY else 1 << dom
         ts = time.perf_counter()
         s = step(u, un)      # synchronises the stream at its end
         lat.append(time.perf_counter() - ts)
@@ -542,20 +547,23 @@ def main():
         Ux = torch.empty(n, dtype=torch.float64, device="cuda")
         st.st_solve_slab(h, torch.as_tensor(u0).cuda(), 0.0, dt, cfg["tol"], o2, Ux, None, stream)
         return Ux.cpu().numpy()
-    U64, U32 = first_slab(0), first_slab(1)
-    precision_split = dict(slab="the first slab of the workload",
-                           fp32_inner_vs_fp64_rel_diff=float(np.linalg.norm(U32 - U64) / np.linalg.norm(U64)))
+    precision_split = None
+    if args.precision_split:
+        U64, U32 = first_slab(0), first_slab(1)
+        precision_split = dict(slab="the first slab of the workload",
+                               fp32_inner_vs_fp64_rel_diff=float(np.linalg.norm(U32 - U64) / np.linalg.norm(U64)))
 
     # roofline of the dominant kernel: algorithmic bytes (accumulated by the
     # library per kernel class) over the HIP-event time of its launches
     def roof_of(cls, name, bound="hbm"):
-        us = sum(s["kernel_us"][cls] for s in stats)
-        calls = sum(s["kernel_calls"][cls] for s in stats)
-        by = sum(s["kernel_bytes"][cls] for s in stats)
+        timed = [s for s in stats if s["kernel_calls"][cls] > 0]      # the slabs whose launches were timed
+        us = sum(s["kernel_us"][cls] for s in timed)
+        calls = sum(s["kernel_calls"][cls] for s in timed)
+        by = sum(s["kernel_bytes"][cls] for s in timed)
         ach = by / (us * 1e-6) / 1e9 if us > 0 else 0.0
         return dict(bound=bound, kernel=name, achieved=round(ach, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                     frac=round(ach / HBM_PEAK_GBS, 4), traffic=None, avg_launch_us=round(us / max(calls, 1), 3),
-                    launches=calls, algorithmic_bytes_per_launch=round(by / max(calls, 1)))
+                    launches=calls, timed_slabs=len(timed), algorithmic_bytes_per_launch=round(by / max(calls, 1)))
 
     names = {st.ST_K_RESIDUAL: "k_op (residual)", st.ST_K_JVP: "k_op (JVP)", st.ST_K_GRAD: "k_visc",
              st.ST_K_MULTIDOT: "k_multidot", st.ST_K_UPDATE: "k_update", st.ST_K_NORMALIZE: "k_scale_v0"}
@@ -575,7 +583,7 @@ def main():
         print(f"# preconditioned leg skipped: element block of {npe} unknowns (at most 1024)", file=sys.stderr)
     if args.precond_leg and npe <= 1024:
         opc = st.st_default_opts(restart=args.restart, cgs_passes=args.cgs_passes, inner_fp32=args.fp32_inner,
-                                 precond=1, timing=0 if args.no_timing else (1 << st.ST_K_PRECOND))
+                                 precond=1)
         u.copy_(torch.as_tensor(u0))
         step_pc = lambda uin, uout: st.st_solve_slab(h, uin, 0.0, dt, cfg["tol"], opc, U, uout, stream)
         step_pc(u, un)                       # warm-up: assembles and inverts the element block
@@ -583,16 +591,18 @@ def main():
         torch.cuda.synchronize()
         lat_pc, stats_pc = [], []
         t0 = time.perf_counter()
-        for _ in range(args.steps):
+        for i in range(args.steps):
+            opc.timing = 0 if args.no_timing or i % TIME_EVERY else 1 << st.ST_K_PRECOND
             ts = time.perf_counter()
             stats_pc.append(step_pc(u, un))
             lat_pc.append(time.perf_counter() - ts)
             u, un = un, u
         torch.cuda.synchronize()
         el_pc = time.perf_counter() - t0
-        us = sum(x["kernel_us"][st.ST_K_PRECOND] for x in stats_pc)
-        calls = sum(x["kernel_calls"][st.ST_K_PRECOND] for x in stats_pc)
-        by = sum(x["kernel_bytes"][st.ST_K_PRECOND] for x in stats_pc)
+        timed_pc = [x for x in stats_pc if x["kernel_calls"][st.ST_K_PRECOND] > 0]
+        us = sum(x["kernel_us"][st.ST_K_PRECOND] for x in timed_pc)
+        calls = sum(x["kernel_calls"][st.ST_K_PRECOND] for x in timed_pc)
+        by = sum(x["kernel_bytes"][st.ST_K_PRECOND] for x in timed_pc)
         precond = dict(
             method="element-block Jacobi, right preconditioning (B^-1 of the element diagonal block of the slab "
                    "Jacobian, the same in every element" +
