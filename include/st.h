@@ -95,7 +95,9 @@ typedef struct {
     double gmres_rtol; /* minimum inner forcing term eta (default 1e-3; raised  */
                        /* to 1e-5 at least when inner_fp32)                     */
     int timing;        /* bit mask of ST_K_* kernel classes to time with HIP    */
-                       /* events on the solve's stream (0 = none)               */
+                       /* events on the solve's stream (0 = none); an event    */
+                       /* pair per launch slows launch-bound solves (17 % for  */
+                       /* a 409,600-unknown slab with one class timed)          */
     int precond;       /* 0: none (default); 1: element-block Jacobi, right     */
                        /* preconditioning (slab solves only; element blocks     */
                        /* of at most 1024 unknowns, nv Nt (N+1)^d)              */
