@@ -633,8 +633,8 @@ def main():
         slabs = dict(note="M slabs from the same u^n: one coupled Newton-GMRES solve against M sequential "
                           "slab solves, both to the workload's tolerance",
                      workload=[multi_slab_bench(cfg, u0, dt, 4, 0), multi_slab_bench(cfg, u0, dt, 4, 1)],
-                     small_16x16=[multi_slab_bench(small, u_small, dt, 8, 0),
-                                  multi_slab_bench(small, u_small, dt, 8, 1)])
+                     small_16x16=[multi_slab_bench(small, u_small, dt, 8, 0)] +
+                                 [multi_slab_bench(small, u_small, dt, M, 1) for M in (4, 8, 16, 32)])
         print(f"# slabs: {slabs}", file=sys.stderr, flush=True)
     bubble = bubble_bench() if args.bubble_leg else None
 
