@@ -464,8 +464,8 @@ def operator_bench(reps, fp32_too=True):
 def main():
     args = parse()
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU (one slab per GPU; the multi-GPU "
-              "decomposition is described in DESIGN.md, not built); use --gpus 1", file=sys.stderr)
+        print("bench.py: runs on one GPU only (a slab, or a multi-slab system, per GPU; splitting one "
+              "over several GPUs is not implemented); use --gpus 1", file=sys.stderr)
         sys.exit(2)
     import numpy as np
     import torch
