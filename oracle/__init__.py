@@ -229,48 +229,88 @@ def last_time_node(p, U) -> np.ndarray:
 
 # ---------------------------------------------------------------------------
 # Embedded error estimate (Sec. "Algorithmic Aspects", adaptive time-stepping;
-# eqs. RK_stage_equations and RK_solution).  The paper leaves the embedded
-# weights open; the reading taken here: b_hat is the interpolatory quadrature
-# on [0, 1] through the first Nt - 1 stage nodes (b_hat_Nt = 0), exact for
-# polynomials of degree Nt - 2, so the embedded solution has order Nt - 1
-# (the stage order of Lobatto IIIC) against 2 Nt - 2 for u^{n+1}.
+# eqs. RK_stage_equations and RK_solution).  The embedded solution is to be
+# one order below u^{n+1} (order 2 Nt - 2), with the strategy of the Radau IIA
+# code the paper cites (Hairer-Wanner IV.8): besides the stage derivatives
+# K_l = F(U_l) the embedded formula may use the derivative at the known start
+# value, K_0 = F(u^n) (an explicit stage at c = 0), with weight gamma_0:
+#     u_hat = u^n + dt (gamma_0 F(u^n) + sum_l b_hat_l K_l).
+# Weights taken (reading of the paper; proofs in the pins):
+#   Nt = 2: gamma_0 = 0, b_hat = (1, 0)            order 1 = 2 Nt - 3
+#   Nt > 2: gamma_0 = b_1, b_hat = (0, b_2 .. b_Nt) order Nt
+# i.e. for Nt > 2 the embedded formula is the Lobatto quadrature with the first
+# stage derivative replaced by the one at u^n.  Nt = 3 gives order 3 = 2 Nt - 3.
+# For Nt = 4 no such formula has order 5: the quadrature conditions up to
+# degree 4 on the four distinct nodes fix the summed weight at c = 0 to b_1,
+# which leaves only gamma_0, and every gamma_0 != 0 fails the order-5 tree
+# conditions (Lobatto IIIC has stage order Nt - 1 = 3, so U_1 - u^n = O(dt^4));
+# order 4 is the highest reachable.
 # ---------------------------------------------------------------------------
+EMBEDDED_ORDER = {2: 1, 3: 3, 4: 4}
+
+
 def embedded_weights(Nt: int):
-    """(A, b, b_hat, c): the Appendix B tableau and the embedded weights."""
+    """(A, b, c, gamma0, b_hat): the Appendix B tableau and the embedded
+    weights (gamma0 on F(u^n), b_hat on the stage derivatives)."""
     A, b, c = butcher_appendix_b(Nt)
-    m = Nt - 1
-    # moment conditions sum_l b_hat_l c_l^q = 1 / (q + 1), q = 0 .. m - 1
-    M = np.array([[c[l] ** q for l in range(m)] for q in range(m)])
-    rhs = np.array([1.0 / (q + 1) for q in range(m)])
     bh = np.zeros(Nt)
-    bh[:m] = np.linalg.solve(M, rhs)
-    return A, b, bh, c
+    if Nt == 2:
+        gamma0 = 0.0
+        bh[0] = 1.0
+    else:
+        gamma0 = float(b[0])
+        bh[1:] = b[1:]
+    return A, b, c, gamma0, bh
+
+
+def stage_derivatives(p, U, uprev):
+    """dt K_l from the stage equations, dt K = (A^-1 (x) I)(U - 1 (x) u^n)
+    (eq. RK_stage_equations with the Appendix B tableau); shape (E, nv, Nt, ns)."""
+    nv = nvars(p.eq, p.dim)
+    ns = (p.N + 1) ** p.dim
+    A, _, _ = butcher_appendix_b(p.Nt)
+    Us = np.asarray(U, dtype=np.float64).reshape(-1, nv, p.Nt, ns)
+    un = np.asarray(uprev, dtype=np.float64).reshape(-1, nv, ns)
+    return np.einsum("lj,evjs->evls", np.linalg.inv(A), Us - un[:, :, None, :])
 
 
 def error_estimate(p, U, uprev, dt, atol, rtol):
-    """Local error estimate of a solved slab.
-
-    Stage derivatives from the stage equations, dt K = (A^-1 (x) I)(U - 1 (x) u^n);
-    u^{n+1} = u^n + dt sum_l b_l K_l and u_hat = u^n + dt sum_l b_hat_l K_l
-    (eq. RK_solution with b and b_hat); e = u^{n+1} - u_hat.  The scalar is the
-    root mean square over every spatial node and variable of
+    """Local error estimate of a solved slab: e = u^{n+1} - u_hat with
+    u^{n+1} = u^n + dt sum_l b_l K_l (eq. RK_solution) and u_hat as above,
+    formed from the weight differences,
+        e = dt sum_l (b_l - b_hat_l) K_l - gamma_0 dt F(u^n),
+    (the difference of the two solutions would lose the digits e has below
+    |u|).  F is the oracle's spatial operator.  The scalar is the root mean
+    square over every spatial node and variable of
     e / (atol + rtol max(|u^n|, |u^{n+1}|)).  Returns (err, e) with e in the
     spatial layout [E][nv][ns]."""
     nv = nvars(p.eq, p.dim)
     ns = (p.N + 1) ** p.dim
-    A, b, bh, _ = embedded_weights(p.Nt)
-    Us = np.asarray(U, dtype=np.float64).reshape(-1, nv, p.Nt, ns)
+    _, b, _, gamma0, bh = embedded_weights(p.Nt)
     un = np.asarray(uprev, dtype=np.float64).reshape(-1, nv, ns)
-    D = Us - un[:, :, None, :]                                   # U_j - u^n
-    hK = np.einsum("lj,evjs->evls", np.linalg.inv(A), D)         # dt K_l
+    hK = stage_derivatives(p, U, uprev)
     u1 = un + np.einsum("l,evls->evs", b, hK)
-    # e = u^{n+1} - u_hat = dt sum_l (b_l - b_hat_l) K_l, formed from the
-    # difference of the weights (the difference of the two solutions would
-    # lose the digits e has below |u|)
     e = np.einsum("l,evls->evs", b - bh, hK)
+    if gamma0 != 0.0:
+        e = e - gamma0 * dt * spatial_op(p, un.ravel()).reshape(un.shape)
     sc = atol + rtol * np.maximum(np.abs(un), np.abs(u1))
     err = float(np.sqrt(np.mean((e / sc) ** 2)))
     return err, e.reshape(-1)
+
+
+def error_scale_terms(p, U, uprev, dt):
+    """The magnitudes the estimate is formed from, per spatial value:
+    sum_l |b_l - b_hat_l| |dt K_l| + |gamma_0| |dt F(u^n)|.  Rounding in
+    forming e is relative to these, not to |e| (for small steps e is the
+    small difference of two stage derivatives)."""
+    nv = nvars(p.eq, p.dim)
+    ns = (p.N + 1) ** p.dim
+    _, b, _, gamma0, bh = embedded_weights(p.Nt)
+    un = np.asarray(uprev, dtype=np.float64).reshape(-1, nv, ns)
+    s = np.einsum("l,evls->evs", np.abs(b - bh), np.abs(stage_derivatives(p, U, uprev)))
+    if gamma0 != 0.0:
+        s = s + abs(gamma0) * dt * np.abs(spatial_op(p, un.ravel()).reshape(un.shape))
+    return s.reshape(-1)
 
 
 # ---------------------------------------------------------------------------

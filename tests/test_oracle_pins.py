@@ -609,79 +609,183 @@ def test_jacobian_block_structure(orc, name):
 # ---------------------------------------------------------------------------
 # Embedded error estimate (Sec. "Algorithmic Aspects", adaptive time-stepping)
 # ---------------------------------------------------------------------------
+def _rooted_trees(order):
+    """All rooted trees with `order` vertices, a tree being the sorted tuple
+    of its subtrees (the leaf is ())."""
+    if order == 1:
+        return [()]
+    out = set()
+
+    def forests(n, smallest):
+        # multisets of trees with n vertices in total, in non-decreasing order
+        if n == 0:
+            yield ()
+            return
+        for k in range(1, n + 1):
+            for t in _rooted_trees(k):
+                if smallest is not None and (k, t) < smallest:
+                    continue
+                for rest in forests(n - k, (k, t)):
+                    yield ((k, t),) + rest
+
+    for f in forests(order - 1, None):
+        out.add(tuple(sorted(t for _, t in f)))
+    return sorted(out)
+
+
+def _tree_order(t):
+    return 1 + sum(_tree_order(c) for c in t)
+
+
+def _tree_density(t):
+    g = _tree_order(t)
+    for c in t:
+        g *= _tree_density(c)
+    return g
+
+
+def _elementary_weights(t, A):
+    """Phi_i(t) = prod over the subtrees t_k of (A Phi(t_k))_i (Butcher)."""
+    phi = np.ones(A.shape[0])
+    for c in t:
+        phi = phi * (A @ _elementary_weights(c, A))
+    return phi
+
+
+def _extended(orc, Nt):
+    """The Lobatto IIIC tableau of Appendix B with an explicit stage at c = 0
+    in front (its row of the matrix is zero: its value is u^n), and the
+    weights of u^{n+1} and of the embedded formula on the extended stages."""
+    A, b, c, gamma0, bh = orc.embedded_weights(Nt)
+    Ax = np.zeros((Nt + 1, Nt + 1))
+    Ax[1:, 1:] = A
+    return Ax, np.concatenate([[0.0], b]), np.concatenate([[gamma0], bh])
+
+
+def _order_by_trees(Ax, w, top=7):
+    """Largest p such that w satisfies every order condition of the trees
+    with at most p vertices."""
+    for q in range(1, top + 1):
+        for t in _rooted_trees(q):
+            if abs(w @ _elementary_weights(t, Ax) - 1.0 / _tree_density(t)) > 1e-12:
+                return q - 1
+    return top
+
+
+def test_rooted_tree_counts():
+    """1, 1, 2, 4, 9, 20, 48 rooted trees with 1..7 vertices (OEIS A000081)."""
+    assert [len(_rooted_trees(q)) for q in range(1, 8)] == [1, 1, 2, 4, 9, 20, 48]
+
+
 @pytest.mark.parametrize("Nt", [2, 3, 4])
-def test_embedded_weights_order(orc, Nt):
-    """b_hat integrates polynomials up to degree Nt - 2 exactly on [0, 1]
-    (Nt = 2: the left rectangle rule, Nt = 3: the midpoint rule), has
-    b_hat_Nt = 0, and is not exact for degree Nt - 1 (so it differs from b)."""
-    A, b, bh, c = orc.embedded_weights(Nt)
-    for q in range(Nt - 1):
-        assert abs(sum(bh[l] * c[l] ** q for l in range(Nt)) - 1.0 / (q + 1)) < 1e-14
-    assert bh[-1] == 0.0
-    assert abs(sum(bh[l] * c[l] ** (Nt - 1) for l in range(Nt)) - 1.0 / Nt) > 1e-3
-    if Nt == 2:
-        assert np.allclose(bh, [1.0, 0.0], atol=1e-15)
-    if Nt == 3:
-        assert np.allclose(bh, [0.0, 1.0, 0.0], atol=1e-15)
+def test_embedded_order_by_trees(orc, Nt):
+    """By the order conditions of all rooted trees (Butcher): u^{n+1} has
+    order 2 Nt - 2 (the paper's order of Lobatto IIIC), the embedded formula
+    one order less for Nt = 2, 3 and order Nt = 4 for Nt = 4."""
+    Ax, b, bh = _extended(orc, Nt)
+    assert _order_by_trees(Ax, b) == 2 * Nt - 2
+    assert _order_by_trees(Ax, bh) == orc.EMBEDDED_ORDER[Nt]
+    assert orc.EMBEDDED_ORDER[Nt] == (2 * Nt - 3 if Nt < 4 else 4)
+
+
+def test_no_order_five_embedding_for_four_stages(orc):
+    """Nt = 4: the order conditions up to order 5, as linear equations in
+    the weights (gamma_0, b_hat) on F(u^n) and the four stage derivatives,
+    have the single solution (0, b): no embedded formula of this kind has
+    order 2 Nt - 3 = 5, so order 4 is the highest one below 2 Nt - 2."""
+    Ax, b, _ = _extended(orc, 4)
+    rows, rhs = [], []
+    for q in range(1, 6):
+        for t in _rooted_trees(q):
+            rows.append(_elementary_weights(t, Ax))
+            rhs.append(1.0 / _tree_density(t))
+    M, r = np.array(rows), np.array(rhs)
+    assert np.linalg.matrix_rank(M, tol=1e-10) == 5
+    x = np.linalg.lstsq(M, r, rcond=None)[0]
+    assert np.allclose(x, b, atol=1e-12)
+    assert np.abs(M @ x - r).max() < 1e-12
 
 
 @pytest.mark.parametrize("Nt", [2, 3, 4])
 def test_error_estimate_linear_test_equation(orc, Nt):
-    """y' = -y on one element (the reaction term, no transport): the slab's
-    estimate equals the closed form h lambda (b - b_hat) . Y with the stages
-    Y = (I - h lambda A)^-1 1 y0, and falls like h^Nt (local error of an
-    order Nt - 1 embedding)."""
+    """y' = lambda y on one element (the reaction term, no transport): the
+    slab's estimate equals the closed form
+    h lambda ((b - b_hat) . Y - gamma_0 y0) with the stages
+    Y = (I - h lambda A)^-1 1 y0, and falls like h^(p+1) with p the embedded
+    order: h^2, h^4 (= h^(2 Nt - 2) for Nt = 2, 3) and h^5 (Nt = 4)."""
     lam, y0 = -1.0, 2.0
-    A, b, bh, _ = orc.embedded_weights(Nt)
+    A, b, _, gamma0, bh = orc.embedded_weights(Nt)
     ests = []
-    for h in (0.2, 0.1, 0.05):
+    hs = (0.1, 0.05, 0.025)
+    for h in hs:
         p = orc.problem(1, [1], [0], [1], 1, Nt, orc.ADVECTION, a=(0.0,), react=lam)
         up = np.full(2, y0)
         U, st = orc.solve(p, up, h, tol=1e-15)
         err, e = orc.error_estimate(p, U, up, h, atol=1.0, rtol=0.0)
         Y = np.linalg.solve(np.eye(Nt) - h * lam * A, np.ones(Nt)) * y0
-        closed = h * lam * float(np.dot(b - bh, Y))
-        assert np.allclose(e, closed, rtol=1e-11, atol=1e-15), (Nt, h, e, closed)
+        closed = h * lam * (float(np.dot(b - bh, Y)) - gamma0 * y0)
+        assert np.allclose(e, closed, rtol=1e-9, atol=1e-15), (Nt, h, e, closed)
         ests.append(abs(closed))
+    want = orc.EMBEDDED_ORDER[Nt] + 1
     for e1, e2 in zip(ests, ests[1:]):
-        assert abs(math.log2(e1 / e2) - Nt) < 0.15, (Nt, ests)
+        assert abs(math.log2(e1 / e2) - want) < 0.15, (Nt, ests)
+    if Nt < 4:
+        assert want == 2 * Nt - 2
 
 
-def test_error_estimate_matches_stage_fluxes(orc):
+@pytest.mark.parametrize("Nt", [2, 3, 4])
+def test_error_estimate_matches_stage_fluxes(orc, Nt):
     """On a solved PDE slab the estimate, formed from the stage values through
-    A^-1, equals u^{Nt} - (u^n + dt sum_l b_hat_l F(U_l)) with F the oracle's
-    spatial operator evaluated at every stage."""
-    p = orc.problem(1, [8], [0], [1], 3, 3, orc.ADVDIFF_BR1, a=(1.0,), nu=0.01)
+    A^-1, equals u^{Nt} - (u^n + dt (gamma_0 F(u^n) + sum_l b_hat_l F(U_l)))
+    with F the oracle's spatial operator evaluated at u^n and at every stage."""
+    p = orc.problem(1, [8], [0], [1], 3, Nt, orc.ADVDIFF_BR1, a=(1.0,), nu=0.01)
     X = orc.node_coords(p)
     up = np.sin(2 * np.pi * X[:, 0, :]).ravel()
     dt = 0.02
     U, st = orc.solve(p, up, dt, tol=1e-15)
     _, e = orc.error_estimate(p, U, up, dt, atol=1.0, rtol=0.0)
-    _, _, bh, _ = orc.embedded_weights(3)
-    Us = U.reshape(8, 1, 3, 4)
-    uh = up.reshape(8, 1, 4).copy()
-    for l in range(3):
+    _, _, _, gamma0, bh = orc.embedded_weights(Nt)
+    Us = U.reshape(8, 1, Nt, 4)
+    uh = up.reshape(8, 1, 4) + dt * gamma0 * orc.spatial_op(p, up).reshape(8, 1, 4)
+    for l in range(Nt):
         F = orc.spatial_op(p, np.ascontiguousarray(Us[:, :, l, :]).ravel()).reshape(8, 1, 4)
         uh += dt * bh[l] * F
     direct = (Us[:, :, -1, :] - uh).ravel()
     assert np.abs(e - direct).max() <= 1e-11 * np.abs(up).max()
-    assert np.abs(e).max() > 1e-8            # a real estimate, not round-off
+    assert np.abs(e).max() > 1e-9            # a real estimate, not round-off
 
 
-@pytest.mark.parametrize("Nt", [2, 3, 4])
-def test_error_estimate_is_inflow_jump(orc, Nt):
-    """With this embedding b - b_hat is +-(first row of A) (both annihilate the
-    moments c^q, q <= Nt - 2, since A satisfies C(Nt - 1) with c_1 = 0), so the
-    first stage equation turns the estimate into +-(U_1 - u^n) for any slab
+def test_error_estimate_two_stages_is_inflow_jump(orc):
+    """Nt = 2: b - b_hat = (-1/2, 1/2) is minus the first row of A, so the
+    first stage equation turns the estimate into -(U_1 - u^n) for any slab
     values, solved or not."""
-    A, b, bh, c = orc.embedded_weights(Nt)
-    s = float(np.sign(np.dot(b - bh, A[0])))
-    assert np.allclose(b - bh, s * A[0], atol=1e-15)
-    p = orc.problem(2, [3, 2], [0, 0], [1, 1], 2, Nt, orc.EULER)
-    rng = np.random.default_rng(Nt)
+    A, b, _, gamma0, bh = orc.embedded_weights(2)
+    assert gamma0 == 0.0 and np.allclose(b - bh, -A[0], atol=1e-15)
+    p = orc.problem(2, [3, 2], [0, 0], [1, 1], 2, 2, orc.EULER)
+    rng = np.random.default_rng(2)
     n, nsp = orc.slab_size(p), orc.space_size(p)
     U = 1.0 + 0.1 * rng.standard_normal(n)
     up = 1.0 + 0.1 * rng.standard_normal(nsp)
     _, e = orc.error_estimate(p, U, up, 0.1, atol=1.0, rtol=0.0)
-    U1 = U.reshape(6, 4, Nt, 9)[:, :, 0, :].ravel()
-    assert np.abs(e - s * (U1 - up)).max() < 1e-13
+    U1 = U.reshape(6, 4, 2, 9)[:, :, 0, :].ravel()
+    assert np.abs(e + (U1 - up)).max() < 1e-13
+
+
+@pytest.mark.parametrize("Nt", [3, 4])
+def test_error_estimate_is_first_stage_flux_difference(orc, Nt):
+    """Nt > 2: b - b_hat = b_1 e_1 and gamma_0 = b_1, so at a solved slab the
+    estimate is b_1 dt (F(U_1) - F(u^n)) -- with the first stage's derivative
+    from the spatial operator rather than from the stage equations."""
+    p = orc.problem(2, [4, 4], [-5, -5], [5, 5], 3, Nt, orc.EULER)
+    X = orc.node_coords(p)
+    up = inputs.isentropic_vortex(X, seed=3).ravel()
+    dt = 0.05
+    U, st = orc.solve(p, up, dt, tol=1e-13, dense_limit=4000)
+    assert st["converged"], st
+    _, b, _, _, _ = orc.embedded_weights(Nt)
+    nv, ns, E = 4, 16, 16
+    U1 = np.ascontiguousarray(U.reshape(E, nv, Nt, ns)[:, :, 0, :]).ravel()
+    direct = b[0] * dt * (orc.spatial_op(p, U1) - orc.spatial_op(p, up))
+    _, e = orc.error_estimate(p, U, up, dt, atol=1.0, rtol=0.0)
+    assert np.abs(e - direct).max() <= 1e-9 * np.abs(direct).max()
+    assert np.abs(direct).max() > 1e-8
