@@ -289,7 +289,11 @@ def error_estimate(p, U, uprev, dt, atol, rtol):
     _, b, _, gamma0, bh = embedded_weights(p.Nt)
     un = np.asarray(uprev, dtype=np.float64).reshape(-1, nv, ns)
     hK = stage_derivatives(p, U, uprev)
-    u1 = un + np.einsum("l,evls->evs", b, hK)
+    # u^{n+1} for the scale: the slab's last time node (eq. un); Lobatto IIIC
+    # is stiffly accurate, so it equals u^n + dt sum_l b_l K_l -- up to
+    # rounding, which a pure relative scale (atol = 0) magnifies where the
+    # state crosses zero
+    u1 = last_time_node(p, U).reshape(un.shape)
     e = np.einsum("l,evls->evs", b - bh, hK)
     if gamma0 != 0.0:
         e = e - gamma0 * dt * spatial_op(p, un.ravel()).reshape(un.shape)
