@@ -221,25 +221,35 @@ int st_solve_slabs(st_handle_t h, int M, const double* u_prev, double t0, double
 
 /* Local error estimate of a solved slab by an embedded solution (Sec.
  * "Algorithmic Aspects", adaptive time-stepping; eqs. (RK_stage_equations),
- * (RK_solution), with the tableau of eq. (SBP_to_RK)).  The stage derivatives
- * follow from the stage values, dt K = (A^-1 (x) I)(U - 1 (x) u_prev); the
- * embedded solution uses weights b_hat, the interpolatory quadrature on [0, 1]
- * through the first Nt - 1 stage nodes (order Nt - 1; the paper names the
- * technique and leaves b_hat open), so e = u^{n+1} - u_hat^{n+1} =
- * dt sum_l (b_l - b_hat_l) K_l.  For this b_hat, b - b_hat is (up to sign) the
- * first row of A, and the first stage equation makes e = +-(U_1 - u_prev): the
- * jump of the slab solution at its inflow time, which is what the kernel
- * forms.  *err (host) = sqrt(mean over the n_space
- * values of (e / (atol + rtol max(|u_prev|, |u^{n+1}|)))^2).  U: device, slab
- * layout; u_prev: device, spatial layout.  atol, rtol >= 0, atol + rtol > 0,
+ * (RK_solution), with the tableau of eq. (SBP_to_RK)).  The embedded solution
+ * is one order below u^{n+1} where that is reachable, built as in the Radau
+ * IIA strategy the paper cites: besides the stage derivatives K_l it may use
+ * F(u_prev), the spatial operator at the known start value,
+ *   u_hat = u_prev + dt (gamma_0 F(u_prev) + sum_l b_hat_l K_l),
+ * with (gamma_0, b_hat) = (0; 1, 0) for Nt = 2 (order 1) and
+ * (b_1; 0, b_2, .., b_Nt) for Nt = 3, 4 (order 3 and 4; no formula of this
+ * kind has order 5 for Nt = 4).  The stage derivatives follow from the stage
+ * values, dt K = (A^-1 (x) I)(U - 1 (x) u_prev) with
+ * A^-1 = 2 (D_tau + M_tau^-1 e_1 e_1^T) (eq. SBP_to_RK), so
+ *   Nt = 2:  e = u^{n+1} - u_hat = -(U_1 - u_prev),
+ *   Nt > 2:  e = w_1 (D_tau (U - 1 (x) u_prev))_1 + (U_1 - u_prev)
+ *                - (w_1 dt / 2) F(u_prev)                    (w_1 = 2 b_1),
+ * which at a solved slab is b_1 dt (F(U_1) - F(u_prev)).  F(u_prev) is one
+ * evaluation of the slab operator at 1 (x) u_prev with the time terms off.
+ * *err (host) = sqrt(mean over the n_space values of
+ * (e / (atol + rtol max(|u_prev|, |u^{n+1}|)))^2).  U: device, slab layout;
+ * u_prev: device, spatial layout; dt > 0 the slab's step (t0 is accepted;
+ * every supported equation is autonomous).  atol, rtol >= 0, atol + rtol > 0,
  * else ST_ERR_BAD_ARG.  Synchronises `stream` (the value is copied to the
- * host); the first call allocates about 4 KB of device memory. */
-int st_error_estimate(st_handle_t h, const double* U, const double* u_prev, double atol, double rtol,
-                      double* err, void* stream);
+ * host); the first call allocates about 4 KB of device memory, and for
+ * Nt > 2 two slab vectors (kept by the handle). */
+int st_error_estimate(st_handle_t h, const double* U, const double* u_prev, double t0, double dt, double atol,
+                      double rtol, double* err, void* stream);
 
-/* Host only: the next step size of an embedded pair whose local error scales
- * like dt^Nt: dt_next = dt min(5, max(0.2, 0.9 err^(-1/Nt))) (5 when err = 0);
- * a step is accepted when err <= 1.  Nt in 2..4, dt > 0, err >= 0, else
+/* Host only: the next step size of the embedded pair above, whose estimate
+ * scales like dt^(q+1) with q = 1, 3, 4 the embedded order for Nt = 2, 3, 4:
+ * dt_next = dt min(5, max(0.2, 0.9 err^(-1/(q+1)))) (5 when err = 0); a step
+ * is accepted when err <= 1.  Nt in 2..4, dt > 0, err >= 0, else
  * ST_ERR_BAD_ARG.  No GPU needed. */
 int st_next_dt(int Nt, double dt, double err, double* dt_next);
 

@@ -311,10 +311,14 @@ struct st_ctx {
     // was assembled for, the preconditioned direction z, 2 descriptor slots
     double* binvT = nullptr;
     double pc_dt = 0.0;
+    std::vector<double> pc_ubar;   // nonlinear: the mean state it was assembled at
     double* pz = nullptr;
     PcSeg* d_pc = nullptr;
-    // embedded error estimate: partial sums + result
+    // embedded error estimate: partial sums + result; for Nt > 2 the state
+    // 1 (x) u_prev and the spatial operator at it (slab vectors)
     double* d_est = nullptr;
+    double* est_u0 = nullptr;
+    double* est_f = nullptr;
     // vector buffers (V, w, R, U, pz, Q, dQ, U32, dQ32, d_part) hold `cap`
     // consecutive slabs; the solve's descriptors: 4 cap operator segments
     // (residual viscous pass, residual, JVP viscous pass, JVP) and cap + 2
@@ -489,15 +493,53 @@ static bool invert_dense(std::vector<double>& A, int n) {
 // in every element.  Nonlinear equations: the Jacobian at the constant state
 // u_bar, the quadrature-weighted mean of u_prev (the mean of the conserved
 // variables, which the scheme conserves on the periodic mesh, so every slab
-// of a run has the same u_bar); a frozen-coefficient approximation of every
-// element's block.
+// of a run has the same u_bar up to round-off); a frozen-coefficient
+// approximation of every element's block.  The inverse is kept per handle
+// for its dt (and u_bar), and rebuilt when either changes.
 static int ensure_precond(st_ctx* h, const double* u_prev, double dt, hipStream_t st) {
     const Problem& pb = h->pb;
     const bool lin = linear_eq(pb.eq.kind);
     const int npe = (int)(pb.nv * pb.Nt * pb.ns);
     if (npe > PC_NPE_MAX) return set_error(ST_ERR_UNSUPPORTED, "element block larger than the preconditioner supports");
     if (!h->pz) CHK(h->alloc(&h->pz, (size_t)pb.n * h->cap));
-    if (h->binvT && h->pc_dt == dt) return ST_OK;
+    const int d = pb.mesh.dim;
+    // nonlinear: the reference state u_bar, the quadrature-weighted mean of
+    // u_prev (the block is rebuilt when it moves beyond round-off)
+    std::vector<double> ubar;
+    if (!lin) {
+        const int64_t nprev = pb.E * pb.nv * pb.ns;
+        std::vector<double> up((size_t)nprev);
+        HIPCHK(hipMemcpyAsync(up.data(), u_prev, sizeof(double) * nprev, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        std::vector<double> W(pb.ns);
+        for (int sn = 0; sn < pb.ns; ++sn) {
+            W[sn] = 1.0;
+            for (int a = 0, q = sn; a < d; ++a, q /= pb.n1) W[sn] *= pb.wx[q % pb.n1];
+        }
+        ubar.assign(pb.nv, 0.0);
+        std::vector<double> amax(pb.nv, 0.0);
+        double wsum = 0.0;
+        for (int sn = 0; sn < pb.ns; ++sn) wsum += W[sn];
+        for (int64_t e = 0; e < pb.E; ++e)
+            for (int v = 0; v < pb.nv; ++v) {
+                const double* ue = up.data() + (e * pb.nv + v) * pb.ns;
+                double t = 0.0;
+                for (int sn = 0; sn < pb.ns; ++sn) {
+                    t += W[sn] * ue[sn];
+                    amax[v] = std::max(amax[v], std::fabs(ue[sn]));
+                }
+                ubar[v] += t;
+            }
+        bool same = h->binvT && h->pc_dt == dt && (int)h->pc_ubar.size() == pb.nv;
+        for (int v = 0; v < pb.nv; ++v) {
+            ubar[v] /= wsum * (double)pb.E;
+            if (!std::isfinite(ubar[v])) return set_error(ST_ERR_BAD_ARG, "preconditioner setup: u_prev is not finite");
+            if (same && std::fabs(ubar[v] - h->pc_ubar[v]) > 1e-12 * std::max(amax[v], 1e-300)) same = false;
+        }
+        if (same) return ST_OK;
+    } else if (h->binvT && h->pc_dt == dt) {
+        return ST_OK;
+    }
     if (pc_prepare(npe) != hipSuccess)
         return set_error(ST_ERR_UNSUPPORTED, "element block needs more LDS than the device grants");
     st_mesh_t m3 = pb.mesh;
@@ -510,7 +552,6 @@ static int ensure_precond(st_ctx* h, const double* u_prev, double dt, hipStream_
     CHK(make_problem(&m3, pb.N, pb.Nt, &pb.eq, pp));
     const int Gp = op_blocks(pp);
     const int64_t np = pp.n;
-    const int d = pb.mesh.dim;
     const bool visc = grad_pass(pb);
     double *din = nullptr, *dout = nullptr, *dstate = nullptr, *dq = nullptr;
     OpSeg* dsegs = nullptr;
@@ -524,29 +565,6 @@ static int ensure_precond(st_ctx* h, const double* u_prev, double dt, hipStream_
     // nonlinear: the reference state u_bar at every node of the probe mesh
     std::vector<double> ref;
     if (!lin) {
-        const int64_t nprev = pb.E * pb.nv * pb.ns;
-        std::vector<double> up((size_t)nprev);
-        HIPCHK(hipMemcpyAsync(up.data(), u_prev, sizeof(double) * nprev, hipMemcpyDeviceToHost, st));
-        HIPCHK(hipStreamSynchronize(st));
-        std::vector<double> W(pb.ns);
-        for (int sn = 0; sn < pb.ns; ++sn) {
-            W[sn] = 1.0;
-            for (int a = 0, q = sn; a < d; ++a, q /= pb.n1) W[sn] *= pb.wx[q % pb.n1];
-        }
-        std::vector<double> ubar(pb.nv, 0.0);
-        double wsum = 0.0;
-        for (int sn = 0; sn < pb.ns; ++sn) wsum += W[sn];
-        for (int64_t e = 0; e < pb.E; ++e)
-            for (int v = 0; v < pb.nv; ++v) {
-                const double* ue = up.data() + (e * pb.nv + v) * pb.ns;
-                double t = 0.0;
-                for (int sn = 0; sn < pb.ns; ++sn) t += W[sn] * ue[sn];
-                ubar[v] += t;
-            }
-        for (int v = 0; v < pb.nv; ++v) {
-            ubar[v] /= wsum * (double)pb.E;
-            if (!std::isfinite(ubar[v])) return set_error(ST_ERR_BAD_ARG, "preconditioner setup: u_prev is not finite");
-        }
         ref.resize((size_t)np);
         const int epe = pb.nv * pb.Nt * pb.ns;   // values of one element, [v][j][s]
         for (int64_t i = 0; i < np; ++i) ref[(size_t)i] = ubar[(i % epe) / (pb.Nt * pb.ns)];
@@ -621,12 +639,13 @@ static int ensure_precond(st_ctx* h, const double* u_prev, double dt, hipStream_
     }
     HIPCHK(hipMemcpy(h->binvT, packed.data(), sizeof(double) * packed.size(), hipMemcpyHostToDevice));
     h->pc_dt = dt;
+    h->pc_ubar = ubar;
     return ST_OK;
 }
 
 namespace stdg {
 void setup_residual(st_ctx* h, int M, const double* U, const double* u_prev, double* R, double dt, OpSeg* dv,
-                    OpSeg* dop, hipStream_t st);
+                    OpSeg* dop, hipStream_t st, bool time_terms = true);
 CoupleArgs couple_args(const Problem& pb, int M, const double* in0, const int* kp, int64_t ld, double* out,
                        const int* skip);
 void launch_residual(st_ctx* h, int M, const OpSeg* dv, const OpSeg* dop, const CoupleArgs& cp, hipStream_t st);
@@ -747,12 +766,15 @@ static void put_slab_segs(OpSeg* dst, int M, const OpSeg& proto, hipStream_t st,
 // Residual of M consecutive slabs at U, in two halves: upload the
 // descriptors (viscous pass to dv[0..M), operator to dop[0..M)) and launch.
 // Slab 0 takes u_prev as inflow, the others none: the coupling kernel adds
-// theirs.
+// theirs.  time_terms = false zeroes D_tau in the descriptor: the kernels then
+// return w_j (dt/2) F(U_j) - delta_j1 (U_1 - u_prev), the spatial operator at
+// every time node (exactly, where U_1 = u_prev).
 void setup_residual(st_ctx* h, int M, const double* U, const double* u_prev, double* R, double dt, OpSeg* dv,
-                    OpSeg* dop, hipStream_t st) {
+                    OpSeg* dop, hipStream_t st, bool time_terms) {
     const Problem& pb = h->pb;
     const int64_t n = pb.n, nq = pb.n * pb.mesh.dim;
-    const OpSeg base = base_opseg(pb, dt);
+    OpSeg base = base_opseg(pb, dt);
+    if (!time_terms) std::memset(base.Dt, 0, sizeof(base.Dt));
     if (grad_pass(pb)) {
         OpSeg g = base;
         visc_tiles(g, pb);
@@ -894,15 +916,43 @@ int st_jvp_slabs(st_handle_t h, int M, const double* U, double t0, double dt, co
     return ST_OK;
 }
 
-int st_error_estimate(st_handle_t h, const double* U, const double* u_prev, double atol, double rtol, double* err,
-                      void* stream) {
+int st_error_estimate(st_handle_t h, const double* U, const double* u_prev, double t0, double dt, double atol,
+                      double rtol, double* err, void* stream) {
+    (void)t0;
     if (!h || !U || !u_prev || !err) return set_error(ST_ERR_BAD_ARG, "st_error_estimate: null argument");
+    if (!(dt > 0.0) || !std::isfinite(dt)) return set_error(ST_ERR_BAD_ARG, "st_error_estimate: dt must be positive");
     if (!(atol >= 0.0) || !(rtol >= 0.0) || !(atol + rtol > 0.0))
         return set_error(ST_ERR_BAD_ARG, "st_error_estimate: need atol, rtol >= 0 and atol + rtol > 0");
     const Problem& pb = h->pb;
     hipStream_t st = (hipStream_t)stream;
     if (!h->d_est) CHK(h->alloc(&h->d_est, (size_t)VMAXBLK + 1));
     EstArgs a;
+    std::memset(&a, 0, sizeof(a));
+    if (pb.Nt > 2) {
+        // (w_1 dt / 2) F(u_prev) at the first time node of est_f: the slab
+        // operator at U0 = 1 (x) u_prev with the time terms off
+        if (!h->est_u0) {
+            CHK(h->alloc(&h->est_u0, (size_t)pb.n));
+            CHK(h->alloc(&h->est_f, (size_t)pb.n));
+        }
+        VecSeg v;
+        std::memset(&v, 0, sizeof(v));
+        v.U = h->est_u0;
+        v.uprev = u_prev;
+        v.n = pb.n;
+        v.nt = pb.Nt;
+        v.ns = pb.ns;
+        v.nblk = vec_blocks(v.n);
+        v.st = h->d_st;
+        put_vecseg(h->d_vs, v, st);
+        vk_init_guess(h->d_vs, 1, v.nblk, st);
+        setup_residual(h, 1, h->est_u0, u_prev, h->est_f, dt, h->d_op + 0, h->d_op + 1, st, false);
+        h->timer.reset(0);
+        launch_residual(h, 1, h->d_op + 0, h->d_op + 1, couple_args(pb, 1, h->est_u0, nullptr, 0, h->est_f, nullptr),
+                        st);
+        for (int j = 0; j < pb.Nt; ++j) a.c[j] = pb.wt[0] * pb.Dt[j];   // w_1 D_tau[0][j]
+        a.fs = h->est_f;
+    }
     a.U = U;
     a.up = u_prev;
     a.part = h->d_est + 1;
@@ -922,11 +972,12 @@ int st_error_estimate(st_handle_t h, const double* U, const double* u_prev, doub
 int st_next_dt(int Nt, double dt, double err, double* dt_next) {
     if (!dt_next || Nt < 2 || Nt > 4 || !(dt > 0.0) || !(err >= 0.0))
         return set_error(ST_ERR_BAD_ARG, "st_next_dt: need Nt in 2..4, dt > 0, err >= 0 and an output");
-    // step-size control of an embedded pair (the estimate is of order Nt - 1,
-    // so the local error scales like dt^Nt): safety factor 0.9, growth in
-    // [0.2, 5]
+    // step-size control of the embedded pair of st_error_estimate: its
+    // estimate is of the embedded order q (1, 3, 4 for Nt = 2, 3, 4), so it
+    // scales like dt^(q+1); safety factor 0.9, growth in [0.2, 5]
     constexpr double fac = 0.9, facmin = 0.2, facmax = 5.0;
-    double f = err > 0.0 ? fac * std::pow(1.0 / err, 1.0 / Nt) : facmax;
+    const int q = Nt == 2 ? 1 : Nt;
+    double f = err > 0.0 ? fac * std::pow(1.0 / err, 1.0 / (q + 1)) : facmax;
     if (!std::isfinite(f)) f = facmin;
     f = std::min(facmax, std::max(facmin, f));
     *dt_next = dt * f;

@@ -570,21 +570,21 @@ __global__ __launch_bounds__(VBLOCK) void k_cast32(const VecSeg* __restrict__ se
 }
 
 // Embedded error estimate (Sec. "Algorithmic Aspects", adaptive time-stepping;
-// eqs. RK_stage_equations, RK_solution).  With the embedded weights b_hat of
-// the interpolatory quadrature through the first Nt - 1 stage nodes, b - b_hat
-// is (up to sign) the first row of the Lobatto IIIC matrix A: both sum the
-// moments c^q, q <= Nt - 2, to zero (A satisfies the simplifying condition
-// C(Nt - 1) and c_1 = 0), and for Nt = 2, 3, 4 their last entries agree in
-// magnitude.  The
-// first stage equation, U_1 = u^n + dt sum_j a_1j K_j, then gives
-// u^{n+1} - u_hat^{n+1} = +-(U_1 - u^n): the estimate is the jump of the slab
-// solution at its inflow time, formed here without cancellation.  Partial
-// sums of its squared scaled values per block.
+// eqs. RK_stage_equations, RK_solution, SBP_to_RK).  The embedded solution
+// u_hat = u^n + dt (gamma_0 F(u^n) + sum_l b_hat_l K_l) has
+//   Nt = 2: gamma_0 = 0, b_hat = (1, 0): b - b_hat is minus the first row of
+//           A, so the first stage equation gives e = -(U_1 - u^n);
+//   Nt > 2: gamma_0 = b_1, b_hat = (0, b_2, ..): e = b_1 dt (K_1 - F(u^n)),
+//           with b_1 dt K_1 = w_1 (D_tau (U - 1 u^n))_1 + (U_1 - u^n) from
+//           A^-1 = 2 (D_tau + M_tau^-1 e_1 e_1^T), and b_1 dt F(u^n) the first
+//           time node of fs.
+// Partial sums of the squared scaled values per block.
 __global__ __launch_bounds__(VBLOCK) void k_errest(EstArgs a) {
     __shared__ double smem[VWAVES];
     __shared__ double s_out[1];
     const auto* __restrict__ U = gl(a.U);
     const auto* __restrict__ up = gl(a.up);
+    const auto* __restrict__ fs = gl(a.fs);
     double acc[1] = {0.0};
     const int64_t stride = (int64_t)a.nblk * VBLOCK;
     const bool narrow = a.nsp <= 0xffffffffLL;     // 32-bit division suffices
@@ -595,8 +595,16 @@ __global__ __launch_bounds__(VBLOCK) void k_errest(EstArgs a) {
         const double u1 = U[base];                               // first time node
         const double uN = U[base + (int64_t)(a.nt - 1) * a.ns];  // u^{n+1}
         const double un = up[i];
+        double e;
+        if (a.nt == 2) {
+            e = un - u1;
+        } else {
+            double k1 = a.c[0] * (u1 - un);
+            for (int j = 1; j < a.nt; ++j) k1 += a.c[j] * (U[base + (int64_t)j * a.ns] - un);
+            e = (k1 + (u1 - un)) - fs[base];
+        }
         const double sc = a.atol + a.rtol * fmax(fabs(un), fabs(uN));
-        const double r = (u1 - un) / sc;
+        const double r = e / sc;
         acc[0] += r * r;
     }
     block_sums<1>(acc, smem, s_out);

@@ -21,16 +21,21 @@ void vk_init_guess(const VecSeg* s, int nseg, int G, hipStream_t st);
 void vk_extract_last(const VecSeg* s, int nseg, int G, hipStream_t st);
 void vk_cast32(const VecSeg* s, int nseg, int G, hipStream_t st);
 // embedded error estimate of a solved slab: err = rms over the nsp spatial
-// values of e / (atol + rtol max(|u^n|, |u^{n+1}|)) with e = U_1 - u^n;
-// part: nblk partial sums, out: the estimate (device)
+// values of e / (atol + rtol max(|u^n|, |u^{n+1}|)) with
+//   nt = 2: e = -(U_1 - u^n)
+//   nt > 2: e = sum_j c_j (U_j - u^n) + (U_1 - u^n) - fs_1
+// (c_j = w_1 D_tau[0][j]; fs: slab vector whose first time node holds
+// (w_1 dt / 2) F(u^n)); part: nblk partial sums, out: the estimate (device)
 struct EstArgs {
     const double* U;
     const double* up;
+    const double* fs;
     double* part;
     double* out;
     int64_t nsp;          // E nv ns spatial values
     int nt, ns, nblk;
     double atol, rtol;
+    double c[4];
 };
 void vk_error_estimate(const EstArgs& a, hipStream_t st);
 // Coupling of consecutive slabs of a multi-slab system: slab m >= 1 takes

@@ -470,6 +470,16 @@ bool tick(st_srv* s) {
     for (Req* r : cont) vc.push_back(vecseg_of(s, r));
     const int Gc = assign_blocks(vc);
     const int64_t off_vc = pb.add(vc);
+    // the Gram-Schmidt launches by pass count (1: CGS, 2: CGS2), so that a
+    // request gets its own number of passes whatever it is batched with
+    std::vector<VecSeg> vp[2];
+    for (Req* r : cont) vp[r->opts.cgs_passes - 1].push_back(vecseg_of(s, r));
+    int Gp[2];
+    int64_t off_vp[2];
+    for (int q = 0; q < 2; ++q) {
+        Gp[q] = assign_blocks(vp[q]);
+        off_vp[q] = pb.add(vp[q]);
+    }
     std::vector<Req*> c32;
     for (Req* r : cont)
         if (r->fp32() && !linear_eq(r->pb.eq.kind)) c32.push_back(r);
@@ -487,8 +497,8 @@ bool tick(st_srv* s) {
     if (!v32.empty()) vk_cast32((VecSeg*)(D1 + off_v32), (int)v32.size(), G32, st);
     VecSeg* dvc = (VecSeg*)(D1 + off_vc);
     const int nc = (int)vc.size();
-    int mmax = 0, passes = 1;
-    for (Req* r : cont) { mmax = std::max(mmax, r->opts.restart); passes = std::max(passes, r->opts.cgs_passes); }
+    int mmax = 0;
+    for (Req* r : cont) mmax = std::max(mmax, r->opts.restart);
     vk_scale_v0(dvc, nc, Gc, st);
     for (int k = 0; k < mmax; ++k) {
         for (auto& g : jgroups) {
@@ -498,9 +508,14 @@ bool tick(st_srv* s) {
                                               : (g.fp32 ? g.ops->jvp32 : g.ops->jvp64);
             f((OpSeg*)(D1 + g.off_op), (int)g.op.size(), g.G, st);
         }
-        for (int p = 0; p < passes; ++p) {
-            vk_multidot(dvc, nc, Gc, k, st);
-            vk_update(dvc, nc, Gc, p, p == passes - 1, k, st);
+        for (int q = 0; q < 2; ++q) {
+            if (vp[q].empty()) continue;
+            VecSeg* dq = (VecSeg*)(D1 + off_vp[q]);
+            const int nq = (int)vp[q].size();
+            for (int p = 0; p <= q; ++p) {
+                vk_multidot(dq, nq, Gp[q], k, st);
+                vk_update(dq, nq, Gp[q], p, p == q, k, st);
+            }
         }
     }
     vk_finish(dvc, nc, st);

@@ -106,7 +106,8 @@ _SIGS = [
                                       ctypes.c_double, ctypes.c_double, ctypes.POINTER(SolverOpts),
                                       ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(Stats), ctypes.c_void_p]),
     ("st_error_estimate", ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double,
-                                         ctypes.c_double, _c_double_p, ctypes.c_void_p]),
+                                         ctypes.c_double, ctypes.c_double, ctypes.c_double, _c_double_p,
+                                         ctypes.c_void_p]),
     ("st_next_dt", ctypes.c_int, [ctypes.c_int, ctypes.c_double, ctypes.c_double, _c_double_p]),
     ("st_server_create", ctypes.c_int, [ctypes.POINTER(ServerOpts), ctypes.POINTER(ctypes.c_void_p)]),
     ("st_server_destroy", ctypes.c_int, [ctypes.c_void_p]),
@@ -255,10 +256,10 @@ def st_jvp_slabs(h, M, U, t0, dt, v, Jv, inner_fp32=0, stream=None) -> None:
                               int(inner_fp32), _stream(stream)))
 
 
-def st_error_estimate(h, U, u_prev, atol, rtol, stream=None) -> float:
+def st_error_estimate(h, U, u_prev, t0, dt, atol, rtol, stream=None) -> float:
     err = ctypes.c_double(0.0)
-    _check(lib().st_error_estimate(h, _dev(U, "U"), _dev(u_prev, "u_prev"), float(atol), float(rtol),
-                                   ctypes.byref(err), _stream(stream)))
+    _check(lib().st_error_estimate(h, _dev(U, "U"), _dev(u_prev, "u_prev"), float(t0), float(dt), float(atol),
+                                   float(rtol), ctypes.byref(err), _stream(stream)))
     return err.value
 
 

@@ -153,7 +153,9 @@ def test_next_dt_controller():
     assert abs(st.st_next_dt(3, 0.1, 1.0) - 0.09) < 1e-15               # safety factor at err = 1
     assert abs(st.st_next_dt(3, 0.1, 0.0) - 0.5) < 1e-15                # growth capped at 5
     assert abs(st.st_next_dt(2, 0.1, 1e6) - 0.02) < 1e-15               # shrink capped at 0.2
-    assert abs(st.st_next_dt(4, 0.2, 1.0 / 16) - 0.2 * 0.9 * 2.0) < 1e-14   # err^(-1/Nt)
+    assert abs(st.st_next_dt(4, 0.2, 1.0 / 32) - 0.2 * 0.9 * 2.0) < 1e-14   # err^(-1/5): order 4
+    assert abs(st.st_next_dt(3, 0.2, 1.0 / 16) - 0.2 * 0.9 * 2.0) < 1e-14   # err^(-1/4): order 3
+    assert abs(st.st_next_dt(2, 0.2, 1.0 / 4) - 0.2 * 0.9 * 2.0) < 1e-14    # err^(-1/2): order 1
     for args in ((1, 0.1, 1.0), (5, 0.1, 1.0), (3, 0.0, 1.0), (3, 0.1, -1.0), (3, 0.1, float("nan"))):
         with pytest.raises(st.StError):
             st.st_next_dt(*args)
