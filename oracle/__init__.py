@@ -17,7 +17,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liboracle.so")
 
-ADVECTION, ADVDIFF_BR1, BURGERS, EULER, NS_BR1 = 1, 2, 3, 4, 5
+ADVECTION, ADVDIFF_BR1, BURGERS, EULER, NS_BR1, ADVDIFF_SIPG = 1, 2, 3, 4, 5, 6
 FORM_DG, FORM_RK, FORM_GALERKIN = 0, 1, 2
 
 
@@ -36,6 +36,10 @@ class Problem(ctypes.Structure):
         ("mu", ctypes.c_double),
         ("prandtl", ctypes.c_double),
         ("react", ctypes.c_double),
+        ("omega", ctypes.c_double),
+        ("center", ctypes.c_double * 3),
+        ("bc", ctypes.c_int * 3),
+        ("bc_value", ctypes.c_double),
     ]
 
 
@@ -105,7 +109,10 @@ def nvars(eq: int, dim: int) -> int:
 
 
 def problem(dim, K, lo, hi, N, Nt, eq, a=(0.0, 0.0, 0.0), nu=0.0, gamma=1.4, mu=0.0,
-            prandtl=0.72, react=0.0) -> Problem:
+            prandtl=0.72, react=0.0, omega=0.0, center=(0.0, 0.0, 0.0), bc=(0, 0, 0),
+            bc_value=0.0) -> Problem:
+    """omega, center: the advection velocity a + omega e_z x (x - center) (2D);
+    bc[a]: 0 periodic, 1 Dirichlet with exterior state bc_value."""
     p = Problem()
     p.dim = dim
     for i in range(3):
@@ -113,8 +120,11 @@ def problem(dim, K, lo, hi, N, Nt, eq, a=(0.0, 0.0, 0.0), nu=0.0, gamma=1.4, mu=
         p.lo[i] = float(lo[i]) if i < dim else 0.0
         p.hi[i] = float(hi[i]) if i < dim else 1.0
         p.a[i] = float(a[i]) if i < len(a) else 0.0
+        p.center[i] = float(center[i]) if i < len(center) else 0.0
+        p.bc[i] = int(bc[i]) if i < len(bc) and i < dim else 0
     p.N, p.Nt, p.eq = N, Nt, eq
     p.nu, p.gamma, p.mu, p.prandtl, p.react = nu, gamma, mu, prandtl, react
+    p.omega, p.bc_value = float(omega), float(bc_value)
     return p
 
 

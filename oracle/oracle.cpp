@@ -24,6 +24,20 @@
  *  - Euler pressure p = (gamma-1)(E - |m|^2/(2 rho)) (ideal gas).
  *  - Navier-Stokes: constant mu, Stokes hypothesis, gas constant 1 so that
  *    T = p/rho, heat conductivity kappa = mu gamma / ((gamma-1) Pr).
+ *  - symmetric interior penalty (ORC_ADVDIFF_SIPG; the paper's flux, Sec.
+ *    "DG-SEM in Space", whose printed formula and code are garbled): the
+ *    standard SIPG bilinear form
+ *      a(u, psi) = sum_K int nu grad u . grad psi - sum_F int nu {grad u}.[[psi]]
+ *                - sum_F int nu {grad psi}.[[u]] + sum_F int sigma [[u]].[[psi]],
+ *    [[u]] = n_K u_K + n_N u_N, sigma = eta nu / h_F, eta = 10 p^2 (p the
+ *    spatial degree, 1 for p = 0) and h_F = cell volume / facet area = h_a,
+ *    all integrals by the LGL rule; the spatial operator is M^-1 of minus it.
+ *  - advection velocity b(x) = a + omega e_z x (x - center) (2D rotation); the
+ *    flux b(x_i) u_i is interpolated at the nodes like every other flux.
+ *  - Dirichlet boundaries (bc = 1, scalar equations): exterior state g =
+ *    bc_value; convective flux Rusanov(u, g); BR1 u_hat = g with the interior
+ *    viscous flux; SIPG by Nitsche's terms, the interior-face terms with the
+ *    averages replaced by the interior values and u_N by g.
  */
 #include "oracle.h"
 
@@ -166,7 +180,9 @@ struct Setup {
     int estride[3], nstride[3];
     std::vector<double> xi, wi, D;     // spatial LGL nodes, weights, D[j*n1+k] = l_k'(xi_j)
     std::vector<double> tau, om, Dt;   // temporal LGL nodes, weights, D_tau
-    bool viscous;
+    bool viscous;                      // BR1 lifted gradient (advection-diffusion BR1, NS)
+    bool sipg;                         // symmetric interior penalty viscous terms
+    double eta;                        // SIPG penalty 10 p^2
 
     explicit Setup(const orc_problem* p) {
         P = *p;
@@ -190,12 +206,30 @@ struct Setup {
         for (int j = 0; j < Nt; ++j)
             for (int k = 0; k < Nt; ++k) Dt[j * Nt + k] = lagrange_deriv(tau, k, tau[j]);
         viscous = (p->eq == ORC_ADVDIFF_BR1 || p->eq == ORC_NS_BR1);
+        sipg = p->eq == ORC_ADVDIFF_SIPG;
+        eta = p->N > 0 ? 10.0 * p->N * p->N : 1.0;
     }
     int ecoord(int e, int a) const { return (e / estride[a]) % K[a]; }
+    // element across the face of e along axis a (dir = +-1); -1 on a
+    // Dirichlet boundary
     int neighbor(int e, int a, int dir) const {
         int c = ecoord(e, a);
+        if (P.bc[a] == 1 && (c + dir < 0 || c + dir >= K[a])) return -1;
         int cn = (c + dir + K[a]) % K[a];
         return e + (cn - c) * estride[a];
+    }
+    // physical coordinate a of spatial node s of element e
+    double coord(int e, int s, int a) const {
+        return P.lo[a] + h[a] * (ecoord(e, a) + 0.5 * (1.0 + xi[ncoord(s, a)]));
+    }
+    // advection velocity b_a at node s of element e (scalar equations)
+    double vel(int e, int s, int a) const {
+        double b = P.a[a];
+        if (d == 2 && P.omega != 0.0) {
+            if (a == 0) b -= P.omega * (coord(e, s, 1) - P.center[1]);
+            if (a == 1) b += P.omega * (coord(e, s, 0) - P.center[0]);
+        }
+        return b;
     }
     int ncoord(int s, int a) const { return (s / nstride[a]) % n1; }
     int node_with(int s, int a, int i) const { return s + (i - ncoord(s, a)) * nstride[a]; }
@@ -212,14 +246,16 @@ struct Setup {
 // ---------------------------------------------------------------------------
 // Pointwise physics (eq. (general) with S = react * u).
 // ---------------------------------------------------------------------------
-// Convective flux along axis a.
+// Convective flux along axis a; ba is the advection velocity b_a at the
+// point (scalar linear equations).
 template <class T>
-void conv_flux(const Setup& S, int a, const T* u, T* f) {
+void conv_flux(const Setup& S, int a, const T* u, T* f, double ba) {
     const orc_problem& P = S.P;
     switch (P.eq) {
     case ORC_ADVECTION:
     case ORC_ADVDIFF_BR1:
-        f[0] = P.a[a] * u[0];
+    case ORC_ADVDIFF_SIPG:
+        f[0] = ba * u[0];
         break;
     case ORC_BURGERS:
         f[0] = 0.5 * u[0] * u[0];
@@ -239,14 +275,15 @@ void conv_flux(const Setup& S, int a, const T* u, T* f) {
     }
 }
 
-// Largest wave speed along axis a.
+// Largest wave speed along axis a (ba as in conv_flux).
 template <class T>
-T wave_speed(const Setup& S, int a, const T* u) {
+T wave_speed(const Setup& S, int a, const T* u, double ba) {
     const orc_problem& P = S.P;
     switch (P.eq) {
     case ORC_ADVECTION:
     case ORC_ADVDIFF_BR1:
-        return T(std::fabs(P.a[a]));
+    case ORC_ADVDIFF_SIPG:
+        return T(std::fabs(ba));
     case ORC_BURGERS:
         return absval(u[0]);
     default: {
@@ -307,10 +344,11 @@ void visc_flux(const Setup& S, int a, const T* u, const T* q, T* f) {
     f[d + 1] = work + kappa * gT[a];
 }
 
-// Total physical flux f_a(u) - fv_a(u, q).
+// Total physical flux f_a(u) - fv_a(u, q) (BR1 equations; for SIPG the
+// convective flux only: its viscous terms are assembled by sipg_terms).
 template <class T>
-void total_flux(const Setup& S, int a, const T* u, const T* q, T* f) {
-    conv_flux(S, a, u, f);
+void total_flux(const Setup& S, int a, const T* u, const T* q, T* f, double ba) {
+    conv_flux(S, a, u, f, ba);
     if (S.viscous) {
         T fv[8];
         visc_flux(S, a, u, q, fv);
@@ -321,12 +359,12 @@ void total_flux(const Setup& S, int a, const T* u, const T* q, T* f) {
 // Numerical flux along +e_a between left state L and right state R:
 // Rusanov for the convective part, central average for the viscous part.
 template <class T>
-void num_flux(const Setup& S, int a, const T* uL, const T* uR, const T* qL, const T* qR, T* H) {
+void num_flux(const Setup& S, int a, const T* uL, const T* uR, const T* qL, const T* qR, T* H, double ba) {
     const int nv = S.nv;
     T fL[8], fR[8];
-    conv_flux(S, a, uL, fL);
-    conv_flux(S, a, uR, fR);
-    T lam = larger(wave_speed(S, a, uL), wave_speed(S, a, uR));
+    conv_flux(S, a, uL, fL, ba);
+    conv_flux(S, a, uR, fR, ba);
+    T lam = larger(wave_speed(S, a, uL, ba), wave_speed(S, a, uR, ba));
     for (int v = 0; v < nv; ++v) H[v] = 0.5 * (fL[v] + fR[v]) + 0.5 * lam * (uL[v] - uR[v]);
     if (S.viscous) {
         T gL[8], gR[8];
@@ -357,14 +395,14 @@ void lifted_gradient(const Setup& S, const T* u, T* q) {
                     for (int k = 0; k < n1; ++k) g += S.D[i * n1 + k] * ue[S.node_with(s, b, k)];
                     if (i == n1 - 1) {
                         int en = S.neighbor(e, b, +1);
-                        T un = u[((long)en * nv + v) * ns + S.node_with(s, b, 0)];
-                        T uhat = 0.5 * (ue[s] + un);
+                        T uhat = T(S.P.bc_value);     // Dirichlet boundary: u_hat = g
+                        if (en >= 0) uhat = 0.5 * (ue[s] + u[((long)en * nv + v) * ns + S.node_with(s, b, 0)]);
                         g += (uhat - ue[s]) / S.wi[n1 - 1];
                     }
                     if (i == 0) {
                         int en = S.neighbor(e, b, -1);
-                        T un = u[((long)en * nv + v) * ns + S.node_with(s, b, n1 - 1)];
-                        T uhat = 0.5 * (un + ue[s]);
+                        T uhat = T(S.P.bc_value);
+                        if (en >= 0) uhat = 0.5 * (u[((long)en * nv + v) * ns + S.node_with(s, b, n1 - 1)] + ue[s]);
                         g -= (uhat - ue[s]) / S.wi[0];
                     }
                     q[(((long)e * d + b) * nv + v) * ns + s] = J * g;
@@ -381,6 +419,92 @@ void gather_node(const Setup& S, const T* u, const T* q, int e, int s, T* un, T*
         for (int b = 0; b < S.d; ++b)
             for (int v = 0; v < S.nv; ++v)
                 qn[b * S.nv + v] = q[(((long)e * S.d + b) * S.nv + v) * S.ns + s];
+}
+
+// SIPG viscous terms, F += -M^-1 a(u, .) with the bilinear form of the
+// header (scalar equation).  Along each axis a the element's nodal basis is
+// l_{i_a}(x_a) times the others, so every term acts on lines of n1 nodes:
+// with J = 2/h_a and the line's values u_k (k = 0..N), for node i of the line
+//   volume:      -nu J^2 (1/w_i) sum_q w_q D_qi (D u)_q        (= -M^-1 int nu u' psi_i')
+//   right face:  consistency +nu (J/w_N) {u'} [i = N],
+//                symmetry    +nu s J^2 (D_Ni / w_i) (u_N - u_R),
+//                penalty     -(eta nu/h_a) (J/w_N) (u_N - u_R) [i = N],
+//   left face:   consistency -nu (J/w_0) {u'} [i = 0],
+//                symmetry    +nu s J^2 (D_0i / w_i) (u_L - u_0),
+//                penalty     -(eta nu/h_a) (J/w_0) (u_0 - u_L) [i = 0],
+// where u' = J D u is the normal derivative, {u'} its average over the two
+// elements (s = 1/2) -- on a Dirichlet boundary the interior value, s = 1
+// and the exterior state g in place of u_R / u_L.
+template <class T>
+void sipg_terms(const Setup& S, const T* u, T* F) {
+    const int d = S.d, ns = S.ns, n1 = S.n1, N = n1 - 1;
+    const double nu = S.P.nu;
+    const T g = T(S.P.bc_value);
+#pragma omp parallel for schedule(static)
+    for (int e = 0; e < S.E; ++e) {
+        const T* ue = u + (long)e * ns;
+        for (int s = 0; s < ns; ++s) {
+            T acc = 0.0;
+            for (int a = 0; a < d; ++a) {
+                const double J = 2.0 / S.h[a];
+                const double sig = S.eta * nu / S.h[a];
+                const int i = S.ncoord(s, a);
+                // the line through s along a, and its derivative
+                T ul[8], du[8];
+                for (int k = 0; k < n1; ++k) ul[k] = ue[S.node_with(s, a, k)];
+                for (int q = 0; q < n1; ++q) {
+                    du[q] = 0.0;
+                    for (int k = 0; k < n1; ++k) du[q] += S.D[q * n1 + k] * ul[k];
+                }
+                T vol = 0.0;
+                for (int q = 0; q < n1; ++q) vol += S.wi[q] * S.D[q * n1 + i] * du[q];
+                acc -= nu * J * J * vol / S.wi[i];
+                // right face of the element
+                {
+                    const int en = S.neighbor(e, a, +1);
+                    T ext, dav;
+                    double sc;
+                    if (en >= 0) {
+                        const T* un = u + (long)en * ns;
+                        T dn = 0.0;
+                        for (int k = 0; k < n1; ++k) dn += S.D[0 * n1 + k] * un[S.node_with(s, a, k)];
+                        ext = un[S.node_with(s, a, 0)];
+                        dav = 0.5 * J * (du[N] + dn);
+                        sc = 0.5;
+                    } else {
+                        ext = g;
+                        dav = J * du[N];
+                        sc = 1.0;
+                    }
+                    const T jump = ul[N] - ext;
+                    if (i == N) acc += nu * (J / S.wi[N]) * dav - sig * (J / S.wi[N]) * jump;
+                    acc += nu * sc * J * J * (S.D[N * n1 + i] / S.wi[i]) * jump;
+                }
+                // left face
+                {
+                    const int en = S.neighbor(e, a, -1);
+                    T ext, dav;
+                    double sc;
+                    if (en >= 0) {
+                        const T* un = u + (long)en * ns;
+                        T dn = 0.0;
+                        for (int k = 0; k < n1; ++k) dn += S.D[N * n1 + k] * un[S.node_with(s, a, k)];
+                        ext = un[S.node_with(s, a, N)];
+                        dav = 0.5 * J * (du[0] + dn);
+                        sc = 0.5;
+                    } else {
+                        ext = g;
+                        dav = J * du[0];
+                        sc = 1.0;
+                    }
+                    const T jump = ext - ul[0];     // (u_L - u_0)
+                    if (i == 0) acc += -nu * (J / S.wi[0]) * dav + sig * (J / S.wi[0]) * jump;
+                    acc += nu * sc * J * J * (S.D[0 * n1 + i] / S.wi[i]) * jump;
+                }
+            }
+            F[(long)e * ns + s] += acc;
+        }
+    }
 }
 
 template <class T>
@@ -404,22 +528,35 @@ void spatial_op(const Setup& S, const T* u, T* F) {
                 const int i = S.ncoord(s, a);
                 // volume term: -(2/h_a) sum_k D_ik f_a(u_k)
                 for (int k = 0; k < n1; ++k) {
-                    gather_node(S, u, q, e, S.node_with(s, a, k), uk, qk);
-                    total_flux(S, a, uk, qk, f);
+                    const int sk = S.node_with(s, a, k);
+                    gather_node(S, u, q, e, sk, uk, qk);
+                    total_flux(S, a, uk, qk, f, S.vel(e, sk, a));
                     for (int v = 0; v < nv; ++v) acc[v] -= J * S.D[i * n1 + k] * f[v];
                 }
-                total_flux(S, a, ui, qi, fo);
-                // surface terms: -(2/h_a) M^-1 B (H - f)
+                const double ba = S.vel(e, s, a);
+                total_flux(S, a, ui, qi, fo, ba);
+                // surface terms: -(2/h_a) M^-1 B (H - f); on a Dirichlet
+                // boundary the exterior state g (its gradient: the interior one)
                 if (i == n1 - 1) {
                     int en = S.neighbor(e, a, +1);
-                    gather_node(S, u, q, en, S.node_with(s, a, 0), un, qn);
-                    num_flux(S, a, ui, un, qi, qn, H);
+                    if (en >= 0) {
+                        gather_node(S, u, q, en, S.node_with(s, a, 0), un, qn);
+                    } else {
+                        for (int v = 0; v < nv; ++v) un[v] = T(S.P.bc_value);
+                        for (int c = 0; c < d * nv; ++c) qn[c] = qi[c];
+                    }
+                    num_flux(S, a, ui, un, qi, qn, H, ba);
                     for (int v = 0; v < nv; ++v) acc[v] -= J * (H[v] - fo[v]) / S.wi[n1 - 1];
                 }
                 if (i == 0) {
                     int en = S.neighbor(e, a, -1);
-                    gather_node(S, u, q, en, S.node_with(s, a, n1 - 1), un, qn);
-                    num_flux(S, a, un, ui, qn, qi, H);
+                    if (en >= 0) {
+                        gather_node(S, u, q, en, S.node_with(s, a, n1 - 1), un, qn);
+                    } else {
+                        for (int v = 0; v < nv; ++v) un[v] = T(S.P.bc_value);
+                        for (int c = 0; c < d * nv; ++c) qn[c] = qi[c];
+                    }
+                    num_flux(S, a, un, ui, qn, qi, H, ba);
                     for (int v = 0; v < nv; ++v) acc[v] += J * (H[v] - fo[v]) / S.wi[0];
                 }
             }
@@ -429,6 +566,7 @@ void spatial_op(const Setup& S, const T* u, T* F) {
             }
         }
     }
+    if (S.sipg) sipg_terms(S, u, F);
 }
 
 // Apply F at every time node of a slab vector.
@@ -610,8 +748,10 @@ void residual_galerkin(const Setup& S, const double* U, const double* uprev, dou
                                         }
                                     }
                                     double uo = uat(e, v, j, sf);
-                                    double un = uat(en, v, j, S.node_with(sf, b, n1 - 1 - iface));
-                                    rhs += Wf * 0.5 * (uo + un) * nrm * ph;
+                                    // Dirichlet boundary: u_hat = g
+                                    double uh = S.P.bc_value;
+                                    if (en >= 0) uh = 0.5 * (uo + uat(en, v, j, S.node_with(sf, b, n1 - 1 - iface)));
+                                    rhs += Wf * uh * nrm * ph;
                                 }
                             }
                             qg[((((long)e * Nt + j) * d + b) * nv + v) * ns + sJ] = rhs / mass;
@@ -624,6 +764,12 @@ void residual_galerkin(const Setup& S, const double* U, const double* uprev, dou
                 for (int v = 0; v < nv; ++v)
                     qn[b * nv + v] = qg[((((long)e * Nt + j) * d + b) * nv + v) * ns + s];
     };
+    // SIPG: derivative along a of the element's polynomial (scalar) at node s
+    auto broken_grad = [&](int e, int j, int s, int a) {
+        double g = 0.0;
+        for (int sp = 0; sp < ns; ++sp) g += uat(e, 0, j, sp) * dphi(sp, s, a);
+        return g;
+    };
 
 #pragma omp parallel for schedule(static)
     for (int e = 0; e < S.E; ++e) {
@@ -635,7 +781,10 @@ void residual_galerkin(const Setup& S, const double* U, const double* uprev, dou
                 const double W = 0.5 * dt * S.om[jq] * S.wphys(sq);
                 gather(e, jq, sq, uq, qq);
                 double fl[3][8];
-                for (int a = 0; a < d; ++a) total_flux(S, a, uq, qq, fl[a]);
+                for (int a = 0; a < d; ++a) {
+                    total_flux(S, a, uq, qq, fl[a], S.vel(e, sq, a));
+                    if (S.sipg) fl[a][0] -= S.P.nu * broken_grad(e, jq, sq, a);   // F_v = nu grad u
+                }
                 for (int jJ = 0; jJ < Nt; ++jJ)
                     for (int sJ = 0; sJ < ns; ++sJ) {
                         const double pt = Lt[jJ * Nt + jq];
@@ -661,9 +810,25 @@ void residual_galerkin(const Setup& S, const double* U, const double* uprev, dou
                         for (int c = 0; c < d; ++c)
                             if (c != a) Wf *= 0.5 * S.h[c] * S.wi[S.ncoord(sf, c)];
                         gather(e, jq, sf, uq, qq);
-                        gather(en, jq, S.node_with(sf, a, n1 - 1 - iface), un, qn);
-                        if (side) num_flux(S, a, uq, un, qq, qn, H);
-                        else      num_flux(S, a, un, uq, qn, qq, H);
+                        const int sfn = S.node_with(sf, a, n1 - 1 - iface);
+                        if (en >= 0) {
+                            gather(en, jq, sfn, un, qn);
+                        } else {     // Dirichlet boundary: exterior state g, interior gradient
+                            for (int v = 0; v < nv; ++v) un[v] = S.P.bc_value;
+                            for (int c = 0; c < d * nv; ++c) qn[c] = qq[c];
+                        }
+                        const double ba = S.vel(e, sf, a);
+                        if (side) num_flux(S, a, uq, un, qq, qn, H, ba);
+                        else      num_flux(S, a, un, uq, qn, qq, H, ba);
+                        // SIPG: {grad u}.n, the jump u_K - u_N and the penalty
+                        double dav = 0.0, jmp = 0.0, sym = 0.0;
+                        if (S.sipg) {
+                            const double dK = broken_grad(e, jq, sf, a);
+                            dav = en >= 0 ? 0.5 * (dK + broken_grad(en, jq, sfn, a)) : dK;
+                            jmp = uq[0] - un[0];
+                            sym = en >= 0 ? 0.5 : 1.0;
+                        }
+                        const double sig = S.eta * S.P.nu / S.h[a];
                         for (int jJ = 0; jJ < Nt; ++jJ)
                             for (int sJ = 0; sJ < ns; ++sJ) {
                                 double ph = Lt[jJ * Nt + jq];
@@ -672,6 +837,12 @@ void residual_galerkin(const Setup& S, const double* U, const double* uprev, dou
                                                    : L[S.ncoord(sJ, c) * n1 + S.ncoord(sf, c)];
                                 for (int v = 0; v < nv; ++v)
                                     res[(size_t)v * nst + jJ * ns + sJ] -= Wf * nrm * H[v] * ph;
+                                if (S.sipg) {
+                                    // -a(u, psi): + nu {u'} n psi + nu {psi'} n (u_K - u_N) - sigma (u_K - u_N) psi
+                                    const double dps = Lt[jJ * Nt + jq] * dphi(sJ, sf, a);
+                                    res[(size_t)jJ * ns + sJ] += Wf * (S.P.nu * nrm * dav * ph +
+                                                                       S.P.nu * sym * nrm * dps * jmp - sig * jmp * ph);
+                                }
                             }
                     }
             }
@@ -866,9 +1037,7 @@ void orc_node_coords(const orc_problem* p, double* X) {
     Setup S(p);
     for (int e = 0; e < S.E; ++e)
         for (int a = 0; a < S.d; ++a)
-            for (int s = 0; s < S.ns; ++s)
-                X[((long)e * S.d + a) * S.ns + s] =
-                    p->lo[a] + S.h[a] * (S.ecoord(e, a) + 0.5 * (1.0 + S.xi[S.ncoord(s, a)]));
+            for (int s = 0; s < S.ns; ++s) X[((long)e * S.d + a) * S.ns + s] = S.coord(e, s, a);
 }
 
 void orc_spatial_op(const orc_problem* p, const double* u, double* F) {
@@ -889,13 +1058,13 @@ void orc_num_flux(const orc_problem* p, int axis, const double* uL, const double
                   const double* qL, const double* qR, double* H) {
     Setup S(p);
     double z[24] = {0};
-    num_flux(S, axis, uL, uR, qL ? qL : z, qR ? qR : z, H);
+    num_flux(S, axis, uL, uR, qL ? qL : z, qR ? qR : z, H, p->a[axis]);
 }
 
 void orc_flux(const orc_problem* p, int axis, const double* u, const double* q, double* f) {
     Setup S(p);
     double z[24] = {0};
-    total_flux(S, axis, u, q ? q : z, f);
+    total_flux(S, axis, u, q ? q : z, f, p->a[axis]);
 }
 
 void orc_residual(const orc_problem* p, int form, const double* U, const double* uprev, double dt,

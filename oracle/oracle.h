@@ -11,7 +11,7 @@
  * Aspects of Space-Time DG-SEM Implementations" (arXiv 2201.05800).
  *
  * Three formulations of one slab (one time element [t_n, t_n + dt] times the
- * whole periodic spatial mesh) are implemented:
+ * whole spatial mesh, periodic unless bc[] says otherwise) are implemented:
  *   ORC_FORM_DG       DG-SEM in time, strong form in space: the slab system
  *                     eq. (DG_vs_RK:DG) written as R = RHS - LHS, whose
  *                     Jacobian is exactly eq. (Jacobian_ST).
@@ -45,7 +45,9 @@ enum {
     ORC_ADVDIFF_BR1 = 2,    /* u_t + a . grad u - nu lap u = 0, BR1 viscous  */
     ORC_BURGERS = 3,        /* u_t + (u^2/2)_x = 0, d = 1                    */
     ORC_EULER = 4,          /* compressible Euler, r = d + 2                 */
-    ORC_NS_BR1 = 5          /* compressible Navier-Stokes, BR1 viscous       */
+    ORC_NS_BR1 = 5,         /* compressible Navier-Stokes, BR1 viscous       */
+    ORC_ADVDIFF_SIPG = 6    /* u_t + div(b u) - nu lap u = 0, symmetric      */
+                            /* interior penalty (eta = 10 p^2)               */
 };
 
 enum { ORC_FORM_DG = 0, ORC_FORM_RK = 1, ORC_FORM_GALERKIN = 2 };
@@ -64,6 +66,14 @@ typedef struct {
     double mu;          /* dynamic viscosity (NS)                             */
     double prandtl;     /* Prandtl number (NS)                                */
     double react;       /* linear source S(u) = react * u (0 on the hot path) */
+    /* advection velocity field of the scalar equations: b(x) = a + omega
+     * e_z x (x - center) in 2D (a rotation about `center`; omega = 0 elsewhere) */
+    double omega;
+    double center[3];
+    /* boundaries per axis: 0 periodic, 1 Dirichlet with the exterior state
+     * bc_value (scalar equations only) */
+    int bc[3];
+    double bc_value;
 } orc_problem;
 
 typedef struct {
