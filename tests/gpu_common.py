@@ -55,8 +55,46 @@ def host(t):
 
 
 def rel(a, b):
+    """The larger of the relative 2-norm error ||a - b|| / ||b|| and the
+    element-wise one max|a - b| / max|b|: a bound on it bounds both, so a
+    defect confined to a few values cannot hide in the norm of a large
+    vector."""
+    a, b = np.asarray(a, dtype=np.float64), np.asarray(b, dtype=np.float64)
     nb = np.linalg.norm(b)
-    return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
+    mb = np.abs(b).max() if b.size else 0.0
+    d = a - b
+    e2 = np.linalg.norm(d) / (nb if nb > 0 else 1.0)
+    emax = (np.abs(d).max() if d.size else 0.0) / (mb if mb > 0 else 1.0)
+    return max(e2, emax)
+
+
+JVP32_NORM_TOL = 2e-5     # relative 2-norm of an FP32-inner JVP against the FP64 oracle
+
+
+def fp32_elementwise_bound(jvp_fn, U, V, Jo):
+    """Element-wise bound for an FP32-inner JVP (FP32 state, FP32 arithmetic
+    and accumulation) against the FP64 value Jo = jvp_fn(U, V).  The JVP of
+    the nonlinear equations cancels strongly at single nodes, so the bound is
+    derived from the conditioning rather than from |Jo|: 64 times the largest
+    change of the oracle's JVP when U and V are rounded to FP32 (the input
+    rounding alone; FP32 arithmetic over a few dozen terms per value adds a
+    similar amount per term), and at least 2e-5 max|Jo|."""
+    U32 = np.asarray(U, dtype=np.float32).astype(np.float64)
+    V32 = np.asarray(V, dtype=np.float32).astype(np.float64)
+    sens = np.abs(jvp_fn(U32, V32) - Jo).max()
+    return max(64.0 * sens, JVP32_NORM_TOL * np.abs(Jo).max())
+
+
+def check_fp32_jvp(J32, Jo, jvp_fn, U, V, label=""):
+    """FP32-inner JVP parity: relative 2-norm <= 2e-5 and every value within
+    fp32_elementwise_bound.  Returns (2-norm error, max error / bound)."""
+    J32, Jo = np.asarray(J32), np.asarray(Jo)
+    e2 = np.linalg.norm(J32 - Jo) / max(np.linalg.norm(Jo), 1e-300)
+    b = fp32_elementwise_bound(jvp_fn, U, V, Jo)
+    em = np.abs(J32 - Jo).max()
+    assert e2 <= JVP32_NORM_TOL, (label, e2)
+    assert em <= b, (label, em, b)
+    return e2, em / b
 
 
 def gpu_residual(P: Pair, U, up, dt):

@@ -17,7 +17,7 @@ import time
 import numpy as np
 import pytest
 
-from gpu_common import Pair, cfg, gpu_jvp, gpu_residual, gpu_solve, rel
+from gpu_common import Pair, cfg, check_fp32_jvp, gpu_jvp, gpu_residual, gpu_solve, rel
 from paper_2201_05800_amd import inputs
 
 pytestmark = pytest.mark.gpu
@@ -83,9 +83,10 @@ def test_full_size_residual_and_jvp(orc, name):
         Jo = orc.jvp(P.p, U, dt, V)
         e_j = rel(J, Jo)
         J32 = gpu_jvp(P, U, V, dt, 1)
-        e_32 = rel(J32, Jo)
-        say(f"{name}: n={P.n} residual {e_r:.2e} jvp {e_j:.2e} jvp32 {e_32:.2e} ({time.time() - t:.1f} s)")
-        assert e_r <= 1e-12 and e_j <= 1e-12 and e_32 <= 2e-5
+        e_32, f_32 = check_fp32_jvp(J32, Jo, lambda a, b: orc.jvp(P.p, a, dt, b), U, V, name)
+        say(f"{name}: n={P.n} residual {e_r:.2e} jvp {e_j:.2e} jvp32 {e_32:.2e} (element-wise at {f_32:.2f} of "
+            f"its bound) ({time.time() - t:.1f} s)")
+        assert e_r <= 1e-12 and e_j <= 1e-12
         assert np.abs(R - Ro).max() <= 1e-12 * np.abs(Ro).max() * 10
     finally:
         P.close()

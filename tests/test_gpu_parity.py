@@ -1,22 +1,25 @@
 """GPU parity: the HIP path (through the C ABI) against the CPU oracle.
 
-Bars: residual and FP64 JVP within 1e-12 relative (2-norm) per evaluation;
-solved slabs within 1e-9 relative in both precision forms.  FP32-inner JVPs
-are compared against the FP64 oracle with the FP32 bound written below.
+Bars: residual and FP64 JVP within 1e-12 relative per evaluation; solved
+slabs within 1e-9 relative in both precision forms.  "Relative" is the larger
+of the 2-norm and the element-wise (max-norm) relative error (gpu_common.rel).
+FP32-inner JVPs are compared against the FP64 oracle with the FP32 bound
+written below.
 """
 import sys
 
 import numpy as np
 import pytest
 
-from gpu_common import Pair, cfg, gpu_jvp, gpu_residual, gpu_solve, rel
+from gpu_common import Pair, cfg, check_fp32_jvp, gpu_jvp, gpu_residual, gpu_solve, rel
 from paper_2201_05800_amd import inputs
 
 pytestmark = pytest.mark.gpu
 
 RES_TOL = 1e-12
 JVP_TOL = 1e-12
-JVP32_TOL = 2e-5      # FP32 state, arithmetic and accumulation vs the FP64 oracle
+# FP32-inner JVPs: gpu_common.check_fp32_jvp (relative 2-norm <= 2e-5, element-wise
+# bound from the conditioning of the JVP under FP32 rounding of its inputs)
 SLAB_TOL = 1e-9
 
 
@@ -61,11 +64,11 @@ def test_sweep_all_kernels(orc, kind):
             J = gpu_jvp(P, U, V, dt)
             Jo = orc.jvp(P.p, U, dt, V)
             J32 = gpu_jvp(P, U, V, dt, fp32=1)
-            e = (rel(R, Ro), rel(J, Jo), rel(J32, Jo))
+            e = (rel(R, Ro), rel(J, Jo), check_fp32_jvp(J32, Jo, lambda a, b: orc.jvp(P.p, a, dt, b), U, V,
+                                                        (k, d, K, N, Nt))[0])
             worst = {kk: max(worst[kk], x) for kk, x in zip(worst, e)}
             assert e[0] <= RES_TOL, (k, d, K, N, Nt, e)
             assert e[1] <= JVP_TOL, (k, d, K, N, Nt, e)
-            assert e[2] <= JVP32_TOL, (k, d, K, N, Nt, e)
         finally:
             P.close()
     say("worst relative errors", kind, worst)
@@ -98,7 +101,7 @@ def test_residual_jvp_mid(orc, c):
             assert rel(gpu_residual(P, U, up, dt), orc.residual(P.p, U, up, dt)) <= RES_TOL
             Jo = orc.jvp(P.p, U, dt, V)
             assert rel(gpu_jvp(P, U, V, dt), Jo) <= JVP_TOL
-            assert rel(gpu_jvp(P, U, V, dt, 1), Jo) <= JVP32_TOL
+            check_fp32_jvp(gpu_jvp(P, U, V, dt, 1), Jo, lambda a, b: orc.jvp(P.p, a, dt, b), U, V, c["K"])
     finally:
         P.close()
 
@@ -209,7 +212,8 @@ def initial(P, kind):
 
 @pytest.mark.parametrize("name,c,dt,init", SOLVES, ids=[s[0] for s in SOLVES])
 @pytest.mark.parametrize("fp32", [0, 1], ids=["fp64", "fp32inner"])
-def test_slab_solve_parity(orc, name, c, dt, init, fp32):
+@pytest.mark.parametrize("cgs", [1, 2], ids=["cgs1", "cgs2"])
+def test_slab_solve_parity(orc, name, c, dt, init, fp32, cgs):
     P = Pair(c)
     try:
         up = initial(P, init)
@@ -220,11 +224,11 @@ def test_slab_solve_parity(orc, name, c, dt, init, fp32):
             else:
                 lam = np.abs(up).max()
             dt = inputs.cfl_dt(5.0, h, c["N"], lam)
-        say("solve", name, "fp32" if fp32 else "fp64", "dt", dt)
-        U, un, stats = gpu_solve(P, up, dt, 1e-12, inner_fp32=fp32)
+        say("solve", name, "fp32" if fp32 else "fp64", "cgs passes", cgs, "dt", dt)
+        U, un, stats = gpu_solve(P, up, dt, 1e-12, inner_fp32=fp32, cgs_passes=cgs)
         Uo, so = orc.solve(P.p, up, dt, tol=1e-13, dense_limit=0)
         e = rel(U, Uo)
-        say(f"  {name} fp32={fp32}: rel err {e:.2e}, outer {stats['newton_its']}, gmres {stats['gmres_its']}, "
+        say(f"  {name} fp32={fp32} cgs={cgs}: rel err {e:.2e}, outer {stats['newton_its']}, gmres {stats['gmres_its']}, "
             f"oracle newton {so['newton_its']} lin {so['linear_its']}")
         assert so["res_final"] <= 1e-12 * max(1.0, so["res0"])
         assert e <= SLAB_TOL

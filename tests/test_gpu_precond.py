@@ -126,6 +126,28 @@ def test_preconditioned_solve_is_deterministic_and_reuses_the_block():
         P.close()
 
 
+def test_nonlinear_block_follows_the_mean_state():
+    """The nonlinear block is assembled at the mean of u_prev: a solve on the
+    same handle with another mean state rebuilds it, so it runs exactly as on
+    a fresh handle (bitwise), and the same mean state reuses it."""
+    c = cfg("burgers", 1, [48], 3, 3)
+    P, Q = Pair(c), Pair(c)
+    try:
+        up1 = nonlin_init(P, "burgers")
+        up2 = up1 + 0.3
+        dt = 0.01
+        gpu_solve(P, up1, dt, 1e-11, precond=1)
+        a = gpu_solve(P, up2, dt, 1e-11, precond=1)       # new mean: rebuilt
+        b = gpu_solve(Q, up2, dt, 1e-11, precond=1)       # fresh handle
+        assert np.array_equal(a[0], b[0])
+        assert a[2]["gmres_its"] == b[2]["gmres_its"]
+        c2 = gpu_solve(P, up2, dt, 1e-11, precond=1)      # same mean: reused
+        assert np.array_equal(a[0], c2[0])
+    finally:
+        P.close()
+        Q.close()
+
+
 def test_preconditioning_rejected_where_unavailable():
     from paper_2201_05800_amd import st
     # an element block of 5 * 2 * 5^3 = 1250 unknowns is above the limit

@@ -59,21 +59,23 @@ def initial_for(P, kind, seed):
 
 def test_alone_vs_mix_bitwise(orc):
     from paper_2201_05800_amd import st
-    cases = [("burgers", burgers_case(40, 3, 3, 1), 0), ("advdiff", advdiff_case(10, 3, 2), 0),
-             ("burgers", burgers_case(23, 5, 4, 2), 1), ("advdiff", advdiff_case(8, 4, 4), 1),
-             ("burgers", burgers_case(64, 2, 2, 3), 0), ("advdiff", advdiff_case(12, 2, 3), 1),
-             ("burgers", burgers_case(7, 2, 3, 4), 1)]     # 63 unknowns: element-wise vector paths
-    pairs = [Pair(c) for _, c, _ in cases]
+    # (kind, problem, FP32-inner, Gram-Schmidt passes): one and two passes
+    # mixed in one batch, each request with its own
+    cases = [("burgers", burgers_case(40, 3, 3, 1), 0, 1), ("advdiff", advdiff_case(10, 3, 2), 0, 2),
+             ("burgers", burgers_case(23, 5, 4, 2), 1, 1), ("advdiff", advdiff_case(8, 4, 4), 1, 2),
+             ("burgers", burgers_case(64, 2, 2, 3), 0, 2), ("advdiff", advdiff_case(12, 2, 3), 1, 1),
+             ("burgers", burgers_case(7, 2, 3, 4), 1, 2)]     # 63 unknowns: element-wise vector paths
+    pairs = [Pair(c) for _, c, _, _ in cases]
     try:
         reqs, ups, dts = [], [], []
-        for (kind, c, fp32), P in zip(cases, pairs):
+        for (kind, c, fp32, cgs), P in zip(cases, pairs):
             up = initial_for(P, kind, seed=11)
             h = min((c["hi"][a] - c["lo"][a]) / c["K"][a] for a in range(c["dim"]))
             lam = np.abs(up).max() if kind == "burgers" else np.sqrt(1.25)
             dt = inputs.cfl_dt(5.0, h, c["N"], lam)
             ups.append(up)
             dts.append(dt)
-            reqs.append(make_req(st, c, up, dt, inner_fp32=fp32))
+            reqs.append(make_req(st, c, up, dt, inner_fp32=fp32, cgs_passes=cgs))
         srv = st.st_server_create(hbm_budget_bytes=2 << 30, max_active=16)
         try:
             # alone: one at a time
@@ -95,12 +97,13 @@ def test_alone_vs_mix_bitwise(orc):
         finally:
             st.st_server_destroy(srv)
         # each served result equals the single-slab driver and the oracle
-        for (kind, c, fp32), P, up, dt, u in zip(cases, pairs, ups, dts, alone):
-            U1, un1, _ = gpu_solve(P, up, dt, 1e-11, inner_fp32=fp32)
+        for (kind, c, fp32, cgs), P, up, dt, u in zip(cases, pairs, ups, dts, alone):
+            U1, un1, _ = gpu_solve(P, up, dt, 1e-11, inner_fp32=fp32, cgs_passes=cgs)
             assert np.array_equal(un1, u), "served result differs from st_solve_slab"
             Uo, so = orc.solve(P.p, up, dt, tol=1e-13, dense_limit=0)
             e = rel(u, orc.last_time_node(P.p, Uo))
-            say(f"served {kind} K={c['K']} N={c['N']} Nt={c['Nt']} fp32={fp32}: rel err vs oracle {e:.2e}")
+            say(f"served {kind} K={c['K']} N={c['N']} Nt={c['Nt']} fp32={fp32} cgs={cgs}: "
+                f"rel err vs oracle {e:.2e}")
             assert e <= 1e-9
     finally:
         for P in pairs:

@@ -10,8 +10,8 @@ import sys
 import numpy as np
 import pytest
 
-from gpu_common import Pair, cfg, dev, host, rel
-from test_gpu_parity import JVP32_TOL, JVP_TOL, RES_TOL, SLAB_TOL, initial
+from gpu_common import Pair, cfg, check_fp32_jvp, dev, host, rel
+from test_gpu_parity import JVP_TOL, RES_TOL, SLAB_TOL, initial
 from paper_2201_05800_amd import inputs
 
 pytestmark = pytest.mark.gpu
@@ -58,9 +58,10 @@ def test_coupled_operator_parity(orc, name, c, M):
         Jo = orc.jvp_slabs(P.p, U, dt, V, M)
         J32 = torch.empty_like(Vd)
         P.st.st_jvp_slabs(P.h, M, Ud, 0.0, dt, Vd, J32, 1)
-        e = (rel(host(R), Ro), rel(host(J), Jo), rel(host(J32), Jo))
+        e = (rel(host(R), Ro), rel(host(J), Jo),
+             check_fp32_jvp(host(J32), Jo, lambda a, b: orc.jvp_slabs(P.p, a, dt, b, M), U, V, M)[0])
         say(f"  rel errors residual {e[0]:.2e} jvp {e[1]:.2e} jvp32 {e[2]:.2e}")
-        assert e[0] <= RES_TOL and e[1] <= JVP_TOL and e[2] <= JVP32_TOL, e
+        assert e[0] <= RES_TOL and e[1] <= JVP_TOL, e
         if M == 1:
             # the single-slab entry points are the M = 1 system
             R1 = torch.empty_like(Ud)
