@@ -219,6 +219,26 @@ int st_solve_slabs(st_handle_t h, int M, const double* u_prev, double t0, double
                    const st_solver_opts_t* opts, double* U_out, double* u_next, st_stats_t* stats,
                    void* stream);
 
+/* The slab residual of st_residual without a handle and without allocating:
+ * for callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc).  The
+ * problem is given as to st_create; U, u_prev, R as to st_residual (device,
+ * caller-owned).  Every other device buffer its kernels use -- the launch
+ * descriptors and, for ST_NS_BR1, the viscous-flux array (mesh.dim values per
+ * unknown) -- lives in one static device array of ST_NOALLOC_SCRATCH_BYTES,
+ * which each GPU the library runs on holds until the process ends.  A
+ * Navier-Stokes slab whose viscous-flux array does not fit (more than about
+ * 16.7 M / (8 dim) unknowns) is rejected with ST_ERR_BAD_ARG; the other
+ * equations have no size limit here.  Calls that overlap on one GPU (other
+ * streams, other threads) share the array and race; calls on one stream are
+ * ordered.  Asynchronous on `stream`; no hipMalloc/hipFree, no host-device
+ * copy, no memset (every value of the array that a kernel reads was written
+ * by the call before, in stream order).  The first call on a device looks up
+ * the array's address there (hipGetSymbolAddress). */
+#define ST_NOALLOC_SCRATCH_BYTES (16u << 20)
+int st_residual_noalloc(const st_mesh_t* mesh, int N, int Nt, const st_equation_t* eq, const double* U,
+                        const double* u_prev, double t0, double dt, double* R, void* stream);
+
 /* Local error estimate of a solved slab by an embedded solution (Sec.
  * "Algorithmic Aspects", adaptive time-stepping; eqs. (RK_stage_equations),
  * (RK_solution), with the tableau of eq. (SBP_to_RK)).  The embedded solution

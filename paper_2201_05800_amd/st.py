@@ -109,6 +109,9 @@ _SIGS = [
                                          ctypes.c_double, ctypes.c_double, ctypes.c_double, _c_double_p,
                                          ctypes.c_void_p]),
     ("st_next_dt", ctypes.c_int, [ctypes.c_int, ctypes.c_double, ctypes.c_double, _c_double_p]),
+    ("st_residual_noalloc", ctypes.c_int, [ctypes.POINTER(Mesh), ctypes.c_int, ctypes.c_int,
+                                           ctypes.POINTER(Equation), ctypes.c_void_p, ctypes.c_void_p,
+                                           ctypes.c_double, ctypes.c_double, ctypes.c_void_p, ctypes.c_void_p]),
     ("st_server_create", ctypes.c_int, [ctypes.POINTER(ServerOpts), ctypes.POINTER(ctypes.c_void_p)]),
     ("st_server_destroy", ctypes.c_int, [ctypes.c_void_p]),
     ("st_submit", ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(Request), ctypes.POINTER(ctypes.c_uint64)]),
@@ -244,6 +247,11 @@ def st_residual(h, U, u_prev, t0, dt, R, stream=None) -> None:
 def st_jvp(h, U, t0, dt, v, Jv, inner_fp32=0, stream=None) -> None:
     _check(lib().st_jvp(h, _dev(U, "U"), float(t0), float(dt), _dev(v, "v"), _dev(Jv, "Jv"), int(inner_fp32),
                         _stream(stream)))
+
+
+def st_residual_noalloc(mesh_, N, Nt, eq, U, u_prev, t0, dt, R, stream=None) -> None:
+    _check(lib().st_residual_noalloc(ctypes.byref(mesh_), int(N), int(Nt), ctypes.byref(eq), _dev(U, "U"),
+                                     _dev(u_prev, "u_prev"), float(t0), float(dt), _dev(R, "R"), _stream(stream)))
 
 
 def st_residual_slabs(h, M, U, u_prev, t0, dt, R, stream=None) -> None:
