@@ -70,8 +70,11 @@ typedef enum {
     ST_ADVDIFF_BR1 = 2, /* Fc = a u, Fv = nu grad u; BR1 viscous flux        */
     ST_BURGERS = 3,     /* Fc = u^2 / 2, dim = 1                             */
     ST_EULER = 4,       /* compressible Euler, Sec. "Euler Equations"        */
-    ST_NS_BR1 = 5       /* compressible Navier-Stokes (constant mu, Stokes   */
+    ST_NS_BR1 = 5,      /* compressible Navier-Stokes (constant mu, Stokes   */
                         /* hypothesis, T = p / rho, Fourier heat flux), BR1  */
+    ST_ADVDIFF_SIPG = 6 /* Fc = b u, Fv = nu grad u; the paper's symmetric   */
+                        /* interior penalty flux, eta = 10 N^2 (Sec. "DG-SEM */
+                        /* in Space")                                        */
 } st_eq_kind_t;
 
 typedef struct {
@@ -81,6 +84,14 @@ typedef struct {
     double gamma;     /* ratio of specific heats (EULER, NS_BR1) */
     double mu;        /* dynamic viscosity (NS_BR1) */
     double prandtl;   /* Prandtl number (NS_BR1) */
+    /* ADVECTION, ADVDIFF_BR1, ADVDIFF_SIPG in 2D with N <= 4: the velocity
+     * field b(x) = a + omega e_z x (x - center), a rotation about `center`
+     * (the rotating pulse of Sec. "Experiments / Advection-Diffusion",
+     * eq. (advdiffeq)); omega = 0: the constant velocity a.  The flux b(x_i) u_i
+     * is interpolated at the nodes; b is divergence free and its normal
+     * component is continuous across every face, the periodic seams included. */
+    double omega;
+    double center[3];
 } st_equation_t;
 
 /* Newton-GMRES options (the paper names Newton-GMRES, Sec. "Euler

@@ -41,13 +41,13 @@ constexpr int BLOCK = 256;         // threads per block of the operator kernels
 constexpr int VBLOCK = 256;        // threads per block of the Krylov vector kernels
 constexpr int VMAXBLK = 512;       // most blocks of one slab in a Krylov vector launch
 
-enum EqKind { EQ_ADV = 1, EQ_ADVDIFF = 2, EQ_BURGERS = 3, EQ_EULER = 4, EQ_NS = 5 };
+enum EqKind { EQ_ADV = 1, EQ_ADVDIFF = 2, EQ_BURGERS = 3, EQ_EULER = 4, EQ_NS = 5, EQ_ADVDIFF_SIPG = 6 };
 
 __host__ __device__ constexpr int nvars_of(int eq, int dim) {
     return (eq == EQ_EULER || eq == EQ_NS) ? dim + 2 : 1;
 }
-__host__ __device__ constexpr bool viscous_eq(int eq) { return eq == EQ_ADVDIFF || eq == EQ_NS; }
-__host__ __device__ constexpr bool linear_eq(int eq) { return eq == EQ_ADV || eq == EQ_ADVDIFF; }
+__host__ __device__ constexpr bool viscous_eq(int eq) { return eq == EQ_ADVDIFF || eq == EQ_NS || eq == EQ_ADVDIFF_SIPG; }
+__host__ __device__ constexpr bool linear_eq(int eq) { return eq == EQ_ADV || eq == EQ_ADVDIFF || eq == EQ_ADVDIFF_SIPG; }
 __host__ __device__ __forceinline__ constexpr int ipow(int b, int e) {
     int r = 1;
     for (int i = 0; i < e; ++i) r *= b;
@@ -185,6 +185,10 @@ struct DynPtr {
 
 // entries per axis of the linear line operator: n1^2 + 4 n1 for n1 <= 8
 constexpr int LIN_AXIS = 8 * 8 + 4 * 8;
+// rotating velocity (2D): the line operator of each axis in three parts
+// (viscous, central advection per unit velocity, Rusanov dissipation per
+// unit speed), packed with stride n1^2 + 4 n1, for n1 <= ROT_MAX_N1
+constexpr int ROT_MAX_N1 = 5;
 
 // One slab instance inside an operator launch.
 struct OpSeg {
@@ -220,8 +224,16 @@ struct OpSeg {
     // line of n1 nodes and the neighbours' lines across its two end faces,
     // per axis a at lin[a * LIN_AXIS]: A[i * n1 + k] (own line), HL[i] and
     // HR[i] (the neighbours' face values), FL[m] and FR[m] (the left and the
-    // right neighbour's node at distance m >= 1 from its face, end rows only)
+    // right neighbour's node at distance m >= 1 from its face, end rows only).
+    // Rotating velocity: part p of axis a at lin[(a * 3 + p) * (n1^2 + 4 n1)]
+    // with the same sub-layout (p = 0 viscous, 1 central per unit b_a,
+    // 2 dissipation per unit |b_a|).
     double lin[3 * LIN_AXIS];
+    // rotating velocity b = a + omega e_z x (x - center) (2D)
+    double lo[2];
+    double xi[8];        // LGL nodes on [-1, 1]
+    double omega;
+    double center[2];
 };
 
 // One slab instance inside a vector (Krylov) launch.

@@ -72,7 +72,11 @@ void lgl_tables(int n, double* x, double* w, double* D) {
     }
 }
 
-const OpTable* find_table(int eq, int dim, int n1, int nt) {
+// Kernel tables by (equation, dim, n1, nt) and velocity kind.  The interior
+// penalty variant of advection-diffusion runs the same line-operator kernels
+// as BR1 (only the host-built line operator differs); the rotating-velocity
+// entries carry the three-part kernels of the linear equations.
+const OpTable* find_table(int eq, int dim, int n1, int nt, bool rot) {
     static std::vector<OpTable> tables;
     static std::once_flag once;
     std::call_once(once, [] {
@@ -81,9 +85,19 @@ const OpTable* find_table(int eq, int dim, int n1, int nt) {
         register_ops_burgers(tables);
         register_ops_euler(tables);
         register_ops_ns(tables);
+        const size_t n0 = tables.size();
+        for (size_t i = 0; i < n0; ++i) {
+            if (!tables[i].res64_rot) continue;
+            OpTable t = tables[i];
+            t.res64 = t.res64_rot;
+            t.lin32 = t.lin32_rot;
+            t.rot = 1;
+            tables.push_back(t);
+        }
     });
+    const int keq = eq == EQ_ADVDIFF_SIPG ? EQ_ADVDIFF : eq;
     for (const auto& t : tables)
-        if (t.eq == eq && t.dim == dim && t.n1 == n1 && t.nt == nt) return &t;
+        if (t.eq == keq && t.dim == dim && t.n1 == n1 && t.nt == nt && (t.rot != 0) == rot) return &t;
     return nullptr;
 }
 
@@ -94,7 +108,7 @@ int make_problem(const st_mesh_t* mesh, int N, int Nt, const st_equation_t* eq, 
     if (!mesh || !eq) return set_error(ST_ERR_BAD_ARG, "null mesh or equation");
     const int d = mesh->dim;
     if (d < 1 || d > 3) return set_error(ST_ERR_BAD_ARG, "dim must be 1, 2 or 3");
-    if (eq->kind < ST_ADVECTION || eq->kind > ST_NS_BR1) return set_error(ST_ERR_BAD_ARG, "unknown equation kind");
+    if (eq->kind < ST_ADVECTION || eq->kind > ST_ADVDIFF_SIPG) return set_error(ST_ERR_BAD_ARG, "unknown equation kind");
     if (eq->kind == ST_BURGERS && d != 1) return set_error(ST_ERR_UNSUPPORTED, "Burgers is one-dimensional");
     if (N < 1 || Nt < 2) return set_error(ST_ERR_BAD_ARG, "need N >= 1 and Nt >= 2");
     pb.mesh = *mesh;
@@ -118,7 +132,11 @@ int make_problem(const st_mesh_t* mesh, int N, int Nt, const st_equation_t* eq, 
     if (pb.E > (int64_t)1 << 30) return set_error(ST_ERR_BAD_ARG, "too many elements");
     pb.n = pb.E * pb.nv * Nt * pb.ns;
     pb.nsp = pb.E * pb.nv * pb.ns;
-    pb.ops = find_table(eq->kind, d, pb.n1, Nt);
+    const bool rot = eq->omega != 0.0;
+    if (!std::isfinite(eq->omega)) return set_error(ST_ERR_BAD_ARG, "omega must be finite");
+    if (rot && (!linear_eq(eq->kind) || d != 2 || pb.n1 > ROT_MAX_N1))
+        return set_error(ST_ERR_UNSUPPORTED, "a rotating velocity needs a linear equation in 2D with N <= 4");
+    pb.ops = find_table(eq->kind, d, pb.n1, Nt, rot);
     if (!pb.ops)
         return set_error(ST_ERR_UNSUPPORTED, "(equation, dim, N, Nt) = (" + std::to_string(eq->kind) + ", " +
                                                  std::to_string(d) + ", " + std::to_string(N) + ", " +
@@ -152,48 +170,89 @@ static void div_magic(int d, unsigned& m, int& sh) {
 }
 
 // Spatial operator of a linear equation (advection, advection-diffusion with
-// BR1) along axis a, restricted to one line of n1 nodes: the contribution
-// F_i = -(2/h) [D f]_i - (2/h) M^-1 B (H - f) at node i of the line is linear
-// in the line's values u, the left neighbour's line uL and the right one's uR
-// (eqs. elementint, surfaceint in strong form, flux:llf; BR1 lifted gradient
-// with u_hat = {u}, central viscous flux).  Evaluated here for the unit
-// vectors, it gives F = A u + BL uL + BR uR; BL is nonzero only in its last
-// column (the neighbour's face value enters every node through the lift) and
-// its first row (the face flux needs the neighbour's normal derivative), BR
-// likewise in its first column and last row.
-static void line_operator(const Problem& pb, int a, double* out) {
+// BR1 or with the symmetric interior penalty) along axis a, restricted to one
+// line of n1 nodes: the contribution F_i at node i of the line is linear in
+// the line's values u, the left neighbour's line uL and the right one's uR
+// (eqs. elementint, surfaceint in strong form, flux:llf).  Evaluated here for
+// the unit vectors, it gives F = A u + BL uL + BR uR; BL is nonzero only in
+// its last column (the neighbour's face value enters every node through the
+// lift) and its first row (the face flux needs the neighbour's normal
+// derivative), BR likewise in its first column and last row (checked).
+//   advection: -(2/h) D (a u), Rusanov {a u} + lambda/2 (u_L - u_R) at the
+//              faces, lifted by -(2/h) M^-1 B (H - f);
+//   BR1:       lifted gradient with u_hat = {u}, central {nu q};
+//   SIPG:      the symmetric interior penalty form, sigma = eta nu / h,
+//              eta = 10 N^2, on the line with J = 2/h:
+//              -nu J^2 M^-1 D^T M D u, and per face the consistency term
+//              nu {u'} (end row), the symmetry term nu/2 J^2 M^-1 D^T e (jump)
+//              (every row), the penalty -sigma J/w (jump) (end row).
+// `av` is the velocity, `lam` the Rusanov wave speed, `nu` the diffusivity.
+static void line_operator_parts(const Problem& pb, int a, double av, double lam, double nu, double* out) {
     const int n1 = pb.n1, N = n1 - 1;
-    const double J = 2.0 / pb.h[a], av = pb.P.a[a], lam = std::fabs(av);
-    const double nu = pb.eq.kind == ST_ADVDIFF_BR1 ? pb.P.nu : 0.0;
+    const double J = 2.0 / pb.h[a];
+    const bool sipg = pb.eq.kind == ST_ADVDIFF_SIPG;
+    const double eta = pb.N > 0 ? 10.0 * pb.N * pb.N : 1.0;
+    const double sig = eta * nu / pb.h[a];
     const double iw0 = 1.0 / pb.wx[0];
     const double* D = pb.Dx;
+    const double* w = pb.wx;
     auto apply = [&](const double* u, const double* uL, const double* uR, double* acc) {
         double g[8], f[8];
-        for (int i = 0; i < n1; ++i) {
-            g[i] = 0.0;
-            for (int k = 0; k < n1; ++k) g[i] += D[i * n1 + k] * u[k];
+        if (!sipg) {
+            for (int i = 0; i < n1; ++i) {
+                g[i] = 0.0;
+                for (int k = 0; k < n1; ++k) g[i] += D[i * n1 + k] * u[k];
+            }
+            g[0] += -iw0 * (0.5 * (u[0] + uL[N]) - u[0]);
+            g[N] += iw0 * (0.5 * (u[N] + uR[0]) - u[N]);
+            for (int i = 0; i < n1; ++i) f[i] = u[i] * av - (J * g[i]) * nu;
+        } else {
+            for (int i = 0; i < n1; ++i) f[i] = u[i] * av;
         }
-        g[0] += -iw0 * (0.5 * (u[0] + uL[N]) - u[0]);
-        g[N] += iw0 * (0.5 * (u[N] + uR[0]) - u[N]);
-        for (int i = 0; i < n1; ++i) f[i] = u[i] * av - (J * g[i]) * nu;
         for (int i = 0; i < n1; ++i) {
             double sv = 0.0;
             for (int k = 0; k < n1; ++k) sv += D[i * n1 + k] * f[k];
             acc[i] = -J * sv;
         }
-        // right face: the neighbour's gradient at its face node, its flux,
-        // the Rusanov flux with u_L = u_N, u_R = uR_0
-        double gn = 0.0;
-        for (int k = 0; k < n1; ++k) gn += D[k] * uR[k];
-        gn += -iw0 * (0.5 * (uR[0] + u[N]) - uR[0]);
-        const double fnr = uR[0] * av - (J * gn) * nu;
+        // right face: Rusanov with u_L = u_N, u_R = uR_0 (BR1: and the
+        // neighbour's lifted-gradient flux)
+        double fnr = uR[0] * av;
+        if (!sipg) {
+            double gn = 0.0;
+            for (int k = 0; k < n1; ++k) gn += D[k] * uR[k];
+            gn += -iw0 * (0.5 * (uR[0] + u[N]) - uR[0]);
+            fnr -= (J * gn) * nu;
+        }
         acc[N] -= J * iw0 * (0.5 * (fnr - f[N]) + 0.5 * lam * (u[N] - uR[0]));
         // left face: u_L = uL_N, u_R = u_0
-        gn = 0.0;
-        for (int k = 0; k < n1; ++k) gn += D[N * n1 + k] * uL[k];
-        gn += iw0 * (0.5 * (uL[N] + u[0]) - uL[N]);
-        const double fnl = uL[N] * av - (J * gn) * nu;
+        double fnl = uL[N] * av;
+        if (!sipg) {
+            double gn = 0.0;
+            for (int k = 0; k < n1; ++k) gn += D[N * n1 + k] * uL[k];
+            gn += iw0 * (0.5 * (uL[N] + u[0]) - uL[N]);
+            fnl -= (J * gn) * nu;
+        }
         acc[0] += J * iw0 * (0.5 * (fnl - f[0]) + 0.5 * lam * (uL[N] - u[0]));
+        if (sipg && nu != 0.0) {
+            double du[8];
+            for (int q = 0; q < n1; ++q) {
+                du[q] = 0.0;
+                for (int k = 0; k < n1; ++k) du[q] += D[q * n1 + k] * u[k];
+            }
+            double dR = 0.0, dL = 0.0;   // the neighbours' derivatives at the shared faces
+            for (int k = 0; k < n1; ++k) {
+                dR += D[k] * uR[k];
+                dL += D[N * n1 + k] * uL[k];
+            }
+            const double jR = u[N] - uR[0], jL = uL[N] - u[0];
+            for (int i = 0; i < n1; ++i) {
+                double vol = 0.0;
+                for (int q = 0; q < n1; ++q) vol += w[q] * D[q * n1 + i] * du[q];
+                acc[i] += -nu * J * J * vol / w[i] + 0.5 * nu * J * J * (D[N * n1 + i] * jR + D[i] * jL) / w[i];
+            }
+            acc[N] += nu * (J / w[N]) * 0.5 * J * (du[N] + dR) - sig * (J / w[N]) * jR;
+            acc[0] += -nu * (J / w[0]) * 0.5 * J * (du[0] + dL) + sig * (J / w[0]) * jL;
+        }
     };
     double M[3][8][8];   // [input line][row i][column k]
     for (int which = 0; which < 3; ++which)
@@ -203,6 +262,13 @@ static void line_operator(const Problem& pb, int a, double* out) {
             double acc[8];
             apply(in[0], in[1], in[2], acc);
             for (int i = 0; i < n1; ++i) M[which][i][k] = acc[i];
+        }
+    // the kernel keeps only the last column and first row of BL (first
+    // column and last row of BR): anything else would be lost
+    for (int i = 0; i < n1; ++i)
+        for (int k = 0; k < n1; ++k) {
+            if (!(k == N || i == 0) && M[1][i][k] != 0.0) std::abort();
+            if (!(k == 0 || i == N) && M[2][i][k] != 0.0) std::abort();
         }
     double* A = out;
     double* HL = A + n1 * n1;
@@ -219,6 +285,27 @@ static void line_operator(const Problem& pb, int a, double* out) {
     for (int m = 1; m < n1; ++m) {
         FL[m] = M[1][0][N - m];   // row 0: left neighbour's node at distance m from its face
         FR[m] = M[2][N][m];       // row N: right neighbour's node at distance m
+    }
+}
+
+// The line operators of the descriptor: constant velocity, one per axis at
+// stride LIN_AXIS; rotating velocity (2D), three parts per axis (viscous,
+// central advection per unit velocity, dissipation per unit speed) packed
+// at stride n1^2 + 4 n1.
+static void line_operators(const Problem& pb, double* lin) {
+    const double nu = pb.eq.kind == ST_ADVECTION ? 0.0 : pb.P.nu;
+    if (!pb.ops->rot) {
+        for (int a = 0; a < pb.mesh.dim; ++a) {
+            const double av = pb.P.a[a];
+            line_operator_parts(pb, a, av, std::fabs(av), nu, lin + a * LIN_AXIS);
+        }
+        return;
+    }
+    const int LA = pb.n1 * pb.n1 + 4 * pb.n1;
+    for (int a = 0; a < pb.mesh.dim; ++a) {
+        line_operator_parts(pb, a, 0.0, 0.0, nu, lin + (a * 3 + 0) * LA);
+        line_operator_parts(pb, a, 1.0, 0.0, 0.0, lin + (a * 3 + 1) * LA);
+        line_operator_parts(pb, a, 0.0, 1.0, 0.0, lin + (a * 3 + 2) * LA);
     }
 }
 
@@ -266,8 +353,13 @@ OpSeg base_opseg(const Problem& pb, double dt) {
     for (int a = 0; a < 2; ++a) div_magic(pb.K[a], s.dm[a], s.ds[a]);
     set_tiles(s, pb, 12);
     s.iw0 = 1.0 / pb.wx[0];
-    if (linear_eq(pb.eq.kind))
-        for (int a = 0; a < pb.mesh.dim; ++a) line_operator(pb, a, s.lin + a * LIN_AXIS);
+    if (linear_eq(pb.eq.kind)) line_operators(pb, s.lin);
+    for (int a = 0; a < 2; ++a) {
+        s.lo[a] = pb.mesh.lo[a];
+        s.center[a] = pb.eq.center[a];
+    }
+    std::memcpy(s.xi, pb.xi, sizeof(s.xi));
+    s.omega = pb.eq.omega;
     s.P = pb.P;
     s.dt = dt;
     s.blk0 = 0;
@@ -485,9 +577,103 @@ static bool invert_dense(std::vector<double>& A, int n) {
     return true;
 }
 
+// Element diagonal block of the slab Jacobian of the scalar equations,
+// assembled on the host.  The own-element part of the spatial operator is the
+// Kronecker sum of the own-line operators A_a of line_operator_parts (the
+// neighbours' lines excluded), sum_a I (x) .. (x) A_a (x) .. (x) I, so with
+// the DG time discretisation (eq. DG_in_time; its Jacobian, eq. Jacobian_ST,
+// in this library's node order [j][s]):
+//   B[(j,s),(k,s')] = (-w_j Dtau[j][k] - delta_j0 delta_k0) delta_ss'
+//                     + (dt/2) w_j delta_jk A_elem[s][s'].
+// Burgers: the Jacobian at the constant state u_bar, which is the advection
+// operator with velocity u_bar and Rusanov speed |u_bar| (the jump term of
+// the linearised wave speed vanishes at a constant state).
+static std::vector<double> scalar_block(const Problem& pb, double dt, double ubar) {
+    const int d = pb.mesh.dim, n1 = pb.n1, ns = pb.ns, Nt = pb.Nt, npe = Nt * ns;
+    const bool burgers = pb.eq.kind == ST_BURGERS;
+    const double nu = (pb.eq.kind == ST_ADVECTION || burgers) ? 0.0 : pb.P.nu;
+    std::vector<double> Aa((size_t)3 * LIN_AXIS);
+    for (int a = 0; a < d; ++a) {
+        const double av = burgers ? ubar : pb.P.a[a];
+        line_operator_parts(pb, a, av, std::fabs(av), nu, Aa.data() + a * LIN_AXIS);
+    }
+    std::vector<double> Ael((size_t)ns * ns, 0.0);
+    for (int s = 0; s < ns; ++s)
+        for (int t = 0; t < ns; ++t)
+            for (int a = 0, st = 1; a < d; ++a, st *= n1) {
+                bool same = true;
+                for (int b = 0, sb = 1; b < d; ++b, sb *= n1)
+                    if (b != a && (s / sb) % n1 != (t / sb) % n1) same = false;
+                if (same) Ael[(size_t)s * ns + t] += Aa[a * LIN_AXIS + ((s / st) % n1) * n1 + (t / st) % n1];
+            }
+    std::vector<double> B((size_t)npe * npe, 0.0);
+    for (int j = 0; j < Nt; ++j)
+        for (int k = 0; k < Nt; ++k) {
+            const double tjk = -pb.wt[j] * pb.Dt[j * Nt + k] - (j == 0 && k == 0 ? 1.0 : 0.0);
+            for (int s = 0; s < ns; ++s) {
+                B[(size_t)(j * ns + s) * npe + k * ns + s] += tjk;
+                if (j == k)
+                    for (int t = 0; t < ns; ++t)
+                        B[(size_t)(j * ns + s) * npe + k * ns + t] += 0.5 * dt * pb.wt[j] * Ael[(size_t)s * ns + t];
+            }
+        }
+    return B;
+}
+
+// Mean state u_bar of u_prev (quadrature-weighted, per variable) and the
+// largest |u_prev| per variable, from host data [E][nv][ns].
+static void mean_state(const Problem& pb, const double* up, std::vector<double>& ubar, std::vector<double>& amax) {
+    const int d = pb.mesh.dim;
+    std::vector<double> W(pb.ns);
+    for (int sn = 0; sn < pb.ns; ++sn) {
+        W[sn] = 1.0;
+        for (int a = 0, q = sn; a < d; ++a, q /= pb.n1) W[sn] *= pb.wx[q % pb.n1];
+    }
+    ubar.assign(pb.nv, 0.0);
+    amax.assign(pb.nv, 0.0);
+    double wsum = 0.0;
+    for (int sn = 0; sn < pb.ns; ++sn) wsum += W[sn];
+    for (int64_t e = 0; e < pb.E; ++e)
+        for (int v = 0; v < pb.nv; ++v) {
+            const double* ue = up + (e * pb.nv + v) * pb.ns;
+            double t = 0.0;
+            for (int sn = 0; sn < pb.ns; ++sn) {
+                t += W[sn] * ue[sn];
+                amax[v] = std::max(amax[v], std::fabs(ue[sn]));
+            }
+            ubar[v] += t;
+        }
+    for (int v = 0; v < pb.nv; ++v) ubar[v] /= wsum * (double)pb.E;
+}
+
+namespace stdg {
+// B^-1 of the scalar equations packed for the matrix-core kernel (host only;
+// u_prev on the host, used for Burgers' mean state).  ST_ERR_UNSUPPORTED for
+// a singular block, a rotating velocity or an element block above the limit.
+int scalar_block_inverse(const Problem& pb, const double* up_host, double dt, std::vector<double>& packed) {
+    const int npe = (int)(pb.nv * pb.Nt * pb.ns);
+    if (npe > PC_NPE_MAX) return set_error(ST_ERR_UNSUPPORTED, "element block larger than the preconditioner supports");
+    if (pb.ops->rot)
+        return set_error(ST_ERR_UNSUPPORTED, "element-block Jacobi needs the same block in every element "
+                                             "(not so with a rotating velocity)");
+    double ubar = 0.0;
+    if (pb.eq.kind == ST_BURGERS) {
+        std::vector<double> ub, am;
+        mean_state(pb, up_host, ub, am);
+        ubar = ub[0];
+        if (!std::isfinite(ubar)) return set_error(ST_ERR_BAD_ARG, "preconditioner setup: u_prev is not finite");
+    }
+    std::vector<double> B = scalar_block(pb, dt, ubar);
+    if (!invert_dense(B, npe)) return set_error(ST_ERR_UNSUPPORTED, "element block of the Jacobian is singular");
+    packed = pc_pack(B, npe);
+    return ST_OK;
+}
+}  // namespace stdg
+
 // Element diagonal block B of the slab Jacobian and its inverse, for this
-// handle's (mesh spacing, N, Nt, equation) and dt.  B is read off the JVP
-// applied to the npe unit vectors of element 0 of a periodic 3^d-element mesh
+// handle's (mesh spacing, N, Nt, equation) and dt.  The scalar equations
+// assemble B on the host (scalar_block).  Euler and Navier-Stokes read B off
+// the JVP applied to the npe unit vectors of element 0 of a periodic 3^d-element mesh
 // with the same spacing (so the element's neighbours are distinct elements
 // and B excludes their coupling).  Linear equations: the Jacobian is the same
 // in every element.  Nonlinear equations: the Jacobian at the constant state
@@ -501,43 +687,43 @@ static int ensure_precond(st_ctx* h, const double* u_prev, double dt, hipStream_
     const bool lin = linear_eq(pb.eq.kind);
     const int npe = (int)(pb.nv * pb.Nt * pb.ns);
     if (npe > PC_NPE_MAX) return set_error(ST_ERR_UNSUPPORTED, "element block larger than the preconditioner supports");
+    if (pb.ops->rot)
+        return set_error(ST_ERR_UNSUPPORTED, "element-block Jacobi needs the same block in every element "
+                                             "(not so with a rotating velocity)");
     if (!h->pz) CHK(h->alloc(&h->pz, (size_t)pb.n * h->cap));
     const int d = pb.mesh.dim;
     // nonlinear: the reference state u_bar, the quadrature-weighted mean of
     // u_prev (the block is rebuilt when it moves beyond round-off)
-    std::vector<double> ubar;
+    std::vector<double> ubar, up;
     if (!lin) {
         const int64_t nprev = pb.E * pb.nv * pb.ns;
-        std::vector<double> up((size_t)nprev);
+        up.resize((size_t)nprev);
         HIPCHK(hipMemcpyAsync(up.data(), u_prev, sizeof(double) * nprev, hipMemcpyDeviceToHost, st));
         HIPCHK(hipStreamSynchronize(st));
-        std::vector<double> W(pb.ns);
-        for (int sn = 0; sn < pb.ns; ++sn) {
-            W[sn] = 1.0;
-            for (int a = 0, q = sn; a < d; ++a, q /= pb.n1) W[sn] *= pb.wx[q % pb.n1];
-        }
-        ubar.assign(pb.nv, 0.0);
-        std::vector<double> amax(pb.nv, 0.0);
-        double wsum = 0.0;
-        for (int sn = 0; sn < pb.ns; ++sn) wsum += W[sn];
-        for (int64_t e = 0; e < pb.E; ++e)
-            for (int v = 0; v < pb.nv; ++v) {
-                const double* ue = up.data() + (e * pb.nv + v) * pb.ns;
-                double t = 0.0;
-                for (int sn = 0; sn < pb.ns; ++sn) {
-                    t += W[sn] * ue[sn];
-                    amax[v] = std::max(amax[v], std::fabs(ue[sn]));
-                }
-                ubar[v] += t;
-            }
+        std::vector<double> amax;
+        mean_state(pb, up.data(), ubar, amax);
         bool same = h->binvT && h->pc_dt == dt && (int)h->pc_ubar.size() == pb.nv;
         for (int v = 0; v < pb.nv; ++v) {
-            ubar[v] /= wsum * (double)pb.E;
             if (!std::isfinite(ubar[v])) return set_error(ST_ERR_BAD_ARG, "preconditioner setup: u_prev is not finite");
             if (same && std::fabs(ubar[v] - h->pc_ubar[v]) > 1e-12 * std::max(amax[v], 1e-300)) same = false;
         }
         if (same) return ST_OK;
     } else if (h->binvT && h->pc_dt == dt) {
+        return ST_OK;
+    }
+    if (pb.nv == 1) {
+        // scalar equations: the block assembled on the host
+        std::vector<double> packed;
+        CHK(scalar_block_inverse(pb, up.data(), dt, packed));
+        if (pc_prepare(npe) != hipSuccess)
+            return set_error(ST_ERR_UNSUPPORTED, "element block needs more LDS than the device grants");
+        if (!h->binvT) {
+            CHK(h->alloc(&h->binvT, packed.size()));
+            CHK(h->alloc(&h->d_pc, 2));
+        }
+        HIPCHK(hipMemcpy(h->binvT, packed.data(), sizeof(double) * packed.size(), hipMemcpyHostToDevice));
+        h->pc_dt = dt;
+        h->pc_ubar = ubar;
         return ST_OK;
     }
     if (pc_prepare(npe) != hipSuccess)

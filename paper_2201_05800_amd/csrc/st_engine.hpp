@@ -5,6 +5,7 @@
 #include "st_krylov.hpp"
 
 #include <string>
+#include <vector>
 
 namespace stdg {
 
@@ -29,12 +30,15 @@ inline int op_blocks(const Problem& pb) {
 
 int set_error(int code, const std::string& msg);
 void lgl_tables(int n, double* x, double* w, double* D);
-const OpTable* find_table(int eq, int dim, int n1, int nt);
+const OpTable* find_table(int eq, int dim, int n1, int nt, bool rot = false);
 int make_problem(const st_mesh_t* mesh, int N, int Nt, const st_equation_t* eq, Problem& pb);
 OpSeg base_opseg(const Problem& pb, double dt);
 // the viscous pass's block traversal (narrower 3D columns than the operator's)
 void visc_tiles(OpSeg& s, const Problem& pb);
 DynPtr dptr(const void* p);
+// B^-1 of a scalar equation's element block (host only), packed for the
+// matrix-core kernel; up_host: u_prev on the host (Burgers' mean state)
+int scalar_block_inverse(const Problem& pb, const double* up_host, double dt, std::vector<double>& packed);
 DynPtr dptr_k(const void* base, int64_t ld, const int* kp);
 
 }  // namespace stdg

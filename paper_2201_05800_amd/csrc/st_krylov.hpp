@@ -78,6 +78,7 @@ using OpLaunch = void (*)(const OpSeg*, int, int, hipStream_t);
 // Kernels of one (equation, dim, N+1, Nt).
 struct OpTable {
     int eq, dim, n1, nt, epb;
+    int rot;             // 1: the rotating-velocity entry (res64 / lin32 are the ROT kernels)
     OpLaunch res64;      // residual, FP64
     OpLaunch lin32;      // linear equations: R(v) with u_prev = 0 in FP32 (FP32-inner JVP)
     OpLaunch jvp64;      // nonlinear JVP, FP64
@@ -86,6 +87,10 @@ struct OpTable {
     OpLaunch visc_res64; // of U (double), for the residual
     OpLaunch visc_jvp64; // its tangent at (U, v), double
     OpLaunch visc_jvp32; // its tangent at (U32, v), float
+    // linear equations in 2D, n1 <= 5: the rotating-velocity variants of
+    // res64 / lin32 (line operator in three parts, b_a per line)
+    OpLaunch res64_rot;
+    OpLaunch lin32_rot;
 };
 
 void register_ops_adv(std::vector<OpTable>& t);

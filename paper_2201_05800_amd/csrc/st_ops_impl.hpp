@@ -626,8 +626,14 @@ __global__ __launch_bounds__((Shape<D, N1, NT, tpt_of(EQ, NT)>::BS)) void k_op(c
 //   2. end nodes add their face-point terms; DG in time (eq. DG_in_time);
 //      store.
 // The JVP of these equations is this kernel on v with u_prev = 0.
+// ROT (2D): the rotating velocity b = a + omega e_z x (x - center); b_a is
+// the same at every node of a line along axis a (it depends on the other
+// coordinate only), so the line operator is Av + b_a Ac + |b_a| Ad, with the
+// three parts in the descriptor and b_a formed per line.  FL / FR (the
+// neighbour's interior nodes) come from the viscous part only: the advection
+// flux sees the neighbour's face value alone.
 // ---------------------------------------------------------------------------
-template <int EQ, int D, int N1, int NT, class CT, class UT>
+template <int EQ, int D, int N1, int NT, class CT, class UT, bool ROT = false>
 __global__ __launch_bounds__((Shape<D, N1, NT, NT>::BS)) void k_lin(const OpSeg* __restrict__ segs, int nseg, int G) {
     using SH = Shape<D, N1, NT, NT>;
     constexpr int NS = SH::NS, NPE = SH::NPE, NF = SH::NF;
@@ -637,8 +643,10 @@ __global__ __launch_bounds__((Shape<D, N1, NT, NT>::BS)) void k_lin(const OpSeg*
     constexpr int PER_AX = EPB * 2 * NF;            // face points per axis
     constexpr int NFP = D * PER_AX;                 // (axis, element, side, face node)
     constexpr int NH = NFP * NT;                    // face-point values, all time nodes
-    constexpr int LA = N1 * N1 + 4 * N1;            // line-operator entries per axis
-    constexpr int NTAB = D * LA;
+    constexpr int LA = N1 * N1 + 4 * N1;            // line-operator entries per axis (per part)
+    constexpr int NP = ROT ? 3 : 1;                 // parts per axis
+    static_assert(!ROT || (D == 2 && N1 <= ROT_MAX_N1), "rotating velocity: 2D, n1 <= 5");
+    constexpr int NTAB = D * NP * LA;
     constexpr int NQ = (NTAB + BS - 1) / BS;
     __shared__ CT tile[NL];                         // [element][time][spatial node]
     __shared__ CT halo[NH];                         // [face point][j]: neighbour's face value
@@ -704,7 +712,7 @@ __global__ __launch_bounds__((Shape<D, N1, NT, NT>::BS)) void k_lin(const OpSeg*
     };
     auto fp_compute = [&](int p, const FPI& fi, const CT (&nl)[NT][N]) {
         if (!fi.ok) return;
-        const CT* Fs = sL + fi.a * LA + N1 * N1 + 2 * N1 + fi.side * N1;   // FL or FR
+        const CT* Fs = sL + fi.a * NP * LA + N1 * N1 + 2 * N1 + fi.side * N1;   // FL or FR (viscous part)
         if (fi.local) {
             // the neighbour's line from the tile (after the first barrier)
             const CT* ln = tile + (fi.en - e0) * LP + fi.rn;
@@ -732,8 +740,12 @@ __global__ __launch_bounds__((Shape<D, N1, NT, NT>::BS)) void k_lin(const OpSeg*
 #pragma unroll
     for (int q = 0; q < NQ; ++q) {
         const int t = tid + q * BS;
-        const int a = t < NTAB ? (int)((unsigned)t / LA) : 0;
-        tL[q] = CT(sg.lin[t < NTAB ? a * LIN_AXIS + (t - a * LA) : 0]);
+        if constexpr (ROT) {
+            tL[q] = CT(sg.lin[t < NTAB ? t : 0]);        // packed parts
+        } else {
+            const int a = t < NTAB ? (int)((unsigned)t / LA) : 0;
+            tL[q] = CT(sg.lin[t < NTAB ? a * LIN_AXIS + (t - a * LA) : 0]);
+        }
     }
     const CT tDt = CT(sg.Dt[tid < NT * NT ? tid : 0]);
     const CT twt = CT(sg.wt[tid < NT ? tid : 0]);
@@ -788,11 +800,29 @@ __global__ __launch_bounds__((Shape<D, N1, NT, NT>::BS)) void k_lin(const OpSeg*
             constexpr int a = decltype(A)::value;
             constexpr int stride = ipow_c<N1, a>;
             const int ia = ic[a];
-            const CT* La = sL + a * LA;
+            const CT* La = sL + a * NP * LA;
             CT Ar[N1];
+            CT hl, hr;
+            if constexpr (ROT) {
+                // b_a of this line: axis 0 depends on y, axis 1 on x
+                const int ob = 1 - a;
+                const int eb = ecoord(sg, e).c[ob];
+                const double xo = sg.lo[ob] + (2.0 / sg.rh[ob]) * (eb + 0.5 * (1.0 + sg.xi[ic[ob]]));
+                const double bd = a == 0 ? sg.P.a[0] - sg.omega * (xo - sg.center[1])
+                                         : sg.P.a[1] + sg.omega * (xo - sg.center[0]);
+                const CT b = CT(bd), ab = CT(fabs(bd));
+                const CT* Lc = La + LA;
+                const CT* Ld = La + 2 * LA;
 #pragma unroll
-            for (int k = 0; k < N1; ++k) Ar[k] = La[ia * N1 + k];
-            const CT hl = La[N1 * N1 + ia], hr = La[N1 * N1 + N1 + ia];
+                for (int k = 0; k < N1; ++k) Ar[k] = La[ia * N1 + k] + b * Lc[ia * N1 + k] + ab * Ld[ia * N1 + k];
+                hl = La[N1 * N1 + ia] + b * Lc[N1 * N1 + ia] + ab * Ld[N1 * N1 + ia];
+                hr = La[N1 * N1 + N1 + ia] + b * Lc[N1 * N1 + N1 + ia] + ab * Ld[N1 * N1 + N1 + ia];
+            } else {
+#pragma unroll
+                for (int k = 0; k < N1; ++k) Ar[k] = La[ia * N1 + k];
+                hl = La[N1 * N1 + ia];
+                hr = La[N1 * N1 + N1 + ia];
+            }
             const int f = face_of(a);
             const CT* hL = halo + fpi(a, el, 0, f) * NT;
             const CT* hR = halo + fpi(a, el, 1, f) * NT;
@@ -1000,9 +1030,9 @@ template <int EQ, int D, int N1, int NT, class CT, class UT, bool JVP>
 void launch_op(const OpSeg* segs, int nseg, int G, hipStream_t st) {
     launch_k(k_op<EQ, D, N1, NT, CT, UT, JVP>, dim3(G), dim3(Shape<D, N1, NT, tpt_of(EQ, NT)>::BS), st, segs, nseg, G);
 }
-template <int EQ, int D, int N1, int NT, class CT, class UT>
+template <int EQ, int D, int N1, int NT, class CT, class UT, bool ROT = false>
 void launch_lin(const OpSeg* segs, int nseg, int G, hipStream_t st) {
-    launch_k(k_lin<EQ, D, N1, NT, CT, UT>, dim3(G), dim3(Shape<D, N1, NT, NT>::BS), st, segs, nseg, G);
+    launch_k(k_lin<EQ, D, N1, NT, CT, UT, ROT>, dim3(G), dim3(Shape<D, N1, NT, NT>::BS), st, segs, nseg, G);
 }
 template <int D, int N1, int NT, class CT, class UT, bool JVP>
 void launch_visc(const OpSeg* segs, int nseg, int G, hipStream_t st) {
@@ -1016,6 +1046,10 @@ OpTable make_table() {
     if constexpr (linear_eq(EQ)) {
         t.res64 = launch_lin<EQ, D, N1, NT, double, double>;
         t.lin32 = launch_lin<EQ, D, N1, NT, float, double>;
+        if constexpr (D == 2 && N1 <= ROT_MAX_N1) {
+            t.res64_rot = launch_lin<EQ, D, N1, NT, double, double, true>;
+            t.lin32_rot = launch_lin<EQ, D, N1, NT, float, double, true>;
+        }
     } else {
         t.res64 = launch_op<EQ, D, N1, NT, double, double, false>;
         t.jvp64 = launch_op<EQ, D, N1, NT, double, double, true>;

@@ -10,6 +10,10 @@
 //   4. enqueues one GMRES cycle for the rest: per Arnoldi step one JVP launch
 //      per (group, precision) and batched multi-dot / update / normalise
 //      launches over all of them, then the Newton update.
+// Requests of the scalar equations may ask for the element-block Jacobi
+// preconditioner (right preconditioning, as in st_solve_slab): the block
+// inverse is assembled on the submitting thread, uploaded at admission, and
+// applied per Arnoldi step by one launch per block size.
 // Requests that arrive while a tick runs are admitted at the next tick.  The
 // per-request arithmetic is the single-slab driver's, with reductions that
 // depend only on the request's own size, so results are bitwise independent
@@ -80,7 +84,7 @@ struct Arena {
 };
 
 struct Layout {
-    int64_t U, R, w, V, uprev, unext, Q, dQ, U32, dQ32, part, total;
+    int64_t U, R, w, V, uprev, unext, Q, dQ, U32, dQ32, part, pz, binv, total;
 };
 
 Layout layout_of(const Problem& pb, const st_solver_opts_t& o) {
@@ -100,6 +104,11 @@ Layout layout_of(const Problem& pb, const st_solver_opts_t& o) {
     L.U32 = (fp32 && nonlin) ? take(4 * n) : -1;
     L.dQ32 = (fp32 && visc) ? take(4 * d * n) : -1;
     L.part = take(8 * (int64_t)vec_blocks(n) * (NPART_SLOTS + 1));
+    // element-block Jacobi: the preconditioned direction and B^-1 (packed)
+    const int npe = pb.nv * pb.Nt * pb.ns;
+    const int64_t pk = (int64_t)((npe + 15) / 16) * ((npe + 3) / 4) * 64;
+    L.pz = o.precond == 1 ? take(8 * n) : -1;
+    L.binv = o.precond == 1 ? take(8 * pk) : -1;
     L.total = off;
     return L;
 }
@@ -108,7 +117,7 @@ int check_opts(const st_solver_opts_t& o) {
     if (o.restart < 1 || o.restart > MMAX) return set_error(ST_ERR_BAD_ARG, "restart must be in 1..32");
     if (o.cgs_passes < 1 || o.cgs_passes > 2) return set_error(ST_ERR_BAD_ARG, "cgs_passes must be 1 or 2");
     if (o.max_newton < 1) return set_error(ST_ERR_BAD_ARG, "max_newton must be >= 1");
-    if (o.precond != 0) return set_error(ST_ERR_UNSUPPORTED, "preconditioning is available in st_solve_slab only");
+    if (o.precond < 0 || o.precond > 1) return set_error(ST_ERR_BAD_ARG, "precond must be 0 or 1");
     return ST_OK;
 }
 
@@ -121,6 +130,7 @@ struct Req {
     double t0, dt, tol;
     std::vector<double> uprev;
     std::vector<double> unext;
+    std::vector<double> binv;     // element-block Jacobi: B^-1 packed (until admitted)
     Layout lay;
     Phase phase = QUEUED;
     std::atomic<bool> cancel{false};
@@ -138,6 +148,8 @@ struct Req {
     double* dp(int64_t off) const { return off < 0 ? nullptr : (double*)(mem + off); }
     float* fp(int64_t off) const { return off < 0 ? nullptr : (float*)(mem + off); }
     bool fp32() const { return opts.inner_fp32 != 0; }
+    bool pc() const { return opts.precond == 1; }
+    int npe() const { return pb.nv * pb.Nt * pb.ns; }
 };
 
 }  // namespace
@@ -298,7 +310,9 @@ std::vector<OpGroup> build_jvp_groups(st_srv* s, const std::vector<Req*>& rs) {
             g = &gs.back();
         }
         GState* st = s->d_states + r->slot;
-        DynPtr Vk = dptr_k(r->dp(r->lay.V), pb.n, &st->k);
+        // the direction: V_k (following the device Arnoldi index), or with
+        // right preconditioning z = B^-1 V_k, formed before the launch
+        DynPtr Vk = r->pc() ? dptr(r->dp(r->lay.pz)) : dptr_k(r->dp(r->lay.V), pb.n, &st->k);
         OpSeg b = base_opseg(pb, r->dt);
         b.skip = &st->done;
         b.out = dptr(r->dp(r->lay.w));
@@ -386,9 +400,11 @@ bool tick(st_srv* s) {
     s->ticks += 1;
     hipStream_t st = s->stream;
 
-    // new requests: u_prev upload, state reset, initial guess
+    // new requests: u_prev (and B^-1) upload, state reset, initial guess
     for (Req* r : fresh) {
         (void)hipMemcpyAsync(r->dp(r->lay.uprev), r->uprev.data(), 8 * r->pb.nsp, hipMemcpyHostToDevice, st);
+        if (r->pc())
+            (void)hipMemcpyAsync(r->dp(r->lay.binv), r->binv.data(), 8 * r->binv.size(), hipMemcpyHostToDevice, st);
         (void)hipMemsetAsync(s->d_states + r->slot, 0, sizeof(GState), st);
     }
     // phase A: residual and norm of every active request
@@ -492,6 +508,57 @@ bool tick(st_srv* s) {
         g.off_grad = pb.add(g.grad);
         g.off_op = pb.add(g.op);
     }
+    // element-block Jacobi: z = B^-1 V_k before each JVP and U += B^-1 (V y)
+    // at the end, one launch per block size; the Newton update of the other
+    // requests stays U += V y
+    struct PcGroup {
+        int npe;
+        std::vector<PcSeg> step, upd;
+        int64_t off_step = 0, off_upd = 0;
+        int G = 0;
+    };
+    std::vector<PcGroup> pgroups;
+    std::vector<VecSeg> vpc, vplain;
+    for (Req* r : cont) {
+        if (!r->pc()) {
+            vplain.push_back(vecseg_of(s, r));
+            continue;
+        }
+        vpc.push_back(vecseg_of(s, r));
+        PcGroup* g = nullptr;
+        for (auto& x : pgroups)
+            if (x.npe == r->npe()) g = &x;
+        if (!g) {
+            pgroups.push_back(PcGroup{r->npe(), {}, {}, 0, 0, 0});
+            g = &pgroups.back();
+        }
+        GState* gs = s->d_states + r->slot;
+        PcSeg a;
+        std::memset(&a, 0, sizeof(a));
+        a.in = dptr_k(r->dp(r->lay.V), r->pb.n, &gs->k);
+        a.out = r->dp(r->lay.pz);
+        a.binvT = r->dp(r->lay.binv);
+        a.skip = &gs->done;
+        a.npe = r->npe();
+        a.E = (int)r->pb.E;
+        a.accumulate = 0;
+        a.nblk = pc_blocks(a.E, a.npe);
+        g->step.push_back(a);
+        PcSeg u = a;
+        u.in = dptr(r->dp(r->lay.w));
+        u.out = r->dp(r->lay.U);
+        u.skip = nullptr;
+        u.accumulate = 1;
+        g->upd.push_back(u);
+    }
+    for (auto& g : pgroups) {
+        g.G = assign_blocks(g.step);
+        assign_blocks(g.upd);
+        g.off_step = pb.add(g.step);
+        g.off_upd = pb.add(g.upd);
+    }
+    const int Gpc = assign_blocks(vpc), Gplain = assign_blocks(vplain);
+    const int64_t off_vpc = pb.add(vpc), off_vplain = pb.add(vplain);
     if (upload(s, 1, pb) != ST_OK) return true;
     char* D1 = s->d_stage[1];
     if (!v32.empty()) vk_cast32((VecSeg*)(D1 + off_v32), (int)v32.size(), G32, st);
@@ -501,6 +568,7 @@ bool tick(st_srv* s) {
     for (Req* r : cont) mmax = std::max(mmax, r->opts.restart);
     vk_scale_v0(dvc, nc, Gc, st);
     for (int k = 0; k < mmax; ++k) {
+        for (auto& g : pgroups) pc_apply((PcSeg*)(D1 + g.off_step), (int)g.step.size(), g.G, g.npe, st);
         for (auto& g : jgroups) {
             if (!g.grad.empty())
                 (g.fp32 ? g.ops->visc_jvp32 : g.ops->visc_jvp64)((OpSeg*)(D1 + g.off_grad), (int)g.grad.size(), g.G, st);
@@ -519,7 +587,11 @@ bool tick(st_srv* s) {
         }
     }
     vk_finish(dvc, nc, st);
-    vk_update_u(dvc, nc, Gc, st);
+    if (!vplain.empty()) vk_update_u((VecSeg*)(D1 + off_vplain), (int)vplain.size(), Gplain, st);
+    if (!vpc.empty()) {
+        pc_combine((VecSeg*)(D1 + off_vpc), (int)vpc.size(), Gpc, st);
+        for (auto& g : pgroups) pc_apply((PcSeg*)(D1 + g.off_upd), (int)g.upd.size(), g.G, g.npe, st);
+    }
     return true;
 }
 
@@ -613,6 +685,15 @@ int st_submit(st_server_t s, const st_request_t* req, uint64_t* ticket) {
     r->eta_rel = linear_eq(r->pb.eq.kind) ? 0.0 : std::max(r->opts.gmres_rtol, 0.0);
     if (r->fp32()) r->eta_rel = std::max(r->eta_rel, 1e-5);
     r->uprev.assign(req->u_prev, req->u_prev + r->pb.nsp);
+    if (r->pc()) {
+        // element-block Jacobi: scalar equations only (their block is
+        // assembled on the host, here, on the submitting thread)
+        if (r->pb.nv != 1) rc = set_error(ST_ERR_UNSUPPORTED, "served preconditioning: scalar equations only");
+        if (rc == ST_OK) rc = scalar_block_inverse(r->pb, r->uprev.data(), r->dt, r->binv);
+        if (rc == ST_OK && pc_prepare(r->npe()) != hipSuccess)
+            rc = set_error(ST_ERR_UNSUPPORTED, "element block needs more LDS than the device grants");
+        if (rc != ST_OK) { delete r; return rc; }
+    }
     {
         std::lock_guard<std::mutex> lk(s->mu);
         r->ticket = s->next_ticket++;

@@ -119,6 +119,17 @@ def euler_bubble_3d(X: np.ndarray, t=0.0, gamma=1.4) -> np.ndarray:
     return euler_conservative(rho, [vel[a] + 0.0 * rho for a in range(3)], 0.3 + 0.0 * rho, gamma)
 
 
+def rotating_pulse(X: np.ndarray, t=0.0, eps=1e-3) -> np.ndarray:
+    """The rotating pulse of Sec. "Experiments / Advection-Diffusion"
+    (analytic solution of eq. advdiffeq with b = (-4 y0, 4 x0), x0 = x - 0.5,
+    y0 = y - 0.5, diffusivity eps) at time t; shape (E, ns)."""
+    x0, y0 = X[:, 0, :] - 0.5, X[:, 1, :] - 0.5
+    xq = x0 * np.cos(4 * t) + y0 * np.sin(4 * t) + 0.25
+    yq = -x0 * np.sin(4 * t) + y0 * np.cos(4 * t)
+    s = 0.004 + 4 * eps * t
+    return 0.004 / s * np.exp(-(xq ** 2 + yq ** 2) / s)
+
+
 def cfl_dt(cfl: float, h_min: float, N: int, lam_max: float) -> float:
     """dt = CFL h_min / ((2N + 1) lambda_max)."""
     return cfl * h_min / ((2 * N + 1) * lam_max)

@@ -25,7 +25,7 @@ ST_ERR_UNSUPPORTED = -6
 ST_ERR_NOT_FOUND = -7
 ST_ERR_CANCELLED = -8
 
-ST_ADVECTION, ST_ADVDIFF_BR1, ST_BURGERS, ST_EULER, ST_NS_BR1 = 1, 2, 3, 4, 5
+ST_ADVECTION, ST_ADVDIFF_BR1, ST_BURGERS, ST_EULER, ST_NS_BR1, ST_ADVDIFF_SIPG = 1, 2, 3, 4, 5, 6
 ST_K_RESIDUAL, ST_K_JVP, ST_K_GRAD, ST_K_MULTIDOT, ST_K_UPDATE, ST_K_NORMALIZE, ST_K_NEWTON, ST_K_PRECOND = range(8)
 KERNEL_CLASSES = ("residual", "jvp", "grad", "multidot", "update", "normalize", "newton", "precond")
 
@@ -39,7 +39,8 @@ class Mesh(ctypes.Structure):
 
 class Equation(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int), ("a", ctypes.c_double * 3), ("nu", ctypes.c_double),
-                ("gamma", ctypes.c_double), ("mu", ctypes.c_double), ("prandtl", ctypes.c_double)]
+                ("gamma", ctypes.c_double), ("mu", ctypes.c_double), ("prandtl", ctypes.c_double),
+                ("omega", ctypes.c_double), ("center", ctypes.c_double * 3)]
 
 
 class SolverOpts(ctypes.Structure):
@@ -190,12 +191,15 @@ def mesh(dim, K, lo, hi) -> Mesh:
     return m
 
 
-def equation(kind, a=(0.0, 0.0, 0.0), nu=0.0, gamma=1.4, mu=0.0, prandtl=0.72) -> Equation:
+def equation(kind, a=(0.0, 0.0, 0.0), nu=0.0, gamma=1.4, mu=0.0, prandtl=0.72, omega=0.0,
+             center=(0.0, 0.0, 0.0)) -> Equation:
     e = Equation()
     e.kind = kind
     for i in range(3):
         e.a[i] = float(a[i]) if i < len(a) else 0.0
+        e.center[i] = float(center[i]) if i < len(center) else 0.0
     e.nu, e.gamma, e.mu, e.prandtl = nu, gamma, mu, prandtl
+    e.omega = float(omega)
     return e
 
 

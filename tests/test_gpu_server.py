@@ -110,6 +110,50 @@ def test_alone_vs_mix_bitwise(orc):
             P.close()
 
 
+def test_served_preconditioned_requests(orc):
+    """Element-block Jacobi in the server (scalar equations): preconditioned
+    and plain requests of both precisions served together; every result is
+    bitwise the single-slab driver's with the same options, matches the
+    oracle within 1e-9, and takes fewer Arnoldi steps than unpreconditioned."""
+    from paper_2201_05800_amd import st
+    cases = [("advdiff", advdiff_case(12, 3, 3), 0, 1), ("burgers", burgers_case(40, 3, 3, 1), 0, 1),
+             ("advdiff", advdiff_case(10, 4, 4), 1, 1), ("burgers", burgers_case(23, 5, 2, 2), 1, 1),
+             ("advdiff", advdiff_case(9, 2, 2), 0, 0), ("burgers", burgers_case(7, 2, 3, 4), 0, 1)]
+    pairs = [Pair(c) for _, c, _, _ in cases]
+    try:
+        reqs, ups, dts = [], [], []
+        for (kind, c, fp32, pc), P in zip(cases, pairs):
+            up = initial_for(P, kind, seed=5)
+            h = min((c["hi"][a] - c["lo"][a]) / c["K"][a] for a in range(c["dim"]))
+            lam = np.abs(up).max() if kind == "burgers" else np.sqrt(1.25)
+            dt = inputs.cfl_dt(5.0, h, c["N"], lam)
+            ups.append(up)
+            dts.append(dt)
+            reqs.append(make_req(st, c, up, dt, inner_fp32=fp32, precond=pc))
+        srv = st.st_server_create(hbm_budget_bytes=2 << 30, max_active=16)
+        try:
+            tks = [st.st_submit(srv, r) for r in reqs]
+            got = wait_all(st, srv, tks, [P.nsp for P in pairs])
+        finally:
+            st.st_server_destroy(srv)
+        for (kind, c, fp32, pc), P, up, dt, t in zip(cases, pairs, ups, dts, tks):
+            rc, u, res = got[t]
+            assert rc == st.ST_OK, (kind, rc)
+            _, un1, s1 = gpu_solve(P, up, dt, 1e-11, inner_fp32=fp32, precond=pc)
+            assert np.array_equal(un1, u), f"served {kind} differs from st_solve_slab (precond={pc})"
+            if pc:
+                _, _, s0 = gpu_solve(P, up, dt, 1e-11, inner_fp32=fp32, precond=0)
+                assert res["gmres_its"] < s0["gmres_its"], (kind, res, s0)
+            Uo, so = orc.solve(P.p, up, dt, tol=1e-13, dense_limit=0)
+            e = rel(u, orc.last_time_node(P.p, Uo))
+            say(f"served {kind} K={c['K']} N={c['N']} Nt={c['Nt']} fp32={fp32} precond={pc}: "
+                f"GMRES {res['gmres_its']}, rel err vs oracle {e:.2e}")
+            assert e <= 1e-9
+    finally:
+        for P in pairs:
+            P.close()
+
+
 def test_continuous_batching_overlap(orc):
     """A request submitted while another runs joins the running batch: it is
     admitted before the first one finishes (server timestamps), and both

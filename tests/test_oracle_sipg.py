@@ -17,6 +17,8 @@ import os
 import numpy as np
 import pytest
 
+from paper_2201_05800_amd import inputs
+
 GOLD = os.path.join(os.path.dirname(__file__), "golden")
 
 
@@ -146,13 +148,7 @@ def test_sipg_rotation_conservation(orc):
     assert abs(lhs - rhs) <= 1e-12 * np.abs(U).max() * 12
 
 
-def pulse_exact(X, t, eps=1e-3):
-    """Rotating pulse of eq. advdiffeq (analytic solution)."""
-    x0, y0 = X[:, 0, :] - 0.5, X[:, 1, :] - 0.5
-    xq = x0 * np.cos(4 * t) + y0 * np.sin(4 * t) + 0.25
-    yq = -x0 * np.sin(4 * t) + y0 * np.cos(4 * t)
-    s = 0.004 + 4 * eps * t
-    return 0.004 / s * np.exp(-(xq ** 2 + yq ** 2) / s)
+pulse_exact = inputs.rotating_pulse
 
 
 def pulse_error(orc, N, Nt):
