@@ -55,13 +55,17 @@ extern "C" {
 #define ST_MAX_SLABS 64            /* slabs of one multi-slab system           */
 #define ST_ERR_CANCELLED (-8)      /* ticket cancelled before completion      */
 
-/* Periodic Cartesian mesh, cf. cartesianDomain(lower, upper, counts) in
- * Sec. "DG-SEM in Space".  Every axis is periodic. */
+/* Cartesian mesh, cf. cartesianDomain(lower, upper, counts) in Sec.
+ * "DG-SEM in Space".  Axes are periodic unless bc[a] = 1: then both ends of
+ * axis a are Dirichlet boundaries with the exterior state bc_value of the
+ * equation (the boundary convective flux of the surface integral; the
+ * scalar linear equations only, constant velocity). */
 typedef struct {
     int dim;          /* 1, 2 or 3 */
     int K[3];         /* elements per axis (unused axes: 1) */
     double lo[3];     /* lower corner */
     double hi[3];     /* upper corner */
+    int bc[3];        /* 0: periodic (default), 1: Dirichlet */
 } st_mesh_t;
 
 /* u_t + div(Fc(u) - Fv(u, grad u)) = 0, eq. (general) without source. */
@@ -92,6 +96,10 @@ typedef struct {
      * component is continuous across every face, the periodic seams included. */
     double omega;
     double center[3];
+    /* exterior state g of Dirichlet boundaries (st_mesh_t.bc): the Rusanov
+     * flux with g, BR1 with u_hat = g and the interior viscous flux, the
+     * interior penalty by Nitsche's terms */
+    double bc_value;
 } st_equation_t;
 
 /* Newton-GMRES options (the paper names Newton-GMRES, Sec. "Euler

@@ -189,6 +189,11 @@ constexpr int LIN_AXIS = 8 * 8 + 4 * 8;
 // (viscous, central advection per unit velocity, Rusanov dissipation per
 // unit speed), packed with stride n1^2 + 4 n1, for n1 <= ROT_MAX_N1
 constexpr int ROT_MAX_N1 = 5;
+// Dirichlet boundaries (linear equations): per axis the own-line operators of
+// an element at the lower, the upper and both boundaries (n1^2 each), and the
+// exterior state's coefficients gL (lower), gR (upper), gL and gR of the
+// element at both boundaries (n1 each), packed with stride 3 n1^2 + 4 n1
+constexpr int LINB_AXIS = 3 * 8 * 8 + 4 * 8;
 
 // One slab instance inside an operator launch.
 struct OpSeg {
@@ -234,6 +239,11 @@ struct OpSeg {
     double xi[8];        // LGL nodes on [-1, 1]
     double omega;
     double center[2];
+    // Dirichlet boundaries: axes with bc[a] = 1, the exterior state (0 in a
+    // JVP: the linear part only), the boundary line operators
+    int bc[3];
+    double bcg;
+    double linb[3 * LINB_AXIS];
 };
 
 // One slab instance inside a vector (Krylov) launch.

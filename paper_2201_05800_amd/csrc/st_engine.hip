@@ -76,7 +76,7 @@ void lgl_tables(int n, double* x, double* w, double* D) {
 // penalty variant of advection-diffusion runs the same line-operator kernels
 // as BR1 (only the host-built line operator differs); the rotating-velocity
 // entries carry the three-part kernels of the linear equations.
-const OpTable* find_table(int eq, int dim, int n1, int nt, bool rot) {
+const OpTable* find_table(int eq, int dim, int n1, int nt, bool rot, bool bnd) {
     static std::vector<OpTable> tables;
     static std::once_flag once;
     std::call_once(once, [] {
@@ -87,17 +87,26 @@ const OpTable* find_table(int eq, int dim, int n1, int nt, bool rot) {
         register_ops_ns(tables);
         const size_t n0 = tables.size();
         for (size_t i = 0; i < n0; ++i) {
-            if (!tables[i].res64_rot) continue;
-            OpTable t = tables[i];
-            t.res64 = t.res64_rot;
-            t.lin32 = t.lin32_rot;
-            t.rot = 1;
-            tables.push_back(t);
+            if (tables[i].res64_rot) {
+                OpTable t = tables[i];
+                t.res64 = t.res64_rot;
+                t.lin32 = t.lin32_rot;
+                t.rot = 1;
+                tables.push_back(t);
+            }
+            if (tables[i].res64_bnd) {
+                OpTable t = tables[i];
+                t.res64 = t.res64_bnd;
+                t.lin32 = t.lin32_bnd;
+                t.bnd = 1;
+                tables.push_back(t);
+            }
         }
     });
     const int keq = eq == EQ_ADVDIFF_SIPG ? EQ_ADVDIFF : eq;
     for (const auto& t : tables)
-        if (t.eq == keq && t.dim == dim && t.n1 == n1 && t.nt == nt && (t.rot != 0) == rot) return &t;
+        if (t.eq == keq && t.dim == dim && t.n1 == n1 && t.nt == nt && (t.rot != 0) == rot && (t.bnd != 0) == bnd)
+            return &t;
     return nullptr;
 }
 
@@ -136,7 +145,17 @@ int make_problem(const st_mesh_t* mesh, int N, int Nt, const st_equation_t* eq, 
     if (!std::isfinite(eq->omega)) return set_error(ST_ERR_BAD_ARG, "omega must be finite");
     if (rot && (!linear_eq(eq->kind) || d != 2 || pb.n1 > ROT_MAX_N1))
         return set_error(ST_ERR_UNSUPPORTED, "a rotating velocity needs a linear equation in 2D with N <= 4");
-    pb.ops = find_table(eq->kind, d, pb.n1, Nt, rot);
+    bool bnd = false;
+    for (int a = 0; a < 3; ++a) {
+        const int b = a < d ? mesh->bc[a] : 0;
+        if (b != 0 && b != 1) return set_error(ST_ERR_BAD_ARG, "bc must be 0 (periodic) or 1 (Dirichlet)");
+        pb.mesh.bc[a] = b;
+        bnd = bnd || b == 1;
+    }
+    if (bnd && (!linear_eq(eq->kind) || rot))
+        return set_error(ST_ERR_UNSUPPORTED, "Dirichlet boundaries: the linear equations with a constant velocity");
+    if (bnd && !std::isfinite(eq->bc_value)) return set_error(ST_ERR_BAD_ARG, "bc_value must be finite");
+    pb.ops = find_table(eq->kind, d, pb.n1, Nt, rot, bnd);
     if (!pb.ops)
         return set_error(ST_ERR_UNSUPPORTED, "(equation, dim, N, Nt) = (" + std::to_string(eq->kind) + ", " +
                                                  std::to_string(d) + ", " + std::to_string(N) + ", " +
@@ -187,7 +206,14 @@ static void div_magic(int d, unsigned& m, int& sh) {
 //              nu {u'} (end row), the symmetry term nu/2 J^2 M^-1 D^T e (jump)
 //              (every row), the penalty -sigma J/w (jump) (end row).
 // `av` is the velocity, `lam` the Rusanov wave speed, `nu` the diffusivity.
-static void line_operator_parts(const Problem& pb, int a, double av, double lam, double nu, double* out) {
+// The line operator as a function of the line u, the neighbours' lines uL,
+// uR and, at a Dirichlet boundary (bl: lower end, br: upper end), the
+// exterior state gv in place of that neighbour: the Rusanov flux with gv,
+// BR1 with u_hat = gv and the own viscous flux, SIPG by Nitsche's terms
+// (the face terms with the own derivative instead of the average, gv instead
+// of the neighbour's face value, the symmetry term at full weight).
+static void line_apply(const Problem& pb, int a, double av, double lam, double nu, const double* u,
+                       const double* uL, const double* uR, bool bl, bool br, double gv, double* acc) {
     const int n1 = pb.n1, N = n1 - 1;
     const double J = 2.0 / pb.h[a];
     const bool sipg = pb.eq.kind == ST_ADVDIFF_SIPG;
@@ -196,63 +222,102 @@ static void line_operator_parts(const Problem& pb, int a, double av, double lam,
     const double iw0 = 1.0 / pb.wx[0];
     const double* D = pb.Dx;
     const double* w = pb.wx;
-    auto apply = [&](const double* u, const double* uL, const double* uR, double* acc) {
-        double g[8], f[8];
-        if (!sipg) {
-            for (int i = 0; i < n1; ++i) {
-                g[i] = 0.0;
-                for (int k = 0; k < n1; ++k) g[i] += D[i * n1 + k] * u[k];
-            }
-            g[0] += -iw0 * (0.5 * (u[0] + uL[N]) - u[0]);
-            g[N] += iw0 * (0.5 * (u[N] + uR[0]) - u[N]);
-            for (int i = 0; i < n1; ++i) f[i] = u[i] * av - (J * g[i]) * nu;
-        } else {
-            for (int i = 0; i < n1; ++i) f[i] = u[i] * av;
-        }
+    const double uLf = bl ? gv : uL[N], uRf = br ? gv : uR[0];     // the states across the two faces
+    double g[8], f[8];
+    if (!sipg) {
         for (int i = 0; i < n1; ++i) {
-            double sv = 0.0;
-            for (int k = 0; k < n1; ++k) sv += D[i * n1 + k] * f[k];
-            acc[i] = -J * sv;
+            g[i] = 0.0;
+            for (int k = 0; k < n1; ++k) g[i] += D[i * n1 + k] * u[k];
         }
-        // right face: Rusanov with u_L = u_N, u_R = uR_0 (BR1: and the
-        // neighbour's lifted-gradient flux)
-        double fnr = uR[0] * av;
-        if (!sipg) {
+        g[0] += -iw0 * ((bl ? gv : 0.5 * (u[0] + uL[N])) - u[0]);
+        g[N] += iw0 * ((br ? gv : 0.5 * (u[N] + uR[0])) - u[N]);
+        for (int i = 0; i < n1; ++i) f[i] = u[i] * av - (J * g[i]) * nu;
+    } else {
+        for (int i = 0; i < n1; ++i) f[i] = u[i] * av;
+    }
+    for (int i = 0; i < n1; ++i) {
+        double sv = 0.0;
+        for (int k = 0; k < n1; ++k) sv += D[i * n1 + k] * f[k];
+        acc[i] = -J * sv;
+    }
+    // upper face: Rusanov with u_L = u_N, u_R = uR_0 (BR1: and the
+    // neighbour's lifted-gradient flux; at a boundary the own one)
+    double fnr = uRf * av;
+    if (!sipg) {
+        if (br) {
+            fnr -= (J * g[N]) * nu;
+        } else {
             double gn = 0.0;
             for (int k = 0; k < n1; ++k) gn += D[k] * uR[k];
             gn += -iw0 * (0.5 * (uR[0] + u[N]) - uR[0]);
             fnr -= (J * gn) * nu;
         }
-        acc[N] -= J * iw0 * (0.5 * (fnr - f[N]) + 0.5 * lam * (u[N] - uR[0]));
-        // left face: u_L = uL_N, u_R = u_0
-        double fnl = uL[N] * av;
-        if (!sipg) {
+    }
+    acc[N] -= J * iw0 * (0.5 * (fnr - f[N]) + 0.5 * lam * (u[N] - uRf));
+    // lower face: u_L = uL_N, u_R = u_0
+    double fnl = uLf * av;
+    if (!sipg) {
+        if (bl) {
+            fnl -= (J * g[0]) * nu;
+        } else {
             double gn = 0.0;
             for (int k = 0; k < n1; ++k) gn += D[N * n1 + k] * uL[k];
             gn += iw0 * (0.5 * (uL[N] + u[0]) - uL[N]);
             fnl -= (J * gn) * nu;
         }
-        acc[0] += J * iw0 * (0.5 * (fnl - f[0]) + 0.5 * lam * (uL[N] - u[0]));
-        if (sipg && nu != 0.0) {
-            double du[8];
-            for (int q = 0; q < n1; ++q) {
-                du[q] = 0.0;
-                for (int k = 0; k < n1; ++k) du[q] += D[q * n1 + k] * u[k];
-            }
-            double dR = 0.0, dL = 0.0;   // the neighbours' derivatives at the shared faces
-            for (int k = 0; k < n1; ++k) {
-                dR += D[k] * uR[k];
-                dL += D[N * n1 + k] * uL[k];
-            }
-            const double jR = u[N] - uR[0], jL = uL[N] - u[0];
-            for (int i = 0; i < n1; ++i) {
-                double vol = 0.0;
-                for (int q = 0; q < n1; ++q) vol += w[q] * D[q * n1 + i] * du[q];
-                acc[i] += -nu * J * J * vol / w[i] + 0.5 * nu * J * J * (D[N * n1 + i] * jR + D[i] * jL) / w[i];
-            }
-            acc[N] += nu * (J / w[N]) * 0.5 * J * (du[N] + dR) - sig * (J / w[N]) * jR;
-            acc[0] += -nu * (J / w[0]) * 0.5 * J * (du[0] + dL) + sig * (J / w[0]) * jL;
+    }
+    acc[0] += J * iw0 * (0.5 * (fnl - f[0]) + 0.5 * lam * (uLf - u[0]));
+    if (sipg && nu != 0.0) {
+        double du[8];
+        for (int q = 0; q < n1; ++q) {
+            du[q] = 0.0;
+            for (int k = 0; k < n1; ++k) du[q] += D[q * n1 + k] * u[k];
         }
+        double dR = 0.0, dL = 0.0;   // the neighbours' derivatives at the shared faces
+        for (int k = 0; k < n1; ++k) {
+            dR += br ? 0.0 : D[k] * uR[k];
+            dL += bl ? 0.0 : D[N * n1 + k] * uL[k];
+        }
+        const double avR = br ? J * du[N] : 0.5 * J * (du[N] + dR);
+        const double avL = bl ? J * du[0] : 0.5 * J * (du[0] + dL);
+        const double sR = br ? 1.0 : 0.5, sL = bl ? 1.0 : 0.5;
+        const double jR = u[N] - uRf, jL = uLf - u[0];
+        for (int i = 0; i < n1; ++i) {
+            double vol = 0.0;
+            for (int q = 0; q < n1; ++q) vol += w[q] * D[q * n1 + i] * du[q];
+            acc[i] += -nu * J * J * vol / w[i] + nu * J * J * (sR * D[N * n1 + i] * jR + sL * D[i] * jL) / w[i];
+        }
+        acc[N] += nu * (J / w[N]) * avR - sig * (J / w[N]) * jR;
+        acc[0] += -nu * (J / w[0]) * avL + sig * (J / w[0]) * jL;
+    }
+}
+
+// Spatial operator of a linear equation (advection, advection-diffusion with
+// BR1 or with the symmetric interior penalty) along axis a, restricted to one
+// line of n1 nodes: the contribution F_i at node i of the line is linear in
+// the line's values u, the left neighbour's line uL and the right one's uR
+// (eqs. elementint, surfaceint in strong form, flux:llf).  Evaluated here for
+// the unit vectors, it gives F = A u + BL uL + BR uR; BL is nonzero only in
+// its last column (the neighbour's face value enters every node through the
+// lift) and its first row (the face flux needs the neighbour's normal
+// derivative), BR likewise in its first column and last row (checked).
+//   advection: -(2/h) D (a u), Rusanov {a u} + lambda/2 (u_L - u_R) at the
+//              faces, lifted by -(2/h) M^-1 B (H - f);
+//   BR1:       lifted gradient with u_hat = {u}, central {nu q};
+//   SIPG:      the symmetric interior penalty form, sigma = eta nu / h,
+//              eta = 10 N^2, on the line with J = 2/h:
+//              -nu J^2 M^-1 D^T M D u, and per face the consistency term
+//              nu {u'} (end row), the symmetry term nu/2 J^2 M^-1 D^T e (jump)
+//              (every row), the penalty -sigma J/w (jump) (end row).
+// `av` is the velocity, `lam` the Rusanov wave speed, `nu` the diffusivity.
+// bnd (may be null): the Dirichlet variants, A_L, A_R, A_LR (own line, the
+// element at the lower / upper / both boundaries) and the exterior state's
+// coefficients gL_L, gR_R, gL_LR, gR_LR.
+static void line_operator_parts(const Problem& pb, int a, double av, double lam, double nu, double* out,
+                                double* bnd = nullptr) {
+    const int n1 = pb.n1, N = n1 - 1;
+    auto apply = [&](const double* u, const double* uL, const double* uR, double* acc) {
+        line_apply(pb, a, av, lam, nu, u, uL, uR, false, false, 0.0, acc);
     };
     double M[3][8][8];   // [input line][row i][column k]
     for (int which = 0; which < 3; ++which)
@@ -286,18 +351,47 @@ static void line_operator_parts(const Problem& pb, int a, double av, double lam,
         FL[m] = M[1][0][N - m];   // row 0: left neighbour's node at distance m from its face
         FR[m] = M[2][N][m];       // row N: right neighbour's node at distance m
     }
+    if (!bnd) return;
+    // Dirichlet variants: own-line matrices with the neighbour across a
+    // boundary replaced by the exterior state (g = 0), and the response to
+    // g = 1 (the other neighbour's contributions HL/HR, FL/FR are unchanged)
+    const double zero[8] = {};
+    for (int var = 0; var < 3; ++var) {
+        const bool bl = var != 1, br = var != 0;
+        double* Av = bnd + var * n1 * n1;
+        for (int k = 0; k < n1; ++k) {
+            double in[8] = {};
+            in[k] = 1.0;
+            double acc[8];
+            line_apply(pb, a, av, lam, nu, in, zero, zero, bl, br, 0.0, acc);
+            for (int i = 0; i < n1; ++i) Av[i * n1 + k] = acc[i];
+        }
+    }
+    double* gc = bnd + 3 * n1 * n1;       // gL_L, gR_R, gL_LR (both ends), gR_LR = 0
+    double acc[8];
+    line_apply(pb, a, av, lam, nu, zero, zero, zero, true, false, 1.0, acc);
+    for (int i = 0; i < n1; ++i) gc[i] = acc[i];
+    line_apply(pb, a, av, lam, nu, zero, zero, zero, false, true, 1.0, acc);
+    for (int i = 0; i < n1; ++i) gc[n1 + i] = acc[i];
+    line_apply(pb, a, av, lam, nu, zero, zero, zero, true, true, 1.0, acc);
+    for (int i = 0; i < n1; ++i) {
+        gc[2 * n1 + i] = acc[i];
+        gc[3 * n1 + i] = 0.0;
+    }
 }
 
 // The line operators of the descriptor: constant velocity, one per axis at
 // stride LIN_AXIS; rotating velocity (2D), three parts per axis (viscous,
 // central advection per unit velocity, dissipation per unit speed) packed
 // at stride n1^2 + 4 n1.
-static void line_operators(const Problem& pb, double* lin) {
+static void line_operators(const Problem& pb, double* lin, double* linb) {
     const double nu = pb.eq.kind == ST_ADVECTION ? 0.0 : pb.P.nu;
     if (!pb.ops->rot) {
+        const int LB = 3 * pb.n1 * pb.n1 + 4 * pb.n1;
         for (int a = 0; a < pb.mesh.dim; ++a) {
             const double av = pb.P.a[a];
-            line_operator_parts(pb, a, av, std::fabs(av), nu, lin + a * LIN_AXIS);
+            line_operator_parts(pb, a, av, std::fabs(av), nu, lin + a * LIN_AXIS,
+                                pb.mesh.bc[a] ? linb + a * LB : nullptr);
         }
         return;
     }
@@ -353,7 +447,9 @@ OpSeg base_opseg(const Problem& pb, double dt) {
     for (int a = 0; a < 2; ++a) div_magic(pb.K[a], s.dm[a], s.ds[a]);
     set_tiles(s, pb, 12);
     s.iw0 = 1.0 / pb.wx[0];
-    if (linear_eq(pb.eq.kind)) line_operators(pb, s.lin);
+    if (linear_eq(pb.eq.kind)) line_operators(pb, s.lin, s.linb);
+    for (int a = 0; a < 3; ++a) s.bc[a] = a < pb.mesh.dim ? pb.mesh.bc[a] : 0;
+    s.bcg = pb.eq.bc_value;
     for (int a = 0; a < 2; ++a) {
         s.lo[a] = pb.mesh.lo[a];
         s.center[a] = pb.eq.center[a];
@@ -1031,9 +1127,10 @@ void setup_jvp(st_ctx* h, int M, const double* U, const double* dir, const int* 
     put_slab_segs(dop, M, base, st, [&](int m, OpSeg& x) {
         x.out = dptr(out + m * n);
         if (linear_eq(kind)) {
-            // J v = R(v) with u_prev = 0
+            // J v = R(v) with u_prev = 0 and no exterior state (the linear part)
             x.U = dirp(m);
             x.uprev = nullptr;
+            x.bcg = 0.0;
         } else {
             x.U = state(m);
             x.V = dirp(m);

@@ -30,7 +30,7 @@ inline int op_blocks(const Problem& pb) {
 
 int set_error(int code, const std::string& msg);
 void lgl_tables(int n, double* x, double* w, double* D);
-const OpTable* find_table(int eq, int dim, int n1, int nt, bool rot = false);
+const OpTable* find_table(int eq, int dim, int n1, int nt, bool rot = false, bool bnd = false);
 int make_problem(const st_mesh_t* mesh, int N, int Nt, const st_equation_t* eq, Problem& pb);
 OpSeg base_opseg(const Problem& pb, double dt);
 // the viscous pass's block traversal (narrower 3D columns than the operator's)

@@ -20,6 +20,7 @@
 #include "st_krylov.hpp"
 
 #include <array>
+#include <cstring>
 #include <utility>
 
 namespace stdg {
@@ -635,10 +636,10 @@ __global__ __launch_bounds__(VBLOCK) void k_couple(CoupleArgs a) {
     }
 }
 
-// Descriptor uploads in stream order: the descriptor is the kernel's first
-// argument, so it sits at the start of the kernel-argument segment, and the
-// threads copy its 8-byte words in parallel (one thread copying a 3 KB
-// operator descriptor took about 8 us).
+// Descriptor uploads in stream order: the descriptor (or a 2 KB chunk of
+// it) is the kernel's first argument, so it sits at the start of the
+// kernel-argument segment, and the threads copy its 8-byte words in parallel
+// (one thread copying a 3 KB operator descriptor took about 8 us).
 template <class S>
 __global__ void k_put_desc(S v, S* dst) {
     static_assert(sizeof(S) % 8 == 0, "descriptor of whole 8-byte words");
@@ -646,6 +647,15 @@ __global__ void k_put_desc(S v, S* dst) {
     const auto* src = (const __attribute__((address_space(4))) uint64_t*)__builtin_amdgcn_kernarg_segment_ptr();
     auto* d = (__attribute__((address_space(1))) uint64_t*)dst;
     for (int i = threadIdx.x; i < (int)(sizeof(S) / 8); i += blockDim.x) d[i] = src[i];
+}
+struct DescChunk {
+    uint64_t w[256];
+};
+__global__ void k_put_chunk(DescChunk v, uint64_t* dst, int nw) {
+    (void)v;
+    const auto* src = (const __attribute__((address_space(4))) uint64_t*)__builtin_amdgcn_kernarg_segment_ptr();
+    auto* d = (__attribute__((address_space(1))) uint64_t*)dst;
+    for (int i = threadIdx.x; i < nw; i += blockDim.x) d[i] = src[i];
 }
 
 // ---------------------------------------------------------------------------
@@ -698,7 +708,15 @@ void vk_couple(const CoupleArgs& a, hipStream_t st) {
     if (a.slabs > 1) LAUNCH_V(k_couple, a.nblk, a);
 }
 void put_opseg(OpSeg* dst, const OpSeg& v, hipStream_t st) {
-    launch_k(k_put_desc<OpSeg>, dim3(1), dim3(256), st, v, dst);
+    static_assert(sizeof(OpSeg) % 8 == 0, "descriptor of whole 8-byte words");
+    constexpr int NW = (int)(sizeof(OpSeg) / 8);
+    const auto* src = reinterpret_cast<const uint64_t*>(&v);
+    for (int w0 = 0; w0 < NW; w0 += 256) {
+        DescChunk c;
+        const int nw = NW - w0 < 256 ? NW - w0 : 256;
+        std::memcpy(c.w, src + w0, sizeof(uint64_t) * nw);
+        launch_k(k_put_chunk, dim3(1), dim3(256), st, c, reinterpret_cast<uint64_t*>(dst) + w0, nw);
+    }
 }
 void put_vecseg(VecSeg* dst, const VecSeg& v, hipStream_t st) {
     launch_k(k_put_desc<VecSeg>, dim3(1), dim3(64), st, v, dst);

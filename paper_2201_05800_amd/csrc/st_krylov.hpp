@@ -79,6 +79,7 @@ using OpLaunch = void (*)(const OpSeg*, int, int, hipStream_t);
 struct OpTable {
     int eq, dim, n1, nt, epb;
     int rot;             // 1: the rotating-velocity entry (res64 / lin32 are the ROT kernels)
+    int bnd;             // 1: the Dirichlet-boundary entry (res64 / lin32 are the BND kernels)
     OpLaunch res64;      // residual, FP64
     OpLaunch lin32;      // linear equations: R(v) with u_prev = 0 in FP32 (FP32-inner JVP)
     OpLaunch jvp64;      // nonlinear JVP, FP64
@@ -91,6 +92,9 @@ struct OpTable {
     // res64 / lin32 (line operator in three parts, b_a per line)
     OpLaunch res64_rot;
     OpLaunch lin32_rot;
+    // linear equations: the Dirichlet-boundary variants of res64 / lin32
+    OpLaunch res64_bnd;
+    OpLaunch lin32_bnd;
 };
 
 void register_ops_adv(std::vector<OpTable>& t);

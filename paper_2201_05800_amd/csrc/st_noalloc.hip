@@ -24,7 +24,7 @@ namespace {
 // operator), then the Navier-Stokes viscous-flux array -Fv (d values per
 // unknown).
 constexpr size_t SCRATCH_BYTES = (size_t)ST_NOALLOC_SCRATCH_BYTES;
-constexpr size_t DESC_SLOT = 4096;
+constexpr size_t DESC_SLOT = 16384;
 constexpr size_t Q_OFFSET = 2 * DESC_SLOT;
 static_assert(sizeof(OpSeg) <= DESC_SLOT, "descriptor slot too small");
 

@@ -632,8 +632,12 @@ __global__ __launch_bounds__((Shape<D, N1, NT, tpt_of(EQ, NT)>::BS)) void k_op(c
 // three parts in the descriptor and b_a formed per line.  FL / FR (the
 // neighbour's interior nodes) come from the viscous part only: the advection
 // flux sees the neighbour's face value alone.
+// BND: Dirichlet boundaries on the axes with bc[a] = 1.  The line of an
+// element at a boundary takes its own-line matrix A_L / A_R / A_LR from the
+// descriptor, the exterior state g in place of the neighbour's face value
+// (with its own coefficient), and no neighbour line (FL / FR) on that side.
 // ---------------------------------------------------------------------------
-template <int EQ, int D, int N1, int NT, class CT, class UT, bool ROT = false>
+template <int EQ, int D, int N1, int NT, class CT, class UT, bool ROT = false, bool BND = false>
 __global__ __launch_bounds__((Shape<D, N1, NT, NT>::BS)) void k_lin(const OpSeg* __restrict__ segs, int nseg, int G) {
     using SH = Shape<D, N1, NT, NT>;
     constexpr int NS = SH::NS, NPE = SH::NPE, NF = SH::NF;
@@ -646,7 +650,9 @@ __global__ __launch_bounds__((Shape<D, N1, NT, NT>::BS)) void k_lin(const OpSeg*
     constexpr int LA = N1 * N1 + 4 * N1;            // line-operator entries per axis (per part)
     constexpr int NP = ROT ? 3 : 1;                 // parts per axis
     static_assert(!ROT || (D == 2 && N1 <= ROT_MAX_N1), "rotating velocity: 2D, n1 <= 5");
-    constexpr int NTAB = D * NP * LA;
+    static_assert(!(ROT && BND), "rotating velocity with boundaries is not built");
+    constexpr int LB = 3 * N1 * N1 + 4 * N1;         // boundary variants per axis
+    constexpr int NTAB = D * NP * LA + (BND ? D * LB : 0);
     constexpr int NQ = (NTAB + BS - 1) / BS;
     __shared__ CT tile[NL];                         // [element][time][spatial node]
     __shared__ CT halo[NH];                         // [face point][j]: neighbour's face value
@@ -683,6 +689,7 @@ __global__ __launch_bounds__((Shape<D, N1, NT, NT>::BS)) void k_lin(const OpSeg*
     struct FPI {
         int a, side, rn, step, en;
         bool ok, local;      // local: the neighbour is one of the block's elements (read from the tile)
+        bool bnd;            // the face is a Dirichlet boundary: no neighbour line
     };
     auto fp_info = [&](int p) {
         FPI fi;
@@ -698,12 +705,18 @@ __global__ __launch_bounds__((Shape<D, N1, NT, NT>::BS)) void k_lin(const OpSeg*
         const int stride = stride_rt<N1>(fi.a);
         fi.rn = face_node_rt<D, N1>(fi.a, f, right) + (right ? -N : N) * stride;   // neighbour's face node
         fi.step = right ? stride : -stride;
-        fi.en = fi.ok ? neighbour(sg, ep, ecoord(sg, ep), fi.a, right) : 0;
-        fi.local = fi.ok && fi.en >= e0 && fi.en < e0 + EPB;
+        const ECoord xe = ecoord(sg, fi.ok ? ep : 0);
+        fi.bnd = false;
+        if constexpr (BND) {
+            const int ca = fi.a == 0 ? xe.c[0] : (fi.a == 1 ? xe.c[1] : xe.c[2]);
+            fi.bnd = fi.ok && sg.bc[fi.a] && (right ? ca == sg.K[fi.a] - 1 : ca == 0);
+        }
+        fi.en = fi.ok ? neighbour(sg, ep, xe, fi.a, right) : 0;
+        fi.local = fi.ok && !fi.bnd && fi.en >= e0 && fi.en < e0 + EPB;
         return fi;
     };
     auto fp_load = [&](const FPI& fi, CT (&nl)[NT][N]) {
-        if (!fi.ok || fi.local) return;
+        if (!fi.ok || fi.local || fi.bnd) return;
         const gptr<UT> lb = Up + (int64_t)fi.en * NPE + fi.rn;
 #pragma unroll
         for (int j = 0; j < NT; ++j)
@@ -712,6 +725,11 @@ __global__ __launch_bounds__((Shape<D, N1, NT, NT>::BS)) void k_lin(const OpSeg*
     };
     auto fp_compute = [&](int p, const FPI& fi, const CT (&nl)[NT][N]) {
         if (!fi.ok) return;
+        if (fi.bnd) {
+#pragma unroll
+            for (int j = 0; j < NT; ++j) fsum[p * NT + j] = CT(0);
+            return;
+        }
         const CT* Fs = sL + fi.a * NP * LA + N1 * N1 + 2 * N1 + fi.side * N1;   // FL or FR (viscous part)
         if (fi.local) {
             // the neighbour's line from the tile (after the first barrier)
@@ -743,28 +761,47 @@ __global__ __launch_bounds__((Shape<D, N1, NT, NT>::BS)) void k_lin(const OpSeg*
         if constexpr (ROT) {
             tL[q] = CT(sg.lin[t < NTAB ? t : 0]);        // packed parts
         } else {
-            const int a = t < NTAB ? (int)((unsigned)t / LA) : 0;
-            tL[q] = CT(sg.lin[t < NTAB ? a * LIN_AXIS + (t - a * LA) : 0]);
+            constexpr int NI = D * LA;                   // interior operators first, then the boundary ones
+            if (t < NI) {
+                const int a = (int)((unsigned)t / LA);
+                tL[q] = CT(sg.lin[a * LIN_AXIS + (t - a * LA)]);
+            } else {
+                const int tb = t < NTAB ? t - NI : 0;
+                const int a = (int)((unsigned)tb / LB);
+                tL[q] = CT(sg.linb[a * LB + (tb - a * LB)]);
+            }
         }
     }
     const CT tDt = CT(sg.Dt[tid < NT * NT ? tid : 0]);
     const CT twt = CT(sg.wt[tid < NT ? tid : 0]);
     CT u[NT];
     CT unb[D][NT];
+    const ECoord ex = ecoord(sg, active ? e : 0);
+    // Dirichlet boundary of the element on axis a, lower (1) and upper (2) end
+    auto bside = [&](int a) -> int {
+        if constexpr (!BND) return 0;
+        if (!sg.bc[a]) return 0;
+        const int ca = a == 0 ? ex.c[0] : (a == 1 ? ex.c[1] : ex.c[2]);
+        return (ca == 0 ? 1 : 0) | (ca == sg.K[a] - 1 ? 2 : 0);
+    };
     if (active) {
         const gptr<UT> Ue = Up + (int64_t)e * NPE + s;
 #pragma unroll
         for (int j = 0; j < NT; ++j) u[j] = CT(Ue[j * NS]);
-        const ECoord x = ecoord(sg, e);
         static_for<0, D>([&](auto A) {
             constexpr int a = decltype(A)::value;
             constexpr int stride = ipow_c<N1, a>;
             const int ia = ic[a];
             if (ia == 0 || ia == N) {
                 const bool right = ia == N;
-                const gptr<UT> Un = Up + (int64_t)neighbour(sg, e, x, a, right) * NPE + s + ((right ? 0 : N) - ia) * stride;
+                if (bside(a) & (right ? 2 : 1)) {
 #pragma unroll
-                for (int j = 0; j < NT; ++j) unb[a][j] = CT(Un[j * NS]);
+                    for (int j = 0; j < NT; ++j) unb[a][j] = CT(sg.bcg);      // the exterior state
+                } else {
+                    const gptr<UT> Un = Up + (int64_t)neighbour(sg, e, ex, a, right) * NPE + s + ((right ? 0 : N) - ia) * stride;
+#pragma unroll
+                    for (int j = 0; j < NT; ++j) unb[a][j] = CT(Un[j * NS]);
+                }
             }
         });
     }
@@ -818,10 +855,23 @@ __global__ __launch_bounds__((Shape<D, N1, NT, NT>::BS)) void k_lin(const OpSeg*
                 hl = La[N1 * N1 + ia] + b * Lc[N1 * N1 + ia] + ab * Ld[N1 * N1 + ia];
                 hr = La[N1 * N1 + N1 + ia] + b * Lc[N1 * N1 + N1 + ia] + ab * Ld[N1 * N1 + N1 + ia];
             } else {
+                const int bs = bside(a);
+                if (BND && bs) {
+                    // the element's own-line matrix at the boundary, and the
+                    // coefficient of the exterior state on the boundary side(s)
+                    const CT* Lb = sL + D * LA + a * LB;
+                    const CT* Ab = Lb + (bs == 3 ? 2 : bs - 1) * N1 * N1;
+                    const CT* gc = Lb + 3 * N1 * N1;
 #pragma unroll
-                for (int k = 0; k < N1; ++k) Ar[k] = La[ia * N1 + k];
-                hl = La[N1 * N1 + ia];
-                hr = La[N1 * N1 + N1 + ia];
+                    for (int k = 0; k < N1; ++k) Ar[k] = Ab[ia * N1 + k];
+                    hl = bs == 1 ? gc[ia] : (bs == 3 ? gc[2 * N1 + ia] : La[N1 * N1 + ia]);
+                    hr = bs == 2 ? gc[N1 + ia] : (bs == 3 ? gc[3 * N1 + ia] : La[N1 * N1 + N1 + ia]);
+                } else {
+#pragma unroll
+                    for (int k = 0; k < N1; ++k) Ar[k] = La[ia * N1 + k];
+                    hl = La[N1 * N1 + ia];
+                    hr = La[N1 * N1 + N1 + ia];
+                }
             }
             const int f = face_of(a);
             const CT* hL = halo + fpi(a, el, 0, f) * NT;
@@ -1030,9 +1080,9 @@ template <int EQ, int D, int N1, int NT, class CT, class UT, bool JVP>
 void launch_op(const OpSeg* segs, int nseg, int G, hipStream_t st) {
     launch_k(k_op<EQ, D, N1, NT, CT, UT, JVP>, dim3(G), dim3(Shape<D, N1, NT, tpt_of(EQ, NT)>::BS), st, segs, nseg, G);
 }
-template <int EQ, int D, int N1, int NT, class CT, class UT, bool ROT = false>
+template <int EQ, int D, int N1, int NT, class CT, class UT, bool ROT = false, bool BND = false>
 void launch_lin(const OpSeg* segs, int nseg, int G, hipStream_t st) {
-    launch_k(k_lin<EQ, D, N1, NT, CT, UT, ROT>, dim3(G), dim3(Shape<D, N1, NT, NT>::BS), st, segs, nseg, G);
+    launch_k(k_lin<EQ, D, N1, NT, CT, UT, ROT, BND>, dim3(G), dim3(Shape<D, N1, NT, NT>::BS), st, segs, nseg, G);
 }
 template <int D, int N1, int NT, class CT, class UT, bool JVP>
 void launch_visc(const OpSeg* segs, int nseg, int G, hipStream_t st) {
@@ -1050,6 +1100,8 @@ OpTable make_table() {
             t.res64_rot = launch_lin<EQ, D, N1, NT, double, double, true>;
             t.lin32_rot = launch_lin<EQ, D, N1, NT, float, double, true>;
         }
+        t.res64_bnd = launch_lin<EQ, D, N1, NT, double, double, false, true>;
+        t.lin32_bnd = launch_lin<EQ, D, N1, NT, float, double, false, true>;
     } else {
         t.res64 = launch_op<EQ, D, N1, NT, double, double, false>;
         t.jvp64 = launch_op<EQ, D, N1, NT, double, double, true>;

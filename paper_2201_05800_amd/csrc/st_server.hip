@@ -331,6 +331,7 @@ std::vector<OpGroup> build_jvp_groups(st_srv* s, const std::vector<Req*>& rs) {
         if (linear_eq(kind)) {
             b.U = Vk;
             b.uprev = nullptr;
+            b.bcg = 0.0;
         } else {
             b.U = state;
             b.V = Vk;

@@ -34,13 +34,13 @@ _c_double_p = ctypes.POINTER(ctypes.c_double)
 
 class Mesh(ctypes.Structure):
     _fields_ = [("dim", ctypes.c_int), ("K", ctypes.c_int * 3), ("lo", ctypes.c_double * 3),
-                ("hi", ctypes.c_double * 3)]
+                ("hi", ctypes.c_double * 3), ("bc", ctypes.c_int * 3)]
 
 
 class Equation(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int), ("a", ctypes.c_double * 3), ("nu", ctypes.c_double),
                 ("gamma", ctypes.c_double), ("mu", ctypes.c_double), ("prandtl", ctypes.c_double),
-                ("omega", ctypes.c_double), ("center", ctypes.c_double * 3)]
+                ("omega", ctypes.c_double), ("center", ctypes.c_double * 3), ("bc_value", ctypes.c_double)]
 
 
 class SolverOpts(ctypes.Structure):
@@ -181,18 +181,19 @@ def _stream(s):
     return ctypes.c_void_p(s.cuda_stream)
 
 
-def mesh(dim, K, lo, hi) -> Mesh:
+def mesh(dim, K, lo, hi, bc=(0, 0, 0)) -> Mesh:
     m = Mesh()
     m.dim = dim
     for a in range(3):
         m.K[a] = int(K[a]) if a < dim else 1
         m.lo[a] = float(lo[a]) if a < dim else 0.0
         m.hi[a] = float(hi[a]) if a < dim else 1.0
+        m.bc[a] = int(bc[a]) if a < dim and a < len(bc) else 0
     return m
 
 
 def equation(kind, a=(0.0, 0.0, 0.0), nu=0.0, gamma=1.4, mu=0.0, prandtl=0.72, omega=0.0,
-             center=(0.0, 0.0, 0.0)) -> Equation:
+             center=(0.0, 0.0, 0.0), bc_value=0.0) -> Equation:
     e = Equation()
     e.kind = kind
     for i in range(3):
@@ -200,6 +201,7 @@ def equation(kind, a=(0.0, 0.0, 0.0), nu=0.0, gamma=1.4, mu=0.0, prandtl=0.72, o
         e.center[i] = float(center[i]) if i < len(center) else 0.0
     e.nu, e.gamma, e.mu, e.prandtl = nu, gamma, mu, prandtl
     e.omega = float(omega)
+    e.bc_value = float(bc_value)
     return e
 
 

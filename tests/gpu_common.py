@@ -10,10 +10,10 @@ KINDS = {"adv": 1, "advdiff": 2, "burgers": 3, "euler": 4, "ns": 5, "sipg": 6}
 
 
 def cfg(kind, dim, K, N, Nt, lo=None, hi=None, a=(1.0, 0.5, -0.25), nu=0.01, gamma=1.4, mu=0.01, prandtl=0.71,
-        omega=0.0, center=(0.0, 0.0, 0.0)):
+        omega=0.0, center=(0.0, 0.0, 0.0), bc=(0, 0, 0), bc_value=0.0):
     return dict(kind=KINDS[kind] if isinstance(kind, str) else kind, dim=dim, K=list(K), N=N, Nt=Nt,
                 lo=lo or [0.0] * dim, hi=hi or [1.0] * dim, a=a, nu=nu, gamma=gamma, mu=mu, prandtl=prandtl,
-                omega=omega, center=center)
+                omega=omega, center=center, bc=tuple(bc), bc_value=bc_value)
 
 
 class Pair:
@@ -26,12 +26,13 @@ class Pair:
         self.st, self.orc = st, oracle
         d = c["dim"]
         om, ce = c.get("omega", 0.0), c.get("center", (0.0, 0.0, 0.0))
+        bc, g = c.get("bc", (0, 0, 0)), c.get("bc_value", 0.0)
         self.p = oracle.problem(d, c["K"], c["lo"], c["hi"], c["N"], c["Nt"], c["kind"], a=c["a"][:d],
                                 nu=c["nu"], gamma=c["gamma"], mu=c["mu"], prandtl=c["prandtl"], omega=om,
-                                center=ce)
-        self.h = st.st_create(st.mesh(d, c["K"], c["lo"], c["hi"]), c["N"], c["Nt"],
+                                center=ce, bc=bc, bc_value=g)
+        self.h = st.st_create(st.mesh(d, c["K"], c["lo"], c["hi"], bc=bc), c["N"], c["Nt"],
                               st.equation(c["kind"], a=c["a"][:d], nu=c["nu"], gamma=c["gamma"], mu=c["mu"],
-                                          prandtl=c["prandtl"], omega=om, center=ce))
+                                          prandtl=c["prandtl"], omega=om, center=ce, bc_value=g))
         self.n, self.nsp, self.nv = st.st_sizes(self.h)
         self.ns = (c["N"] + 1) ** d
         self.E = int(np.prod(c["K"]))
