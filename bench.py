@@ -843,10 +843,13 @@ def main():
         st.st_destroy(hb)
         slabs = dict(note="M slabs from the same u^n: one coupled Newton-GMRES solve against M sequential "
                           "slab solves, both to the workload's tolerance",
-                     advdiff2d_64x64=[multi_slab_bench(big, u_big, 1.0 / 128, 4, 0),
-                                      multi_slab_bench(big, u_big, 1.0 / 128, 4, 1)],
+                     precond="0 none, 1 element-block Jacobi slab by slab, 2 the same blocks with forward "
+                             "substitution over the slabs",
+                     advdiff2d_64x64=[multi_slab_bench(big, u_big, 1.0 / 128, 4, pc) for pc in (0, 1, 2)] +
+                                     [multi_slab_bench(big, u_big, 1.0 / 128, 16, 2)],
                      small_16x16=[multi_slab_bench(small, u_small, 1.0 / 128, 8, 0)] +
-                                 [multi_slab_bench(small, u_small, 1.0 / 128, M, 1) for M in (4, 8, 16, 32)])
+                                 [multi_slab_bench(small, u_small, 1.0 / 128, M, pc) for M in (4, 8, 16, 32)
+                                  for pc in (1, 2)])
         print(f"# slabs: {slabs}", file=sys.stderr, flush=True)
     bubble = bubble_bench() if args.bubble_leg else None
     pulse = pulse_table_bench() if args.pulse_leg else None

@@ -108,7 +108,10 @@ typedef struct {
     int restart;       /* GMRES restart length m, 1..32 (default 30)            */
     int max_newton;    /* outer iterations; each is one residual evaluation and */
                        /* one GMRES cycle of at most m steps (default 60)       */
-    int cgs_passes;    /* classical Gram-Schmidt passes, 1 or 2 (default 1)     */
+    int cgs_passes;    /* classical Gram-Schmidt passes: 1 or 2 (default 1), or */
+                       /* 0 adaptive: one pass, and a second one in the steps   */
+                       /* where the new vector's norm falls below 1/sqrt(2) of  */
+                       /* the projected vector's (selective reorthogonalisation)*/
     int inner_fp32;    /* 1: JVPs in FP32 (state, math, accumulation); the      */
                        /* residual, Arnoldi and update stay FP64                */
     double gmres_rtol; /* minimum inner forcing term eta (default 1e-3; raised  */
@@ -118,8 +121,11 @@ typedef struct {
                        /* pair per launch slows launch-bound solves (17 % for  */
                        /* a 409,600-unknown slab with one class timed)          */
     int precond;       /* 0: none (default); 1: element-block Jacobi, right     */
-                       /* preconditioning (slab solves only; element blocks     */
-                       /* of at most 1024 unknowns, nv Nt (N+1)^d)              */
+                       /* preconditioning (element blocks of at most 1024       */
+                       /* unknowns, nv Nt (N+1)^d); 2: for coupled slabs        */
+                       /* (st_solve_slabs) the same blocks plus forward         */
+                       /* substitution over the slabs; as 1 for a single slab;  */
+                       /* the server takes 0 and 1                              */
 } st_solver_opts_t;
 
 /* Kernel classes of the slab solve (bits of st_solver_opts_t.timing and
@@ -233,7 +239,16 @@ int st_jvp_slabs(st_handle_t h, int M, const double* U, double t0, double dt, co
 /* Newton-GMRES on the coupled system of M slabs, as st_solve_slab (same
  * options, preconditioner block in every element of every slab, stopping
  * test on the 2-norm of the whole residual); U_out receives M n_slab values,
- * u_next the end state of the last slab. */
+ * u_next the end state of the last slab.  opts->precond = 1 applies the
+ * element blocks slab by slab (block Jacobi, the inflow coupling left out);
+ * opts->precond = 2 solves the block lower bidiagonal system with those
+ * blocks on the diagonal and the exact inflow coupling below it, by forward
+ * substitution over the slabs, element by element:
+ *   z_0 = B^-1 r_0,   z_m = B^-1 (r_m - (e_1 (x) I)(e_Nt^T (x) I) z_{m-1}),
+ * so that the preconditioned operator differs from the identity only by the
+ * couplings between neighbouring elements (and, for the nonlinear
+ * equations, by the frozen mean state); device memory: npe nv (N+1)^d more
+ * doubles. */
 int st_solve_slabs(st_handle_t h, int M, const double* u_prev, double t0, double dt, double tol,
                    const st_solver_opts_t* opts, double* U_out, double* u_next, st_stats_t* stats,
                    void* stream);
@@ -243,12 +258,12 @@ int st_solve_slabs(st_handle_t h, int M, const double* u_prev, double t0, double
  * capture, tight serving loops, harnesses that forbid hipMalloc).  The
  * problem is given as to st_create; U, u_prev, R as to st_residual (device,
  * caller-owned).  Every other device buffer its kernels use -- the launch
- * descriptors and, for ST_NS_BR1, the viscous-flux array (mesh.dim values per
- * unknown) -- lives in one static device array of ST_NOALLOC_SCRATCH_BYTES,
- * which each GPU the library runs on holds until the process ends.  A
- * Navier-Stokes slab whose viscous-flux array does not fit (more than about
- * 16.7 M / (8 dim) unknowns) is rejected with ST_ERR_BAD_ARG; the other
- * equations have no size limit here.  Calls that overlap on one GPU (other
+ * descriptors and, for ST_NS_BR1, the output of the viscous pass ((dim + 1)
+ * Nt (N+1)^(dim-1) (N + 1 + 2 dim) doubles per element) -- lives in one
+ * static device array of ST_NOALLOC_SCRATCH_BYTES, which each GPU the
+ * library runs on holds until the process ends.  A Navier-Stokes slab whose
+ * viscous-pass output does not fit (the array less 32 KiB of descriptors) is
+ * rejected with ST_ERR_BAD_ARG; the other equations have no size limit here.  Calls that overlap on one GPU (other
  * streams, other threads) share the array and race; calls on one stream are
  * ordered.  Asynchronous on `stream`; no hipMalloc/hipFree, no host-device
  * copy, no memset (every value of the array that a kernel reads was written

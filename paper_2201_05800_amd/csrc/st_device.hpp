@@ -54,6 +54,22 @@ __host__ __device__ __forceinline__ constexpr int ipow(int b, int e) {
     return r;
 }
 
+// Output of the Navier-Stokes viscous pass, per element, for the d + 1
+// variables after the density (whose viscous flux is zero):
+//   [0, visc_vr_per_elem): the viscous terms of the element's own residual,
+//      [v - 1][time node][spatial node];
+//   then the face traces: on each of the 2d faces the viscous part of the
+//      face-normal total flux, -Fv_a, at every face node and time node,
+//      [axis][side (0 left, 1 right)][v - 1][time node][face node], the face
+//      node index running over the other axes in increasing order, the
+//      first fastest.
+__host__ __device__ constexpr int visc_vr_per_elem(int dim, int n1, int nt) {
+    return (dim + 1) * nt * ipow(n1, dim);
+}
+__host__ __device__ constexpr int visc_per_elem(int dim, int n1, int nt) {
+    return visc_vr_per_elem(dim, n1, nt) + 2 * dim * (dim + 1) * nt * ipow(n1, dim - 1);
+}
+
 // ---------------------------------------------------------------------------
 // forward-mode dual numbers  x + x' eps,  eps^2 = 0
 // ---------------------------------------------------------------------------
@@ -271,6 +287,17 @@ struct VecSeg {
 
 // One slab inside an element-block Jacobi launch: out_e = B^-1 in_e for every
 // element e (the element's npe consecutive values), or out_e += B^-1 in_e.
+// Forward substitution over the slabs of a coupled system (k_slab_sweep).
+struct SweepArgs {
+    const double* C;      // npe x nl: the first-time-node columns of B^-1 (row-major)
+    double* y;            // B^-1 r of every slab (slab m at m n); overwritten by z unless acc
+    double* acc;          // null, or acc += z in every slab
+    const int* skip;      // skip when *skip != 0 (may be null)
+    int64_t n;            // unknowns per slab
+    int npe, nl, nt, ns;  // unknowns per element, nv ns, Nt, spatial nodes per element
+    int E, M;             // elements per slab, slabs
+};
+
 struct PcSeg {
     DynPtr in;            // input vector (may follow the Arnoldi index)
     double* out;

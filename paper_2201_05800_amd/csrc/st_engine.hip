@@ -495,9 +495,12 @@ struct st_ctx {
     int m_alloc = 0;
     GState* h_st = nullptr;     // pinned host mirror of the state header
     std::vector<void*> allocs;
-    // element-block Jacobi (linear equations): B^-1 column-major, the dt it
-    // was assembled for, the preconditioned direction z, 2 descriptor slots
+    // element-block Jacobi: B^-1 packed for the matrix cores, the dt it was
+    // assembled for, the preconditioned direction z, 3 descriptor slots;
+    // pc_C: the first-time-node columns of B^-1 (forward substitution over
+    // the slabs of a coupled system)
     double* binvT = nullptr;
+    double* pc_C = nullptr;
     double pc_dt = 0.0;
     std::vector<double> pc_ubar;   // nonlinear: the mean state it was assembled at
     double* pz = nullptr;
@@ -609,8 +612,8 @@ static int ensure_cap(st_ctx* h, int M) {
     CHK(h->alloc(&h->d_opm, (size_t)4 * c));
     CHK(h->alloc(&h->d_vsm, (size_t)c + 2));
     if (grad_pass(pb)) {
-        CHK(h->alloc(&h->Q, n * pb.mesh.dim));
-        CHK(h->alloc(&h->dQ, n * pb.mesh.dim));
+        CHK(h->alloc(&h->Q, (size_t)visc_len(pb) * c));
+        CHK(h->alloc(&h->dQ, (size_t)visc_len(pb) * c));
     }
     return ST_OK;
 }
@@ -620,7 +623,7 @@ static int ensure_fp32(st_ctx* h) {
     if (h->U32) return ST_OK;
     const size_t n = (size_t)pb.n * h->cap;
     CHK(h->alloc(&h->U32, n));
-    if (grad_pass(pb)) CHK(h->alloc(&h->dQ32, n * pb.mesh.dim));
+    if (grad_pass(pb)) CHK(h->alloc(&h->dQ32, (size_t)visc_len(pb) * h->cap));
     return ST_OK;
 }
 
@@ -778,6 +781,20 @@ int scalar_block_inverse(const Problem& pb, const double* up_host, double dt, st
 // of a run has the same u_bar up to round-off); a frozen-coefficient
 // approximation of every element's block.  The inverse is kept per handle
 // for its dt (and u_bar), and rebuilt when either changes.
+static int upload_block_inverse(st_ctx* h, const std::vector<double>& packed) {
+    const Problem& pb = h->pb;
+    const int npe = (int)(pb.nv * pb.Nt * pb.ns);
+    const std::vector<double> C = pc_inflow_columns(packed, npe, pb.nv, pb.Nt, pb.ns);
+    if (!h->binvT) {
+        CHK(h->alloc(&h->binvT, packed.size()));
+        CHK(h->alloc(&h->pc_C, C.size()));
+        CHK(h->alloc(&h->d_pc, 3));
+    }
+    HIPCHK(hipMemcpy(h->binvT, packed.data(), sizeof(double) * packed.size(), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(h->pc_C, C.data(), sizeof(double) * C.size(), hipMemcpyHostToDevice));
+    return ST_OK;
+}
+
 static int ensure_precond(st_ctx* h, const double* u_prev, double dt, hipStream_t st) {
     const Problem& pb = h->pb;
     const bool lin = linear_eq(pb.eq.kind);
@@ -813,11 +830,7 @@ static int ensure_precond(st_ctx* h, const double* u_prev, double dt, hipStream_
         CHK(scalar_block_inverse(pb, up.data(), dt, packed));
         if (pc_prepare(npe) != hipSuccess)
             return set_error(ST_ERR_UNSUPPORTED, "element block needs more LDS than the device grants");
-        if (!h->binvT) {
-            CHK(h->alloc(&h->binvT, packed.size()));
-            CHK(h->alloc(&h->d_pc, 2));
-        }
-        HIPCHK(hipMemcpy(h->binvT, packed.data(), sizeof(double) * packed.size(), hipMemcpyHostToDevice));
+        CHK(upload_block_inverse(h, packed));
         h->pc_dt = dt;
         h->pc_ubar = ubar;
         return ST_OK;
@@ -833,7 +846,7 @@ static int ensure_precond(st_ctx* h, const double* u_prev, double dt, hipStream_
     Problem pp;
     CHK(make_problem(&m3, pb.N, pb.Nt, &pb.eq, pp));
     const int Gp = op_blocks(pp);
-    const int64_t np = pp.n;
+    const int64_t np = pp.n, nq = visc_len(pp);
     const bool visc = grad_pass(pb);
     double *din = nullptr, *dout = nullptr, *dstate = nullptr, *dq = nullptr;
     OpSeg* dsegs = nullptr;
@@ -862,7 +875,7 @@ static int ensure_precond(st_ctx* h, const double* u_prev, double dt, hipStream_
         hipMalloc((void**)&dout, sizeof(double) * np * npe) != hipSuccess ||
         hipMalloc((void**)&dsegs, sizeof(OpSeg) * npe * (visc ? 2 : 1)) != hipSuccess ||
         (!lin && hipMalloc((void**)&dstate, sizeof(double) * np) != hipSuccess) ||
-        (visc && hipMalloc((void**)&dq, sizeof(double) * np * d * npe) != hipSuccess)) {
+        (visc && hipMalloc((void**)&dq, sizeof(double) * nq * npe) != hipSuccess)) {
         cleanup();
         return set_error(ST_ERR_HIP, "preconditioner setup: device allocation failed");
     }
@@ -878,9 +891,9 @@ static int ensure_precond(st_ctx* h, const double* u_prev, double dt, hipStream_
             if (visc) {
                 OpSeg g = segs[c];
                 visc_tiles(g, pp);
-                g.out = dptr(dq + (size_t)c * d * np);
+                g.out = dptr(dq + (size_t)c * nq);
                 gsegs[c] = g;
-                segs[c].Q = dptr(dq + (size_t)c * d * np);
+                segs[c].Q = dptr(dq + (size_t)c * nq);
             }
         }
     }
@@ -915,11 +928,7 @@ static int ensure_precond(st_ctx* h, const double* u_prev, double dt, hipStream_
     if (!invert_dense(Bm, npe)) return set_error(ST_ERR_UNSUPPORTED, "element block of the Jacobian is singular");
     // B^-1 in the kernel's matrix-core operand order
     const std::vector<double> packed = pc_pack(Bm, npe);
-    if (!h->binvT) {
-        CHK(h->alloc(&h->binvT, packed.size()));
-        CHK(h->alloc(&h->d_pc, 2));
-    }
-    HIPCHK(hipMemcpy(h->binvT, packed.data(), sizeof(double) * packed.size(), hipMemcpyHostToDevice));
+    CHK(upload_block_inverse(h, packed));
     h->pc_dt = dt;
     h->pc_ubar = ubar;
     return ST_OK;
@@ -1054,7 +1063,7 @@ static void put_slab_segs(OpSeg* dst, int M, const OpSeg& proto, hipStream_t st,
 void setup_residual(st_ctx* h, int M, const double* U, const double* u_prev, double* R, double dt, OpSeg* dv,
                     OpSeg* dop, hipStream_t st, bool time_terms) {
     const Problem& pb = h->pb;
-    const int64_t n = pb.n, nq = pb.n * pb.mesh.dim;
+    const int64_t n = pb.n, nq = visc_len(pb);
     OpSeg base = base_opseg(pb, dt);
     if (!time_terms) std::memset(base.Dt, 0, sizeof(base.Dt));
     if (grad_pass(pb)) {
@@ -1109,7 +1118,7 @@ void setup_jvp(st_ctx* h, int M, const double* U, const double* dir, const int* 
                const int* skip, bool fp32, double dt, OpSeg* dv, OpSeg* dop, hipStream_t st) {
     const Problem& pb = h->pb;
     const int kind = pb.eq.kind;
-    const int64_t n = pb.n, nq = pb.n * pb.mesh.dim;
+    const int64_t n = pb.n, nq = visc_len(pb);
     OpSeg base = base_opseg(pb, dt);
     base.skip = skip;
     auto dirp = [&](int m) { return DynPtr{dir + m * n, ld, kp, 0}; };
@@ -1286,9 +1295,9 @@ int st_solve_slabs(st_handle_t h, int M, const double* u_prev, double t0, double
     st_default_opts(&o);
     if (opts_in) o = *opts_in;
     if (o.restart < 1 || o.restart > MMAX) return set_error(ST_ERR_BAD_ARG, "restart must be in 1..32");
-    if (o.cgs_passes < 1 || o.cgs_passes > 2) return set_error(ST_ERR_BAD_ARG, "cgs_passes must be 1 or 2");
+    if (o.cgs_passes < 0 || o.cgs_passes > 2) return set_error(ST_ERR_BAD_ARG, "cgs_passes must be 0, 1 or 2");
     if (o.max_newton < 1) return set_error(ST_ERR_BAD_ARG, "max_newton must be >= 1");
-    if (o.precond < 0 || o.precond > 1) return set_error(ST_ERR_BAD_ARG, "precond must be 0 or 1");
+    if (o.precond < 0 || o.precond > 2) return set_error(ST_ERR_BAD_ARG, "precond must be 0, 1 or 2");
     const Problem& pb = h->pb;
     const bool fp32 = o.inner_fp32 != 0;
     const int m = o.restart;
@@ -1296,7 +1305,8 @@ int st_solve_slabs(st_handle_t h, int M, const double* u_prev, double t0, double
     CHK(ensure_solve(h, m));
     if (fp32) CHK(ensure_fp32(h));
     hipStream_t st = (hipStream_t)stream;
-    const bool pc = o.precond == 1;
+    const bool pc = o.precond >= 1;
+    const bool sweep = o.precond == 2 && M > 1;   // forward substitution over the slabs
     if (pc) CHK(ensure_precond(h, u_prev, dt, st));
     const int kind = pb.eq.kind;
     const int64_t nM = pb.n * M;             // unknowns of the (multi-slab) system
@@ -1383,7 +1393,26 @@ int st_solve_slabs(st_handle_t h, int M, const double* u_prev, double t0, double
         u.skip = nullptr;
         u.accumulate = 1;
         put_pcseg(h->d_pc + 1, u, st);
+        PcSeg y = u;                     // coupled slabs: B^-1 (V y) to pz, then the sweep adds P^-1 (V y) to U
+        y.out = h->pz;
+        y.accumulate = 0;
+        put_pcseg(h->d_pc + 2, y, st);
     }
+    SweepArgs sw_dir, sw_upd;
+    std::memset(&sw_dir, 0, sizeof(sw_dir));
+    sw_dir.C = h->pc_C;
+    sw_dir.y = h->pz;
+    sw_dir.skip = skip;
+    sw_dir.n = pb.n;
+    sw_dir.npe = npe;
+    sw_dir.nl = pb.nv * pb.ns;
+    sw_dir.nt = pb.Nt;
+    sw_dir.ns = pb.ns;
+    sw_dir.E = (int)pb.E;
+    sw_dir.M = M;
+    sw_upd = sw_dir;
+    sw_upd.acc = h->U;
+    sw_upd.skip = nullptr;
 
     int status = ST_ERR_NO_CONVERGENCE;
     int outer = 0;
@@ -1412,15 +1441,23 @@ int st_solve_slabs(st_handle_t h, int M, const double* u_prev, double t0, double
         T.run(ST_K_NORMALIZE, st, [&] { vk_scale_v0(dvs, 1, Gv, st); });
         for (int k = 0; k < m; ++k) {
             if (pc) T.run(ST_K_PRECOND, st, [&] { pc_apply(h->d_pc + 0, 1, Gpc, npe, st); });
+            if (sweep) T.run(ST_K_PRECOND, st, [&] { pc_sweep(sw_dir, st); });
             launch_jvp(h, M, fp32, d_jv, d_jop, cp_jvp, st);
-            for (int p = 0; p < o.cgs_passes; ++p) {
-                T.run(ST_K_MULTIDOT, st, [&] { vk_multidot(dvs, 1, Gv, k, st); });
-                T.run(ST_K_UPDATE, st, [&] { vk_update(dvs, 1, Gv, p, p == o.cgs_passes - 1, k, st); });
+            const int npass = o.cgs_passes == 0 ? 2 : o.cgs_passes;
+            for (int p = 0; p < npass; ++p) {
+                int lastp = 0, gate = 0;
+                gs_pass_plan(o.cgs_passes, p, &lastp, &gate);
+                T.run(ST_K_MULTIDOT, st, [&] { vk_multidot(dvs, 1, Gv, k, st, gate); });
+                T.run(ST_K_UPDATE, st, [&] { vk_update(dvs, 1, Gv, p, lastp, k, st); });
             }
         }
         T.run(ST_K_NEWTON, st, [&] {
             vk_finish(dvs, 1, st);
-            if (pc) {
+            if (sweep) {
+                pc_combine(dvs, 1, Gv, st);
+                pc_apply(h->d_pc + 2, 1, Gpc, npe, st);
+                pc_sweep(sw_upd, st);
+            } else if (pc) {
                 pc_combine(dvs, 1, Gv, st);
                 pc_apply(h->d_pc + 1, 1, Gpc, npe, st);
             } else {
@@ -1455,15 +1492,19 @@ int st_solve_slabs(st_handle_t h, int M, const double* u_prev, double t0, double
         const double jvp_b = lin ? 2.0 * n8 : (fp32 ? 2.5 : 3.0) * n8;   // [U,] v in, Jv out
         stats->kernel_bytes[ST_K_JVP] = its * (jvp_b + cpl);
         if (visc) {
-            const double d = pb.mesh.dim;
-            // viscous pass: residual reads U, writes d values per unknown; JVP
-            // reads U and v, writes d tangent values per unknown
+            // viscous pass: residual reads U and writes its output (the
+            // viscous terms of the own residual, the face traces); JVP reads U
+            // and v and writes the output's tangent
+            const double tr = 8.0 * (double)visc_len(pb) * M;
             stats->kernel_bytes[ST_K_GRAD] =
-                (outer + 1) * n8 * (1.0 + d) + its * n8 * ((fp32 ? 1.5 : 2.0) + (fp32 ? 0.5 : 1.0) * d);
+                (outer + 1) * (n8 + tr) + its * ((fp32 ? 1.5 : 2.0) * n8 + (fp32 ? 0.5 : 1.0) * tr);
         }
-        if (pc) stats->kernel_bytes[ST_K_PRECOND] = (its + outer) * 2.0 * n8;   // direction in, z out
-        stats->kernel_bytes[ST_K_MULTIDOT] = h->h_st->kbytes[3] * o.cgs_passes;
-        stats->kernel_bytes[ST_K_UPDATE] = h->h_st->kbytes[4] * o.cgs_passes;
+        // direction in, z out; the sweep over coupled slabs: y in, z out (slabs 1..M-1)
+        if (pc) stats->kernel_bytes[ST_K_PRECOND] = (its + outer) * 2.0 * n8;
+        if (sweep) stats->kernel_bytes[ST_K_PRECOND] += its * (n8 + 8.0 * (double)pb.n * (M - 1));
+        // accumulated per Gram-Schmidt pass that did work
+        stats->kernel_bytes[ST_K_MULTIDOT] = h->h_st->kbytes[3];
+        stats->kernel_bytes[ST_K_UPDATE] = h->h_st->kbytes[4];
         stats->newton_its = outer;
         stats->gmres_its = h->h_st->iters_total;
         stats->res0 = r0;

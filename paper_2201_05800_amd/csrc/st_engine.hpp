@@ -24,6 +24,9 @@ struct Problem {
 // the operator needs the viscous pass first (Navier-Stokes BR1)
 inline bool grad_pass(const Problem& pb) { return pb.ops->visc_res64 != nullptr; }
 
+// values of the Navier-Stokes viscous pass's output for one slab
+inline int64_t visc_len(const Problem& pb) { return pb.E * visc_per_elem(pb.mesh.dim, pb.n1, pb.Nt); }
+
 inline int op_blocks(const Problem& pb) {
     return (int)((pb.E + pb.ops->epb - 1) / pb.ops->epb);
 }

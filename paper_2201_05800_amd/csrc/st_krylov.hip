@@ -264,9 +264,10 @@ __global__ __launch_bounds__(VBLOCK) void k_scale_v0(const VecSeg* __restrict__ 
 
 // Projections V_i . w (i < NV) and w . w of one Gram-Schmidt pass, as one
 // row of partial sums per block -> part.  The loads of every thread's first
-// elements are in flight before the cycle state is read.
+// elements are in flight before the cycle state is read, except with gate
+// set (a pass that usually finds its step finished: the state is read first).
 template <int NV>
-__global__ __launch_bounds__(VBLOCK) void k_multidot(const VecSeg* __restrict__ segs, int nseg) {
+__global__ __launch_bounds__(VBLOCK) void k_multidot(const VecSeg* __restrict__ segs, int nseg, int gate) {
     __shared__ double smem[VWAVES * (NV + 1)];
     __shared__ double s_out[NV + 1];
     const VecSeg& sg = segs[find_vseg(segs, nseg, blockIdx.x)];
@@ -285,6 +286,7 @@ __global__ __launch_bounds__(VBLOCK) void k_multidot(const VecSeg* __restrict__ 
         const auto* __restrict__ w = gl((const E*)sg.w);
         int64_t t = (int64_t)lb * VBLOCK + threadIdx.x;
         E a[UN][NV], wv[UN];
+        if (gate && (st->done || st->k != NV - 1)) return false;
         load_group<NV, UN>(V, w, n, t, stride, a, wv);
         if (st->done || st->k != NV - 1) return false;
         auto accumulate = [&](bool first) {
@@ -324,6 +326,14 @@ __global__ __launch_bounds__(VBLOCK) void k_multidot(const VecSeg* __restrict__ 
 // table (every block reduces it the same way).
 //  * not the last pass: w -= sum_i h_i V_i; block 0 accumulates h into the
 //    Arnoldi column (hacc) and, on pass 0, keeps ||w||^2 (breakdown test).
+//  * adaptive pass 0 (last = 2): the last pass unless the corrected vector's
+//    norm by Pythagoras, h_{k+1,k}^2 = w.w - sum_i h_i^2, falls below
+//    REORTH w.w -- then the cancellation would leave the new vector neither
+//    normalised nor orthogonal to working precision, so the pass acts as a
+//    first pass and the second pass (enqueued always, exiting at once when
+//    the step is finished) repeats the projection: selective
+//    reorthogonalisation, classical Gram-Schmidt twice where once is not
+//    enough.
 //  * last pass: the new norm follows from the multi-dot's w.w slot,
 //    h_{k+1,k}^2 = w.w - sum_i h_i^2 (the basis is orthonormal), so the
 //    Givens rotation of column k, the residual estimate and the stopping test
@@ -334,6 +344,11 @@ __global__ __launch_bounds__(VBLOCK) void k_multidot(const VecSeg* __restrict__ 
 // by another block of this kernel; a block that sees done = 1 set here skips
 // a sweep whose result is not needed.  Every thread's first elements are
 // loaded while the table is reduced.
+// reorthogonalise when ||w - V h||^2 < ||w||^2 / 2: the criterion of Daniel,
+// Gragg, Kaufman and Stewart (1976), under which a second classical pass
+// restores orthogonality to working precision ("twice is enough")
+constexpr double REORTH = 0.5;
+
 template <int NV, class E, int UN>
 DI void update_body(const VecSeg& sg, GState* st, int lb, int64_t stride, int pass, int last, double* s_tmp,
                     double* s_h, double* s_col, double* s_cs, double* s_sn, double* s_hacc, double* s_misc) {
@@ -349,7 +364,10 @@ DI void update_body(const VecSeg& sg, GState* st, int lb, int64_t stride, int pa
     // for the vectors, and the table loads below go out while the vectors
     // are still in flight.
     const auto* sr = gl((const GState*)st);
-    const int done = sr->done;
+    // a gated pass (the second pass of the adaptive form) reads the state
+    // before it loads: it usually finds the step finished
+    if (pass > 0 && last == 1 && (sr->done || sr->k != k)) return;
+    const int done = sr->done || sr->k != k;      // finished, or advanced by the adaptive pass 0
     // g_k, the absolute tolerance and ||w||^2 of pass 0, one per thread
     const double misc_i = !last ? 0.0 : (ti == 0 ? sr->g[k] : (ti == 1 ? sr->eta_abs : (ti == 2 && pass > 0 ? sr->wn0 : 0.0)));
     const double cs_i = (last && ti < k) ? sr->cs[ti] : 0.0;
@@ -373,10 +391,21 @@ DI void update_body(const VecSeg& sg, GState* st, int lb, int64_t stride, int pa
 
     double scale = 1.0;                 // 1 / h_{k+1,k} on the last pass
     auto* __restrict__ dst = w;         // where the corrected vector goes (units of E)
-    if (!last) {
+    bool fin = last != 0;
+    if (last == 2) {
+        double hn2 = ww;
+#pragma unroll
+        for (int i = 0; i < NV; ++i) hn2 -= h[i] * h[i];
+        fin = hn2 > REORTH * ww;         // same bits in every block; NaN: the second pass decides
+    }
+    if (!fin) {
         if (lb == 0 && ti <= NV) {
             if (ti < NV) st->hacc[ti] = s_hacc[ti] + s_h[ti];
             else if (pass == 0) st->wn0 = ww;
+            if (ti == 0) {
+                st->kbytes[3] += 8.0 * (double)(NV + 1) * (double)n;   // this pass's multi-dot
+                st->kbytes[4] += 8.0 * (double)(NV + 2) * (double)n;   // and correction (w in place)
+            }
         }
     } else {
         // Arnoldi column k (earlier passes were committed by earlier kernels)
@@ -670,10 +699,10 @@ LaunchTiming& launch_timing() {
 
 namespace {
 template <int NV>
-void md_launch(const VecSeg* s, int nseg, int G, int, hipStream_t st) { LAUNCH_V(k_multidot<NV>, G, s, nseg); }
+void md_launch(const VecSeg* s, int nseg, int G, int gate, hipStream_t st) { LAUNCH_V(k_multidot<NV>, G, s, nseg, gate); }
 template <int NV>
 void up_launch(const VecSeg* s, int nseg, int G, int pl, hipStream_t st) {
-    LAUNCH_V(k_update<NV>, G, s, nseg, pl >> 1, pl & 1);
+    LAUNCH_V(k_update<NV>, G, s, nseg, pl >> 2, pl & 3);
 }
 using VLaunch = void (*)(const VecSeg*, int, int, int, hipStream_t);
 template <int... I>
@@ -685,13 +714,23 @@ constexpr std::array<VLaunch, sizeof...(I)> up_table(std::integer_sequence<int, 
 void vk_rnorm(const VecSeg* s, int nseg, int G, hipStream_t st) { LAUNCH_V(k_rnorm, G, s, nseg); }
 void vk_begin(const VecSeg* s, int nseg, hipStream_t st) { LAUNCH_V(k_begin, nseg, s, nseg); }
 void vk_scale_v0(const VecSeg* s, int nseg, int G, hipStream_t st) { LAUNCH_V(k_scale_v0, G, s, nseg); }
-void vk_multidot(const VecSeg* s, int nseg, int G, int k, hipStream_t st) {
+void vk_multidot(const VecSeg* s, int nseg, int G, int k, hipStream_t st, int gate) {
     static const auto tbl = md_table(std::make_integer_sequence<int, MMAX>{});
-    tbl[k](s, nseg, G, 0, st);
+    tbl[k](s, nseg, G, gate, st);
 }
 void vk_update(const VecSeg* s, int nseg, int G, int pass, int last, int k, hipStream_t st) {
     static const auto tbl = up_table(std::make_integer_sequence<int, MMAX>{});
-    tbl[k](s, nseg, G, (pass << 1) | (last ? 1 : 0), st);
+    tbl[k](s, nseg, G, (pass << 2) | (last & 3), st);
+}
+void gs_pass_plan(int passes, int p, int* last, int* gate) {
+    // passes 1: CGS1; 2: CGS2; 0: adaptive (pass 0 decides whether pass 1 runs)
+    if (passes == 0) {
+        *last = p == 0 ? 2 : 1;
+        *gate = p == 1;
+    } else {
+        *last = p == passes - 1 ? 1 : 0;
+        *gate = 0;
+    }
 }
 void vk_finish(const VecSeg* s, int nseg, hipStream_t st) {
     launch_k(k_finish, dim3(nseg), dim3(BLOCK), st, s, nseg);

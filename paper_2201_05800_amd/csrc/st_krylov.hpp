@@ -11,10 +11,15 @@ constexpr int NPART_SLOTS = MMAX + 2;   // per-block partial slots of the multi-
 void vk_rnorm(const VecSeg* s, int nseg, int G, hipStream_t st);      // partial ||R||^2
 void vk_begin(const VecSeg* s, int nseg, hipStream_t st);             // ||R||, cycle state
 void vk_scale_v0(const VecSeg* s, int nseg, int G, hipStream_t st);
-// k: the Arnoldi step index (0 .. m-1), the same for every slab of the launch
-void vk_multidot(const VecSeg* s, int nseg, int G, int k, hipStream_t st);
-// pass: Gram-Schmidt pass index; last: the final pass (writes V_{k+1} normalised)
+// k: the Arnoldi step index (0 .. m-1), the same for every slab of the launch;
+// gate: read the cycle state before loading (a pass that usually exits)
+void vk_multidot(const VecSeg* s, int nseg, int G, int k, hipStream_t st, int gate = 0);
+// pass: Gram-Schmidt pass index; last: 1 the final pass (writes V_{k+1}
+// normalised), 0 not, 2 the final pass unless the new vector's norm cancels
+// (then the next pass is)
 void vk_update(const VecSeg* s, int nseg, int G, int pass, int last, int k, hipStream_t st);
+// last / gate of pass p for a cgs_passes option (0 adaptive, 1, 2)
+void gs_pass_plan(int passes, int p, int* last, int* gate);
 void vk_finish(const VecSeg* s, int nseg, hipStream_t st);
 void vk_update_u(const VecSeg* s, int nseg, int G, hipStream_t st);
 void vk_init_guess(const VecSeg* s, int nseg, int G, hipStream_t st);
@@ -68,6 +73,10 @@ std::vector<double> pc_pack(const std::vector<double>& binv, int npe);
 // every segment of one launch has the same npe
 void pc_apply(const PcSeg* s, int nseg, int G, int npe, hipStream_t st);
 void pc_combine(const VecSeg* s, int nseg, int G, hipStream_t st);
+// forward substitution over the slabs of a coupled system (k_slab_sweep)
+void pc_sweep(const SweepArgs& a, hipStream_t st);
+// the first-time-node columns of B^-1 (npe x nv ns, row-major) from its packed form
+std::vector<double> pc_inflow_columns(const std::vector<double>& packed, int npe, int nv, int nt, int ns);
 void pc_set_units(double* x, int64_t ld, int count, hipStream_t st);
 void put_pcseg(PcSeg* dst, const PcSeg& v, hipStream_t st);
 void put_opseg(OpSeg* dst, const OpSeg& v, hipStream_t st);

@@ -3,7 +3,7 @@
 // tight serving loops, harnesses that forbid hipMalloc).  It takes the problem
 // itself instead of a handle, and every device buffer its kernels need beyond
 // the caller's inputs and outputs -- the launch descriptors and, for
-// Navier-Stokes, the viscous-flux array of the BR1 pass -- from one
+// Navier-Stokes, the output of the BR1 viscous pass -- from one
 // file-scope device array of fixed size.  The kernels are st_residual's.
 #include "st_engine.hpp"
 
@@ -21,8 +21,7 @@ static __device__ __align__(256) unsigned char scratch[ST_NOALLOC_SCRATCH_BYTES]
 namespace {
 
 // Layout of the static scratch array: two operator descriptors (viscous pass,
-// operator), then the Navier-Stokes viscous-flux array -Fv (d values per
-// unknown).
+// operator), then the Navier-Stokes viscous pass's output (visc_len values).
 constexpr size_t SCRATCH_BYTES = (size_t)ST_NOALLOC_SCRATCH_BYTES;
 constexpr size_t DESC_SLOT = 16384;
 constexpr size_t Q_OFFSET = 2 * DESC_SLOT;
@@ -64,9 +63,9 @@ int st_residual_noalloc(const st_mesh_t* mesh, int N, int Nt, const st_equation_
     int rc = make_problem(mesh, N, Nt, eq, pb);
     if (rc != ST_OK) return rc;
     const bool visc = grad_pass(pb);
-    const size_t qbytes = visc ? sizeof(double) * (size_t)pb.n * pb.mesh.dim : 0;
+    const size_t qbytes = visc ? sizeof(double) * (size_t)visc_len(pb) : 0;
     if (Q_OFFSET + qbytes > SCRATCH_BYTES)
-        return set_error(ST_ERR_BAD_ARG, "st_residual_noalloc: the viscous-flux array (" + std::to_string(qbytes) +
+        return set_error(ST_ERR_BAD_ARG, "st_residual_noalloc: the viscous pass's output (" + std::to_string(qbytes) +
                                              " bytes) exceeds the static scratch (" +
                                              std::to_string(SCRATCH_BYTES - Q_OFFSET) + " bytes)");
     void* base = nullptr;

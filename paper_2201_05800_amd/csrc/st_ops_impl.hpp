@@ -301,14 +301,118 @@ struct Flux {
     }
 };
 
+// Index of spatial node (coordinates ic) on a face normal to axis a: the
+// other axes in increasing order, the first one fastest.
+template <int D, int N1>
+DI int face_index(int a, const int* ic) {
+    if constexpr (D == 1) return 0;
+    else if constexpr (D == 2) return a == 0 ? ic[1] : ic[0];
+    else return a == 0 ? ic[1] + N1 * ic[2] : ic[0] + N1 * (a == 1 ? ic[2] : ic[1]);
+}
+
+// Offset of (axis a, side, variable v >= 1, time node j, face node f) in an
+// element's viscous face traces (vtrace_per_elem values per element).
+template <int D, int N1, int NT>
+DI int vtrace_at(int a, int side, int v, int j, int f) {
+    constexpr int NF = ipow(N1, D - 1);
+    return ((a * 2 + side) * (D + 1) + v - 1) * (NT * NF) + j * NF + f;
+}
+
+// BR1 viscous state of the Navier-Stokes equations at one node of an element
+// tile: the lifted gradient of the conservative variables along each axis b
+// (strong form),
+//   q_b = (2/h_b) [ sum_k D_{i_b,k} u_k + M^-1 B (u_hat - u) ],  u_hat = {u},
+// for the node's time level (no viscous flux in time), folded at once into
+// the velocity and temperature gradients of Flux::Visc.
+//   tile: [plane][v][node] with pitch NL, the value plane then (JVP) the
+//         tangent plane; nd: the node's tile index, s its spatial node;
+//   sD:   the LGL differentiation matrix (LDS copy);
+//   u, w: the node's state and its primitives;
+//   nb(b, right, un): the neighbour's state across the face of axis b at the
+//         matching node (called on face nodes only; interior lifts vanish);
+//   zs:   PARK only: [row][node] with pitch NL, D D + D rows (twice as many
+//         for a JVP: values, then tangents), where the gradients are parked
+//         axis by axis and reloaded, so that fewer registers are live while
+//         the next axes are differentiated.
+template <int D, int N1, class CT, class T, class F, bool JVP, bool PARK, class NB>
+DI void br1_visc(const CT* tile, const CT* sD, CT* zs, int NL, int nd, int s, const T* u,
+                 const typename F::Prim& w, const OpSeg& sg, NB&& nb, typename F::Visc& z) {
+    constexpr int R = D + 2;
+    constexpr int NZ = D * D + D;
+    const CT iw0 = CT(sg.iw0);
+    F::visc_pre(w, z);
+    static_for<0, D>([&](auto B_) {
+        constexpr int b = decltype(B_)::value;
+        constexpr int stride = ipow(N1, b);
+        const int ib = coord<N1, b>(s);
+        T un[R];
+        if (ib == 0 || ib == N1 - 1) {
+            nb(b, ib == N1 - 1, un);
+        } else {
+#pragma unroll
+            for (int v = 0; v < R; ++v) un[v] = u[v];
+        }
+        CT Drow[N1];
+#pragma unroll
+        for (int k = 0; k < N1; ++k) Drow[k] = sD[ib * N1 + k];
+        const CT J = CT(sg.rh[b]);
+        const CT lw = ib == N1 - 1 ? iw0 : (ib == 0 ? -iw0 : CT(0));
+        T qb[R];
+#pragma unroll
+        for (int v = 0; v < R; ++v) {
+            const CT* ln = tile + v * NL + nd - ib * stride;
+            CT gv = Drow[0] * ln[0];
+#pragma unroll
+            for (int k = 1; k < N1; ++k) gv += Drow[k] * ln[k * stride];
+            T g;
+            if constexpr (JVP) {
+                const CT* lt = ln + R * NL;
+                CT gt = Drow[0] * lt[0];
+#pragma unroll
+                for (int k = 1; k < N1; ++k) gt += Drow[k] * lt[k * stride];
+                g = make_state<T>(gv, gt);
+            } else {
+                g = gv;
+            }
+            g = g + lw * (CT(0.5) * (u[v] + un[v]) - u[v]);
+            qb[v] = J * g;
+        }
+        F::visc_axis(b, w, qb, z, sg.P);
+        if constexpr (PARK) {
+#pragma unroll
+            for (int c = 0; c < D; ++c) {
+                zs[(b * D + c) * NL + nd] = value(z.gv[b][c]);
+                if constexpr (JVP) zs[(NZ + b * D + c) * NL + nd] = part(z.gv[b][c]);
+            }
+            zs[(D * D + b) * NL + nd] = value(z.gT[b]);
+            if constexpr (JVP) zs[(NZ + D * D + b) * NL + nd] = part(z.gT[b]);
+        }
+    });
+    if constexpr (PARK) {
+        // reload (the asm keeps the compiler from carrying the values in
+        // registers across the axes instead)
+        __asm__ volatile("" ::: "memory");
+        auto ld = [&](int row) { return make_state<T>(zs[row * NL + nd], JVP ? zs[(NZ + row) * NL + nd] : CT(0)); };
+#pragma unroll
+        for (int b = 0; b < D; ++b) {
+#pragma unroll
+            for (int c = 0; c < D; ++c) z.gv[b][c] = ld(b * D + c);
+            z.gT[b] = ld(D * D + b);
+        }
+    }
+    F::visc_div(z);
+}
+
 // ---------------------------------------------------------------------------
 // Residual / JVP kernel of the nonlinear equations (the linear ones use
 // k_lin below).
 //   JVP = false: out = R(U) with u_prev (null = 0); CT compute type, UT storage
 //                type of U.
 //   JVP = true : out = J(U) v by dual numbers (U of type UT, v double).
-// Navier-Stokes reads the viscous part of the total flux, own and the
-// neighbours' at face nodes, from the viscous pass (k_visc).
+// Navier-Stokes: the convective part as for Euler; the viscous pass (k_visc)
+// has left the viscous terms of the element's own residual (added at the
+// end) and its face traces of -Fv, from which the face points add the
+// neighbour's half of the BR1 flux.
 // ---------------------------------------------------------------------------
 template <int EQ, int D, int N1, int NT, class CT, class UT, bool JVP>
 __global__ __launch_bounds__((Shape<D, N1, NT, tpt_of(EQ, NT)>::BS)) void k_op(const OpSeg* __restrict__ segs,
@@ -327,6 +431,8 @@ __global__ __launch_bounds__((Shape<D, N1, NT, tpt_of(EQ, NT)>::BS)) void k_op(c
     constexpr int EV = R * NPE;                  // values of one element
     constexpr int LP = lds_pitch(NPE);           // LDS pitch of one element's nodes
     constexpr int NL = EPB * LP;                 // LDS plane: the block's nodes of one variable
+    // NS: the viscous pass's output per element, and where its traces start
+    constexpr int PE = NSV ? visc_per_elem(D, N1, NT) : 0, VRS = NSV ? visc_vr_per_elem(D, N1, NT) : 0;
     __shared__ CT tile[TS * R * NL];             // [plane][v][node]: value, then tangent
     __shared__ CT buf[D * R * NL];               // [a][v][node]: flux along a, then H - f
     __shared__ CT sD[N1 * N1], sDt[NT * NT], swt[NT];
@@ -338,8 +444,7 @@ __global__ __launch_bounds__((Shape<D, N1, NT, tpt_of(EQ, NT)>::BS)) void k_op(c
     const int skip = load_index(sg.skip);
     const gptr<UT> __restrict__ Up = resolve<UT>(sg.U);
     const gptr<double> __restrict__ Vp = JVP ? resolve<double>(sg.V) : nullptr;
-    // NS: the viscous part of the total flux, -Fv along every axis (its
-    // tangent for a JVP), from the viscous pass (k_visc)
+    // NS: the viscous pass's output (its tangent for a JVP)
     const gptr<CT> __restrict__ Qp = NSV ? resolve<CT>(sg.Q) : nullptr;
     const gptr<double> __restrict__ out = resolve<double>(sg.out);
     if (skip) return;
@@ -372,17 +477,20 @@ __global__ __launch_bounds__((Shape<D, N1, NT, tpt_of(EQ, NT)>::BS)) void k_op(c
         if constexpr (JVP) x.d += g;
         else x += g;
     };
-    // -Fv along axis a at element node rr of element ee
-    auto load_visc = [&](int ee, int rr, int a, CT* g) {
-        const gptr<CT> Qe = Qp + (int64_t)ee * (D * EV);
+    // -Fv of element ee from its face traces at offset o (variable 1; the
+    // density's viscous flux is zero)
+    auto load_trace = [&](int ee, int o, CT* g) {
+        const gptr<CT> Qe = Qp + (int64_t)ee * PE + VRS;
+        g[0] = CT(0);
 #pragma unroll
-        for (int v = 0; v < R; ++v) g[v] = Qe[(a * R + v) * NPE + rr];
+        for (int v = 1; v < R; ++v) g[v] = Qe[o + (v - 1) * (NT * NF)];
     };
 
     // Face points: (axis a, element, side, time group, face node), axis-major
     // so that a wavefront mostly works on one axis.
     struct FPI {
         int a, pel, to0, rn0, en, stride;
+        int tq;                  // NS: the neighbour's face-trace offset (its face on the other side)
         bool right, ok, local;   // local: the neighbour is one of the block's elements (state from the tile)
     };
     auto fp_info = [&](int p) {
@@ -404,6 +512,7 @@ __global__ __launch_bounds__((Shape<D, N1, NT, tpt_of(EQ, NT)>::BS)) void k_op(c
         fi.to0 = fi.pel * LP + jg * TPT * NS + so;                                     // own block node
         fi.en = fi.ok ? neighbour(sg, ep, ecoord(sg, ep), fi.a, fi.right) : 0;
         fi.local = fi.ok && fi.en >= e0 && fi.en < e0 + EPB;
+        fi.tq = NSV ? vtrace_at<D, N1, NT>(fi.a, fi.right ? 0 : 1, 1, jg * TPT, f) : 0;
         return fi;
     };
     // neighbour data of a face point: its state (and NS: its -Fv along the
@@ -417,7 +526,7 @@ __global__ __launch_bounds__((Shape<D, N1, NT, tpt_of(EQ, NT)>::BS)) void k_op(c
 #pragma unroll
         for (int jj = 0; jj < TPT; ++jj) {
             if (!fi.local) load_state(fi.en, fi.rn0 + jj * NS, d.un[jj]);
-            if constexpr (NSV) load_visc(fi.en, fi.rn0 + jj * NS, fi.a, d.gn[jj]);
+            if constexpr (NSV) load_trace(fi.en, fi.tq + jj * NF, d.gn[jj]);
         }
     };
     auto fp_compute = [&](const FPI& fi, const FPD& d) {
@@ -479,14 +588,15 @@ __global__ __launch_bounds__((Shape<D, N1, NT, tpt_of(EQ, NT)>::BS)) void k_op(c
     const CT tDt = CT(sg.Dt[tid < NT * NT ? tid : 0]);
     const CT twt = CT(sg.wt[tid < NT ? tid : 0]);
     T u[TPT][R];
-    CT gv[NSV ? TPT : 1][NSV ? D : 1][NSV ? R : 1];    // own -Fv, every axis
+    CT vr[NSV ? R : 1];                                   // NS: own viscous residual terms (v >= 1)
     if (active) {
 #pragma unroll
-        for (int jj = 0; jj < TPT; ++jj) {
-            load_state(e, r0 + jj * NS, u[jj]);
-            if constexpr (NSV)
+        for (int jj = 0; jj < TPT; ++jj) load_state(e, r0 + jj * NS, u[jj]);
+        if constexpr (NSV) {
+            static_assert(TPT == 1, "Navier-Stokes takes one space-time node per thread");
+            const gptr<CT> Qe = Qp + (int64_t)e * PE;
 #pragma unroll
-                for (int a = 0; a < D; ++a) load_visc(e, r0 + jj * NS, a, gv[jj][a]);
+            for (int v = 1; v < R; ++v) vr[v] = Qe[(v - 1) * NPE + r0];
         }
     } else {
 #pragma unroll
@@ -510,7 +620,8 @@ __global__ __launch_bounds__((Shape<D, N1, NT, tpt_of(EQ, NT)>::BS)) void k_op(c
             }
     }
 
-    // (1) total flux along every axis at the own nodes -> buf
+    // (1) total flux along every axis at the own nodes -> buf (NS: the
+    //     convective part; the viscous terms come from the viscous pass)
     if (active) {
 #pragma unroll
         for (int jj = 0; jj < TPT; ++jj) {
@@ -519,9 +630,6 @@ __global__ __launch_bounds__((Shape<D, N1, NT, tpt_of(EQ, NT)>::BS)) void k_op(c
                 constexpr int a = decltype(A)::value;
                 T f[R];
                 F::conv(a, u[jj], w, f, P);
-                if constexpr (NSV)
-#pragma unroll
-                    for (int v = 0; v < R; ++v) add_part(f[v], gv[jj][a][v]);
 #pragma unroll
                 for (int v = 0; v < R; ++v) buf[(a * R + v) * NL + nd0 + jj * NS] = part(f[v]);
             });
@@ -583,6 +691,9 @@ __global__ __launch_bounds__((Shape<D, N1, NT, tpt_of(EQ, NT)>::BS)) void k_op(c
                     for (int v = 0; v < R; ++v) acc[jj][v] -= wl * buf[(a * R + v) * NL + nd0 + jj * NS];
             }
         });
+        if constexpr (NSV)
+#pragma unroll
+            for (int v = 1; v < R; ++v) acc[0][v] += vr[v];
         const CT hdt = CT(0.5 * sg.dt);
         const gptr<double> oe = out + (int64_t)e * EV + r0;
 #pragma unroll
@@ -927,18 +1038,22 @@ __global__ __launch_bounds__((Shape<D, N1, NT, NT>::BS)) void k_lin(const OpSeg*
 }
 
 // ---------------------------------------------------------------------------
-// Navier-Stokes viscous pass.  The BR1 lifted gradient of the conservative
-// variables (strong form),
-//   q_b = (2/h_b) [ sum_k D_{i_b,k} u_k + M^-1 B (u_hat - u) ],  u_hat = {u},
-// for every time node (no viscous flux in time), and from it the viscous part
-// of the total flux, -Fv(u, q), along every axis, which k_op adds to the
-// convective flux at its own nodes and reads for the neighbours' face nodes.
-// JVP = true: the tangent of -Fv at (U, v) by dual numbers (U of type UT, v
-// double).  Output out[((e * D + a) * R + v) * Nt + j) * ns + s], type CT.
-// Same block shape and traversal as k_op.
+// Navier-Stokes viscous pass.  Every node computes its BR1 viscous state
+// (br1_visc) and from it g_a = -Fv_a(u, q), the viscous part of the total
+// flux along each axis a.  The pass writes, per element (layout of
+// visc_per_elem):
+//   * the viscous terms of the element's own residual, in k_op's units
+//     (before the DG time terms): the volume term -(2/h_a) sum_k D_{ia,k} g_a,k
+//     over the axes, and on face nodes the own half of the BR1 face flux
+//     {g} - g = (g_nb - g) / 2, lifted: + (1/2) (2/h_a) M^-1 B g;
+//   * the face traces of g_a along the face axis (corner and edge nodes on
+//     every face they lie on), from which the neighbours add the other half.
+// k_op then treats Navier-Stokes like Euler, plus these two reads.
+// JVP = true: the tangent at (U, v) by dual numbers (U of type UT, v
+// double).  Output of type CT.  Same block shape as k_op.
 // ---------------------------------------------------------------------------
-// At least two waves per SIMD are asked for; the FP64 tangent pass keeps
-// within that by parking the viscous state in LDS (below).
+// At least two waves per SIMD are asked for; the pass keeps within that by
+// parking the viscous state in LDS (br1_visc).
 template <int D, int N1, int NT, class CT, class UT, bool JVP>
 __global__ __attribute__((amdgpu_waves_per_eu(2))) __launch_bounds__((Shape<D, N1, NT, 1>::BS)) void k_visc(const OpSeg* __restrict__ segs, int nseg, int G) {
     using SH = Shape<D, N1, NT, 1>;
@@ -947,13 +1062,11 @@ __global__ __attribute__((amdgpu_waves_per_eu(2))) __launch_bounds__((Shape<D, N
     constexpr int R = D + 2;
     constexpr int NS = SH::NS, NPE = SH::NPE, EPB = SH::EPB, B = SH::B;
     constexpr int EV = R * NPE;
+    constexpr int PE = visc_per_elem(D, N1, NT), VRS = visc_vr_per_elem(D, N1, NT);
     constexpr int TS = JVP ? 2 : 1;
     __shared__ CT tile[TS * R * B];             // [plane][v][node]
-    // JVP: the velocity and temperature gradients (value, tangent) parked in
-    // LDS while the next axes are differentiated, so the tangent pass holds
-    // fewer registers ([plane][b * D + c | D * D + b][node])
-    constexpr int NZ = D * D + D;
-    __shared__ CT zs[JVP ? 2 * NZ * B : 1];
+    constexpr int NZ = D * D + D;               // = D (R - 1): also the rows of g staged below
+    __shared__ CT zs[(JVP ? 2 : 1) * NZ * B];   // parked viscous state, then g [a][v - 1][node]
     __shared__ CT sD[N1 * N1];
     const int L = xcd_remap(blockIdx.x, G);
     const OpSeg& sg = segs[find_seg(segs, nseg, L)];
@@ -966,7 +1079,8 @@ __global__ __attribute__((amdgpu_waves_per_eu(2))) __launch_bounds__((Shape<D, N
     const int tid = threadIdx.x;
     const int el = (int)((unsigned)tid / NPE);
     const int r = tid - el * NPE;
-    const int s = (int)((unsigned)r % NS);
+    const int j = (int)((unsigned)r / NS);
+    const int s = r - j * NS;
     const int e0 = block_elem0<EPB>(sg, L - sg.blk0);
     const int e = e0 + el;
     const bool active = (tid < B) && (e < sg.E);
@@ -991,86 +1105,69 @@ __global__ __attribute__((amdgpu_waves_per_eu(2))) __launch_bounds__((Shape<D, N
         }
     }
     __syncthreads();
-    if (!active) return;
+    int ic[D];
+    static_for<0, D>([&](auto A) { ic[decltype(A)::value] = coord<N1, decltype(A)::value>(s); });
+    const gptr<CT> Qe = Qp + (int64_t)e * PE;
     const CT iw0 = CT(sg.iw0);
-    const ECoord x = ecoord(sg, e);
-    const typename F::Prim w = F::prim(u, P);
-    typename F::Visc z;
-    F::visc_pre(w, z);
-    // lifted gradient along each axis b, folded into the viscous state at
-    // once; the neighbour across the face of a face node is read per axis
-    // (few registers held: this pass carries the whole viscous state)
-    static_for<0, D>([&](auto B_) {
-        constexpr int b = decltype(B_)::value;
-        constexpr int stride = ipow(N1, b);
-        const int ib = coord<N1, b>(s);
-        T un[R];
-        if (ib == 0 || ib == N1 - 1) {
-            const bool right = ib == N1 - 1;
-            load_state(neighbour(sg, e, x, b, right), r + ((right ? 0 : N1 - 1) - ib) * stride, un);
-        } else {
+    CT vr[R];                                   // the node's own viscous residual terms (v >= 1)
+    if (active) {
+        const ECoord x = ecoord(sg, e);
+        const typename F::Prim w = F::prim(u, P);
+        typename F::Visc z;
+        br1_visc<D, N1, CT, T, F, JVP, true>(tile, sD, zs, B, tid, s, u, w, sg,
+                                             [&](int b, bool right, T* un) {
+                                                 const int stride = b == 0 ? 1 : (b == 1 ? N1 : N1 * N1);
+                                                 load_state(neighbour(sg, e, x, b, right),
+                                                            r + ((right ? 0 : N1 - 1) - ic[b]) * stride, un);
+                                             },
+                                             z);
 #pragma unroll
-            for (int v = 0; v < R; ++v) un[v] = u[v];   // interior: the lift below vanishes exactly
-        }
-        CT Drow[N1];
+        for (int v = 1; v < R; ++v) vr[v] = CT(0);
+        // g along every axis: staged for the volume term (this thread's
+        // column of zs only, which its own reload above has consumed), on
+        // face nodes stored as traces and lifted into the own half
+        static_for<0, D>([&](auto A) {
+            constexpr int a = decltype(A)::value;
+            T f[R];
 #pragma unroll
-        for (int k = 0; k < N1; ++k) Drow[k] = sD[ib * N1 + k];
-        const CT J = CT(sg.rh[b]);
-        const CT lw = ib == N1 - 1 ? iw0 : (ib == 0 ? -iw0 : CT(0));
-        T qb[R];
+            for (int v = 0; v < R; ++v) f[v] = make_state<T>(CT(0), CT(0));
+            F::sub_visc(a, w, z, f, P);
 #pragma unroll
-        for (int v = 0; v < R; ++v) {
-            const CT* ln = tile + v * B + tid - ib * stride;
-            CT gv = Drow[0] * ln[0];
+            for (int v = 1; v < R; ++v) zs[(a * (R - 1) + v - 1) * B + tid] = part(f[v]);
+            const int ia = ic[a];
+            if (ia == 0 || ia == N1 - 1) {
+                const int o = VRS + vtrace_at<D, N1, NT>(a, ia == 0 ? 0 : 1, 1, j, face_index<D, N1>(a, ic));
+                const CT wl = ia == N1 - 1 ? CT(sg.rh[a]) * iw0 : -(CT(sg.rh[a]) * iw0);
 #pragma unroll
-            for (int k = 1; k < N1; ++k) gv += Drow[k] * ln[k * stride];
-            T g;
-            if constexpr (JVP) {
-                const CT* lt = ln + R * B;
-                CT gt = Drow[0] * lt[0];
-#pragma unroll
-                for (int k = 1; k < N1; ++k) gt += Drow[k] * lt[k * stride];
-                g = make_state<T>(gv, gt);
-            } else {
-                g = gv;
+                for (int v = 1; v < R; ++v) {
+                    Qe[o + (v - 1) * (NT * ipow(N1, D - 1))] = part(f[v]);
+                    vr[v] += CT(0.5) * wl * part(f[v]);
+                }
             }
-            g = g + lw * (CT(0.5) * (u[v] + un[v]) - u[v]);
-            qb[v] = J * g;
-        }
-        F::visc_axis(b, w, qb, z, P);
-        if constexpr (JVP) {
-#pragma unroll
-            for (int c = 0; c < D; ++c) {
-                zs[(b * D + c) * B + tid] = value(z.gv[b][c]);
-                zs[(NZ + b * D + c) * B + tid] = part(z.gv[b][c]);
-            }
-            zs[(D * D + b) * B + tid] = value(z.gT[b]);
-            zs[(NZ + D * D + b) * B + tid] = part(z.gT[b]);
-        }
-    });
-    if constexpr (JVP) {
-        // reload (the asm keeps the compiler from carrying the values in
-        // registers across the axes instead)
-        __asm__ volatile("" ::: "memory");
-#pragma unroll
-        for (int b = 0; b < D; ++b) {
-#pragma unroll
-            for (int c = 0; c < D; ++c)
-                z.gv[b][c] = make_state<T>(zs[(b * D + c) * B + tid], zs[(NZ + b * D + c) * B + tid]);
-            z.gT[b] = make_state<T>(zs[(D * D + b) * B + tid], zs[(NZ + D * D + b) * B + tid]);
-        }
+        });
     }
-    F::visc_div(z);
-    const gptr<CT> Qe = Qp + (int64_t)e * (D * EV);
+    __syncthreads();
+    if (!active) return;
+    // volume term -(2/h_a) sum_k D_{ia,k} g_a,k
     static_for<0, D>([&](auto A) {
         constexpr int a = decltype(A)::value;
-        T f[R];
+        constexpr int stride = ipow(N1, a);
+        const int ia = ic[a];
+        CT Drow[N1];
 #pragma unroll
-        for (int v = 0; v < R; ++v) f[v] = make_state<T>(CT(0), CT(0));
-        F::sub_visc(a, w, z, f, P);
+        for (int k = 0; k < N1; ++k) Drow[k] = sD[ia * N1 + k];
+        const CT J = CT(sg.rh[a]);
 #pragma unroll
-        for (int v = 0; v < R; ++v) Qe[(a * R + v) * NPE + r] = part(f[v]);
+        for (int v = 1; v < R; ++v) {
+            const CT* ln = zs + (a * (R - 1) + v - 1) * B + tid - ia * stride;
+            CT sum = Drow[0] * ln[0];
+#pragma unroll
+            for (int k = 1; k < N1; ++k) sum += Drow[k] * ln[k * stride];
+            vr[v] -= J * sum;
+        }
     });
+#pragma unroll
+    for (int v = 1; v < R; ++v) Qe[(v - 1) * NPE + r] = vr[v];
 }
 
 // ---------------------------------------------------------------------------

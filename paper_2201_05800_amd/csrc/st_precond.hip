@@ -304,6 +304,54 @@ __global__ __launch_bounds__(VBLOCK) void k_combine(const VecSeg* __restrict__ s
     }
 }
 
+// Forward substitution over the M slabs of a coupled system.  Slab m's
+// inflow term -(U_1 - u^n) (eq. DG_in_time) takes u^n from slab m-1's last
+// time node, so the coupled Jacobian is blockdiag(J_m) + L, with L the unit
+// coupling of slab m's first time node to slab m-1's last.  The
+// preconditioner P = blockdiag(B) + L (B the element block of each J_m) is
+// solved exactly, element by element: with y = B^-1 r of every slab already
+// computed (k_bjacobi),
+//   z_0 = y_0,   z_m = y_m - C l_{m-1}  (m >= 1),   l_m = z_m at the last time node,
+// C = the columns of B^-1 at the first time node (npe x nl, nl = nv ns).
+// One wavefront per element, the slabs in sequence; C staged in LDS when
+// CL.  acc null: z overwrites y in slabs 1..M-1; acc set: acc += z in every
+// slab (the Newton update) and y is left as it is.
+template <bool CL>
+__global__ __launch_bounds__(PC_BLOCK) void k_slab_sweep(SweepArgs a) {
+    extern __shared__ double sm[];           // [CL ? npe nl : 0] C, then [4 waves][2][nl] l
+    if (pc_index(a.skip)) return;
+    const int npe = a.npe, nl = a.nl, nt = a.nt, ns = a.ns;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int e = blockIdx.x * (PC_BLOCK / 64) + wave;
+    const bool active = e < a.E;
+    const double* Cp = a.C;
+    if constexpr (CL) {
+        for (int t = threadIdx.x; t < npe * nl; t += PC_BLOCK) sm[t] = gp(a.C)[t];
+        Cp = sm;
+    }
+    double* lb = sm + (CL ? npe * nl : 0) + wave * 2 * nl;
+    for (int m = 0; m < a.M; ++m) {
+        __syncthreads();                     // l_{m-1} written (and C staged)
+        if (!active) continue;
+        const int64_t off = (int64_t)m * a.n + (int64_t)e * npe;
+        auto* __restrict__ ym = gp(a.y) + off;
+        const double* lprev = lb + ((m + 1) & 1) * nl;
+        double* lnext = lb + (m & 1) * nl;
+        for (int row = lane; row < npe; row += 64) {
+            double z = ym[row];
+            if (m > 0) {
+                const double* Cr = Cp + (int64_t)row * nl;
+                for (int k = 0; k < nl; ++k) z -= Cr[k] * lprev[k];
+            }
+            // row = (v nt + j) ns + s
+            const int vj = row / ns, s = row - vj * ns, v = vj / nt, j = vj - v * nt;
+            if (j == nt - 1) lnext[v * ns + s] = z;
+            if (a.acc) gp(a.acc)[off + row] += z;
+            else if (m > 0) ym[row] = z;
+        }
+    }
+}
+
 __global__ void k_set_units(double* x, int64_t ld, int count) {
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c < count) x[(int64_t)c * ld + c] = 1.0;
@@ -337,6 +385,17 @@ void pc_apply(const PcSeg* s, int nseg, int G, int npe, hipStream_t st) {
             launch_ks(k_bjacobi<false>, dim3(G), dim3(PC_BLOCK), bjacobi_lds(npe), st, s, nseg);
     }
 }
+// C in LDS up to this many bytes (several blocks per CU still fit)
+constexpr size_t SWEEP_C_LDS = 48 * 1024;
+static size_t sweep_lds(const SweepArgs& a, bool cl) {
+    return sizeof(double) * ((cl ? (size_t)a.npe * a.nl : 0) + (size_t)(PC_BLOCK / 64) * 2 * a.nl);
+}
+void pc_sweep(const SweepArgs& a, hipStream_t st) {
+    const bool cl = sizeof(double) * (size_t)a.npe * a.nl <= SWEEP_C_LDS;
+    const dim3 G((a.E + PC_BLOCK / 64 - 1) / (PC_BLOCK / 64));
+    if (cl) launch_ks(k_slab_sweep<true>, G, dim3(PC_BLOCK), sweep_lds(a, true), st, a);
+    else launch_ks(k_slab_sweep<false>, G, dim3(PC_BLOCK), sweep_lds(a, false), st, a);
+}
 void pc_combine(const VecSeg* s, int nseg, int G, hipStream_t st) {
     launch_k(k_combine, dim3(G), dim3(VBLOCK), st, s, nseg);
 }
@@ -363,5 +422,19 @@ std::vector<double> pc_pack(const std::vector<double>& binv, int npe) {
                 if (row < npe && col < npe) a[((size_t)rt * KS + ks) * 64 + l] = binv[(size_t)row * npe + col];
             }
     return a;
+}
+
+// C of k_slab_sweep from the packed B^-1: C[row][v ns + s] = (B^-1)[row][(v nt + 0) ns + s].
+std::vector<double> pc_inflow_columns(const std::vector<double>& packed, int npe, int nv, int nt, int ns) {
+    const int KS = (npe + 3) / 4, nl = nv * ns;
+    std::vector<double> c((size_t)npe * nl);
+    for (int row = 0; row < npe; ++row)
+        for (int v = 0; v < nv; ++v)
+            for (int s = 0; s < ns; ++s) {
+                const int col = v * nt * ns + s;
+                c[(size_t)row * nl + v * ns + s] =
+                    packed[((size_t)(row / 16) * KS + col / 4) * 64 + (row % 16) + 16 * (col % 4)];
+            }
+    return c;
 }
 }  // namespace stdg

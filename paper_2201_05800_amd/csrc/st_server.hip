@@ -91,7 +91,7 @@ Layout layout_of(const Problem& pb, const st_solver_opts_t& o) {
     Layout L;
     int64_t off = 0;
     auto take = [&](int64_t bytes) { int64_t at = off; off += align_up(std::max<int64_t>(bytes, 8)); return at; };
-    const int64_t n = pb.n, d = pb.mesh.dim;
+    const int64_t n = pb.n;
     const bool visc = grad_pass(pb), nonlin = !linear_eq(pb.eq.kind), fp32 = o.inner_fp32 != 0;
     L.U = take(8 * n);
     L.R = take(8 * n);
@@ -99,10 +99,10 @@ Layout layout_of(const Problem& pb, const st_solver_opts_t& o) {
     L.V = take(8 * n * o.restart);
     L.uprev = take(8 * pb.nsp);
     L.unext = take(8 * pb.nsp);
-    L.Q = visc ? take(8 * d * n) : -1;
-    L.dQ = visc ? take(8 * d * n) : -1;
+    L.Q = visc ? take(8 * visc_len(pb)) : -1;
+    L.dQ = visc ? take(8 * visc_len(pb)) : -1;
     L.U32 = (fp32 && nonlin) ? take(4 * n) : -1;
-    L.dQ32 = (fp32 && visc) ? take(4 * d * n) : -1;
+    L.dQ32 = (fp32 && visc) ? take(4 * visc_len(pb)) : -1;
     L.part = take(8 * (int64_t)vec_blocks(n) * (NPART_SLOTS + 1));
     // element-block Jacobi: the preconditioned direction and B^-1 (packed)
     const int npe = pb.nv * pb.Nt * pb.ns;
@@ -115,7 +115,7 @@ Layout layout_of(const Problem& pb, const st_solver_opts_t& o) {
 
 int check_opts(const st_solver_opts_t& o) {
     if (o.restart < 1 || o.restart > MMAX) return set_error(ST_ERR_BAD_ARG, "restart must be in 1..32");
-    if (o.cgs_passes < 1 || o.cgs_passes > 2) return set_error(ST_ERR_BAD_ARG, "cgs_passes must be 1 or 2");
+    if (o.cgs_passes < 0 || o.cgs_passes > 2) return set_error(ST_ERR_BAD_ARG, "cgs_passes must be 0, 1 or 2");
     if (o.max_newton < 1) return set_error(ST_ERR_BAD_ARG, "max_newton must be >= 1");
     if (o.precond < 0 || o.precond > 1) return set_error(ST_ERR_BAD_ARG, "precond must be 0 or 1");
     return ST_OK;
@@ -487,13 +487,13 @@ bool tick(st_srv* s) {
     for (Req* r : cont) vc.push_back(vecseg_of(s, r));
     const int Gc = assign_blocks(vc);
     const int64_t off_vc = pb.add(vc);
-    // the Gram-Schmidt launches by pass count (1: CGS, 2: CGS2), so that a
-    // request gets its own number of passes whatever it is batched with
-    std::vector<VecSeg> vp[2];
-    for (Req* r : cont) vp[r->opts.cgs_passes - 1].push_back(vecseg_of(s, r));
-    int Gp[2];
-    int64_t off_vp[2];
-    for (int q = 0; q < 2; ++q) {
+    // the Gram-Schmidt launches by form ([0] CGS, [1] CGS2, [2] adaptive), so
+    // that a request gets its own passes whatever it is batched with
+    std::vector<VecSeg> vp[3];
+    for (Req* r : cont) vp[r->opts.cgs_passes == 0 ? 2 : r->opts.cgs_passes - 1].push_back(vecseg_of(s, r));
+    int Gp[3];
+    int64_t off_vp[3];
+    for (int q = 0; q < 3; ++q) {
         Gp[q] = assign_blocks(vp[q]);
         off_vp[q] = pb.add(vp[q]);
     }
@@ -577,13 +577,16 @@ bool tick(st_srv* s) {
                                               : (g.fp32 ? g.ops->jvp32 : g.ops->jvp64);
             f((OpSeg*)(D1 + g.off_op), (int)g.op.size(), g.G, st);
         }
-        for (int q = 0; q < 2; ++q) {
+        for (int q = 0; q < 3; ++q) {
             if (vp[q].empty()) continue;
             VecSeg* dq = (VecSeg*)(D1 + off_vp[q]);
             const int nq = (int)vp[q].size();
-            for (int p = 0; p <= q; ++p) {
-                vk_multidot(dq, nq, Gp[q], k, st);
-                vk_update(dq, nq, Gp[q], p, p == q, k, st);
+            const int passes = q == 2 ? 0 : q + 1;
+            for (int p = 0; p < (q == 0 ? 1 : 2); ++p) {
+                int lastp = 0, gate = 0;
+                gs_pass_plan(passes, p, &lastp, &gate);
+                vk_multidot(dq, nq, Gp[q], k, st, gate);
+                vk_update(dq, nq, Gp[q], p, lastp, k, st);
             }
         }
     }

@@ -212,7 +212,7 @@ def initial(P, kind):
 
 @pytest.mark.parametrize("name,c,dt,init", SOLVES, ids=[s[0] for s in SOLVES])
 @pytest.mark.parametrize("fp32", [0, 1], ids=["fp64", "fp32inner"])
-@pytest.mark.parametrize("cgs", [1, 2], ids=["cgs1", "cgs2"])
+@pytest.mark.parametrize("cgs", [1, 2, 0], ids=["cgs1", "cgs2", "cgs_adaptive"])
 def test_slab_solve_parity(orc, name, c, dt, init, fp32, cgs):
     P = Pair(c)
     try:

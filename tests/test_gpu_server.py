@@ -59,12 +59,13 @@ def initial_for(P, kind, seed):
 
 def test_alone_vs_mix_bitwise(orc):
     from paper_2201_05800_amd import st
-    # (kind, problem, FP32-inner, Gram-Schmidt passes): one and two passes
-    # mixed in one batch, each request with its own
+    # (kind, problem, FP32-inner, Gram-Schmidt passes): one, two and the
+    # adaptive form (0) mixed in one batch, each request with its own
     cases = [("burgers", burgers_case(40, 3, 3, 1), 0, 1), ("advdiff", advdiff_case(10, 3, 2), 0, 2),
              ("burgers", burgers_case(23, 5, 4, 2), 1, 1), ("advdiff", advdiff_case(8, 4, 4), 1, 2),
              ("burgers", burgers_case(64, 2, 2, 3), 0, 2), ("advdiff", advdiff_case(12, 2, 3), 1, 1),
-             ("burgers", burgers_case(7, 2, 3, 4), 1, 2)]     # 63 unknowns: element-wise vector paths
+             ("burgers", burgers_case(7, 2, 3, 4), 1, 2),     # 63 unknowns: element-wise vector paths
+             ("advdiff", advdiff_case(9, 3, 3), 0, 0), ("burgers", burgers_case(30, 4, 3, 5), 1, 0)]
     pairs = [Pair(c) for _, c, _, _ in cases]
     try:
         reqs, ups, dts = [], [], []

@@ -86,16 +86,18 @@ SOLVES = [
 
 
 @pytest.mark.parametrize("name,c,dt,init,M", SOLVES, ids=[s[0] for s in SOLVES])
-@pytest.mark.parametrize("mode", ["fp64", "fp32inner", "precond"])
+@pytest.mark.parametrize("mode", ["fp64", "fp32inner", "precond", "precond_sweep"])
 def test_coupled_solve_parity(orc, name, c, dt, init, M, mode):
-    """The coupled M-slab solve against the oracle's slab-by-slab solution."""
+    """The coupled M-slab solve against the oracle's slab-by-slab solution
+    (precond: element-block Jacobi slab by slab; precond_sweep: the same
+    blocks with forward substitution over the slabs)."""
     import torch
     P = Pair(c)
     try:
         up = initial(P, init)
         say("slabs solve", name, mode, "M", M, "dt", dt)
-        o = P.st.st_default_opts(inner_fp32=1 if mode == "fp32inner" else 0, precond=1 if mode == "precond" else 0,
-                                 max_newton=60)
+        pc = {"precond": 1, "precond_sweep": 2}.get(mode, 0)
+        o = P.st.st_default_opts(inner_fp32=1 if mode == "fp32inner" else 0, precond=pc, max_newton=60)
         U = torch.empty(P.n * M, dtype=torch.float64, device="cuda")
         un = torch.empty(P.nsp, dtype=torch.float64, device="cuda")
         st = P.st.st_solve_slabs(P.h, M, dev(up), 0.0, dt, 1e-12, o, U, un)
@@ -104,6 +106,35 @@ def test_coupled_solve_parity(orc, name, c, dt, init, M, mode):
         eu = rel(host(un), orc.last_time_node(P.p, Uo[-P.n:]))
         say(f"  rel err {e:.2e} (u_next {eu:.2e}), outer {st['newton_its']}, gmres {st['gmres_its']}")
         assert e <= SLAB_TOL and eu <= SLAB_TOL
+    finally:
+        P.close()
+
+
+@pytest.mark.parametrize("name,c,dt,init", [
+    ("advdiff2d", cfg("advdiff", 2, [12, 10], 4, 4, a=(1.0, 0.5), nu=1e-3), 1.0 / 128, "fourier"),
+    ("burgers1d", cfg("burgers", 1, [48], 3, 3), 0.01, "burgers"),
+], ids=["advdiff2d", "burgers1d"])
+def test_sweep_cuts_iterations(orc, name, c, dt, init):
+    """Eight coupled slabs: forward substitution over the slabs takes fewer
+    GMRES iterations than the slab-by-slab blocks, and both reach the
+    oracle's solution."""
+    import torch
+    P = Pair(c)
+    M = 8
+    try:
+        up = initial(P, init)
+        Uo = orc.solve_slabs(P.p, up, dt, M, tol=1e-12)
+        its = {}
+        for pc in (1, 2):
+            o = P.st.st_default_opts(precond=pc, max_newton=60)
+            U = torch.empty(P.n * M, dtype=torch.float64, device="cuda")
+            un = torch.empty(P.nsp, dtype=torch.float64, device="cuda")
+            st = P.st.st_solve_slabs(P.h, M, dev(up), 0.0, dt, 1e-12, o, U, un)
+            its[pc] = st["gmres_its"]
+            e = rel(host(U), Uo)
+            say(f"sweep {name} precond {pc}: rel err {e:.2e}, outer {st['newton_its']}, gmres {st['gmres_its']}")
+            assert e <= SLAB_TOL
+        assert its[2] < its[1], its
     finally:
         P.close()
 

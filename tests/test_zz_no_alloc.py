@@ -69,8 +69,8 @@ def test_noalloc_matches_st_residual(name, big, small):
 
 def test_noalloc_rejects_oversized_viscous_array():
     from paper_2201_05800_amd import st
-    # 3D Navier-Stokes, 16^3 hexes, N = 3, Nt = 3: 3.9 M unknowns, a 94 MB
-    # viscous-flux array, beyond the 16 MiB static array
+    # 3D Navier-Stokes, 16^3 hexes, N = 3, Nt = 3: 3.9 M unknowns, 63 MB of
+    # viscous-pass output, beyond the 16 MiB static array
     m = st.mesh(3, [16, 16, 16], [0, 0, 0], [6.283185307179586] * 3)
     eq = st.equation(st.ST_NS_BR1, gamma=1.4, mu=1.0 / 1600, prandtl=0.71)
     x = torch.zeros(8, dtype=torch.float64, device="cuda")
