@@ -86,7 +86,7 @@ DI void map_sweep(const X* x, Y* y, int64_t n, int64_t t0, int64_t stride, F f) 
                     Y2 b;
                     b.x = f(a[q].x);
                     b.y = f(a[q].y);
-                    y2[i + q * stride] = b;
+                    store_nt(&y2[i + q * stride], b);
                 }
         }
     } else {
@@ -99,7 +99,7 @@ DI void map_sweep(const X* x, Y* y, int64_t n, int64_t t0, int64_t stride, F f) 
                 if (i + q * stride < n) a[q] = x1[i + q * stride];
 #pragma unroll
             for (int q = 0; q < UNP; ++q)
-                if (i + q * stride < n) y1[i + q * stride] = f(a[q]);
+                if (i + q * stride < n) store_nt(&y1[i + q * stride], f(a[q]));
         }
     }
 }
@@ -247,6 +247,7 @@ __global__ __launch_bounds__(VBLOCK) void k_begin(const VecSeg* __restrict__ seg
     st->g[0] = nr;
     const double ea = sg.eta_rel * nr, ef = sg.eta_tgt * st->target;
     st->eta_abs = ea > ef ? ea : ef;
+    st->reorth = 0;
     st->nonfinite = !isfinite(nr2);
     st->done = (nr <= st->target) || st->nonfinite;
 }
@@ -286,7 +287,7 @@ __global__ __launch_bounds__(VBLOCK) void k_multidot(const VecSeg* __restrict__ 
         const auto* __restrict__ w = gl((const E*)sg.w);
         int64_t t = (int64_t)lb * VBLOCK + threadIdx.x;
         E a[UN][NV], wv[UN];
-        if (gate && (st->done || st->k != NV - 1)) return false;
+        if (gate && (st->done || !st->reorth)) return false;
         load_group<NV, UN>(V, w, n, t, stride, a, wv);
         if (st->done || st->k != NV - 1) return false;
         auto accumulate = [&](bool first) {
@@ -364,10 +365,13 @@ DI void update_body(const VecSeg& sg, GState* st, int lb, int64_t stride, int pa
     // for the vectors, and the table loads below go out while the vectors
     // are still in flight.
     const auto* sr = gl((const GState*)st);
-    // a gated pass (the second pass of the adaptive form) reads the state
-    // before it loads: it usually finds the step finished
-    if (pass > 0 && last == 1 && (sr->done || sr->k != k)) return;
-    const int done = sr->done || sr->k != k;      // finished, or advanced by the adaptive pass 0
+    // the gated second pass of the adaptive form (last = 3) reads the state
+    // before it loads: it usually finds that pass 0 finished the step.  (The
+    // flag is written by pass 0's launch only; k and done may change within
+    // this launch, where block 0 commits the step.)
+    if (last == 3 && (sr->done || !sr->reorth)) return;
+    if (last == 3) last = 1;
+    const int done = sr->done;
     // g_k, the absolute tolerance and ||w||^2 of pass 0, one per thread
     const double misc_i = !last ? 0.0 : (ti == 0 ? sr->g[k] : (ti == 1 ? sr->eta_abs : (ti == 2 && pass > 0 ? sr->wn0 : 0.0)));
     const double cs_i = (last && ti < k) ? sr->cs[ti] : 0.0;
@@ -398,6 +402,7 @@ DI void update_body(const VecSeg& sg, GState* st, int lb, int64_t stride, int pa
         for (int i = 0; i < NV; ++i) hn2 -= h[i] * h[i];
         fin = hn2 > REORTH * ww;         // same bits in every block; NaN: the second pass decides
     }
+    if (last == 2 && lb == 0 && ti == 0) st->reorth = fin ? 0 : 1;
     if (!fin) {
         if (lb == 0 && ti <= NV) {
             if (ti < NV) st->hacc[ti] = s_hacc[ti] + s_h[ti];
@@ -469,7 +474,7 @@ DI void update_body(const VecSeg& sg, GState* st, int lb, int64_t stride, int pa
         for (int q = 0; q < UN; ++q) {
 #pragma unroll
             for (int i = 0; i < NV; ++i) sub_scaled(wv[q], h[i], a[q][i]);
-            if (t + q * stride < ne) dst[t + q * stride] = scaled(scale, wv[q]);
+            if (t + q * stride < ne) store_nt(&dst[t + q * stride], scaled(scale, wv[q]));
         }
     };
     correct();
@@ -725,7 +730,7 @@ void vk_update(const VecSeg* s, int nseg, int G, int pass, int last, int k, hipS
 void gs_pass_plan(int passes, int p, int* last, int* gate) {
     // passes 1: CGS1; 2: CGS2; 0: adaptive (pass 0 decides whether pass 1 runs)
     if (passes == 0) {
-        *last = p == 0 ? 2 : 1;
+        *last = p == 0 ? 2 : 3;
         *gate = p == 1;
     } else {
         *last = p == passes - 1 ? 1 : 0;

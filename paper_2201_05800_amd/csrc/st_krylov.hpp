@@ -16,7 +16,7 @@ void vk_scale_v0(const VecSeg* s, int nseg, int G, hipStream_t st);
 void vk_multidot(const VecSeg* s, int nseg, int G, int k, hipStream_t st, int gate = 0);
 // pass: Gram-Schmidt pass index; last: 1 the final pass (writes V_{k+1}
 // normalised), 0 not, 2 the final pass unless the new vector's norm cancels
-// (then the next pass is)
+// (then the next pass is), 3 that next pass (exits unless pass 0 asked for it)
 void vk_update(const VecSeg* s, int nseg, int G, int pass, int last, int k, hipStream_t st);
 // last / gate of pass p for a cgs_passes option (0 adaptive, 1, 2)
 void gs_pass_plan(int passes, int p, int* last, int* gate);

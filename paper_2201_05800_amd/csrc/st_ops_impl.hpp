@@ -714,7 +714,7 @@ __global__ __launch_bounds__((Shape<D, N1, NT, tpt_of(EQ, NT)>::BS)) void k_op(c
                     const CT up = (!JVP && upv) ? CT(upv[(int64_t)e * (R * NS) + v * NS + s]) : CT(0);
                     res -= tv(0) - up;
                 }
-                oe[v * NPE + jj * NS] = double(res);
+                store_nt(&oe[v * NPE + jj * NS], double(res));
             }
         }
     }
@@ -1032,7 +1032,7 @@ __global__ __launch_bounds__((Shape<D, N1, NT, NT>::BS)) void k_lin(const OpSeg*
                 const CT up = upv ? CT(upv[(int64_t)e * NS + s]) : CT(0);
                 res -= u[0] - up;
             }
-            oe[j * NS] = double(res);
+            store_nt(&oe[j * NS], double(res));
         }
     }
 }
@@ -1167,6 +1167,7 @@ __global__ __attribute__((amdgpu_waves_per_eu(2))) __launch_bounds__((Shape<D, N
         }
     });
 #pragma unroll
+    // plain stores: k_op reads this output next, partly from the caches
     for (int v = 1; v < R; ++v) Qe[(v - 1) * NPE + r] = vr[v];
 }
 

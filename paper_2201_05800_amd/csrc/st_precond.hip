@@ -161,7 +161,7 @@ __global__ __launch_bounds__(PC_BLOCK) void k_bjacobi(const PcSeg* __restrict__ 
                     if (row < npe) {
                         double z = acc[q][r];
                         if (sg.accumulate) z += out[(int64_t)j * npe + row];
-                        out[(int64_t)j * npe + row] = z;
+                        store_nt(&out[(int64_t)j * npe + row], z);
                     }
                 }
             }
@@ -190,7 +190,7 @@ __global__ __launch_bounds__(PC_BLOCK) void k_bjacobi(const PcSeg* __restrict__ 
         const int j = t / npe, row = t - j * npe;
         double z = sm[j * SR + row];
         if (sg.accumulate) z += out[t];
-        out[t] = z;
+        store_nt(&out[t], z);
     }
 }
 
@@ -273,7 +273,7 @@ __global__ __launch_bounds__(PC_BLOCK) void k_bjacobi_ks(const PcSeg* __restrict
         z += sm[(48 + j) * NR + r];
         const int64_t t = (int64_t)j * npe + row;
         if (sg.accumulate) z += out[t];
-        out[t] = z;
+        store_nt(&out[t], z);
     }
 }
 
@@ -300,7 +300,7 @@ __global__ __launch_bounds__(VBLOCK) void k_combine(const VecSeg* __restrict__ s
 #pragma unroll
             for (int j = 0; j < 8; ++j) u += s_y[i0 + j < MMAX ? i0 + j : MMAX - 1] * (i0 + j < kf ? a[j] : 0.0);
         }
-        w[t] = u;
+        store_nt(&w[t], u);
     }
 }
 
