@@ -289,14 +289,16 @@ int st_residual_noalloc(const st_mesh_t* mesh, int N, int Nt, const st_equation_
  *   Nt > 2:  e = w_1 (D_tau (U - 1 (x) u_prev))_1 + (U_1 - u_prev)
  *                - (w_1 dt / 2) F(u_prev)                    (w_1 = 2 b_1),
  * which at a solved slab is b_1 dt (F(U_1) - F(u_prev)).  F(u_prev) is one
- * evaluation of the slab operator at 1 (x) u_prev with the time terms off.
+ * evaluation of the spatial operator at one time level (the residual
+ * kernels instantiated for a single time node).
  * *err (host) = sqrt(mean over the n_space values of
  * (e / (atol + rtol max(|u_prev|, |u^{n+1}|)))^2).  U: device, slab layout;
  * u_prev: device, spatial layout; dt > 0 the slab's step (t0 is accepted;
  * every supported equation is autonomous).  atol, rtol >= 0, atol + rtol > 0,
  * else ST_ERR_BAD_ARG.  Synchronises `stream` (the value is copied to the
  * host); the first call allocates about 4 KB of device memory, and for
- * Nt > 2 two slab vectors (kept by the handle). */
+ * Nt > 2 one spatial vector (Navier-Stokes: plus its viscous pass's output
+ * at one time level), kept by the handle. */
 int st_error_estimate(st_handle_t h, const double* U, const double* u_prev, double t0, double dt, double atol,
                       double rtol, double* err, void* stream);
 

@@ -505,11 +505,12 @@ struct st_ctx {
     std::vector<double> pc_ubar;   // nonlinear: the mean state it was assembled at
     double* pz = nullptr;
     PcSeg* d_pc = nullptr;
-    // embedded error estimate: partial sums + result; for Nt > 2 the state
-    // 1 (x) u_prev and the spatial operator at it (slab vectors)
+    // embedded error estimate: partial sums + result; for Nt > 2 the spatial
+    // operator at u_prev (a spatial vector) and, for Navier-Stokes, the
+    // viscous pass's output at one time level
     double* d_est = nullptr;
-    double* est_u0 = nullptr;
     double* est_f = nullptr;
+    double* est_q = nullptr;
     // vector buffers (V, w, R, U, pz, Q, dQ, U32, dQ32, d_part) hold `cap`
     // consecutive slabs; the solve's descriptors: 4 cap operator segments
     // (residual viscous pass, residual, JVP viscous pass, JVP) and cap + 2
@@ -1221,29 +1222,38 @@ int st_error_estimate(st_handle_t h, const double* U, const double* u_prev, doub
     EstArgs a;
     std::memset(&a, 0, sizeof(a));
     if (pb.Nt > 2) {
-        // (w_1 dt / 2) F(u_prev) at the first time node of est_f: the slab
-        // operator at U0 = 1 (x) u_prev with the time terms off
-        if (!h->est_u0) {
-            CHK(h->alloc(&h->est_u0, (size_t)pb.n));
-            CHK(h->alloc(&h->est_f, (size_t)pb.n));
+        // (dt / 2) F(u_prev) in est_f: the residual kernels for one time
+        // level with the time derivative off and unit weight, at u_prev with
+        // u_prev as its own inflow (that term is then exactly zero)
+        Problem p1 = pb;
+        p1.Nt = 1;
+        p1.n = pb.nsp;
+        p1.ops = find_table(pb.eq.kind, pb.mesh.dim, pb.n1, 1, pb.ops->rot != 0, pb.ops->bnd != 0);
+        if (!p1.ops) return set_error(ST_ERR_UNSUPPORTED, "st_error_estimate: no one-time-level operator");
+        p1.wt[0] = 1.0;
+        p1.Dt[0] = 0.0;
+        if (!h->est_f) CHK(h->alloc(&h->est_f, (size_t)pb.nsp));
+        if (grad_pass(p1) && !h->est_q) CHK(h->alloc(&h->est_q, (size_t)visc_len(p1)));
+        const OpSeg b = base_opseg(p1, dt);
+        if (grad_pass(p1)) {
+            OpSeg g = b;
+            visc_tiles(g, p1);
+            g.U = dptr(u_prev);
+            g.out = dptr(h->est_q);
+            put_opseg(h->d_op + 0, g, st);
         }
-        VecSeg v;
-        std::memset(&v, 0, sizeof(v));
-        v.U = h->est_u0;
-        v.uprev = u_prev;
-        v.n = pb.n;
-        v.nt = pb.Nt;
-        v.ns = pb.ns;
-        v.nblk = vec_blocks(v.n);
-        v.st = h->d_st;
-        put_vecseg(h->d_vs, v, st);
-        vk_init_guess(h->d_vs, 1, v.nblk, st);
-        setup_residual(h, 1, h->est_u0, u_prev, h->est_f, dt, h->d_op + 0, h->d_op + 1, st, false);
-        h->timer.reset(0);
-        launch_residual(h, 1, h->d_op + 0, h->d_op + 1, couple_args(pb, 1, h->est_u0, nullptr, 0, h->est_f, nullptr),
-                        st);
+        OpSeg x = b;
+        if (grad_pass(p1)) x.Q = dptr(h->est_q);
+        x.U = dptr(u_prev);
+        x.uprev = u_prev;
+        x.out = dptr(h->est_f);
+        put_opseg(h->d_op + 1, x, st);
+        const int G = op_blocks(p1);
+        if (grad_pass(p1)) p1.ops->visc_res64(h->d_op + 0, 1, G, st);
+        p1.ops->res64(h->d_op + 1, 1, G, st);
         for (int j = 0; j < pb.Nt; ++j) a.c[j] = pb.wt[0] * pb.Dt[j];   // w_1 D_tau[0][j]
         a.fs = h->est_f;
+        a.fsw = pb.wt[0];
     }
     a.U = U;
     a.up = u_prev;

@@ -636,7 +636,7 @@ __global__ __launch_bounds__(VBLOCK) void k_errest(EstArgs a) {
         } else {
             double k1 = a.c[0] * (u1 - un);
             for (int j = 1; j < a.nt; ++j) k1 += a.c[j] * (U[base + (int64_t)j * a.ns] - un);
-            e = (k1 + (u1 - un)) - fs[base];
+            e = (k1 + (u1 - un)) - a.fsw * fs[i];
         }
         const double sc = a.atol + a.rtol * fmax(fabs(un), fabs(uN));
         const double r = e / sc;

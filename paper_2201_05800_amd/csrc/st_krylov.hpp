@@ -34,7 +34,8 @@ void vk_cast32(const VecSeg* s, int nseg, int G, hipStream_t st);
 struct EstArgs {
     const double* U;
     const double* up;
-    const double* fs;
+    const double* fs;     // (dt / 2) F(u_prev), a spatial vector (Nt > 2)
+    double fsw;           // its weight w_1
     double* part;
     double* out;
     int64_t nsp;          // E nv ns spatial values

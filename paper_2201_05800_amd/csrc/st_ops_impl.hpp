@@ -1213,4 +1213,23 @@ OpTable make_table() {
     return t;
 }
 
+// The spatial operator at one time level: the residual kernels instantiated
+// for a single time node, run with the time derivative off and unit weight,
+// give (dt/2) F(u) (the inflow term vanishes when u_prev is the state
+// itself).  Only the FP64 residual entries are filled.
+template <int EQ, int D, int N1>
+OpTable make_spatial_table() {
+    OpTable t{};
+    t.eq = EQ; t.dim = D; t.n1 = N1; t.nt = 1; t.epb = Shape<D, N1, 1, 1>::EPB;
+    if constexpr (linear_eq(EQ)) {
+        t.res64 = launch_lin<EQ, D, N1, 1, double, double>;
+        if constexpr (D == 2 && N1 <= ROT_MAX_N1) t.res64_rot = launch_lin<EQ, D, N1, 1, double, double, true>;
+        t.res64_bnd = launch_lin<EQ, D, N1, 1, double, double, false, true>;
+    } else {
+        t.res64 = launch_op<EQ, D, N1, 1, double, double, false>;
+    }
+    if constexpr (EQ == EQ_NS) t.visc_res64 = launch_visc<D, N1, 1, double, double, false>;
+    return t;
+}
+
 }  // namespace stdg
