@@ -55,8 +55,10 @@ static bool pc_small(int npe) {
     return T <= PC_TW && (KS + 3) / 4 <= 8;
 }
 int pc_blocks(int E, int npe) {
-    const int groups = (E + PC_EB - 1) / PC_EB;
-    return pc_small(npe) ? groups * ((npe + 15) / 16) : groups;
+    const int groups = (E + PC_EB - 1) / PC_EB, T = (npe + 15) / 16;
+    if (pc_small(npe)) return groups * T;                      // one block per (elements, row tile)
+    if (T > 4 * PC_TW) return groups * ((T + 4 * PC_TW - 1) / (4 * PC_TW));   // per (elements, row group)
+    return groups;
 }
 
 // out_e (+)= B^-1 in_e for 16 elements per block, as the dense product
@@ -66,11 +68,9 @@ int pc_blocks(int E, int npe) {
 // register i div 4).  B^-1 comes packed per (16-row tile, 4-column step) in
 // that A-operand lane order (zero padded), so each operand is one coalesced
 // load; the block's inputs are staged in LDS in B-operand order; wavefront w
-// takes the row tiles w, w + 4, ... of a group of at most 4 PC_TW tiles.
-// Up to 512 rows (one group) the result goes back through LDS for coalesced
-// stores; larger blocks (up to 1024 rows) run the groups one after the other
-// on the same staged inputs and store each group's tiles directly.
-template <bool GROUPED>
+// takes the row tiles w, w + 4, ... (at most 4 PC_TW tiles: up to 512 rows;
+// larger blocks take k_bjacobi_big).  The result goes back through LDS for
+// coalesced stores.
 __global__ __launch_bounds__(PC_BLOCK) void k_bjacobi(const PcSeg* __restrict__ segs, int nseg) {
     extern __shared__ double sm[];           // [KS * 64] B operands, then [16][npe | 1] results
     const PcSeg& sg = segs[find_pseg(segs, nseg, blockIdx.x)];
@@ -87,8 +87,6 @@ __global__ __launch_bounds__(PC_BLOCK) void k_bjacobi(const PcSeg* __restrict__ 
     const auto* __restrict__ in = gp(inb) + (int64_t)e0 * npe;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const auto* __restrict__ A = gp(sg.binvT);
-    constexpr int GT = 4 * PC_TW;            // row tiles per group
-    int g0 = 0;                              // first row tile of the group
     // A operands of column steps [ks0, ks0 + PC_KC), double buffered: the
     // next chunk's loads are in flight while the current chunk multiplies
     auto load_chunk = [&](int ks0, double (&a)[PC_KC][PC_TW]) {
@@ -96,7 +94,7 @@ __global__ __launch_bounds__(PC_BLOCK) void k_bjacobi(const PcSeg* __restrict__ 
         for (int c = 0; c < PC_KC; ++c)
 #pragma unroll
             for (int q = 0; q < PC_TW; ++q) {
-                const int ks = ks0 + c, rt = g0 + wave + 4 * q;
+                const int ks = ks0 + c, rt = wave + 4 * q;
                 a[c][q] = (rt < T && ks < KS) ? A[((int64_t)rt * KS + ks) * 64 + lane] : 0.0;
             }
     };
@@ -109,7 +107,7 @@ __global__ __launch_bounds__(PC_BLOCK) void k_bjacobi(const PcSeg* __restrict__ 
             const double b = sm[ks * 64 + lane];
 #pragma unroll
             for (int q = 0; q < PC_TW; ++q)
-                if (g0 + wave + 4 * q < T) acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[c][q], b, acc[q], 0, 0, 0);
+                if (wave + 4 * q < T) acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[c][q], b, acc[q], 0, 0, 0);
         }
     };
     double a0[PC_KC][PC_TW], a1[PC_KC][PC_TW];
@@ -137,40 +135,14 @@ __global__ __launch_bounds__(PC_BLOCK) void k_bjacobi(const PcSeg* __restrict__ 
     }
     __syncthreads();
     auto* __restrict__ out = gp(sg.out) + (int64_t)e0 * npe;
-    for (;;) {
 #pragma unroll
-        for (int q = 0; q < PC_TW; ++q) acc[q] = v4d{0.0, 0.0, 0.0, 0.0};
-        for (int ks0 = 0; ks0 < KS; ks0 += 2 * PC_KC) {
-            load_chunk(ks0 + PC_KC, a1);
-            mul_chunk(ks0, a0);
-            if (ks0 + PC_KC >= KS) break;
-            load_chunk(ks0 + 2 * PC_KC, a0);
-            mul_chunk(ks0 + PC_KC, a1);
-        }
-        if constexpr (!GROUPED) break;
-        // this group's tiles straight to memory: element j = lane & 15,
-        // rows 16 rt + (lane >> 4) + 4 r
-        const int j = lane & 15;
-#pragma unroll
-        for (int q = 0; q < PC_TW; ++q) {
-            const int rt = g0 + wave + 4 * q;
-            if (rt < T && j < ne) {
-#pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const int row = rt * 16 + (lane >> 4) + 4 * r;
-                    if (row < npe) {
-                        double z = acc[q][r];
-                        if (sg.accumulate) z += out[(int64_t)j * npe + row];
-                        store_nt(&out[(int64_t)j * npe + row], z);
-                    }
-                }
-            }
-        }
-        if constexpr (GROUPED) {
-            g0 += GT;
-            if (g0 >= T) return;
-            load_chunk(0, a0);
-        }
+    for (int q = 0; q < PC_TW; ++q) acc[q] = v4d{0.0, 0.0, 0.0, 0.0};
+    for (int ks0 = 0; ks0 < KS; ks0 += 2 * PC_KC) {
+        load_chunk(ks0 + PC_KC, a1);
+        mul_chunk(ks0, a0);
+        if (ks0 + PC_KC >= KS) break;
+        load_chunk(ks0 + 2 * PC_KC, a0);
+        mul_chunk(ks0 + PC_KC, a1);
     }
     __syncthreads();                         // B operands consumed: reuse sm for the results
     const int SR = npe | 1;                  // odd row stride: no LDS bank conflicts across j
@@ -191,6 +163,114 @@ __global__ __launch_bounds__(PC_BLOCK) void k_bjacobi(const PcSeg* __restrict__ 
         double z = sm[j * SR + row];
         if (sg.accumulate) z += out[t];
         store_nt(&out[t], z);
+    }
+}
+
+// Large blocks (more than 512 rows, at most 1024): one GPU block per (16
+// elements, group of 4 PC_TW row tiles), with the elements' inputs staged in
+// PC_PARTS parts of the column steps, so that they take half the LDS and two
+// blocks share a CU (two waves per SIMD hide the latency of the streamed A
+// operands, which come from L2 and the Infinity Cache; the row groups in
+// separate blocks give a 4096-element slab 512 of them).  The group
+// accumulates over the parts in registers and stores its tiles directly.
+constexpr int PC_PARTS = 2;
+constexpr int PC_KCB = 4;                   // column steps per A-operand chunk (registers of two waves per SIMD)
+__global__ __launch_bounds__(PC_BLOCK, 2) void k_bjacobi_big(const PcSeg* __restrict__ segs, int nseg) {
+    extern __shared__ double sm[];           // [KP * 64] B operands of one part
+    const PcSeg& sg = segs[find_pseg(segs, nseg, blockIdx.x)];
+    const int skip = pc_index(sg.skip);
+    const int kin = pc_index(sg.in.kp);
+    if (skip) return;
+    const int npe = sg.npe;
+    const int KS = (npe + 3) >> 2, T = (npe + 15) >> 4;
+    const int KP = (KS + PC_PARTS - 1) / PC_PARTS;
+    constexpr int GT = 4 * PC_TW;            // row tiles per group
+    const int NG = (T + GT - 1) / GT;        // row groups
+    const int b = blockIdx.x - sg.blk0;
+    const int eg = b / NG;
+    const int g0 = (b - eg * NG) * GT;       // first row tile of this block's group
+    const int e0 = eg * PC_EB;
+    const int ne = min(PC_EB, sg.E - e0);
+    const double* inb = static_cast<const double*>(sg.in.base);
+    if (sg.in.kp) inb += (int64_t)(kin + sg.in.koff) * sg.in.ld;
+    const auto* __restrict__ in = gp(inb) + (int64_t)e0 * npe;
+    auto* __restrict__ out = gp(sg.out) + (int64_t)e0 * npe;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const auto* __restrict__ A = gp(sg.binvT);
+    // A operands of column steps [ks0, ks0 + PC_KCB) below ke, double
+    // buffered: the next chunk's loads are in flight while one multiplies
+    auto load_chunk = [&](int ks0, int ke, double (&a)[PC_KCB][PC_TW]) {
+#pragma unroll
+        for (int c = 0; c < PC_KCB; ++c)
+#pragma unroll
+            for (int q = 0; q < PC_TW; ++q) {
+                const int ks = ks0 + c, rt = g0 + wave + 4 * q;
+                a[c][q] = (rt < T && ks < ke) ? A[((int64_t)rt * KS + ks) * 64 + lane] : 0.0;
+            }
+    };
+    v4d acc[PC_TW];
+    auto mul_chunk = [&](int ks0, int kb, int ke, const double (&a)[PC_KCB][PC_TW]) {
+#pragma unroll
+        for (int c = 0; c < PC_KCB; ++c) {
+            const int ks = ks0 + c;
+            if (ks >= ke) break;
+            const double b = sm[(ks - kb) * 64 + lane];
+#pragma unroll
+            for (int q = 0; q < PC_TW; ++q)
+                if (g0 + wave + 4 * q < T) acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[c][q], b, acc[q], 0, 0, 0);
+        }
+    };
+    double a0[PC_KCB][PC_TW], a1[PC_KCB][PC_TW];
+#pragma unroll
+    for (int q = 0; q < PC_TW; ++q) acc[q] = v4d{0.0, 0.0, 0.0, 0.0};
+    for (int kb = 0; kb < KS; kb += KP) {
+        const int ke = min(KS, kb + KP);
+        load_chunk(kb, ke, a0);               // in flight while the part is staged
+        __syncthreads();                      // the previous part's operands are consumed
+        // column steps [kb, ke) of the block's elements in B-operand order:
+        // element-fastest thread order, so thread t writes LDS word t; zeros
+        // past npe and past the last element
+        constexpr int SQ = 8;
+        const int cnt = PC_EB * 4 * (ke - kb);
+        for (int t0 = threadIdx.x; t0 < cnt; t0 += SQ * PC_BLOCK) {
+            double v[SQ];
+#pragma unroll
+            for (int q = 0; q < SQ; ++q) {
+                const int t = t0 + q * PC_BLOCK;
+                const int j = t & (PC_EB - 1), c = 4 * kb + (t >> 4);
+                v[q] = (t < cnt && j < ne && c < npe) ? in[(int64_t)j * npe + c] : 0.0;
+            }
+#pragma unroll
+            for (int q = 0; q < SQ; ++q) {
+                const int t = t0 + q * PC_BLOCK;
+                if (t < cnt) sm[t] = v[q];
+            }
+        }
+        __syncthreads();
+        for (int ks0 = kb; ks0 < ke; ks0 += 2 * PC_KCB) {
+            load_chunk(ks0 + PC_KCB, ke, a1);
+            mul_chunk(ks0, kb, ke, a0);
+            if (ks0 + PC_KCB >= ke) break;
+            load_chunk(ks0 + 2 * PC_KCB, ke, a0);
+            mul_chunk(ks0 + PC_KCB, kb, ke, a1);
+        }
+    }
+    // the group's tiles: element j = lane & 15, rows 16 rt + (lane >> 4) + 4 r
+    const int j = lane & 15;
+#pragma unroll
+    for (int q = 0; q < PC_TW; ++q) {
+        const int rt = g0 + wave + 4 * q;
+        if (rt < T && j < ne) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int row = rt * 16 + (lane >> 4) + 4 * r;
+                if (row < npe) {
+                    double z = acc[q][r];
+                    if (sg.accumulate) z += out[(int64_t)j * npe + row];
+                    store_nt(&out[(int64_t)j * npe + row], z);
+                }
+            }
+        }
     }
 }
 
@@ -362,7 +442,7 @@ __global__ void k_put_pcseg(PcSeg* dst, PcSeg v) { if (threadIdx.x == 0 && block
 // dynamic LDS of k_bjacobi for element blocks of npe unknowns
 static size_t bjacobi_lds(int npe) {
     const int KS = (npe + 3) / 4, T = (npe + 15) / 16;
-    if (T > 4 * PC_TW) return sizeof(double) * 64 * (size_t)KS;    // grouped rows: inputs only
+    if (T > 4 * PC_TW) return sizeof(double) * 64 * (size_t)((KS + PC_PARTS - 1) / PC_PARTS);   // one part
     return sizeof(double) * std::max<size_t>(64 * (size_t)KS, 16 * (size_t)(npe | 1));
 }
 
@@ -370,7 +450,7 @@ hipError_t pc_prepare(int npe) {
     if (npe < 1 || npe > PC_NPE_MAX) return hipErrorInvalidValue;
     const size_t shm = bjacobi_lds(npe);
     if (shm <= 64 * 1024) return hipSuccess;
-    return hipFuncSetAttribute((const void*)k_bjacobi<true>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+    return hipFuncSetAttribute((const void*)k_bjacobi, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
 }
 
 void pc_apply(const PcSeg* s, int nseg, int G, int npe, hipStream_t st) {
@@ -380,9 +460,9 @@ void pc_apply(const PcSeg* s, int nseg, int G, int npe, hipStream_t st) {
         launch_ks(k_bjacobi_ks, dim3(G), dim3(PC_BLOCK), shm, st, s, nseg);
     } else {
         if (T > 4 * PC_TW)
-            launch_ks(k_bjacobi<true>, dim3(G), dim3(PC_BLOCK), bjacobi_lds(npe), st, s, nseg);
+            launch_ks(k_bjacobi_big, dim3(G), dim3(PC_BLOCK), bjacobi_lds(npe), st, s, nseg);
         else
-            launch_ks(k_bjacobi<false>, dim3(G), dim3(PC_BLOCK), bjacobi_lds(npe), st, s, nseg);
+            launch_ks(k_bjacobi, dim3(G), dim3(PC_BLOCK), bjacobi_lds(npe), st, s, nseg);
     }
 }
 // C in LDS up to this many bytes (several blocks per CU still fit)
