@@ -40,6 +40,13 @@ constexpr int PC_BLOCK = 256;               // 4 wavefronts
 constexpr int PC_EB = 16;                   // elements per block (the MFMA column count)
 constexpr int PC_TW = 8;                    // row tiles per wavefront and row group
 constexpr int PC_KC = 4;                    // column steps per operand chunk
+// k_bjacobi_big (blocks above 512 rows)
+constexpr int PB_EB = 32;                   // elements per block: two MFMA column sets
+constexpr int PB_TW = 4;                    // row tiles per wavefront
+constexpr int PB_GT = 4 * PB_TW;            // row tiles per block (row group)
+constexpr int PB_KCB = 4;                   // column steps per A-operand chunk
+constexpr int PB_KP = 6 * PB_KCB;           // column steps per staged part (three chunk pairs)
+constexpr int PB_SQ = PB_EB * 4 * PB_KP / PC_BLOCK;   // staged words per thread and part
 typedef double v4d __attribute__((ext_vector_type(4)));
 // a flag or index in device memory, zero for a null pointer (branch free: the
 // pointer is selected, then always loaded); every lane reads the same word
@@ -57,7 +64,7 @@ static bool pc_small(int npe) {
 int pc_blocks(int E, int npe) {
     const int groups = (E + PC_EB - 1) / PC_EB, T = (npe + 15) / 16;
     if (pc_small(npe)) return groups * T;                      // one block per (elements, row tile)
-    if (T > 4 * PC_TW) return groups * ((T + 4 * PC_TW - 1) / (4 * PC_TW));   // per (elements, row group)
+    if (T > 4 * PC_TW) return (E + PB_EB - 1) / PB_EB * ((T + PB_GT - 1) / PB_GT);   // per (elements, row group)
     return groups;
 }
 
@@ -166,108 +173,138 @@ __global__ __launch_bounds__(PC_BLOCK) void k_bjacobi(const PcSeg* __restrict__ 
     }
 }
 
-// Large blocks (more than 512 rows, at most 1024): one GPU block per (16
-// elements, group of 4 PC_TW row tiles), with the elements' inputs staged in
-// PC_PARTS parts of the column steps, so that they take half the LDS and two
-// blocks share a CU (two waves per SIMD hide the latency of the streamed A
-// operands, which come from L2 and the Infinity Cache; the row groups in
-// separate blocks give a 4096-element slab 512 of them).  The group
-// accumulates over the parts in registers and stores its tiles directly.
-constexpr int PC_PARTS = 2;
-constexpr int PC_KCB = 4;                   // column steps per A-operand chunk (registers of two waves per SIMD)
+// Large blocks (more than 512 rows, at most 1024): one GPU block per (32
+// elements, group of PB_GT row tiles).  Every A operand (16 rows x 4 columns
+// of B^-1, streamed from the caches) feeds two products, one per half of the
+// 32 elements, and every B operand from LDS feeds the PB_TW row tiles of its
+// wavefront.  The elements' inputs are staged in parts of PB_KP column steps,
+// double buffered (48 KB of LDS, two blocks per CU): the next part's loads
+// are in flight while the current part is multiplied, and the A operands run
+// one chunk ahead across the parts.  A part is straight-line code: loads take
+// clamped indices rather than branches, the column steps run on to a whole
+// number of parts (zero inputs there), the last part loads a next part it
+// never stores, and row tiles past the last one multiply and are not stored.
+// Consecutive blocks take consecutive row groups of the same elements;
+// workgroups go round-robin over the 8 XCDs, so where the number of row
+// groups divides 8 (4 for npe from 769 to 1024) each XCD streams the same
+// rows of B^-1 (a quarter of it, 1.8 MB at npe = 960), which then stay in its
+// L2.  The group accumulates in registers (the column steps in order, as the
+// other kernels) and stores its tiles directly.
 __global__ __launch_bounds__(PC_BLOCK, 2) void k_bjacobi_big(const PcSeg* __restrict__ segs, int nseg) {
-    extern __shared__ double sm[];           // [KP * 64] B operands of one part
+    extern __shared__ double sm[];           // two buffers of [PB_KP][2][64] B operands
+    constexpr int BW = PB_EB * 4 * PB_KP;    // words of one buffer
     const PcSeg& sg = segs[find_pseg(segs, nseg, blockIdx.x)];
     const int skip = pc_index(sg.skip);
     const int kin = pc_index(sg.in.kp);
     if (skip) return;
     const int npe = sg.npe;
     const int KS = (npe + 3) >> 2, T = (npe + 15) >> 4;
-    const int KP = (KS + PC_PARTS - 1) / PC_PARTS;
-    constexpr int GT = 4 * PC_TW;            // row tiles per group
-    const int NG = (T + GT - 1) / GT;        // row groups
+    const int NG = (T + PB_GT - 1) / PB_GT;  // row groups
     const int b = blockIdx.x - sg.blk0;
     const int eg = b / NG;
-    const int g0 = (b - eg * NG) * GT;       // first row tile of this block's group
-    const int e0 = eg * PC_EB;
-    const int ne = min(PC_EB, sg.E - e0);
+    const int g0 = (b - eg * NG) * PB_GT;    // first row tile of this block's group
+    const int e0 = eg * PB_EB;
+    const int ne = min(PB_EB, sg.E - e0);
     const double* inb = static_cast<const double*>(sg.in.base);
     if (sg.in.kp) inb += (int64_t)(kin + sg.in.koff) * sg.in.ld;
     const auto* __restrict__ in = gp(inb) + (int64_t)e0 * npe;
     auto* __restrict__ out = gp(sg.out) + (int64_t)e0 * npe;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const auto* __restrict__ A = gp(sg.binvT);
-    // A operands of column steps [ks0, ks0 + PC_KCB) below ke, double
-    // buffered: the next chunk's loads are in flight while one multiplies
-    auto load_chunk = [&](int ks0, int ke, double (&a)[PC_KCB][PC_TW]) {
+    // A operands of column steps [ks0, ks0 + PB_KCB) (clamped: past KS they
+    // are loaded and meet zero inputs or are never used)
+    auto load_chunk = [&](int ks0, double (&a)[PB_KCB][PB_TW]) {
 #pragma unroll
-        for (int c = 0; c < PC_KCB; ++c)
+        for (int c = 0; c < PB_KCB; ++c)
 #pragma unroll
-            for (int q = 0; q < PC_TW; ++q) {
-                const int ks = ks0 + c, rt = g0 + wave + 4 * q;
-                a[c][q] = (rt < T && ks < ke) ? A[((int64_t)rt * KS + ks) * 64 + lane] : 0.0;
+            for (int q = 0; q < PB_TW; ++q) {
+                const int ks = min(ks0 + c, KS - 1), rt = min(g0 + wave + 4 * q, T - 1);
+                a[c][q] = A[((int64_t)rt * KS + ks) * 64 + lane];
             }
     };
-    v4d acc[PC_TW];
-    auto mul_chunk = [&](int ks0, int kb, int ke, const double (&a)[PC_KCB][PC_TW]) {
+    v4d acc[PB_TW][2];
+    // the products of column steps [ks0, ks0 + PB_KCB), kr steps into the part
+    auto mul_chunk = [&](const double* buf, int kr, const double (&a)[PB_KCB][PB_TW]) {
 #pragma unroll
-        for (int c = 0; c < PC_KCB; ++c) {
-            const int ks = ks0 + c;
-            if (ks >= ke) break;
-            const double b = sm[(ks - kb) * 64 + lane];
+        for (int c = 0; c < PB_KCB; ++c) {
+            const double b0 = buf[((kr + c) * 2 + 0) * 64 + lane];
+            const double b1 = buf[((kr + c) * 2 + 1) * 64 + lane];
 #pragma unroll
-            for (int q = 0; q < PC_TW; ++q)
-                if (g0 + wave + 4 * q < T) acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[c][q], b, acc[q], 0, 0, 0);
+            for (int q = 0; q < PB_TW; ++q) {
+                acc[q][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[c][q], b0, acc[q][0], 0, 0, 0);
+                acc[q][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[c][q], b1, acc[q][1], 0, 0, 0);
+            }
         }
     };
-    double a0[PC_KCB][PC_TW], a1[PC_KCB][PC_TW];
+    // column steps [kb, kb + PB_KP) of the block's elements in B-operand
+    // order, buffer word w = ((ks - kb) 2 + half) 64 + lane, lane = j + 16
+    // (col mod 4): thread t + q PC_BLOCK holds word t + q PC_BLOCK; zeros past
+    // npe and past the last element (selected when the words are stored, so
+    // that nothing waits for the loads before then)
+    double st[PB_SQ];
+    unsigned okm = 0;
+    auto stage_load = [&](int kb) {
+        okm = 0;
 #pragma unroll
-    for (int q = 0; q < PC_TW; ++q) acc[q] = v4d{0.0, 0.0, 0.0, 0.0};
-    for (int kb = 0; kb < KS; kb += KP) {
-        const int ke = min(KS, kb + KP);
-        load_chunk(kb, ke, a0);               // in flight while the part is staged
-        __syncthreads();                      // the previous part's operands are consumed
-        // column steps [kb, ke) of the block's elements in B-operand order:
-        // element-fastest thread order, so thread t writes LDS word t; zeros
-        // past npe and past the last element
-        constexpr int SQ = 8;
-        const int cnt = PC_EB * 4 * (ke - kb);
-        for (int t0 = threadIdx.x; t0 < cnt; t0 += SQ * PC_BLOCK) {
-            double v[SQ];
-#pragma unroll
-            for (int q = 0; q < SQ; ++q) {
-                const int t = t0 + q * PC_BLOCK;
-                const int j = t & (PC_EB - 1), c = 4 * kb + (t >> 4);
-                v[q] = (t < cnt && j < ne && c < npe) ? in[(int64_t)j * npe + c] : 0.0;
-            }
-#pragma unroll
-            for (int q = 0; q < SQ; ++q) {
-                const int t = t0 + q * PC_BLOCK;
-                if (t < cnt) sm[t] = v[q];
-            }
+        for (int q = 0; q < PB_SQ; ++q) {
+            const int t = threadIdx.x + q * PC_BLOCK;
+            const int l = t & 63, j = ((t >> 6) & 1) * 16 + (l & 15);
+            const int c = 4 * (kb + (t >> 7)) + (l >> 4);
+            const bool ok = j < ne && c < npe;
+            st[q] = in[ok ? (int64_t)j * npe + c : 0];
+            okm |= (ok ? 1u : 0u) << q;
         }
-        __syncthreads();
-        for (int ks0 = kb; ks0 < ke; ks0 += 2 * PC_KCB) {
-            load_chunk(ks0 + PC_KCB, ke, a1);
-            mul_chunk(ks0, kb, ke, a0);
-            if (ks0 + PC_KCB >= ke) break;
-            load_chunk(ks0 + 2 * PC_KCB, ke, a0);
-            mul_chunk(ks0 + PC_KCB, kb, ke, a1);
+    };
+    auto stage_store = [&](double* buf) {
+#pragma unroll
+        for (int q = 0; q < PB_SQ; ++q) buf[threadIdx.x + q * PC_BLOCK] = (okm >> q) & 1u ? st[q] : 0.0;
+    };
+    double a0[PB_KCB][PB_TW], a1[PB_KCB][PB_TW];
+#pragma unroll
+    for (int q = 0; q < PB_TW; ++q) acc[q][0] = acc[q][1] = v4d{0.0, 0.0, 0.0, 0.0};
+    load_chunk(0, a0);
+    stage_load(0);
+    stage_store(sm);
+    __syncthreads();
+    for (int kb = 0, p = 0; kb < KS; kb += PB_KP, ++p) {
+        const double* buf = sm + (p & 1) * BW;
+        // three chunk pairs; the next part's inputs are requested after the
+        // first A chunk, so that the products wait for them only from the
+        // second pair on
+#pragma unroll
+        for (int pr = 0; pr < PB_KP / (2 * PB_KCB); ++pr) {
+            const int ks0 = kb + 2 * PB_KCB * pr;
+            load_chunk(ks0 + PB_KCB, a1);
+            if (pr == 0) stage_load(kb + PB_KP);
+            __builtin_amdgcn_sched_barrier(0);
+            mul_chunk(buf, 2 * PB_KCB * pr, a0);
+            load_chunk(ks0 + 2 * PB_KCB, a0);  // after the last pair: the next part's first chunk
+            __builtin_amdgcn_sched_barrier(0);
+            mul_chunk(buf, 2 * PB_KCB * pr + PB_KCB, a1);
+        }
+        if (kb + PB_KP < KS) {
+            // the other buffer was last read in the previous part, before
+            // the barrier that ended it
+            stage_store(sm + ((p + 1) & 1) * BW);
+            __syncthreads();
         }
     }
-    // the group's tiles: element j = lane & 15, rows 16 rt + (lane >> 4) + 4 r
-    const int j = lane & 15;
+    // the group's tiles: element 16 h + (lane & 15), rows 16 rt + (lane >> 4) + 4 r
 #pragma unroll
-    for (int q = 0; q < PC_TW; ++q) {
-        const int rt = g0 + wave + 4 * q;
-        if (rt < T && j < ne) {
+    for (int h = 0; h < 2; ++h) {
+        const int j = 16 * h + (lane & 15);
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int row = rt * 16 + (lane >> 4) + 4 * r;
-                if (row < npe) {
-                    double z = acc[q][r];
-                    if (sg.accumulate) z += out[(int64_t)j * npe + row];
-                    store_nt(&out[(int64_t)j * npe + row], z);
+        for (int q = 0; q < PB_TW; ++q) {
+            const int rt = g0 + wave + 4 * q;
+            if (rt < T && j < ne) {
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int row = rt * 16 + (lane >> 4) + 4 * r;
+                    if (row < npe) {
+                        double z = acc[q][h][r];
+                        if (sg.accumulate) z += out[(int64_t)j * npe + row];
+                        store_nt(&out[(int64_t)j * npe + row], z);
+                    }
                 }
             }
         }
@@ -442,7 +479,7 @@ __global__ void k_put_pcseg(PcSeg* dst, PcSeg v) { if (threadIdx.x == 0 && block
 // dynamic LDS of k_bjacobi for element blocks of npe unknowns
 static size_t bjacobi_lds(int npe) {
     const int KS = (npe + 3) / 4, T = (npe + 15) / 16;
-    if (T > 4 * PC_TW) return sizeof(double) * 64 * (size_t)((KS + PC_PARTS - 1) / PC_PARTS);   // one part
+    if (T > 4 * PC_TW) return sizeof(double) * 2 * PB_EB * 4 * PB_KP;   // two part buffers
     return sizeof(double) * std::max<size_t>(64 * (size_t)KS, 16 * (size_t)(npe | 1));
 }
 
