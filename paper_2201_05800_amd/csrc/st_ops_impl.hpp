@@ -1140,7 +1140,7 @@ __global__ __attribute__((amdgpu_waves_per_eu(2))) __launch_bounds__((Shape<D, N
                 const CT wl = ia == N1 - 1 ? CT(sg.rh[a]) * iw0 : -(CT(sg.rh[a]) * iw0);
 #pragma unroll
                 for (int v = 1; v < R; ++v) {
-                    Qe[o + (v - 1) * (NT * ipow(N1, D - 1))] = part(f[v]);
+                    store_nt(&Qe[o + (v - 1) * (NT * ipow(N1, D - 1))], part(f[v]));
                     vr[v] += CT(0.5) * wl * part(f[v]);
                 }
             }
@@ -1167,8 +1167,7 @@ __global__ __attribute__((amdgpu_waves_per_eu(2))) __launch_bounds__((Shape<D, N
         }
     });
 #pragma unroll
-    // plain stores: k_op reads this output next, partly from the caches
-    for (int v = 1; v < R; ++v) Qe[(v - 1) * NPE + r] = vr[v];
+    for (int v = 1; v < R; ++v) store_nt(&Qe[(v - 1) * NPE + r], vr[v]);
 }
 
 // ---------------------------------------------------------------------------
