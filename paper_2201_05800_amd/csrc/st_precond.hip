@@ -289,25 +289,35 @@ __global__ __launch_bounds__(PC_BLOCK, 2) void k_bjacobi_big(const PcSeg* __rest
             __syncthreads();
         }
     }
-    // the group's tiles: element 16 h + (lane & 15), rows 16 rt + (lane >> 4) + 4 r
+    // The group's tiles go back through LDS, one half of the elements at a
+    // time, so that consecutive threads store consecutive rows of an element
+    // (whole cache lines; stored from the MFMA layout directly, each
+    // instruction would write 32-byte pieces of 16 elements).  Tile rt holds
+    // element 16 h + (lane & 15) at rows 16 rt + (lane >> 4) + 4 r; LDS word
+    // (j, local row) at j SR + row - 16 g0 with an odd stride SR.
+    constexpr int SR = 16 * PB_GT + 1;
+    static_assert(16 * SR <= 2 * PB_EB * 4 * PB_KP, "the result tile fits the part buffers");
+    __syncthreads();                          // every wave is done with the part buffers
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
-        const int j = 16 * h + (lane & 15);
 #pragma unroll
         for (int q = 0; q < PB_TW; ++q) {
-            const int rt = g0 + wave + 4 * q;
-            if (rt < T && j < ne) {
+            const int rl = (wave + 4 * q) * 16 + (lane >> 4);
 #pragma unroll
-                for (int r = 0; r < 4; ++r) {
-                    const int row = rt * 16 + (lane >> 4) + 4 * r;
-                    if (row < npe) {
-                        double z = acc[q][h][r];
-                        if (sg.accumulate) z += out[(int64_t)j * npe + row];
-                        store_nt(&out[(int64_t)j * npe + row], z);
-                    }
-                }
+            for (int r = 0; r < 4; ++r) sm[(lane & 15) * SR + rl + 4 * r] = acc[q][h][r];
+        }
+        __syncthreads();
+        const int row0 = g0 * 16;
+        for (int t = threadIdx.x; t < 16 * 16 * PB_GT; t += PC_BLOCK) {
+            const int jj = t / (16 * PB_GT), rl = t - jj * (16 * PB_GT);
+            const int j = 16 * h + jj, row = row0 + rl;
+            if (j < ne && row < npe) {
+                double z = sm[jj * SR + rl];
+                if (sg.accumulate) z += out[(int64_t)j * npe + row];
+                store_nt(&out[(int64_t)j * npe + row], z);
             }
         }
+        __syncthreads();                      // the LDS tile is read before the next half overwrites it
     }
 }
 
