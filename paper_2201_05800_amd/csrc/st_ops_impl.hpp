@@ -330,15 +330,17 @@ DI int vtrace_at(int a, int side, int v, int j, int f) {
 //   u, w: the node's state and its primitives;
 //   nb(b, right, un): the neighbour's state across the face of axis b at the
 //         matching node (called on face nodes only; interior lifts vanish);
-//   zs:   PARK only: [row][node] with pitch NL, D D + D rows (twice as many
-//         for a JVP: values, then tangents), where the gradients are parked
-//         axis by axis and reloaded, so that fewer registers are live while
-//         the next axes are differentiated.
+//   zs:   PARK only: [row][node] with pitch NL, D D + D rows, where the
+//         gradients are parked axis by axis and reloaded, so that fewer
+//         registers are live while the next axes are differentiated: the
+//         values (residual), the tangents (JVP; their values stay in
+//         registers, which keeps the JVP pass's LDS at the residual's).
 template <int D, int N1, class CT, class T, class F, bool JVP, bool PARK, class NB>
 DI void br1_visc(const CT* tile, const CT* sD, CT* zs, int NL, int nd, int s, const T* u,
                  const typename F::Prim& w, const OpSeg& sg, NB&& nb, typename F::Visc& z) {
     constexpr int R = D + 2;
     constexpr int NZ = D * D + D;
+    CT keep[JVP ? NZ : 1];                      // JVP: the parked rows' values
     const CT iw0 = CT(sg.iw0);
     F::visc_pre(w, z);
     static_for<0, D>([&](auto B_) {
@@ -379,20 +381,27 @@ DI void br1_visc(const CT* tile, const CT* sD, CT* zs, int NL, int nd, int s, co
         }
         F::visc_axis(b, w, qb, z, sg.P);
         if constexpr (PARK) {
+            auto park = [&](int row, const T& x) {
+                if constexpr (JVP) {
+                    keep[row] = value(x);
+                    zs[row * NL + nd] = part(x);
+                } else {
+                    zs[row * NL + nd] = value(x);
+                }
+            };
 #pragma unroll
-            for (int c = 0; c < D; ++c) {
-                zs[(b * D + c) * NL + nd] = value(z.gv[b][c]);
-                if constexpr (JVP) zs[(NZ + b * D + c) * NL + nd] = part(z.gv[b][c]);
-            }
-            zs[(D * D + b) * NL + nd] = value(z.gT[b]);
-            if constexpr (JVP) zs[(NZ + D * D + b) * NL + nd] = part(z.gT[b]);
+            for (int c = 0; c < D; ++c) park(b * D + c, z.gv[b][c]);
+            park(D * D + b, z.gT[b]);
         }
     });
     if constexpr (PARK) {
-        // reload (the asm keeps the compiler from carrying the values in
-        // registers across the axes instead)
+        // reload (the asm keeps the compiler from carrying the parked parts
+        // in registers across the axes instead)
         __asm__ volatile("" ::: "memory");
-        auto ld = [&](int row) { return make_state<T>(zs[row * NL + nd], JVP ? zs[(NZ + row) * NL + nd] : CT(0)); };
+        auto ld = [&](int row) {
+            if constexpr (JVP) return make_state<T>(keep[row], zs[row * NL + nd]);
+            else return make_state<T>(zs[row * NL + nd], CT(0));
+        };
 #pragma unroll
         for (int b = 0; b < D; ++b) {
 #pragma unroll
@@ -1066,7 +1075,7 @@ __global__ __attribute__((amdgpu_waves_per_eu(2))) __launch_bounds__((Shape<D, N
     constexpr int TS = JVP ? 2 : 1;
     __shared__ CT tile[TS * R * B];             // [plane][v][node]
     constexpr int NZ = D * D + D;               // = D (R - 1): also the rows of g staged below
-    __shared__ CT zs[(JVP ? 2 : 1) * NZ * B];   // parked viscous state, then g [a][v - 1][node]
+    __shared__ CT zs[NZ * B];                   // parked viscous state, then g [a][v - 1][node]
     __shared__ CT sD[N1 * N1];
     const int L = xcd_remap(blockIdx.x, G);
     const OpSeg& sg = segs[find_seg(segs, nseg, L)];
