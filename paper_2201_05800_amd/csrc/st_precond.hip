@@ -189,7 +189,7 @@ __global__ __launch_bounds__(PC_BLOCK) void k_bjacobi(const PcSeg* __restrict__ 
 // groups divides 8 (4 for npe from 769 to 1024) each XCD streams the same
 // rows of B^-1 (a quarter of it, 1.8 MB at npe = 960), which then stay in its
 // L2.  The group accumulates in registers (the column steps in order, as the
-// other kernels) and stores its tiles directly.
+// other kernels) and writes its rows back through LDS.
 __global__ __launch_bounds__(PC_BLOCK, 2) void k_bjacobi_big(const PcSeg* __restrict__ segs, int nseg) {
     extern __shared__ double sm[];           // two buffers of [PB_KP][2][64] B operands
     constexpr int BW = PB_EB * 4 * PB_KP;    // words of one buffer
