@@ -71,6 +71,11 @@ NONLIN = [
     # (row groups of the matrix-core kernel, LDS above 64 KB)
     ("ns3d-tgv-3-N3Nt3", cfg("ns", 3, [3, 3, 3], 3, 3, lo=[0, 0, 0], hi=[6.283185307179586] * 3, mu=1.0 / 1600),
      "tgv"),
+    # 5 * 2 * 4^3 = 640 unknowns: three row groups of the large-block kernel
+    ("ns3d-tgv-3-N3Nt2", cfg("ns", 3, [3, 3, 3], 3, 2, lo=[0, 0, 0], hi=[6.283185307179586] * 3, mu=1.0 / 1600),
+     "tgv"),
+    # 960 unknowns, 48 elements: a full group of 32 elements and a ragged one
+    ("euler3d-tgv-4x4x3-N3Nt3", cfg("euler", 3, [4, 4, 3], 3, 3, lo=[0, 0, 0], hi=[6.283185307179586] * 3), "tgv"),
 ]
 
 
