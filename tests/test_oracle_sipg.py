@@ -109,6 +109,41 @@ def test_br1_and_advection_dirichlet_boundaries(orc):
     assert np.abs(F - want).max() <= 1e-12
 
 
+@pytest.mark.parametrize("g,c", [(0.7, 0.2), (-0.4, 0.3), (0.5, -0.9)])
+def test_burgers_dirichlet_boundary_flux(orc, g, c):
+    """Burgers with the exterior state g at both ends of [0, 1] (the Rusanov
+    flux of eq. flux:llf with g in place of the missing neighbour): a
+    constant state c feels only the two boundary faces, whose lifted terms
+    are (2/h) (H_L - c^2/2) / w_0 at the left end node and
+    -(2/h) (H_R - c^2/2) / w_N at the right one, with
+    H = (f(u_L) + f(u_R))/2 + max(|u_L|, |u_R|) (u_L - u_R)/2; the state g
+    itself is steady; the JVP matches central differences."""
+    K, N = 4, 3
+    n1, h = N + 1, 1.0 / K
+    p = orc.problem(1, [K], [0], [1], N, 2, orc.BURGERS, bc=(1,), bc_value=g)
+    F = orc.spatial_op(p, np.full(K * n1, c))
+    _, w, _ = orc.lgl(n1)
+    lam = max(abs(g), abs(c))
+    f = lambda u: 0.5 * u * u
+    HL = 0.5 * (f(g) + f(c)) + 0.5 * lam * (g - c)
+    HR = 0.5 * (f(c) + f(g)) + 0.5 * lam * (c - g)
+    want = np.zeros(K * n1)
+    want[0] = (2.0 / h) * (HL - f(c)) / w[0]
+    want[-1] = -(2.0 / h) * (HR - f(c)) / w[-1]
+    assert np.abs(F - want).max() <= 1e-13 * max(1.0, np.abs(want).max())
+    assert np.abs(orc.spatial_op(p, np.full(K * n1, g))).max() <= 1e-13
+    q = orc.problem(1, [K], [0], [1], N, 3, orc.BURGERS, bc=(1,), bc_value=g)
+    rng = np.random.default_rng(7)
+    n, m = orc.slab_size(q), orc.space_size(q)
+    U = c + 0.2 * rng.standard_normal(n)
+    up = c + 0.2 * rng.standard_normal(m)
+    V = rng.standard_normal(n)
+    dt, eps = 0.05, 1e-6
+    J = orc.jvp(q, U, dt, V)
+    fd = (orc.residual(q, U + eps * V, up, dt) - orc.residual(q, U - eps * V, up, dt)) / (2 * eps)
+    assert np.abs(J - fd).max() <= 1e-7 * np.abs(J).max()
+
+
 @pytest.mark.parametrize("case", ["periodic-rot", "dirichlet-rot", "mixed-const"])
 def test_sipg_galerkin_form_and_stdg_lodg(orc, case):
     """The literal space-time Galerkin weak form (the penalty terms written as
