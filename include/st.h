@@ -58,8 +58,9 @@ extern "C" {
 /* Cartesian mesh, cf. cartesianDomain(lower, upper, counts) in Sec.
  * "DG-SEM in Space".  Axes are periodic unless bc[a] = 1: then both ends of
  * axis a are Dirichlet boundaries with the exterior state bc_value of the
- * equation (the boundary convective flux of the surface integral; the
- * scalar linear equations only, constant velocity). */
+ * equation (the boundary convective flux of the surface integral): the
+ * scalar linear equations with a constant velocity, and Burgers; the other
+ * equations return ST_ERR_UNSUPPORTED from st_create. */
 typedef struct {
     int dim;          /* 1, 2 or 3 */
     int K[3];         /* elements per axis (unused axes: 1) */

@@ -98,6 +98,8 @@ const OpTable* find_table(int eq, int dim, int n1, int nt, bool rot, bool bnd) {
                 OpTable t = tables[i];
                 t.res64 = t.res64_bnd;
                 t.lin32 = t.lin32_bnd;
+                t.jvp64 = t.jvp64_bnd;
+                t.jvp32 = t.jvp32_bnd;
                 t.bnd = 1;
                 tables.push_back(t);
             }
@@ -152,8 +154,9 @@ int make_problem(const st_mesh_t* mesh, int N, int Nt, const st_equation_t* eq, 
         pb.mesh.bc[a] = b;
         bnd = bnd || b == 1;
     }
-    if (bnd && (!linear_eq(eq->kind) || rot))
-        return set_error(ST_ERR_UNSUPPORTED, "Dirichlet boundaries: the linear equations with a constant velocity");
+    if (bnd && (!(linear_eq(eq->kind) || eq->kind == ST_BURGERS) || rot))
+        return set_error(ST_ERR_UNSUPPORTED,
+                         "Dirichlet boundaries: the linear equations with a constant velocity, and Burgers");
     if (bnd && !std::isfinite(eq->bc_value)) return set_error(ST_ERR_BAD_ARG, "bc_value must be finite");
     pb.ops = find_table(eq->kind, d, pb.n1, Nt, rot, bnd);
     if (!pb.ops)

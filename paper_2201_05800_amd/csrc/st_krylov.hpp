@@ -102,9 +102,12 @@ struct OpTable {
     // res64 / lin32 (line operator in three parts, b_a per line)
     OpLaunch res64_rot;
     OpLaunch lin32_rot;
-    // linear equations: the Dirichlet-boundary variants of res64 / lin32
+    // the Dirichlet-boundary variants of res64 / lin32 (linear equations) and
+    // of res64 / jvp64 / jvp32 (Burgers)
     OpLaunch res64_bnd;
     OpLaunch lin32_bnd;
+    OpLaunch jvp64_bnd;
+    OpLaunch jvp32_bnd;
 };
 
 void register_ops_adv(std::vector<OpTable>& t);

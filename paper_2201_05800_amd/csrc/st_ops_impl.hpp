@@ -422,8 +422,11 @@ DI void br1_visc(const CT* tile, const CT* sD, CT* zs, int NL, int nd, int s, co
 // has left the viscous terms of the element's own residual (added at the
 // end) and its face traces of -Fv, from which the face points add the
 // neighbour's half of the BR1 flux.
+// BND (Burgers): Dirichlet boundaries on the axes with bc[a] = 1; a face on
+// the domain boundary takes the exterior state g (constant: no tangent) in
+// place of the neighbour's state in its Rusanov flux.
 // ---------------------------------------------------------------------------
-template <int EQ, int D, int N1, int NT, class CT, class UT, bool JVP>
+template <int EQ, int D, int N1, int NT, class CT, class UT, bool JVP, bool BND = false>
 __global__ __launch_bounds__((Shape<D, N1, NT, tpt_of(EQ, NT)>::BS)) void k_op(const OpSeg* __restrict__ segs,
                                                                                int nseg, int G) {
     constexpr int TPT = tpt_of(EQ, NT);
@@ -434,6 +437,7 @@ __global__ __launch_bounds__((Shape<D, N1, NT, tpt_of(EQ, NT)>::BS)) void k_op(c
     constexpr int NS = SH::NS, NPE = SH::NPE, NF = SH::NF, NJ = SH::NJ, NTH = SH::NTH;
     constexpr int EPB = SH::EPB, B = SH::B, BS = SH::BS, NFP = SH::NFP;
     static_assert(!linear_eq(EQ), "the linear equations use k_lin");
+    static_assert(!BND || EQ == EQ_BURGERS, "Dirichlet boundaries of the nonlinear equations: Burgers");
     constexpr bool NSV = EQ == EQ_NS;
     constexpr int TS = JVP ? 2 : 1;
     constexpr int PL = JVP ? R : 0;             // tile plane of the stored part
@@ -501,6 +505,7 @@ __global__ __launch_bounds__((Shape<D, N1, NT, tpt_of(EQ, NT)>::BS)) void k_op(c
         int a, pel, to0, rn0, en, stride;
         int tq;                  // NS: the neighbour's face-trace offset (its face on the other side)
         bool right, ok, local;   // local: the neighbour is one of the block's elements (state from the tile)
+        bool bnd;                // BND: the face is on a Dirichlet boundary (exterior state)
     };
     auto fp_info = [&](int p) {
         FPI fi;
@@ -519,8 +524,14 @@ __global__ __launch_bounds__((Shape<D, N1, NT, tpt_of(EQ, NT)>::BS)) void k_op(c
         const int so = face_node_rt<D, N1>(fi.a, f, fi.right);
         fi.rn0 = jg * TPT * NS + so + (fi.right ? -(N1 - 1) : (N1 - 1)) * fi.stride;   // neighbour's node
         fi.to0 = fi.pel * LP + jg * TPT * NS + so;                                     // own block node
-        fi.en = fi.ok ? neighbour(sg, ep, ecoord(sg, ep), fi.a, fi.right) : 0;
-        fi.local = fi.ok && fi.en >= e0 && fi.en < e0 + EPB;
+        const ECoord xe = ecoord(sg, fi.ok ? ep : 0);
+        fi.en = fi.ok ? neighbour(sg, ep, xe, fi.a, fi.right) : 0;
+        fi.bnd = false;
+        if constexpr (BND) {
+            const int ca = fi.a == 0 ? xe.c[0] : (fi.a == 1 ? xe.c[1] : xe.c[2]);
+            fi.bnd = fi.ok && sg.bc[fi.a] && (fi.right ? ca == sg.K[fi.a] - 1 : ca == 0);
+        }
+        fi.local = fi.ok && !fi.bnd && fi.en >= e0 && fi.en < e0 + EPB;
         fi.tq = NSV ? vtrace_at<D, N1, NT>(fi.a, fi.right ? 0 : 1, 1, jg * TPT, f) : 0;
         return fi;
     };
@@ -531,7 +542,7 @@ __global__ __launch_bounds__((Shape<D, N1, NT, tpt_of(EQ, NT)>::BS)) void k_op(c
         CT gn[NSV ? TPT : 1][NSV ? R : 1];
     };
     auto fp_load = [&](const FPI& fi, FPD& d) {
-        if (!fi.ok) return;
+        if (!fi.ok || fi.bnd) return;
 #pragma unroll
         for (int jj = 0; jj < TPT; ++jj) {
             if (!fi.local) load_state(fi.en, fi.rn0 + jj * NS, d.un[jj]);
@@ -563,6 +574,9 @@ __global__ __launch_bounds__((Shape<D, N1, NT, tpt_of(EQ, NT)>::BS)) void k_op(c
                             if constexpr (JVP) unl[v] = make_state<T>(tile[v * NL + tn], tile[(R + v) * NL + tn]);
                             else unl[v] = tile[v * NL + tn];
                         }
+                    } else if (BND && fi.bnd) {
+#pragma unroll
+                        for (int v = 0; v < R; ++v) unl[v] = make_state<T>(CT(sg.bcg), CT(0));
                     } else {
 #pragma unroll
                         for (int v = 0; v < R; ++v) unl[v] = d.un[jj][v];
@@ -1182,9 +1196,10 @@ __global__ __attribute__((amdgpu_waves_per_eu(2))) __launch_bounds__((Shape<D, N
 // ---------------------------------------------------------------------------
 // host launchers
 // ---------------------------------------------------------------------------
-template <int EQ, int D, int N1, int NT, class CT, class UT, bool JVP>
+template <int EQ, int D, int N1, int NT, class CT, class UT, bool JVP, bool BND = false>
 void launch_op(const OpSeg* segs, int nseg, int G, hipStream_t st) {
-    launch_k(k_op<EQ, D, N1, NT, CT, UT, JVP>, dim3(G), dim3(Shape<D, N1, NT, tpt_of(EQ, NT)>::BS), st, segs, nseg, G);
+    launch_k(k_op<EQ, D, N1, NT, CT, UT, JVP, BND>, dim3(G), dim3(Shape<D, N1, NT, tpt_of(EQ, NT)>::BS), st, segs,
+             nseg, G);
 }
 template <int EQ, int D, int N1, int NT, class CT, class UT, bool ROT = false, bool BND = false>
 void launch_lin(const OpSeg* segs, int nseg, int G, hipStream_t st) {
@@ -1212,6 +1227,11 @@ OpTable make_table() {
         t.res64 = launch_op<EQ, D, N1, NT, double, double, false>;
         t.jvp64 = launch_op<EQ, D, N1, NT, double, double, true>;
         t.jvp32 = launch_op<EQ, D, N1, NT, float, float, true>;
+        if constexpr (EQ == EQ_BURGERS) {
+            t.res64_bnd = launch_op<EQ, D, N1, NT, double, double, false, true>;
+            t.jvp64_bnd = launch_op<EQ, D, N1, NT, double, double, true, true>;
+            t.jvp32_bnd = launch_op<EQ, D, N1, NT, float, float, true, true>;
+        }
     }
     if constexpr (EQ == EQ_NS) {
         t.visc_res64 = launch_visc<D, N1, NT, double, double, false>;
@@ -1235,6 +1255,7 @@ OpTable make_spatial_table() {
         t.res64_bnd = launch_lin<EQ, D, N1, 1, double, double, false, true>;
     } else {
         t.res64 = launch_op<EQ, D, N1, 1, double, double, false>;
+        if constexpr (EQ == EQ_BURGERS) t.res64_bnd = launch_op<EQ, D, N1, 1, double, double, false, true>;
     }
     if constexpr (EQ == EQ_NS) t.visc_res64 = launch_visc<D, N1, 1, double, double, false>;
     return t;

@@ -1,11 +1,12 @@
 """GPU parity of Dirichlet boundaries (the boundary convective flux of the
 surface integral, Sec. "DG-SEM in Space"; the exterior state g: Rusanov flux
 with g, BR1 with u_hat = g and the interior viscous flux, the interior
-penalty by Nitsche's terms) for the linear equations, against the oracle:
-residual, FP64 and FP32-inner JVP of every compiled (dim, N, Nt) with
-boundaries on some axes, an element with both ends on the boundary, mid
+penalty by Nitsche's terms) for the linear equations and Burgers, against
+the oracle: residual, FP64 and FP32-inner JVP of every compiled (dim, N, Nt)
+with boundaries on some axes, an element with both ends on the boundary, mid
 sizes (tiled and ragged traversals), and slab solves (heat equation with
-g = 0, inflow with g != 0).  "Relative" as in gpu_common.rel."""
+g = 0, inflow with g != 0, Burgers with inflow and outflow, with and without
+the element-block preconditioner).  "Relative" as in gpu_common.rel."""
 import sys
 
 import numpy as np
@@ -96,6 +97,42 @@ def test_boundary_slab_solves(orc, kind, fp32):
         U, un, s = gpu_solve(P, up, 1.0 / 24, 1e-12, inner_fp32=fp32)
         Uo, so = orc.solve(P.p, up, 1.0 / 24, tol=1e-13)
         assert rel(U, Uo) <= 1e-9
+    finally:
+        P.close()
+
+
+def test_burgers_boundary_operators(orc):
+    """Burgers with Dirichlet boundaries (g = 0.3), every compiled (N, Nt):
+    residual and JVPs against the oracle; and one element between the two
+    boundaries."""
+    for N in range(1, 6):
+        for Nt in (2, 3, 4):
+            for K in (5, 1):
+                P = Pair(cfg("burgers", 1, [K], N, Nt, bc=(1,), bc_value=0.3))
+                try:
+                    e = _ops(orc, P, 100 + 10 * N + Nt + K, ("burgers", K, N, Nt))
+                finally:
+                    P.close()
+    say("burgers boundary sweep, last", e)
+
+
+@pytest.mark.parametrize("fp32", [0, 1], ids=["fp64", "fp32inner"])
+@pytest.mark.parametrize("precond", [0, 1], ids=["plain", "bjacobi"])
+def test_burgers_boundary_slab_solves(orc, fp32, precond):
+    """Burgers on [0, 1] with g = 0.5 at both ends (inflow on the left,
+    outflow on the right for the positive data): four slabs one after
+    another, each matching the oracle's solution within 1e-9."""
+    P = Pair(cfg("burgers", 1, [24], 3, 3, bc=(1,), bc_value=0.5))
+    try:
+        X = P.coords()[:, 0, :]
+        up = (0.5 + 0.2 * np.sin(2 * np.pi * X) + 0.1 * np.cos(6 * np.pi * X)).ravel()
+        for k in range(4):
+            U, un, s = gpu_solve(P, up, 0.01, 1e-12, inner_fp32=fp32, precond=precond)
+            Uo, so = orc.solve(P.p, up, 0.01, tol=1e-13, dense_limit=0)
+            e = rel(U, Uo)
+            assert e <= 1e-9, (k, e)
+            up = un
+        say(f"burgers boundary slabs fp32={fp32} precond={precond}: {e:.2e}, gmres {s['gmres_its']}")
     finally:
         P.close()
 

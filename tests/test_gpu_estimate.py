@@ -53,6 +53,8 @@ CASES = [
     ("adv1d-Nt2", cfg("adv", 1, [10], 4, 2, a=(1.0,)), 1.0 / 20),
     ("advdiff2d-Nt4", cfg("advdiff", 2, [12, 10], 4, 4, a=(1.0, 0.5), nu=1e-3), 1.0 / 64),
     ("burgers-odd-n", cfg("burgers", 1, [7], 2, 3), 0.02),
+    # Dirichlet boundaries (exterior state 0.45): the one-time-level kernel's boundary variant
+    ("burgers-dirichlet", cfg("burgers", 1, [9], 3, 3, bc=(1,), bc_value=0.45), 0.02),
     ("euler2d", cfg("euler", 2, [6, 6], 3, 3, lo=[-5, -5], hi=[5, 5]), 0.05),
     ("ns3d-Nt2", cfg("ns", 3, [2, 2, 2], 2, 2, lo=[0, 0, 0], hi=[6.283185307179586] * 3, mu=1.0 / 1600), 0.05),
 ]
