@@ -20,8 +20,9 @@ def say(*a):
 
 def make_req(st, c, up, dt, tol=1e-11, **o):
     d = c["dim"]
-    m = st.mesh(d, c["K"], c["lo"], c["hi"])
-    eq = st.equation(c["kind"], a=c["a"][:d], nu=c["nu"], gamma=c["gamma"], mu=c["mu"], prandtl=c["prandtl"])
+    m = st.mesh(d, c["K"], c["lo"], c["hi"], bc=c.get("bc", (0, 0, 0)))
+    eq = st.equation(c["kind"], a=c["a"][:d], nu=c["nu"], gamma=c["gamma"], mu=c["mu"], prandtl=c["prandtl"],
+                     bc_value=c.get("bc_value", 0.0))
     return st.request(m, c["N"], c["Nt"], eq, up, 0.0, dt, tol, st.st_default_opts(**o))
 
 
@@ -149,6 +150,52 @@ def test_served_preconditioned_requests(orc):
             e = rel(u, orc.last_time_node(P.p, Uo))
             say(f"served {kind} K={c['K']} N={c['N']} Nt={c['Nt']} fp32={fp32} precond={pc}: "
                 f"GMRES {res['gmres_its']}, rel err vs oracle {e:.2e}")
+            assert e <= 1e-9
+    finally:
+        for P in pairs:
+            P.close()
+
+
+def test_served_boundary_requests(orc):
+    """Requests with Dirichlet boundaries (Burgers and advection-diffusion,
+    exterior states 0.5 and 0.2) served together with a periodic one, both
+    precisions, with and without the element-block preconditioner: each
+    result is bitwise the single-slab driver's and matches the oracle within
+    1e-9."""
+    from paper_2201_05800_amd import st
+    cases = [("burgers", cfg("burgers", 1, [30], 3, 3, bc=(1,), bc_value=0.5), 0, 0),
+             ("burgers", cfg("burgers", 1, [17], 4, 2, bc=(1,), bc_value=0.5), 1, 1),
+             ("advdiff", cfg("advdiff", 2, [9, 7], 3, 3, a=(1.0, 0.5), nu=1e-3, bc=(1, 0), bc_value=0.2), 0, 1),
+             ("advdiff", cfg("advdiff", 2, [6, 6], 2, 4, a=(1.0, 0.5), nu=1e-3, bc=(1, 1), bc_value=0.2), 1, 0),
+             ("burgers", burgers_case(20, 3, 3, 6), 0, 1)]
+    pairs = [Pair(c) for _, c, _, _ in cases]
+    try:
+        reqs, ups, dts = [], [], []
+        for (kind, c, fp32, pc), P in zip(cases, pairs):
+            up = initial_for(P, kind, seed=8)
+            if kind == "burgers":
+                up = up + 0.4                       # positive data: inflow at the left end
+            h = min((c["hi"][a] - c["lo"][a]) / c["K"][a] for a in range(c["dim"]))
+            lam = np.abs(up).max() if kind == "burgers" else np.sqrt(1.25)
+            dt = inputs.cfl_dt(5.0, h, c["N"], lam)
+            ups.append(up)
+            dts.append(dt)
+            reqs.append(make_req(st, c, up, dt, inner_fp32=fp32, precond=pc))
+        srv = st.st_server_create(hbm_budget_bytes=2 << 30, max_active=16)
+        try:
+            tks = [st.st_submit(srv, r) for r in reqs]
+            got = wait_all(st, srv, tks, [P.nsp for P in pairs])
+        finally:
+            st.st_server_destroy(srv)
+        for (kind, c, fp32, pc), P, up, dt, t in zip(cases, pairs, ups, dts, tks):
+            rc, u, res = got[t]
+            assert rc == st.ST_OK, (kind, rc)
+            _, un1, _ = gpu_solve(P, up, dt, 1e-11, inner_fp32=fp32, precond=pc)
+            assert np.array_equal(un1, u), f"served {kind} differs from st_solve_slab"
+            Uo, so = orc.solve(P.p, up, dt, tol=1e-13, dense_limit=0)
+            e = rel(u, orc.last_time_node(P.p, Uo))
+            say(f"served {kind} K={c['K']} bc={c['bc']} fp32={fp32} precond={pc}: GMRES {res['gmres_its']}, "
+                f"rel err vs oracle {e:.2e}")
             assert e <= 1e-9
     finally:
         for P in pairs:
