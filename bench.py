@@ -678,7 +678,9 @@ def leg_summary(w, r, steps):
 def forms_leg(name, args, stream):
     """Plain FP64 and FP32-inner solves of the same slabs: the FP64 run steps
     from u0; every slab is solved in both forms from the FP64 run's state, each
-    timed on its own; the FP32-inner slab is compared with the FP64 one."""
+    timed on its own; the FP32-inner slab is compared with the FP64 one.  The
+    same slabs are also solved with the element-block Jacobi in both forms
+    (timed on their own, compared with the plain FP64 slab)."""
     import numpy as np
     import torch
     from paper_2201_05800_amd import st
@@ -686,35 +688,41 @@ def forms_leg(name, args, stream):
     try:
         o64 = st.st_default_opts(restart=args.restart, cgs_passes=args.cgs_passes)
         o32 = st.st_default_opts(restart=args.restart, cgs_passes=args.cgs_passes, inner_fp32=1)
+        o64p = st.st_default_opts(restart=args.restart, cgs_passes=args.cgs_passes, precond=1)
+        o32p = st.st_default_opts(restart=args.restart, cgs_passes=args.cgs_passes, inner_fp32=1, precond=1)
+        forms = (o64, o32, o64p, o32p)
         u = torch.as_tensor(w.u0).cuda()
         un = torch.empty(w.nsp, dtype=torch.float64, device="cuda")
-        un32 = torch.empty_like(un)
-        U32 = torch.empty_like(w.U)
-        # warm-up of both forms (first-call allocations)
-        st.st_solve_slab(w.h, u, 0.0, w.dt, w.cfg["tol"], o64, w.U, un, stream)
-        st.st_solve_slab(w.h, u, 0.0, w.dt, w.cfg["tol"], o32, U32, un32, stream)
-        t64 = t32 = 0.0
-        its = {0: [], 1: []}
-        diffs = []
+        uns = [un] + [torch.empty_like(un) for _ in forms[1:]]
+        Us = [w.U] + [torch.empty_like(w.U) for _ in forms[1:]]
+        # warm-up of every form (first-call allocations, the block inverse)
+        for o, U_, un_ in zip(forms, Us, uns):
+            st.st_solve_slab(w.h, u, 0.0, w.dt, w.cfg["tol"], o, U_, un_, stream)
+        t = [0.0] * len(forms)
+        its = [[] for _ in forms]
+        diffs = [[] for _ in forms]
         for _ in range(args.forms_steps):
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            s64 = st.st_solve_slab(w.h, u, 0.0, w.dt, w.cfg["tol"], o64, w.U, un, stream)
-            t1 = time.perf_counter()
-            s32 = st.st_solve_slab(w.h, u, 0.0, w.dt, w.cfg["tol"], o32, U32, un32, stream)
-            t2 = time.perf_counter()
-            t64 += t1 - t0
-            t32 += t2 - t1
-            its[0].append(s64["gmres_its"])
-            its[1].append(s32["gmres_its"])
-            diffs.append(float(torch.linalg.norm(U32 - w.U) / torch.linalg.norm(w.U)))
-            u, un = un, u
+            for i, (o, U_, un_) in enumerate(zip(forms, Us, uns)):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                s_ = st.st_solve_slab(w.h, u, 0.0, w.dt, w.cfg["tol"], o, U_, un_, stream)
+                t[i] += time.perf_counter() - t0
+                its[i].append(s_["gmres_its"])
+            for i in range(1, len(forms)):
+                diffs[i].append(float(torch.linalg.norm(Us[i] - w.U) / torch.linalg.norm(w.U)))
+            u, uns[0] = uns[0], u
         k = args.forms_steps
+        ms = [x * 1e3 / k for x in t]
         return dict(workload=w.cfg["workload"], unknowns_per_slab=w.n, slabs=k, tol=w.cfg["tol"],
-                    fp64_ms_per_slab=t64 * 1e3 / k, fp32_inner_ms_per_slab=t32 * 1e3 / k,
-                    fp32_inner_speedup=t64 / t32, fp64_gmres_its_per_slab=float(np.mean(its[0])),
+                    fp64_ms_per_slab=ms[0], fp32_inner_ms_per_slab=ms[1],
+                    fp32_inner_speedup=ms[0] / ms[1], fp64_gmres_its_per_slab=float(np.mean(its[0])),
                     fp32_inner_gmres_its_per_slab=float(np.mean(its[1])),
-                    fp32_inner_vs_fp64_max_rel_diff=max(diffs),
+                    fp32_inner_vs_fp64_max_rel_diff=max(diffs[1]),
+                    preconditioned=dict(fp64_ms_per_slab=ms[2], fp32_inner_ms_per_slab=ms[3],
+                                        fp64_gmres_its_per_slab=float(np.mean(its[2])),
+                                        fp32_inner_gmres_its_per_slab=float(np.mean(its[3])),
+                                        fp64_vs_plain_max_rel_diff=max(diffs[2]),
+                                        fp32_inner_vs_plain_max_rel_diff=max(diffs[3])),
                     note="each slab solved in both forms from the same state; relative 2-norm difference of the "
                          "solved slabs; reduced boxes of these workloads match the oracle within 1e-9 in both "
                          "forms (GPU tests)")
