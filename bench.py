@@ -802,7 +802,7 @@ def main():
                    "Jacobian, the same in every element" +
                    ("" if cfg["kind"] in (st.ST_ADVECTION, st.ST_ADVDIFF_BR1) else ", taken at the mean state") + ")",
             speedup_vs_plain=elapsed / rp["elapsed"], **leg_summary(w, rp, args.steps),
-            precond_kernel=dict(kernel="k_bjacobi", avg_launch_us=round(us / max(calls, 1), 3),
+            precond_kernel=dict(kernel="k_bjacobi_big", avg_launch_us=round(us / max(calls, 1), 3),
                                 achieved_GBs=round(by / (us * 1e-6) / 1e9, 1) if us > 0 else None,
                                 achieved_TFLOPs=round(2.0 * npe * n * calls / (us * 1e-6) / 1e12, 2) if us > 0 else None,
                                 peak_TFLOPs=78.6, element_block=npe,

@@ -38,12 +38,8 @@ DI int find_pseg(const Seg* segs, int nseg, int b) {
 }
 constexpr int PC_BLOCK = 256;               // 4 wavefronts
 constexpr int PC_EB = 16;                   // elements per block (the MFMA column count)
-constexpr int PC_TW = 8;                    // row tiles per wavefront and row group
-constexpr int PC_KC = 4;                    // column steps per operand chunk
 // k_bjacobi_big (blocks above 512 rows)
 constexpr int PB_EB = 32;                   // elements per block: two MFMA column sets
-constexpr int PB_TW = 4;                    // row tiles per wavefront
-constexpr int PB_GT = 4 * PB_TW;            // row tiles per block (row group)
 constexpr int PB_KCB = 4;                   // column steps per A-operand chunk
 constexpr int PB_KP = 6 * PB_KCB;           // column steps per staged part (three chunk pairs)
 constexpr int PB_SQ = PB_EB * 4 * PB_KP / PC_BLOCK;   // staged words per thread and part
@@ -59,122 +55,30 @@ DI int pc_index(const int* p) {
 // the small-block kernel (k_bjacobi_ks) runs one 16-row tile of B^-1 per block
 static bool pc_small(int npe) {
     const int KS = (npe + 3) / 4, T = (npe + 15) / 16;
-    return T <= PC_TW && (KS + 3) / 4 <= 8;
+    return T <= 8 && (KS + 3) / 4 <= 8;
 }
+// row tiles per wavefront of k_bjacobi_big for T row tiles: 3 where one row
+// group of 12 holds them all (fewer idle tiles than a group of 16), else 4
+// (larger blocks keep groups of 16 tiles: four of them at npe = 960, so
+// that each XCD streams a quarter of B^-1)
+static int pb_tile_width(int T) { return T <= 12 ? 3 : 4; }
 int pc_blocks(int E, int npe) {
-    const int groups = (E + PC_EB - 1) / PC_EB, T = (npe + 15) / 16;
-    if (pc_small(npe)) return groups * T;                      // one block per (elements, row tile)
-    if (T > 4 * PC_TW) return (E + PB_EB - 1) / PB_EB * ((T + PB_GT - 1) / PB_GT);   // per (elements, row group)
-    return groups;
+    const int T = (npe + 15) / 16;
+    if (pc_small(npe)) return (E + PC_EB - 1) / PC_EB * T;      // one block per (elements, row tile)
+    const int GT = 4 * pb_tile_width(T);
+    return (E + PB_EB - 1) / PB_EB * ((T + GT - 1) / GT);       // per (elements, row group)
 }
 
-// out_e (+)= B^-1 in_e for 16 elements per block, as the dense product
-// Z = B^-1 [in_e0 ... in_e15] on the FP64 matrix cores
-// (v_mfma_f64_16x16x4f64: A 16x4 with A[i][k] in lane i + 16k, B 4x16 with
-// B[k][j] in lane j + 16k, D 16x16 with D[i][j] in lane j + 16 (i mod 4),
-// register i div 4).  B^-1 comes packed per (16-row tile, 4-column step) in
-// that A-operand lane order (zero padded), so each operand is one coalesced
-// load; the block's inputs are staged in LDS in B-operand order; wavefront w
-// takes the row tiles w, w + 4, ... (at most 4 PC_TW tiles: up to 512 rows;
-// larger blocks take k_bjacobi_big).  The result goes back through LDS for
-// coalesced stores.
-__global__ __launch_bounds__(PC_BLOCK) void k_bjacobi(const PcSeg* __restrict__ segs, int nseg) {
-    extern __shared__ double sm[];           // [KS * 64] B operands, then [16][npe | 1] results
-    const PcSeg& sg = segs[find_pseg(segs, nseg, blockIdx.x)];
-    // the skip flag and the Arnoldi index behind the input pointer in one round
-    const int skip = pc_index(sg.skip);
-    const int kin = pc_index(sg.in.kp);
-    if (skip) return;
-    const int npe = sg.npe;
-    const int KS = (npe + 3) >> 2, T = (npe + 15) >> 4;
-    const int e0 = (blockIdx.x - sg.blk0) * PC_EB;
-    const int ne = min(PC_EB, sg.E - e0);
-    const double* inb = static_cast<const double*>(sg.in.base);
-    if (sg.in.kp) inb += (int64_t)(kin + sg.in.koff) * sg.in.ld;
-    const auto* __restrict__ in = gp(inb) + (int64_t)e0 * npe;
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const auto* __restrict__ A = gp(sg.binvT);
-    // A operands of column steps [ks0, ks0 + PC_KC), double buffered: the
-    // next chunk's loads are in flight while the current chunk multiplies
-    auto load_chunk = [&](int ks0, double (&a)[PC_KC][PC_TW]) {
-#pragma unroll
-        for (int c = 0; c < PC_KC; ++c)
-#pragma unroll
-            for (int q = 0; q < PC_TW; ++q) {
-                const int ks = ks0 + c, rt = wave + 4 * q;
-                a[c][q] = (rt < T && ks < KS) ? A[((int64_t)rt * KS + ks) * 64 + lane] : 0.0;
-            }
-    };
-    v4d acc[PC_TW];
-    auto mul_chunk = [&](int ks0, const double (&a)[PC_KC][PC_TW]) {
-#pragma unroll
-        for (int c = 0; c < PC_KC; ++c) {
-            const int ks = ks0 + c;
-            if (ks >= KS) break;
-            const double b = sm[ks * 64 + lane];
-#pragma unroll
-            for (int q = 0; q < PC_TW; ++q)
-                if (wave + 4 * q < T) acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[c][q], b, acc[q], 0, 0, 0);
-        }
-    };
-    double a0[PC_KC][PC_TW], a1[PC_KC][PC_TW];
-    load_chunk(0, a0);                        // overlaps the staging below
-    for (int t = threadIdx.x; t < KS * 64; t += PC_BLOCK) sm[t] = 0.0;
-    __syncthreads();
-    // element-fastest thread order: consecutive lanes write consecutive LDS
-    // words (B-operand order), reads stay within the block's 16 elements;
-    // eight loads per thread in flight before they are staged
-    constexpr int SQ = 8;
-    for (int t0 = threadIdx.x; t0 < PC_EB * npe; t0 += SQ * PC_BLOCK) {
-        double v[SQ];
-#pragma unroll
-        for (int q = 0; q < SQ; ++q) {
-            const int t = t0 + q * PC_BLOCK;
-            const int j = t & (PC_EB - 1), c = t >> 4;
-            v[q] = (t < PC_EB * npe && j < ne) ? in[(int64_t)j * npe + c] : 0.0;
-        }
-#pragma unroll
-        for (int q = 0; q < SQ; ++q) {
-            const int t = t0 + q * PC_BLOCK;
-            const int j = t & (PC_EB - 1), c = t >> 4;
-            if (t < PC_EB * npe) sm[(c >> 2) * 64 + j + 16 * (c & 3)] = v[q];
-        }
-    }
-    __syncthreads();
-    auto* __restrict__ out = gp(sg.out) + (int64_t)e0 * npe;
-#pragma unroll
-    for (int q = 0; q < PC_TW; ++q) acc[q] = v4d{0.0, 0.0, 0.0, 0.0};
-    for (int ks0 = 0; ks0 < KS; ks0 += 2 * PC_KC) {
-        load_chunk(ks0 + PC_KC, a1);
-        mul_chunk(ks0, a0);
-        if (ks0 + PC_KC >= KS) break;
-        load_chunk(ks0 + 2 * PC_KC, a0);
-        mul_chunk(ks0 + PC_KC, a1);
-    }
-    __syncthreads();                         // B operands consumed: reuse sm for the results
-    const int SR = npe | 1;                  // odd row stride: no LDS bank conflicts across j
-#pragma unroll
-    for (int q = 0; q < PC_TW; ++q) {
-        const int rt = wave + 4 * q;
-        if (rt < T) {
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int row = rt * 16 + (lane >> 4) + 4 * r, j = lane & 15;
-                if (row < npe) sm[j * SR + row] = acc[q][r];
-            }
-        }
-    }
-    __syncthreads();
-    for (int t = threadIdx.x; t < ne * npe; t += PC_BLOCK) {
-        const int j = t / npe, row = t - j * npe;
-        double z = sm[j * SR + row];
-        if (sg.accumulate) z += out[t];
-        store_nt(&out[t], z);
-    }
-}
-
-// Large blocks (more than 512 rows, at most 1024): one GPU block per (32
-// elements, group of PB_GT row tiles).  Every A operand (16 rows x 4 columns
+// out_e (+)= B^-1 in_e for every element, as dense products on the FP64
+// matrix cores (v_mfma_f64_16x16x4f64: A 16x4 with A[i][k] in lane i + 16k,
+// B 4x16 with B[k][j] in lane j + 16k, D 16x16 with D[i][j] in lane
+// j + 16 (i mod 4), register i div 4).  B^-1 comes packed per (16-row tile,
+// 4-column step) in that A-operand lane order (zero padded), so each operand
+// is one coalesced load; the elements' inputs are staged in LDS in B-operand
+// order.
+// Blocks above 128 unknowns (at most 1024): one GPU block per (32 elements,
+// group of PB_GT = 4 PB_TW row tiles; PB_TW 3 for blocks of at most 192
+// unknowns, else 4: pb_tile_width).  Every A operand (16 rows x 4 columns
 // of B^-1, streamed from the caches) feeds two products, one per half of the
 // 32 elements, and every B operand from LDS feeds the PB_TW row tiles of its
 // wavefront.  The elements' inputs are staged in parts of PB_KP column steps,
@@ -190,7 +94,9 @@ __global__ __launch_bounds__(PC_BLOCK) void k_bjacobi(const PcSeg* __restrict__ 
 // rows of B^-1 (a quarter of it, 1.8 MB at npe = 960), which then stay in its
 // L2.  The group accumulates in registers (the column steps in order, as the
 // other kernels) and writes its rows back through LDS.
+template <int PB_TW>
 __global__ __launch_bounds__(PC_BLOCK, 2) void k_bjacobi_big(const PcSeg* __restrict__ segs, int nseg) {
+    constexpr int PB_GT = 4 * PB_TW;         // row tiles per block (row group)
     extern __shared__ double sm[];           // two buffers of [PB_KP][2][64] B operands
     constexpr int BW = PB_EB * 4 * PB_KP;    // words of one buffer
     const PcSeg& sg = segs[find_pseg(segs, nseg, blockIdx.x)];
@@ -437,7 +343,7 @@ __global__ __launch_bounds__(VBLOCK) void k_combine(const VecSeg* __restrict__ s
 // coupling of slab m's first time node to slab m-1's last.  The
 // preconditioner P = blockdiag(B) + L (B the element block of each J_m) is
 // solved exactly, element by element: with y = B^-1 r of every slab already
-// computed (k_bjacobi),
+// computed (pc_apply),
 //   z_0 = y_0,   z_m = y_m - C l_{m-1}  (m >= 1),   l_m = z_m at the last time node,
 // C = the columns of B^-1 at the first time node (npe x nl, nl = nv ns).
 // One wavefront per element, the slabs in sequence; C staged in LDS when
@@ -486,31 +392,27 @@ __global__ void k_set_units(double* x, int64_t ld, int count) {
 
 __global__ void k_put_pcseg(PcSeg* dst, PcSeg v) { if (threadIdx.x == 0 && blockIdx.x == 0) *dst = v; }
 
-// dynamic LDS of k_bjacobi for element blocks of npe unknowns
+// dynamic LDS of the block Jacobi kernels for element blocks of npe unknowns
 static size_t bjacobi_lds(int npe) {
-    const int KS = (npe + 3) / 4, T = (npe + 15) / 16;
-    if (T > 4 * PC_TW) return sizeof(double) * 2 * PB_EB * 4 * PB_KP;   // two part buffers
-    return sizeof(double) * std::max<size_t>(64 * (size_t)KS, 16 * (size_t)(npe | 1));
+    const int KS = (npe + 3) / 4;
+    if (pc_small(npe)) return sizeof(double) * std::max<size_t>(64 * (size_t)KS, 4 * 16 * 17);   // k_bjacobi_ks
+    return sizeof(double) * 2 * PB_EB * 4 * PB_KP;                                             // two part buffers
 }
 
 hipError_t pc_prepare(int npe) {
     if (npe < 1 || npe > PC_NPE_MAX) return hipErrorInvalidValue;
-    const size_t shm = bjacobi_lds(npe);
-    if (shm <= 64 * 1024) return hipSuccess;
-    return hipFuncSetAttribute((const void*)k_bjacobi, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm);
+    return bjacobi_lds(npe) <= 64 * 1024 ? hipSuccess : hipErrorInvalidValue;
 }
 
 void pc_apply(const PcSeg* s, int nseg, int G, int npe, hipStream_t st) {
-    const int KS = (npe + 3) / 4, T = (npe + 15) / 16;
-    if (pc_small(npe)) {
-        const size_t shm = sizeof(double) * std::max<size_t>(64 * (size_t)KS, 4 * 16 * 17);
+    const int T = (npe + 15) / 16;
+    const size_t shm = bjacobi_lds(npe);
+    if (pc_small(npe))
         launch_ks(k_bjacobi_ks, dim3(G), dim3(PC_BLOCK), shm, st, s, nseg);
-    } else {
-        if (T > 4 * PC_TW)
-            launch_ks(k_bjacobi_big, dim3(G), dim3(PC_BLOCK), bjacobi_lds(npe), st, s, nseg);
-        else
-            launch_ks(k_bjacobi, dim3(G), dim3(PC_BLOCK), bjacobi_lds(npe), st, s, nseg);
-    }
+    else if (pb_tile_width(T) == 3)
+        launch_ks(k_bjacobi_big<3>, dim3(G), dim3(PC_BLOCK), shm, st, s, nseg);
+    else
+        launch_ks(k_bjacobi_big<4>, dim3(G), dim3(PC_BLOCK), shm, st, s, nseg);
 }
 // C in LDS up to this many bytes (several blocks per CU still fit)
 constexpr size_t SWEEP_C_LDS = 48 * 1024;
@@ -536,7 +438,7 @@ void put_pcseg(PcSeg* dst, const PcSeg& v, hipStream_t st) {
 }  // namespace stdg
 
 namespace stdg {
-// Operand order of k_bjacobi: for row tile rt (16 rows) and column step ks
+// Operand order of the block Jacobi kernels: for row tile rt (16 rows) and column step ks
 // (4 columns), 64 values in lane order, lane l holding
 // (B^-1)[16 rt + l mod 16][4 ks + l div 16], zero outside npe x npe.
 std::vector<double> pc_pack(const std::vector<double>& binv, int npe) {
