@@ -38,7 +38,7 @@ DI int find_pseg(const Seg* segs, int nseg, int b) {
 }
 constexpr int PC_BLOCK = 256;               // 4 wavefronts
 constexpr int PC_EB = 16;                   // elements per block (the MFMA column count)
-// k_bjacobi_big (blocks above 512 rows)
+// k_bjacobi_big (blocks above 128 unknowns)
 constexpr int PB_EB = 32;                   // elements per block: two MFMA column sets
 constexpr int PB_KCB = 4;                   // column steps per A-operand chunk
 constexpr int PB_KP = 6 * PB_KCB;           // column steps per staged part (three chunk pairs)
@@ -92,8 +92,8 @@ int pc_blocks(int E, int npe) {
 // workgroups go round-robin over the 8 XCDs, so where the number of row
 // groups divides 8 (4 for npe from 769 to 1024) each XCD streams the same
 // rows of B^-1 (a quarter of it, 1.8 MB at npe = 960), which then stay in its
-// L2.  The group accumulates in registers (the column steps in order, as the
-// other kernels) and writes its rows back through LDS.
+// L2.  The group accumulates in registers (the column steps in order) and
+// writes its rows back through LDS.
 template <int PB_TW>
 __global__ __launch_bounds__(PC_BLOCK, 2) void k_bjacobi_big(const PcSeg* __restrict__ segs, int nseg) {
     constexpr int PB_GT = 4 * PB_TW;         // row tiles per block (row group)
