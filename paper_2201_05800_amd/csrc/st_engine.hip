@@ -1323,6 +1323,7 @@ int st_solve_slabs(st_handle_t h, int M, const double* u_prev, double t0, double
     if (pc) CHK(ensure_precond(h, u_prev, dt, st));
     const int kind = pb.eq.kind;
     const int64_t nM = pb.n * M;             // unknowns of the (multi-slab) system
+    const int gstream = gs_stream((int64_t)(m + 1) * nM * 8);   // the Krylov basis beyond the Infinity Cache
 
     // forcing: linear equations solve each cycle as far as the outer tolerance
     double eta_rel = linear_eq(kind) ? 0.0 : std::max(o.gmres_rtol, 0.0);
@@ -1460,8 +1461,8 @@ int st_solve_slabs(st_handle_t h, int M, const double* u_prev, double t0, double
             for (int p = 0; p < npass; ++p) {
                 int lastp = 0, gate = 0;
                 gs_pass_plan(o.cgs_passes, p, &lastp, &gate);
-                T.run(ST_K_MULTIDOT, st, [&] { vk_multidot(dvs, 1, Gv, k, st, gate); });
-                T.run(ST_K_UPDATE, st, [&] { vk_update(dvs, 1, Gv, p, lastp, k, st); });
+                T.run(ST_K_MULTIDOT, st, [&] { vk_multidot(dvs, 1, Gv, k, st, gate, gstream); });
+                T.run(ST_K_UPDATE, st, [&] { vk_update(dvs, 1, Gv, p, lastp, k, st, gstream); });
             }
         }
         T.run(ST_K_NEWTON, st, [&] {

@@ -184,8 +184,14 @@ DI v2d scaled(double s, v2d w) { return v2d{s * w.x, s * w.y}; }
 
 // Basis entries V_i[t + q stride] (i < NV, q < UN) and w[t + q stride], in
 // units of E (n of them per vector); zero past the end.  All loads are
-// issued before any is used.
-template <int NV, int UN, class E>
+// issued before any is used.  NTL: non-temporal loads, for bases larger
+// than the Infinity Cache holds (they would only evict each other there).
+template <bool NTL, class E>
+DI E load_v(const __attribute__((address_space(1))) E* p) {
+    if constexpr (NTL) return __builtin_nontemporal_load(p);
+    else return *p;
+}
+template <int NV, int UN, bool NTL, class E>
 DI void load_group(const __attribute__((address_space(1))) E* V, const __attribute__((address_space(1))) E* w,
                    int64_t n, int64_t t, int64_t stride, E (&a)[UN][NV], E (&wv)[UN]) {
 #pragma unroll
@@ -193,8 +199,8 @@ DI void load_group(const __attribute__((address_space(1))) E* V, const __attribu
         const int64_t tq = t + q * stride;
         const bool p = tq < n;
 #pragma unroll
-        for (int i = 0; i < NV; ++i) a[q][i] = p ? V[(int64_t)i * n + tq] : zero_of(E{});
-        wv[q] = p ? w[tq] : zero_of(E{});
+        for (int i = 0; i < NV; ++i) a[q][i] = p ? load_v<NTL>(&V[(int64_t)i * n + tq]) : zero_of(E{});
+        wv[q] = p ? load_v<NTL>(&w[tq]) : zero_of(E{});
     }
 }
 // pairs where n is even and the vectors are 16-byte aligned
@@ -267,7 +273,7 @@ __global__ __launch_bounds__(VBLOCK) void k_scale_v0(const VecSeg* __restrict__ 
 // row of partial sums per block -> part.  The loads of every thread's first
 // elements are in flight before the cycle state is read, except with gate
 // set (a pass that usually finds its step finished: the state is read first).
-template <int NV>
+template <int NV, bool NTL>
 __global__ __launch_bounds__(VBLOCK) void k_multidot(const VecSeg* __restrict__ segs, int nseg, int gate) {
     __shared__ double smem[VWAVES * (NV + 1)];
     __shared__ double s_out[NV + 1];
@@ -288,7 +294,7 @@ __global__ __launch_bounds__(VBLOCK) void k_multidot(const VecSeg* __restrict__ 
         int64_t t = (int64_t)lb * VBLOCK + threadIdx.x;
         E a[UN][NV], wv[UN];
         if (gate && (st->done || !st->reorth)) return false;
-        load_group<NV, UN>(V, w, n, t, stride, a, wv);
+        load_group<NV, UN, NTL>(V, w, n, t, stride, a, wv);
         if (st->done || st->k != NV - 1) return false;
         auto accumulate = [&](bool first) {
 #pragma unroll
@@ -305,7 +311,7 @@ __global__ __launch_bounds__(VBLOCK) void k_multidot(const VecSeg* __restrict__ 
         };
         accumulate(true);
         for (t += UN * stride; t < n; t += UN * stride) {
-            load_group<NV, UN>(V, w, n, t, stride, a, wv);
+            load_group<NV, UN, NTL>(V, w, n, t, stride, a, wv);
             accumulate(false);
         }
         return true;
@@ -350,7 +356,7 @@ __global__ __launch_bounds__(VBLOCK) void k_multidot(const VecSeg* __restrict__ 
 // restores orthogonality to working precision ("twice is enough")
 constexpr double REORTH = 0.5;
 
-template <int NV, class E, int UN>
+template <int NV, class E, int UN, bool NTL>
 DI void update_body(const VecSeg& sg, GState* st, int lb, int64_t stride, int pass, int last, double* s_tmp,
                     double* s_h, double* s_col, double* s_cs, double* s_sn, double* s_hacc, double* s_misc) {
     constexpr int k = NV - 1;
@@ -379,7 +385,7 @@ DI void update_body(const VecSeg& sg, GState* st, int lb, int64_t stride, int pa
     const double hacc_i = (pass > 0 && ti < NV) ? sr->hacc[ti] : 0.0;
     int64_t t = (int64_t)lb * VBLOCK + ti;
     E a[UN][NV], wv[UN];
-    load_group<NV, UN>(V, w, ne, t, stride, a, wv);
+    load_group<NV, UN, NTL>(V, w, ne, t, stride, a, wv);
     if (done) return;
     if (ti < NV) {
         s_cs[ti] = cs_i;
@@ -479,12 +485,12 @@ DI void update_body(const VecSeg& sg, GState* st, int lb, int64_t stride, int pa
     };
     correct();
     for (t += UN * stride; t < ne; t += UN * stride) {
-        load_group<NV, UN>(V, w, ne, t, stride, a, wv);
+        load_group<NV, UN, NTL>(V, w, ne, t, stride, a, wv);
         correct();
     }
 }
 
-template <int NV>
+template <int NV, bool NTL>
 __global__ __launch_bounds__(VBLOCK) void k_update(const VecSeg* __restrict__ segs, int nseg, int pass,
                                                    int last) {
     __shared__ double s_tmp[VBLOCK];
@@ -500,12 +506,12 @@ __global__ __launch_bounds__(VBLOCK) void k_update(const VecSeg* __restrict__ se
     constexpr int UP = sweep_unroll_pairs<NV>();
     if constexpr (UP > 0) {
         if (use_pairs(n, sg.V, sg.w)) {
-            update_body<NV, v2d, UP>(sg, st, lb, stride, pass, last, s_tmp, s_h, s_col, s_cs, s_sn, s_hacc,
+            update_body<NV, v2d, UP, NTL>(sg, st, lb, stride, pass, last, s_tmp, s_h, s_col, s_cs, s_sn, s_hacc,
                                      s_misc);
             return;
         }
     }
-    update_body<NV, double, sweep_unroll<NV>()>(sg, st, lb, stride, pass, last, s_tmp, s_h, s_col, s_cs, s_sn,
+    update_body<NV, double, sweep_unroll<NV>(), NTL>(sg, st, lb, stride, pass, last, s_tmp, s_h, s_col, s_cs, s_sn,
                                                 s_hacc, s_misc);
 }
 
@@ -703,29 +709,37 @@ LaunchTiming& launch_timing() {
 }
 
 namespace {
-template <int NV>
-void md_launch(const VecSeg* s, int nseg, int G, int gate, hipStream_t st) { LAUNCH_V(k_multidot<NV>, G, s, nseg, gate); }
-template <int NV>
+template <int NV, bool NTL>
+void md_launch(const VecSeg* s, int nseg, int G, int gate, hipStream_t st) {
+    LAUNCH_V((k_multidot<NV, NTL>), G, s, nseg, gate);
+}
+template <int NV, bool NTL>
 void up_launch(const VecSeg* s, int nseg, int G, int pl, hipStream_t st) {
-    LAUNCH_V(k_update<NV>, G, s, nseg, pl >> 2, pl & 3);
+    LAUNCH_V((k_update<NV, NTL>), G, s, nseg, pl >> 2, pl & 3);
 }
 using VLaunch = void (*)(const VecSeg*, int, int, int, hipStream_t);
-template <int... I>
-constexpr std::array<VLaunch, sizeof...(I)> md_table(std::integer_sequence<int, I...>) { return {&md_launch<I + 1>...}; }
-template <int... I>
-constexpr std::array<VLaunch, sizeof...(I)> up_table(std::integer_sequence<int, I...>) { return {&up_launch<I + 1>...}; }
+template <bool NTL, int... I>
+constexpr std::array<VLaunch, sizeof...(I)> md_table(std::integer_sequence<int, I...>) {
+    return {&md_launch<I + 1, NTL>...};
+}
+template <bool NTL, int... I>
+constexpr std::array<VLaunch, sizeof...(I)> up_table(std::integer_sequence<int, I...>) {
+    return {&up_launch<I + 1, NTL>...};
+}
 }  // namespace
 
 void vk_rnorm(const VecSeg* s, int nseg, int G, hipStream_t st) { LAUNCH_V(k_rnorm, G, s, nseg); }
 void vk_begin(const VecSeg* s, int nseg, hipStream_t st) { LAUNCH_V(k_begin, nseg, s, nseg); }
 void vk_scale_v0(const VecSeg* s, int nseg, int G, hipStream_t st) { LAUNCH_V(k_scale_v0, G, s, nseg); }
-void vk_multidot(const VecSeg* s, int nseg, int G, int k, hipStream_t st, int gate) {
-    static const auto tbl = md_table(std::make_integer_sequence<int, MMAX>{});
-    tbl[k](s, nseg, G, gate, st);
+void vk_multidot(const VecSeg* s, int nseg, int G, int k, hipStream_t st, int gate, int stream) {
+    static const auto tbl = md_table<false>(std::make_integer_sequence<int, MMAX>{});
+    static const auto tbl_nt = md_table<true>(std::make_integer_sequence<int, MMAX>{});
+    (stream ? tbl_nt : tbl)[k](s, nseg, G, gate, st);
 }
-void vk_update(const VecSeg* s, int nseg, int G, int pass, int last, int k, hipStream_t st) {
-    static const auto tbl = up_table(std::make_integer_sequence<int, MMAX>{});
-    tbl[k](s, nseg, G, (pass << 2) | (last & 3), st);
+void vk_update(const VecSeg* s, int nseg, int G, int pass, int last, int k, hipStream_t st, int stream) {
+    static const auto tbl = up_table<false>(std::make_integer_sequence<int, MMAX>{});
+    static const auto tbl_nt = up_table<true>(std::make_integer_sequence<int, MMAX>{});
+    (stream ? tbl_nt : tbl)[k](s, nseg, G, (pass << 2) | (last & 3), st);
 }
 void gs_pass_plan(int passes, int p, int* last, int* gate) {
     // passes 1: CGS1; 2: CGS2; 0: adaptive (pass 0 decides whether pass 1 runs)

@@ -12,12 +12,21 @@ void vk_rnorm(const VecSeg* s, int nseg, int G, hipStream_t st);      // partial
 void vk_begin(const VecSeg* s, int nseg, hipStream_t st);             // ||R||, cycle state
 void vk_scale_v0(const VecSeg* s, int nseg, int G, hipStream_t st);
 // k: the Arnoldi step index (0 .. m-1), the same for every slab of the launch;
-// gate: read the cycle state before loading (a pass that usually exits)
-void vk_multidot(const VecSeg* s, int nseg, int G, int k, hipStream_t st, int gate = 0);
+// gate: read the cycle state before loading (a pass that usually exits);
+// stream: non-temporal basis loads (gs_stream)
+void vk_multidot(const VecSeg* s, int nseg, int G, int k, hipStream_t st, int gate, int stream);
 // pass: Gram-Schmidt pass index; last: 1 the final pass (writes V_{k+1}
 // normalised), 0 not, 2 the final pass unless the new vector's norm cancels
 // (then the next pass is), 3 that next pass (exits unless pass 0 asked for it)
-void vk_update(const VecSeg* s, int nseg, int G, int pass, int last, int k, hipStream_t st);
+void vk_update(const VecSeg* s, int nseg, int G, int pass, int last, int k, hipStream_t st, int stream);
+// Whether the Gram-Schmidt sweeps of a launch load the basis non-temporally:
+// where the Krylov bases of the launch (basis_bytes in all) exceed what the
+// 256 MB Infinity Cache could hold, caching them only makes the vectors evict
+// each other (3D Navier-Stokes slab, 976 MB of basis: 5 % less time per
+// slab with non-temporal loads; 2D advection-diffusion slab, 102 MB: 4 %
+// more).  The arithmetic, and so every result, is the same either way.
+constexpr int64_t GS_STREAM_BYTES = (int64_t)192 << 20;
+inline int gs_stream(int64_t basis_bytes) { return basis_bytes > GS_STREAM_BYTES ? 1 : 0; }
 // last / gate of pass p for a cgs_passes option (0 adaptive, 1, 2)
 void gs_pass_plan(int passes, int p, int* last, int* gate);
 void vk_finish(const VecSeg* s, int nseg, hipStream_t st);

@@ -566,7 +566,12 @@ bool tick(st_srv* s) {
     VecSeg* dvc = (VecSeg*)(D1 + off_vc);
     const int nc = (int)vc.size();
     int mmax = 0;
-    for (Req* r : cont) mmax = std::max(mmax, r->opts.restart);
+    int64_t basis = 0;                    // Krylov bases of the tick's requests, bytes
+    for (Req* r : cont) {
+        mmax = std::max(mmax, r->opts.restart);
+        basis += (int64_t)(r->opts.restart + 1) * r->pb.n * 8;
+    }
+    const int gstream = gs_stream(basis);
     vk_scale_v0(dvc, nc, Gc, st);
     for (int k = 0; k < mmax; ++k) {
         for (auto& g : pgroups) pc_apply((PcSeg*)(D1 + g.off_step), (int)g.step.size(), g.G, g.npe, st);
@@ -585,8 +590,8 @@ bool tick(st_srv* s) {
             for (int p = 0; p < (q == 0 ? 1 : 2); ++p) {
                 int lastp = 0, gate = 0;
                 gs_pass_plan(passes, p, &lastp, &gate);
-                vk_multidot(dq, nq, Gp[q], k, st, gate);
-                vk_update(dq, nq, Gp[q], p, lastp, k, st);
+                vk_multidot(dq, nq, Gp[q], k, st, gate, gstream);
+                vk_update(dq, nq, Gp[q], p, lastp, k, st, gstream);
             }
         }
     }
