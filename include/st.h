@@ -175,7 +175,11 @@ int st_lgl(int n, double* x, double* w, double* D);
 /* Create a handle for one (mesh, N, Nt, equation).  N in 1..5 (1..4 for
  * dim 3; 1..4 for EULER / NS_BR1), Nt in 2..4.  Allocates device workspace
  * on the current device.  Returns ST_ERR_UNSUPPORTED for combinations that
- * are not compiled in. */
+ * are not compiled in.  The calls of one handle share its workspace and its
+ * launch descriptors (which a call rewrites only where they differ from what
+ * the previous call on the same stream left): calls on one stream follow
+ * stream order; calls of one handle on different streams or threads must
+ * not overlap (synchronise between them). */
 int st_create(const st_mesh_t* mesh, int N, int Nt, const st_equation_t* eq, st_handle_t* out);
 int st_destroy(st_handle_t h);
 

@@ -522,6 +522,32 @@ struct st_ctx {
     OpSeg* d_opm = nullptr;
     VecSeg* d_vsm = nullptr;
 
+    // Host copies of the operator descriptors last written to the slots of
+    // d_op and d_opm, each with the stream that wrote it.  A descriptor is
+    // about 10 KB, written by five launches; a call that would write the
+    // same bytes to a slot on the same stream skips them, since stream order
+    // has already put those bytes there (repeated st_residual / st_jvp calls
+    // on the same buffers: 25-70 us less per call).  Every write to those
+    // slots goes through put_op; reallocating d_opm clears the copies.
+    struct OpCopy {
+        const OpSeg* dst;
+        hipStream_t st;
+        OpSeg v;
+    };
+    std::vector<OpCopy> op_copies;
+    void put_op(OpSeg* dst, const OpSeg& v, hipStream_t st) {
+        for (auto& c : op_copies) {
+            if (c.dst != dst) continue;
+            if (c.st == st && std::memcmp(&c.v, &v, sizeof(OpSeg)) == 0) return;
+            put_opseg(dst, v, st);
+            c.st = st;
+            c.v = v;
+            return;
+        }
+        put_opseg(dst, v, st);
+        op_copies.push_back(OpCopy{dst, st, v});
+    }
+
     // optional HIP-event timing of kernel classes (st_solver_opts_t.timing)
     struct Timer {
         int mask = 0;
@@ -608,6 +634,7 @@ static int ensure_cap(st_ctx* h, int M) {
     h->V = h->w = h->R = h->U = h->pz = h->Q = h->dQ = h->d_part = nullptr;
     h->U32 = h->dQ32 = nullptr;
     h->d_opm = nullptr;
+    h->op_copies.clear();
     h->d_vsm = nullptr;
     h->m_alloc = 0;
     h->cap = c;
@@ -1049,12 +1076,12 @@ namespace stdg {
 // Descriptors of M consecutive slabs: segment m covers blocks [m G, (m+1) G)
 // of one launch; `make(m, seg)` fills slab m's pointers.
 template <class F>
-static void put_slab_segs(OpSeg* dst, int M, const OpSeg& proto, hipStream_t st, F&& make) {
+static void put_slab_segs(st_ctx* h, OpSeg* dst, int M, const OpSeg& proto, hipStream_t st, F&& make) {
     for (int m = 0; m < M; ++m) {
         OpSeg s = proto;
         s.blk0 = m * proto.nblk;
         make(m, s);
-        put_opseg(dst + m, s, st);
+        h->put_op(dst + m, s, st);
     }
 }
 
@@ -1073,12 +1100,12 @@ void setup_residual(st_ctx* h, int M, const double* U, const double* u_prev, dou
     if (grad_pass(pb)) {
         OpSeg g = base;
         visc_tiles(g, pb);
-        put_slab_segs(dv, M, g, st, [&](int m, OpSeg& x) {
+        put_slab_segs(h, dv, M, g, st, [&](int m, OpSeg& x) {
             x.U = dptr(U + m * n);
             x.out = dptr(h->Q + m * nq);
         });
     }
-    put_slab_segs(dop, M, base, st, [&](int m, OpSeg& x) {
+    put_slab_segs(h, dop, M, base, st, [&](int m, OpSeg& x) {
         if (grad_pass(pb)) x.Q = dptr(h->Q + m * nq);
         x.U = dptr(U + m * n);
         x.uprev = m == 0 ? u_prev : nullptr;
@@ -1131,13 +1158,13 @@ void setup_jvp(st_ctx* h, int M, const double* U, const double* dir, const int* 
     if (grad_pass(pb)) {
         OpSeg g = base;
         visc_tiles(g, pb);
-        put_slab_segs(dv, M, g, st, [&](int m, OpSeg& x) {
+        put_slab_segs(h, dv, M, g, st, [&](int m, OpSeg& x) {
             x.U = state(m);
             x.V = dirp(m);
             x.out = dq(m);
         });
     }
-    put_slab_segs(dop, M, base, st, [&](int m, OpSeg& x) {
+    put_slab_segs(h, dop, M, base, st, [&](int m, OpSeg& x) {
         x.out = dptr(out + m * n);
         if (linear_eq(kind)) {
             // J v = R(v) with u_prev = 0 and no exterior state (the linear part)
@@ -1243,14 +1270,14 @@ int st_error_estimate(st_handle_t h, const double* U, const double* u_prev, doub
             visc_tiles(g, p1);
             g.U = dptr(u_prev);
             g.out = dptr(h->est_q);
-            put_opseg(h->d_op + 0, g, st);
+            h->put_op(h->d_op + 0, g, st);
         }
         OpSeg x = b;
         if (grad_pass(p1)) x.Q = dptr(h->est_q);
         x.U = dptr(u_prev);
         x.uprev = u_prev;
         x.out = dptr(h->est_f);
-        put_opseg(h->d_op + 1, x, st);
+        h->put_op(h->d_op + 1, x, st);
         const int G = op_blocks(p1);
         if (grad_pass(p1)) p1.ops->visc_res64(h->d_op + 0, 1, G, st);
         p1.ops->res64(h->d_op + 1, 1, G, st);
