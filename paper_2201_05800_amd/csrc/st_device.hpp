@@ -185,12 +185,16 @@ struct GState {
     unsigned ticket;// last-block-done counter of the running reduction
     int reorth;     // adaptive Gram-Schmidt: the step's second pass is needed
                     // (set by pass 0, read by the gated pass-1 kernels)
+    int stall;      // outer iterations since ||R|| last fell below 0.9 best
+    int stop;       // outer iteration stops: 1 converged, 2 non-finite, 3 the
+                    // Newton-step limit or no progress (VecSeg.dev_stop)
     double target;  // outer stopping threshold tol * max(1, ||R(U0)||)
     double beta;    // ||r0|| of the cycle
     double eta_abs; // absolute inner tolerance of the cycle
     double rnorm;   // ||R(U)|| at the cycle start
     double wn0;     // ||w||^2 before orthogonalisation
     double inv;     // 1 / h_{k+1,k} for the normalisation
+    double best;    // smallest ||R|| of the progress test
     double kbytes[8];  // algorithmic bytes of the Krylov kernels that did work
     double hacc[MMAX + 1];
     double hp[MMAX + 1];
@@ -293,6 +297,13 @@ struct VecSeg {
     int ns;          // spatial nodes per element
     int blk0;
     int nblk;
+    // 1: k_begin also stops the outer iteration after max_newton Newton
+    // updates, and after 8 outer iterations in a row that do not bring ||R||
+    // below 0.9 times its smallest value so far (the solver's own tests, so
+    // that work enqueued before the host has read them exits at once); 0:
+    // only on convergence and non-finite values
+    int dev_stop;
+    int max_newton;
 };
 
 // One slab inside an element-block Jacobi launch: out_e = B^-1 in_e for every

@@ -497,6 +497,7 @@ struct st_ctx {
     double* U = nullptr;
     int m_alloc = 0;
     GState* h_st = nullptr;     // pinned host mirror of the state header
+    hipEvent_t ev_state = nullptr;  // recorded after each copy of the header
     std::vector<void*> allocs;
     // element-block Jacobi: B^-1 packed for the matrix cores, the dt it was
     // assembled for, the preconditioned direction z, 3 descriptor slots;
@@ -607,6 +608,7 @@ struct st_ctx {
         for (hipEvent_t e : timer.pool) (void)hipEventDestroy(e);
         for (void* p : allocs) (void)hipFree(p);
         if (h_st) (void)hipHostFree(h_st);
+        if (ev_state) (void)hipEventDestroy(ev_state);
     }
 };
 
@@ -1012,6 +1014,8 @@ int st_create(const st_mesh_t* mesh, int N, int Nt, const st_equation_t* eq, st_
     }
     e = hipHostMalloc((void**)&h->h_st, sizeof(GState), hipHostMallocDefault);
     if (e != hipSuccess) { delete h; return set_error(ST_ERR_HIP, std::string("hipHostMalloc: ") + hipGetErrorString(e)); }
+    e = hipEventCreateWithFlags(&h->ev_state, hipEventDisableTiming);
+    if (e != hipSuccess) { delete h; return set_error(ST_ERR_HIP, std::string("hipEventCreate: ") + hipGetErrorString(e)); }
     *out = h;
     return ST_OK;
 }
@@ -1377,6 +1381,8 @@ int st_solve_slabs(st_handle_t h, int M, const double* u_prev, double t0, double
     vs.ns = pb.ns;
     vs.blk0 = 0;
     vs.nblk = vec_blocks(nM);
+    vs.dev_stop = 1;
+    vs.max_newton = o.max_newton;
     const int Gv = vs.nblk;
     h->timer.reset(o.timing);
     HIPCHK(hipMemsetAsync(h->d_st, 0, sizeof(GState), st));
@@ -1460,6 +1466,24 @@ int st_solve_slabs(st_handle_t h, int M, const double* u_prev, double t0, double
     double r0 = 0.0, rn = 0.0, best = INFINITY;
     int stall = 0;
     auto& T = h->timer;
+    // one Arnoldi step (every kernel of it exits at once when the cycle is done)
+    auto arnoldi_step = [&](int k) {
+        if (pc) T.run(ST_K_PRECOND, st, [&] { pc_apply(h->d_pc + 0, 1, Gpc, npe, st); });
+        if (sweep) T.run(ST_K_PRECOND, st, [&] { pc_sweep(sw_dir, st); });
+        launch_jvp(h, M, fp32, d_jv, d_jop, cp_jvp, st);
+        const int npass = o.cgs_passes == 0 ? 2 : o.cgs_passes;
+        for (int p = 0; p < npass; ++p) {
+            int lastp = 0, gate = 0;
+            gs_pass_plan(o.cgs_passes, p, &lastp, &gate);
+            T.run(ST_K_MULTIDOT, st, [&] { vk_multidot(dvs, 1, Gv, k, st, gate, gstream); });
+            T.run(ST_K_UPDATE, st, [&] { vk_update(dvs, 1, Gv, p, lastp, k, st, gstream); });
+        }
+    };
+    // Steps of each cycle enqueued before the host reads the outer iteration's
+    // state: the GPU runs them while the host waits for the state, decides and
+    // enqueues the rest.  k_begin takes the same stopping decisions as the host
+    // below (VecSeg.dev_stop), so when the iteration stops they exit at once.
+    const int kpre = std::min(m, 2);
     for (;;) {
         launch_residual(h, M, d_rv, d_rop, cp_res, st);
         T.run(ST_K_NEWTON, st, [&] {
@@ -1467,31 +1491,26 @@ int st_solve_slabs(st_handle_t h, int M, const double* u_prev, double t0, double
             vk_begin(dvs, 1, st);
         }, false);
         HIPCHK(hipMemcpyAsync(h->h_st, h->d_st, offsetof(GState, hacc), hipMemcpyDeviceToHost, st));
-        HIPCHK(hipStreamSynchronize(st));
-        const GState& hs = *h->h_st;
-        rn = hs.rnorm;
-        if (outer == 0) r0 = rn;
-        if (hs.nonfinite) { status = ST_ERR_NONFINITE; break; }
-        if (rn <= hs.target) { status = ST_OK; break; }
-        if (outer >= o.max_newton) break;
-        if (rn < 0.9 * best) { best = rn; stall = 0; }
-        else if (++stall >= 8) break;     // no progress over 8 outer iterations
-        ++outer;
+        HIPCHK(hipEventRecord(h->ev_state, st));
         // Jacobian base point of FP32-inner JVPs: the FP32 copy of U
         if (fp32 && !linear_eq(kind)) T.run(ST_K_NEWTON, st, [&] { vk_cast32(dvs, 1, Gv, st); });
         T.run(ST_K_NORMALIZE, st, [&] { vk_scale_v0(dvs, 1, Gv, st); });
-        for (int k = 0; k < m; ++k) {
-            if (pc) T.run(ST_K_PRECOND, st, [&] { pc_apply(h->d_pc + 0, 1, Gpc, npe, st); });
-            if (sweep) T.run(ST_K_PRECOND, st, [&] { pc_sweep(sw_dir, st); });
-            launch_jvp(h, M, fp32, d_jv, d_jop, cp_jvp, st);
-            const int npass = o.cgs_passes == 0 ? 2 : o.cgs_passes;
-            for (int p = 0; p < npass; ++p) {
-                int lastp = 0, gate = 0;
-                gs_pass_plan(o.cgs_passes, p, &lastp, &gate);
-                T.run(ST_K_MULTIDOT, st, [&] { vk_multidot(dvs, 1, Gv, k, st, gate, gstream); });
-                T.run(ST_K_UPDATE, st, [&] { vk_update(dvs, 1, Gv, p, lastp, k, st, gstream); });
-            }
-        }
+        for (int k = 0; k < kpre; ++k) arnoldi_step(k);
+        HIPCHK(hipEventSynchronize(h->ev_state));
+        const GState& hs = *h->h_st;
+        rn = hs.rnorm;
+        if (outer == 0) r0 = rn;
+        bool more = false;
+        if (hs.nonfinite) status = ST_ERR_NONFINITE;
+        else if (rn <= hs.target) status = ST_OK;
+        else if (outer >= o.max_newton) {}
+        else if (rn < 0.9 * best) { best = rn; stall = 0; more = true; }
+        else more = ++stall < 8;          // no progress over 8 outer iterations: stop
+        if (more == (hs.stop != 0))
+            return set_error(ST_ERR_HIP, "st_solve_slab: device and host stopping tests disagree");
+        if (!more) break;
+        ++outer;
+        for (int k = kpre; k < m; ++k) arnoldi_step(k);
         T.run(ST_K_NEWTON, st, [&] {
             vk_finish(dvs, 1, st);
             if (sweep) {

@@ -255,7 +255,15 @@ __global__ __launch_bounds__(VBLOCK) void k_begin(const VecSeg* __restrict__ seg
     st->eta_abs = ea > ef ? ea : ef;
     st->reorth = 0;
     st->nonfinite = !isfinite(nr2);
-    st->done = (nr <= st->target) || st->nonfinite;
+    int stop = st->nonfinite ? 2 : (nr <= st->target ? 1 : 0);
+    if (!stop && sg.dev_stop) {
+        const int taken = st->outer - 1;     // Newton updates before this residual
+        if (taken >= sg.max_newton) stop = 3;
+        else if (taken == 0 || nr < 0.9 * st->best) { st->best = nr; st->stall = 0; }
+        else if (++st->stall >= 8) stop = 3;
+    }
+    st->stop = stop;
+    st->done = stop != 0;
 }
 
 // V_0 = -R / beta
